@@ -1,0 +1,119 @@
+/* mvn.h - C ABI of the MI355X (gfx950) separation-of-variables MVN library.
+ *
+ * Computes Phi_n(a, b; mu, Sigma) = P(a <= X <= b), X ~ N(mu, Sigma)
+ * (arXiv 2405.14892, Section III-A, Eq. (q1)) with Genz's separation of
+ * variables (Section III-B, Eqs. (sov1)-(sov2)) over randomised Richtmyer
+ * quasi-Monte Carlo points, organised as the paper's PMVN/QMC algorithms
+ * (Algorithms 2 and 3) but as one persistent GPU sweep per sample block.
+ *
+ * Conventions for every entry point:
+ *   - Pointers named d_* or documented "device" are device (HBM) pointers;
+ *     all others are host pointers.  The library never allocates device
+ *     memory: callers size buffers with the *_bytes queries and pass them in.
+ *   - Calls are asynchronous on the given stream and return after host-side
+ *     validation and enqueue.  Results are ready when the stream reaches them.
+ *   - Return value 0 = enqueued.  A negative value -k means argument k
+ *     (1-based) is invalid; nothing was enqueued.  -1000 - e means a HIP
+ *     runtime error e at launch.  mvn_last_error() gives a message.
+ *   - Matrices are row-major; Sigma is symmetric so only its lower triangle
+ *     is read and row- or column-major storage are equivalent.
+ *   - Only one call per stream at a time uses a given workspace.
+ */
+#ifndef MVN_H
+#define MVN_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Arithmetic of the Cholesky trailing updates and the SOV limit-update GEMMs.
+ * The diagonal-block factorisation, Phi / Phi^-1 / log and the per-sample
+ * log-products are always FP64. */
+typedef enum { MVN_FP64 = 0, MVN_FP32 = 1, MVN_BF16 = 2 } mvn_precision;
+
+/* Matern covariance parameters (Section III-C, Eq. for C(h; theta)):
+ * C(h) = sigma2 / (2^(nu-1) Gamma(nu)) (h/beta)^nu K_nu(h/beta), plus
+ * nugget on the diagonal.  The paper calls the range "a"; here it is beta.
+ * Supported nu: 0.5 and 1.5 (closed forms). */
+typedef struct mvn_matern {
+  double sigma2, beta, nu, nugget;
+} mvn_matern;
+
+typedef struct mvn_options {
+  int tile;          /* Cholesky tile size (>= 16); Algorithm 1's tile m      */
+  int precision;     /* mvn_precision                                          */
+  int periodize;     /* 1 = baker's transform of the QMC points, 0 = off       */
+  int reserved0;
+  double tlr_eps;    /* <= 0: dense factor (tile low-rank not in this build)  */
+  int max_rank;
+  int reserved1;
+} mvn_options;
+
+/* Factor handle, filled by mvn_cholesky.  Plain data; copy freely.
+ * L is row-major with leading dimension ld (>= n, a multiple of 128); rows
+ * and columns n..ld-1 hold the identity so blocked kernels need no bounds
+ * checks.  *info (device int) is 0 on success or k > 0 if the leading minor
+ * of order k is not positive definite (LAPACK dpotrf convention). */
+typedef struct mvn_factor {
+  int n;
+  int ld;
+  int precision;
+  int flags;
+  double* L;        /* device, ld*ld doubles                                   */
+  int* info;        /* device, 1 int                                           */
+  void* reserved[4];
+} mvn_factor;
+
+/* Sizes.  All return 0 on success and write the byte count. */
+int mvn_factor_bytes(int n, const mvn_options* opts, size_t* bytes);
+int mvn_cholesky_workspace_bytes(int n, const mvn_options* opts, size_t* bytes);
+int mvn_prob_workspace_bytes(int n, int N, int S, const mvn_options* opts, size_t* bytes);
+
+/* Sigma = L L^T (Algorithm 1, covariance generation and factorisation).
+ *   n        dimension (>= 1)
+ *   d_sigma  device n x n covariance with row stride ld_sigma, or NULL to
+ *            generate it from d_locs and kern (Matern + nugget)
+ *   d_locs   device n x 2 locations (x, y), read when d_sigma is NULL
+ *   factor_buf / factor_bytes   device memory for the factor
+ *   ws / ws_bytes               device workspace (may be NULL if 0 bytes)
+ *   out      host struct receiving the handle
+ * Non-positive-definite input is reported in *out->info (device), not by
+ * the return value; later kernels on the stream see it and propagate NaN. */
+int mvn_cholesky(int n, const double* d_sigma, int ld_sigma, const double* d_locs,
+                 const mvn_matern* kern, const mvn_options* opts,
+                 void* factor_buf, size_t factor_bytes, void* ws, size_t ws_bytes,
+                 mvn_factor* out, hipStream_t stream);
+
+/* P(a <= X <= b) by the SOV estimator (Algorithm 2 with Eq. (sov1)), over
+ * N Richtmyer points j = 1..N and S random shifts drawn from `seed`.
+ *   d_a, d_b  device limits (n doubles, may be -inf / +inf, a_i <= b_i)
+ *   d_mu      device mean (n doubles) or NULL for a zero mean
+ *   d_out     device output, 4 + S doubles:
+ *               [0] log P-hat  [1] P-hat (0 on underflow)
+ *               [2] standard error of P-hat over shifts (NaN if S == 1)
+ *               [3] relative standard error   [4 + s] log P-hat of shift s
+ *             All NaN if the factor's info != 0 or a limit is NaN / a > b.
+ *   d_ell     device, N*S doubles or NULL: per-sample log prod d_i, sample
+ *             column c = s*N + (j-1).
+ * The QMC point of sample (s, j) in dimension i is
+ *   w = ((j*A_i + D_{s,i} mod 2^64) >> 11 + 1/2) 2^-53 with
+ *   A_i = floor(frac(sqrt(p_{i+1})) 2^64) (p_k the k-th prime) and
+ *   D_{s,i} = SplitMix64 output s*n + i from state `seed`. */
+int mvn_prob(const mvn_factor* f, const double* d_a, const double* d_b, const double* d_mu,
+             int N, int S, uint64_t seed, const mvn_options* opts,
+             void* ws, size_t ws_bytes, double* d_out, double* d_ell, hipStream_t stream);
+
+/* Message for the last negative return on this thread ("" if none). */
+const char* mvn_last_error(void);
+
+/* Library version as 10000*major + 100*minor + patch. */
+int mvn_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MVN_H */

@@ -1,0 +1,130 @@
+"""MI355X (gfx950) separation-of-variables MVN probabilities.
+
+Python face of libmvn.so: the functions carry the C entry points' names and
+only marshal torch tensors (device memory, current HIP stream) into the C
+ABI declared in include/mvn.h.  The estimator is Genz's separation of
+variables with randomised Richtmyer QMC, as parallelised in arXiv 2405.14892
+(Algorithms 1-3).
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+from . import _lib
+from ._lib import (MVN_BF16, MVN_FP32, MVN_FP64, MvnError, MvnFactor, MvnMatern,  # noqa: F401
+                   MvnOptions, options)
+
+__all__ = ["mvn_factor_bytes", "mvn_prob_workspace_bytes", "mvn_cholesky", "mvn_prob", "Factor",
+           "options", "MvnError", "MVN_FP64", "MVN_FP32", "MVN_BF16", "library_path"]
+
+
+def library_path() -> str:
+    return _lib.LIB_PATH
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream(device):
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _dev_f64(x, device):
+    torch = _torch()
+    t = torch.as_tensor(x, dtype=torch.float64)
+    return t.to(device).contiguous()
+
+
+def mvn_factor_bytes(n: int, opts: MvnOptions | None = None) -> int:
+    out = ctypes.c_size_t(0)
+    _lib.check(_lib.lib().mvn_factor_bytes(n, ctypes.byref(opts or options()), ctypes.byref(out)))
+    return out.value
+
+
+def mvn_prob_workspace_bytes(n: int, N: int, S: int, opts: MvnOptions | None = None) -> int:
+    out = ctypes.c_size_t(0)
+    _lib.check(_lib.lib().mvn_prob_workspace_bytes(n, N, S, ctypes.byref(opts or options()),
+                                                   ctypes.byref(out)))
+    return out.value
+
+
+@dataclass
+class Factor:
+    """Handle from mvn_cholesky plus the device buffer that backs it."""
+    handle: MvnFactor
+    buffer: object  # torch uint8 tensor on the device
+    device: object
+
+    @property
+    def n(self) -> int:
+        return self.handle.n
+
+    @property
+    def ld(self) -> int:
+        return self.handle.ld
+
+    def L(self):
+        """The factor as an n x n float64 tensor view (lower triangular)."""
+        torch = _torch()
+        ld = self.handle.ld
+        return self.buffer[: ld * ld * 8].view(torch.float64).view(ld, ld)[: self.n, : self.n]
+
+    def info(self) -> int:
+        torch = _torch()
+        ld = self.handle.ld
+        off = (ld * ld * 8 + 255) // 256 * 256
+        return int(self.buffer[off: off + 4].view(torch.int32).item())
+
+
+def mvn_cholesky(n: int, sigma=None, locs=None, kern: tuple | None = None,
+                 opts: MvnOptions | None = None, device="cuda") -> Factor:
+    """Factor Sigma (device n x n) or the Matern covariance of ``locs``
+    (n x 2) with ``kern = (sigma2, beta, nu, nugget)``."""
+    torch = _torch()
+    opts = opts or options()
+    fb = mvn_factor_bytes(n, opts)
+    buf = torch.empty(fb, dtype=torch.uint8, device=device)
+    s = _dev_f64(sigma, device) if sigma is not None else None
+    lc = _dev_f64(locs, device) if locs is not None else None
+    km = MvnMatern(*kern) if kern is not None else None
+    h = MvnFactor()
+    code = _lib.lib().mvn_cholesky(
+        n, _ptr(s), n if s is not None else 0, _ptr(lc), ctypes.byref(km) if km else None,
+        ctypes.byref(opts), _ptr(buf), fb, None, 0, ctypes.byref(h), _stream(device))
+    _lib.check(code)
+    f = Factor(h, buf, device)
+    f._keep = (s, lc)  # inputs must outlive the asynchronous launch
+    return f
+
+
+def mvn_prob(f: Factor, a, b, mu=None, N: int = 1000, S: int = 10, seed: int = 1,
+             opts: MvnOptions | None = None, return_ell: bool = False, workspace=None):
+    """SOV estimate of P(a <= X <= b).  Returns a dict of device tensors:
+    logP, P, stderr, rel_stderr, logP_s[S] (and ell[N*S] if asked)."""
+    torch = _torch()
+    opts = opts or options()
+    dev = f.device
+    ta, tb = _dev_f64(a, dev), _dev_f64(b, dev)
+    tm = _dev_f64(mu, dev) if mu is not None else None
+    wsb = mvn_prob_workspace_bytes(f.n, N, S, opts)
+    if workspace is None or workspace.numel() < wsb:
+        workspace = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    out = torch.empty(4 + S, dtype=torch.float64, device=dev)
+    ell = torch.empty(N * S, dtype=torch.float64, device=dev) if return_ell else None
+    code = _lib.lib().mvn_prob(ctypes.byref(f.handle), _ptr(ta), _ptr(tb), _ptr(tm), N, S,
+                               ctypes.c_uint64(seed), ctypes.byref(opts), _ptr(workspace), wsb,
+                               _ptr(out), _ptr(ell), _stream(dev))
+    _lib.check(code)
+    res = {"logP": out[0], "P": out[1], "stderr": out[2], "rel_stderr": out[3], "logP_s": out[4:],
+           "out": out, "_keep": (ta, tb, tm, workspace)}
+    if return_ell:
+        res["ell"] = ell
+    return res

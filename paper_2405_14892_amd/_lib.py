@@ -1,0 +1,78 @@
+"""ctypes binding of libmvn.so (argument marshalling only).
+
+Every function here has the name of the C entry point it calls (see
+include/mvn.h).  torch supplies device memory and the current stream; all
+arithmetic happens in the library's HIP kernels.  There is no fallback: if
+the library is missing, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import c_double, c_int, c_size_t, c_uint64, c_void_p, POINTER
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmvn.so")
+
+MVN_FP64, MVN_FP32, MVN_BF16 = 0, 1, 2
+
+
+class MvnMatern(ctypes.Structure):
+    _fields_ = [("sigma2", c_double), ("beta", c_double), ("nu", c_double), ("nugget", c_double)]
+
+
+class MvnOptions(ctypes.Structure):
+    _fields_ = [("tile", c_int), ("precision", c_int), ("periodize", c_int), ("reserved0", c_int),
+                ("tlr_eps", c_double), ("max_rank", c_int), ("reserved1", c_int)]
+
+
+class MvnFactor(ctypes.Structure):
+    _fields_ = [("n", c_int), ("ld", c_int), ("precision", c_int), ("flags", c_int),
+                ("L", c_void_p), ("info", c_void_p), ("reserved", c_void_p * 4)]
+
+
+class MvnError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"mvn error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "mvn_factor_bytes": (c_int, [c_int, POINTER(MvnOptions), POINTER(c_size_t)]),
+    "mvn_cholesky_workspace_bytes": (c_int, [c_int, POINTER(MvnOptions), POINTER(c_size_t)]),
+    "mvn_prob_workspace_bytes": (c_int, [c_int, c_int, c_int, POINTER(MvnOptions), POINTER(c_size_t)]),
+    "mvn_cholesky": (c_int, [c_int, c_void_p, c_int, c_void_p, POINTER(MvnMatern), POINTER(MvnOptions),
+                             c_void_p, c_size_t, c_void_p, c_size_t, POINTER(MvnFactor), c_void_p]),
+    "mvn_prob": (c_int, [POINTER(MvnFactor), c_void_p, c_void_p, c_void_p, c_int, c_int, c_uint64,
+                         POINTER(MvnOptions), c_void_p, c_size_t, c_void_p, c_void_p, c_void_p]),
+    "mvn_last_error": (ctypes.c_char_p, []),
+    "mvn_version": (c_int, []),
+}
+
+
+def lib() -> ctypes.CDLL:
+    """Load libmvn.so (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2405_14892_amd.build`")
+        h = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(h, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = h
+    return _lib
+
+
+def check(code: int) -> None:
+    if code != 0:
+        raise MvnError(code, lib().mvn_last_error().decode())
+
+
+def options(tile: int = 256, precision: int = MVN_FP64, periodize: bool = False,
+            tlr_eps: float = 0.0, max_rank: int = 0) -> MvnOptions:
+    return MvnOptions(tile, precision, 1 if periodize else 0, 0, tlr_eps, max_rank, 0)

@@ -1,0 +1,258 @@
+// C ABI of the library (declared in include/mvn.h): argument validation,
+// workspace carving, the Richtmyer lattice table, and the launch sequences.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <mutex>
+#include <vector>
+
+#include "../../include/mvn.h"
+#include "launch.h"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* where) {
+  snprintf(g_err, sizeof g_err, "%s: %s", where, hipGetErrorString(e));
+  return -1000 - (int)e;
+}
+
+constexpr size_t kAlign = 256;
+constexpr int kMaxGrid = 256;  // persistent sweep workgroups (one per CU on MI355X)
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+int padded(int n) { return (n + 127) / 128 * 128; }
+
+bool opts_ok(const mvn_options* o, int* arg_bad_tile) {
+  if (!o) return true;
+  *arg_bad_tile = 0;
+  if (o->tile < 16 || o->tile % 4 != 0) *arg_bad_tile = 1;
+  return *arg_bad_tile == 0;
+}
+
+// ---------------------------------------------------------------- lattice
+// A_i = floor(frac(sqrt(p_{i+1})) 2^64) with exact integer arithmetic:
+// q = floor(sqrt p), r = p - q^2, F is the largest integer with
+// (q 2^64 + F)^2 <= p 2^128, i.e. F^2 + 2 q F 2^64 <= r 2^128.
+bool frac_ok(uint64_t q, uint64_t r, uint64_t F) {
+  const unsigned __int128 sq = (unsigned __int128)F * F;
+  const unsigned __int128 hi = sq >> 64;
+  const uint64_t lo = (uint64_t)sq;
+  const unsigned __int128 lhs = hi + (unsigned __int128)2 * q * F;
+  const unsigned __int128 rhs = (unsigned __int128)r << 64;
+  return lhs < rhs || (lhs == rhs && lo == 0);
+}
+
+uint64_t frac_sqrt_2p64(uint64_t p) {
+  uint64_t q = (uint64_t)sqrtl((long double)p);
+  while (q * q > p) --q;
+  while ((q + 1) * (q + 1) <= p) ++q;
+  const uint64_t r = p - q * q;
+  long double est = ldexpl((long double)r / (sqrtl((long double)p) + (long double)q), 64);
+  uint64_t F = est >= 18446744073709551615.0L ? UINT64_MAX : (uint64_t)est;
+  while (!frac_ok(q, r, F)) --F;
+  while (F != UINT64_MAX && frac_ok(q, r, F + 1)) ++F;
+  return F;
+}
+
+std::mutex g_lat_mu;
+uint64_t* g_lat_host = nullptr;   // pinned; grow-only (older tables stay alive)
+int g_lat_n = 0;
+
+const uint64_t* lattice_table(int n) {
+  std::lock_guard<std::mutex> lk(g_lat_mu);
+  if (n <= g_lat_n) return g_lat_host;
+  int want = n < 4096 ? 4096 : n;
+  // sieve enough primes: p_k < k (ln k + ln ln k) for k >= 6
+  const double lw = log((double)want + 16);
+  size_t limit = (size_t)(want * (lw + log(lw) + 3)) + 64;
+  std::vector<uint8_t> comp(limit + 1, 0);
+  std::vector<uint64_t> primes;
+  primes.reserve(want);
+  for (size_t v = 2; v <= limit && (int)primes.size() < want; ++v) {
+    if (comp[v]) continue;
+    primes.push_back(v);
+    for (size_t m = v * v; m <= limit; m += v) comp[m] = 1;
+  }
+  if ((int)primes.size() < want) return nullptr;
+  uint64_t* buf = nullptr;
+  if (hipHostMalloc((void**)&buf, sizeof(uint64_t) * want, hipHostMallocDefault) != hipSuccess)
+    return nullptr;
+  for (int i = 0; i < want; ++i) buf[i] = frac_sqrt_2p64(primes[i]);
+  g_lat_host = buf;  // the previous table is deliberately kept: in-flight copies may read it
+  g_lat_n = want;
+  return buf;
+}
+
+struct ProbLayout {
+  size_t at, bt, lat, shift, ell, part, bad, yscr, total;
+  int ld, grid;
+};
+
+ProbLayout prob_layout(int n, int N, int S) {
+  ProbLayout L{};
+  L.ld = padded(n);
+  const long NS = (long)N * S;
+  const long chunks = (NS + mvn::sweep_tile_cols() - 1) / mvn::sweep_tile_cols();
+  L.grid = (int)(chunks < kMaxGrid ? chunks : kMaxGrid);
+  size_t off = 0;
+  L.at = off; off = align_up(off + sizeof(double) * L.ld);
+  L.bt = off; off = align_up(off + sizeof(double) * L.ld);
+  L.lat = off; off = align_up(off + sizeof(uint64_t) * L.ld);
+  L.shift = off; off = align_up(off + sizeof(uint64_t) * (size_t)n * S);
+  L.ell = off; off = align_up(off + sizeof(double) * (size_t)NS);
+  L.part = off; off = align_up(off + sizeof(double) * 2 * (size_t)S);
+  L.bad = off; off = align_up(off + sizeof(int));
+  L.yscr = off; off = align_up(off + sizeof(double) * (size_t)L.grid * L.ld * mvn::sweep_tile_cols());
+  L.total = off;
+  return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mvn_last_error(void) { return g_err; }
+
+int mvn_version(void) { return 100; }
+
+int mvn_factor_bytes(int n, const mvn_options* opts, size_t* bytes) {
+  if (n < 1) return fail(-1, "n must be >= 1 (got %d)", n);
+  if (!bytes) return fail(-3, "bytes is NULL");
+  (void)opts;
+  const size_t ld = padded(n);
+  *bytes = align_up(sizeof(double) * ld * ld) + kAlign;
+  return 0;
+}
+
+int mvn_cholesky_workspace_bytes(int n, const mvn_options* opts, size_t* bytes) {
+  if (n < 1) return fail(-1, "n must be >= 1 (got %d)", n);
+  if (!bytes) return fail(-3, "bytes is NULL");
+  (void)opts;
+  *bytes = 0;
+  return 0;
+}
+
+int mvn_prob_workspace_bytes(int n, int N, int S, const mvn_options* opts, size_t* bytes) {
+  if (n < 1) return fail(-1, "n must be >= 1 (got %d)", n);
+  if (N < 1) return fail(-2, "N must be >= 1 (got %d)", N);
+  if (S < 1) return fail(-3, "S must be >= 1 (got %d)", S);
+  if (!bytes) return fail(-5, "bytes is NULL");
+  (void)opts;
+  *bytes = prob_layout(n, N, S).total;
+  return 0;
+}
+
+int mvn_cholesky(int n, const double* d_sigma, int ld_sigma, const double* d_locs,
+                 const mvn_matern* kern, const mvn_options* opts, void* factor_buf,
+                 size_t factor_bytes, void* ws, size_t ws_bytes, mvn_factor* out,
+                 hipStream_t stream) {
+  (void)ws;
+  (void)ws_bytes;
+  if (n < 1) return fail(-1, "n must be >= 1 (got %d)", n);
+  if (d_sigma && ld_sigma < n) return fail(-3, "ld_sigma %d < n %d", ld_sigma, n);
+  if (!d_sigma) {
+    if (!d_locs) return fail(-4, "either sigma or locations are required");
+    if (!kern) return fail(-5, "kernel parameters are required with locations");
+    if (!(kern->nu == 0.5 || kern->nu == 1.5))
+      return fail(-5, "Matern smoothness nu must be 0.5 or 1.5 (got %g)", kern->nu);
+    if (!(kern->sigma2 > 0) || !(kern->beta > 0) || !(kern->nugget >= 0))
+      return fail(-5, "Matern parameters need sigma2 > 0, beta > 0, nugget >= 0");
+  }
+  if (!opts) return fail(-6, "options are required");
+  int bad_tile = 0;
+  if (!opts_ok(opts, &bad_tile)) return fail(-6, "tile must be >= 16 and a multiple of 4 (got %d)", opts->tile);
+  if (opts->precision != MVN_FP64) return fail(-6, "only MVN_FP64 factors are available in this build");
+  if (opts->tlr_eps > 0) return fail(-6, "tile low-rank factors are not available in this build");
+  size_t need = 0;
+  mvn_factor_bytes(n, opts, &need);
+  if (!factor_buf) return fail(-7, "factor buffer is NULL");
+  if (factor_bytes < need) return fail(-8, "factor buffer too small: %zu < %zu", factor_bytes, need);
+  if (!out) return fail(-11, "out is NULL");
+  const int ld = padded(n);
+  double* L = (double*)factor_buf;
+  int* info = (int*)((char*)factor_buf + align_up(sizeof(double) * (size_t)ld * ld));
+  out->n = n;
+  out->ld = ld;
+  out->precision = MVN_FP64;
+  out->flags = 0;
+  out->L = L;
+  out->info = info;
+  for (int k = 0; k < 4; ++k) out->reserved[k] = nullptr;
+  hipError_t e = mvn::launch_build_matrix(n, ld, d_sigma, ld_sigma, d_locs, kern ? kern->sigma2 : 0,
+                                          kern ? kern->beta : 1, kern ? kern->nu : 0.5,
+                                          kern ? kern->nugget : 0, L, info, stream);
+  if (e != hipSuccess) return hip_fail(e, "build_matrix");
+  e = mvn::launch_cholesky_f64(ld, opts->tile, L, info, stream);
+  if (e != hipSuccess) return hip_fail(e, "cholesky");
+  return 0;
+}
+
+int mvn_prob(const mvn_factor* f, const double* d_a, const double* d_b, const double* d_mu, int N,
+             int S, uint64_t seed, const mvn_options* opts, void* ws, size_t ws_bytes, double* d_out,
+             double* d_ell, hipStream_t stream) {
+  if (!f || !f->L || !f->info || f->n < 1 || f->ld != padded(f->n))
+    return fail(-1, "invalid factor handle");
+  if (!d_a) return fail(-2, "lower limits are NULL");
+  if (!d_b) return fail(-3, "upper limits are NULL");
+  if (N < 1) return fail(-5, "N must be >= 1 (got %d)", N);
+  if (S < 1) return fail(-6, "S must be >= 1 (got %d)", S);
+  if ((long)N * S > (long)INT32_MAX * 64) return fail(-5, "N*S too large");
+  if (!opts) return fail(-8, "options are required");
+  if (opts->precision != MVN_FP64) return fail(-8, "only MVN_FP64 sweeps are available in this build");
+  const int n = f->n;
+  const ProbLayout Lay = prob_layout(n, N, S);
+  if (!ws) return fail(-9, "workspace is NULL");
+  if (ws_bytes < Lay.total) return fail(-10, "workspace too small: %zu < %zu", ws_bytes, Lay.total);
+  if (!d_out) return fail(-11, "output is NULL");
+  const uint64_t* lat = lattice_table(n);
+  if (!lat) return fail(-1, "could not build the lattice table for n = %d", n);
+  char* w = (char*)ws;
+  double* at = (double*)(w + Lay.at);
+  double* bt = (double*)(w + Lay.bt);
+  uint64_t* dlat = (uint64_t*)(w + Lay.lat);
+  uint64_t* shift = (uint64_t*)(w + Lay.shift);
+  double* ell = d_ell ? d_ell : (double*)(w + Lay.ell);
+  double* part = (double*)(w + Lay.part);
+  int* bad = (int*)(w + Lay.bad);
+  double* yscr = (double*)(w + Lay.yscr);
+  hipError_t e = hipMemcpyAsync(dlat, lat, sizeof(uint64_t) * n, hipMemcpyHostToDevice, stream);
+  if (e != hipSuccess) return hip_fail(e, "lattice copy");
+  e = mvn::launch_prob_setup(n, f->ld, S, seed, d_a, d_b, d_mu, at, bt, shift, bad, stream);
+  if (e != hipSuccess) return hip_fail(e, "setup");
+  mvn::SweepArgs sa{};
+  sa.L = f->L;
+  sa.ld = f->ld;
+  sa.n = n;
+  sa.at = at;
+  sa.bt = bt;
+  sa.lattice = dlat;
+  sa.shift = shift;
+  sa.N = N;
+  sa.S = S;
+  sa.periodize = opts->periodize ? 1 : 0;
+  sa.yscr = yscr;
+  sa.ell = ell;
+  sa.grid = Lay.grid;
+  e = mvn::launch_sweep_f64(sa, stream);
+  if (e != hipSuccess) return hip_fail(e, "sweep");
+  e = mvn::launch_reduce(ell, N, S, part, f->info, bad, d_out, stream);
+  if (e != hipSuccess) return hip_fail(e, "reduce");
+  return 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,255 @@
+// Covariance generation and dense tiled Cholesky, FP64 (arXiv 2405.14892,
+// Algorithm 1: generate Sigma from the Matern kernel, then L <- dpotrf(Sigma)).
+//
+// The factorisation is right-looking over tiles of width `tile`.  Inside a
+// tile column, sub-panels of 32 columns are finished left-looking:
+//   chol_diag  - update the 32 x 32 diagonal block by the earlier sub-panels
+//                of the same tile column, factor it in LDS (one workgroup);
+//   chol_trsm  - update the rows below by the same sub-panels and solve
+//                X L_dd^T = B (one lane per row, operands staged in LDS);
+// then chol_syrk subtracts the tile column's outer product from the trailing
+// matrix with FP64 MFMA on 128 x 128 lower tiles (the bulk of the flops).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "gemm_f64.h"
+#include "launch.h"
+
+namespace mvn {
+
+constexpr int kSub = 32;  // sub-panel width
+
+// ------------------------------------------------------------ covariance
+__global__ __launch_bounds__(256) void build_matrix_kernel(int n, int ld, const double* __restrict__ sigma,
+                                                           int lds, const double* __restrict__ locs,
+                                                           double sigma2, double beta, double nu,
+                                                           double nugget, double* __restrict__ A,
+                                                           int* __restrict__ info) {
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *info = 0;
+  const long i = (long)blockIdx.y * 16 + (threadIdx.x >> 4);
+  const long j = (long)blockIdx.x * 16 + (threadIdx.x & 15);
+  if (i >= ld || j > i) return;
+  double v;
+  if (i >= n || j >= n) {
+    v = (i == j) ? 1.0 : 0.0;
+  } else if (sigma) {
+    v = sigma[i * lds + j];
+  } else {
+    const double dx = locs[2 * i] - locs[2 * j];
+    const double dy = locs[2 * i + 1] - locs[2 * j + 1];
+    const double z = sqrt(dx * dx + dy * dy) / beta;
+    v = (nu == 0.5) ? sigma2 * exp(-z) : sigma2 * (1.0 + z) * exp(-z);
+    if (i == j) v += nugget;
+  }
+  A[i * ld + j] = v;
+}
+
+hipError_t launch_build_matrix(int n, int ld, const double* sigma, int lds, const double* locs,
+                               double sigma2, double beta, double nu, double nugget, double* A,
+                               int* info, hipStream_t st) {
+  dim3 grid(ld / 16, ld / 16);
+  hipLaunchKernelGGL(build_matrix_kernel, grid, dim3(256), 0, st, n, ld, sigma, lds, locs, sigma2,
+                     beta, nu, nugget, A, info);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ diagonal block
+// D = A[j0:j0+jw, j0:j0+jw] - A[j0:j0+jw, k0:j0] A[j0:j0+jw, k0:j0]^T, then
+// D = chol(D) in LDS.  One workgroup of 256 lanes.
+__global__ __launch_bounds__(256) void chol_diag_kernel(double* __restrict__ A, int ld, int k0, int j0,
+                                                        int jw, int* __restrict__ info) {
+  if (*info != 0) return;
+  __shared__ double D[kSub][kSub + 1];
+  __shared__ double P[kSub][64 + 1];
+  __shared__ int fail;
+  const int t = threadIdx.x;
+  if (t == 0) fail = 0;
+  // four lower-triangle entries per lane (e = t + 256 q)
+  double s[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int e = t + 256 * q, r = e >> 5, c = e & 31;
+    s[q] = (r < jw && c <= r) ? A[(long)(j0 + r) * ld + j0 + c] : 0.0;
+  }
+  for (int kc = k0; kc < j0; kc += 64) {
+    const int kw = min(64, j0 - kc);
+    __syncthreads();
+    for (int e = t; e < kSub * 64; e += 256) {
+      const int r = e >> 6, k = e & 63;
+      P[r][k] = (r < jw && k < kw) ? A[(long)(j0 + r) * ld + kc + k] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = t + 256 * q, r = e >> 5, c = e & 31;
+      if (r < jw && c <= r) {
+        double acc = 0.0;
+        for (int k = 0; k < kw; ++k) acc += P[r][k] * P[c][k];
+        s[q] -= acc;
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int e = t + 256 * q, r = e >> 5, c = e & 31;
+    D[r][c] = (r < jw && c <= r) ? s[q] : 0.0;
+  }
+  __syncthreads();
+  int j = 0;
+  for (; j < jw; ++j) {
+    if (t == 0) {
+      const double piv = D[j][j];
+      if (!(piv > 0.0)) fail = j0 + j + 1;
+      else D[j][j] = sqrt(piv);
+    }
+    __syncthreads();
+    if (fail) break;
+    const double djj = D[j][j];
+    for (int r = j + 1 + t; r < jw; r += 256) D[r][j] /= djj;
+    __syncthreads();
+    for (int e = t; e < kSub * kSub; e += 256) {
+      const int r = e >> 5, c = e & 31;
+      if (c > j && c <= r && r < jw) D[r][c] -= D[r][j] * D[c][j];
+    }
+    __syncthreads();
+  }
+  if (fail) {
+    if (t == 0) atomicCAS(info, 0, fail);
+    return;
+  }
+  for (int e = t; e < kSub * kSub; e += 256) {
+    const int r = e >> 5, c = e & 31;
+    if (r < jw && c <= r) A[(long)(j0 + r) * ld + j0 + c] = D[r][c];
+  }
+}
+
+// ------------------------------------------------------------ panel solve
+// Rows i >= j0 + jw: x = A[i, j0:j0+jw] - A[i, k0:j0] A[j0:j0+jw, k0:j0]^T,
+// then x <- x L_dd^{-T} (forward substitution).  One lane per row.
+__global__ __launch_bounds__(256) void chol_trsm_kernel(double* __restrict__ A, int ld, int k0, int j0,
+                                                        int jw, const int* __restrict__ info) {
+  if (*info != 0) return;
+  __shared__ double B[kSub][64 + 1];
+  __shared__ double D[kSub][kSub + 1];
+  const int t = threadIdx.x;
+  const long i = (long)j0 + jw + (long)blockIdx.x * 256 + t;
+  const bool live = i < ld;
+  double x[kSub];
+#pragma unroll
+  for (int c = 0; c < kSub; ++c) x[c] = (live && c < jw) ? A[i * ld + j0 + c] : 0.0;
+  for (int kc = k0; kc < j0; kc += 64) {
+    const int kw = min(64, j0 - kc);
+    __syncthreads();
+    for (int e = t; e < kSub * 64; e += 256) {
+      const int r = e >> 6, k = e & 63;
+      B[r][k] = (r < jw && k < kw) ? A[(long)(j0 + r) * ld + kc + k] : 0.0;
+    }
+    __syncthreads();
+    if (live) {
+      const double* arow = A + i * ld + kc;
+      for (int k = 0; k < kw; ++k) {
+        const double av = arow[k];
+#pragma unroll
+        for (int c = 0; c < kSub; ++c) x[c] -= av * B[c][k];
+      }
+    }
+  }
+  __syncthreads();
+  for (int e = t; e < kSub * kSub; e += 256) {
+    const int r = e >> 5, c = e & 31;
+    D[r][c] = (r < jw && c <= r) ? A[(long)(j0 + r) * ld + j0 + c] : (r == c ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  if (!live) return;
+#pragma unroll
+  for (int c = 0; c < kSub; ++c) {
+    double v = x[c];
+#pragma unroll
+    for (int cp = 0; cp < c; ++cp) v -= x[cp] * D[c][cp];
+    x[c] = v / D[c][c];
+  }
+#pragma unroll
+  for (int c = 0; c < kSub; ++c)
+    if (c < jw) A[i * ld + j0 + c] = x[c];
+}
+
+// ------------------------------------------------------------ trailing update
+// C = A[r0:, r0:] (lower 128 x 128 tiles) -= P P^T with P = A[r0:, k0:k0+kw].
+__global__ __launch_bounds__(256) void chol_syrk_kernel(double* __restrict__ A, int ld, int k0, int kw,
+                                                        const int* __restrict__ info) {
+  if (*info != 0) return;
+  __shared__ double lds[2 * 2 * kStageDoubles];
+  const long b = blockIdx.x;
+  long ti = (long)((sqrt(8.0 * (double)b + 1.0) - 1.0) * 0.5);
+  while ((ti + 1) * (ti + 2) / 2 <= b) ++ti;
+  while (ti * (ti + 1) / 2 > b) --ti;
+  const long tj = b - ti * (ti + 1) / 2;
+  const long r0 = (long)k0 + kw;
+  const long rowA = r0 + ti * kTile, rowB = r0 + tj * kTile;
+  Acc acc;
+  acc_zero(acc);
+  const int nst = (kw + kStageK - 1) / kStageK;
+  double ra[8], rb[8];
+  load_rows<true>(A, ld, rowA, k0, ld, (long)k0 + kw, ra);
+  load_rows<true>(A, ld, rowB, k0, ld, (long)k0 + kw, rb);
+  store_rows(lds, ra);
+  store_rows(lds + kStageDoubles, rb);
+  __syncthreads();
+  for (int s = 0; s < nst; ++s) {
+    double* cur = lds + (s & 1) * 2 * kStageDoubles;
+    double* nxt = lds + ((s + 1) & 1) * 2 * kStageDoubles;
+    if (s + 1 < nst) {
+      load_rows<true>(A, ld, rowA, (long)k0 + (s + 1) * kStageK, ld, (long)k0 + kw, ra);
+      load_rows<true>(A, ld, rowB, (long)k0 + (s + 1) * kStageK, ld, (long)k0 + kw, rb);
+    }
+    mma_stage(cur, cur + kStageDoubles, acc);
+    if (s + 1 < nst) {
+      store_rows(nxt, ra);
+      store_rows(nxt + kStageDoubles, rb);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int ib = 0; ib < 4; ++ib)
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const long gi = rowA + acc_row(ib, r), gj = rowB + acc_col(jb);
+        if (gi < ld && gj < ld && gj <= gi) A[gi * ld + gj] -= acc.v[ib][jb][r];
+      }
+}
+
+__global__ __launch_bounds__(256) void zero_upper_kernel(double* __restrict__ A, int ld) {
+  const long i = (long)blockIdx.y * 16 + (threadIdx.x >> 4);
+  const long j = (long)blockIdx.x * 16 + (threadIdx.x & 15);
+  if (i < ld && j < ld && j > i) A[i * ld + j] = 0.0;
+}
+
+hipError_t launch_cholesky_f64(int ld, int tile, double* A, int* info, hipStream_t st) {
+  for (int k0 = 0; k0 < ld; k0 += tile) {
+    const int kw = min(tile, ld - k0);
+    for (int j0 = k0; j0 < k0 + kw; j0 += kSub) {
+      const int jw = min(kSub, k0 + kw - j0);
+      hipLaunchKernelGGL(chol_diag_kernel, dim3(1), dim3(256), 0, st, A, ld, k0, j0, jw, info);
+      const int rows = ld - (j0 + jw);
+      if (rows > 0)
+        hipLaunchKernelGGL(chol_trsm_kernel, dim3((rows + 255) / 256), dim3(256), 0, st, A, ld, k0,
+                           j0, jw, (const int*)info);
+    }
+    const int rem = ld - (k0 + kw);
+    if (rem > 0) {
+      const long nt = (rem + kTile - 1) / kTile;
+      hipLaunchKernelGGL(chol_syrk_kernel, dim3((unsigned)(nt * (nt + 1) / 2)), dim3(256), 0, st, A,
+                         ld, k0, kw, (const int*)info);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(zero_upper_kernel, dim3(ld / 16, ld / 16), dim3(256), 0, st, A, ld);
+  return hipGetLastError();
+}
+
+}  // namespace mvn

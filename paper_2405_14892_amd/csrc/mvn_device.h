@@ -1,0 +1,162 @@
+// Device (and host-testable) arithmetic of the SOV conditioning step.
+//
+// The step is Eq. (sov1) of arXiv 2405.14892, Section III-B: for a sample with
+// conditional limits a', b' and uniform w,
+//     d = Phi(b') - Phi(a'),   y = Phi^-1( Phi(a') + w d ),   l += log d.
+// It is evaluated with exact identities that avoid cancellation:
+//   * reflection (a', b', w) -> (-b', -a', 1-w), y -> -y when a' > 0, so the
+//     lower end never sits in the upper tail;
+//   * y from Phi^-1(p) when p = Phi(a') + u d <= 1/2, else from -Phi^-1(q)
+//     with q = Phi(-b') + (1-u) d = 1 - p;
+//   * log-scale d and p when b' < -35 (both ends deep in the lower tail).
+// Phi uses erfc/erfcx; Phi^-1 is Wichura's algorithm AS 241 (PPND16, Applied
+// Statistics 37, 1988), and the log-scale inverse is Newton's method on
+// log Phi(y) = lp from the asymptotic expansion of the normal tail.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <math.h>
+
+#define MVN_HD __host__ __device__ __forceinline__
+
+namespace mvn {
+
+constexpr double kSqrt1_2 = 0.70710678118654752440;       // 1/sqrt(2)
+constexpr double kSqrt2OverPi = 0.79788456080286535588;   // sqrt(2/pi)
+constexpr double kLog2Pi = 1.83787706640934548356;        // log(2 pi)
+constexpr double kDeepTail = -35.0;
+
+// ---------------------------------------------------------------- Phi
+// Phi(x) = erfc(-x/sqrt 2)/2; relative accuracy in the lower tail.
+MVN_HD double ncdf(double x) { return 0.5 * erfc(-x * kSqrt1_2); }
+
+// log Phi(x) for x <= 0 (any depth): log(erfcx(-x/sqrt2)/2) - x^2/2.
+MVN_HD double log_ncdf_lower(double x) {
+  if (x == -INFINITY) return -INFINITY;
+  if (x > -5.0) return log(ncdf(x));
+  return log(0.5 * erfcx(-x * kSqrt1_2)) - 0.5 * x * x;
+}
+
+// ---------------------------------------------------------------- Phi^-1
+// AS 241 PPND16 for 0 < p <= 1/2 (returns a value <= 0).
+MVN_HD double ninv_lower(double p) {
+  const double q = p - 0.5;
+  if (fabs(q) <= 0.425) {
+    const double r = 0.180625 - q * q;
+    const double num = (((((((2.5090809287301226727e+3 * r + 3.3430575583588128105e+4) * r +
+                             6.7265770927008700853e+4) * r + 4.5921953931549871457e+4) * r +
+                           1.3731693765509461125e+4) * r + 1.9715909503065514427e+3) * r +
+                         1.3314166789178437745e+2) * r + 3.3871328727963666080e+0);
+    const double den = (((((((5.2264952788528545610e+3 * r + 2.8729085735721942674e+4) * r +
+                             3.9307895800092710610e+4) * r + 2.1213794301586595867e+4) * r +
+                           5.3941960214247511077e+3) * r + 6.8718700749205790830e+2) * r +
+                         4.2313330701600911252e+1) * r + 1.0);
+    return q * num / den;
+  }
+  double r = sqrt(-log(p));
+  double val;
+  if (r <= 5.0) {
+    r -= 1.6;
+    val = (((((((7.74545014278341407640e-4 * r + 2.27238449892691845833e-2) * r +
+                2.41780725177450611770e-1) * r + 1.27045825245236838258e+0) * r +
+              3.64784832476320460504e+0) * r + 5.76949722146069140550e+0) * r +
+            4.63033784615654529590e+0) * r + 1.42343711074968357734e+0) /
+          (((((((1.05075007164441684324e-9 * r + 5.47593808499534494600e-4) * r +
+                1.51986665636164571966e-2) * r + 1.48103976427480074590e-1) * r +
+              6.89767334985100004550e-1) * r + 1.67638483018380384940e+0) * r +
+            2.05319162663775882187e+0) * r + 1.0);
+  } else {
+    r -= 5.0;
+    val = (((((((2.01033439929228813265e-7 * r + 2.71155556874348757815e-5) * r +
+                1.24266094738807843860e-3) * r + 2.65321895265761230930e-2) * r +
+              2.96560571828504891230e-1) * r + 1.78482653991729133580e+0) * r +
+            5.46378491116411436990e+0) * r + 6.65790464350110377720e+0) /
+          (((((((2.04426310338993978564e-15 * r + 1.42151175831644588870e-7) * r +
+                1.84631831751005468180e-5) * r + 7.86869131145613259100e-4) * r +
+              1.48753612908506148525e-2) * r + 1.36929880922735805310e-1) * r +
+            5.99832206555887937690e-1) * r + 1.0);
+  }
+  return -val;
+}
+
+// Phi^-1 from lp = log p, p tiny (lp < log 1e-300 allowed).  Start from the
+// tail expansion log Phi(y) ~ -y^2/2 - log|y| - log(2 pi)/2, then Newton
+// steps y <- y - (log Phi(y) - lp) / (phi(y)/Phi(y)).
+MVN_HD double ninv_log(double lp) {
+  if (lp > -680.0) return ninv_lower(exp(lp));
+  if (lp == -INFINITY) return -INFINITY;
+  const double t = -2.0 * lp - kLog2Pi;
+  double y = -sqrt(t - log(t));
+  for (int it = 0; it < 4; ++it) {
+    const double z = -y * kSqrt1_2;
+    const double ex = erfcx(z);
+    const double f = log(0.5 * ex) - 0.5 * y * y - lp;
+    const double mills = kSqrt2OverPi / ex;  // phi(y)/Phi(y)
+    y -= f / mills;
+  }
+  return y;
+}
+
+// ---------------------------------------------------------------- the step
+struct Step {
+  double y;
+  double logd;
+};
+
+// One conditioning step (see header comment).  w in (0,1); cw = 1 - w.
+MVN_HD Step condition(double alpha, double beta, double w, double cw) {
+  const bool refl = alpha > 0.0;
+  const double lo = refl ? -beta : alpha;
+  const double hi = refl ? -alpha : beta;
+  const double u = refl ? cw : w;
+  const double v = refl ? w : cw;
+  double y, logd;
+  if (!(hi < kDeepTail)) {
+    const double pa = ncdf(lo);
+    // one erfc serves both Phi(hi) and Phi(-hi)
+    const double e = 0.5 * erfc(fabs(hi) * kSqrt1_2);
+    const double pb = hi > 0.0 ? 1.0 - e : e;
+    const double qb = hi > 0.0 ? e : 1.0 - e;
+    const double d = pb - pa;
+    const double p = pa + u * d;
+    if (p <= 0.5) {
+      y = ninv_lower(p);
+    } else {
+      y = -ninv_lower(qb + v * d);
+    }
+    logd = log(d);
+  } else {
+    const double la = log_ncdf_lower(lo);
+    const double lb = log_ncdf_lower(hi);
+    logd = lb + log1p(-exp(la - lb));
+    const double t = log(u) + logd;
+    // logaddexp(la, t)
+    const double mx = la > t ? la : t;
+    const double lp = (mx == -INFINITY) ? -INFINITY : mx + log1p(exp(-fabs(la - t)));
+    y = ninv_log(lp);
+  }
+  if (!(logd > -INFINITY)) {  // zero mass (or NaN): dead sample
+    y = 0.0;
+    logd = -INFINITY;
+  }
+  return Step{refl ? -y : y, logd};
+}
+
+// ---------------------------------------------------------------- QMC points
+// SplitMix64 output k (0-based) from state `seed` (Steele, Lea & Flood 2014).
+MVN_HD uint64_t splitmix64(uint64_t seed, uint64_t k) {
+  uint64_t z = seed + (k + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Richtmyer point j (1-based) of dimension with generator A and shift D.
+MVN_HD double richtmyer(uint64_t j, uint64_t A, uint64_t D, int periodize) {
+  const uint64_t x = j * A + D;
+  double w = ((double)(x >> 11) + 0.5) * 0x1.0p-53;
+  if (periodize) w = 1.0 - fabs(2.0 * w - 1.0);
+  return w;
+}
+
+}  // namespace mvn

@@ -1,0 +1,44 @@
+// Host build of the device conditioning arithmetic, for CPU checks of the
+// AS 241 coefficients and the branch structure against SciPy.
+// Reads lines "op x [y w]" from stdin and prints results with %.17g.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+
+// erfcx for the host build only: exp(x^2) erfc(x) in long double, with the
+// continued-fraction tail for large x.
+static double host_erfcx(double x) {
+  if (x < 25.0) return (double)(expl((long double)x * x) * erfcl((long double)x));
+  long double t = x, s = 1.0L / (t * sqrtl(3.14159265358979323846264338327950288L));
+  long double x2 = 2.0L * t * t;
+  return (double)(s * (1.0L - 1.0L / x2 + 3.0L / (x2 * x2) - 15.0L / (x2 * x2 * x2)));
+}
+__host__ double erfcx(double x) { return host_erfcx(x); }
+
+#include "../../paper_2405_14892_amd/csrc/mvn_device.h"
+
+int main() {
+  char op[32];
+  double x, y, w;
+  while (scanf("%31s", op) == 1) {
+    if (!strcmp(op, "ninv")) {
+      scanf("%lf", &x);
+      printf("%.17g\n", mvn::ninv_lower(x));
+    } else if (!strcmp(op, "ninvlog")) {
+      scanf("%lf", &x);
+      printf("%.17g\n", mvn::ninv_log(x));
+    } else if (!strcmp(op, "lncdf")) {
+      scanf("%lf", &x);
+      printf("%.17g\n", mvn::log_ncdf_lower(x));
+    } else if (!strcmp(op, "cond")) {
+      scanf("%lf %lf %lf", &x, &y, &w);
+      mvn::Step s = mvn::condition(x, y, w, 1.0 - w);
+      printf("%.17g %.17g\n", s.y, s.logd);
+    } else if (!strcmp(op, "sm")) {
+      unsigned long long seed, k;
+      scanf("%llu %llu", &seed, &k);
+      printf("%llu\n", (unsigned long long)mvn::splitmix64(seed, k));
+    }
+  }
+  return 0;
+}

@@ -1,0 +1,99 @@
+"""CPU-side checks of the library: it loads, exports every entry point that
+include/mvn.h declares, sizes buffers without a device, and its device
+arithmetic (compiled for the host from the same header) matches SciPy."""
+import ctypes
+import os
+import re
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+import scipy.special as sp
+
+import paper_2405_14892_amd as mvn
+from paper_2405_14892_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    text = open(os.path.join(ROOT, "include", "mvn.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(mvn_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    h = ctypes.CDLL(_lib.LIB_PATH)
+    names = _declared_symbols()
+    assert len(names) >= 6
+    for name in names:
+        assert hasattr(h, name), name
+        assert name in _lib.SIGNATURES, name
+    assert _lib.lib().mvn_version() >= 100
+
+
+def test_size_queries_and_host_validation_need_no_device():
+    opts = mvn.options(tile=128)
+    fb = mvn.mvn_factor_bytes(400, opts)
+    assert fb >= 512 * 512 * 8
+    ws = mvn.mvn_prob_workspace_bytes(400, 10_000, 10, opts)
+    # per-sample log-products + one 512 x 128 scratch block per workgroup
+    assert ws >= 10_000 * 10 * 8 + 256 * 512 * 128 * 8
+    with pytest.raises(mvn.MvnError) as e:
+        mvn.mvn_factor_bytes(0, opts)
+    assert e.value.code == -1
+    with pytest.raises(mvn.MvnError) as e:
+        mvn.mvn_prob_workspace_bytes(10, 5, 0, opts)
+    assert e.value.code == -3
+    h = _lib.lib()
+    out = _lib.MvnFactor()
+    code = h.mvn_cholesky(0, None, 0, None, None, ctypes.byref(opts), None, 0, None, 0,
+                          ctypes.byref(out), None)
+    assert code == -1 and b"n must be" in h.mvn_last_error()
+
+
+@pytest.fixture(scope="module")
+def harness(tmp_path_factory):
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not available")
+    exe = str(tmp_path_factory.mktemp("h") / "math_harness")
+    src = os.path.join(ROOT, "tests", "host", "math_harness.cpp")
+    subprocess.run([hipcc, "-x", "hip", "--offload-arch=gfx950", "-O2", "-o", exe, src], check=True,
+                   capture_output=True)
+    return exe
+
+
+def _run(exe, lines):
+    out = subprocess.run([exe], input="\n".join(lines) + "\n", capture_output=True, text=True,
+                         check=True).stdout
+    return [l for l in out.split("\n") if l]
+
+
+def test_as241_inverse_normal_matches_scipy(harness):
+    ps = np.concatenate([np.logspace(-300, -1, 2000), np.linspace(0.01, 0.5, 1000)])
+    got = np.array([float(v) for v in _run(harness, [f"ninv {float(p)!r}" for p in ps])])
+    rel = np.abs(got - sp.ndtri(ps)) / np.abs(sp.ndtri(ps)).clip(1e-300)
+    assert rel.max() < 2e-15
+
+
+def test_conditioning_step_matches_oracle(harness):
+    from oracle import sov
+    rng = np.random.default_rng(0)
+    al = np.concatenate([rng.normal(0, 3, 1500), rng.uniform(-60, 60, 500), [-np.inf] * 100])
+    be = al + np.abs(rng.normal(0, 3, al.size))
+    be[:150] = np.inf
+    be[np.isinf(al)] = rng.normal(0, 10, 100)
+    w = rng.uniform(size=al.size)
+    res = _run(harness, [f"cond {float(a)!r} {float(b)!r} {float(x)!r}" for a, b, x in zip(al, be, w)])
+    gy = np.array([float(r.split()[0]) for r in res])
+    gl = np.array([float(r.split()[1]) for r in res])
+    oy, ol = sov.condition(al, be, w)
+    assert np.max(np.abs(gy - oy)) < 1e-11
+    assert np.max(np.abs(gl - ol) / np.maximum(1, np.abs(ol))) < 1e-12
+
+
+def test_splitmix64_matches_published_outputs(harness):
+    got = [int(v) for v in _run(harness, ["sm 0 0", "sm 0 1", "sm 0 2"])]
+    assert got == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
