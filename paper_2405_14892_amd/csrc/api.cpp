@@ -32,7 +32,7 @@ int hip_fail(hipError_t e, const char* where) {
 }
 
 constexpr size_t kAlign = 256;
-constexpr int kMaxGrid = 256;  // persistent sweep workgroups (one per CU on MI355X)
+constexpr int kMaxGrid = 512;  // persistent sweep workgroups (two per CU on MI355X)
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 int padded(int n) { return (n + 127) / 128 * 128; }
@@ -99,7 +99,7 @@ const uint64_t* lattice_table(int n) {
 }
 
 struct ProbLayout {
-  size_t at, bt, lat, shift, ell, part, bad, yscr, total;
+  size_t at, bt, lat, ell, part, bad, yscr, total;
   int ld, grid;
 };
 
@@ -113,7 +113,6 @@ ProbLayout prob_layout(int n, int N, int S) {
   L.at = off; off = align_up(off + sizeof(double) * L.ld);
   L.bt = off; off = align_up(off + sizeof(double) * L.ld);
   L.lat = off; off = align_up(off + sizeof(uint64_t) * L.ld);
-  L.shift = off; off = align_up(off + sizeof(uint64_t) * (size_t)n * S);
   L.ell = off; off = align_up(off + sizeof(double) * (size_t)NS);
   L.part = off; off = align_up(off + sizeof(double) * 2 * (size_t)S);
   L.bad = off; off = align_up(off + sizeof(int));
@@ -225,14 +224,13 @@ int mvn_prob(const mvn_factor* f, const double* d_a, const double* d_b, const do
   double* at = (double*)(w + Lay.at);
   double* bt = (double*)(w + Lay.bt);
   uint64_t* dlat = (uint64_t*)(w + Lay.lat);
-  uint64_t* shift = (uint64_t*)(w + Lay.shift);
   double* ell = d_ell ? d_ell : (double*)(w + Lay.ell);
   double* part = (double*)(w + Lay.part);
   int* bad = (int*)(w + Lay.bad);
   double* yscr = (double*)(w + Lay.yscr);
   hipError_t e = hipMemcpyAsync(dlat, lat, sizeof(uint64_t) * n, hipMemcpyHostToDevice, stream);
   if (e != hipSuccess) return hip_fail(e, "lattice copy");
-  e = mvn::launch_prob_setup(n, f->ld, S, seed, d_a, d_b, d_mu, at, bt, shift, bad, stream);
+  e = mvn::launch_prob_setup(n, f->ld, d_a, d_b, d_mu, at, bt, bad, stream);
   if (e != hipSuccess) return hip_fail(e, "setup");
   mvn::SweepArgs sa{};
   sa.L = f->L;
@@ -241,7 +239,7 @@ int mvn_prob(const mvn_factor* f, const double* d_a, const double* d_b, const do
   sa.at = at;
   sa.bt = bt;
   sa.lattice = dlat;
-  sa.shift = shift;
+  sa.seed = seed;
   sa.N = N;
   sa.S = S;
   sa.periodize = opts->periodize ? 1 : 0;

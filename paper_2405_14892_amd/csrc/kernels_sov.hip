@@ -3,7 +3,7 @@
 // Algorithm 2 done as a log-sum-exp.
 //
 // Samples are independent (the recurrence is sequential only along the
-// dimension, Section IV-C), so one workgroup owns a block of 128 sample
+// dimension, Section IV-C), so one workgroup owns a block of 64 sample
 // columns for the whole sweep and never synchronises with other workgroups;
 // only the factor L is shared.  For each block row r of 128 dimensions:
 //   1. S = L[r-block, 0:r*128] . Y[0:r*128, cols]   (FP64 MFMA, K = r*128)
@@ -15,7 +15,7 @@
 //      l += log d_i;
 //   3. y of the block goes to the workgroup's Y scratch for later K loops.
 // The uniform matrix R of Algorithm 2 is replaced by Richtmyer points
-// generated in registers from the lattice and shift tables.
+// generated in registers from the lattice table and the SplitMix64 shift.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -27,15 +27,9 @@
 
 namespace mvn {
 
-int sweep_tile_cols() { return kTile; }
-
 // ------------------------------------------------------------ setup
-__global__ __launch_bounds__(256) void shift_table_kernel(uint64_t seed, int n, int S,
-                                                          uint64_t* __restrict__ shift,
-                                                          int* __restrict__ bad) {
-  const long k = (long)blockIdx.x * 256 + threadIdx.x;
-  if (k == 0) *bad = INT_MAX;
-  if (k < (long)n * S) shift[k] = splitmix64(seed, (uint64_t)k);
+__global__ void flag_init_kernel(int* __restrict__ bad) {
+  if (threadIdx.x == 0) *bad = INT_MAX;
 }
 
 __global__ __launch_bounds__(256) void centre_kernel(int n, int ld, const double* __restrict__ a,
@@ -56,92 +50,180 @@ __global__ __launch_bounds__(256) void centre_kernel(int n, int ld, const double
   bt[i] = bi - m;
 }
 
-hipError_t launch_prob_setup(int n, int ld, int S, uint64_t seed, const double* a, const double* b,
-                             const double* mu, double* at, double* bt, uint64_t* shift, int* bad,
-                             hipStream_t st) {
-  const long tot = (long)n * S;
-  hipLaunchKernelGGL(shift_table_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, seed,
-                     n, S, shift, bad);
+hipError_t launch_prob_setup(int n, int ld, const double* a, const double* b, const double* mu,
+                             double* at, double* bt, int* bad, hipStream_t st) {
+  hipLaunchKernelGGL(flag_init_kernel, dim3(1), dim3(64), 0, st, bad);
   hipLaunchKernelGGL(centre_kernel, dim3((ld + 255) / 256), dim3(256), 0, st, n, ld, a, b, mu, at, bt,
                      bad);
   return hipGetLastError();
 }
 
 // ------------------------------------------------------------ the sweep
-__global__ __launch_bounds__(256) void sweep_f64_kernel(SweepArgs p) {
-  // 128 KB: two double-buffered GEMM stages during step 1, then the
-  // 128 x 128 block T (S, overwritten row by row with y) during step 2.
-  __shared__ double lds[kTile * kTile];
+// Tile of the sweep: 128 block rows x 64 sample columns per workgroup of
+// four wave64s; wave w owns rows [32 w, 32 w + 32) x all 64 columns, i.e.
+// 2 x 4 blocks of the 16 x 16 FP64 MFMA.  76 KB of LDS and <= 256 registers
+// per lane let two workgroups share a CU, so one workgroup's conditioning
+// (VALU) overlaps the other's GEMM (MFMA).
+constexpr int kCols = 64;                         // sample columns per workgroup
+constexpr int kBLd = kCols + 1;                   // LDS row stride of the Y stage
+constexpr int kBStage = kStageK * kBLd;
+constexpr int kSlab = 8;                          // rows of L staged per LDS slab
+
+int sweep_tile_cols() { return kCols; }
+
+__device__ __forceinline__ void load_y(const double* __restrict__ Y, long k0, double (&r)[4]) {
   const int t = threadIdx.x;
+  const double2* p2 = reinterpret_cast<const double2*>(Y + (k0 + (t >> 4)) * kCols + (t & 15) * 4);
+  const double2 v0 = p2[0], v1 = p2[1];
+  r[0] = v0.x; r[1] = v0.y; r[2] = v1.x; r[3] = v1.y;
+}
+
+__device__ __forceinline__ void store_y(double* __restrict__ lds, const double (&r)[4]) {
+  const int t = threadIdx.x;
+  double* d = lds + (t >> 4) * kBLd + (t & 15) * 4;
+  d[0] = r[0]; d[1] = r[1]; d[2] = r[2]; d[3] = r[3];
+}
+
+struct SweepAcc {
+  f64x4 v[2][4];
+};
+
+__device__ __forceinline__ void sweep_mma(const double* __restrict__ As, const double* __restrict__ Bs,
+                                          SweepAcc& acc) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int kk = 0; kk < kStageK / 4; ++kk) {
+    const int k = kk * 4 + (lane >> 4);
+    double a[2], b[4];
+#pragma unroll
+    for (int ib = 0; ib < 2; ++ib) a[ib] = As[k * kLdsLd + w * 32 + ib * 16 + (lane & 15)];
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb) b[jb] = Bs[k * kBLd + jb * 16 + (lane & 15)];
+#pragma unroll
+    for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+      for (int jb = 0; jb < 4; ++jb)
+        acc.v[ib][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ib], b[jb], acc.v[ib][jb], 0, 0, 0);
+  }
+}
+
+__global__ __launch_bounds__(256, 2) void sweep_f64_kernel(SweepArgs p) {
+  // 64 KB: double-buffered GEMM stages during step 1, then the 128 x 64
+  // block T (S, overwritten row by row with y) during step 2.
+  __shared__ double lds[kTile * kCols];
+  // step 2 operands: a slab of rows of the diagonal block of L, and the
+  // block's per-row constants (limits, 1/L_ii, lattice generator)
+  __shared__ double slab[kSlab * kTile];
+  __shared__ double c_at[kTile], c_bt[kTile], c_rl[kTile];
+  __shared__ uint64_t c_lat[kTile];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const long NS = (long)p.N * p.S;
-  const long nchunks = (NS + kTile - 1) / kTile;
-  double* Y = p.yscr + (long)blockIdx.x * p.ld * kTile;
+  const long nchunks = (NS + kCols - 1) / kCols;
+  double* Y = p.yscr + (long)blockIdx.x * p.ld * kCols;
   const long ld = p.ld;
+  double* As0 = lds;
+  double* Bs0 = lds + kStageDoubles;
+  double* As1 = lds + kStageDoubles + kBStage;
+  double* Bs1 = As1 + kStageDoubles;
 
   for (long chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x) {
-    const long col = chunk * kTile + (t & (kTile - 1));
-    const bool owner = t < kTile;
+    const long col = chunk * kCols + lane;
+    const bool owner = wv == 0;
     const bool valid = owner && col < NS;
-    const long sidx = valid ? col / p.N : 0;
+    const uint64_t sidx = valid ? (uint64_t)(col / p.N) : 0;
     const uint64_t jpt = valid ? (uint64_t)(col % p.N) + 1 : 1;
     double ell = 0.0;
 
     for (int i0 = 0; i0 < p.n; i0 += kTile) {
       const int rows = min(kTile, p.n - i0);
-      Acc acc;
-      acc_zero(acc);
+      SweepAcc acc;
+#pragma unroll
+      for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+        for (int jb = 0; jb < 4; ++jb) acc.v[ib][jb] = f64x4{0.0, 0.0, 0.0, 0.0};
       // ---- step 1: S = L[i0:i0+128, 0:i0] Y[0:i0, :]
       if (i0 > 0) {
         const int nst = i0 / kStageK;
-        double ra[8], rb[8];
+        double ra[8], rb[4];
         load_rows<false>(p.L, ld, i0, 0, 0, 0, ra);
-        load_cols(Y, kTile, 0, rb);
-        store_rows(lds, ra);
-        store_cols(lds + kStageDoubles, rb);
+        load_y(Y, 0, rb);
+        store_rows(As0, ra);
+        store_y(Bs0, rb);
         __syncthreads();
         for (int s = 0; s < nst; ++s) {
-          double* cur = lds + (s & 1) * 2 * kStageDoubles;
-          double* nxt = lds + ((s + 1) & 1) * 2 * kStageDoubles;
+          const bool odd = s & 1;
           if (s + 1 < nst) {
             load_rows<false>(p.L, ld, i0, (long)(s + 1) * kStageK, 0, 0, ra);
-            load_cols(Y, kTile, (long)(s + 1) * kStageK, rb);
+            load_y(Y, (long)(s + 1) * kStageK, rb);
           }
-          mma_stage(cur, cur + kStageDoubles, acc);
+          sweep_mma(odd ? As1 : As0, odd ? Bs1 : Bs0, acc);
           if (s + 1 < nst) {
-            store_rows(nxt, ra);
-            store_cols(nxt + kStageDoubles, rb);
+            store_rows(odd ? As0 : As1, ra);
+            store_y(odd ? Bs0 : Bs1, rb);
           }
           __syncthreads();
         }
       }
-      // accumulators -> T[row][col]
+      // accumulators -> T[row][col]; per-row constants -> LDS
 #pragma unroll
-      for (int ib = 0; ib < 4; ++ib)
+      for (int ib = 0; ib < 2; ++ib)
 #pragma unroll
         for (int jb = 0; jb < 4; ++jb)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) lds[acc_row(ib, r) * kTile + acc_col(jb)] = acc.v[ib][jb][r];
-      __syncthreads();
-      // ---- step 2: conditioning of the diagonal block, lane = column
-      if (owner) {
-        const int c = t;
-        for (int i = 0; i < rows; ++i) {
-          const long g = i0 + i;
-          const double* Lg = p.L + g * ld + i0;
-          double s = lds[i * kTile + c];
-          for (int k = 0; k < i; ++k) s += Lg[k] * lds[k * kTile + c];
-          const double lgg = Lg[i];
-          const double alpha = (p.at[g] - s) / lgg;
-          const double beta = (p.bt[g] - s) / lgg;
-          const double w = richtmyer(jpt, p.lattice[g], p.shift[sidx * p.n + g], p.periodize);
-          const Step st = condition(alpha, beta, w, 1.0 - w);
-          lds[i * kTile + c] = valid ? st.y : 0.0;
-          ell += st.logd;
+          for (int r = 0; r < 4; ++r)
+            lds[(wv * 32 + ib * 16 + (lane >> 4) + 4 * r) * kCols + jb * 16 + (lane & 15)] = acc.v[ib][jb][r];
+      if (t < rows) {
+        const long g = i0 + t;
+        c_at[t] = p.at[g];
+        c_bt[t] = p.bt[g];
+        c_rl[t] = 1.0 / p.L[g * ld + g];
+        c_lat[t] = p.lattice[g];
+      }
+      // ---- step 2: conditioning of the diagonal block by wave 0, lane =
+      // column, in slabs of rows whose L entries are staged in LDS
+      for (int q = 0; q < rows; q += kSlab) {
+        __syncthreads();
+        for (int e = t; e < kSlab * kTile; e += 256) {
+          const int ii = e / kTile, k = e % kTile;
+          slab[e] = (q + ii < rows && k < q + ii) ? p.L[(long)(i0 + q + ii) * ld + i0 + k] : 0.0;
+        }
+        __syncthreads();
+        if (owner) {
+          const int iend = min(q + kSlab, rows);
+          for (int i = q; i < iend; ++i) {
+            // s_i = S_i + sum_{k<i} L_ik y_k over the block; the slab row is
+            // zero from column i on, so the sum runs to a multiple of 8 with
+            // four independent partial sums (the LDS reads then pipeline)
+            const double* Li = slab + (i - q) * kTile;
+            const double* Tk = lds + lane;
+            double s0 = lds[i * kCols + lane], s1 = 0.0, s2 = 0.0, s3 = 0.0;
+            const int kend = (i + 7) & ~7;
+            for (int k = 0; k < kend; k += 8) {
+              s0 += Li[k] * Tk[k * kCols];
+              s1 += Li[k + 1] * Tk[(k + 1) * kCols];
+              s2 += Li[k + 2] * Tk[(k + 2) * kCols];
+              s3 += Li[k + 3] * Tk[(k + 3) * kCols];
+              s0 += Li[k + 4] * Tk[(k + 4) * kCols];
+              s1 += Li[k + 5] * Tk[(k + 5) * kCols];
+              s2 += Li[k + 6] * Tk[(k + 6) * kCols];
+              s3 += Li[k + 7] * Tk[(k + 7) * kCols];
+            }
+            const double s = (s0 + s1) + (s2 + s3);
+            const double rl = c_rl[i];
+            const double alpha = (c_at[i] - s) * rl;
+            const double beta = (c_bt[i] - s) * rl;
+            const uint64_t g = (uint64_t)(i0 + i);
+            const double w = richtmyer(jpt, c_lat[i], splitmix64(p.seed, sidx * (uint64_t)p.n + g),
+                                       p.periodize);
+            const Step st = condition(alpha, beta, w, 1.0 - w);
+            lds[i * kCols + lane] = valid ? st.y : 0.0;
+            ell += st.logd;
+          }
         }
       }
       __syncthreads();
       // ---- step 3: y block -> scratch
-      for (int e = t; e < rows * kTile; e += 256) Y[(long)(i0 + e / kTile) * kTile + (e % kTile)] = lds[e];
+      for (int e = t; e < rows * kCols; e += 256) Y[(long)i0 * kCols + e] = lds[e];
       __syncthreads();
     }
     if (valid) p.ell[col] = ell;

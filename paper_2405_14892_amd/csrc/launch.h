@@ -23,17 +23,16 @@ struct SweepArgs {
   const double* at;        // centred lower limits (padded to ld)
   const double* bt;        // centred upper limits
   const uint64_t* lattice; // A_i, n entries
-  const uint64_t* shift;   // D_{s,i}, S*n entries, shift-major
+  uint64_t seed;           // shift D_{s,i} = SplitMix64 output s*n + i from this state
   int N, S, periodize;
   double* yscr;            // per-workgroup scratch, grid x ld x 128 doubles
   double* ell;             // N*S per-sample log-products
   int grid;                // persistent workgroups
 };
 
-// Setup of one probability call: shift table, centred limits, flags.
-hipError_t launch_prob_setup(int n, int ld, int S, uint64_t seed, const double* a, const double* b,
-                             const double* mu, double* at, double* bt, uint64_t* shift, int* bad,
-                             hipStream_t st);
+// Setup of one probability call: centred limits and the invalid-limit flag.
+hipError_t launch_prob_setup(int n, int ld, const double* a, const double* b, const double* mu,
+                             double* at, double* bt, int* bad, hipStream_t st);
 
 hipError_t launch_sweep_f64(const SweepArgs& a, hipStream_t st);
 

@@ -18,6 +18,15 @@
 #include <math.h>
 
 #define MVN_HD __host__ __device__ __forceinline__
+// The conditioning step is kept out of line on the device: inlined into
+// the sweep's row loop, loop-invariant code motion would pin its ~60
+// polynomial constants in registers for the whole loop.  (Host builds of
+// this header, used to check the arithmetic on the CPU, inline it.)
+#if defined(__HIP_DEVICE_COMPILE__)
+#define MVN_HD_COLD __host__ __device__ __attribute__((noinline))
+#else
+#define MVN_HD_COLD __host__ __device__ inline
+#endif
 
 namespace mvn {
 
@@ -103,8 +112,21 @@ struct Step {
   double logd;
 };
 
+// Both ends below -35: d and p from log Phi (returns y and log d in the
+// unreflected frame of (lo, hi)).  Rare, so out of line as well.
+MVN_HD_COLD Step deep_tail(double lo, double hi, double u) {
+  const double la = log_ncdf_lower(lo);
+  const double lb = log_ncdf_lower(hi);
+  const double logd = lb + log1p(-exp(la - lb));
+  const double t = log(u) + logd;
+  // logaddexp(la, t)
+  const double mx = la > t ? la : t;
+  const double lp = (mx == -INFINITY) ? -INFINITY : mx + log1p(exp(-fabs(la - t)));
+  return Step{ninv_log(lp), logd};
+}
+
 // One conditioning step (see header comment).  w in (0,1); cw = 1 - w.
-MVN_HD Step condition(double alpha, double beta, double w, double cw) {
+MVN_HD_COLD Step condition(double alpha, double beta, double w, double cw) {
   const bool refl = alpha > 0.0;
   const double lo = refl ? -beta : alpha;
   const double hi = refl ? -alpha : beta;
@@ -126,14 +148,9 @@ MVN_HD Step condition(double alpha, double beta, double w, double cw) {
     }
     logd = log(d);
   } else {
-    const double la = log_ncdf_lower(lo);
-    const double lb = log_ncdf_lower(hi);
-    logd = lb + log1p(-exp(la - lb));
-    const double t = log(u) + logd;
-    // logaddexp(la, t)
-    const double mx = la > t ? la : t;
-    const double lp = (mx == -INFINITY) ? -INFINITY : mx + log1p(exp(-fabs(la - t)));
-    y = ninv_log(lp);
+    const Step s = deep_tail(lo, hi, u);
+    y = s.y;
+    logd = s.logd;
   }
   if (!(logd > -INFINITY)) {  // zero mass (or NaN): dead sample
     y = 0.0;
