@@ -24,6 +24,23 @@ sys.path.insert(0, ROOT)
 METRIC = "MVN probs/sec + effective TFLOP/s (Cholesky+SOV) at stated error vs FP64 oracle"
 PEAK_FP64_TFLOPS = 78.6
 
+# HBM bytes per sweep launch on this workload from rocprofv3 FETCH_SIZE x2 + WRITE_SIZE x1
+# (scales from a 1 GiB copy; profiles/sweep_f64_prec16k.md), valid only for the kernel
+# sources they were measured on.
+TRAFFIC_SOURCES = ["paper_2405_14892_amd/csrc/kernels_sov.hip", "paper_2405_14892_amd/csrc/mvn_device.h",
+                   "paper_2405_14892_amd/csrc/gemm_f64.h"]
+TRAFFIC_MEASURED = {"prec16k": ("3694a5d041d9fa63", 3.231e12)}
+
+
+def _traffic(workload: str):
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    rec = TRAFFIC_MEASURED.get(workload)
+    return rec[1] if rec and rec[0] == h.hexdigest()[:16] else None
+
 
 def _cpu_baseline(w, n_sub: int = 4096, cols: int = 512) -> dict:
     """The oracle, untuned, on a bounded sample of the same workload: the
@@ -154,7 +171,7 @@ def main() -> int:
         "result": {"logP": float(res[0]), "rel_stderr": float(res[3])},
         "roofline": {"bound": "mfma", "kernel": "sweep_f64_kernel (SOV GEMM + conditioning)",
                      "achieved": sweep_tf, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": sweep_tf / PEAK_FP64_TFLOPS, "traffic": None,
+                     "frac": sweep_tf / PEAK_FP64_TFLOPS, "traffic": _traffic(args.workload),
                      "algorithmic_flops_per_launch": sov_flops},
     }
     if not args.no_cpu_baseline:
