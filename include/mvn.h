@@ -30,10 +30,13 @@
 extern "C" {
 #endif
 
-/* Arithmetic of the Cholesky trailing updates and the SOV limit-update GEMMs.
- * The diagonal-block factorisation, Phi / Phi^-1 / log and the per-sample
- * log-products are always FP64. */
-typedef enum { MVN_FP64 = 0, MVN_FP32 = 1, MVN_BF16 = 2 } mvn_precision;
+/* Arithmetic of the Cholesky trailing updates and the SOV limit-update GEMMs
+ * (MFMA; FP32 accumulation for the reduced types).  The diagonal-block
+ * factorisation and panel solves, the in-block recurrence, Phi / Phi^-1 /
+ * log and the per-sample log-products are always FP64.
+ *   MVN_BF16X3: operands split as x = hi + lo (both BF16) and the products
+ *   hi*hi + hi*lo + lo*hi accumulated (about 16 significant bits). */
+typedef enum { MVN_FP64 = 0, MVN_FP32 = 1, MVN_BF16 = 2, MVN_BF16X3 = 3 } mvn_precision;
 
 /* Matern covariance parameters (Section III-C, Eq. for C(h; theta)):
  * C(h) = sigma2 / (2^(nu-1) Gamma(nu)) (h/beta)^nu K_nu(h/beta), plus
@@ -54,6 +57,8 @@ typedef struct mvn_options {
 } mvn_options;
 
 /* Factor handle, filled by mvn_cholesky.  Plain data; copy freely.
+ * opts->precision selects the trailing-update arithmetic and which operand
+ * copy of L is kept for the sweep.
  * L is row-major with leading dimension ld (>= n, a multiple of 128); rows
  * and columns n..ld-1 hold the identity so blocked kernels need no bounds
  * checks.  *info (device int) is 0 on success or k > 0 if the leading minor
@@ -61,11 +66,14 @@ typedef struct mvn_options {
 typedef struct mvn_factor {
   int n;
   int ld;
-  int precision;
+  int precision;    /* arithmetic the factor was built with (mvn_precision)    */
   int flags;
   double* L;        /* device, ld*ld doubles                                   */
   int* info;        /* device, 1 int                                           */
-  void* reserved[4];
+  void* L_low;      /* device copy of L as the sweep's GEMM operand: ld*ld     */
+                    /* floats (FP32), BF16 (BF16), two BF16 planes (BF16X3);  */
+                    /* NULL for FP64                                           */
+  void* reserved[3];
 } mvn_factor;
 
 /* Sizes.  All return 0 on success and write the byte count. */
@@ -99,6 +107,8 @@ int mvn_cholesky(int n, const double* d_sigma, int ld_sigma, const double* d_loc
  *             All NaN if the factor's info != 0 or a limit is NaN / a > b.
  *   d_ell     device, N*S doubles or NULL: per-sample log prod d_i, sample
  *             column c = s*N + (j-1).
+ * opts->precision selects the arithmetic of the limit-update GEMM: MVN_FP64
+ * always, or the precision the factor was built with.
  * The QMC point of sample (s, j) in dimension i is
  *   w = ((j*A_i + D_{s,i} mod 2^64) >> 11 + 1/2) 2^-53 with
  *   A_i = floor(frac(sqrt(p_{i+1})) 2^64) (p_k the k-th prime) and

@@ -12,11 +12,11 @@ import ctypes
 from dataclasses import dataclass
 
 from . import _lib
-from ._lib import (MVN_BF16, MVN_FP32, MVN_FP64, MvnError, MvnFactor, MvnMatern,  # noqa: F401
-                   MvnOptions, options)
+from ._lib import (MVN_BF16, MVN_BF16X3, MVN_FP32, MVN_FP64, MvnError, MvnFactor,  # noqa: F401
+                   MvnMatern, MvnOptions, options)
 
 __all__ = ["mvn_factor_bytes", "mvn_prob_workspace_bytes", "mvn_cholesky", "mvn_prob", "Factor",
-           "options", "MvnError", "MVN_FP64", "MVN_FP32", "MVN_BF16", "library_path"]
+           "options", "MvnError", "MVN_FP64", "MVN_FP32", "MVN_BF16", "MVN_BF16X3", "library_path"]
 
 
 def library_path() -> str:

@@ -14,7 +14,7 @@ from ctypes import c_double, c_int, c_size_t, c_uint64, c_void_p, POINTER
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmvn.so")
 
-MVN_FP64, MVN_FP32, MVN_BF16 = 0, 1, 2
+MVN_FP64, MVN_FP32, MVN_BF16, MVN_BF16X3 = 0, 1, 2, 3
 
 
 class MvnMatern(ctypes.Structure):
@@ -28,7 +28,7 @@ class MvnOptions(ctypes.Structure):
 
 class MvnFactor(ctypes.Structure):
     _fields_ = [("n", c_int), ("ld", c_int), ("precision", c_int), ("flags", c_int),
-                ("L", c_void_p), ("info", c_void_p), ("reserved", c_void_p * 4)]
+                ("L", c_void_p), ("info", c_void_p), ("L_low", c_void_p), ("reserved", c_void_p * 3)]
 
 
 class MvnError(RuntimeError):

@@ -37,6 +37,9 @@ constexpr int kMaxGrid = 512;  // persistent sweep workgroups (two per CU on MI3
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 int padded(int n) { return (n + 127) / 128 * 128; }
 
+int elem_bytes_low(int prec) { return prec == MVN_FP32 ? 4 : prec == MVN_BF16 ? 2 : prec == MVN_BF16X3 ? 4 : 0; }
+bool prec_ok(int prec) { return prec >= MVN_FP64 && prec <= MVN_BF16X3; }
+
 bool opts_ok(const mvn_options* o, int* arg_bad_tile) {
   if (!o) return true;
   *arg_bad_tile = 0;
@@ -103,7 +106,7 @@ struct ProbLayout {
   int ld, grid;
 };
 
-ProbLayout prob_layout(int n, int N, int S) {
+ProbLayout prob_layout(int n, int N, int S, int prec) {
   ProbLayout L{};
   L.ld = padded(n);
   const long NS = (long)N * S;
@@ -116,7 +119,8 @@ ProbLayout prob_layout(int n, int N, int S) {
   L.ell = off; off = align_up(off + sizeof(double) * (size_t)NS);
   L.part = off; off = align_up(off + sizeof(double) * 2 * (size_t)S);
   L.bad = off; off = align_up(off + sizeof(int));
-  L.yscr = off; off = align_up(off + sizeof(double) * (size_t)L.grid * L.ld * mvn::sweep_tile_cols());
+  L.yscr = off;
+  off = align_up(off + (size_t)mvn::sweep_elem_bytes(prec) * (size_t)L.grid * mvn::sweep_yslice(prec, L.ld));
   L.total = off;
   return L;
 }
@@ -132,9 +136,10 @@ int mvn_version(void) { return 100; }
 int mvn_factor_bytes(int n, const mvn_options* opts, size_t* bytes) {
   if (n < 1) return fail(-1, "n must be >= 1 (got %d)", n);
   if (!bytes) return fail(-3, "bytes is NULL");
-  (void)opts;
+  const int prec = opts ? opts->precision : MVN_FP64;
+  if (!prec_ok(prec)) return fail(-2, "unknown precision %d", prec);
   const size_t ld = padded(n);
-  *bytes = align_up(sizeof(double) * ld * ld) + kAlign;
+  *bytes = align_up(sizeof(double) * ld * ld) + kAlign + align_up((size_t)elem_bytes_low(prec) * ld * ld);
   return 0;
 }
 
@@ -151,8 +156,9 @@ int mvn_prob_workspace_bytes(int n, int N, int S, const mvn_options* opts, size_
   if (N < 1) return fail(-2, "N must be >= 1 (got %d)", N);
   if (S < 1) return fail(-3, "S must be >= 1 (got %d)", S);
   if (!bytes) return fail(-5, "bytes is NULL");
-  (void)opts;
-  *bytes = prob_layout(n, N, S).total;
+  const int prec = opts ? opts->precision : MVN_FP64;
+  if (!prec_ok(prec)) return fail(-4, "unknown precision %d", prec);
+  *bytes = prob_layout(n, N, S, prec).total;
   return 0;
 }
 
@@ -175,7 +181,7 @@ int mvn_cholesky(int n, const double* d_sigma, int ld_sigma, const double* d_loc
   if (!opts) return fail(-6, "options are required");
   int bad_tile = 0;
   if (!opts_ok(opts, &bad_tile)) return fail(-6, "tile must be >= 16 and a multiple of 4 (got %d)", opts->tile);
-  if (opts->precision != MVN_FP64) return fail(-6, "only MVN_FP64 factors are available in this build");
+  if (!prec_ok(opts->precision)) return fail(-6, "unknown precision %d", opts->precision);
   if (opts->tlr_eps > 0) return fail(-6, "tile low-rank factors are not available in this build");
   size_t need = 0;
   mvn_factor_bytes(n, opts, &need);
@@ -185,18 +191,23 @@ int mvn_cholesky(int n, const double* d_sigma, int ld_sigma, const double* d_loc
   const int ld = padded(n);
   double* L = (double*)factor_buf;
   int* info = (int*)((char*)factor_buf + align_up(sizeof(double) * (size_t)ld * ld));
+  void* low = opts->precision == MVN_FP64
+                  ? nullptr
+                  : (char*)factor_buf + align_up(sizeof(double) * (size_t)ld * ld) + kAlign;
   out->n = n;
   out->ld = ld;
-  out->precision = MVN_FP64;
+  out->precision = opts->precision;
   out->flags = 0;
   out->L = L;
   out->info = info;
-  for (int k = 0; k < 4; ++k) out->reserved[k] = nullptr;
+  out->L_low = low;
+  for (int k = 0; k < 3; ++k) out->reserved[k] = nullptr;
   hipError_t e = mvn::launch_build_matrix(n, ld, d_sigma, ld_sigma, d_locs, kern ? kern->sigma2 : 0,
                                           kern ? kern->beta : 1, kern ? kern->nu : 0.5,
                                           kern ? kern->nugget : 0, L, info, stream);
   if (e != hipSuccess) return hip_fail(e, "build_matrix");
-  e = mvn::launch_cholesky_f64(ld, opts->tile, L, info, stream);
+  e = opts->precision == MVN_FP64 ? mvn::launch_cholesky_f64(ld, opts->tile, L, info, stream)
+                                  : mvn::launch_cholesky_lp(opts->precision, ld, opts->tile, L, info, low, stream);
   if (e != hipSuccess) return hip_fail(e, "cholesky");
   return 0;
 }
@@ -212,9 +223,12 @@ int mvn_prob(const mvn_factor* f, const double* d_a, const double* d_b, const do
   if (S < 1) return fail(-6, "S must be >= 1 (got %d)", S);
   if ((long)N * S > (long)INT32_MAX * 64) return fail(-5, "N*S too large");
   if (!opts) return fail(-8, "options are required");
-  if (opts->precision != MVN_FP64) return fail(-8, "only MVN_FP64 sweeps are available in this build");
+  const int prec = opts->precision;
+  if (!prec_ok(prec)) return fail(-8, "unknown precision %d", prec);
+  if (prec != MVN_FP64 && (prec != f->precision || !f->L_low))
+    return fail(-8, "the factor holds no operand copy for precision %d (built with %d)", prec, f->precision);
   const int n = f->n;
-  const ProbLayout Lay = prob_layout(n, N, S);
+  const ProbLayout Lay = prob_layout(n, N, S, prec);
   if (!ws) return fail(-9, "workspace is NULL");
   if (ws_bytes < Lay.total) return fail(-10, "workspace too small: %zu < %zu", ws_bytes, Lay.total);
   if (!d_out) return fail(-11, "output is NULL");
@@ -227,13 +241,16 @@ int mvn_prob(const mvn_factor* f, const double* d_a, const double* d_b, const do
   double* ell = d_ell ? d_ell : (double*)(w + Lay.ell);
   double* part = (double*)(w + Lay.part);
   int* bad = (int*)(w + Lay.bad);
-  double* yscr = (double*)(w + Lay.yscr);
+  void* yscr = (void*)(w + Lay.yscr);
   hipError_t e = hipMemcpyAsync(dlat, lat, sizeof(uint64_t) * n, hipMemcpyHostToDevice, stream);
   if (e != hipSuccess) return hip_fail(e, "lattice copy");
   e = mvn::launch_prob_setup(n, f->ld, d_a, d_b, d_mu, at, bt, bad, stream);
   if (e != hipSuccess) return hip_fail(e, "setup");
   mvn::SweepArgs sa{};
   sa.L = f->L;
+  sa.Llow = prec == MVN_FP64 ? (const void*)f->L : f->L_low;
+  sa.prec = prec;
+  sa.yslice = mvn::sweep_yslice(prec, f->ld);
   sa.ld = f->ld;
   sa.n = n;
   sa.at = at;
@@ -246,7 +263,7 @@ int mvn_prob(const mvn_factor* f, const double* d_a, const double* d_b, const do
   sa.yscr = yscr;
   sa.ell = ell;
   sa.grid = Lay.grid;
-  e = mvn::launch_sweep_f64(sa, stream);
+  e = mvn::launch_sweep(sa, stream);
   if (e != hipSuccess) return hip_fail(e, "sweep");
   e = mvn::launch_reduce(ell, N, S, part, f->info, bad, d_out, stream);
   if (e != hipSuccess) return hip_fail(e, "reduce");

@@ -15,6 +15,7 @@
 
 #include "gemm_f64.h"
 #include "launch.h"
+#include "sweep_gemm.h"
 
 namespace mvn {
 
@@ -249,6 +250,157 @@ hipError_t launch_cholesky_f64(int ld, int tile, double* A, int* info, hipStream
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(zero_upper_kernel, dim3(ld / 16, ld / 16), dim3(256), 0, st, A, ld);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ mixed precision
+// Trailing update C -= P P^T with the products in FP32 or BF16 on MFMA and
+// FP32 accumulation (C stays FP64).  128 x 64 tiles of C on the sweep's GEMM
+// policies; P (FP64) is converted while it is staged into LDS.
+template <class G>
+struct SyrkStage;
+
+template <>
+struct SyrkStage<GemmF32> {
+  using G = GemmF32;
+  struct Regs { double a[16]; double b[8]; };
+  static __device__ __forceinline__ void load(const double* A, long ld, long ra0, long rb0, long k0,
+                                              long klim, Regs& r) {
+    const int t = threadIdx.x;
+    const long row = ra0 + (t >> 1), kb = k0 + (t & 1) * 16;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) r.a[q] = (row < ld && kb + q < klim) ? A[row * ld + kb + q] : 0.0;
+    const long cr = rb0 + (t >> 2), kc = k0 + (t & 3) * 8;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) r.b[q] = (cr < ld && kc + q < klim) ? A[cr * ld + kc + q] : 0.0;
+  }
+  static __device__ __forceinline__ void store(void* stage, const Regs& r) {
+    float* As = (float*)stage;
+    float* Bs = As + G::kAStage;
+    const int t = threadIdx.x;
+    const int row = t >> 1, kb = (t & 1) * 16;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) As[(kb + q) * G::kALd + row] = (float)r.a[q];
+    const int c = t >> 2, kc = (t & 3) * 8;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) Bs[(kc + q) * G::kBLd + c] = (float)r.b[q];
+  }
+};
+
+template <int SPLIT>
+struct SyrkStage<GemmBF16T<SPLIT>> {
+  using G = GemmBF16T<SPLIT>;
+  static constexpr int kAH = G::kK / 2, kBQ = G::kK / 4;
+  struct Regs { double a[kAH]; double b[kBQ]; };
+  static __device__ __forceinline__ void load(const double* A, long ld, long ra0, long rb0, long k0,
+                                              long klim, Regs& r) {
+    const int t = threadIdx.x;
+    const long row = ra0 + (t >> 1), kb = k0 + (t & 1) * kAH;
+#pragma unroll
+    for (int q = 0; q < kAH; ++q) r.a[q] = (row < ld && kb + q < klim) ? A[row * ld + kb + q] : 0.0;
+    const long cr = rb0 + (t >> 2), kc = k0 + (t & 3) * kBQ;
+#pragma unroll
+    for (int q = 0; q < kBQ; ++q) r.b[q] = (cr < ld && kc + q < klim) ? A[cr * ld + kc + q] : 0.0;
+  }
+  static __device__ __forceinline__ void store(void* stage, const Regs& r) {
+    __bf16* As = (__bf16*)stage;
+    __bf16* Bs = As + G::kAStage;
+    const int t = threadIdx.x;
+    __bf16* da = As + (t >> 1) * G::kALd + (t & 1) * kAH;
+#pragma unroll
+    for (int q = 0; q < kAH; ++q) {
+      const __bf16 hi = to_bf16(r.a[q]);
+      da[q] = hi;
+      if (SPLIT == 2) da[G::kAPlane + q] = to_bf16(r.a[q] - (double)(float)hi);
+    }
+    __bf16* db = Bs + (t >> 2) * G::kBLd + (t & 3) * kBQ;
+#pragma unroll
+    for (int q = 0; q < kBQ; ++q) {
+      const __bf16 hi = to_bf16(r.b[q]);
+      db[q] = hi;
+      if (SPLIT == 2) db[G::kBPlane + q] = to_bf16(r.b[q] - (double)(float)hi);
+    }
+  }
+};
+
+template <class G>
+__global__ __launch_bounds__(256) void chol_syrk_lp_kernel(double* __restrict__ A, int ld, int k0, int kw,
+                                                           const int* __restrict__ info) {
+  if (*info != 0) return;
+  __shared__ __attribute__((aligned(16))) double lds[kTile * kCols];
+  const long r0 = (long)k0 + kw;
+  const long rowA = r0 + (long)blockIdx.y * kTile, colB = r0 + (long)blockIdx.x * kCols;
+  if (colB > rowA + kTile - 1 || rowA >= ld) return;  // tile entirely above the diagonal
+  typename G::Acc acc;
+  G::zero(acc);
+  const long klim = (long)k0 + kw;
+  const int nst = (kw + G::kK - 1) / G::kK;
+  char* st0 = (char*)lds;
+  char* st1 = (char*)lds + G::kStageBytes;
+  typename SyrkStage<G>::Regs r;
+  SyrkStage<G>::load(A, ld, rowA, colB, k0, klim, r);
+  SyrkStage<G>::store(st0, r);
+  __syncthreads();
+  for (int s = 0; s < nst; ++s) {
+    const bool odd = s & 1;
+    if (s + 1 < nst) SyrkStage<G>::load(A, ld, rowA, colB, (long)k0 + (long)(s + 1) * G::kK, klim, r);
+    G::mma(odd ? st1 : st0, acc);
+    if (s + 1 < nst) SyrkStage<G>::store(odd ? st0 : st1, r);
+    __syncthreads();
+  }
+  G::to_block(acc, lds);
+  __syncthreads();
+  for (int e = threadIdx.x; e < kTile * kCols; e += 256) {
+    const long gi = rowA + e / kCols, gj = colB + e % kCols;
+    if (gi < ld && gj < ld && gj <= gi) A[gi * ld + gj] -= lds[e];
+  }
+}
+
+// Low-precision operand copy of the finished factor for the sweep's GEMM:
+// FP32, BF16, or BF16 hi and lo planes (x = hi + lo).
+template <class E, int SPLIT>
+__global__ __launch_bounds__(256) void convert_factor_kernel(const double* __restrict__ L, long ld,
+                                                             E* __restrict__ out) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= ld * ld) return;
+  const double v = L[e];
+  const E hi = (E)(float)v;
+  out[e] = hi;
+  if (SPLIT == 2) out[ld * ld + e] = (E)(float)(v - (double)(float)hi);
+}
+
+hipError_t launch_cholesky_lp(int prec, int ld, int tile, double* A, int* info, void* low, hipStream_t st) {
+  for (int k0 = 0; k0 < ld; k0 += tile) {
+    const int kw = min(tile, ld - k0);
+    for (int j0 = k0; j0 < k0 + kw; j0 += kSub) {
+      const int jw = min(kSub, k0 + kw - j0);
+      hipLaunchKernelGGL(chol_diag_kernel, dim3(1), dim3(256), 0, st, A, ld, k0, j0, jw, info);
+      const int rows = ld - (j0 + jw);
+      if (rows > 0)
+        hipLaunchKernelGGL(chol_trsm_kernel, dim3((rows + 255) / 256), dim3(256), 0, st, A, ld, k0,
+                           j0, jw, (const int*)info);
+    }
+    const int rem = ld - (k0 + kw);
+    if (rem > 0) {
+      dim3 grid((rem + kCols - 1) / kCols, (rem + kTile - 1) / kTile);
+      switch (prec) {
+        case 1: hipLaunchKernelGGL(chol_syrk_lp_kernel<GemmF32>, grid, dim3(256), 0, st, A, ld, k0, kw, (const int*)info); break;
+        case 2: hipLaunchKernelGGL(chol_syrk_lp_kernel<GemmBF16>, grid, dim3(256), 0, st, A, ld, k0, kw, (const int*)info); break;
+        case 3: hipLaunchKernelGGL(chol_syrk_lp_kernel<GemmBF16x3>, grid, dim3(256), 0, st, A, ld, k0, kw, (const int*)info); break;
+        default: return hipErrorInvalidValue;
+      }
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(zero_upper_kernel, dim3(ld / 16, ld / 16), dim3(256), 0, st, A, ld);
+  const long tot = (long)ld * ld;
+  const dim3 cg((unsigned)((tot + 255) / 256));
+  switch (prec) {
+    case 1: hipLaunchKernelGGL((convert_factor_kernel<float, 1>), cg, dim3(256), 0, st, (const double*)A, (long)ld, (float*)low); break;
+    case 2: hipLaunchKernelGGL((convert_factor_kernel<__bf16, 1>), cg, dim3(256), 0, st, (const double*)A, (long)ld, (__bf16*)low); break;
+    case 3: hipLaunchKernelGGL((convert_factor_kernel<__bf16, 2>), cg, dim3(256), 0, st, (const double*)A, (long)ld, (__bf16*)low); break;
+  }
   return hipGetLastError();
 }
 

@@ -6,7 +6,8 @@
 // dimension, Section IV-C), so one workgroup owns a block of 64 sample
 // columns for the whole sweep and never synchronises with other workgroups;
 // only the factor L is shared.  For each block row r of 128 dimensions:
-//   1. S = L[r-block, 0:r*128] . Y[0:r*128, cols]   (FP64 MFMA, K = r*128)
+//   1. S = L[r-block, 0:r*128] . Y[0:r*128, cols]   (MFMA, K = r*128, in
+//      FP64, or FP32 / BF16 / split BF16 with FP32 accumulation)
 //      - the paper's GEMM update of the limit matrices A and B, applied
 //        once to a shared shift instead of to two copies of the limits;
 //   2. conditioning of the diagonal block, one lane per sample column:
@@ -24,6 +25,7 @@
 #include "gemm_f64.h"
 #include "launch.h"
 #include "mvn_device.h"
+#include "sweep_gemm.h"
 
 namespace mvn {
 
@@ -59,58 +61,21 @@ hipError_t launch_prob_setup(int n, int ld, const double* a, const double* b, co
 }
 
 // ------------------------------------------------------------ the sweep
-// Tile of the sweep: 128 block rows x 64 sample columns per workgroup of
-// four wave64s; wave w owns rows [32 w, 32 w + 32) x all 64 columns, i.e.
-// 2 x 4 blocks of the 16 x 16 FP64 MFMA.  76 KB of LDS and <= 256 registers
-// per lane let two workgroups share a CU, so one workgroup's conditioning
-// (VALU) overlaps the other's GEMM (MFMA).
-constexpr int kCols = 64;                         // sample columns per workgroup
-constexpr int kBLd = kCols + 1;                   // LDS row stride of the Y stage
-constexpr int kBStage = kStageK * kBLd;
-constexpr int kSlab = 8;                          // rows of L staged per LDS slab
+// One workgroup of four wave64s owns 64 sample columns (see sweep_gemm.h for
+// the GEMM tiling).  76 KB of LDS and <= 256 registers per lane let two
+// workgroups share a CU, so one workgroup's conditioning (VALU) can overlap
+// the other's GEMM (MFMA).
+constexpr int kSlab = 8;  // rows of the diagonal block of L staged per LDS slab
 
 int sweep_tile_cols() { return kCols; }
 
-__device__ __forceinline__ void load_y(const double* __restrict__ Y, long k0, double (&r)[4]) {
-  const int t = threadIdx.x;
-  const double2* p2 = reinterpret_cast<const double2*>(Y + (k0 + (t >> 4)) * kCols + (t & 15) * 4);
-  const double2 v0 = p2[0], v1 = p2[1];
-  r[0] = v0.x; r[1] = v0.y; r[2] = v1.x; r[3] = v1.y;
-}
-
-__device__ __forceinline__ void store_y(double* __restrict__ lds, const double (&r)[4]) {
-  const int t = threadIdx.x;
-  double* d = lds + (t >> 4) * kBLd + (t & 15) * 4;
-  d[0] = r[0]; d[1] = r[1]; d[2] = r[2]; d[3] = r[3];
-}
-
-struct SweepAcc {
-  f64x4 v[2][4];
-};
-
-__device__ __forceinline__ void sweep_mma(const double* __restrict__ As, const double* __restrict__ Bs,
-                                          SweepAcc& acc) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-#pragma unroll
-  for (int kk = 0; kk < kStageK / 4; ++kk) {
-    const int k = kk * 4 + (lane >> 4);
-    double a[2], b[4];
-#pragma unroll
-    for (int ib = 0; ib < 2; ++ib) a[ib] = As[k * kLdsLd + w * 32 + ib * 16 + (lane & 15)];
-#pragma unroll
-    for (int jb = 0; jb < 4; ++jb) b[jb] = Bs[k * kBLd + jb * 16 + (lane & 15)];
-#pragma unroll
-    for (int ib = 0; ib < 2; ++ib)
-#pragma unroll
-      for (int jb = 0; jb < 4; ++jb)
-        acc.v[ib][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ib], b[jb], acc.v[ib][jb], 0, 0, 0);
-  }
-}
-
-__global__ __launch_bounds__(256, 2) void sweep_f64_kernel(SweepArgs p) {
+template <class G>
+__global__ __launch_bounds__(256, 2) void sweep_kernel(SweepArgs p) {
+  using E = typename G::E;
+  static_assert(2 * G::kStageBytes <= kTile * kCols * 8, "GEMM stages must fit in the block buffer");
   // 64 KB: double-buffered GEMM stages during step 1, then the 128 x 64
-  // block T (S, overwritten row by row with y) during step 2.
-  __shared__ double lds[kTile * kCols];
+  // FP64 block T (S, overwritten row by row with y) during step 2.
+  __shared__ __attribute__((aligned(16))) double lds[kTile * kCols];
   // step 2 operands: a slab of rows of the diagonal block of L, and the
   // block's per-row constants (limits, 1/L_ii, lattice generator)
   __shared__ double slab[kSlab * kTile];
@@ -119,12 +84,11 @@ __global__ __launch_bounds__(256, 2) void sweep_f64_kernel(SweepArgs p) {
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const long NS = (long)p.N * p.S;
   const long nchunks = (NS + kCols - 1) / kCols;
-  double* Y = p.yscr + (long)blockIdx.x * p.ld * kCols;
   const long ld = p.ld;
-  double* As0 = lds;
-  double* Bs0 = lds + kStageDoubles;
-  double* As1 = lds + kStageDoubles + kBStage;
-  double* Bs1 = As1 + kStageDoubles;
+  const E* Lg = (const E*)p.Llow;
+  E* Y = (E*)p.yscr + (long)blockIdx.x * p.yslice;
+  char* stage0 = (char*)lds;
+  char* stage1 = (char*)lds + G::kStageBytes;
 
   for (long chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x) {
     const long col = chunk * kCols + lane;
@@ -136,42 +100,25 @@ __global__ __launch_bounds__(256, 2) void sweep_f64_kernel(SweepArgs p) {
 
     for (int i0 = 0; i0 < p.n; i0 += kTile) {
       const int rows = min(kTile, p.n - i0);
-      SweepAcc acc;
-#pragma unroll
-      for (int ib = 0; ib < 2; ++ib)
-#pragma unroll
-        for (int jb = 0; jb < 4; ++jb) acc.v[ib][jb] = f64x4{0.0, 0.0, 0.0, 0.0};
+      typename G::Acc acc;
+      G::zero(acc);
       // ---- step 1: S = L[i0:i0+128, 0:i0] Y[0:i0, :]
       if (i0 > 0) {
-        const int nst = i0 / kStageK;
-        double ra[8], rb[4];
-        load_rows<false>(p.L, ld, i0, 0, 0, 0, ra);
-        load_y(Y, 0, rb);
-        store_rows(As0, ra);
-        store_y(Bs0, rb);
+        const int nst = i0 / G::kK;
+        typename G::Regs r;
+        G::load(Lg, ld, i0, 0, Y, ld, r);
+        G::store(stage0, r);
         __syncthreads();
         for (int s = 0; s < nst; ++s) {
           const bool odd = s & 1;
-          if (s + 1 < nst) {
-            load_rows<false>(p.L, ld, i0, (long)(s + 1) * kStageK, 0, 0, ra);
-            load_y(Y, (long)(s + 1) * kStageK, rb);
-          }
-          sweep_mma(odd ? As1 : As0, odd ? Bs1 : Bs0, acc);
-          if (s + 1 < nst) {
-            store_rows(odd ? As0 : As1, ra);
-            store_y(odd ? Bs0 : Bs1, rb);
-          }
+          if (s + 1 < nst) G::load(Lg, ld, i0, (long)(s + 1) * G::kK, Y, ld, r);
+          G::mma(odd ? stage1 : stage0, acc);
+          if (s + 1 < nst) G::store(odd ? stage0 : stage1, r);
           __syncthreads();
         }
       }
-      // accumulators -> T[row][col]; per-row constants -> LDS
-#pragma unroll
-      for (int ib = 0; ib < 2; ++ib)
-#pragma unroll
-        for (int jb = 0; jb < 4; ++jb)
-#pragma unroll
-          for (int r = 0; r < 4; ++r)
-            lds[(wv * 32 + ib * 16 + (lane >> 4) + 4 * r) * kCols + jb * 16 + (lane & 15)] = acc.v[ib][jb][r];
+      // accumulators -> T[row][col] in FP64; per-row constants -> LDS
+      G::to_block(acc, lds);
       if (t < rows) {
         const long g = i0 + t;
         c_at[t] = p.at[g];
@@ -180,7 +127,7 @@ __global__ __launch_bounds__(256, 2) void sweep_f64_kernel(SweepArgs p) {
         c_lat[t] = p.lattice[g];
       }
       // ---- step 2: conditioning of the diagonal block by wave 0, lane =
-      // column, in slabs of rows whose L entries are staged in LDS
+      // column, in slabs of rows whose FP64 L entries are staged in LDS
       for (int q = 0; q < rows; q += kSlab) {
         __syncthreads();
         for (int e = t; e < kSlab * kTile; e += 256) {
@@ -222,16 +169,29 @@ __global__ __launch_bounds__(256, 2) void sweep_f64_kernel(SweepArgs p) {
         }
       }
       __syncthreads();
-      // ---- step 3: y block -> scratch
-      for (int e = t; e < rows * kCols; e += 256) Y[(long)i0 * kCols + e] = lds[e];
+      // ---- step 3: y block -> scratch (in the GEMM's operand type)
+      G::put_y(lds, Y, ld, i0, rows);
       __syncthreads();
     }
     if (valid) p.ell[col] = ell;
   }
 }
 
-hipError_t launch_sweep_f64(const SweepArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(sweep_f64_kernel, dim3(a.grid), dim3(256), 0, st, a);
+long sweep_yslice(int prec, int ld) {
+  // elements per workgroup slice of the Y scratch, and bytes per element
+  return (long)ld * kCols * (prec == 3 ? 2 : 1);
+}
+
+int sweep_elem_bytes(int prec) { return prec == 0 ? 8 : prec == 1 ? 4 : 2; }
+
+hipError_t launch_sweep(const SweepArgs& a, hipStream_t st) {
+  switch (a.prec) {
+    case 0: hipLaunchKernelGGL(sweep_kernel<GemmF64>, dim3(a.grid), dim3(256), 0, st, a); break;
+    case 1: hipLaunchKernelGGL(sweep_kernel<GemmF32>, dim3(a.grid), dim3(256), 0, st, a); break;
+    case 2: hipLaunchKernelGGL(sweep_kernel<GemmBF16>, dim3(a.grid), dim3(256), 0, st, a); break;
+    case 3: hipLaunchKernelGGL(sweep_kernel<GemmBF16x3>, dim3(a.grid), dim3(256), 0, st, a); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -16,16 +16,25 @@ hipError_t launch_build_matrix(int n, int ld, const double* sigma, int lds, cons
 // 1-based index of the first non-positive pivot.  Upper triangle zeroed.
 hipError_t launch_cholesky_f64(int ld, int tile, double* A, int* info, hipStream_t st);
 
+// The same factorisation with the trailing updates in FP32 (prec 1), BF16
+// (2) or split BF16 (3) on MFMA, followed by the low-precision operand copy
+// of L for the sweep (`low`: ld*ld floats, ld*ld BF16, or two BF16 planes).
+hipError_t launch_cholesky_lp(int prec, int ld, int tile, double* A, int* info, void* low,
+                              hipStream_t st);
+
 struct SweepArgs {
-  const double* L;
+  const double* L;         // FP64 factor (diagonal blocks, pivots)
+  const void* Llow;        // factor in the GEMM's operand type (== L for FP64)
   int ld;
   int n;
+  int prec;                // 0 FP64, 1 FP32, 2 BF16, 3 split BF16 (x3)
   const double* at;        // centred lower limits (padded to ld)
   const double* bt;        // centred upper limits
   const uint64_t* lattice; // A_i, n entries
   uint64_t seed;           // shift D_{s,i} = SplitMix64 output s*n + i from this state
   int N, S, periodize;
-  double* yscr;            // per-workgroup scratch, grid x ld x 128 doubles
+  void* yscr;              // per-workgroup Y scratch, grid x yslice elements
+  long yslice;
   double* ell;             // N*S per-sample log-products
   int grid;                // persistent workgroups
 };
@@ -34,7 +43,9 @@ struct SweepArgs {
 hipError_t launch_prob_setup(int n, int ld, const double* a, const double* b, const double* mu,
                              double* at, double* bt, int* bad, hipStream_t st);
 
-hipError_t launch_sweep_f64(const SweepArgs& a, hipStream_t st);
+hipError_t launch_sweep(const SweepArgs& a, hipStream_t st);
+long sweep_yslice(int prec, int ld);
+int sweep_elem_bytes(int prec);
 
 // log-sum-exp over samples, per shift and overall, into out[4 + S].
 hipError_t launch_reduce(const double* ell, int N, int S, double* part, const int* info_factor,
