@@ -21,6 +21,11 @@ ARCH = os.environ.get("MVN_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["api.cpp", "kernels_chol.hip", "kernels_sov.hip"]
 
+# Per-file extra flags.  The sweep inlines the FP64 conditioning step into
+# its row loop; machine loop-invariant code motion would hoist the step's
+# ~60 materialised 64-bit constants out of that loop and spill registers.
+EXTRA_FLAGS = {"kernels_sov.hip": ["-mllvm", "-disable-machine-licm"]}
+
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     # packed FP32 instructions off for all device code
@@ -38,7 +43,7 @@ def _hipcc() -> str:
 
 def _compile(src: str) -> str:
     obj = os.path.join(OBJ, os.path.basename(src) + ".o")
-    cmd = [_hipcc(), *HIPCC_FLAGS, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj,
+    cmd = [_hipcc(), *HIPCC_FLAGS, *EXTRA_FLAGS.get(src, []), "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj,
            f"-I{os.path.join(ROOT, 'include')}"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:

@@ -18,10 +18,9 @@
 #include <math.h>
 
 #define MVN_HD __host__ __device__ __forceinline__
-// The conditioning step is kept out of line on the device: inlined into
-// the sweep's row loop, loop-invariant code motion would pin its ~60
-// polynomial constants in registers for the whole loop.  (Host builds of
-// this header, used to check the arithmetic on the CPU, inline it.)
+// Rare paths and check wrappers are kept out of line on the device so they
+// add no register pressure where the common path is inlined.  (Host builds
+// of this header, used to check the arithmetic on the CPU, inline them.)
 #if defined(__HIP_DEVICE_COMPILE__)
 #define MVN_HD_COLD __host__ __device__ __attribute__((noinline))
 #else
@@ -107,13 +106,19 @@ MVN_HD double ninv_log(double lp) {
 }
 
 // ---------------------------------------------------------------- the step
+// Result of one step: y, and the factor d = m * 2^e (e = 0 except in the
+// log-scale branch, where d itself would underflow; m = 0 marks a sample
+// whose interval has zero mass).
 struct Step {
   double y;
-  double logd;
+  double m;
+  int e;
 };
 
-// Both ends below -35: d and p from log Phi (returns y and log d in the
-// unreflected frame of (lo, hi)).  Rare, so out of line as well.
+constexpr double kLn2 = 0.69314718055994530942;
+
+// Both ends below -35: d and p from log Phi (y and d in the unreflected
+// frame of (lo, hi)).  Rare, so out of line.
 MVN_HD_COLD Step deep_tail(double lo, double hi, double u) {
   const double la = log_ncdf_lower(lo);
   const double lb = log_ncdf_lower(hi);
@@ -122,41 +127,70 @@ MVN_HD_COLD Step deep_tail(double lo, double hi, double u) {
   // logaddexp(la, t)
   const double mx = la > t ? la : t;
   const double lp = (mx == -INFINITY) ? -INFINITY : mx + log1p(exp(-fabs(la - t)));
-  return Step{ninv_log(lp), logd};
+  if (!(logd > -INFINITY)) return Step{0.0, 0.0, 0};
+  const double ef = floor(logd / kLn2);
+  return Step{ninv_log(lp), exp(logd - ef * kLn2), (int)ef};
 }
 
 // One conditioning step (see header comment).  w in (0,1); cw = 1 - w.
-MVN_HD_COLD Step condition(double alpha, double beta, double w, double cw) {
+MVN_HD Step condition_step(double alpha, double beta, double w, double cw) {
   const bool refl = alpha > 0.0;
   const double lo = refl ? -beta : alpha;
   const double hi = refl ? -alpha : beta;
   const double u = refl ? cw : w;
   const double v = refl ? w : cw;
-  double y, logd;
+  Step st;
   if (!(hi < kDeepTail)) {
-    const double pa = ncdf(lo);
+    // Phi(-inf) = 0 needs no erfc (every row with an infinite lower limit)
+    const double pa = (lo == -INFINITY) ? 0.0 : ncdf(lo);
     // one erfc serves both Phi(hi) and Phi(-hi)
     const double e = 0.5 * erfc(fabs(hi) * kSqrt1_2);
     const double pb = hi > 0.0 ? 1.0 - e : e;
     const double qb = hi > 0.0 ? e : 1.0 - e;
     const double d = pb - pa;
     const double p = pa + u * d;
-    if (p <= 0.5) {
-      y = ninv_lower(p);
-    } else {
-      y = -ninv_lower(qb + v * d);
-    }
-    logd = log(d);
+    st.y = (p <= 0.5) ? ninv_lower(p) : -ninv_lower(qb + v * d);
+    st.m = d;
+    st.e = 0;
   } else {
-    const Step s = deep_tail(lo, hi, u);
-    y = s.y;
-    logd = s.logd;
+    st = deep_tail(lo, hi, u);
   }
-  if (!(logd > -INFINITY)) {  // zero mass (or NaN): dead sample
-    y = 0.0;
-    logd = -INFINITY;
+  if (!(st.m > 0.0)) {  // zero mass (or NaN): dead sample
+    st.y = 0.0;
+    st.m = 0.0;
+    st.e = 0;
   }
-  return Step{refl ? -y : y, logd};
+  if (refl) st.y = -st.y;
+  return st;
+}
+
+// Running product of the d_i as m * 2^e with m renormalised into [1/2, 1)
+// after every factor: exact exponent bookkeeping, one log per sample at
+// the end instead of one per step.
+struct LogProd {
+  double m;
+  int e;
+};
+
+MVN_HD void logprod_mul(LogProd& a, const Step& s) {
+  int k;
+  a.m = frexp(a.m * s.m, &k);
+  a.e += k + s.e;
+}
+
+MVN_HD double logprod_log(const LogProd& a) {
+  return a.m > 0.0 ? log(a.m) + (double)a.e * kLn2 : -INFINITY;
+}
+
+// (y, log d) of one step, for checks of the arithmetic.
+struct StepLog {
+  double y;
+  double logd;
+};
+
+MVN_HD_COLD StepLog condition(double alpha, double beta, double w, double cw) {
+  const Step s = condition_step(alpha, beta, w, cw);
+  return StepLog{s.y, s.m > 0.0 ? log(s.m) + (double)s.e * kLn2 : -INFINITY};
 }
 
 // ---------------------------------------------------------------- QMC points

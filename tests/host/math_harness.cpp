@@ -32,7 +32,7 @@ int main() {
       printf("%.17g\n", mvn::log_ncdf_lower(x));
     } else if (!strcmp(op, "cond")) {
       scanf("%lf %lf %lf", &x, &y, &w);
-      mvn::Step s = mvn::condition(x, y, w, 1.0 - w);
+      mvn::StepLog s = mvn::condition(x, y, w, 1.0 - w);
       printf("%.17g %.17g\n", s.y, s.logd);
     } else if (!strcmp(op, "sm")) {
       unsigned long long seed, k;
