@@ -117,6 +117,21 @@ int mvn_prob(const mvn_factor* f, const double* d_a, const double* d_b, const do
              int N, int S, uint64_t seed, const mvn_options* opts,
              void* ws, size_t ws_bytes, double* d_out, double* d_ell, hipStream_t stream);
 
+/* Gradient of log P-hat at fixed QMC points (the same estimator and points
+ * as mvn_prob): reverse-mode differentiation of the recurrence of Eq. (sov1),
+ * with checkpointed shifts s_i instead of stored y.  FP64.
+ *   d_out            as for mvn_prob (4 + S doubles)
+ *   d_da, d_db       device, n doubles each (or NULL): d log P-hat / d a_i,
+ *                    d log P-hat / d b_i
+ *   d_dmu            device, n doubles (or NULL): d log P-hat / d mu_i =
+ *                    -(d/da_i + d/db_i)
+ * Infinite limits get a zero derivative.  All outputs NaN under the same
+ * conditions as mvn_prob, or when every sample has zero mass. */
+int mvn_prob_grad_workspace_bytes(int n, int N, int S, const mvn_options* opts, size_t* bytes);
+int mvn_prob_grad(const mvn_factor* f, const double* d_a, const double* d_b, const double* d_mu,
+                  int N, int S, uint64_t seed, const mvn_options* opts, void* ws, size_t ws_bytes,
+                  double* d_out, double* d_da, double* d_db, double* d_dmu, hipStream_t stream);
+
 /* Message for the last negative return on this thread ("" if none). */
 const char* mvn_last_error(void);
 

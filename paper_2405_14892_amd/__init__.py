@@ -16,6 +16,7 @@ from ._lib import (MVN_BF16, MVN_BF16X3, MVN_FP32, MVN_FP64, MvnError, MvnFactor
                    MvnMatern, MvnOptions, options)
 
 __all__ = ["mvn_factor_bytes", "mvn_prob_workspace_bytes", "mvn_cholesky", "mvn_prob", "Factor",
+           "mvn_prob_grad_workspace_bytes", "mvn_prob_grad", "MVNLogProb",
            "options", "MvnError", "MVN_FP64", "MVN_FP32", "MVN_BF16", "MVN_BF16X3", "library_path"]
 
 
@@ -128,3 +129,68 @@ def mvn_prob(f: Factor, a, b, mu=None, N: int = 1000, S: int = 10, seed: int = 1
     if return_ell:
         res["ell"] = ell
     return res
+
+
+def mvn_prob_grad_workspace_bytes(n: int, N: int, S: int, opts: MvnOptions | None = None) -> int:
+    out = ctypes.c_size_t(0)
+    _lib.check(_lib.lib().mvn_prob_grad_workspace_bytes(n, N, S, ctypes.byref(opts or options()),
+                                                        ctypes.byref(out)))
+    return out.value
+
+
+def mvn_prob_grad(f: Factor, a, b, mu=None, N: int = 1000, S: int = 1, seed: int = 1,
+                  opts: MvnOptions | None = None):
+    """log P-hat and its gradient w.r.t. a, b, mu at fixed QMC points.
+    Returns a dict of device tensors: logP, P, out[4+S], da, db, dmu."""
+    torch = _torch()
+    opts = opts or options()
+    dev = f.device
+    ta, tb = _dev_f64(a, dev), _dev_f64(b, dev)
+    tm = _dev_f64(mu, dev) if mu is not None else None
+    wsb = mvn_prob_grad_workspace_bytes(f.n, N, S, opts)
+    ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    out = torch.empty(4 + S, dtype=torch.float64, device=dev)
+    da = torch.empty(f.n, dtype=torch.float64, device=dev)
+    db = torch.empty(f.n, dtype=torch.float64, device=dev)
+    dmu = torch.empty(f.n, dtype=torch.float64, device=dev)
+    code = _lib.lib().mvn_prob_grad(ctypes.byref(f.handle), _ptr(ta), _ptr(tb), _ptr(tm), N, S,
+                                    ctypes.c_uint64(seed), ctypes.byref(opts), _ptr(ws), wsb, _ptr(out),
+                                    _ptr(da), _ptr(db), _ptr(dmu), _stream(dev))
+    _lib.check(code)
+    return {"logP": out[0], "P": out[1], "out": out, "da": da, "db": db, "dmu": dmu,
+            "_keep": (ta, tb, tm, ws)}
+
+
+def _make_autograd():
+    torch = _torch()
+
+    class MVNLogProb(torch.autograd.Function):
+        """log P(a <= X <= b), X ~ N(mu, L L^T), as a differentiable function
+        of (a, b, mu) at fixed QMC points.  forward calls mvn_prob_grad (the
+        adjoint sweep runs with the forward sweep, on the same points) and
+        saves the gradients; backward scales them by the incoming gradient."""
+
+        @staticmethod
+        def forward(ctx, a, b, mu, factor, N, S, seed):
+            r = mvn_prob_grad(factor, a.detach(), b.detach(), mu.detach(), N=N, S=S, seed=seed)
+            ctx.save_for_backward(r["da"], r["db"], r["dmu"])
+            return r["logP"].clone().to(a.dtype)
+
+        @staticmethod
+        def backward(ctx, g):
+            da, db, dmu = ctx.saved_tensors
+            return g * da, g * db, g * dmu, None, None, None, None
+
+    return MVNLogProb
+
+
+class _LazyAutograd:
+    _cls = None
+
+    def __getattr__(self, name):
+        if _LazyAutograd._cls is None:
+            _LazyAutograd._cls = _make_autograd()
+        return getattr(_LazyAutograd._cls, name)
+
+
+MVNLogProb = _LazyAutograd()

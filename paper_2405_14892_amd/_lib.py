@@ -48,6 +48,10 @@ SIGNATURES = {
                              c_void_p, c_size_t, c_void_p, c_size_t, POINTER(MvnFactor), c_void_p]),
     "mvn_prob": (c_int, [POINTER(MvnFactor), c_void_p, c_void_p, c_void_p, c_int, c_int, c_uint64,
                          POINTER(MvnOptions), c_void_p, c_size_t, c_void_p, c_void_p, c_void_p]),
+    "mvn_prob_grad_workspace_bytes": (c_int, [c_int, c_int, c_int, POINTER(MvnOptions), POINTER(c_size_t)]),
+    "mvn_prob_grad": (c_int, [POINTER(MvnFactor), c_void_p, c_void_p, c_void_p, c_int, c_int, c_uint64,
+                              POINTER(MvnOptions), c_void_p, c_size_t, c_void_p, c_void_p, c_void_p,
+                              c_void_p, c_void_p]),
     "mvn_last_error": (ctypes.c_char_p, []),
     "mvn_version": (c_int, []),
 }

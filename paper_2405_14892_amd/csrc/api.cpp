@@ -125,6 +125,36 @@ ProbLayout prob_layout(int n, int N, int S, int prec) {
   return L;
 }
 
+struct GradLayout {
+  size_t at, bt, lat, ell, part, bad, yscr, sfw, sbar, gpart, mz, scale, total;
+  int ld, grid;
+  long nchunks;
+};
+
+GradLayout grad_layout(int n, int N, int S) {
+  GradLayout L{};
+  L.ld = padded(n);
+  const long NS = (long)N * S;
+  L.nchunks = (NS + mvn::sweep_tile_cols() - 1) / mvn::sweep_tile_cols();
+  L.grid = (int)(L.nchunks < kMaxGrid ? L.nchunks : kMaxGrid);
+  const size_t slice = sizeof(double) * (size_t)L.ld * mvn::sweep_tile_cols();
+  size_t off = 0;
+  L.at = off; off = align_up(off + sizeof(double) * L.ld);
+  L.bt = off; off = align_up(off + sizeof(double) * L.ld);
+  L.lat = off; off = align_up(off + sizeof(uint64_t) * L.ld);
+  L.ell = off; off = align_up(off + sizeof(double) * (size_t)NS);
+  L.part = off; off = align_up(off + sizeof(double) * 2 * (size_t)S);
+  L.bad = off; off = align_up(off + sizeof(int));
+  L.yscr = off; off = align_up(off + slice * L.grid);
+  L.sfw = off; off = align_up(off + slice * L.grid);
+  L.sbar = off; off = align_up(off + slice * L.grid);
+  L.gpart = off; off = align_up(off + sizeof(double) * 2 * (size_t)L.ld * L.nchunks);
+  L.mz = off; off = align_up(off + sizeof(double) * 2 * (size_t)L.nchunks);
+  L.scale = off; off = align_up(off + sizeof(double) * ((size_t)L.nchunks + 1));
+  L.total = off;
+  return L;
+}
+
 }  // namespace
 
 extern "C" {
@@ -159,6 +189,16 @@ int mvn_prob_workspace_bytes(int n, int N, int S, const mvn_options* opts, size_
   const int prec = opts ? opts->precision : MVN_FP64;
   if (!prec_ok(prec)) return fail(-4, "unknown precision %d", prec);
   *bytes = prob_layout(n, N, S, prec).total;
+  return 0;
+}
+
+int mvn_prob_grad_workspace_bytes(int n, int N, int S, const mvn_options* opts, size_t* bytes) {
+  if (n < 1) return fail(-1, "n must be >= 1 (got %d)", n);
+  if (N < 1) return fail(-2, "N must be >= 1 (got %d)", N);
+  if (S < 1) return fail(-3, "S must be >= 1 (got %d)", S);
+  if (!bytes) return fail(-5, "bytes is NULL");
+  (void)opts;
+  *bytes = grad_layout(n, N, S).total;
   return 0;
 }
 
@@ -265,6 +305,60 @@ int mvn_prob(const mvn_factor* f, const double* d_a, const double* d_b, const do
   sa.grid = Lay.grid;
   e = mvn::launch_sweep(sa, stream);
   if (e != hipSuccess) return hip_fail(e, "sweep");
+  e = mvn::launch_reduce(ell, N, S, part, f->info, bad, d_out, stream);
+  if (e != hipSuccess) return hip_fail(e, "reduce");
+  return 0;
+}
+
+int mvn_prob_grad(const mvn_factor* f, const double* d_a, const double* d_b, const double* d_mu,
+                  int N, int S, uint64_t seed, const mvn_options* opts, void* ws, size_t ws_bytes,
+                  double* d_out, double* d_da, double* d_db, double* d_dmu, hipStream_t stream) {
+  if (!f || !f->L || !f->info || f->n < 1 || f->ld != padded(f->n))
+    return fail(-1, "invalid factor handle");
+  if (!d_a) return fail(-2, "lower limits are NULL");
+  if (!d_b) return fail(-3, "upper limits are NULL");
+  if (N < 1) return fail(-5, "N must be >= 1 (got %d)", N);
+  if (S < 1) return fail(-6, "S must be >= 1 (got %d)", S);
+  if (!opts) return fail(-8, "options are required");
+  if (opts->precision != MVN_FP64) return fail(-8, "the adjoint sweep is FP64");
+  const int n = f->n;
+  const GradLayout Lay = grad_layout(n, N, S);
+  if (!ws) return fail(-9, "workspace is NULL");
+  if (ws_bytes < Lay.total) return fail(-10, "workspace too small: %zu < %zu", ws_bytes, Lay.total);
+  if (!d_out) return fail(-11, "output is NULL");
+  const uint64_t* lat = lattice_table(n);
+  if (!lat) return fail(-1, "could not build the lattice table for n = %d", n);
+  char* w = (char*)ws;
+  double* at = (double*)(w + Lay.at);
+  double* bt = (double*)(w + Lay.bt);
+  uint64_t* dlat = (uint64_t*)(w + Lay.lat);
+  double* ell = (double*)(w + Lay.ell);
+  double* part = (double*)(w + Lay.part);
+  int* bad = (int*)(w + Lay.bad);
+  hipError_t e = hipMemcpyAsync(dlat, lat, sizeof(uint64_t) * n, hipMemcpyHostToDevice, stream);
+  if (e != hipSuccess) return hip_fail(e, "lattice copy");
+  e = mvn::launch_prob_setup(n, f->ld, d_a, d_b, d_mu, at, bt, bad, stream);
+  if (e != hipSuccess) return hip_fail(e, "setup");
+  mvn::GradArgs ga{};
+  ga.L = f->L;
+  ga.ld = f->ld;
+  ga.n = n;
+  ga.at = at;
+  ga.bt = bt;
+  ga.lattice = dlat;
+  ga.seed = seed;
+  ga.N = N;
+  ga.S = S;
+  ga.periodize = opts->periodize ? 1 : 0;
+  ga.yscr = (double*)(w + Lay.yscr);
+  ga.sfw = (double*)(w + Lay.sfw);
+  ga.sbar = (double*)(w + Lay.sbar);
+  ga.ell = ell;
+  ga.gpart = (double*)(w + Lay.gpart);
+  ga.mz = (double*)(w + Lay.mz);
+  ga.grid = Lay.grid;
+  e = mvn::launch_grad(ga, f->info, bad, (double*)(w + Lay.scale), d_da, d_db, d_dmu, stream);
+  if (e != hipSuccess) return hip_fail(e, "adjoint sweep");
   e = mvn::launch_reduce(ell, N, S, part, f->info, bad, d_out, stream);
   if (e != hipSuccess) return hip_fail(e, "reduce");
   return 0;

@@ -26,6 +26,7 @@
 #include "gemm_f64.h"
 #include "launch.h"
 #include "mvn_device.h"
+#include "sweep_block.h"
 #include "sweep_gemm.h"
 
 namespace mvn {
@@ -66,69 +67,7 @@ hipError_t launch_prob_setup(int n, int ld, const double* a, const double* b, co
 // the GEMM tiling).  76 KB of LDS and <= 256 registers per lane let two
 // workgroups share a CU, so one workgroup's conditioning (VALU) can overlap
 // the other's GEMM (MFMA).
-constexpr int kSlab = 8;  // rows of the diagonal block of L staged per LDS slab
-
 int sweep_tile_cols() { return kCols; }
-
-typedef __attribute__((address_space(3))) double lds_f64;
-typedef __attribute__((address_space(3))) uint64_t lds_u64;
-
-// Step 2 of the sweep for one 128-row block, called by all 256 lanes once per
-// block: rows of the diagonal block of L are staged 8 at a time in LDS (all
-// lanes), and wave 0 (lane = sample column) runs the recurrence
-//   s_i = S_i + sum_{k<i} L_ik y_k,  a' = (a~_i - s_i)/L_ii,
-//   b' = (b~_i - s_i)/L_ii,  (y_i, d_i) = condition_step(a', b', w_i),
-// leaving y_i in T and folding d_i into the sample's running product.
-// This file is compiled without machine loop-invariant code motion: hoisting
-// the step's ~60 polynomial constants out of the row loop would pin them in
-// registers next to the GEMM's accumulators and force spills (build.py).
-__device__ __forceinline__ LogProd condition_block(
-    lds_f64* T, lds_f64* slab, const lds_f64* c_at, const lds_f64* c_bt, const lds_f64* c_rl,
-    const lds_u64* c_lat, const double* __restrict__ L, long ld, int i0, int rows, int n,
-    uint64_t jpt, uint64_t sidx, uint64_t seed, int periodize, bool valid, LogProd prod) {
-  const int t = threadIdx.x, lane = t & 63;
-  const bool owner = (t >> 6) == 0;
-  for (int q = 0; q < rows; q += kSlab) {
-    __syncthreads();
-    for (int e = t; e < kSlab * kTile; e += 256) {
-      const int ii = e / kTile, k = e % kTile;
-      slab[e] = (q + ii < rows && k < q + ii) ? L[(long)(i0 + q + ii) * ld + i0 + k] : 0.0;
-    }
-    __syncthreads();
-    if (owner) {
-      const int iend = min(q + kSlab, rows);
-      for (int i = q; i < iend; ++i) {
-        // the slab row is zero from column i on, so the sum runs to a
-        // multiple of 8 with four independent partial sums (the LDS reads
-        // then pipeline)
-        const lds_f64* Li = slab + (i - q) * kTile;
-        const lds_f64* Tk = T + lane;
-        double s0 = T[i * kCols + lane], s1 = 0.0, s2 = 0.0, s3 = 0.0;
-        const int kend = (i + 7) & ~7;
-        for (int k = 0; k < kend; k += 8) {
-          s0 += Li[k] * Tk[k * kCols];
-          s1 += Li[k + 1] * Tk[(k + 1) * kCols];
-          s2 += Li[k + 2] * Tk[(k + 2) * kCols];
-          s3 += Li[k + 3] * Tk[(k + 3) * kCols];
-          s0 += Li[k + 4] * Tk[(k + 4) * kCols];
-          s1 += Li[k + 5] * Tk[(k + 5) * kCols];
-          s2 += Li[k + 6] * Tk[(k + 6) * kCols];
-          s3 += Li[k + 7] * Tk[(k + 7) * kCols];
-        }
-        const double sum = (s0 + s1) + (s2 + s3);
-        const double rl = c_rl[i];
-        const double alpha = (c_at[i] - sum) * rl;
-        const double beta = (c_bt[i] - sum) * rl;
-        const uint64_t g = (uint64_t)(i0 + i);
-        const double w = richtmyer(jpt, c_lat[i], splitmix64(seed, sidx * (uint64_t)n + g), periodize);
-        const Step st = condition_step(alpha, beta, w, 1.0 - w);
-        T[i * kCols + lane] = valid ? st.y : 0.0;
-        logprod_mul(prod, st);
-      }
-    }
-  }
-  return prod;
-}
 
 template <class G>
 __global__ __launch_bounds__(256, 2) void sweep_kernel(SweepArgs p) {

@@ -47,6 +47,29 @@ hipError_t launch_sweep(const SweepArgs& a, hipStream_t st);
 long sweep_yslice(int prec, int ld);
 int sweep_elem_bytes(int prec);
 
+struct GradArgs {
+  const double* L;
+  int ld;
+  int n;
+  const double* at;
+  const double* bt;
+  const uint64_t* lattice;
+  uint64_t seed;
+  int N, S, periodize;
+  double* yscr;    // grid x ld x 64: y of the forward pass
+  double* sfw;     // grid x ld x 64: shifts s_i of the forward pass
+  double* sbar;    // grid x ld x 64: adjoints of s (reverse pass)
+  double* ell;     // N*S per-sample log-products
+  double* gpart;   // nchunks x 2 x ld: per-chunk partial gradients (a~, then b~)
+  double* mz;      // nchunks x 2: (max l, sum exp(l - max)) per chunk
+  int grid;
+};
+
+// Forward + adjoint sweep, then the fixed-order combination of the chunks'
+// partial gradients into da, db, dmu (each n doubles or NULL).
+hipError_t launch_grad(const GradArgs& a, const int* info_factor, const int* bad, double* scale,
+                       double* da, double* db, double* dmu, hipStream_t st);
+
 // log-sum-exp over samples, per shift and overall, into out[4 + S].
 hipError_t launch_reduce(const double* ell, int N, int S, double* part, const int* info_factor,
                          const int* bad_limits, double* out, hipStream_t st);
