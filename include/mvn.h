@@ -132,6 +132,36 @@ int mvn_prob_grad(const mvn_factor* f, const double* d_a, const double* d_b, con
                   int N, int S, uint64_t seed, const mvn_options* opts, void* ws, size_t ws_bytes,
                   double* d_out, double* d_da, double* d_db, double* d_dmu, hipStream_t stream);
 
+/* ---------------------------------------------------------------- batches
+ * Many MVN problems of uneven dimension in one call: the nested sets of
+ * confidence-region detection (Algorithm 1 evaluates PMVN on growing
+ * subsets of the sites).  Problem p uses the n_p locations
+ * d_locs[d_idx[o_p + i]] (o_p = n_0 + ... + n_{p-1}) with the Matern kernel,
+ * limits d_a[o_p + i], d_b[o_p + i] and mean d_mu[o_p + i] (or NULL), and the
+ * same N, S, seed as mvn_prob for its own dimension.
+ *
+ * mvn_batch_plan (host only) lays the batch out: it writes `plan`
+ * (mvn_batch_plan_bytes(count) bytes of host memory; per-problem offsets and
+ * the order of decreasing size) and the factor and workspace sizes.  The
+ * caller copies the plan to device memory once and passes it to
+ * mvn_prob_batch, whose launch sequence then allocates nothing and never
+ * synchronises (it can be captured in a graph and replayed).
+ *   n_p     host, count sizes (each >= 1), the same array for both calls
+ *   d_idx   device, sum n_p int64 location indices
+ *   d_out   device, count x (4 + S) doubles, per problem as for mvn_prob
+ *   d_info  device, count ints: Cholesky info per problem
+ * The factorisations use 128-wide tiles and opts->precision for the trailing
+ * updates and the sweep GEMMs.  Sweep work items (problem, 64 samples) are
+ * taken from a device counter in order of decreasing problem size. */
+int mvn_batch_plan_bytes(int count, size_t* bytes);
+int mvn_batch_plan(int count, const int* n_p, int N, int S, const mvn_options* opts, void* plan,
+                   size_t plan_bytes, size_t* factor_bytes, size_t* ws_bytes);
+int mvn_prob_batch(int count, const int* n_p, const void* d_plan, const int64_t* d_idx,
+                   const double* d_locs, const mvn_matern* kern, const double* d_a, const double* d_b,
+                   const double* d_mu, int N, int S, uint64_t seed, const mvn_options* opts,
+                   void* factor_buf, size_t factor_bytes, void* ws, size_t ws_bytes, double* d_out,
+                   int* d_info, hipStream_t stream);
+
 /* Message for the last negative return on this thread ("" if none). */
 const char* mvn_last_error(void);
 

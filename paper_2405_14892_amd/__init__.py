@@ -16,7 +16,8 @@ from ._lib import (MVN_BF16, MVN_BF16X3, MVN_FP32, MVN_FP64, MvnError, MvnFactor
                    MvnMatern, MvnOptions, options)
 
 __all__ = ["mvn_factor_bytes", "mvn_prob_workspace_bytes", "mvn_cholesky", "mvn_prob", "Factor",
-           "mvn_prob_grad_workspace_bytes", "mvn_prob_grad", "MVNLogProb",
+           "mvn_prob_grad_workspace_bytes", "mvn_prob_grad", "MVNLogProb", "BatchPlan",
+           "mvn_batch_plan", "mvn_prob_batch",
            "options", "MvnError", "MVN_FP64", "MVN_FP32", "MVN_BF16", "MVN_BF16X3", "library_path"]
 
 
@@ -194,3 +195,57 @@ class _LazyAutograd:
 
 
 MVNLogProb = _LazyAutograd()
+
+
+@dataclass
+class BatchPlan:
+    """A planned batch: host sizes, the plan on the device, and the buffers
+    mvn_prob_batch fills (allocated once, reusable across calls)."""
+    n_p: object            # numpy int32 array (host)
+    plan: object           # device uint8 tensor
+    factor: object         # device uint8 tensor
+    workspace: object      # device uint8 tensor
+    out: object            # device float64 (count, 4 + S)
+    info: object           # device int32 (count,)
+    N: int
+    S: int
+    opts: MvnOptions
+
+
+def mvn_batch_plan(n_p, N: int, S: int, opts: MvnOptions | None = None, device="cuda") -> BatchPlan:
+    import numpy as np
+    torch = _torch()
+    opts = opts or options()
+    sizes = np.ascontiguousarray(np.asarray(n_p, dtype=np.int32))
+    count = int(sizes.size)
+    pb = ctypes.c_size_t(0)
+    _lib.check(_lib.lib().mvn_batch_plan_bytes(count, ctypes.byref(pb)))
+    host = np.zeros(pb.value, dtype=np.uint8)
+    fb, wb = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    _lib.check(_lib.lib().mvn_batch_plan(count, sizes.ctypes.data_as(ctypes.c_void_p), N, S, ctypes.byref(opts),
+                                         host.ctypes.data_as(ctypes.c_void_p), pb.value, ctypes.byref(fb),
+                                         ctypes.byref(wb)))
+    return BatchPlan(sizes, torch.from_numpy(host).to(device), torch.empty(fb.value, dtype=torch.uint8, device=device),
+                     torch.empty(wb.value, dtype=torch.uint8, device=device),
+                     torch.empty((count, 4 + S), dtype=torch.float64, device=device),
+                     torch.empty(count, dtype=torch.int32, device=device), N, S, opts)
+
+
+def mvn_prob_batch(plan: BatchPlan, idx, locs, kern: tuple, a, b, mu=None, seed: int = 1):
+    """Enqueue the whole batch (factorisations, sweep, reductions) on the
+    current stream; results land in plan.out and plan.info."""
+    torch = _torch()
+    dev = plan.out.device
+    tidx = torch.as_tensor(idx, dtype=torch.int64).to(dev).contiguous()
+    tl = _dev_f64(locs, dev)
+    ta, tb = _dev_f64(a, dev), _dev_f64(b, dev)
+    tm = _dev_f64(mu, dev) if mu is not None else None
+    km = MvnMatern(*kern)
+    code = _lib.lib().mvn_prob_batch(
+        int(plan.n_p.size), plan.n_p.ctypes.data_as(ctypes.c_void_p), _ptr(plan.plan), _ptr(tidx), _ptr(tl),
+        ctypes.byref(km), _ptr(ta), _ptr(tb), _ptr(tm), plan.N, plan.S, ctypes.c_uint64(seed),
+        ctypes.byref(plan.opts), _ptr(plan.factor), plan.factor.numel(), _ptr(plan.workspace),
+        plan.workspace.numel(), _ptr(plan.out), _ptr(plan.info), _stream(dev))
+    _lib.check(code)
+    plan._keep = (tidx, tl, ta, tb, tm)
+    return plan.out

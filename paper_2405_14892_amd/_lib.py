@@ -52,6 +52,12 @@ SIGNATURES = {
     "mvn_prob_grad": (c_int, [POINTER(MvnFactor), c_void_p, c_void_p, c_void_p, c_int, c_int, c_uint64,
                               POINTER(MvnOptions), c_void_p, c_size_t, c_void_p, c_void_p, c_void_p,
                               c_void_p, c_void_p]),
+    "mvn_batch_plan_bytes": (c_int, [c_int, POINTER(c_size_t)]),
+    "mvn_batch_plan": (c_int, [c_int, c_void_p, c_int, c_int, POINTER(MvnOptions), c_void_p, c_size_t,
+                               POINTER(c_size_t), POINTER(c_size_t)]),
+    "mvn_prob_batch": (c_int, [c_int, c_void_p, c_void_p, c_void_p, c_void_p, POINTER(MvnMatern), c_void_p,
+                               c_void_p, c_void_p, c_int, c_int, c_uint64, POINTER(MvnOptions), c_void_p,
+                               c_size_t, c_void_p, c_size_t, c_void_p, c_void_p, c_void_p]),
     "mvn_last_error": (ctypes.c_char_p, []),
     "mvn_version": (c_int, []),
 }

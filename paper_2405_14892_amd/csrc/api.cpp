@@ -7,6 +7,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <vector>
 
@@ -153,6 +154,78 @@ GradLayout grad_layout(int n, int N, int S) {
   L.scale = off; off = align_up(off + sizeof(double) * ((size_t)L.nchunks + 1));
   L.total = off;
   return L;
+}
+
+// ---------------------------------------------------------------- batches
+struct BatchPlan {
+  std::vector<mvn::BatchDesc> desc;
+  std::vector<int> order, ld_rank;
+  long factor_elems = 0, total_tiles = 0, sum_n = 0;
+  int nmax = 0, ldmax = 0;
+};
+
+bool batch_plan_host(int count, const int* n_p, BatchPlan& P) {
+  P.desc.resize(count);
+  P.order.resize(count);
+  long fo = 0, lo = 0, to = 0;
+  for (int p = 0; p < count; ++p) {
+    if (n_p[p] < 1) return false;
+    mvn::BatchDesc& d = P.desc[p];
+    d.n = n_p[p];
+    d.ld = padded(n_p[p]);
+    d.factor_off = fo;
+    d.lim_off = lo;
+    d.tile_off = to;
+    d.reserved = 0;
+    fo += (long)d.ld * d.ld;
+    lo += d.n;
+    const long nb = d.ld / 64;
+    to += nb * (nb + 1) / 2;
+    P.nmax = d.n > P.nmax ? d.n : P.nmax;
+  }
+  P.factor_elems = fo;
+  P.sum_n = lo;
+  P.total_tiles = to;
+  for (int p = 0; p < count; ++p) P.order[p] = p;
+  std::stable_sort(P.order.begin(), P.order.end(), [&](int x, int y) { return n_p[x] > n_p[y]; });
+  P.ld_rank.resize(count);
+  for (int r = 0; r < count; ++r) P.ld_rank[r] = P.desc[P.order[r]].ld;
+  P.ldmax = P.ld_rank[0];
+  return true;
+}
+
+size_t batch_plan_bytes(int count) {
+  return align_up(sizeof(mvn::BatchDesc) * (size_t)count) + align_up(sizeof(int) * (size_t)count);
+}
+
+size_t batch_factor_bytes(const BatchPlan& P, int prec) {
+  return align_up(sizeof(double) * (size_t)P.factor_elems) + align_up((size_t)elem_bytes_low(prec) * P.factor_elems);
+}
+
+struct BatchWs {
+  size_t at, bt, lat, ell, part, bad, counter, yscr, total;
+  int grid;
+  long items;
+};
+
+BatchWs batch_ws(const BatchPlan& P, int count, int N, int S, int prec) {
+  BatchWs W{};
+  const long NS = (long)N * S;
+  const long chunks = (NS + mvn::sweep_tile_cols() - 1) / mvn::sweep_tile_cols();
+  W.items = chunks * count;
+  W.grid = (int)(W.items < kMaxGrid ? W.items : kMaxGrid);
+  size_t off = 0;
+  W.at = off; off = align_up(off + sizeof(double) * (size_t)P.sum_n);
+  W.bt = off; off = align_up(off + sizeof(double) * (size_t)P.sum_n);
+  W.lat = off; off = align_up(off + sizeof(uint64_t) * (size_t)P.ldmax);
+  W.ell = off; off = align_up(off + sizeof(double) * (size_t)NS * count);
+  W.part = off; off = align_up(off + sizeof(double) * 2 * (size_t)S * count);
+  W.bad = off; off = align_up(off + sizeof(int) * (size_t)count);
+  W.counter = off; off = align_up(off + sizeof(unsigned long long));
+  W.yscr = off;
+  off = align_up(off + (size_t)mvn::sweep_elem_bytes(prec) * (size_t)W.grid * mvn::sweep_yslice(prec, P.ldmax));
+  W.total = off;
+  return W;
 }
 
 }  // namespace
@@ -361,6 +434,112 @@ int mvn_prob_grad(const mvn_factor* f, const double* d_a, const double* d_b, con
   if (e != hipSuccess) return hip_fail(e, "adjoint sweep");
   e = mvn::launch_reduce(ell, N, S, part, f->info, bad, d_out, stream);
   if (e != hipSuccess) return hip_fail(e, "reduce");
+  return 0;
+}
+
+int mvn_batch_plan_bytes(int count, size_t* bytes) {
+  if (count < 1) return fail(-1, "count must be >= 1 (got %d)", count);
+  if (!bytes) return fail(-2, "bytes is NULL");
+  *bytes = batch_plan_bytes(count);
+  return 0;
+}
+
+int mvn_batch_plan(int count, const int* n_p, int N, int S, const mvn_options* opts, void* plan,
+                   size_t plan_bytes, size_t* factor_bytes, size_t* ws_bytes) {
+  if (count < 1) return fail(-1, "count must be >= 1 (got %d)", count);
+  if (!n_p) return fail(-2, "sizes are NULL");
+  if (N < 1) return fail(-3, "N must be >= 1 (got %d)", N);
+  if (S < 1) return fail(-4, "S must be >= 1 (got %d)", S);
+  const int prec = opts ? opts->precision : MVN_FP64;
+  if (!prec_ok(prec)) return fail(-5, "unknown precision %d", prec);
+  BatchPlan P;
+  if (!batch_plan_host(count, n_p, P)) return fail(-2, "every problem needs n >= 1");
+  if (plan) {
+    if (plan_bytes < batch_plan_bytes(count)) return fail(-7, "plan buffer too small");
+    memcpy(plan, P.desc.data(), sizeof(mvn::BatchDesc) * count);
+    memcpy((char*)plan + align_up(sizeof(mvn::BatchDesc) * (size_t)count), P.order.data(), sizeof(int) * count);
+  }
+  if (factor_bytes) *factor_bytes = batch_factor_bytes(P, prec);
+  if (ws_bytes) *ws_bytes = batch_ws(P, count, N, S, prec).total;
+  return 0;
+}
+
+int mvn_prob_batch(int count, const int* n_p, const void* d_plan, const int64_t* d_idx, const double* d_locs,
+                   const mvn_matern* kern, const double* d_a, const double* d_b, const double* d_mu, int N, int S,
+                   uint64_t seed, const mvn_options* opts, void* factor_buf, size_t factor_bytes, void* ws,
+                   size_t ws_bytes, double* d_out, int* d_info, hipStream_t stream) {
+  if (count < 1) return fail(-1, "count must be >= 1 (got %d)", count);
+  if (!n_p) return fail(-2, "sizes are NULL");
+  if (!d_plan) return fail(-3, "plan is NULL");
+  if (!d_idx) return fail(-4, "location indices are NULL");
+  if (!d_locs) return fail(-5, "locations are NULL");
+  if (!kern || !(kern->nu == 0.5 || kern->nu == 1.5) || !(kern->sigma2 > 0) || !(kern->beta > 0) ||
+      !(kern->nugget >= 0))
+    return fail(-6, "Matern parameters need nu in {0.5, 1.5}, sigma2 > 0, beta > 0, nugget >= 0");
+  if (!d_a) return fail(-7, "lower limits are NULL");
+  if (!d_b) return fail(-8, "upper limits are NULL");
+  if (N < 1) return fail(-10, "N must be >= 1 (got %d)", N);
+  if (S < 1) return fail(-11, "S must be >= 1 (got %d)", S);
+  if (!opts) return fail(-13, "options are required");
+  const int prec = opts->precision;
+  if (!prec_ok(prec)) return fail(-13, "unknown precision %d", prec);
+  BatchPlan P;
+  if (!batch_plan_host(count, n_p, P)) return fail(-2, "every problem needs n >= 1");
+  if (!factor_buf) return fail(-14, "factor buffer is NULL");
+  if (factor_bytes < batch_factor_bytes(P, prec)) return fail(-15, "factor buffer too small");
+  const BatchWs W = batch_ws(P, count, N, S, prec);
+  if (!ws) return fail(-16, "workspace is NULL");
+  if (ws_bytes < W.total) return fail(-17, "workspace too small: %zu < %zu", ws_bytes, W.total);
+  if (!d_out) return fail(-18, "output is NULL");
+  if (!d_info) return fail(-19, "info is NULL");
+  const uint64_t* lat = lattice_table(P.ldmax);
+  if (!lat) return fail(-2, "could not build the lattice table");
+  const mvn::BatchDesc* desc = (const mvn::BatchDesc*)d_plan;
+  const int* order = (const int*)((const char*)d_plan + align_up(sizeof(mvn::BatchDesc) * (size_t)count));
+  double* factor = (double*)factor_buf;
+  void* low = prec == MVN_FP64 ? nullptr : (char*)factor_buf + align_up(sizeof(double) * (size_t)P.factor_elems);
+  char* w = (char*)ws;
+  double* at = (double*)(w + W.at);
+  double* bt = (double*)(w + W.bt);
+  uint64_t* dlat = (uint64_t*)(w + W.lat);
+  double* ell = (double*)(w + W.ell);
+  double* part = (double*)(w + W.part);
+  int* bad = (int*)(w + W.bad);
+  unsigned long long* counter = (unsigned long long*)(w + W.counter);
+  hipError_t e = hipMemcpyAsync(dlat, lat, sizeof(uint64_t) * P.ldmax, hipMemcpyHostToDevice, stream);
+  if (e != hipSuccess) return hip_fail(e, "lattice copy");
+  e = mvn::launch_batch_build(desc, count, P.total_tiles, d_idx, d_locs, kern->sigma2, kern->beta, kern->nu,
+                              kern->nugget, factor, d_info, stream);
+  if (e != hipSuccess) return hip_fail(e, "batch build");
+  e = mvn::launch_batch_cholesky(prec, desc, order, P.ld_rank.data(), count, factor, d_info, low,
+                                 P.factor_elems, stream);
+  if (e != hipSuccess) return hip_fail(e, "batch cholesky");
+  e = mvn::launch_batch_setup(desc, count, P.nmax, d_a, d_b, d_mu, at, bt, bad, counter, stream);
+  if (e != hipSuccess) return hip_fail(e, "batch setup");
+  mvn::BatchSweepArgs a{};
+  a.desc = desc;
+  a.order = order;
+  a.L = factor;
+  a.Llow = prec == MVN_FP64 ? (const void*)factor : low;
+  a.at = at;
+  a.bt = bt;
+  a.lattice = dlat;
+  a.seed = seed;
+  a.N = N;
+  a.S = S;
+  a.periodize = opts->periodize ? 1 : 0;
+  a.prec = prec;
+  a.yscr = (void*)(w + W.yscr);
+  a.yslice = mvn::sweep_yslice(prec, P.ldmax);
+  a.ell = ell;
+  a.counter = counter;
+  a.total_items = W.items;
+  a.lplane = P.factor_elems;
+  a.grid = W.grid;
+  e = mvn::launch_batch_sweep(a, stream);
+  if (e != hipSuccess) return hip_fail(e, "batch sweep");
+  e = mvn::launch_batch_reduce(ell, count, N, S, part, d_info, bad, d_out, stream);
+  if (e != hipSuccess) return hip_fail(e, "batch reduce");
   return 0;
 }
 

@@ -58,8 +58,8 @@ hipError_t launch_build_matrix(int n, int ld, const double* sigma, int lds, cons
 // ------------------------------------------------------------ diagonal block
 // D = A[j0:j0+jw, j0:j0+jw] - A[j0:j0+jw, k0:j0] A[j0:j0+jw, k0:j0]^T, then
 // D = chol(D) in LDS.  One workgroup of 256 lanes.
-__global__ __launch_bounds__(256) void chol_diag_kernel(double* __restrict__ A, int ld, int k0, int j0,
-                                                        int jw, int* __restrict__ info) {
+__device__ __forceinline__ void chol_diag_body(double* __restrict__ A, int ld, int k0, int j0, int jw,
+                                               int* __restrict__ info) {
   if (*info != 0) return;
   __shared__ double D[kSub][kSub + 1];
   __shared__ double P[kSub][64 + 1];
@@ -126,16 +126,21 @@ __global__ __launch_bounds__(256) void chol_diag_kernel(double* __restrict__ A, 
   }
 }
 
+__global__ __launch_bounds__(256) void chol_diag_kernel(double* __restrict__ A, int ld, int k0, int j0,
+                                                        int jw, int* __restrict__ info) {
+  chol_diag_body(A, ld, k0, j0, jw, info);
+}
+
 // ------------------------------------------------------------ panel solve
 // Rows i >= j0 + jw: x = A[i, j0:j0+jw] - A[i, k0:j0] A[j0:j0+jw, k0:j0]^T,
 // then x <- x L_dd^{-T} (forward substitution).  One lane per row.
-__global__ __launch_bounds__(256) void chol_trsm_kernel(double* __restrict__ A, int ld, int k0, int j0,
-                                                        int jw, const int* __restrict__ info) {
+__device__ __forceinline__ void chol_trsm_body(double* __restrict__ A, int ld, int k0, int j0, int jw,
+                                               const int* __restrict__ info, int rblock) {
   if (*info != 0) return;
   __shared__ double B[kSub][64 + 1];
   __shared__ double D[kSub][kSub + 1];
   const int t = threadIdx.x;
-  const long i = (long)j0 + jw + (long)blockIdx.x * 256 + t;
+  const long i = (long)j0 + jw + (long)rblock * 256 + t;
   const bool live = i < ld;
   double x[kSub];
 #pragma unroll
@@ -176,13 +181,17 @@ __global__ __launch_bounds__(256) void chol_trsm_kernel(double* __restrict__ A, 
     if (c < jw) A[i * ld + j0 + c] = x[c];
 }
 
+__global__ __launch_bounds__(256) void chol_trsm_kernel(double* __restrict__ A, int ld, int k0, int j0,
+                                                        int jw, const int* __restrict__ info) {
+  chol_trsm_body(A, ld, k0, j0, jw, info, blockIdx.x);
+}
+
 // ------------------------------------------------------------ trailing update
 // C = A[r0:, r0:] (lower 128 x 128 tiles) -= P P^T with P = A[r0:, k0:k0+kw].
-__global__ __launch_bounds__(256) void chol_syrk_kernel(double* __restrict__ A, int ld, int k0, int kw,
-                                                        const int* __restrict__ info) {
+__device__ __forceinline__ void chol_syrk_body(double* __restrict__ A, int ld, int k0, int kw,
+                                               const int* __restrict__ info, long b) {
   if (*info != 0) return;
   __shared__ double lds[2 * 2 * kStageDoubles];
-  const long b = blockIdx.x;
   long ti = (long)((sqrt(8.0 * (double)b + 1.0) - 1.0) * 0.5);
   while ((ti + 1) * (ti + 2) / 2 <= b) ++ti;
   while (ti * (ti + 1) / 2 > b) --ti;
@@ -221,6 +230,11 @@ __global__ __launch_bounds__(256) void chol_syrk_kernel(double* __restrict__ A, 
         const long gi = rowA + acc_row(ib, r), gj = rowB + acc_col(jb);
         if (gi < ld && gj < ld && gj <= gi) A[gi * ld + gj] -= acc.v[ib][jb][r];
       }
+}
+
+__global__ __launch_bounds__(256) void chol_syrk_kernel(double* __restrict__ A, int ld, int k0, int kw,
+                                                        const int* __restrict__ info) {
+  chol_syrk_body(A, ld, k0, kw, info, blockIdx.x);
 }
 
 __global__ __launch_bounds__(256) void zero_upper_kernel(double* __restrict__ A, int ld) {
@@ -324,12 +338,12 @@ struct SyrkStage<GemmBF16T<SPLIT>> {
 };
 
 template <class G>
-__global__ __launch_bounds__(256) void chol_syrk_lp_kernel(double* __restrict__ A, int ld, int k0, int kw,
-                                                           const int* __restrict__ info) {
+__device__ __forceinline__ void chol_syrk_lp_body(double* __restrict__ A, int ld, int k0, int kw,
+                                                  const int* __restrict__ info, int bx, int by) {
   if (*info != 0) return;
   __shared__ __attribute__((aligned(16))) double lds[kTile * kCols];
   const long r0 = (long)k0 + kw;
-  const long rowA = r0 + (long)blockIdx.y * kTile, colB = r0 + (long)blockIdx.x * kCols;
+  const long rowA = r0 + (long)by * kTile, colB = r0 + (long)bx * kCols;
   if (colB > rowA + kTile - 1 || rowA >= ld) return;  // tile entirely above the diagonal
   typename G::Acc acc;
   G::zero(acc);
@@ -356,8 +370,25 @@ __global__ __launch_bounds__(256) void chol_syrk_lp_kernel(double* __restrict__ 
   }
 }
 
+template <class G>
+__global__ __launch_bounds__(256) void chol_syrk_lp_kernel(double* __restrict__ A, int ld, int k0, int kw,
+                                                           const int* __restrict__ info) {
+  chol_syrk_lp_body<G>(A, ld, k0, kw, info, blockIdx.x, blockIdx.y);
+}
+
 // Low-precision operand copy of the finished factor for the sweep's GEMM:
 // FP32, BF16, or BF16 hi and lo planes (x = hi + lo).
+template <class E, int SPLIT>
+__global__ __launch_bounds__(256) void convert_factor_flat_kernel(const double* __restrict__ L, long elems,
+                                                                  E* __restrict__ out) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= elems) return;
+  const double v = L[e];
+  const E hi = (E)(float)v;
+  out[e] = hi;
+  if (SPLIT == 2) out[elems + e] = (E)(float)(v - (double)(float)hi);
+}
+
 template <class E, int SPLIT>
 __global__ __launch_bounds__(256) void convert_factor_kernel(const double* __restrict__ L, long ld,
                                                              E* __restrict__ out) {
@@ -400,6 +431,146 @@ hipError_t launch_cholesky_lp(int prec, int ld, int tile, double* A, int* info, 
     case 1: hipLaunchKernelGGL((convert_factor_kernel<float, 1>), cg, dim3(256), 0, st, (const double*)A, (long)ld, (float*)low); break;
     case 2: hipLaunchKernelGGL((convert_factor_kernel<__bf16, 1>), cg, dim3(256), 0, st, (const double*)A, (long)ld, (__bf16*)low); break;
     case 3: hipLaunchKernelGGL((convert_factor_kernel<__bf16, 2>), cg, dim3(256), 0, st, (const double*)A, (long)ld, (__bf16*)low); break;
+  }
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ batches
+__device__ __forceinline__ int batch_find(const BatchDesc* desc, int count, long b) {
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (desc[mid].tile_off <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(256) void batch_build_kernel(const BatchDesc* __restrict__ desc, int count,
+                                                          const int64_t* __restrict__ idx,
+                                                          const double* __restrict__ locs, double sigma2,
+                                                          double beta, double nu, double nugget,
+                                                          double* __restrict__ factor, int* __restrict__ info) {
+  const long b = blockIdx.x;
+  const int p = batch_find(desc, count, b);
+  const BatchDesc d = desc[p];
+  const long lt = b - d.tile_off;
+  long ti = (long)((sqrt(8.0 * (double)lt + 1.0) - 1.0) * 0.5);
+  while ((ti + 1) * (ti + 2) / 2 <= lt) ++ti;
+  while (ti * (ti + 1) / 2 > lt) --ti;
+  const long tj = lt - ti * (ti + 1) / 2;
+  if (lt == 0 && threadIdx.x == 0) info[p] = 0;
+  double* A = factor + d.factor_off;
+  const int64_t* ix = idx + d.lim_off;
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const long i = ti * 64 + (e >> 6), j = tj * 64 + (e & 63);
+    if (j > i) continue;
+    double v;
+    if (i >= d.n || j >= d.n) {
+      v = (i == j) ? 1.0 : 0.0;
+    } else {
+      const long gi = ix[i], gj = ix[j];
+      const double dx = locs[2 * gi] - locs[2 * gj];
+      const double dy = locs[2 * gi + 1] - locs[2 * gj + 1];
+      const double z = sqrt(dx * dx + dy * dy) / beta;
+      v = (nu == 0.5) ? sigma2 * exp(-z) : sigma2 * (1.0 + z) * exp(-z);
+      if (i == j) v += nugget;
+    }
+    A[i * d.ld + j] = v;
+  }
+}
+
+hipError_t launch_batch_build(const BatchDesc* desc, int count, long total_tiles, const int64_t* idx,
+                              const double* locs, double sigma2, double beta, double nu, double nugget,
+                              double* factor, int* info, hipStream_t st) {
+  hipLaunchKernelGGL(batch_build_kernel, dim3((unsigned)total_tiles), dim3(256), 0, st, desc, count, idx,
+                     locs, sigma2, beta, nu, nugget, factor, info);
+  return hipGetLastError();
+}
+
+constexpr int kBatchTile = 128;
+
+__global__ __launch_bounds__(256) void batch_diag_kernel(const BatchDesc* __restrict__ desc,
+                                                         const int* __restrict__ order, double* factor,
+                                                         int k0, int j0, int* info) {
+  const int p = order[blockIdx.x];
+  const BatchDesc d = desc[p];
+  chol_diag_body(factor + d.factor_off, d.ld, k0, j0, kSub, info + p);
+}
+
+__global__ __launch_bounds__(256) void batch_trsm_kernel(const BatchDesc* __restrict__ desc,
+                                                         const int* __restrict__ order, double* factor,
+                                                         int k0, int j0, const int* info) {
+  const int p = order[blockIdx.y];
+  const BatchDesc d = desc[p];
+  if ((long)blockIdx.x * 256 >= (long)d.ld - (j0 + kSub)) return;
+  chol_trsm_body(factor + d.factor_off, d.ld, k0, j0, kSub, info + p, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void batch_syrk_kernel(const BatchDesc* __restrict__ desc,
+                                                         const int* __restrict__ order, double* factor,
+                                                         int k0, const int* info) {
+  const int p = order[blockIdx.y];
+  const BatchDesc d = desc[p];
+  const long nt = ((long)d.ld - (k0 + kBatchTile)) / kTile;
+  if ((long)blockIdx.x >= nt * (nt + 1) / 2) return;
+  chol_syrk_body(factor + d.factor_off, d.ld, k0, kBatchTile, info + p, blockIdx.x);
+}
+
+template <class G>
+__global__ __launch_bounds__(256) void batch_syrk_lp_kernel(const BatchDesc* __restrict__ desc,
+                                                            const int* __restrict__ order, double* factor,
+                                                            int k0, const int* info) {
+  const int p = order[blockIdx.z];
+  const BatchDesc d = desc[p];
+  const long rem = (long)d.ld - (k0 + kBatchTile);
+  if ((long)blockIdx.x * kCols >= rem || (long)blockIdx.y * kTile >= rem) return;
+  chol_syrk_lp_body<G>(factor + d.factor_off, d.ld, k0, kBatchTile, info + p, blockIdx.x, blockIdx.y);
+}
+
+hipError_t launch_batch_cholesky(int prec, const BatchDesc* desc, const int* order, const int* ld_rank,
+                                 int count, double* factor, int* info, void* low, long factor_elems,
+                                 hipStream_t st) {
+  const int ldmax = ld_rank[0];
+  for (int k0 = 0; k0 < ldmax; k0 += kBatchTile) {
+    int cnt = 0;
+    while (cnt < count && ld_rank[cnt] > k0) ++cnt;
+    for (int j0 = k0; j0 < k0 + kBatchTile; j0 += kSub) {
+      hipLaunchKernelGGL(batch_diag_kernel, dim3(cnt), dim3(256), 0, st, desc, order, factor, k0, j0, info);
+      const int rows = ldmax - (j0 + kSub);
+      if (rows > 0)
+        hipLaunchKernelGGL(batch_trsm_kernel, dim3((rows + 255) / 256, cnt), dim3(256), 0, st, desc, order,
+                           factor, k0, j0, (const int*)info);
+    }
+    int cnt2 = 0;
+    while (cnt2 < count && ld_rank[cnt2] > k0 + kBatchTile) ++cnt2;
+    const int rem = ldmax - (k0 + kBatchTile);
+    if (rem > 0 && cnt2 > 0) {
+      if (prec == 0) {
+        const long nt = rem / kTile;
+        hipLaunchKernelGGL(batch_syrk_kernel, dim3((unsigned)(nt * (nt + 1) / 2), cnt2), dim3(256), 0, st, desc,
+                           order, factor, k0, (const int*)info);
+      } else {
+        dim3 g(rem / kCols, rem / kTile, cnt2);
+        switch (prec) {
+          case 1: hipLaunchKernelGGL(batch_syrk_lp_kernel<GemmF32>, g, dim3(256), 0, st, desc, order, factor, k0, (const int*)info); break;
+          case 2: hipLaunchKernelGGL(batch_syrk_lp_kernel<GemmBF16>, g, dim3(256), 0, st, desc, order, factor, k0, (const int*)info); break;
+          case 3: hipLaunchKernelGGL(batch_syrk_lp_kernel<GemmBF16x3>, g, dim3(256), 0, st, desc, order, factor, k0, (const int*)info); break;
+          default: return hipErrorInvalidValue;
+        }
+      }
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (prec != 0) {
+    // one conversion over the whole packed factor; plane stride = factor_elems
+    const dim3 cg((unsigned)((factor_elems + 255) / 256));
+    switch (prec) {
+      case 1: hipLaunchKernelGGL((convert_factor_flat_kernel<float, 1>), cg, dim3(256), 0, st, (const double*)factor, factor_elems, (float*)low); break;
+      case 2: hipLaunchKernelGGL((convert_factor_flat_kernel<__bf16, 1>), cg, dim3(256), 0, st, (const double*)factor, factor_elems, (__bf16*)low); break;
+      case 3: hipLaunchKernelGGL((convert_factor_flat_kernel<__bf16, 2>), cg, dim3(256), 0, st, (const double*)factor, factor_elems, (__bf16*)low); break;
+    }
   }
   return hipGetLastError();
 }

@@ -119,12 +119,12 @@ __global__ __launch_bounds__(256, 2) void grad_kernel(GradArgs p) {
       if (i0 > 0) {
         const int nst = i0 / G::kK;
         G::Regs r;
-        G::load(p.L, ld, i0, 0, Y, ld, r);
+        G::load(p.L, ld, 0, i0, 0, Y, ld, r);
         G::store(stage0, r);
         __syncthreads();
         for (int s = 0; s < nst; ++s) {
           const bool odd = s & 1;
-          if (s + 1 < nst) G::load(p.L, ld, i0, (long)(s + 1) * G::kK, Y, ld, r);
+          if (s + 1 < nst) G::load(p.L, ld, 0, i0, (long)(s + 1) * G::kK, Y, ld, r);
           G::mma(odd ? stage1 : stage0, acc);
           if (s + 1 < nst) G::store(odd ? stage0 : stage1, r);
           __syncthreads();

@@ -69,73 +69,119 @@ hipError_t launch_prob_setup(int n, int ld, const double* a, const double* b, co
 // the other's GEMM (MFMA).
 int sweep_tile_cols() { return kCols; }
 
+// Shared memory of one sweep workgroup.
+struct SweepLds {
+  double* T;         // 128 x 64 block (also the double-buffered GEMM stages)
+  double* slab;
+  double* c_at;
+  double* c_bt;
+  double* c_rl;
+  uint64_t* c_lat;
+};
+
+// The whole sweep of one 64-column chunk of one problem: for every 128-row
+// block, the GEMM (step 1), the conditioning (step 2) and the y write-back
+// (step 3).  Writes l of the chunk's valid samples to ell[col].
+template <class G>
+__device__ __forceinline__ void sweep_chunk(const SweepLds& sh, const double* __restrict__ L,
+                                            const typename G::E* __restrict__ Lg, long lplane, long ld, int n,
+                                            const double* __restrict__ at, const double* __restrict__ bt,
+                                            const uint64_t* __restrict__ lattice, uint64_t seed, int N, int S,
+                                            int periodize, typename G::E* __restrict__ Y,
+                                            double* __restrict__ ell, long chunk) {
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const long NS = (long)N * S;
+  char* stage0 = (char*)sh.T;
+  char* stage1 = (char*)sh.T + G::kStageBytes;
+  const long col = chunk * kCols + lane;
+  const bool owner = wv == 0;
+  const bool valid = owner && col < NS;
+  const uint64_t sidx = valid ? (uint64_t)(col / N) : 0;
+  const uint64_t jpt = valid ? (uint64_t)(col % N) + 1 : 1;
+  LogProd prod{1.0, 0};
+
+  for (int i0 = 0; i0 < n; i0 += kTile) {
+    const int rows = min(kTile, n - i0);
+    typename G::Acc acc;
+    G::zero(acc);
+    // ---- step 1: S = L[i0:i0+128, 0:i0] Y[0:i0, :]
+    if (i0 > 0) {
+      const int nst = i0 / G::kK;
+      typename G::Regs r;
+      G::load(Lg, ld, lplane, i0, 0, Y, ld, r);
+      G::store(stage0, r);
+      __syncthreads();
+      for (int s = 0; s < nst; ++s) {
+        const bool odd = s & 1;
+        if (s + 1 < nst) G::load(Lg, ld, lplane, i0, (long)(s + 1) * G::kK, Y, ld, r);
+        G::mma(odd ? stage1 : stage0, acc);
+        if (s + 1 < nst) G::store(odd ? stage0 : stage1, r);
+        __syncthreads();
+      }
+    }
+    // accumulators -> T[row][col] in FP64; per-row constants -> LDS
+    G::to_block(acc, sh.T);
+    if (t < rows) {
+      const long g = i0 + t;
+      sh.c_at[t] = at[g];
+      sh.c_bt[t] = bt[g];
+      sh.c_rl[t] = 1.0 / L[g * ld + g];
+      sh.c_lat[t] = lattice[g];
+    }
+    // ---- step 2: conditioning of the diagonal block
+    prod = condition_block((lds_f64*)sh.T, (lds_f64*)sh.slab, (const lds_f64*)sh.c_at,
+                           (const lds_f64*)sh.c_bt, (const lds_f64*)sh.c_rl, (const lds_u64*)sh.c_lat, L, ld,
+                           i0, rows, n, jpt, sidx, seed, periodize, valid, prod);
+    __syncthreads();
+    // ---- step 3: y block -> scratch (in the GEMM's operand type)
+    G::put_y(sh.T, Y, ld, i0, rows);
+    __syncthreads();
+  }
+  if (valid) ell[col] = logprod_log(prod);
+}
+
+#define MVN_SWEEP_LDS                                                     \
+  __shared__ __attribute__((aligned(16))) double lds_T[kTile * kCols];    \
+  __shared__ double lds_slab[kSlab * kTile];                              \
+  __shared__ double lds_at[kTile], lds_bt[kTile], lds_rl[kTile];          \
+  __shared__ uint64_t lds_lat[kTile];                                     \
+  const SweepLds sh{lds_T, lds_slab, lds_at, lds_bt, lds_rl, lds_lat}
+
 template <class G>
 __global__ __launch_bounds__(256, 2) void sweep_kernel(SweepArgs p) {
   using E = typename G::E;
   static_assert(2 * G::kStageBytes <= kTile * kCols * 8, "GEMM stages must fit in the block buffer");
-  // 64 KB: double-buffered GEMM stages during step 1, then the 128 x 64
-  // FP64 block T (S, overwritten row by row with y) during step 2.
-  __shared__ __attribute__((aligned(16))) double lds[kTile * kCols];
-  // step 2 operands: a slab of rows of the diagonal block of L, and the
-  // block's per-row constants (limits, 1/L_ii, lattice generator)
-  __shared__ double slab[kSlab * kTile];
-  __shared__ double c_at[kTile], c_bt[kTile], c_rl[kTile];
-  __shared__ uint64_t c_lat[kTile];
-  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  const long NS = (long)p.N * p.S;
-  const long nchunks = (NS + kCols - 1) / kCols;
-  const long ld = p.ld;
-  const E* Lg = (const E*)p.Llow;
+  MVN_SWEEP_LDS;
+  const long nchunks = ((long)p.N * p.S + kCols - 1) / kCols;
   E* Y = (E*)p.yscr + (long)blockIdx.x * p.yslice;
-  char* stage0 = (char*)lds;
-  char* stage1 = (char*)lds + G::kStageBytes;
+  for (long chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x)
+    sweep_chunk<G>(sh, p.L, (const E*)p.Llow, (long)p.ld * p.ld, p.ld, p.n, p.at, p.bt, p.lattice, p.seed,
+                   p.N, p.S, p.periodize, Y, p.ell, chunk);
+}
 
-  for (long chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x) {
-    const long col = chunk * kCols + lane;
-    const bool owner = wv == 0;
-    const bool valid = owner && col < NS;
-    const uint64_t sidx = valid ? (uint64_t)(col / p.N) : 0;
-    const uint64_t jpt = valid ? (uint64_t)(col % p.N) + 1 : 1;
-    LogProd prod{1.0, 0};
-
-    for (int i0 = 0; i0 < p.n; i0 += kTile) {
-      const int rows = min(kTile, p.n - i0);
-      typename G::Acc acc;
-      G::zero(acc);
-      // ---- step 1: S = L[i0:i0+128, 0:i0] Y[0:i0, :]
-      if (i0 > 0) {
-        const int nst = i0 / G::kK;
-        typename G::Regs r;
-        G::load(Lg, ld, i0, 0, Y, ld, r);
-        G::store(stage0, r);
-        __syncthreads();
-        for (int s = 0; s < nst; ++s) {
-          const bool odd = s & 1;
-          if (s + 1 < nst) G::load(Lg, ld, i0, (long)(s + 1) * G::kK, Y, ld, r);
-          G::mma(odd ? stage1 : stage0, acc);
-          if (s + 1 < nst) G::store(odd ? stage0 : stage1, r);
-          __syncthreads();
-        }
-      }
-      // accumulators -> T[row][col] in FP64; per-row constants -> LDS
-      G::to_block(acc, lds);
-      if (t < rows) {
-        const long g = i0 + t;
-        c_at[t] = p.at[g];
-        c_bt[t] = p.bt[g];
-        c_rl[t] = 1.0 / p.L[g * ld + g];
-        c_lat[t] = p.lattice[g];
-      }
-      // ---- step 2: conditioning of the diagonal block
-      prod = condition_block((lds_f64*)lds, (lds_f64*)slab, (const lds_f64*)c_at, (const lds_f64*)c_bt,
-                             (const lds_f64*)c_rl, (const lds_u64*)c_lat, p.L, ld, i0, rows, p.n, jpt,
-                             sidx, p.seed, p.periodize, valid, prod);
-      __syncthreads();
-      // ---- step 3: y block -> scratch (in the GEMM's operand type)
-      G::put_y(lds, Y, ld, i0, rows);
-      __syncthreads();
-    }
-    if (valid) p.ell[col] = logprod_log(prod);
+// Batches: work items (problem rank, chunk) in order of decreasing problem
+// size, pulled from a device counter; every workgroup leaves when the
+// counter passes the number of items.
+template <class G>
+__global__ __launch_bounds__(256, 2) void batch_sweep_kernel(BatchSweepArgs p) {
+  using E = typename G::E;
+  MVN_SWEEP_LDS;
+  __shared__ long s_item;
+  const long nchunks = ((long)p.N * p.S + kCols - 1) / kCols;
+  const long NS = (long)p.N * p.S;
+  E* Y = (E*)p.yscr + (long)blockIdx.x * p.yslice;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = (long)atomicAdd(p.counter, 1ull);
+    __syncthreads();
+    const long item = s_item;
+    __syncthreads();
+    if (item >= p.total_items) break;
+    const int prob = p.order[item / nchunks];
+    const long chunk = item % nchunks;
+    const BatchDesc d = p.desc[prob];
+    sweep_chunk<G>(sh, p.L + d.factor_off, (const E*)p.Llow + d.factor_off, p.lplane, d.ld, d.n,
+                   p.at + d.lim_off, p.bt + d.lim_off, p.lattice, p.seed, p.N, p.S, p.periodize, Y,
+                   p.ell + (long)prob * NS, chunk);
   }
 }
 
@@ -159,11 +205,11 @@ hipError_t launch_sweep(const SweepArgs& a, hipStream_t st) {
 
 // ------------------------------------------------------------ reduction
 // Per shift: M_s = max_j l, Z_s = sum_j exp(l - M_s) in a fixed-order tree.
-__global__ __launch_bounds__(256) void lse_partial_kernel(const double* __restrict__ ell, int N,
-                                                          double* __restrict__ part) {
+__device__ __forceinline__ void lse_partial_body(const double* __restrict__ ell, int N,
+                                                 double* __restrict__ part, int s) {
   __shared__ double red[256];
   const int t = threadIdx.x;
-  const double* e = ell + (long)blockIdx.x * N;
+  const double* e = ell + (long)s * N;
   double m = -INFINITY;
   for (int j = t; j < N; j += 256) m = fmax(m, e[j]);
   red[t] = m;
@@ -184,16 +230,21 @@ __global__ __launch_bounds__(256) void lse_partial_kernel(const double* __restri
     __syncthreads();
   }
   if (t == 0) {
-    part[2 * blockIdx.x] = M;
-    part[2 * blockIdx.x + 1] = red[0];
+    part[2 * s] = M;
+    part[2 * s + 1] = red[0];
   }
+}
+
+__global__ __launch_bounds__(256) void lse_partial_kernel(const double* __restrict__ ell, int N,
+                                                          double* __restrict__ part) {
+  lse_partial_body(ell, N, part, blockIdx.x);
 }
 
 // log P_s = M_s + log Z_s - log N;  log P = LSE_s log P_s - log S;
 // relative standard error = sd_s(P_s) / (sqrt(S) mean_s P_s), in scaled form.
-__global__ void lse_final_kernel(const double* __restrict__ part, int N, int S,
-                                 const int* __restrict__ info_factor, const int* __restrict__ bad,
-                                 double* __restrict__ out) {
+__device__ __forceinline__ void lse_final_body(const double* __restrict__ part, int N, int S,
+                                               const int* __restrict__ info_factor,
+                                               const int* __restrict__ bad, double* __restrict__ out) {
   if (threadIdx.x != 0) return;
   const bool broken = (info_factor && *info_factor != 0) || (bad && *bad != INT_MAX);
   if (broken) {
@@ -231,11 +282,82 @@ __global__ void lse_final_kernel(const double* __restrict__ part, int N, int S,
   }
 }
 
+__global__ void lse_final_kernel(const double* __restrict__ part, int N, int S,
+                                 const int* __restrict__ info_factor, const int* __restrict__ bad,
+                                 double* __restrict__ out) {
+  lse_final_body(part, N, S, info_factor, bad, out);
+}
+
 hipError_t launch_reduce(const double* ell, int N, int S, double* part, const int* info_factor,
                          const int* bad_limits, double* out, hipStream_t st) {
   hipLaunchKernelGGL(lse_partial_kernel, dim3(S), dim3(256), 0, st, ell, N, part);
   hipLaunchKernelGGL(lse_final_kernel, dim3(1), dim3(64), 0, st, (const double*)part, N, S,
                      info_factor, bad_limits, out);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ batches
+__global__ void batch_init_kernel(int* __restrict__ bad, int count, unsigned long long* __restrict__ counter) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < count) bad[i] = INT_MAX;
+  if (i == 0) *counter = 0ull;
+}
+
+__global__ __launch_bounds__(256) void batch_centre_kernel(const BatchDesc* __restrict__ desc,
+                                                           const double* __restrict__ a,
+                                                           const double* __restrict__ b,
+                                                           const double* __restrict__ mu,
+                                                           double* __restrict__ at, double* __restrict__ bt,
+                                                           int* __restrict__ bad) {
+  const int p = blockIdx.y;
+  const BatchDesc d = desc[p];
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= d.n) return;
+  const long g = d.lim_off + i;
+  const double ai = a[g], bi = b[g], m = mu ? mu[g] : 0.0;
+  if (isnan(ai) || isnan(bi) || !isfinite(m) || ai > bi) atomicMin(bad + p, i + 1);
+  at[g] = ai - m;
+  bt[g] = bi - m;
+}
+
+hipError_t launch_batch_setup(const BatchDesc* desc, int count, int nmax, const double* a, const double* b,
+                              const double* mu, double* at, double* bt, int* bad,
+                              unsigned long long* counter, hipStream_t st) {
+  hipLaunchKernelGGL(batch_init_kernel, dim3((count + 255) / 256), dim3(256), 0, st, bad, count, counter);
+  hipLaunchKernelGGL(batch_centre_kernel, dim3((nmax + 255) / 256, count), dim3(256), 0, st, desc, a, b, mu,
+                     at, bt, bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_sweep(const BatchSweepArgs& a, hipStream_t st) {
+  switch (a.prec) {
+    case 0: hipLaunchKernelGGL(batch_sweep_kernel<GemmF64>, dim3(a.grid), dim3(256), 0, st, a); break;
+    case 1: hipLaunchKernelGGL(batch_sweep_kernel<GemmF32>, dim3(a.grid), dim3(256), 0, st, a); break;
+    case 2: hipLaunchKernelGGL(batch_sweep_kernel<GemmBF16>, dim3(a.grid), dim3(256), 0, st, a); break;
+    case 3: hipLaunchKernelGGL(batch_sweep_kernel<GemmBF16x3>, dim3(a.grid), dim3(256), 0, st, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void batch_lse_partial_kernel(const double* __restrict__ ell, int N, int S,
+                                                                double* __restrict__ part) {
+  const int p = blockIdx.y;
+  lse_partial_body(ell + (long)p * N * S, N, part + (long)p * 2 * S, blockIdx.x);
+}
+
+__global__ void batch_lse_final_kernel(const double* __restrict__ part, int N, int S,
+                                       const int* __restrict__ info, const int* __restrict__ bad,
+                                       double* __restrict__ out) {
+  const int p = blockIdx.x;
+  lse_final_body(part + (long)p * 2 * S, N, S, info + p, bad + p, out + (long)p * (4 + S));
+}
+
+hipError_t launch_batch_reduce(const double* ell, int count, int N, int S, double* part, const int* info,
+                               const int* bad, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(batch_lse_partial_kernel, dim3(S, count), dim3(256), 0, st, ell, N, S, part);
+  hipLaunchKernelGGL(batch_lse_final_kernel, dim3(count), dim3(64), 0, st, (const double*)part, N, S, info,
+                     bad, out);
   return hipGetLastError();
 }
 

@@ -76,4 +76,57 @@ hipError_t launch_reduce(const double* ell, int N, int S, double* part, const in
 
 int sweep_tile_cols();
 
+// ---------------------------------------------------------------- batches
+// Per-problem descriptor of a batch (written by the host plan, read on the
+// device).  Offsets are in elements of the packed buffers.
+struct BatchDesc {
+  int64_t factor_off;   // L_p at factor + factor_off (ld x ld doubles); low copy at the same offset
+  int64_t lim_off;      // limits / location indices of the problem start here
+  int64_t tile_off;     // first 64 x 64 lower tile of the problem in the flat build grid
+  int32_t n;
+  int32_t ld;           // n rounded up to 128
+  int64_t reserved;
+};
+static_assert(sizeof(BatchDesc) == 40, "descriptor layout");
+
+// Sigma_p = C(||s_{idx_i} - s_{idx_j}||) + nugget on the lower tiles of every
+// problem (one 64 x 64 tile per workgroup, flat over all problems); clears
+// info[p].
+hipError_t launch_batch_build(const BatchDesc* desc, int count, long total_tiles, const int64_t* idx,
+                              const double* locs, double sigma2, double beta, double nu, double nugget,
+                              double* factor, int* info, hipStream_t st);
+
+// Tiled Cholesky (tile 128) of every problem, one launch per step for all
+// problems that still have that step.  ld_rank[r] is the padded size of the
+// problem of rank r (ranks sorted by size, largest first); order[r] is its id.
+hipError_t launch_batch_cholesky(int prec, const BatchDesc* desc, const int* order, const int* ld_rank,
+                                 int count, double* factor, int* info, void* low, long factor_elems,
+                                 hipStream_t st);
+
+struct BatchSweepArgs {
+  const BatchDesc* desc;
+  const int* order;
+  const double* L;         // factor base (FP64)
+  const void* Llow;        // low-precision copy base (== L for FP64)
+  const double* at;        // centred limits, packed like the inputs
+  const double* bt;
+  const uint64_t* lattice;
+  uint64_t seed;
+  int N, S, periodize, prec;
+  void* yscr;
+  long yslice;
+  double* ell;             // count x N*S
+  unsigned long long* counter;
+  long total_items;        // count x chunks per problem
+  long lplane;             // element distance of the BF16 hi and lo planes of the packed low copy
+  int grid;
+};
+
+hipError_t launch_batch_setup(const BatchDesc* desc, int count, int nmax, const double* a, const double* b,
+                              const double* mu, double* at, double* bt, int* bad,
+                              unsigned long long* counter, hipStream_t st);
+hipError_t launch_batch_sweep(const BatchSweepArgs& a, hipStream_t st);
+hipError_t launch_batch_reduce(const double* ell, int count, int N, int S, double* part, const int* info,
+                               const int* bad, double* out, hipStream_t st);
+
 }  // namespace mvn

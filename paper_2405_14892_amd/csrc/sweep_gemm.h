@@ -50,7 +50,7 @@ struct GemmF64 {
       for (int j = 0; j < 4; ++j) acc.v[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
   }
   // L: row-major [ld][ld]; Y: [ld][64]
-  static __device__ __forceinline__ void load(const E* __restrict__ L, long ld, long i0, long k0,
+  static __device__ __forceinline__ void load(const E* __restrict__ L, long ld, long, long i0, long k0,
                                               const E* __restrict__ Y, long, Regs& r) {
     load_rows<false>(L, ld, i0, k0, 0, 0, r.a);
     const int t = threadIdx.x;
@@ -118,7 +118,7 @@ struct GemmF32 {
 #pragma unroll
       for (int j = 0; j < 4; ++j) acc.v[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
   }
-  static __device__ __forceinline__ void load(const E* __restrict__ L, long ld, long i0, long k0,
+  static __device__ __forceinline__ void load(const E* __restrict__ L, long ld, long, long i0, long k0,
                                               const E* __restrict__ Y, long, Regs& r) {
     const int t = threadIdx.x;
     const float4* pa = reinterpret_cast<const float4*>(L + (i0 + (t >> 1)) * ld + k0 + (t & 1) * 16);
@@ -202,14 +202,14 @@ struct GemmBF16T {
 #pragma unroll
       for (int j = 0; j < 4; ++j) acc.v[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
   }
-  // L planes: row-major [ld][ld] each, plane stride ld*ld; Y planes: column-
-  // major [64][ldy] each, plane stride 64*ldy
-  static __device__ __forceinline__ void load(const E* __restrict__ L, long ld, long i0, long k0,
-                                              const E* __restrict__ Y, long ldy, Regs& r) {
+  // L planes: row-major [ld][ld] each, `lplane` elements apart; Y planes:
+  // column-major [64][ldy] each, plane stride 64*ldy
+  static __device__ __forceinline__ void load(const E* __restrict__ L, long ld, long lplane, long i0,
+                                              long k0, const E* __restrict__ Y, long ldy, Regs& r) {
     const int t = threadIdx.x;
 #pragma unroll
     for (int sp = 0; sp < SPLIT; ++sp) {
-      const uint4* pa = reinterpret_cast<const uint4*>(L + sp * ld * ld + (i0 + (t >> 1)) * ld + k0 +
+      const uint4* pa = reinterpret_cast<const uint4*>(L + sp * lplane + (i0 + (t >> 1)) * ld + k0 +
                                                        (t & 1) * (kK / 2));
 #pragma unroll
       for (int q = 0; q < kAChunks; ++q) r.a[sp][q] = pa[q];
