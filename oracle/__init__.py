@@ -26,3 +26,4 @@ from .cholesky import cholesky, NotPositiveDefinite  # noqa: F401
 from .qmc import first_primes, lattice, splitmix64, shifts, points  # noqa: F401
 from .sov import centre, condition, sweep, reduce_samples, mvn_prob  # noqa: F401
 from .grad import tangent_sweep, logp_directional, logp_fd  # noqa: F401
+from .tlr import compress_tile, tlr_cholesky, tlr_dense  # noqa: F401
