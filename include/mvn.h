@@ -47,33 +47,59 @@ typedef struct mvn_matern {
 } mvn_matern;
 
 typedef struct mvn_options {
-  int tile;          /* Cholesky tile size (>= 16); Algorithm 1's tile m      */
-  int precision;     /* mvn_precision                                          */
+  int tile;          /* Cholesky tile size m (Algorithm 1).  Dense: >= 16 and  */
+                     /* a multiple of 4.  TLR: a multiple of 128 in           */
+                     /* [128, 1024]                                           */
+  int precision;     /* mvn_precision (TLR factors: MVN_FP64 only)            */
   int periodize;     /* 1 = baker's transform of the QMC points, 0 = off       */
   int reserved0;
-  double tlr_eps;    /* <= 0: dense factor (tile low-rank not in this build)  */
-  int max_rank;
+  double tlr_eps;    /* > 0: tile low-rank factor (Section III-E): every      */
+                     /* off-diagonal tile is compressed to U V^T with         */
+                     /* ||A_ij - U V^T||_F <= tlr_eps (absolute).  <= 0: dense */
+  int max_rank;      /* TLR rank cap, 1 .. min(256, tile)                      */
   int reserved1;
 } mvn_options;
 
 /* Factor handle, filled by mvn_cholesky.  Plain data; copy freely.
  * opts->precision selects the trailing-update arithmetic and which operand
- * copy of L is kept for the sweep.
- * L is row-major with leading dimension ld (>= n, a multiple of 128); rows
- * and columns n..ld-1 hold the identity so blocked kernels need no bounds
- * checks.  *info (device int) is 0 on success or k > 0 if the leading minor
- * of order k is not positive definite (LAPACK dpotrf convention). */
+ * copy of L is kept for the sweep.  *info (device int) is 0 on success or
+ * k > 0 if the leading minor of order k is not positive definite (LAPACK
+ * dpotrf convention).
+ *
+ * Dense factor (flags == 0): L is row-major with leading dimension ld (>= n,
+ * a multiple of 128); rows and columns n..ld-1 hold the identity so blocked
+ * kernels need no bounds checks.
+ *
+ * Tile low-rank factor (flags & MVN_FACTOR_TLR), tile edge m = tile,
+ * nt = ld / m tiles per side, rank stride rs = max_rank rounded up to 16:
+ *   L      the nt(nt+1)/2 lower m x m tiles, tile (i, j) at
+ *          (i(i+1)/2 + j) m^2 doubles, row-major with leading dimension m.
+ *          Diagonal tiles hold the dense factors L_ii; off-diagonal tiles
+ *          hold the updated covariance tiles they were compressed from.
+ *   U, Vt  for i > k, panel p = i(i-1)/2 + k: U at p m rs doubles (m x rs,
+ *          row-major), Vt at p rs m doubles (rs x m, row-major), with
+ *          L_ik = U_ik Vt_ik (columns / rows past the rank are zero).
+ *   ranks  device int per panel; negative when max_rank stopped the
+ *          compression before the residual reached tlr_eps. */
+#define MVN_FACTOR_TLR 1
 typedef struct mvn_factor {
   int n;
-  int ld;
+  int ld;           /* dense: padded n; TLR: nt * tile                         */
   int precision;    /* arithmetic the factor was built with (mvn_precision)    */
-  int flags;
-  double* L;        /* device, ld*ld doubles                                   */
+  int flags;        /* MVN_FACTOR_TLR or 0                                     */
+  double* L;        /* device: dense ld*ld doubles, or the TLR tiles           */
   int* info;        /* device, 1 int                                           */
   void* L_low;      /* device copy of L as the sweep's GEMM operand: ld*ld     */
                     /* floats (FP32), BF16 (BF16), two BF16 planes (BF16X3);  */
-                    /* NULL for FP64                                           */
-  void* reserved[3];
+                    /* NULL for FP64 and TLR                                   */
+  int tile;         /* TLR tile edge m (0 for dense)                           */
+  int rank_stride;  /* TLR rs (0 for dense)                                    */
+  double* U;        /* device, TLR only                                        */
+  double* Vt;       /* device, TLR only                                        */
+  int* ranks;       /* device, TLR only                                        */
+  double tlr_eps;   /* TLR accuracy the factor was built with                  */
+  int max_rank;     /* TLR rank cap                                            */
+  int reserved1;
 } mvn_factor;
 
 /* Sizes.  All return 0 on success and write the byte count. */
@@ -82,6 +108,13 @@ int mvn_cholesky_workspace_bytes(int n, const mvn_options* opts, size_t* bytes);
 int mvn_prob_workspace_bytes(int n, int N, int S, const mvn_options* opts, size_t* bytes);
 
 /* Sigma = L L^T (Algorithm 1, covariance generation and factorisation).
+ * With opts->tlr_eps > 0 the factor is tile low-rank (Section III-E): the
+ * tiles are factored right-looking; each off-diagonal panel tile is
+ * compressed by adaptive cross approximation, accepted only when the exact
+ * residual Frobenius norm is <= tlr_eps, then L_ik = U_ik (L_kk^{-1} V_ik)^T
+ * and the trailing tiles are updated with the low-rank products (FP64).
+ * The TLR factorisation needs the workspace of
+ * mvn_cholesky_workspace_bytes; the dense one needs none.
  *   n        dimension (>= 1)
  *   d_sigma  device n x n covariance with row stride ld_sigma, or NULL to
  *            generate it from d_locs and kern (Matern + nugget)
@@ -108,7 +141,10 @@ int mvn_cholesky(int n, const double* d_sigma, int ld_sigma, const double* d_loc
  *   d_ell     device, N*S doubles or NULL: per-sample log prod d_i, sample
  *             column c = s*N + (j-1).
  * opts->precision selects the arithmetic of the limit-update GEMM: MVN_FP64
- * always, or the precision the factor was built with.
+ * always, or the precision the factor was built with.  For a TLR factor
+ * (FP64 only) the update of tile-row i is sum_j U_ij (Vt_ij Y_j) plus the
+ * dense diagonal tile; the workspace query must then be given options with
+ * the factor's tile, max_rank and tlr_eps > 0.
  * The QMC point of sample (s, j) in dimension i is
  *   w = ((j*A_i + D_{s,i} mod 2^64) >> 11 + 1/2) 2^-53 with
  *   A_i = floor(frac(sqrt(p_{i+1})) 2^64) (p_k the k-th prime) and
@@ -126,7 +162,8 @@ int mvn_prob(const mvn_factor* f, const double* d_a, const double* d_b, const do
  *   d_dmu            device, n doubles (or NULL): d log P-hat / d mu_i =
  *                    -(d/da_i + d/db_i)
  * Infinite limits get a zero derivative.  All outputs NaN under the same
- * conditions as mvn_prob, or when every sample has zero mass. */
+ * conditions as mvn_prob, or when every sample has zero mass.  Dense FP64
+ * factors only. */
 int mvn_prob_grad_workspace_bytes(int n, int N, int S, const mvn_options* opts, size_t* bytes);
 int mvn_prob_grad(const mvn_factor* f, const double* d_a, const double* d_b, const double* d_mu,
                   int N, int S, uint64_t seed, const mvn_options* opts, void* ws, size_t ws_bytes,

@@ -12,10 +12,10 @@ import ctypes
 from dataclasses import dataclass
 
 from . import _lib
-from ._lib import (MVN_BF16, MVN_BF16X3, MVN_FP32, MVN_FP64, MvnError, MvnFactor,  # noqa: F401
-                   MvnMatern, MvnOptions, options)
+from ._lib import (MVN_BF16, MVN_BF16X3, MVN_FACTOR_TLR, MVN_FP32, MVN_FP64, MvnError,  # noqa: F401
+                   MvnFactor, MvnMatern, MvnOptions, options)
 
-__all__ = ["mvn_factor_bytes", "mvn_prob_workspace_bytes", "mvn_cholesky", "mvn_prob", "Factor",
+__all__ = ["mvn_factor_bytes", "mvn_cholesky_workspace_bytes", "mvn_prob_workspace_bytes", "mvn_cholesky", "mvn_prob", "Factor",
            "mvn_prob_grad_workspace_bytes", "mvn_prob_grad", "MVNLogProb", "BatchPlan",
            "mvn_batch_plan", "mvn_prob_batch",
            "options", "MvnError", "MVN_FP64", "MVN_FP32", "MVN_BF16", "MVN_BF16X3", "library_path"]
@@ -51,6 +51,12 @@ def mvn_factor_bytes(n: int, opts: MvnOptions | None = None) -> int:
     return out.value
 
 
+def mvn_cholesky_workspace_bytes(n: int, opts: MvnOptions | None = None) -> int:
+    out = ctypes.c_size_t(0)
+    _lib.check(_lib.lib().mvn_cholesky_workspace_bytes(n, ctypes.byref(opts or options()), ctypes.byref(out)))
+    return out.value
+
+
 def mvn_prob_workspace_bytes(n: int, N: int, S: int, opts: MvnOptions | None = None) -> int:
     out = ctypes.c_size_t(0)
     _lib.check(_lib.lib().mvn_prob_workspace_bytes(n, N, S, ctypes.byref(opts or options()),
@@ -73,17 +79,59 @@ class Factor:
     def ld(self) -> int:
         return self.handle.ld
 
-    def L(self):
-        """The factor as an n x n float64 tensor view (lower triangular)."""
+    @property
+    def is_tlr(self) -> bool:
+        return bool(self.handle.flags & MVN_FACTOR_TLR)
+
+    def _view(self, ptr: int, count: int, dtype):
         torch = _torch()
+        off = ptr - self.buffer.data_ptr()
+        size = torch.empty((), dtype=dtype).element_size()
+        return self.buffer[off: off + count * size].view(dtype)
+
+    def L(self):
+        """Dense factor as an n x n float64 tensor view (lower triangular)."""
+        torch = _torch()
+        if self.is_tlr:
+            raise MvnError(-1, "a TLR factor has no dense L; use tiles(), U(), Vt(), ranks()")
         ld = self.handle.ld
-        return self.buffer[: ld * ld * 8].view(torch.float64).view(ld, ld)[: self.n, : self.n]
+        return self._view(self.handle.L, ld * ld, torch.float64).view(ld, ld)[: self.n, : self.n]
 
     def info(self) -> int:
         torch = _torch()
-        ld = self.handle.ld
-        off = (ld * ld * 8 + 255) // 256 * 256
-        return int(self.buffer[off: off + 4].view(torch.int32).item())
+        return int(self._view(self.handle.info, 1, torch.int32).item())
+
+    # ---- tile low-rank buffers (raw device views, layouts as in mvn.h)
+    @property
+    def nt(self) -> int:
+        return self.handle.ld // self.handle.tile if self.is_tlr else 0
+
+    def tiles(self):
+        """(nt(nt+1)/2, m, m) float64: tile (i, j), j <= i, at i(i+1)/2 + j."""
+        torch = _torch()
+        m, nt = self.handle.tile, self.nt
+        cnt = nt * (nt + 1) // 2
+        return self._view(self.handle.L, cnt * m * m, torch.float64).view(cnt, m, m)
+
+    def U(self):
+        """(nt(nt-1)/2, m, rs) float64: panel (i, k), k < i, at i(i-1)/2 + k."""
+        torch = _torch()
+        m, nt, rs = self.handle.tile, self.nt, self.handle.rank_stride
+        cnt = nt * (nt - 1) // 2
+        return self._view(self.handle.U, cnt * m * rs, torch.float64).view(cnt, m, rs)
+
+    def Vt(self):
+        """(nt(nt-1)/2, rs, m) float64 with L_ik = U_ik Vt_ik."""
+        torch = _torch()
+        m, nt, rs = self.handle.tile, self.nt, self.handle.rank_stride
+        cnt = nt * (nt - 1) // 2
+        return self._view(self.handle.Vt, cnt * rs * m, torch.float64).view(cnt, rs, m)
+
+    def ranks(self):
+        """(nt(nt-1)/2,) int32 ranks (negative: capped by max_rank)."""
+        torch = _torch()
+        nt = self.nt
+        return self._view(self.handle.ranks, max(nt * (nt - 1) // 2, 1), torch.int32)[: nt * (nt - 1) // 2]
 
 
 def mvn_cholesky(n: int, sigma=None, locs=None, kern: tuple | None = None,
@@ -93,17 +141,19 @@ def mvn_cholesky(n: int, sigma=None, locs=None, kern: tuple | None = None,
     torch = _torch()
     opts = opts or options()
     fb = mvn_factor_bytes(n, opts)
+    wb = mvn_cholesky_workspace_bytes(n, opts)
     buf = torch.empty(fb, dtype=torch.uint8, device=device)
+    ws = torch.empty(wb, dtype=torch.uint8, device=device) if wb else None
     s = _dev_f64(sigma, device) if sigma is not None else None
     lc = _dev_f64(locs, device) if locs is not None else None
     km = MvnMatern(*kern) if kern is not None else None
     h = MvnFactor()
     code = _lib.lib().mvn_cholesky(
         n, _ptr(s), n if s is not None else 0, _ptr(lc), ctypes.byref(km) if km else None,
-        ctypes.byref(opts), _ptr(buf), fb, None, 0, ctypes.byref(h), _stream(device))
+        ctypes.byref(opts), _ptr(buf), fb, _ptr(ws), wb, ctypes.byref(h), _stream(device))
     _lib.check(code)
     f = Factor(h, buf, device)
-    f._keep = (s, lc)  # inputs must outlive the asynchronous launch
+    f._keep = (s, lc, ws)  # inputs and workspace must outlive the asynchronous launch
     return f
 
 

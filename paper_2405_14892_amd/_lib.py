@@ -26,9 +26,14 @@ class MvnOptions(ctypes.Structure):
                 ("tlr_eps", c_double), ("max_rank", c_int), ("reserved1", c_int)]
 
 
+MVN_FACTOR_TLR = 1
+
+
 class MvnFactor(ctypes.Structure):
     _fields_ = [("n", c_int), ("ld", c_int), ("precision", c_int), ("flags", c_int),
-                ("L", c_void_p), ("info", c_void_p), ("L_low", c_void_p), ("reserved", c_void_p * 3)]
+                ("L", c_void_p), ("info", c_void_p), ("L_low", c_void_p),
+                ("tile", c_int), ("rank_stride", c_int), ("U", c_void_p), ("Vt", c_void_p),
+                ("ranks", c_void_p), ("tlr_eps", c_double), ("max_rank", c_int), ("reserved1", c_int)]
 
 
 class MvnError(RuntimeError):

@@ -103,16 +103,21 @@ const uint64_t* lattice_table(int n) {
 }
 
 struct ProbLayout {
-  size_t at, bt, lat, ell, part, bad, yscr, total;
+  size_t at, bt, lat, ell, part, bad, yscr, zscr, total;
   int ld, grid;
+  long yslice, zslice;
 };
 
-ProbLayout prob_layout(int n, int N, int S, int prec) {
+// Workspace of one probability call.  ld is the factor's leading dimension
+// (rows of the Y scratch); zslice > 0 adds the TLR Z scratch (FP64).
+ProbLayout prob_layout_ld(int ld, int N, int S, int prec, long zslice) {
   ProbLayout L{};
-  L.ld = padded(n);
+  L.ld = ld;
   const long NS = (long)N * S;
   const long chunks = (NS + mvn::sweep_tile_cols() - 1) / mvn::sweep_tile_cols();
   L.grid = (int)(chunks < kMaxGrid ? chunks : kMaxGrid);
+  L.yslice = mvn::sweep_yslice(prec, L.ld);
+  L.zslice = zslice;
   size_t off = 0;
   L.at = off; off = align_up(off + sizeof(double) * L.ld);
   L.bt = off; off = align_up(off + sizeof(double) * L.ld);
@@ -121,10 +126,61 @@ ProbLayout prob_layout(int n, int N, int S, int prec) {
   L.part = off; off = align_up(off + sizeof(double) * 2 * (size_t)S);
   L.bad = off; off = align_up(off + sizeof(int));
   L.yscr = off;
-  off = align_up(off + (size_t)mvn::sweep_elem_bytes(prec) * (size_t)L.grid * mvn::sweep_yslice(prec, L.ld));
+  off = align_up(off + (size_t)mvn::sweep_elem_bytes(prec) * (size_t)L.grid * L.yslice);
+  L.zscr = off;
+  off = align_up(off + sizeof(double) * (size_t)L.grid * (size_t)zslice);
   L.total = off;
   return L;
 }
+
+ProbLayout prob_layout(int n, int N, int S, int prec) { return prob_layout_ld(padded(n), N, S, prec, 0); }
+
+// ---------------------------------------------------------------- tile low rank
+// Factor buffer of a TLR factor: tiles | info | U | Vt (+128 rows) | ranks.
+struct TlrGeom {
+  int m, nt, rs, ld;
+  long ntiles, npanels;
+  size_t tiles, info, U, Vt, ranks, total;
+  size_t ws_local, ws_wt, ws_t, ws_total;  // factorisation workspace
+};
+
+TlrGeom tlr_geom(int n, int m, int max_rank) {
+  TlrGeom G{};
+  G.m = m;
+  G.nt = (n + m - 1) / m;
+  G.ld = G.nt * m;
+  G.rs = (max_rank + 15) / 16 * 16;
+  G.ntiles = (long)G.nt * (G.nt + 1) / 2;
+  G.npanels = (long)G.nt * (G.nt - 1) / 2;
+  size_t off = 0;
+  G.tiles = off; off = align_up(off + sizeof(double) * (size_t)G.ntiles * m * m);
+  G.info = off; off = align_up(off + sizeof(int));
+  G.U = off; off = align_up(off + sizeof(double) * (size_t)G.npanels * m * G.rs);
+  G.Vt = off; off = align_up(off + sizeof(double) * ((size_t)G.npanels * G.rs + 128) * m);
+  G.ranks = off; off = align_up(off + sizeof(int) * (size_t)(G.npanels > 0 ? G.npanels : 1));
+  G.total = off;
+  const long batch = std::min<long>(mvn::kTlrPairBatch, G.npanels > 0 ? G.npanels : 1);
+  size_t w = 0;
+  G.ws_local = w; w = align_up(w + sizeof(int));
+  G.ws_wt = w; w = align_up(w + sizeof(double) * (size_t)batch * G.rs * G.rs);
+  G.ws_t = w; w = align_up(w + sizeof(double) * (size_t)batch * m * G.rs);
+  G.ws_total = w;
+  return G;
+}
+
+// 0 if the TLR options are usable, else writes the message and returns 1.
+int tlr_opts_check(const mvn_options* o) {
+  if (o->precision != MVN_FP64) return fail(1, "tile low-rank factors are FP64 (precision %d)", o->precision);
+  if (o->tile < 128 || o->tile > mvn::kTlrMaxTile || o->tile % 128 != 0)
+    return fail(1, "TLR tile must be a multiple of 128 in [128, %d] (got %d)", mvn::kTlrMaxTile, o->tile);
+  if (o->max_rank < 1 || o->max_rank > mvn::kTlrMaxRank || o->max_rank > o->tile)
+    return fail(1, "TLR max_rank must be in [1, min(%d, tile)] (got %d)", mvn::kTlrMaxRank, o->max_rank);
+  return 0;
+}
+
+bool is_tlr(const mvn_options* o) { return o && o->tlr_eps > 0; }
+
+long tlr_zslice(const TlrGeom& G) { return (long)(G.nt > 1 ? G.nt - 1 : 1) * G.rs * mvn::sweep_tile_cols(); }
 
 struct GradLayout {
   size_t at, bt, lat, ell, part, bad, yscr, sfw, sbar, gpart, mz, scale, total;
@@ -241,6 +297,11 @@ int mvn_factor_bytes(int n, const mvn_options* opts, size_t* bytes) {
   if (!bytes) return fail(-3, "bytes is NULL");
   const int prec = opts ? opts->precision : MVN_FP64;
   if (!prec_ok(prec)) return fail(-2, "unknown precision %d", prec);
+  if (is_tlr(opts)) {
+    if (tlr_opts_check(opts)) return -2;
+    *bytes = tlr_geom(n, opts->tile, opts->max_rank).total;
+    return 0;
+  }
   const size_t ld = padded(n);
   *bytes = align_up(sizeof(double) * ld * ld) + kAlign + align_up((size_t)elem_bytes_low(prec) * ld * ld);
   return 0;
@@ -249,8 +310,11 @@ int mvn_factor_bytes(int n, const mvn_options* opts, size_t* bytes) {
 int mvn_cholesky_workspace_bytes(int n, const mvn_options* opts, size_t* bytes) {
   if (n < 1) return fail(-1, "n must be >= 1 (got %d)", n);
   if (!bytes) return fail(-3, "bytes is NULL");
-  (void)opts;
   *bytes = 0;
+  if (is_tlr(opts)) {
+    if (tlr_opts_check(opts)) return -2;
+    *bytes = tlr_geom(n, opts->tile, opts->max_rank).ws_total;
+  }
   return 0;
 }
 
@@ -261,6 +325,12 @@ int mvn_prob_workspace_bytes(int n, int N, int S, const mvn_options* opts, size_
   if (!bytes) return fail(-5, "bytes is NULL");
   const int prec = opts ? opts->precision : MVN_FP64;
   if (!prec_ok(prec)) return fail(-4, "unknown precision %d", prec);
+  if (is_tlr(opts)) {
+    if (tlr_opts_check(opts)) return -4;
+    const TlrGeom G = tlr_geom(n, opts->tile, opts->max_rank);
+    *bytes = prob_layout_ld(G.ld, N, S, MVN_FP64, tlr_zslice(G)).total;
+    return 0;
+  }
   *bytes = prob_layout(n, N, S, prec).total;
   return 0;
 }
@@ -279,8 +349,6 @@ int mvn_cholesky(int n, const double* d_sigma, int ld_sigma, const double* d_loc
                  const mvn_matern* kern, const mvn_options* opts, void* factor_buf,
                  size_t factor_bytes, void* ws, size_t ws_bytes, mvn_factor* out,
                  hipStream_t stream) {
-  (void)ws;
-  (void)ws_bytes;
   if (n < 1) return fail(-1, "n must be >= 1 (got %d)", n);
   if (d_sigma && ld_sigma < n) return fail(-3, "ld_sigma %d < n %d", ld_sigma, n);
   if (!d_sigma) {
@@ -295,7 +363,53 @@ int mvn_cholesky(int n, const double* d_sigma, int ld_sigma, const double* d_loc
   int bad_tile = 0;
   if (!opts_ok(opts, &bad_tile)) return fail(-6, "tile must be >= 16 and a multiple of 4 (got %d)", opts->tile);
   if (!prec_ok(opts->precision)) return fail(-6, "unknown precision %d", opts->precision);
-  if (opts->tlr_eps > 0) return fail(-6, "tile low-rank factors are not available in this build");
+  if (is_tlr(opts)) {
+    if (tlr_opts_check(opts)) return -6;
+    const TlrGeom G = tlr_geom(n, opts->tile, opts->max_rank);
+    if (!factor_buf) return fail(-7, "factor buffer is NULL");
+    if (factor_bytes < G.total) return fail(-8, "factor buffer too small: %zu < %zu", factor_bytes, G.total);
+    if (!ws) return fail(-9, "workspace is NULL (the TLR factorisation needs %zu bytes)", G.ws_total);
+    if (ws_bytes < G.ws_total) return fail(-10, "workspace too small: %zu < %zu", ws_bytes, G.ws_total);
+    if (!out) return fail(-11, "out is NULL");
+    char* fb = (char*)factor_buf;
+    char* w = (char*)ws;
+    memset(out, 0, sizeof *out);
+    out->n = n;
+    out->ld = G.ld;
+    out->precision = MVN_FP64;
+    out->flags = MVN_FACTOR_TLR;
+    out->L = (double*)(fb + G.tiles);
+    out->info = (int*)(fb + G.info);
+    out->L_low = nullptr;
+    out->tile = G.m;
+    out->rank_stride = G.rs;
+    out->U = (double*)(fb + G.U);
+    out->Vt = (double*)(fb + G.Vt);
+    out->ranks = (int*)(fb + G.ranks);
+    out->tlr_eps = opts->tlr_eps;
+    out->max_rank = opts->max_rank;
+    hipError_t e = mvn::launch_tlr_build(n, G.m, G.nt, d_sigma, ld_sigma, d_locs, kern ? kern->sigma2 : 0,
+                                         kern ? kern->beta : 1, kern ? kern->nu : 0.5, kern ? kern->nugget : 0,
+                                         out->L, out->info, stream);
+    if (e != hipSuccess) return hip_fail(e, "tlr build");
+    mvn::TlrCholArgs a{};
+    a.tiles = out->L;
+    a.U = out->U;
+    a.Vt = out->Vt;
+    a.ranks = out->ranks;
+    a.info = out->info;
+    a.local_info = (int*)(w + G.ws_local);
+    a.WT = (double*)(w + G.ws_wt);
+    a.T = (double*)(w + G.ws_t);
+    a.m = G.m;
+    a.nt = G.nt;
+    a.rs = G.rs;
+    a.rcap = opts->max_rank;
+    a.eps = opts->tlr_eps;
+    e = mvn::launch_tlr_cholesky(a, stream);
+    if (e != hipSuccess) return hip_fail(e, "tlr cholesky");
+    return 0;
+  }
   size_t need = 0;
   mvn_factor_bytes(n, opts, &need);
   if (!factor_buf) return fail(-7, "factor buffer is NULL");
@@ -314,7 +428,14 @@ int mvn_cholesky(int n, const double* d_sigma, int ld_sigma, const double* d_loc
   out->L = L;
   out->info = info;
   out->L_low = low;
-  for (int k = 0; k < 3; ++k) out->reserved[k] = nullptr;
+  out->tile = 0;
+  out->rank_stride = 0;
+  out->U = nullptr;
+  out->Vt = nullptr;
+  out->ranks = nullptr;
+  out->tlr_eps = 0;
+  out->max_rank = 0;
+  out->reserved1 = 0;
   hipError_t e = mvn::launch_build_matrix(n, ld, d_sigma, ld_sigma, d_locs, kern ? kern->sigma2 : 0,
                                           kern ? kern->beta : 1, kern ? kern->nu : 0.5,
                                           kern ? kern->nugget : 0, L, info, stream);
@@ -328,7 +449,11 @@ int mvn_cholesky(int n, const double* d_sigma, int ld_sigma, const double* d_loc
 int mvn_prob(const mvn_factor* f, const double* d_a, const double* d_b, const double* d_mu, int N,
              int S, uint64_t seed, const mvn_options* opts, void* ws, size_t ws_bytes, double* d_out,
              double* d_ell, hipStream_t stream) {
-  if (!f || !f->L || !f->info || f->n < 1 || f->ld != padded(f->n))
+  if (!f || !f->L || !f->info || f->n < 1) return fail(-1, "invalid factor handle");
+  const bool tlr = (f->flags & MVN_FACTOR_TLR) != 0;
+  if (tlr ? (f->tile < 128 || f->tile % 128 != 0 || f->ld % f->tile != 0 || f->ld < f->n || f->ld - f->n >= f->tile ||
+             !f->U || !f->Vt || !f->ranks || f->rank_stride < 16 || f->rank_stride % 16 != 0)
+          : f->ld != padded(f->n))
     return fail(-1, "invalid factor handle");
   if (!d_a) return fail(-2, "lower limits are NULL");
   if (!d_b) return fail(-3, "upper limits are NULL");
@@ -338,6 +463,55 @@ int mvn_prob(const mvn_factor* f, const double* d_a, const double* d_b, const do
   if (!opts) return fail(-8, "options are required");
   const int prec = opts->precision;
   if (!prec_ok(prec)) return fail(-8, "unknown precision %d", prec);
+  if (tlr) {
+    if (prec != MVN_FP64) return fail(-8, "the TLR sweep is FP64");
+    const int n = f->n, m = f->tile, nt = f->ld / f->tile, rs = f->rank_stride;
+    const long zs = (long)(nt > 1 ? nt - 1 : 1) * rs * mvn::sweep_tile_cols();
+    const ProbLayout Lay = prob_layout_ld(f->ld, N, S, MVN_FP64, zs);
+    if (!ws) return fail(-9, "workspace is NULL");
+    if (ws_bytes < Lay.total) return fail(-10, "workspace too small: %zu < %zu", ws_bytes, Lay.total);
+    if (!d_out) return fail(-11, "output is NULL");
+    const uint64_t* lat = lattice_table(n);
+    if (!lat) return fail(-1, "could not build the lattice table for n = %d", n);
+    char* w = (char*)ws;
+    double* at = (double*)(w + Lay.at);
+    double* bt = (double*)(w + Lay.bt);
+    uint64_t* dlat = (uint64_t*)(w + Lay.lat);
+    double* ell = d_ell ? d_ell : (double*)(w + Lay.ell);
+    double* part = (double*)(w + Lay.part);
+    int* bad = (int*)(w + Lay.bad);
+    hipError_t e = hipMemcpyAsync(dlat, lat, sizeof(uint64_t) * n, hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) return hip_fail(e, "lattice copy");
+    e = mvn::launch_prob_setup(n, f->ld, d_a, d_b, d_mu, at, bt, bad, stream);
+    if (e != hipSuccess) return hip_fail(e, "setup");
+    mvn::TlrSweepArgs ta{};
+    ta.tiles = f->L;
+    ta.U = f->U;
+    ta.Vt = f->Vt;
+    ta.ranks = f->ranks;
+    ta.m = m;
+    ta.nt = nt;
+    ta.rs = rs;
+    ta.n = n;
+    ta.at = at;
+    ta.bt = bt;
+    ta.lattice = dlat;
+    ta.seed = seed;
+    ta.N = N;
+    ta.S = S;
+    ta.periodize = opts->periodize ? 1 : 0;
+    ta.yscr = (double*)(w + Lay.yscr);
+    ta.yslice = Lay.yslice;
+    ta.zscr = (double*)(w + Lay.zscr);
+    ta.zslice = Lay.zslice;
+    ta.ell = ell;
+    ta.grid = Lay.grid;
+    e = mvn::launch_tlr_sweep(ta, stream);
+    if (e != hipSuccess) return hip_fail(e, "tlr sweep");
+    e = mvn::launch_reduce(ell, N, S, part, f->info, bad, d_out, stream);
+    if (e != hipSuccess) return hip_fail(e, "reduce");
+    return 0;
+  }
   if (prec != MVN_FP64 && (prec != f->precision || !f->L_low))
     return fail(-8, "the factor holds no operand copy for precision %d (built with %d)", prec, f->precision);
   const int n = f->n;
@@ -388,6 +562,7 @@ int mvn_prob_grad(const mvn_factor* f, const double* d_a, const double* d_b, con
                   double* d_out, double* d_da, double* d_db, double* d_dmu, hipStream_t stream) {
   if (!f || !f->L || !f->info || f->n < 1 || f->ld != padded(f->n))
     return fail(-1, "invalid factor handle");
+  if (f->flags & MVN_FACTOR_TLR) return fail(-1, "the adjoint sweep needs a dense factor");
   if (!d_a) return fail(-2, "lower limits are NULL");
   if (!d_b) return fail(-3, "upper limits are NULL");
   if (N < 1) return fail(-5, "N must be >= 1 (got %d)", N);
@@ -483,6 +658,7 @@ int mvn_prob_batch(int count, const int* n_p, const void* d_plan, const int64_t*
   if (!opts) return fail(-13, "options are required");
   const int prec = opts->precision;
   if (!prec_ok(prec)) return fail(-13, "unknown precision %d", prec);
+  if (is_tlr(opts)) return fail(-13, "batched problems use dense factors (tlr_eps must be <= 0)");
   BatchPlan P;
   if (!batch_plan_host(count, n_p, P)) return fail(-2, "every problem needs n >= 1");
   if (!factor_buf) return fail(-14, "factor buffer is NULL");

@@ -118,4 +118,55 @@ __device__ __forceinline__ void mma_stage(const double* __restrict__ As,
   }
 }
 
+// One 128 x 128 tile of C (ldc) = beta C + alpha A B^T with A (M x K, lda)
+// and B (N x K, ldb) row-major.  tile_m, tile_n pick the tile.  beta is 0
+// (overwrite) or 1 (accumulate).  With MASK the loads are masked at M, N, K;
+// without it K must be a multiple of 16 and all 128 rows of both operand
+// tiles must be readable (rows past M, N only reach masked-out outputs).
+// Stores are always masked at M, N.
+template <bool MASK = true>
+__device__ __forceinline__ void gemm_nt_tile(double* __restrict__ C, long ldc, const double* __restrict__ A,
+                                             long lda, const double* __restrict__ B, long ldb, long M, long N,
+                                             long K, double alpha, double beta, long tile_m, long tile_n,
+                                             double* lds /* 4 * kStageDoubles */) {
+  const long rowA = tile_m * kTile, rowB = tile_n * kTile;
+  Acc acc;
+  acc_zero(acc);
+  const int nst = (int)((K + kStageK - 1) / kStageK);
+  if (nst > 0) {
+    double ra[8], rb[8];
+    load_rows<MASK>(A, lda, rowA, 0, M, K, ra);
+    load_rows<MASK>(B, ldb, rowB, 0, N, K, rb);
+    store_rows(lds, ra);
+    store_rows(lds + kStageDoubles, rb);
+    __syncthreads();
+    for (int s = 0; s < nst; ++s) {
+      double* cur = lds + (s & 1) * 2 * kStageDoubles;
+      double* nxt = lds + ((s + 1) & 1) * 2 * kStageDoubles;
+      if (s + 1 < nst) {
+        load_rows<MASK>(A, lda, rowA, (long)(s + 1) * kStageK, M, K, ra);
+        load_rows<MASK>(B, ldb, rowB, (long)(s + 1) * kStageK, N, K, rb);
+      }
+      mma_stage(cur, cur + kStageDoubles, acc);
+      if (s + 1 < nst) {
+        store_rows(nxt, ra);
+        store_rows(nxt + kStageDoubles, rb);
+      }
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int ib = 0; ib < 4; ++ib)
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const long gi = rowA + acc_row(ib, r), gj = rowB + acc_col(jb);
+        if (gi < M && gj < N) {
+          double* c = C + gi * ldc + gj;
+          *c = (beta == 0.0 ? 0.0 : *c) + alpha * acc.v[ib][jb][r];
+        }
+      }
+}
+
 }  // namespace mvn

@@ -1,0 +1,583 @@
+// Tile low-rank (TLR) factorisation (arXiv 2405.14892, Section III-E for the
+// tile compression; Algorithm 1's factorisation in its TLR form).  The sweep
+// through a TLR factor is in kernels_tlr_sweep.hip.
+//
+// Storage (device, inside the caller's factor buffer):
+//   tiles  lower m x m tiles, tile-major: tile (i, j), j <= i, at
+//          (i(i+1)/2 + j) m^2 doubles, row-major with leading dimension m;
+//          rows / columns past n hold the identity.  After the
+//          factorisation the diagonal tiles hold L_ii (upper part zero) and
+//          the off-diagonal tiles the updated A_ij they were compressed from.
+//   U      panel (i, k), i > k, at (i(i-1)/2 + k) m rs doubles: m x rs
+//          row-major (rs = rank stride, a multiple of 16)
+//   Vt     panel (i, k) at (i(i-1)/2 + k) rs m doubles: rs x m row-major,
+//          holding V'^T = (L_kk^{-1} V)^T, so that L_ik = U_ik V'^T_ik;
+//          followed by 128 rows of slack so that 128-row GEMM loads of the
+//          last panel stay inside the buffer
+//   ranks  int per panel; negative if the rank cap stopped the compression
+//          before the residual reached eps (|rank| is used)
+// Columns of U and rows of Vt past the rank are zero, so GEMMs whose K is
+// the rank rounded up to 16 are exact.
+//
+// Factorisation over tile columns; the tiles not yet factored are kept
+// dense and every update uses the low-rank factors:
+//   1. L_kk = chol(A_kk)                        (the dense tiled Cholesky)
+//   2. A_ik ~ U_ik V_ik^T, i > k                (adaptive cross
+//      approximation, stopped only when the exact residual Frobenius norm is
+//      <= eps, so ||A_ik - U V^T||_2 <= eps as for the truncated SVD)
+//   3. V'^T_ik = V^T_ik L_kk^{-T}               (row solves)
+//   4. A_ij -= U_ik (V'^T_ik V'_jk) U_jk^T       (FP64 MFMA GEMMs whose
+//      dimensions come from the device rank table)
+// The updates are applied left-looking: all of a tile's updates are summed
+// in one segmented-K GEMM just before its column is factored.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+#include "gemm_f64.h"
+#include "launch.h"
+#include "mvn_device.h"
+
+namespace mvn {
+
+__device__ __forceinline__ long tri_lo(long i, long j) { return i * (i + 1) / 2 + j; }   // j <= i
+__device__ __forceinline__ long tri_st(long i, long k) { return i * (i - 1) / 2 + k; }   // k < i
+
+// b = i(i+1)/2 + j with 0 <= j <= i
+__device__ __forceinline__ void tri_inverse(long b, long& i, long& j) {
+  long t = (long)((sqrt(8.0 * (double)b + 1.0) - 1.0) * 0.5);
+  while ((t + 1) * (t + 2) / 2 <= b) ++t;
+  while (t * (t + 1) / 2 > b) --t;
+  i = t;
+  j = b - t * (t + 1) / 2;
+}
+
+// ------------------------------------------------------------ build
+// One 64 x 64 sub-block of one lower tile per workgroup; clears *info.
+__global__ __launch_bounds__(256) void tlr_build_kernel(int n, int m, const double* __restrict__ sigma, int lds,
+                                                        const double* __restrict__ locs, double sigma2,
+                                                        double beta, double nu, double nugget,
+                                                        double* __restrict__ tiles, int* __restrict__ info) {
+  const long per = (long)(m / 64) * (m / 64);
+  const long t = blockIdx.x / per, sb = blockIdx.x % per;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *info = 0;
+  long ti, tj;
+  tri_inverse(t, ti, tj);
+  const long r0 = (sb / (m / 64)) * 64, c0 = (sb % (m / 64)) * 64;
+  double* A = tiles + t * (long)m * m;
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const long lr = r0 + (e >> 6), lc = c0 + (e & 63);
+    const long i = ti * m + lr, j = tj * m + lc;
+    double v;
+    if (i >= n || j >= n) {
+      v = (i == j) ? 1.0 : 0.0;
+    } else if (sigma) {
+      v = i >= j ? sigma[i * lds + j] : sigma[j * lds + i];
+    } else {
+      const double dx = locs[2 * i] - locs[2 * j];
+      const double dy = locs[2 * i + 1] - locs[2 * j + 1];
+      const double z = sqrt(dx * dx + dy * dy) / beta;
+      v = (nu == 0.5) ? sigma2 * exp(-z) : sigma2 * (1.0 + z) * exp(-z);
+      if (i == j) v += nugget;
+    }
+    A[lr * m + lc] = v;
+  }
+}
+
+// ------------------------------------------------------------ compression
+// Block-wide reductions over the 256 lanes: a shuffle tree inside each
+// wave64, then the four wave results through LDS (ties to the lower index).
+__device__ __forceinline__ void block_argmax(double v, int idx, double* sv, int* si, double& best, int& bidx) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ov = __shfl_xor(v, off);
+    const int oi = __shfl_xor(idx, off);
+    if (ov > v || (ov == v && oi < idx)) {
+      v = ov;
+      idx = oi;
+    }
+  }
+  if (lane == 0) {
+    sv[w] = v;
+    si[w] = idx;
+  }
+  __syncthreads();
+  best = sv[0];
+  bidx = si[0];
+#pragma unroll
+  for (int q = 1; q < 4; ++q)
+    if (sv[q] > best || (sv[q] == best && si[q] < bidx)) {
+      best = sv[q];
+      bidx = si[q];
+    }
+  __syncthreads();
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+__device__ __forceinline__ double block_sum(double v, double* sv) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  v = wave_sum(v);
+  if (lane == 0) sv[w] = v;
+  __syncthreads();
+  const double r = (sv[0] + sv[1]) + (sv[2] + sv[3]);
+  __syncthreads();
+  return r;
+}
+
+// Two sums in one exchange.
+__device__ __forceinline__ void block_sum2(double& a, double& b, double* sv) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  a = wave_sum(a);
+  b = wave_sum(b);
+  if (lane == 0) {
+    sv[w] = a;
+    sv[4 + w] = b;
+  }
+  __syncthreads();
+  a = (sv[0] + sv[1]) + (sv[2] + sv[3]);
+  b = (sv[4] + sv[5]) + (sv[6] + sv[7]);
+  __syncthreads();
+}
+
+// ||A - U V^T||_F^2 for one m x m tile: U (m x rs, row-major) and V^T
+// (rs x m, row-major), both zero past column / row kr (a multiple of 16).
+// The product runs on FP64 MFMA in 128 x 128 blocks (the kernel's LDS stage
+// buffers); every lane then folds its accumulator entries against A.
+__device__ __forceinline__ double residual_norm2(const double* __restrict__ A, int m, const double* __restrict__ Up, int rs,
+                                 const double* __restrict__ Vp, int kr, double* lds, double* sv) {
+  double res2 = 0.0;
+  const int nb = m / kTile, nst = kr / kStageK;
+  for (int bb = 0; bb < nb * nb; ++bb) {
+    const int bi = bb / nb, bj = bb % nb;
+    Acc acc;
+    acc_zero(acc);
+    if (nst > 0) {
+      double ra[8], rb[8];
+      load_rows<false>(Up, rs, (long)bi * kTile, 0, 0, 0, ra);
+      load_cols(Vp + (long)bj * kTile, m, 0, rb);
+      store_rows(lds, ra);
+      store_cols(lds + kStageDoubles, rb);
+      __syncthreads();
+      for (int s = 0; s < nst; ++s) {
+        double* cur = lds + (s & 1) * 2 * kStageDoubles;
+        double* nxt = lds + ((s + 1) & 1) * 2 * kStageDoubles;
+        if (s + 1 < nst) {
+          load_rows<false>(Up, rs, (long)bi * kTile, (long)(s + 1) * kStageK, 0, 0, ra);
+          load_cols(Vp + (long)bj * kTile, m, (long)(s + 1) * kStageK, rb);
+        }
+        mma_stage(cur, cur + kStageDoubles, acc);
+        if (s + 1 < nst) {
+          store_rows(nxt, ra);
+          store_cols(nxt + kStageDoubles, rb);
+        }
+        __syncthreads();
+      }
+    }
+#pragma unroll
+    for (int ib = 0; ib < 4; ++ib)
+#pragma unroll
+      for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const long gi = (long)bi * kTile + acc_row(ib, q), gj = (long)bj * kTile + acc_col(jb);
+          const double d = A[gi * m + gj] - acc.v[ib][jb][q];
+          res2 += d * d;
+        }
+  }
+  return block_sum(res2, sv);
+}
+
+// Partially pivoted cross approximation of panel tile (k + 1 + blockIdx.x, k),
+// one workgroup per tile.  Each step takes the residual row at the pivot row,
+// the pivot column at its largest entry among unused columns, the residual
+// column there, and the next pivot row at that column's largest entry among
+// unused rows.  When ||u|| ||v|| <= eps / 2 (or the rank reaches the cap) the
+// exact residual ||A - U V^T||_F is formed, and the approximation is accepted
+// only if it is <= eps; otherwise the crosses continue.  A row whose residual
+// vanishes is skipped; if every row has been used the approximation is exact.
+__global__ __launch_bounds__(256) void tlr_aca_kernel(const double* __restrict__ tiles, int k, int m, int rs,
+                                                      int rcap, double eps, double* __restrict__ U,
+                                                      double* __restrict__ Vt, int* __restrict__ ranks,
+                                                      const int* __restrict__ info) {
+  if (*info != 0) return;
+  __shared__ double row[kTlrMaxTile];
+  __shared__ unsigned char urow[kTlrMaxTile], ucol[kTlrMaxTile];
+  __shared__ double sv[256];
+  __shared__ int si[256];
+  __shared__ int s_next;
+  __shared__ double lds[4 * kStageDoubles];
+  __shared__ double uq[kTlrMaxRank];  // U row irow, then V^T column jp
+  const int t = threadIdx.x;
+  const long i = k + 1 + blockIdx.x;
+  const double* A = tiles + tri_lo(i, k) * (long)m * m;
+  const long pid = tri_st(i, k);
+  double* Up = U + pid * (long)m * rs;
+  double* Vp = Vt + pid * (long)rs * m;
+  for (long e = t; e < (long)m * rs; e += 256) {
+    Up[e] = 0.0;
+    Vp[e] = 0.0;
+  }
+  for (int e = t; e < m; e += 256) urow[e] = ucol[e] = 0;
+  __syncthreads();
+  int r = 0, irow = 0, flag = 0, next_check = 0;
+  for (int guard = 0; guard < 2 * m; ++guard) {
+    bool check = false;
+    // residual row irow (lane t holds columns t, t + 256, t + 512, t + 768)
+    double best = -1.0;
+    int bj = 0;
+    {
+      // columns past m (m < 1024) are computed on column m - 1 and dropped,
+      // so the loads carry no branches and stay in flight together
+      double v[4];
+      int jc[4];
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        jc[jj] = min(t + 256 * jj, m - 1);
+        v[jj] = A[(long)irow * m + jc[jj]];
+      }
+      if (t < r) uq[t] = Up[(long)irow * rs + t];
+      __syncthreads();
+#pragma unroll 8
+      for (int q = 0; q < r; ++q) {
+        const double u = uq[q];
+        const double* vq = Vp + (long)q * m;
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) v[jj] -= u * vq[jc[jj]];
+      }
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        const int j = t + 256 * jj;
+        if (j < m) {
+          row[j] = v[jj];
+          if (!ucol[j] && fabs(v[jj]) > best) {
+            best = fabs(v[jj]);
+            bj = j;
+          }
+        }
+      }
+    }
+    double piv;
+    int jp;
+    block_argmax(best, bj, sv, si, piv, jp);
+    if (t == 0) urow[irow] = 1;
+    __syncthreads();
+    if (!(piv > 0.0)) {
+      // this row's residual is zero: take the first unused row, or stop
+      if (t == 0) {
+        int nx = -1;
+        for (int e = 0; e < m; ++e)
+          if (!urow[e]) {
+            nx = e;
+            break;
+          }
+        s_next = nx;
+      }
+      __syncthreads();
+      const int nx = s_next;
+      __syncthreads();
+      if (nx < 0) break;  // every row used: the approximation is exact
+      irow = nx;
+      continue;
+    }
+    if (r == rcap) {
+      flag = 1;  // a further cross is needed but the cap is reached
+      break;
+    }
+    double nu2 = 0.0, nv2 = 0.0;
+    const double p = row[jp];
+    for (int j = t; j < m; j += 256) {
+      const double v = row[j] / p;
+      Vp[(long)r * m + j] = v;
+      nv2 += v * v;
+    }
+    // residual column jp (U_(:, r)); next pivot row
+    double cb = -1.0;
+    int bi = 0;
+    {
+      double v[4];
+      const double* ur[4];
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        const int ic = min(t + 256 * jj, m - 1);
+        v[jj] = A[(long)ic * m + jp];
+        ur[jj] = Up + (long)ic * rs;
+      }
+      __syncthreads();  // every lane is done with uq (row residual)
+      if (t < r) uq[t] = Vp[(long)t * m + jp];
+      __syncthreads();
+#pragma unroll 8
+      for (int q = 0; q < r; ++q) {
+        const double vq = uq[q];
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) v[jj] -= ur[jj][q] * vq;
+      }
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        const int ii = t + 256 * jj;
+        if (ii < m) {
+          Up[(long)ii * rs + r] = v[jj];
+          nu2 += v[jj] * v[jj];
+          if (!urow[ii] && fabs(v[jj]) > cb) {
+            cb = fabs(v[jj]);
+            bi = ii;
+          }
+        }
+      }
+    }
+    if (t == 0) ucol[jp] = 1;
+    block_sum2(nu2, nv2, sv);
+    double cbest;
+    int ip;
+    block_argmax(cb, bi, sv, si, cbest, ip);
+    ++r;
+    if (cbest >= 0.0) {
+      irow = ip;
+    } else {
+      check = true;  // every row used
+    }
+    if ((sqrt(nu2 * nv2) <= 0.5 * eps && r >= next_check) || r == rcap) check = true;
+    if (!check) continue;
+    // exact residual; after a failed check the next one waits a few crosses
+    const double res2 = residual_norm2(A, m, Up, rs, Vp, (r + 15) & ~15, lds, sv);
+    next_check = r + max(2, r / 8);
+    if (res2 <= eps * eps) break;
+    if (cbest < 0.0) break;  // rows exhausted; what is left is rounding
+    if (r == rcap) {
+      flag = 1;
+      break;
+    }
+  }
+  if (t == 0) ranks[pid] = flag ? -r : r;
+}
+
+// ------------------------------------------------------------ row solves
+// x L_kk^T = b for every rank row of every panel of step k (the rows of Vt),
+// one wave per row and four rows per workgroup (grid: panels x rs / 4).
+// Lane c owns column c0 + c of the current 64-column block: the part of its
+// sum over earlier blocks is a dot product against rows of L_kk staged in
+// LDS; inside the block a 64-step forward substitution broadcasts each
+// solved value from its lane.
+__global__ __launch_bounds__(256) void tlr_trsm_rows_kernel(const double* __restrict__ tiles, int k, int m,
+                                                            int rs, double* __restrict__ Vt,
+                                                            const int* __restrict__ ranks,
+                                                            const int* __restrict__ info) {
+  if (*info != 0) return;
+  __shared__ double Ls[64][64 + 1];
+  __shared__ double rd[64];
+  __shared__ double xs[4][kTlrMaxTile];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const long i = k + 1 + blockIdx.x;
+  const long pid = tri_st(i, k);
+  const int rk = abs(ranks[pid]);
+  if ((int)blockIdx.y * 4 >= rk) return;  // uniform over the workgroup
+  const int row = blockIdx.y * 4 + w;
+  const bool live = row < rk;
+  const double* L = tiles + tri_lo(k, k) * (long)m * m;
+  double* x = Vt + pid * (long)rs * m + (long)(live ? row : 0) * m;
+  for (int c0 = 0; c0 < m; c0 += 64) {
+    double acc = live ? x[c0 + lane] : 0.0;
+    for (int l0 = 0; l0 < c0; l0 += 64) {
+      __syncthreads();
+      for (int e = t; e < 64 * 64; e += 256) Ls[e >> 6][e & 63] = L[(long)(c0 + (e >> 6)) * m + l0 + (e & 63)];
+      __syncthreads();
+      double a0 = 0.0, a1 = 0.0;
+#pragma unroll 8
+      for (int ll = 0; ll < 64; ll += 2) {
+        a0 += xs[w][l0 + ll] * Ls[lane][ll];
+        a1 += xs[w][l0 + ll + 1] * Ls[lane][ll + 1];
+      }
+      acc -= a0 + a1;
+    }
+    __syncthreads();
+    for (int e = t; e < 64 * 64; e += 256) {
+      const int rr = e >> 6, ll = e & 63;
+      Ls[rr][ll] = ll <= rr ? L[(long)(c0 + rr) * m + c0 + ll] : 0.0;
+    }
+    if (t < 64) rd[t] = 1.0 / L[(long)(c0 + t) * m + c0 + t];
+    __syncthreads();
+    double xv = 0.0;
+    for (int c = 0; c < 64; ++c) {
+      const double xc = __shfl(acc, c) * rd[c];
+      if (lane == c) xv = xc;
+      if (lane > c) acc -= xc * Ls[lane][c];
+    }
+    xs[w][c0 + lane] = xv;
+    if (live) x[c0 + lane] = xv;
+  }
+}
+
+// ------------------------------------------------------------ updates
+// Left-looking: before column j is factored, every tile (i, j), i >= j,
+// takes all of its updates at once,
+//   A_ij -= sum_{k<j} U_ik W_ijk U_jk^T,   W_ijk = V'^T_ik V'_jk,
+// so each tile is read and written once.  The (i, k) pairs of one launch
+// are z = (i - i0) nk + (k - k0) for i in [i0, i0 + ni), k in [k0, k0 + nk).
+
+// WT_z = V'^T_jk (V'^T_ik)^T: r_jk x r_ik.  Grid (pairs, rs/128, rs/128):
+// the pair is the fastest grid index, so that the workgroups that have work
+// (mostly tile (0, 0)) are consecutive and spread over all XCDs.
+__global__ __launch_bounds__(256) void tlr_w_kernel(int j, int i0, int k0, int nk, int m, int rs,
+                                                    const double* __restrict__ Vt, const int* __restrict__ ranks,
+                                                    double* __restrict__ WT, const int* __restrict__ info) {
+  if (*info != 0) return;
+  __shared__ double lds[4 * kStageDoubles];
+  const long z = blockIdx.x;
+  const long i = i0 + z / nk, k = k0 + z % nk;
+  const int ri = abs(ranks[tri_st(i, k)]), rj = abs(ranks[tri_st(j, k)]);
+  if ((long)blockIdx.y * kTile >= rj || (long)blockIdx.z * kTile >= ri) return;
+  // unmasked loads: K = m, and the 128-row operand tiles stay inside the Vt
+  // arena (its 128 rows of slack cover the last panel)
+  gemm_nt_tile<false>(WT + z * rs * rs, rs, Vt + tri_st(j, k) * (long)rs * m, m, Vt + tri_st(i, k) * (long)rs * m,
+                      m, rj, ri, m, 1.0, 0.0, blockIdx.y, blockIdx.z, lds);
+}
+
+// T_z = U_ik W_ijk: m x r_jk (B operand WT_z, K = r_ik); columns r_jk up to
+// the next multiple of 16 are set to zero for the segmented K loop below.
+__global__ __launch_bounds__(256) void tlr_t_kernel(int j, int i0, int k0, int nk, int m, int rs,
+                                                    const double* __restrict__ U, const int* __restrict__ ranks,
+                                                    const double* __restrict__ WT, double* __restrict__ T,
+                                                    const int* __restrict__ info) {
+  if (*info != 0) return;
+  __shared__ double lds[4 * kStageDoubles];
+  const long i = i0 + blockIdx.z / nk, k = k0 + blockIdx.z % nk;
+  const int ri = abs(ranks[tri_st(i, k)]), rj = abs(ranks[tri_st(j, k)]);
+  if ((long)blockIdx.y * kTile >= rj) return;
+  double* Tz = T + (long)blockIdx.z * m * rs;
+  gemm_nt_tile(Tz, rs, U + tri_st(i, k) * (long)m * rs, rs, WT + (long)blockIdx.z * rs * rs, rs, m, rj, ri, 1.0,
+               0.0, blockIdx.x, blockIdx.y, lds);
+  const int r16 = (rj + 15) & ~15;
+  if ((int)blockIdx.y == rj / kTile && r16 > rj) {
+    const int w = r16 - rj;
+    for (int e = threadIdx.x; e < kTile * w; e += 256)
+      Tz[((long)blockIdx.x * kTile + e / w) * rs + rj + e % w] = 0.0;
+  }
+}
+
+// A_ij -= sum_k T_z U_jk^T for k in [k0, k0 + nk): one 128 x 128 block of
+// tile (i0 + blockIdx.z, j) per workgroup, K running over the k segments
+// (each rounded up to 16; T_z and U_jk are zero past r_jk).  Of a diagonal
+// tile only the lower blocks are updated.
+__global__ __launch_bounds__(256) void tlr_u_kernel(int j, int i0, int k0, int nk, int m, int rs,
+                                                    double* __restrict__ tiles, const double* __restrict__ U,
+                                                    const int* __restrict__ ranks, const double* __restrict__ T,
+                                                    const int* __restrict__ info) {
+  if (*info != 0) return;
+  __shared__ double lds[4 * kStageDoubles];
+  const long i = i0 + blockIdx.z;
+  const long tr = blockIdx.y, tc = blockIdx.x;
+  if (i == j && tc > tr) return;
+  int nst = 0;
+  for (int kk = 0; kk < nk; ++kk) nst += (abs(ranks[tri_st(j, k0 + kk)]) + kStageK - 1) / kStageK;
+  if (nst == 0) return;
+  Acc acc;
+  acc_zero(acc);
+  int ck = 0, cs = 0;  // cursor: segment k0 + ck, stage cs inside it
+  auto load = [&](double (&ra)[8], double (&rb)[8]) {
+    while (cs * kStageK >= abs(ranks[tri_st(j, k0 + ck)])) {
+      ++ck;
+      cs = 0;
+    }
+    const long z = (long)blockIdx.z * nk + ck;
+    load_rows<false>(T + z * m * rs, rs, tr * kTile, (long)cs * kStageK, 0, 0, ra);
+    load_rows<false>(U + tri_st(j, k0 + ck) * (long)m * rs, rs, tc * kTile, (long)cs * kStageK, 0, 0, rb);
+    ++cs;
+  };
+  double ra[8], rb[8];
+  load(ra, rb);
+  store_rows(lds, ra);
+  store_rows(lds + kStageDoubles, rb);
+  __syncthreads();
+  for (int s = 0; s < nst; ++s) {
+    double* cur = lds + (s & 1) * 2 * kStageDoubles;
+    double* nxt = lds + ((s + 1) & 1) * 2 * kStageDoubles;
+    if (s + 1 < nst) load(ra, rb);
+    mma_stage(cur, cur + kStageDoubles, acc);
+    if (s + 1 < nst) {
+      store_rows(nxt, ra);
+      store_rows(nxt + kStageDoubles, rb);
+    }
+    __syncthreads();
+  }
+  double* C = tiles + tri_lo(i, j) * (long)m * m;
+#pragma unroll
+  for (int ib = 0; ib < 4; ++ib)
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        double* c = C + (tr * kTile + acc_row(ib, q)) * (long)m + tc * kTile + acc_col(jb);
+        *c -= acc.v[ib][jb][q];
+      }
+}
+
+// local = info (so that a failed earlier step skips the tile's kernels)
+__global__ void tlr_info_copy_kernel(const int* __restrict__ info, int* __restrict__ local) {
+  if (threadIdx.x == 0) *local = *info;
+}
+
+// info = first failing global pivot (1-based) from the tile's local info
+__global__ void tlr_info_kernel(int* __restrict__ info, const int* __restrict__ local, int offset) {
+  if (threadIdx.x == 0 && *local != 0 && *info == 0) *info = *local + offset;
+}
+
+hipError_t launch_tlr_build(int n, int m, int nt, const double* sigma, int lds, const double* locs,
+                            double sigma2, double beta, double nu, double nugget, double* tiles, int* info,
+                            hipStream_t st) {
+  const long sub = (long)(m / 64) * (m / 64) * ((long)nt * (nt + 1) / 2);
+  hipLaunchKernelGGL(tlr_build_kernel, dim3((unsigned)sub), dim3(256), 0, st, n, m, sigma, lds, locs, sigma2,
+                     beta, nu, nugget, tiles, info);
+  return hipGetLastError();
+}
+
+hipError_t launch_tlr_cholesky(const TlrCholArgs& a, hipStream_t st) {
+  const int m = a.m, nt = a.nt, rs = a.rs;
+  const unsigned rt = (unsigned)((rs + kTile - 1) / kTile), mt = (unsigned)(m / kTile);
+  for (int j = 0; j < nt; ++j) {
+    // updates of column j from the panels k < j, in launches of at most
+    // kTlrPairBatch (i, k) pairs
+    if (j > 0) {
+      const int nk = (int)std::min<long>(j, kTlrPairBatch);
+      const int ni_max = (int)std::max<long>(1, kTlrPairBatch / nk);
+      for (int i0 = j; i0 < nt; i0 += ni_max) {
+        const int ni = std::min(ni_max, nt - i0);
+        for (int k0 = 0; k0 < j; k0 += nk) {
+          const int nkc = std::min(nk, j - k0);
+          const unsigned np = (unsigned)(ni * nkc);
+          hipLaunchKernelGGL(tlr_w_kernel, dim3(np, rt, rt), dim3(256), 0, st, j, i0, k0, nkc, m, rs,
+                             (const double*)a.Vt, (const int*)a.ranks, a.WT, (const int*)a.info);
+          hipLaunchKernelGGL(tlr_t_kernel, dim3(mt, rt, np), dim3(256), 0, st, j, i0, k0, nkc, m, rs,
+                             (const double*)a.U, (const int*)a.ranks, (const double*)a.WT, a.T,
+                             (const int*)a.info);
+          hipLaunchKernelGGL(tlr_u_kernel, dim3(mt, mt, (unsigned)ni), dim3(256), 0, st, j, i0, k0, nkc, m, rs,
+                             a.tiles, (const double*)a.U, (const int*)a.ranks, (const double*)a.T,
+                             (const int*)a.info);
+        }
+      }
+    }
+    double* Djj = a.tiles + (long)(j * (j + 1) / 2 + j) * m * m;
+    hipLaunchKernelGGL(tlr_info_copy_kernel, dim3(1), dim3(64), 0, st, (const int*)a.info, a.local_info);
+    hipError_t e = launch_cholesky_f64(m, 128, Djj, a.local_info, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(tlr_info_kernel, dim3(1), dim3(64), 0, st, a.info, (const int*)a.local_info, j * m);
+    const int P = nt - j - 1;
+    if (P > 0) {
+      hipLaunchKernelGGL(tlr_aca_kernel, dim3(P), dim3(256), 0, st, (const double*)a.tiles, j, m, rs, a.rcap,
+                         a.eps, a.U, a.Vt, a.ranks, (const int*)a.info);
+      hipLaunchKernelGGL(tlr_trsm_rows_kernel, dim3(P, rs / 4), dim3(256), 0, st, (const double*)a.tiles, j, m, rs,
+                         a.Vt, (const int*)a.ranks, (const int*)a.info);
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace mvn

@@ -129,4 +129,49 @@ hipError_t launch_batch_sweep(const BatchSweepArgs& a, hipStream_t st);
 hipError_t launch_batch_reduce(const double* ell, int count, int N, int S, double* part, const int* info,
                                const int* bad, double* out, hipStream_t st);
 
+// ---------------------------------------------------------------- tile low rank
+constexpr int kTlrMaxTile = 1024;   // largest TLR tile edge (LDS rows of the compression kernel)
+constexpr int kTlrMaxRank = 256;    // largest rank cap (one lane per rank row in the row solves)
+constexpr long kTlrPairBatch = 256; // tile pairs per update launch (sizes the WT / T workspace)
+
+// Lower tiles of Sigma (tile-major, m x m each, identity past n) from the
+// caller's Sigma or from locations with the Matern kernel; clears *info.
+hipError_t launch_tlr_build(int n, int m, int nt, const double* sigma, int lds, const double* locs,
+                            double sigma2, double beta, double nu, double nugget, double* tiles, int* info,
+                            hipStream_t st);
+
+struct TlrCholArgs {
+  double* tiles;     // nt(nt+1)/2 tiles of m x m
+  double* U;         // nt(nt-1)/2 panels of m x rs
+  double* Vt;        // nt(nt-1)/2 panels of rs x m (+ 128 rows of slack)
+  int* ranks;        // nt(nt-1)/2
+  int* info;         // global info (1 int)
+  int* local_info;   // per-tile info scratch (1 int)
+  double* WT;        // kTlrPairBatch x rs x rs
+  double* T;         // kTlrPairBatch x m x rs
+  int m, nt, rs, rcap;
+  double eps;
+};
+hipError_t launch_tlr_cholesky(const TlrCholArgs& a, hipStream_t st);
+
+struct TlrSweepArgs {
+  const double* tiles;
+  const double* U;
+  const double* Vt;
+  const int* ranks;
+  int m, nt, rs, n;
+  const double* at;
+  const double* bt;
+  const uint64_t* lattice;
+  uint64_t seed;
+  int N, S, periodize;
+  double* yscr;     // grid x (nt m) x 64
+  long yslice;
+  double* zscr;     // grid x (nt - 1) x rs x 64
+  long zslice;
+  double* ell;
+  int grid;
+};
+hipError_t launch_tlr_sweep(const TlrSweepArgs& a, hipStream_t st);
+
 }  // namespace mvn

@@ -21,7 +21,9 @@ typedef __attribute__((address_space(3))) uint64_t lds_u64;
 //   s_i = S_i + sum_{k<i} L_ik y_k,  a' = (a~_i - s_i)/L_ii,
 //   b' = (b~_i - s_i)/L_ii,  (y_i, d_i) = condition_step(a', b', w_i),
 // leaving y_i in T and folding d_i into the sample's running product
-// (and, for the adjoint, s_i in s_out[(i0 + i) * 64 + lane]).
+// (and, for the adjoint, s_i in s_out[(i0 + i) * 64 + lane]).  L and the
+// row indices are local to a diagonal tile starting at global row goff
+// (0 for a dense factor); goff + i0 + i is the QMC dimension of row i.
 // This file is compiled without machine loop-invariant code motion: hoisting
 // the step's ~60 polynomial constants out of the row loop would pin them in
 // registers next to the GEMM's accumulators and force spills (build.py).
@@ -29,7 +31,7 @@ __device__ __forceinline__ LogProd condition_block(
     lds_f64* T, lds_f64* slab, const lds_f64* c_at, const lds_f64* c_bt, const lds_f64* c_rl,
     const lds_u64* c_lat, const double* __restrict__ L, long ld, int i0, int rows, int n,
     uint64_t jpt, uint64_t sidx, uint64_t seed, int periodize, bool valid, LogProd prod,
-    double* __restrict__ s_out = nullptr) {
+    double* __restrict__ s_out = nullptr, int goff = 0) {
   const int t = threadIdx.x, lane = t & 63;
   const bool owner = (t >> 6) == 0;
   for (int q = 0; q < rows; q += kSlab) {
@@ -64,7 +66,7 @@ __device__ __forceinline__ LogProd condition_block(
         const double rl = c_rl[i];
         const double alpha = (c_at[i] - sum) * rl;
         const double beta = (c_bt[i] - sum) * rl;
-        const uint64_t g = (uint64_t)(i0 + i);
+        const uint64_t g = (uint64_t)(goff + i0 + i);
         const double w = richtmyer(jpt, c_lat[i], splitmix64(seed, sidx * (uint64_t)n + g), periodize);
         const Step st = condition_step(alpha, beta, w, 1.0 - w);
         T[i * kCols + lane] = valid ? st.y : 0.0;

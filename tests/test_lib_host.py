@@ -97,3 +97,58 @@ def test_conditioning_step_matches_oracle(harness):
 def test_splitmix64_matches_published_outputs(harness):
     got = [int(v) for v in _run(harness, ["sm 0 0", "sm 0 1", "sm 0 2"])]
     assert got == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+
+
+def test_ctypes_structs_match_the_c_header(tmp_path):
+    """sizeof / offsetof of the public structs, from the C compiler, equal the
+    ctypes mirrors the binding passes by reference."""
+    fields = {"mvn_options": _lib.MvnOptions, "mvn_factor": _lib.MvnFactor, "mvn_matern": _lib.MvnMatern}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "mvn.h"', "int main(void) {"]
+    for cname, cls in fields.items():
+        lines.append(f'  printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for f, _ in cls._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = str(tmp_path / "layout")
+    subprocess.run(["gcc", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"), "-I", "/opt/rocm/include",
+                    str(src), "-o", exe], check=True, capture_output=True)
+    out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = {(a, b): int(c) for a, b, c in (l.split() for l in out if l)}
+    for cname, cls in fields.items():
+        assert got[(cname, "sizeof")] == ctypes.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert got[(cname, f)] == getattr(cls, f).offset, (cname, f)
+
+
+def test_tlr_size_queries_and_option_checks():
+    opts = mvn.options(tile=256, tlr_eps=1e-6, max_rank=100)
+    n, m, rs = 1000, 256, 112
+    nt = 4
+    fb = mvn.mvn_factor_bytes(n, opts)
+    tiles = nt * (nt + 1) // 2 * m * m * 8
+    panels = nt * (nt - 1) // 2
+    assert fb >= tiles + panels * m * rs * 8 * 2 + 128 * m * 8 + panels * 4
+    assert fb < tiles + panels * m * rs * 8 * 2 + 128 * m * 8 + 8192
+    ws = mvn.mvn_cholesky_workspace_bytes(n, opts)
+    assert ws >= panels * (rs * rs + m * rs) * 8
+    assert mvn.mvn_cholesky_workspace_bytes(n, mvn.options(tile=256)) == 0
+    pw = mvn.mvn_prob_workspace_bytes(n, 1000, 2, opts)
+    assert pw >= 2000 * 8 + 32 * (nt * m * 64 + (nt - 1) * rs * 64) * 8
+    for bad in (dict(tile=200), dict(tile=2048), dict(max_rank=0), dict(max_rank=300),
+                dict(precision=mvn.MVN_FP32)):
+        kw = dict(tile=256, tlr_eps=1e-6, max_rank=100)
+        kw.update(bad)
+        with pytest.raises(mvn.MvnError) as e:
+            mvn.mvn_factor_bytes(n, mvn.options(**kw))
+        assert e.value.code == -2, bad
+    # the batched entry point takes dense factors only
+    h = _lib.lib()
+    plan = ctypes.create_string_buffer(4096)
+    sizes = (ctypes.c_int * 1)(10)
+    code = h.mvn_prob_batch(1, sizes, plan, ctypes.c_void_p(8), ctypes.c_void_p(8),
+                            ctypes.byref(_lib.MvnMatern(1.0, 0.1, 0.5, 0.0)), ctypes.c_void_p(8),
+                            ctypes.c_void_p(8), None, 10, 1, 1, ctypes.byref(opts), None, 0, None, 0, None,
+                            None, None)
+    assert code == -13 and b"dense" in h.mvn_last_error()
