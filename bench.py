@@ -6,7 +6,20 @@ sweep over N = 20000 Richtmyer points x S = 10 shifts with the final
 log-sum-exp reduction.  Inputs (locations, limits) are resident in HBM before
 the timed region.  Prints one JSON line.
 
-    python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--no-cpu-baseline]
+After the timed steps the same line carries measured variants (each run once
+after a warm-up, outside the timed region):
+  precision   FP32 / BF16 / split-BF16 trailing updates and sweep GEMMs on the
+              same problem, with their error against the FP64 result
+  oracle400   the 400-site problem in every precision against the CPU oracle
+              on identical QMC points
+  tlr64k      the 65536-site problem: dense FP64 vs tile low-rank at 1e-5 and
+              1e-7 (ranks, times, log P difference)
+  batch2000   2000 confidence-region problems of uneven size in one call
+  grad4096    forward + adjoint sweep for d log P / d(a, b, mu)
+
+    python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--no-cpu-baseline] [--no-variants]
+    python bench.py --workload tlr64k --tlr-eps 1e-5 --no-variants --no-cpu-baseline
+    python bench.py --precision bf16 --no-variants --no-cpu-baseline
 """
 from __future__ import annotations
 
@@ -17,19 +30,22 @@ import math
 import os
 import sys
 import time
+import traceback
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "MVN probs/sec + effective TFLOP/s (Cholesky+SOV) at stated error vs FP64 oracle"
-PEAK_FP64_TFLOPS = 78.6
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0, "bf16x3": 2500.0}
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3}
 
-# HBM bytes per sweep launch on this workload from rocprofv3 FETCH_SIZE x2 + WRITE_SIZE x1
-# (scales from a 1 GiB copy; profiles/sweep_f64_prec16k.md), valid only for the kernel
-# sources they were measured on.
+# HBM bytes per sweep launch on the 16384-site FP64 workload from rocprofv3
+# FETCH_SIZE x2 + WRITE_SIZE x1 (factors from a 1 GiB copy; the summary is
+# profiles/sweep_kernel_f64_prec16k.md), valid only for the kernel sources
+# they were measured on (checked by hash).
 TRAFFIC_SOURCES = ["paper_2405_14892_amd/csrc/kernels_sov.hip", "paper_2405_14892_amd/csrc/mvn_device.h",
-                   "paper_2405_14892_amd/csrc/gemm_f64.h"]
-TRAFFIC_MEASURED = {"prec16k": ("3694a5d041d9fa63", 3.231e12)}
+                   "paper_2405_14892_amd/csrc/sweep_gemm.h", "paper_2405_14892_amd/csrc/sweep_block.h"]
+TRAFFIC_MEASURED = {"prec16k": ("3b1cbb579b974297", 4.1486e12)}
 
 
 def _traffic(workload: str):
@@ -72,13 +88,266 @@ def _cpu_baseline(w, n_sub: int = 4096, cols: int = 512) -> dict:
             "seconds_full_problem_extrapolated": full}
 
 
+class Problem:
+    """One MVN problem with its device buffers, run through the C ABI on the
+    current stream; phase times come from HIP events on that stream."""
+
+    def __init__(self, w, opts, dev):
+        import torch
+        import paper_2405_14892_amd as mvn
+        from paper_2405_14892_amd import _lib
+        self.torch, self.mvn, self.lib = torch, mvn, _lib
+        self.h = _lib.lib()
+        self.w, self.opts, self.dev = w, opts, dev
+        n, N, S = w.n, w.N, w.S
+        self.kern = _lib.MvnMatern(w.sigma2, w.beta, w.nu, w.nugget)
+        f64 = lambda x: torch.as_tensor(x, dtype=torch.float64).to(dev).contiguous()
+        self.locs, self.a, self.b = f64(w.locs), f64(w.a), f64(w.b)
+        self.mu = f64(w.mu) if w.mu is not None else None
+        self.fb = mvn.mvn_factor_bytes(n, opts)
+        self.cwb = mvn.mvn_cholesky_workspace_bytes(n, opts)
+        self.wsb = mvn.mvn_prob_workspace_bytes(n, N, S, opts)
+        self.fbuf = torch.empty(self.fb, dtype=torch.uint8, device=dev)
+        self.cws = torch.empty(max(self.cwb, 1), dtype=torch.uint8, device=dev)
+        self.ws = torch.empty(self.wsb, dtype=torch.uint8, device=dev)
+        self.out = torch.empty(4 + S, dtype=torch.float64, device=dev)
+        self.fac = _lib.MvnFactor()
+        self.stream = torch.cuda.current_stream(dev)
+        self.sp = ctypes.c_void_p(self.stream.cuda_stream)
+
+    @staticmethod
+    def _p(t):
+        return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+    def step(self):
+        """Enqueue one problem; returns the (start, factored, done) events."""
+        torch, P, w = self.torch, self._p, self.w
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        e[0].record(self.stream)
+        self.lib.check(self.h.mvn_cholesky(w.n, None, 0, P(self.locs), ctypes.byref(self.kern),
+                                           ctypes.byref(self.opts), P(self.fbuf), self.fb, P(self.cws), self.cwb,
+                                           ctypes.byref(self.fac), self.sp))
+        e[1].record(self.stream)
+        self.lib.check(self.h.mvn_prob(ctypes.byref(self.fac), P(self.a), P(self.b), P(self.mu), w.N, w.S,
+                                       ctypes.c_uint64(w.seed), ctypes.byref(self.opts), P(self.ws), self.wsb,
+                                       P(self.out), None, self.sp))
+        e[2].record(self.stream)
+        return e
+
+    def run(self, steps, warmup):
+        torch = self.torch
+        for _ in range(warmup):
+            self.step()
+            torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev = [self.step() for _ in range(steps)]
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / steps
+        chol = [a.elapsed_time(b) for a, b, _ in ev]
+        sov = [b.elapsed_time(c) for _, b, c in ev]
+        res = self.out.cpu().numpy()
+        return {"wall_ms": wall * 1e3, "cholesky_ms": sum(chol) / len(chol), "sov_ms": sum(sov) / len(sov),
+                "logP": float(res[0]), "P": float(res[1]), "rel_stderr": float(res[3]), "info": self.info()}
+
+    def info(self):
+        off = self.fac.info - self.fbuf.data_ptr()
+        return int(self.fbuf[off: off + 4].view(self.torch.int32).item())
+
+    def ranks(self):
+        import numpy as np
+        nt = self.fac.ld // self.fac.tile
+        cnt = nt * (nt - 1) // 2
+        off = self.fac.ranks - self.fbuf.data_ptr()
+        return self.fbuf[off: off + 4 * cnt].view(self.torch.int32).cpu().numpy().astype(np.int64)
+
+
+def _flops(n, NS):
+    return n ** 3 / 3.0, float(n) * (n - 1) * NS
+
+
+def _free():
+    import gc
+    import torch
+    gc.collect()
+    torch.cuda.empty_cache()
+
+
+def variant_precision(w, dev, ref) -> dict:
+    import paper_2405_14892_amd as mvn
+    out = {}
+    for name in ("fp32", "bf16", "bf16x3"):
+        p = Problem(w, mvn.options(tile=w.tile, precision=PRECISIONS[name]), dev)
+        r = p.run(1, 1)
+        chol, sov = _flops(w.n, w.N * w.S)
+        out[name] = {"wall_ms": r["wall_ms"], "cholesky_ms": r["cholesky_ms"], "sov_ms": r["sov_ms"],
+                     "info": r["info"], "logP": r["logP"], "abs_dlogP_vs_fp64": abs(r["logP"] - ref["logP"]),
+                     "abs_dP_vs_fp64": abs(r["P"] - ref["P"]), "rel_stderr": r["rel_stderr"],
+                     "speedup_vs_fp64": ref["wall_ms"] / r["wall_ms"],
+                     "sweep_tflops": sov / (r["sov_ms"] * 1e-3) / 1e12,
+                     "cholesky_tflops": chol / (r["cholesky_ms"] * 1e-3) / 1e12}
+        del p
+        _free()
+    out["note"] = ("error against the FP64 GPU result on identical QMC points; the FP64 path matches "
+                   "the oracle to 1e-10 (parity tests and oracle400).  info > 0: the reduced-precision "
+                   "trailing updates lost positive definiteness at that pivot (all outputs NaN)")
+    return out
+
+
+def variant_oracle400(dev) -> dict:
+    import numpy as np
+    import oracle
+    import paper_2405_14892_amd as mvn
+    import workloads
+    out = {}
+    for excursion in (False, True):
+        w = workloads.make_workload("dense400", positive_excursion=excursion)
+        t0 = time.perf_counter()
+        L = oracle.cholesky(oracle.covariance(w.locs, w.sigma2, w.beta, w.nu, w.nugget))
+        at, bt = oracle.centre(w.a, w.b, w.mu)
+        ref = oracle.reduce_samples(oracle.sweep(L, at, bt, w.N, w.S, w.seed), w.N, w.S)
+        t_or = time.perf_counter() - t0
+        key = "b=mu-u" if excursion else "b=u-mu"
+        rows = {"oracle_logP": ref["logP"], "oracle_P": ref["P"], "oracle_rel_stderr": ref["rel_stderr"],
+                "oracle_seconds": t_or}
+        for name, code in PRECISIONS.items():
+            p = Problem(w, mvn.options(tile=w.tile, precision=code), dev)
+            r = p.run(3, 1)
+            rows[name] = {"wall_ms": r["wall_ms"], "abs_dlogP": abs(r["logP"] - ref["logP"]),
+                          "abs_dP": abs(r["P"] - ref["P"])}
+            del p
+        out[key] = rows
+        _free()
+    return out
+
+
+def variant_tlr(dev) -> dict:
+    import numpy as np
+    import paper_2405_14892_amd as mvn
+    import workloads
+    w = workloads.make_workload("tlr64k")
+    chol_f, sov_f = _flops(w.n, w.N * w.S)
+    out = {}
+    p = Problem(w, mvn.options(tile=512), dev)
+    r = p.run(1, 0)
+    out["dense_fp64"] = {"wall_ms": r["wall_ms"], "cholesky_ms": r["cholesky_ms"], "sov_ms": r["sov_ms"],
+                         "logP": r["logP"], "info": r["info"],
+                         "cholesky_tflops": chol_f / (r["cholesky_ms"] * 1e-3) / 1e12,
+                         "sweep_tflops": sov_f / (r["sov_ms"] * 1e-3) / 1e12}
+    dense = r
+    del p
+    _free()
+    for eps in (1e-5, 1e-7):
+        p = Problem(w, mvn.options(tile=w.tile, tlr_eps=eps, max_rank=256), dev)
+        r = p.run(1, 1)
+        ranks = np.abs(p.ranks())
+        m = w.tile
+        nt = p.fac.ld // m
+        # executed sweep flops per sample: 4 m k_ij over the panels + the dense diagonal tiles
+        sweep_exec = (4.0 * m * ranks.sum() + nt * float(m) * m) * w.N * w.S
+        out[f"tlr_{eps:g}"] = {
+            "wall_ms": r["wall_ms"], "cholesky_ms": r["cholesky_ms"], "sov_ms": r["sov_ms"], "logP": r["logP"],
+            "abs_dlogP_vs_dense": abs(r["logP"] - dense["logP"]), "info": r["info"],
+            "speedup_vs_dense": dense["wall_ms"] / r["wall_ms"],
+            "cholesky_speedup_vs_dense": dense["cholesky_ms"] / r["cholesky_ms"],
+            "sweep_speedup_vs_dense": dense["sov_ms"] / r["sov_ms"],
+            "effective_tflops": (chol_f + sov_f) / (r["wall_ms"] * 1e-3) / 1e12,
+            "sweep_executed_tflops": sweep_exec / (r["sov_ms"] * 1e-3) / 1e12,
+            "ranks": {"mean": float(ranks.mean()), "max": int(ranks.max()),
+                      "adjacent_mean": float(np.mean([ranks[i * (i - 1) // 2 + i - 1] for i in range(1, nt)])),
+                      "histogram_by_16": np.bincount(np.minimum(ranks // 16, 16)).tolist()}}
+        del p
+        _free()
+    out["config"] = (f"n={w.n} (256^2 Morton grid), Matern nu={w.nu}, beta={w.beta}, nugget={w.nugget}, "
+                     f"N={w.N} x S={w.S}; dense tile 512, TLR tile {w.tile}, max_rank 256")
+    return out
+
+
+def variant_batch(dev) -> dict:
+    import numpy as np
+    import torch
+    import paper_2405_14892_amd as mvn
+    import workloads
+    bw = workloads.make_batch()
+    sizes = bw.n_p.astype(np.int32)
+    idx = torch.as_tensor(bw.idx).to(dev)
+    locs = torch.as_tensor(bw.locs).to(dev)
+    a, b = torch.as_tensor(bw.a).to(dev), torch.as_tensor(bw.b).to(dev)
+    kern = (bw.sigma2, bw.beta, bw.nu, bw.nugget)
+    NS = bw.N * bw.S
+    sov_f = float(np.sum(bw.n_p.astype(np.float64) * (bw.n_p - 1))) * NS
+    out = {}
+    for name in ("fp32", "bf16", "fp64"):
+        plan = mvn.mvn_batch_plan(sizes, bw.N, bw.S, mvn.options(tile=128, precision=PRECISIONS[name]), device=dev)
+        mvn.mvn_prob_batch(plan, idx, locs, kern, a, b, None, seed=bw.seed)
+        torch.cuda.synchronize()
+        st = torch.cuda.current_stream(dev)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        reps = 2
+        for _ in range(reps):
+            mvn.mvn_prob_batch(plan, idx, locs, kern, a, b, None, seed=bw.seed)
+        e1.record(st)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        res = plan.out.cpu().numpy()
+        out[name] = {"ms_per_batch": ms, "problems_per_s": len(sizes) / (ms * 1e-3),
+                     "sweep_tflops_equiv": sov_f / (ms * 1e-3) / 1e12,
+                     "failed": int((plan.info.cpu().numpy() != 0).sum()), "_P": res[:, 1]}
+        del plan
+        _free()
+    ref = out["fp64"].pop("_P")
+    for name in ("fp32", "bf16"):
+        Pm = out[name].pop("_P")
+        out[name]["max_abs_dP_vs_fp64"] = float(np.max(np.abs(Pm - ref)))
+    out["config"] = (f"{len(sizes)} problems, n_p in [{int(sizes.min())}, {int(sizes.max())}], "
+                     f"sum n_p = {int(sizes.sum())}, N={bw.N} x S={bw.S}, 128 tiles")
+    return out
+
+
+def variant_grad(dev) -> dict:
+    import torch
+    import paper_2405_14892_amd as mvn
+    import workloads
+    w = workloads.make_workload("grad4096")
+    f = mvn.mvn_cholesky(w.n, locs=w.locs, kern=(w.sigma2, w.beta, w.nu, w.nugget),
+                         opts=mvn.options(tile=w.tile), device=dev)
+    st = torch.cuda.current_stream(dev)
+
+    def timed(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            r = fn()
+        e1.record(st)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps, r
+
+    ws = torch.empty(mvn.mvn_prob_workspace_bytes(w.n, w.N, w.S), dtype=torch.uint8, device=dev)
+    fwd_ms, rf = timed(lambda: mvn.mvn_prob(f, w.a, w.b, w.mu, N=w.N, S=w.S, seed=w.seed, workspace=ws))
+    grad_ms, rg = timed(lambda: mvn.mvn_prob_grad(f, w.a, w.b, w.mu, N=w.N, S=w.S, seed=w.seed))
+    out = {"forward_ms": fwd_ms, "forward_plus_adjoint_ms": grad_ms, "ratio": grad_ms / fwd_ms,
+           "logP": float(rg["logP"].item()), "abs_dlogP_vs_forward": abs(float(rg["logP"].item()) -
+                                                                       float(rf["logP"].item())),
+           "config": f"n={w.n}, N={w.N} x S={w.S}, FP64, finite limits a=mu-3, b=mu+u"}
+    del f, ws
+    _free()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="prec16k")
+    ap.add_argument("--precision", default="fp64", choices=sorted(PRECISIONS))
+    ap.add_argument("--tlr-eps", type=float, default=0.0)
+    ap.add_argument("--max-rank", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -98,84 +367,80 @@ def main() -> int:
                                    "part of this build", "n_gpus": args.gpus}))
         return 2
 
-    import numpy as np
     import torch
 
     import paper_2405_14892_amd as mvn
-    from paper_2405_14892_amd import _lib
     import workloads
 
     w = workloads.make_workload(args.workload)
     n, N, S = w.n, w.N, w.S
     dev = torch.device("cuda:0")
-    h = _lib.lib()
-    opts = mvn.options(tile=w.tile)
-    kern = _lib.MvnMatern(w.sigma2, w.beta, w.nu, w.nugget)
-    locs = torch.as_tensor(w.locs, dtype=torch.float64).to(dev).contiguous()
-    a = torch.as_tensor(w.a, dtype=torch.float64).to(dev).contiguous()
-    b = torch.as_tensor(w.b, dtype=torch.float64).to(dev).contiguous()
-    mu = torch.as_tensor(w.mu, dtype=torch.float64).to(dev).contiguous() if w.mu is not None else None
-    fb = mvn.mvn_factor_bytes(n, opts)
-    wsb = mvn.mvn_prob_workspace_bytes(n, N, S, opts)
-    fbuf = torch.empty(fb, dtype=torch.uint8, device=dev)
-    ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
-    out = torch.empty(4 + S, dtype=torch.float64, device=dev)
-    fac = _lib.MvnFactor()
-    stream = torch.cuda.current_stream(dev)
-    sp = ctypes.c_void_p(stream.cuda_stream)
-    P = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
-
-    ev = []
-
-    def step(record: bool):
-        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
-        e0.record(stream)
-        _lib.check(h.mvn_cholesky(n, None, 0, P(locs), ctypes.byref(kern), ctypes.byref(opts), P(fbuf),
-                                  fb, None, 0, ctypes.byref(fac), sp))
-        e1.record(stream)
-        _lib.check(h.mvn_prob(ctypes.byref(fac), P(a), P(b), P(mu), N, S, ctypes.c_uint64(w.seed),
-                              ctypes.byref(opts), P(ws), wsb, P(out), None, sp))
-        e2.record(stream)
-        if record:
-            ev.append((e0, e1, e2))
-
+    tlr = args.tlr_eps > 0
+    opts = (mvn.options(tile=w.tile, tlr_eps=args.tlr_eps, max_rank=args.max_rank) if tlr
+            else mvn.options(tile=w.tile, precision=PRECISIONS[args.precision]))
+    prob = Problem(w, opts, dev)
     for i in range(args.warmup):
-        step(False)
+        prob.step()
         torch.cuda.synchronize()
         print(f"# warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step(True)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    chol_ms = float(np.mean([e0.elapsed_time(e1) for e0, e1, _ in ev]))
-    sov_ms = float(np.mean([e1.elapsed_time(e2) for _, e1, e2 in ev]))
-    res = out.cpu().numpy()
-    ms = elapsed / args.steps * 1e3
-    chol_flops = n ** 3 / 3.0
-    sov_flops = float(n) * (n - 1) * N * S
-    sweep_tf = sov_flops / (sov_ms * 1e-3) / 1e12
+    r = prob.run(args.steps, 0)
+    print(f"# {args.steps} timed steps done", file=sys.stderr, flush=True)
+    del prob
+    _free()
+    ms = r["wall_ms"]
+    chol_flops, sov_flops = _flops(n, N * S)
+    sweep_tf = sov_flops / (r["sov_ms"] * 1e-3) / 1e12
+    peak = PEAK_TFLOPS["fp64" if tlr else args.precision]
+    kernel = ("tlr_sweep_kernel (TLR SOV update + conditioning)" if tlr else
+              "sweep_kernel (SOV GEMM + conditioning)")
     line = {
         "metric": METRIC,
-        "value": args.steps / elapsed,
+        "value": 1e3 / ms,
         "unit": "MVN probs/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64", "data": "synthetic",
+        "dtype": "f64" if (tlr or args.precision == "fp64") else f"{args.precision}+f64",
+        "data": "synthetic",
         "config": {"workload": f"{args.workload}: n={n} ({int(math.isqrt(n))}^2 grid), Matern nu={w.nu}, "
-                               f"beta={w.beta}, nugget={w.nugget}, N={N} x S={S} QMC, tile {w.tile}",
-                   "n": n, "N": N, "S": S, "tile": w.tile, "precision": "fp64"},
+                               f"beta={w.beta}, nugget={w.nugget}, N={N} x S={S} QMC, tile {w.tile}"
+                               + (f", TLR eps={args.tlr_eps:g}, max_rank={args.max_rank}" if tlr else ""),
+                   "n": n, "N": N, "S": S, "tile": w.tile, "precision": "fp64" if tlr else args.precision,
+                   "tlr_eps": args.tlr_eps if tlr else None},
         "effective_tflops": (chol_flops + sov_flops) / (ms * 1e-3) / 1e12,
-        "phase_ms": {"cholesky": chol_ms, "sov": sov_ms},
-        "result": {"logP": float(res[0]), "rel_stderr": float(res[3])},
-        "roofline": {"bound": "mfma", "kernel": "sweep_f64_kernel (SOV GEMM + conditioning)",
-                     "achieved": sweep_tf, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": sweep_tf / PEAK_FP64_TFLOPS, "traffic": _traffic(args.workload),
-                     "algorithmic_flops_per_launch": sov_flops},
+        "conditioning_steps_per_s": n * N * S / (r["sov_ms"] * 1e-3),
+        "phase_ms": {"cholesky": r["cholesky_ms"], "sov": r["sov_ms"]},
+        "result": {"logP": r["logP"], "P": r["P"], "rel_stderr": r["rel_stderr"], "info": r["info"]},
+        "roofline": {"bound": "mfma", "kernel": kernel, "achieved": sweep_tf, "peak": peak, "unit": "TFLOP/s",
+                     "frac": sweep_tf / peak,
+                     "traffic": None if (tlr or args.precision != "fp64") else _traffic(args.workload),
+                     "algorithmic_flops_per_launch": sov_flops,
+                     "note": "achieved = n(n-1)*N*S dense-equivalent flops / event time of the mvn_prob call"},
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = _cpu_baseline(w)
+        print("# cpu baseline done", file=sys.stderr, flush=True)
+    if not args.no_variants:
+        variants = {}
+        jobs = [("precision", lambda: variant_precision(w, dev, r)) if (args.workload == "prec16k" and
+                                                                       args.precision == "fp64" and not tlr) else None,
+                ("oracle400", lambda: variant_oracle400(dev)),
+                ("tlr64k", lambda: variant_tlr(dev)),
+                ("batch2000", lambda: variant_batch(dev)),
+                ("grad4096", lambda: variant_grad(dev))]
+        for job in jobs:
+            if job is None:
+                continue
+            name, fn = job
+            t0 = time.perf_counter()
+            try:
+                variants[name] = fn()
+            except Exception as e:  # a failed variant is reported, the line is still printed
+                variants[name] = {"error": f"{type(e).__name__}: {e}",
+                                  "trace": traceback.format_exc(limit=3)}
+            variants[name]["bench_seconds"] = time.perf_counter() - t0
+            print(f"# variant {name} done ({time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
+            _free()
+        line["variants"] = variants
     print(json.dumps(line))
     return 0
 
