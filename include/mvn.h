@@ -32,8 +32,11 @@ extern "C" {
 
 /* Arithmetic of the Cholesky trailing updates and the SOV limit-update GEMMs
  * (MFMA; FP32 accumulation for the reduced types).  The diagonal-block
- * factorisation and panel solves, the in-block recurrence, Phi / Phi^-1 /
- * log and the per-sample log-products are always FP64.
+ * factorisation and panel solves, the in-block recurrence, log and the
+ * per-sample log-products are always FP64.  Phi and Phi^-1 of the
+ * conditioning step are FP64 in MVN_FP64; in the reduced modes they run in
+ * FP32 where both conditional limits are >= -5 and the interval mass keeps
+ * at least half of Phi(b') (log d and y within a few 1e-6), FP64 elsewhere.
  *   MVN_BF16X3: operands split as x = hi + lo (both BF16) and the products
  *   hi*hi + hi*lo + lo*hi accumulated (about 16 significant bits). */
 typedef enum { MVN_FP64 = 0, MVN_FP32 = 1, MVN_BF16 = 2, MVN_BF16X3 = 3 } mvn_precision;

@@ -23,6 +23,8 @@
 #include <stdint.h>
 #include <limits.h>
 
+#include <type_traits>
+
 #include "gemm_f64.h"
 #include "launch.h"
 #include "mvn_device.h"
@@ -129,9 +131,10 @@ __device__ __forceinline__ void sweep_chunk(const SweepLds& sh, const double* __
       sh.c_lat[t] = lattice[g];
     }
     // ---- step 2: conditioning of the diagonal block
-    prod = condition_block((lds_f64*)sh.T, (lds_f64*)sh.slab, (const lds_f64*)sh.c_at,
-                           (const lds_f64*)sh.c_bt, (const lds_f64*)sh.c_rl, (const lds_u64*)sh.c_lat, L, ld,
-                           i0, rows, n, jpt, sidx, seed, periodize, valid, prod);
+    prod = condition_block<!std::is_same<G, GemmF64>::value>(
+        (lds_f64*)sh.T, (lds_f64*)sh.slab, (const lds_f64*)sh.c_at, (const lds_f64*)sh.c_bt,
+        (const lds_f64*)sh.c_rl, (const lds_u64*)sh.c_lat, L, ld, i0, rows, n, jpt, sidx, seed, periodize, valid,
+        prod);
     __syncthreads();
     // ---- step 3: y block -> scratch (in the GEMM's operand type)
     G::put_y(sh.T, Y, ld, i0, rows);

@@ -46,45 +46,39 @@ MVN_HD double log_ncdf_lower(double x) {
 }
 
 // ---------------------------------------------------------------- Phi^-1
-// AS 241 PPND16 for 0 < p <= 1/2 (returns a value <= 0).
+// AS 241 PPND16 for 0 < p <= 1/2 (returns a value <= 0).  Its three ranges
+// (|p - 1/2| <= 0.425; sqrt(-log p) <= 5; beyond) are degree-7/7 rationals
+// in a transformed variable.  Here each lane selects its variable and
+// coefficients and evaluates one rational with one division, so a wave whose
+// lanes fall in different ranges does not run every branch (the result is
+// the same, operation for operation, as evaluating the lane's own branch).
 MVN_HD double ninv_lower(double p) {
   const double q = p - 0.5;
-  if (fabs(q) <= 0.425) {
-    const double r = 0.180625 - q * q;
-    const double num = (((((((2.5090809287301226727e+3 * r + 3.3430575583588128105e+4) * r +
-                             6.7265770927008700853e+4) * r + 4.5921953931549871457e+4) * r +
-                           1.3731693765509461125e+4) * r + 1.9715909503065514427e+3) * r +
-                         1.3314166789178437745e+2) * r + 3.3871328727963666080e+0);
-    const double den = (((((((5.2264952788528545610e+3 * r + 2.8729085735721942674e+4) * r +
-                             3.9307895800092710610e+4) * r + 2.1213794301586595867e+4) * r +
-                           5.3941960214247511077e+3) * r + 6.8718700749205790830e+2) * r +
-                         4.2313330701600911252e+1) * r + 1.0);
-    return q * num / den;
-  }
-  double r = sqrt(-log(p));
-  double val;
-  if (r <= 5.0) {
-    r -= 1.6;
-    val = (((((((7.74545014278341407640e-4 * r + 2.27238449892691845833e-2) * r +
-                2.41780725177450611770e-1) * r + 1.27045825245236838258e+0) * r +
-              3.64784832476320460504e+0) * r + 5.76949722146069140550e+0) * r +
-            4.63033784615654529590e+0) * r + 1.42343711074968357734e+0) /
-          (((((((1.05075007164441684324e-9 * r + 5.47593808499534494600e-4) * r +
-                1.51986665636164571966e-2) * r + 1.48103976427480074590e-1) * r +
-              6.89767334985100004550e-1) * r + 1.67638483018380384940e+0) * r +
-            2.05319162663775882187e+0) * r + 1.0);
-  } else {
-    r -= 5.0;
-    val = (((((((2.01033439929228813265e-7 * r + 2.71155556874348757815e-5) * r +
-                1.24266094738807843860e-3) * r + 2.65321895265761230930e-2) * r +
-              2.96560571828504891230e-1) * r + 1.78482653991729133580e+0) * r +
-            5.46378491116411436990e+0) * r + 6.65790464350110377720e+0) /
-          (((((((2.04426310338993978564e-15 * r + 1.42151175831644588870e-7) * r +
-                1.84631831751005468180e-5) * r + 7.86869131145613259100e-4) * r +
-              1.48753612908506148525e-2) * r + 1.36929880922735805310e-1) * r +
-            5.99832206555887937690e-1) * r + 1.0);
-  }
-  return -val;
+  const bool central = fabs(q) <= 0.425;
+  const double rt = central ? 1.0 : sqrt(-log(p));
+  const bool near = rt <= 5.0;
+  const double x = central ? 0.180625 - q * q : (near ? rt - 1.6 : rt - 5.0);
+#define MVN_SEL(c, n, f) (central ? (c) : (near ? (n) : (f)))
+  const double n7 = MVN_SEL(2.5090809287301226727e+3, 7.74545014278341407640e-4, 2.01033439929228813265e-7);
+  const double n6 = MVN_SEL(3.3430575583588128105e+4, 2.27238449892691845833e-2, 2.71155556874348757815e-5);
+  const double n5 = MVN_SEL(6.7265770927008700853e+4, 2.41780725177450611770e-1, 1.24266094738807843860e-3);
+  const double n4 = MVN_SEL(4.5921953931549871457e+4, 1.27045825245236838258e+0, 2.65321895265761230930e-2);
+  const double n3 = MVN_SEL(1.3731693765509461125e+4, 3.64784832476320460504e+0, 2.96560571828504891230e-1);
+  const double n2 = MVN_SEL(1.9715909503065514427e+3, 5.76949722146069140550e+0, 1.78482653991729133580e+0);
+  const double n1 = MVN_SEL(1.3314166789178437745e+2, 4.63033784615654529590e+0, 5.46378491116411436990e+0);
+  const double n0 = MVN_SEL(3.3871328727963666080e+0, 1.42343711074968357734e+0, 6.65790464350110377720e+0);
+  const double d7 = MVN_SEL(5.2264952788528545610e+3, 1.05075007164441684324e-9, 2.04426310338993978564e-15);
+  const double d6 = MVN_SEL(2.8729085735721942674e+4, 5.47593808499534494600e-4, 1.42151175831644588870e-7);
+  const double d5 = MVN_SEL(3.9307895800092710610e+4, 1.51986665636164571966e-2, 1.84631831751005468180e-5);
+  const double d4 = MVN_SEL(2.1213794301586595867e+4, 1.48103976427480074590e-1, 7.86869131145613259100e-4);
+  const double d3 = MVN_SEL(5.3941960214247511077e+3, 6.89767334985100004550e-1, 1.48753612908506148525e-2);
+  const double d2 = MVN_SEL(6.8718700749205790830e+2, 1.67638483018380384940e+0, 1.36929880922735805310e-1);
+  const double d1 = MVN_SEL(4.2313330701600911252e+1, 2.05319162663775882187e+0, 5.99832206555887937690e-1);
+#undef MVN_SEL
+  const double num = (((((((n7 * x + n6) * x + n5) * x + n4) * x + n3) * x + n2) * x + n1) * x + n0);
+  const double den = (((((((d7 * x + d6) * x + d5) * x + d4) * x + d3) * x + d2) * x + d1) * x + 1.0);
+  const double r = (central ? q * num : num) / den;
+  return central ? r : -r;
 }
 
 // Phi^-1 from lp = log p, p tiny (lp < log 1e-300 allowed).  Start from the
@@ -149,7 +143,11 @@ MVN_HD Step condition_step(double alpha, double beta, double w, double cw) {
     const double qb = hi > 0.0 ? e : 1.0 - e;
     const double d = pb - pa;
     const double p = pa + u * d;
-    st.y = (p <= 0.5) ? ninv_lower(p) : -ninv_lower(qb + v * d);
+    // one Phi^-1 evaluation: the argument is chosen first, so lanes of a
+    // wave that take different sides do not run the function twice
+    const bool low = p <= 0.5;
+    const double t = ninv_lower(low ? p : qb + v * d);
+    st.y = low ? t : -t;
     st.m = d;
     st.e = 0;
   } else {
@@ -161,6 +159,63 @@ MVN_HD Step condition_step(double alpha, double beta, double w, double cw) {
     st.e = 0;
   }
   if (refl) st.y = -st.y;
+  return st;
+}
+
+// ---------------------------------------------------------------- the step, reduced precision
+// Single-precision AS 241 (PPND7, about 7 significant digits) for
+// 0 < p <= 1/2, with the same range selection as ninv_lower.
+MVN_HD float ninv_lower_f32(float p) {
+  const float q = p - 0.5f;
+  const bool central = fabsf(q) <= 0.425f;
+  const float rt = central ? 1.0f : sqrtf(-logf(p));
+  const bool near = rt <= 5.0f;
+  const float x = central ? 0.180625f - q * q : (near ? rt - 1.6f : rt - 5.0f);
+#define MVN_SEL(c, n, f) (central ? (c) : (near ? (n) : (f)))
+  const float n3 = MVN_SEL(5.9109374720e+1f, 1.7023821103e-1f, 1.7337203997e-2f);
+  const float n2 = MVN_SEL(1.5929113202e+2f, 1.3067284816e+0f, 4.2868294337e-1f);
+  const float n1 = MVN_SEL(5.0434271938e+1f, 2.7568153900e+0f, 3.0812263860e+0f);
+  const float n0 = MVN_SEL(3.3871327179e+0f, 1.4234372777e+0f, 6.6579051150e+0f);
+  const float d3 = MVN_SEL(6.7187563600e+1f, 0.0f, 0.0f);
+  const float d2 = MVN_SEL(7.8757757664e+1f, 1.2021132975e-1f, 1.2258202635e-2f);
+  const float d1 = MVN_SEL(1.7895169469e+1f, 7.3700164250e-1f, 2.4197894225e-1f);
+#undef MVN_SEL
+  const float num = ((n3 * x + n2) * x + n1) * x + n0;
+  const float den = ((d3 * x + d2) * x + d1) * x + 1.0f;
+  const float r = (central ? q * num : num) / den;
+  return central ? r : -r;
+}
+
+// The conditioning step of the reduced-precision modes: Phi and Phi^-1 in
+// FP32 where that keeps log d and y within a few 1e-6: both limits at or
+// above -5 (rounding a limit x to FP32 moves log Phi(x) by about
+// x^2 * 6e-8) and d = Phi(b') - Phi(a') at least half of Phi(b') (at most one
+// bit cancels).  Every other lane (lower tails, narrow intervals) takes the
+// FP64 step.  The factor d is returned in
+// FP64 and accumulated in log space as in the FP64 step.
+MVN_HD Step condition_step_mixed(double alpha, double beta, double w, double cw) {
+  const bool refl = alpha > 0.0;
+  const double lo = refl ? -beta : alpha;
+  const double hi = refl ? -alpha : beta;
+  bool ok = hi >= -5.0 && (lo == -INFINITY || lo >= -5.0);
+  Step st{0.0, 0.0, 0};
+  if (ok) {
+    const float his = (float)hi;
+    const float e = 0.5f * erfcf(fabsf(his) * 0.70710678f);
+    const float pb = his > 0.0f ? 1.0f - e : e;
+    const float qb = his > 0.0f ? e : 1.0f - e;
+    const float pa = (lo == -INFINITY) ? 0.0f : 0.5f * erfcf(-(float)lo * 0.70710678f);
+    const float d = pb - pa;
+    ok = d >= 0.5f * pb && d > 0.0f;
+    const float u = (float)(refl ? cw : w), v = (float)(refl ? w : cw);
+    const float p = pa + u * d;
+    const bool low = p <= 0.5f;
+    const float t = ninv_lower_f32(low ? p : qb + v * d);
+    st.y = (double)(low ? t : -t);
+    st.m = (double)d;
+    if (refl) st.y = -st.y;
+  }
+  if (!ok) st = condition_step(alpha, beta, w, cw);
   return st;
 }
 

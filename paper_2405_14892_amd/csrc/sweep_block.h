@@ -21,12 +21,14 @@ typedef __attribute__((address_space(3))) uint64_t lds_u64;
 //   s_i = S_i + sum_{k<i} L_ik y_k,  a' = (a~_i - s_i)/L_ii,
 //   b' = (b~_i - s_i)/L_ii,  (y_i, d_i) = condition_step(a', b', w_i),
 // leaving y_i in T and folding d_i into the sample's running product
-// (and, for the adjoint, s_i in s_out[(i0 + i) * 64 + lane]).  L and the
+// (and, for the adjoint, s_i in s_out[(i0 + i) * 64 + lane]).  MIXED selects
+// the reduced-precision step (FP32 central Phi / Phi^-1).  L and the
 // row indices are local to a diagonal tile starting at global row goff
 // (0 for a dense factor); goff + i0 + i is the QMC dimension of row i.
 // This file is compiled without machine loop-invariant code motion: hoisting
 // the step's ~60 polynomial constants out of the row loop would pin them in
 // registers next to the GEMM's accumulators and force spills (build.py).
+template <bool MIXED = false>
 __device__ __forceinline__ LogProd condition_block(
     lds_f64* T, lds_f64* slab, const lds_f64* c_at, const lds_f64* c_bt, const lds_f64* c_rl,
     const lds_u64* c_lat, const double* __restrict__ L, long ld, int i0, int rows, int n,
@@ -68,7 +70,8 @@ __device__ __forceinline__ LogProd condition_block(
         const double beta = (c_bt[i] - sum) * rl;
         const uint64_t g = (uint64_t)(goff + i0 + i);
         const double w = richtmyer(jpt, c_lat[i], splitmix64(seed, sidx * (uint64_t)n + g), periodize);
-        const Step st = condition_step(alpha, beta, w, 1.0 - w);
+        const Step st = MIXED ? condition_step_mixed(alpha, beta, w, 1.0 - w)
+                              : condition_step(alpha, beta, w, 1.0 - w);
         T[i * kCols + lane] = valid ? st.y : 0.0;
         logprod_mul(prod, st);
       }

@@ -34,6 +34,14 @@ int main() {
       scanf("%lf %lf %lf", &x, &y, &w);
       mvn::StepLog s = mvn::condition(x, y, w, 1.0 - w);
       printf("%.17g %.17g\n", s.y, s.logd);
+    } else if (!strcmp(op, "condmix")) {
+      scanf("%lf %lf %lf", &x, &y, &w);
+      mvn::Step s = mvn::condition_step_mixed(x, y, w, 1.0 - w);
+      const double ld = s.m > 0.0 ? std::log(s.m) + (double)s.e * mvn::kLn2 : -INFINITY;
+      printf("%.17g %.17g\n", s.y, ld);
+    } else if (!strcmp(op, "ninv32")) {
+      scanf("%lf", &x);
+      printf("%.17g\n", (double)mvn::ninv_lower_f32((float)x));
     } else if (!strcmp(op, "sm")) {
       unsigned long long seed, k;
       scanf("%llu %llu", &seed, &k);

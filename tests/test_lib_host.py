@@ -152,3 +152,34 @@ def test_tlr_size_queries_and_option_checks():
                             ctypes.c_void_p(8), None, 10, 1, 1, ctypes.byref(opts), None, 0, None, 0, None,
                             None, None)
     assert code == -13 and b"dense" in h.mvn_last_error()
+
+
+def test_fp32_inverse_normal_within_single_precision(harness):
+    """PPND7 in FP32 (the reduced-precision modes' central Phi^-1) against
+    SciPy: absolute error below 3e-7 (1 + |y|) from p = 1e-33 to 1/2."""
+    ps = np.concatenate([np.logspace(-33, -1, 2000), np.linspace(0.01, 0.5, 1000)])
+    got = np.array([float(v) for v in _run(harness, [f"ninv32 {float(p)!r}" for p in ps])])
+    ref = sp.ndtri(ps.astype(np.float32).astype(np.float64))
+    assert np.max(np.abs(got - ref) / (1 + np.abs(ref))) < 3e-7
+
+
+def test_mixed_conditioning_step_close_to_oracle(harness):
+    """The reduced-precision step (FP32 central Phi / Phi^-1, FP64 tails)
+    against the oracle's FP64 step: y within 1e-5 (1 + |y|), log d within
+    1e-5, on the same inputs as the FP64 check (wide, narrow, deep and
+    one-sided intervals)."""
+    from oracle import sov
+    rng = np.random.default_rng(0)
+    al = np.concatenate([rng.normal(0, 3, 1500), rng.uniform(-60, 60, 500), [-np.inf] * 100])
+    be = al + np.abs(rng.normal(0, 3, al.size))
+    be[:150] = np.inf
+    be[np.isinf(al)] = rng.normal(0, 10, 100)
+    w = rng.uniform(size=al.size)
+    res = _run(harness, [f"condmix {float(a)!r} {float(b)!r} {float(x)!r}" for a, b, x in zip(al, be, w)])
+    gy = np.array([float(r.split()[0]) for r in res])
+    gl = np.array([float(r.split()[1]) for r in res])
+    oy, ol = sov.condition(al, be, w)
+    assert np.max(np.abs(gy - oy) / (1 + np.abs(oy))) < 1e-5
+    fin = np.isfinite(ol)
+    assert np.array_equal(fin, np.isfinite(gl))
+    assert np.max(np.abs(gl[fin] - ol[fin])) < 1e-5
