@@ -14,7 +14,10 @@ after a warm-up, outside the timed region):
               on identical QMC points
   tlr64k      the 65536-site problem: dense FP64 vs tile low-rank at 1e-5 and
               1e-7 (ranks, times, log P difference)
+  autotune    the autotuner's choice of Cholesky tile and sweep block rows
+              for the timed workload, with every candidate's time
   batch2000   2000 confidence-region problems of uneven size in one call
+              (sweep block rows chosen by the autotuner)
   grad4096    forward + adjoint sweep for d log P / d(a, b, mu)
 
     python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--no-cpu-baseline] [--no-variants]
@@ -264,9 +267,12 @@ def variant_tlr(dev) -> dict:
 
 
 def variant_batch(dev) -> dict:
+    """The 2000-problem batch: the autotuner picks the sweep block rows per
+    precision (both shapes timed), then the tuned configuration is timed."""
     import numpy as np
     import torch
     import paper_2405_14892_amd as mvn
+    from paper_2405_14892_amd import autotune
     import workloads
     bw = workloads.make_batch()
     sizes = bw.n_p.astype(np.int32)
@@ -278,7 +284,11 @@ def variant_batch(dev) -> dict:
     sov_f = float(np.sum(bw.n_p.astype(np.float64) * (bw.n_p - 1))) * NS
     out = {}
     for name in ("fp32", "bf16", "fp64"):
-        plan = mvn.mvn_batch_plan(sizes, bw.N, bw.S, mvn.options(tile=128, precision=PRECISIONS[name]), device=dev)
+        tuned = autotune.tune_batch(sizes, idx, locs, kern, a, b, N=bw.N, S=bw.S, seed=bw.seed,
+                                    precision=PRECISIONS[name], device=dev)
+        rows = tuned["sweep_rows"]
+        plan = mvn.mvn_batch_plan(sizes, bw.N, bw.S, mvn.options(tile=128, precision=PRECISIONS[name],
+                                                                 sweep_rows=rows), device=dev)
         mvn.mvn_prob_batch(plan, idx, locs, kern, a, b, None, seed=bw.seed)
         torch.cuda.synchronize()
         st = torch.cuda.current_stream(dev)
@@ -292,7 +302,9 @@ def variant_batch(dev) -> dict:
         ms = e0.elapsed_time(e1) / reps
         res = plan.out.cpu().numpy()
         out[name] = {"ms_per_batch": ms, "problems_per_s": len(sizes) / (ms * 1e-3),
+                     "sweep_rows": rows, "autotune_s_by_rows": tuned["batch_s"],
                      "sweep_tflops_equiv": sov_f / (ms * 1e-3) / 1e12,
+                     "conditioning_steps_per_s": float(sizes.sum()) * NS / (ms * 1e-3),
                      "failed": int((plan.info.cpu().numpy() != 0).sum()), "_P": res[:, 1]}
         del plan
         _free()
@@ -301,8 +313,20 @@ def variant_batch(dev) -> dict:
         Pm = out[name].pop("_P")
         out[name]["max_abs_dP_vs_fp64"] = float(np.max(np.abs(Pm - ref)))
     out["config"] = (f"{len(sizes)} problems, n_p in [{int(sizes.min())}, {int(sizes.max())}], "
-                     f"sum n_p = {int(sizes.sum())}, N={bw.N} x S={bw.S}, 128 tiles")
+                     f"sum n_p = {int(sizes.sum())}, N={bw.N} x S={bw.S}, 128-wide Cholesky steps; "
+                     "sweep block rows chosen by the autotuner")
     return out
+
+
+def variant_autotune_dense(w, dev) -> dict:
+    """The autotuner on the timed workload itself: Cholesky tile and sweep
+    block rows, every candidate timed once."""
+    from paper_2405_14892_amd import autotune
+    kern = (w.sigma2, w.beta, w.nu, w.nugget)
+    res = autotune.tune_dense(w.n, w.locs, kern, w.a, w.b, w.mu, N=w.N, S=w.S, seed=w.seed,
+                              tiles=(256, 512, 1024), device=dev)
+    res.pop("key", None)
+    return res
 
 
 def variant_grad(dev) -> dict:
@@ -423,6 +447,7 @@ def main() -> int:
         variants = {}
         jobs = [("precision", lambda: variant_precision(w, dev, r)) if (args.workload == "prec16k" and
                                                                        args.precision == "fp64" and not tlr) else None,
+                ("autotune", lambda: variant_autotune_dense(w, dev)) if not tlr else None,
                 ("oracle400", lambda: variant_oracle400(dev)),
                 ("tlr64k", lambda: variant_tlr(dev)),
                 ("batch2000", lambda: variant_batch(dev)),

@@ -22,7 +22,7 @@ class MvnMatern(ctypes.Structure):
 
 
 class MvnOptions(ctypes.Structure):
-    _fields_ = [("tile", c_int), ("precision", c_int), ("periodize", c_int), ("reserved0", c_int),
+    _fields_ = [("tile", c_int), ("precision", c_int), ("periodize", c_int), ("sweep_rows", c_int),
                 ("tlr_eps", c_double), ("max_rank", c_int), ("reserved1", c_int)]
 
 
@@ -89,5 +89,5 @@ def check(code: int) -> None:
 
 
 def options(tile: int = 256, precision: int = MVN_FP64, periodize: bool = False,
-            tlr_eps: float = 0.0, max_rank: int = 0) -> MvnOptions:
-    return MvnOptions(tile, precision, 1 if periodize else 0, 0, tlr_eps, max_rank, 0)
+            tlr_eps: float = 0.0, max_rank: int = 0, sweep_rows: int = 0) -> MvnOptions:
+    return MvnOptions(tile, precision, 1 if periodize else 0, sweep_rows, tlr_eps, max_rank, 0)

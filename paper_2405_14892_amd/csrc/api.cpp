@@ -33,7 +33,12 @@ int hip_fail(hipError_t e, const char* where) {
 }
 
 constexpr size_t kAlign = 256;
-constexpr int kMaxGrid = 512;  // persistent sweep workgroups (two per CU on MI355X)
+constexpr int kCUs = 256;      // compute units of an MI355X: the persistent grids are sized for it
+
+// Rows per sweep block: 0 selects the default (128).
+int sweep_rows(const mvn_options* o) { return (!o || o->sweep_rows == 0) ? 128 : o->sweep_rows; }
+bool sweep_rows_ok(const mvn_options* o) { return !o || o->sweep_rows == 0 || o->sweep_rows == 64 || o->sweep_rows == 128; }
+int max_grid(int rows) { return kCUs * mvn::sweep_wg_per_cu(rows); }
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 int padded(int n) { return (n + 127) / 128 * 128; }
@@ -110,12 +115,13 @@ struct ProbLayout {
 
 // Workspace of one probability call.  ld is the factor's leading dimension
 // (rows of the Y scratch); zslice > 0 adds the TLR Z scratch (FP64).
-ProbLayout prob_layout_ld(int ld, int N, int S, int prec, long zslice) {
+ProbLayout prob_layout_ld(int ld, int N, int S, int prec, long zslice, int rows) {
   ProbLayout L{};
   L.ld = ld;
   const long NS = (long)N * S;
   const long chunks = (NS + mvn::sweep_tile_cols() - 1) / mvn::sweep_tile_cols();
-  L.grid = (int)(chunks < kMaxGrid ? chunks : kMaxGrid);
+  const int gmax = max_grid(rows);
+  L.grid = (int)(chunks < gmax ? chunks : gmax);
   L.yslice = mvn::sweep_yslice(prec, L.ld);
   L.zslice = zslice;
   size_t off = 0;
@@ -133,7 +139,9 @@ ProbLayout prob_layout_ld(int ld, int N, int S, int prec, long zslice) {
   return L;
 }
 
-ProbLayout prob_layout(int n, int N, int S, int prec) { return prob_layout_ld(padded(n), N, S, prec, 0); }
+ProbLayout prob_layout(int n, int N, int S, int prec, int rows) {
+  return prob_layout_ld(padded(n), N, S, prec, 0, rows);
+}
 
 // ---------------------------------------------------------------- tile low rank
 // Factor buffer of a TLR factor: tiles | info | U | Vt (+128 rows) | ranks.
@@ -193,7 +201,7 @@ GradLayout grad_layout(int n, int N, int S) {
   L.ld = padded(n);
   const long NS = (long)N * S;
   L.nchunks = (NS + mvn::sweep_tile_cols() - 1) / mvn::sweep_tile_cols();
-  L.grid = (int)(L.nchunks < kMaxGrid ? L.nchunks : kMaxGrid);
+  L.grid = (int)(L.nchunks < max_grid(128) ? L.nchunks : max_grid(128));
   const size_t slice = sizeof(double) * (size_t)L.ld * mvn::sweep_tile_cols();
   size_t off = 0;
   L.at = off; off = align_up(off + sizeof(double) * L.ld);
@@ -264,12 +272,13 @@ struct BatchWs {
   long items;
 };
 
-BatchWs batch_ws(const BatchPlan& P, int count, int N, int S, int prec) {
+BatchWs batch_ws(const BatchPlan& P, int count, int N, int S, int prec, int rows) {
   BatchWs W{};
   const long NS = (long)N * S;
   const long chunks = (NS + mvn::sweep_tile_cols() - 1) / mvn::sweep_tile_cols();
   W.items = chunks * count;
-  W.grid = (int)(W.items < kMaxGrid ? W.items : kMaxGrid);
+  const int gmax = max_grid(rows);
+  W.grid = (int)(W.items < gmax ? W.items : gmax);
   size_t off = 0;
   W.at = off; off = align_up(off + sizeof(double) * (size_t)P.sum_n);
   W.bt = off; off = align_up(off + sizeof(double) * (size_t)P.sum_n);
@@ -328,10 +337,11 @@ int mvn_prob_workspace_bytes(int n, int N, int S, const mvn_options* opts, size_
   if (is_tlr(opts)) {
     if (tlr_opts_check(opts)) return -4;
     const TlrGeom G = tlr_geom(n, opts->tile, opts->max_rank);
-    *bytes = prob_layout_ld(G.ld, N, S, MVN_FP64, tlr_zslice(G)).total;
+    *bytes = prob_layout_ld(G.ld, N, S, MVN_FP64, tlr_zslice(G), 128).total;
     return 0;
   }
-  *bytes = prob_layout(n, N, S, prec).total;
+  if (!sweep_rows_ok(opts)) return fail(-4, "sweep_rows must be 0, 64 or 128 (got %d)", opts->sweep_rows);
+  *bytes = prob_layout(n, N, S, prec, sweep_rows(opts)).total;
   return 0;
 }
 
@@ -467,7 +477,7 @@ int mvn_prob(const mvn_factor* f, const double* d_a, const double* d_b, const do
     if (prec != MVN_FP64) return fail(-8, "the TLR sweep is FP64");
     const int n = f->n, m = f->tile, nt = f->ld / f->tile, rs = f->rank_stride;
     const long zs = (long)(nt > 1 ? nt - 1 : 1) * rs * mvn::sweep_tile_cols();
-    const ProbLayout Lay = prob_layout_ld(f->ld, N, S, MVN_FP64, zs);
+    const ProbLayout Lay = prob_layout_ld(f->ld, N, S, MVN_FP64, zs, 128);
     if (!ws) return fail(-9, "workspace is NULL");
     if (ws_bytes < Lay.total) return fail(-10, "workspace too small: %zu < %zu", ws_bytes, Lay.total);
     if (!d_out) return fail(-11, "output is NULL");
@@ -514,8 +524,10 @@ int mvn_prob(const mvn_factor* f, const double* d_a, const double* d_b, const do
   }
   if (prec != MVN_FP64 && (prec != f->precision || !f->L_low))
     return fail(-8, "the factor holds no operand copy for precision %d (built with %d)", prec, f->precision);
+  if (!sweep_rows_ok(opts)) return fail(-8, "sweep_rows must be 0, 64 or 128 (got %d)", opts->sweep_rows);
   const int n = f->n;
-  const ProbLayout Lay = prob_layout(n, N, S, prec);
+  const int rows = sweep_rows(opts);
+  const ProbLayout Lay = prob_layout(n, N, S, prec, rows);
   if (!ws) return fail(-9, "workspace is NULL");
   if (ws_bytes < Lay.total) return fail(-10, "workspace too small: %zu < %zu", ws_bytes, Lay.total);
   if (!d_out) return fail(-11, "output is NULL");
@@ -550,6 +562,7 @@ int mvn_prob(const mvn_factor* f, const double* d_a, const double* d_b, const do
   sa.yscr = yscr;
   sa.ell = ell;
   sa.grid = Lay.grid;
+  sa.rows = rows;
   e = mvn::launch_sweep(sa, stream);
   if (e != hipSuccess) return hip_fail(e, "sweep");
   e = mvn::launch_reduce(ell, N, S, part, f->info, bad, d_out, stream);
@@ -634,8 +647,9 @@ int mvn_batch_plan(int count, const int* n_p, int N, int S, const mvn_options* o
     memcpy(plan, P.desc.data(), sizeof(mvn::BatchDesc) * count);
     memcpy((char*)plan + align_up(sizeof(mvn::BatchDesc) * (size_t)count), P.order.data(), sizeof(int) * count);
   }
+  if (!sweep_rows_ok(opts)) return fail(-5, "sweep_rows must be 0, 64 or 128 (got %d)", opts->sweep_rows);
   if (factor_bytes) *factor_bytes = batch_factor_bytes(P, prec);
-  if (ws_bytes) *ws_bytes = batch_ws(P, count, N, S, prec).total;
+  if (ws_bytes) *ws_bytes = batch_ws(P, count, N, S, prec, sweep_rows(opts)).total;
   return 0;
 }
 
@@ -663,7 +677,8 @@ int mvn_prob_batch(int count, const int* n_p, const void* d_plan, const int64_t*
   if (!batch_plan_host(count, n_p, P)) return fail(-2, "every problem needs n >= 1");
   if (!factor_buf) return fail(-14, "factor buffer is NULL");
   if (factor_bytes < batch_factor_bytes(P, prec)) return fail(-15, "factor buffer too small");
-  const BatchWs W = batch_ws(P, count, N, S, prec);
+  if (!sweep_rows_ok(opts)) return fail(-13, "sweep_rows must be 0, 64 or 128 (got %d)", opts->sweep_rows);
+  const BatchWs W = batch_ws(P, count, N, S, prec, sweep_rows(opts));
   if (!ws) return fail(-16, "workspace is NULL");
   if (ws_bytes < W.total) return fail(-17, "workspace too small: %zu < %zu", ws_bytes, W.total);
   if (!d_out) return fail(-18, "output is NULL");
@@ -712,6 +727,7 @@ int mvn_prob_batch(int count, const int* n_p, const void* d_plan, const int64_t*
   a.total_items = W.items;
   a.lplane = P.factor_elems;
   a.grid = W.grid;
+  a.rows = sweep_rows(opts);
   e = mvn::launch_batch_sweep(a, stream);
   if (e != hipSuccess) return hip_fail(e, "batch sweep");
   e = mvn::launch_batch_reduce(ell, count, N, S, part, d_info, bad, d_out, stream);

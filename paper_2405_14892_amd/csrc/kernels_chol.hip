@@ -302,8 +302,8 @@ struct SyrkStage<GemmF32> {
 };
 
 template <int SPLIT>
-struct SyrkStage<GemmBF16T<SPLIT>> {
-  using G = GemmBF16T<SPLIT>;
+struct SyrkStage<GemmBF16T<SPLIT, 128>> {
+  using G = GemmBF16T<SPLIT, 128>;
   static constexpr int kAH = G::kK / 2, kBQ = G::kK / 4;
   struct Regs { double a[kAH]; double b[kBQ]; };
   static __device__ __forceinline__ void load(const double* A, long ld, long ra0, long rb0, long k0,

@@ -73,7 +73,7 @@ int sweep_tile_cols() { return kCols; }
 
 // Shared memory of one sweep workgroup.
 struct SweepLds {
-  double* T;         // 128 x 64 block (also the double-buffered GEMM stages)
+  double* T;         // RB x 64 block (also the double-buffered GEMM stages)
   double* slab;
   double* c_at;
   double* c_bt;
@@ -81,7 +81,7 @@ struct SweepLds {
   uint64_t* c_lat;
 };
 
-// The whole sweep of one 64-column chunk of one problem: for every 128-row
+// The whole sweep of one 64-column chunk of one problem: for every RB-row
 // block, the GEMM (step 1), the conditioning (step 2) and the y write-back
 // (step 3).  Writes l of the chunk's valid samples to ell[col].
 template <class G>
@@ -91,6 +91,7 @@ __device__ __forceinline__ void sweep_chunk(const SweepLds& sh, const double* __
                                             const uint64_t* __restrict__ lattice, uint64_t seed, int N, int S,
                                             int periodize, typename G::E* __restrict__ Y,
                                             double* __restrict__ ell, long chunk) {
+  constexpr int RB = G::kRows;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const long NS = (long)N * S;
   char* stage0 = (char*)sh.T;
@@ -102,11 +103,11 @@ __device__ __forceinline__ void sweep_chunk(const SweepLds& sh, const double* __
   const uint64_t jpt = valid ? (uint64_t)(col % N) + 1 : 1;
   LogProd prod{1.0, 0};
 
-  for (int i0 = 0; i0 < n; i0 += kTile) {
-    const int rows = min(kTile, n - i0);
+  for (int i0 = 0; i0 < n; i0 += RB) {
+    const int rows = min(RB, n - i0);
     typename G::Acc acc;
     G::zero(acc);
-    // ---- step 1: S = L[i0:i0+128, 0:i0] Y[0:i0, :]
+    // ---- step 1: S = L[i0:i0+RB, 0:i0] Y[0:i0, :]
     if (i0 > 0) {
       const int nst = i0 / G::kK;
       typename G::Regs r;
@@ -131,7 +132,7 @@ __device__ __forceinline__ void sweep_chunk(const SweepLds& sh, const double* __
       sh.c_lat[t] = lattice[g];
     }
     // ---- step 2: conditioning of the diagonal block
-    prod = condition_block<!std::is_same<G, GemmF64>::value>(
+    prod = condition_block<!std::is_same<typename G::E, double>::value, RB>(
         (lds_f64*)sh.T, (lds_f64*)sh.slab, (const lds_f64*)sh.c_at, (const lds_f64*)sh.c_bt,
         (const lds_f64*)sh.c_rl, (const lds_u64*)sh.c_lat, L, ld, i0, rows, n, jpt, sidx, seed, periodize, valid,
         prod);
@@ -143,18 +144,30 @@ __device__ __forceinline__ void sweep_chunk(const SweepLds& sh, const double* __
   if (valid) ell[col] = logprod_log(prod);
 }
 
-#define MVN_SWEEP_LDS                                                     \
-  __shared__ __attribute__((aligned(16))) double lds_T[kTile * kCols];    \
-  __shared__ double lds_slab[kSlab * kTile];                              \
-  __shared__ double lds_at[kTile], lds_bt[kTile], lds_rl[kTile];          \
-  __shared__ uint64_t lds_lat[kTile];                                     \
+// LDS of one workgroup for policy G: the block buffer holds RB x 64 FP64 or
+// the two GEMM stages, whichever is larger.
+template <class G>
+struct SweepLdsSize {
+  static constexpr int kT = G::kRows * kCols > G::kStageBytes / 4 ? G::kRows * kCols : G::kStageBytes / 4;
+};
+
+#define MVN_SWEEP_LDS(G)                                                              \
+  __shared__ __attribute__((aligned(16))) double lds_T[SweepLdsSize<G>::kT];          \
+  __shared__ double lds_slab[kSlab * G::kRows];                                       \
+  __shared__ double lds_at[G::kRows], lds_bt[G::kRows], lds_rl[G::kRows];             \
+  __shared__ uint64_t lds_lat[G::kRows];                                              \
   const SweepLds sh{lds_T, lds_slab, lds_at, lds_bt, lds_rl, lds_lat}
 
+// Two workgroups per CU for the 128-row shape, three for the 64-row shape.
 template <class G>
-__global__ __launch_bounds__(256, 2) void sweep_kernel(SweepArgs p) {
+struct SweepOccupancy {
+  static constexpr int kWG = G::kRows == 128 ? 2 : 3;
+};
+
+template <class G>
+__global__ __launch_bounds__(256, SweepOccupancy<G>::kWG) void sweep_kernel(SweepArgs p) {
   using E = typename G::E;
-  static_assert(2 * G::kStageBytes <= kTile * kCols * 8, "GEMM stages must fit in the block buffer");
-  MVN_SWEEP_LDS;
+  MVN_SWEEP_LDS(G);
   const long nchunks = ((long)p.N * p.S + kCols - 1) / kCols;
   E* Y = (E*)p.yscr + (long)blockIdx.x * p.yslice;
   for (long chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x)
@@ -166,9 +179,9 @@ __global__ __launch_bounds__(256, 2) void sweep_kernel(SweepArgs p) {
 // size, pulled from a device counter; every workgroup leaves when the
 // counter passes the number of items.
 template <class G>
-__global__ __launch_bounds__(256, 2) void batch_sweep_kernel(BatchSweepArgs p) {
+__global__ __launch_bounds__(256, SweepOccupancy<G>::kWG) void batch_sweep_kernel(BatchSweepArgs p) {
   using E = typename G::E;
-  MVN_SWEEP_LDS;
+  MVN_SWEEP_LDS(G);
   __shared__ long s_item;
   const long nchunks = ((long)p.N * p.S + kCols - 1) / kCols;
   const long NS = (long)p.N * p.S;
@@ -188,6 +201,8 @@ __global__ __launch_bounds__(256, 2) void batch_sweep_kernel(BatchSweepArgs p) {
   }
 }
 
+int sweep_wg_per_cu(int rows) { return rows == 64 ? 3 : 2; }
+
 long sweep_yslice(int prec, int ld) {
   // elements per workgroup slice of the Y scratch, and bytes per element
   return (long)ld * kCols * (prec == 3 ? 2 : 1);
@@ -196,12 +211,23 @@ long sweep_yslice(int prec, int ld) {
 int sweep_elem_bytes(int prec) { return prec == 0 ? 8 : prec == 1 ? 4 : 2; }
 
 hipError_t launch_sweep(const SweepArgs& a, hipStream_t st) {
-  switch (a.prec) {
-    case 0: hipLaunchKernelGGL(sweep_kernel<GemmF64>, dim3(a.grid), dim3(256), 0, st, a); break;
-    case 1: hipLaunchKernelGGL(sweep_kernel<GemmF32>, dim3(a.grid), dim3(256), 0, st, a); break;
-    case 2: hipLaunchKernelGGL(sweep_kernel<GemmBF16>, dim3(a.grid), dim3(256), 0, st, a); break;
-    case 3: hipLaunchKernelGGL(sweep_kernel<GemmBF16x3>, dim3(a.grid), dim3(256), 0, st, a); break;
-    default: return hipErrorInvalidValue;
+  const dim3 g(a.grid), b(256);
+  if (a.rows == 64) {
+    switch (a.prec) {
+      case 0: hipLaunchKernelGGL(sweep_kernel<GemmF64T<64>>, g, b, 0, st, a); break;
+      case 1: hipLaunchKernelGGL(sweep_kernel<GemmF32T<64>>, g, b, 0, st, a); break;
+      case 2: hipLaunchKernelGGL((sweep_kernel<GemmBF16T<1, 64>>), g, b, 0, st, a); break;
+      case 3: hipLaunchKernelGGL((sweep_kernel<GemmBF16T<2, 64>>), g, b, 0, st, a); break;
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    switch (a.prec) {
+      case 0: hipLaunchKernelGGL(sweep_kernel<GemmF64>, g, b, 0, st, a); break;
+      case 1: hipLaunchKernelGGL(sweep_kernel<GemmF32>, g, b, 0, st, a); break;
+      case 2: hipLaunchKernelGGL(sweep_kernel<GemmBF16>, g, b, 0, st, a); break;
+      case 3: hipLaunchKernelGGL(sweep_kernel<GemmBF16x3>, g, b, 0, st, a); break;
+      default: return hipErrorInvalidValue;
+    }
   }
   return hipGetLastError();
 }
@@ -333,12 +359,23 @@ hipError_t launch_batch_setup(const BatchDesc* desc, int count, int nmax, const 
 }
 
 hipError_t launch_batch_sweep(const BatchSweepArgs& a, hipStream_t st) {
-  switch (a.prec) {
-    case 0: hipLaunchKernelGGL(batch_sweep_kernel<GemmF64>, dim3(a.grid), dim3(256), 0, st, a); break;
-    case 1: hipLaunchKernelGGL(batch_sweep_kernel<GemmF32>, dim3(a.grid), dim3(256), 0, st, a); break;
-    case 2: hipLaunchKernelGGL(batch_sweep_kernel<GemmBF16>, dim3(a.grid), dim3(256), 0, st, a); break;
-    case 3: hipLaunchKernelGGL(batch_sweep_kernel<GemmBF16x3>, dim3(a.grid), dim3(256), 0, st, a); break;
-    default: return hipErrorInvalidValue;
+  const dim3 g(a.grid), b(256);
+  if (a.rows == 64) {
+    switch (a.prec) {
+      case 0: hipLaunchKernelGGL(batch_sweep_kernel<GemmF64T<64>>, g, b, 0, st, a); break;
+      case 1: hipLaunchKernelGGL(batch_sweep_kernel<GemmF32T<64>>, g, b, 0, st, a); break;
+      case 2: hipLaunchKernelGGL((batch_sweep_kernel<GemmBF16T<1, 64>>), g, b, 0, st, a); break;
+      case 3: hipLaunchKernelGGL((batch_sweep_kernel<GemmBF16T<2, 64>>), g, b, 0, st, a); break;
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    switch (a.prec) {
+      case 0: hipLaunchKernelGGL(batch_sweep_kernel<GemmF64>, g, b, 0, st, a); break;
+      case 1: hipLaunchKernelGGL(batch_sweep_kernel<GemmF32>, g, b, 0, st, a); break;
+      case 2: hipLaunchKernelGGL(batch_sweep_kernel<GemmBF16>, g, b, 0, st, a); break;
+      case 3: hipLaunchKernelGGL(batch_sweep_kernel<GemmBF16x3>, g, b, 0, st, a); break;
+      default: return hipErrorInvalidValue;
+    }
   }
   return hipGetLastError();
 }

@@ -37,6 +37,7 @@ struct SweepArgs {
   long yslice;
   double* ell;             // N*S per-sample log-products
   int grid;                // persistent workgroups
+  int rows;                // rows per sweep block: 128 (two workgroups per CU) or 64 (three)
 };
 
 // Setup of one probability call: centred limits and the invalid-limit flag.
@@ -75,6 +76,8 @@ hipError_t launch_reduce(const double* ell, int N, int S, double* part, const in
                          const int* bad_limits, double* out, hipStream_t st);
 
 int sweep_tile_cols();
+// Workgroups of the sweep that share one CU for a block-row count (128 or 64).
+int sweep_wg_per_cu(int rows);
 
 // ---------------------------------------------------------------- batches
 // Per-problem descriptor of a batch (written by the host plan, read on the
@@ -120,6 +123,7 @@ struct BatchSweepArgs {
   long total_items;        // count x chunks per problem
   long lplane;             // element distance of the BF16 hi and lo planes of the packed low copy
   int grid;
+  int rows;                // rows per sweep block (128 or 64)
 };
 
 hipError_t launch_batch_setup(const BatchDesc* desc, int count, int nmax, const double* a, const double* b,

@@ -22,13 +22,14 @@ typedef __attribute__((address_space(3))) uint64_t lds_u64;
 //   b' = (b~_i - s_i)/L_ii,  (y_i, d_i) = condition_step(a', b', w_i),
 // leaving y_i in T and folding d_i into the sample's running product
 // (and, for the adjoint, s_i in s_out[(i0 + i) * 64 + lane]).  MIXED selects
-// the reduced-precision step (FP32 central Phi / Phi^-1).  L and the
+// the reduced-precision step (FP32 central Phi / Phi^-1); SL is the slab row
+// stride (the block's row count, rows <= SL).  L and the
 // row indices are local to a diagonal tile starting at global row goff
 // (0 for a dense factor); goff + i0 + i is the QMC dimension of row i.
 // This file is compiled without machine loop-invariant code motion: hoisting
 // the step's ~60 polynomial constants out of the row loop would pin them in
 // registers next to the GEMM's accumulators and force spills (build.py).
-template <bool MIXED = false>
+template <bool MIXED = false, int SL = kTile>
 __device__ __forceinline__ LogProd condition_block(
     lds_f64* T, lds_f64* slab, const lds_f64* c_at, const lds_f64* c_bt, const lds_f64* c_rl,
     const lds_u64* c_lat, const double* __restrict__ L, long ld, int i0, int rows, int n,
@@ -38,8 +39,8 @@ __device__ __forceinline__ LogProd condition_block(
   const bool owner = (t >> 6) == 0;
   for (int q = 0; q < rows; q += kSlab) {
     __syncthreads();
-    for (int e = t; e < kSlab * kTile; e += 256) {
-      const int ii = e / kTile, k = e % kTile;
+    for (int e = t; e < kSlab * SL; e += 256) {
+      const int ii = e / SL, k = e % SL;
       slab[e] = (q + ii < rows && k < q + ii) ? L[(long)(i0 + q + ii) * ld + i0 + k] : 0.0;
     }
     __syncthreads();
@@ -49,7 +50,7 @@ __device__ __forceinline__ LogProd condition_block(
         // the slab row is zero from column i on, so the sum runs to a
         // multiple of 8 with four independent partial sums (the LDS reads
         // then pipeline)
-        const lds_f64* Li = slab + (i - q) * kTile;
+        const lds_f64* Li = slab + (i - q) * SL;
         const lds_f64* Tk = T + lane;
         double s0 = T[i * kCols + lane], s1 = 0.0, s2 = 0.0, s3 = 0.0;
         const int kend = (i + 7) & ~7;

@@ -3,10 +3,13 @@
 // element type of the factor copy and of the Y scratch, the stage loaders,
 // the MFMA step, and the mapping of its accumulators onto the 128 x 64 block.
 //
-// Tile: 128 block rows x 64 sample columns per workgroup of four wave64s;
-// wave w owns rows [32 w, 32 w + 32) x all 64 columns = 2 x 4 MFMA blocks of
-// 16 x 16.  K advances in LDS stages, double-buffered; the next stage's global
-// loads are in flight while the current stage's MFMAs run.
+// Tile: RB block rows (128 or 64) x 64 sample columns per workgroup of four
+// wave64s; wave w owns rows [w RB/4, (w+1) RB/4) x all 64 columns = RB/64 x 4
+// MFMA blocks of 16 x 16.  K advances in LDS stages, double-buffered; the
+// next stage's global loads are in flight while the current stage's MFMAs
+// run.  The 64-row shape needs about 47 KB of LDS, so three workgroups (three
+// conditioning waves) share a CU instead of two; the 128-row shape reads the
+// sample block Y half as often.
 //
 //   GemmF64   v_mfma_f64_16x16x4_f64, FP64 operands; stage 16 deep
 //   GemmF32   v_mfma_f32_16x16x4_f32, FP32 operands, FP32 accumulation;
@@ -35,25 +38,38 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 __device__ __forceinline__ __bf16 to_bf16(double x) { return (__bf16)(float)x; }
 
 // ---------------------------------------------------------------- FP64
-struct GemmF64 {
+template <int RB>
+struct GemmF64T {
   using E = double;
+  static constexpr int kRows = RB;
+  static constexpr int kRW = RB / 4;      // rows per wave
+  static constexpr int kIB = kRW / 16;    // 16-row MFMA blocks per wave
   static constexpr int kK = 16;
-  static constexpr int kALd = 128 + 1, kBLd = 64 + 1;
+  static constexpr int kEA = RB * kK / 256;  // A elements per lane per stage
+  static constexpr int kALd = RB + 1, kBLd = 64 + 1;
   static constexpr int kAStage = kK * kALd, kBStage = kK * kBLd;  // elements
   static constexpr int kStageBytes = (kAStage + kBStage) * 8;
-  struct Acc { f64x4 v[2][4]; };
-  struct Regs { double a[8]; double b[4]; };
+  struct Acc { f64x4 v[kIB][4]; };
+  struct Regs { double a[kEA]; double b[4]; };
   static __device__ __forceinline__ void zero(Acc& acc) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < kIB; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j) acc.v[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
   }
-  // L: row-major [ld][ld]; Y: [ld][64]
+  // L: row-major [ld][ld]; Y: [ld][64].  Lane t loads kEA consecutive k of
+  // row t / (kK / kEA).
   static __device__ __forceinline__ void load(const E* __restrict__ L, long ld, long, long i0, long k0,
                                               const E* __restrict__ Y, long, Regs& r) {
-    load_rows<false>(L, ld, i0, k0, 0, 0, r.a);
     const int t = threadIdx.x;
+    constexpr int tpr = kK / kEA;
+    const double2* pa = reinterpret_cast<const double2*>(L + (i0 + t / tpr) * ld + k0 + (t % tpr) * kEA);
+#pragma unroll
+    for (int q = 0; q < kEA / 2; ++q) {
+      const double2 v = pa[q];
+      r.a[2 * q] = v.x;
+      r.a[2 * q + 1] = v.y;
+    }
     const double2* p2 = reinterpret_cast<const double2*>(Y + (k0 + (t >> 4)) * kCols + (t & 15) * 4);
     const double2 v0 = p2[0], v1 = p2[1];
     r.b[0] = v0.x; r.b[1] = v0.y; r.b[2] = v1.x; r.b[3] = v1.y;
@@ -62,9 +78,10 @@ struct GemmF64 {
     double* As = (double*)stage;
     double* Bs = As + kAStage;
     const int t = threadIdx.x;
-    const int row = t >> 1, kb = (t & 1) * 8;
+    constexpr int tpr = kK / kEA;
+    const int row = t / tpr, kb = (t % tpr) * kEA;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) As[(kb + q) * kALd + row] = r.a[q];
+    for (int q = 0; q < kEA; ++q) As[(kb + q) * kALd + row] = r.a[q];
     double* d = Bs + (t >> 4) * kBLd + (t & 15) * 4;
     d[0] = r.b[0]; d[1] = r.b[1]; d[2] = r.b[2]; d[3] = r.b[3];
   }
@@ -75,13 +92,13 @@ struct GemmF64 {
 #pragma unroll
     for (int kk = 0; kk < kK / 4; ++kk) {
       const int k = kk * 4 + (lane >> 4);
-      double a[2], b[4];
+      double a[kIB], b[4];
 #pragma unroll
-      for (int ib = 0; ib < 2; ++ib) a[ib] = As[k * kALd + w * 32 + ib * 16 + (lane & 15)];
+      for (int ib = 0; ib < kIB; ++ib) a[ib] = As[k * kALd + w * kRW + ib * 16 + (lane & 15)];
 #pragma unroll
       for (int jb = 0; jb < 4; ++jb) b[jb] = Bs[k * kBLd + jb * 16 + (lane & 15)];
 #pragma unroll
-      for (int ib = 0; ib < 2; ++ib)
+      for (int ib = 0; ib < kIB; ++ib)
 #pragma unroll
         for (int jb = 0; jb < 4; ++jb)
           acc.v[ib][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ib], b[jb], acc.v[ib][jb], 0, 0, 0);
@@ -90,12 +107,12 @@ struct GemmF64 {
   static __device__ __forceinline__ void to_block(const Acc& acc, double* T) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
-    for (int ib = 0; ib < 2; ++ib)
+    for (int ib = 0; ib < kIB; ++ib)
 #pragma unroll
       for (int jb = 0; jb < 4; ++jb)
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-          T[(w * 32 + ib * 16 + (lane >> 4) + 4 * r) * kCols + jb * 16 + (lane & 15)] = acc.v[ib][jb][r];
+          T[(w * kRW + ib * 16 + (lane >> 4) + 4 * r) * kCols + jb * 16 + (lane & 15)] = acc.v[ib][jb][r];
   }
   // y block (FP64 in T, rows x 64) -> Y scratch rows i0..i0+rows
   static __device__ __forceinline__ void put_y(const double* T, E* __restrict__ Y, long, int i0, int rows) {
@@ -104,26 +121,32 @@ struct GemmF64 {
 };
 
 // ---------------------------------------------------------------- FP32
-struct GemmF32 {
+template <int RB>
+struct GemmF32T {
   using E = float;
+  static constexpr int kRows = RB;
+  static constexpr int kRW = RB / 4;
+  static constexpr int kIB = kRW / 16;
   static constexpr int kK = 32;
-  static constexpr int kALd = 128 + 4, kBLd = 64 + 4;
+  static constexpr int kEA = RB * kK / 256;  // 16 or 8
+  static constexpr int kALd = RB + 4, kBLd = 64 + 4;
   static constexpr int kAStage = kK * kALd, kBStage = kK * kBLd;
   static constexpr int kStageBytes = (kAStage + kBStage) * 4;
-  struct Acc { f32x4 v[2][4]; };
-  struct Regs { float a[16]; float b[8]; };
+  struct Acc { f32x4 v[kIB][4]; };
+  struct Regs { float a[kEA]; float b[8]; };
   static __device__ __forceinline__ void zero(Acc& acc) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < kIB; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j) acc.v[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
   }
   static __device__ __forceinline__ void load(const E* __restrict__ L, long ld, long, long i0, long k0,
                                               const E* __restrict__ Y, long, Regs& r) {
     const int t = threadIdx.x;
-    const float4* pa = reinterpret_cast<const float4*>(L + (i0 + (t >> 1)) * ld + k0 + (t & 1) * 16);
+    constexpr int tpr = kK / kEA;
+    const float4* pa = reinterpret_cast<const float4*>(L + (i0 + t / tpr) * ld + k0 + (t % tpr) * kEA);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < kEA / 4; ++q) {
       const float4 v = pa[q];
       r.a[4 * q] = v.x; r.a[4 * q + 1] = v.y; r.a[4 * q + 2] = v.z; r.a[4 * q + 3] = v.w;
     }
@@ -138,9 +161,10 @@ struct GemmF32 {
     float* As = (float*)stage;
     float* Bs = As + kAStage;
     const int t = threadIdx.x;
-    const int row = t >> 1, kb = (t & 1) * 16;
+    constexpr int tpr = kK / kEA;
+    const int row = t / tpr, kb = (t % tpr) * kEA;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) As[(kb + q) * kALd + row] = r.a[q];
+    for (int q = 0; q < kEA; ++q) As[(kb + q) * kALd + row] = r.a[q];
     float* d = Bs + (t >> 3) * kBLd + (t & 7) * 8;
 #pragma unroll
     for (int q = 0; q < 8; ++q) d[q] = r.b[q];
@@ -152,13 +176,13 @@ struct GemmF32 {
 #pragma unroll
     for (int kk = 0; kk < kK / 4; ++kk) {
       const int k = kk * 4 + (lane >> 4);
-      float a[2], b[4];
+      float a[kIB], b[4];
 #pragma unroll
-      for (int ib = 0; ib < 2; ++ib) a[ib] = As[k * kALd + w * 32 + ib * 16 + (lane & 15)];
+      for (int ib = 0; ib < kIB; ++ib) a[ib] = As[k * kALd + w * kRW + ib * 16 + (lane & 15)];
 #pragma unroll
       for (int jb = 0; jb < 4; ++jb) b[jb] = Bs[k * kBLd + jb * 16 + (lane & 15)];
 #pragma unroll
-      for (int ib = 0; ib < 2; ++ib)
+      for (int ib = 0; ib < kIB; ++ib)
 #pragma unroll
         for (int jb = 0; jb < 4; ++jb)
           acc.v[ib][jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ib], b[jb], acc.v[ib][jb], 0, 0, 0);
@@ -167,12 +191,12 @@ struct GemmF32 {
   static __device__ __forceinline__ void to_block(const Acc& acc, double* T) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
-    for (int ib = 0; ib < 2; ++ib)
+    for (int ib = 0; ib < kIB; ++ib)
 #pragma unroll
       for (int jb = 0; jb < 4; ++jb)
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-          T[(w * 32 + ib * 16 + 4 * (lane >> 4) + r) * kCols + jb * 16 + (lane & 15)] =
+          T[(w * kRW + ib * 16 + 4 * (lane >> 4) + r) * kCols + jb * 16 + (lane & 15)] =
               (double)acc.v[ib][jb][r];
   }
   static __device__ __forceinline__ void put_y(const double* T, E* __restrict__ Y, long, int i0, int rows) {
@@ -181,24 +205,29 @@ struct GemmF32 {
 };
 
 // ---------------------------------------------------------------- BF16
-// Split count 1: plain BF16 operands.  Split count 2 (GemmBF16x3): operands
-// are stored as hi and lo planes and three products are accumulated.
-template <int SPLIT>
+// Split count 1: plain BF16 operands.  Split count 2 (the x3 policy):
+// operands are stored as hi and lo planes and three products are accumulated.
+template <int SPLIT, int RB>
 struct GemmBF16T {
   using E = __bf16;
+  static constexpr int kRows = RB;
+  static constexpr int kRW = RB / 4;
+  static constexpr int kIB = kRW / 16;
   static constexpr int kK = SPLIT == 1 ? 64 : 32;
   static constexpr int kALd = kK + 8, kBLd = kK + 8;           // row strides (elements)
-  static constexpr int kAPlane = 128 * kALd, kBPlane = 64 * kBLd;
+  static constexpr int kAPlane = RB * kALd, kBPlane = 64 * kBLd;
   static constexpr int kAStage = SPLIT * kAPlane, kBStage = SPLIT * kBPlane;
   static constexpr int kStageBytes = (kAStage + kBStage) * 2;
-  struct Acc { f32x4 v[2][4]; };
-  // per lane: A row t/2, k half; B column t/4, k quarter (16-byte chunks)
-  static constexpr int kAChunks = kK / 16;                    // uint4 per lane per plane (A)
+  struct Acc { f32x4 v[kIB][4]; };
+  // per lane: A row t / (kK / kEA) with kEA consecutive k; B column t/4, k
+  // quarter (16-byte chunks)
+  static constexpr int kEA = RB * kK / 256;
+  static constexpr int kAChunks = kEA / 8;                    // uint4 per lane per plane (A)
   static constexpr int kBChunks = kK / 32;                    // uint4 per lane per plane (B)
   struct Regs { uint4 a[SPLIT][kAChunks]; uint4 b[SPLIT][kBChunks]; };
   static __device__ __forceinline__ void zero(Acc& acc) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < kIB; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j) acc.v[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
   }
@@ -207,10 +236,11 @@ struct GemmBF16T {
   static __device__ __forceinline__ void load(const E* __restrict__ L, long ld, long lplane, long i0,
                                               long k0, const E* __restrict__ Y, long ldy, Regs& r) {
     const int t = threadIdx.x;
+    constexpr int tpr = kK / kEA;
 #pragma unroll
     for (int sp = 0; sp < SPLIT; ++sp) {
-      const uint4* pa = reinterpret_cast<const uint4*>(L + sp * lplane + (i0 + (t >> 1)) * ld + k0 +
-                                                       (t & 1) * (kK / 2));
+      const uint4* pa = reinterpret_cast<const uint4*>(L + sp * lplane + (i0 + t / tpr) * ld + k0 +
+                                                       (t % tpr) * kEA);
 #pragma unroll
       for (int q = 0; q < kAChunks; ++q) r.a[sp][q] = pa[q];
       const uint4* pb = reinterpret_cast<const uint4*>(Y + sp * (long)kCols * ldy + (long)(t >> 2) * ldy +
@@ -223,9 +253,10 @@ struct GemmBF16T {
     E* As = (E*)stage;
     E* Bs = As + kAStage;
     const int t = threadIdx.x;
+    constexpr int tpr = kK / kEA;
 #pragma unroll
     for (int sp = 0; sp < SPLIT; ++sp) {
-      uint4* da = reinterpret_cast<uint4*>(As + sp * kAPlane + (t >> 1) * kALd + (t & 1) * (kK / 2));
+      uint4* da = reinterpret_cast<uint4*>(As + sp * kAPlane + (t / tpr) * kALd + (t % tpr) * kEA);
 #pragma unroll
       for (int q = 0; q < kAChunks; ++q) da[q] = r.a[sp][q];
       uint4* db = reinterpret_cast<uint4*>(Bs + sp * kBPlane + (t >> 2) * kBLd + (t & 3) * (kK / 4));
@@ -240,19 +271,19 @@ struct GemmBF16T {
 #pragma unroll
     for (int kk = 0; kk < kK / 32; ++kk) {
       const int k = kk * 32 + 8 * (lane >> 4);
-      bf16x8 a[SPLIT][2], b[SPLIT][4];
+      bf16x8 a[SPLIT][kIB], b[SPLIT][4];
 #pragma unroll
       for (int sp = 0; sp < SPLIT; ++sp) {
 #pragma unroll
-        for (int ib = 0; ib < 2; ++ib)
+        for (int ib = 0; ib < kIB; ++ib)
           a[sp][ib] = *reinterpret_cast<const bf16x8*>(As + sp * kAPlane +
-                                                      (w * 32 + ib * 16 + (lane & 15)) * kALd + k);
+                                                      (w * kRW + ib * 16 + (lane & 15)) * kALd + k);
 #pragma unroll
         for (int jb = 0; jb < 4; ++jb)
           b[sp][jb] = *reinterpret_cast<const bf16x8*>(Bs + sp * kBPlane + (jb * 16 + (lane & 15)) * kBLd + k);
       }
 #pragma unroll
-      for (int ib = 0; ib < 2; ++ib)
+      for (int ib = 0; ib < kIB; ++ib)
 #pragma unroll
         for (int jb = 0; jb < 4; ++jb) {
           acc.v[ib][jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][ib], b[0][jb], acc.v[ib][jb], 0, 0, 0);
@@ -266,22 +297,22 @@ struct GemmBF16T {
   static __device__ __forceinline__ void to_block(const Acc& acc, double* T) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
-    for (int ib = 0; ib < 2; ++ib)
+    for (int ib = 0; ib < kIB; ++ib)
 #pragma unroll
       for (int jb = 0; jb < 4; ++jb)
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-          T[(w * 32 + ib * 16 + 4 * (lane >> 4) + r) * kCols + jb * 16 + (lane & 15)] =
+          T[(w * kRW + ib * 16 + 4 * (lane >> 4) + r) * kCols + jb * 16 + (lane & 15)] =
               (double)acc.v[ib][jb][r];
   }
   // y block -> column-major Y planes: lane (c = t % 64, quarter t / 64) packs
-  // 8 consecutive rows of its column into one 16-byte store.  All 128 rows
-  // of the block are written (rows past n are never read by later GEMMs).
+  // 8 consecutive rows of its column into one 16-byte store.  All RB rows of
+  // the block are written (rows past n are never read by later GEMMs).
   static __device__ __forceinline__ void put_y(const double* T, E* __restrict__ Y, long ldy, int i0, int) {
     const int t = threadIdx.x, c = t & 63, rq = t >> 6;
 #pragma unroll
-    for (int g = 0; g < 4; ++g) {
-      const int r0 = rq * 32 + g * 8;
+    for (int g = 0; g < RB / 32; ++g) {
+      const int r0 = rq * (RB / 4) + g * 8;
       bf16x8 hi, lo;
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
@@ -295,7 +326,9 @@ struct GemmBF16T {
   }
 };
 
-using GemmBF16 = GemmBF16T<1>;
-using GemmBF16x3 = GemmBF16T<2>;
+using GemmF64 = GemmF64T<128>;
+using GemmF32 = GemmF32T<128>;
+using GemmBF16 = GemmBF16T<1, 128>;
+using GemmBF16x3 = GemmBF16T<2, 128>;
 
 }  // namespace mvn

@@ -26,7 +26,9 @@ def _oracle(bw, sizes, idx, a, b, off, N, S):
 SIZES = [1, 7, 300, 50, 129, 257, 5, 64, 200, 130]
 
 
-def test_batch_fp64_matches_oracle_per_problem():
+@pytest.mark.parametrize("rows", [128, 64])
+def test_batch_fp64_matches_oracle_per_problem(rows):
+    """Both sweep shapes (128- and 64-row blocks) on ragged sizes."""
     # n_max of the generator must reach the largest requested size
     bw = workloads.make_batch(count=len(SIZES), n_min=300, n_max=301, seed=7, N=400, S=3)
     sizes = np.array(SIZES, dtype=np.int32)
@@ -36,7 +38,7 @@ def test_batch_fp64_matches_oracle_per_problem():
     a = np.concatenate([bw.a[bw.off[p]:bw.off[p] + n] for p, n in enumerate(SIZES)])
     b = np.concatenate([bw.b[bw.off[p]:bw.off[p] + n] for p, n in enumerate(SIZES)])
     N, S = 400, 3
-    plan = mvn.mvn_batch_plan(sizes, N, S)
+    plan = mvn.mvn_batch_plan(sizes, N, S, opts=mvn.options(tile=128, sweep_rows=rows))
     out = mvn.mvn_prob_batch(plan, idx, bw.locs, (bw.sigma2, bw.beta, bw.nu, bw.nugget), a, b, seed=bw.seed)
     torch.cuda.synchronize()
     assert torch.all(plan.info == 0)
@@ -47,11 +49,12 @@ def test_batch_fp64_matches_oracle_per_problem():
         np.testing.assert_allclose(got[p, 4:], ref[p]["logP_s"], rtol=0, atol=1e-10)
 
 
-@pytest.mark.parametrize("prec", [mvn.MVN_FP32, mvn.MVN_BF16X3])
-def test_batch_mixed_precision_within_1e4(prec):
+@pytest.mark.parametrize("prec,rows", [(mvn.MVN_FP32, 128), (mvn.MVN_BF16X3, 128), (mvn.MVN_FP32, 64),
+                                       (mvn.MVN_BF16X3, 64)])
+def test_batch_mixed_precision_within_1e4(prec, rows):
     bw = workloads.make_batch(count=8, n_min=100, n_max=600, seed=5, positive_excursion=True, N=800, S=4)
     N, S = 800, 4
-    plan = mvn.mvn_batch_plan(bw.n_p, N, S, opts=mvn.options(tile=128, precision=prec))
+    plan = mvn.mvn_batch_plan(bw.n_p, N, S, opts=mvn.options(tile=128, precision=prec, sweep_rows=rows))
     out = mvn.mvn_prob_batch(plan, bw.idx, bw.locs, (bw.sigma2, bw.beta, bw.nu, bw.nugget), bw.a, bw.b,
                              seed=bw.seed)
     torch.cuda.synchronize()
@@ -60,6 +63,26 @@ def test_batch_mixed_precision_within_1e4(prec):
     ref = _oracle(bw, bw.n_p, bw.idx, bw.a, bw.b, bw.off, N, S)
     for p in range(len(bw.n_p)):
         assert abs(got[p, 1] - ref[p]["P"]) <= 1e-4, (p, got[p, 1], ref[p]["P"])
+
+
+@pytest.mark.parametrize("rows", [128, 64])
+def test_batch_plain_bf16_error_statement(rows):
+    """Plain BF16 GEMMs (8 significant bits) do not meet 1e-4 on every
+    problem of this batch (|dP| reached 1.5e-4 at P = 0.40); the stated
+    error bar for MVN_BF16 is 1e-3 absolute, and the split form MVN_BF16X3
+    is the BF16 mode that meets 1e-4."""
+    bw = workloads.make_batch(count=8, n_min=100, n_max=600, seed=5, positive_excursion=True, N=800, S=4)
+    N, S = 800, 4
+    plan = mvn.mvn_batch_plan(bw.n_p, N, S, opts=mvn.options(tile=128, precision=mvn.MVN_BF16, sweep_rows=rows))
+    out = mvn.mvn_prob_batch(plan, bw.idx, bw.locs, (bw.sigma2, bw.beta, bw.nu, bw.nugget), bw.a, bw.b,
+                             seed=bw.seed)
+    torch.cuda.synchronize()
+    assert torch.all(plan.info == 0)
+    got = out.cpu().numpy()
+    ref = _oracle(bw, bw.n_p, bw.idx, bw.a, bw.b, bw.off, N, S)
+    err = [abs(got[p, 1] - ref[p]["P"]) for p in range(len(bw.n_p))]
+    print(f"rows={rows} BF16 max |dP| = {max(err):.3g}")
+    assert max(err) <= 1e-3, err
 
 
 def test_batch_graph_capture_replays_match_eager():

@@ -57,10 +57,11 @@ def test_cholesky_from_sigma_and_not_spd():
     assert torch.isnan(r["out"]).all()
 
 
-def _prob_case(w, N, S, tile=None):
+def _prob_case(w, N, S, tile=None, rows=0):
     f = mvn.mvn_cholesky(w.n, locs=w.locs, kern=(w.sigma2, w.beta, w.nu, w.nugget),
                          opts=mvn.options(tile=tile or w.tile), device=DEV)
-    r = mvn.mvn_prob(f, w.a, w.b, w.mu, N=N, S=S, seed=w.seed, return_ell=True)
+    r = mvn.mvn_prob(f, w.a, w.b, w.mu, N=N, S=S, seed=w.seed, return_ell=True,
+                     opts=mvn.options(tile=tile or w.tile, sweep_rows=rows))
     torch.cuda.synchronize()
     L = oracle.cholesky(oracle.covariance(w.locs, w.sigma2, w.beta, w.nu, w.nugget))
     at, bt = oracle.centre(w.a, w.b, w.mu)
@@ -82,11 +83,13 @@ def test_prob_per_sample_parity_dense400_ragged():
     assert r["rel_stderr"].item() == pytest.approx(ref["rel_stderr"], rel=1e-8)
 
 
-def test_prob_full_dense400_workload():
-    """The full n = 400, N = 10000 x S = 10 workload: log P-hat to 1e-10."""
+@pytest.mark.parametrize("rows", [128, 64])
+def test_prob_full_dense400_workload(rows):
+    """The full n = 400, N = 10000 x S = 10 workload: log P-hat to 1e-10, with
+    both sweep shapes (128- and 64-row blocks)."""
     w = workloads.make_workload("dense400")
-    print("dense400 full", flush=True)
-    f, r, L, at, bt = _prob_case(w, w.N, w.S)
+    print(f"dense400 full rows={rows}", flush=True)
+    f, r, L, at, bt = _prob_case(w, w.N, w.S, rows=rows)
     ell_ref = oracle.sweep(L, at, bt, w.N, w.S, w.seed)
     ref = oracle.reduce_samples(ell_ref, w.N, w.S)
     assert abs(r["logP"].item() - ref["logP"]) < 1e-10
