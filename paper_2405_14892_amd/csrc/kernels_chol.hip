@@ -5,8 +5,8 @@
 // tile column, sub-panels of 32 columns are finished left-looking:
 //   chol_diag  - update the 32 x 32 diagonal block by the earlier sub-panels
 //                of the same tile column, factor it in LDS (one workgroup);
-//   chol_trsm  - update the rows below by the same sub-panels and solve
-//                X L_dd^T = B (one lane per row, operands staged in LDS);
+//   chol_panel - update 128-row blocks below by the same sub-panels on FP64
+//                MFMA and solve X L_dd^T = B (one lane per row);
 // then chol_syrk subtracts the tile column's outer product from the trailing
 // matrix with FP64 MFMA on 128 x 128 lower tiles (the bulk of the flops).
 #include <hip/hip_runtime.h>
@@ -132,62 +132,131 @@ __global__ __launch_bounds__(256) void chol_diag_kernel(double* __restrict__ A, 
 }
 
 // ------------------------------------------------------------ panel solve
-// Rows i >= j0 + jw: x = A[i, j0:j0+jw] - A[i, k0:j0] A[j0:j0+jw, k0:j0]^T,
-// then x <- x L_dd^{-T} (forward substitution).  One lane per row.
-__device__ __forceinline__ void chol_trsm_body(double* __restrict__ A, int ld, int k0, int j0, int jw,
-                                               const int* __restrict__ info, int rblock) {
+// Rows i >= j0 + jw, 128 per workgroup: the update
+// X = A[i, j0:j0+jw] - A[i, k0:j0] A[j0:j0+jw, k0:j0]^T on FP64 MFMA (four
+// waves of 32 rows x 32 columns, K staged 16 deep in LDS, double-buffered),
+// then the forward substitution x <- x L_dd^{-T} one lane per row.
+// FULL: jw == 32 (every sub-panel except the last of a tile whose width is
+// not a multiple of 32); the constant bound keeps the substitution in
+// registers.
+template <bool FULL>
+__device__ __forceinline__ void chol_panel_body(double* __restrict__ A, int ld, int k0, int j0, int jw_arg,
+                                                const int* __restrict__ info, int rblock) {
   if (*info != 0) return;
-  __shared__ double B[kSub][64 + 1];
+  const int jw = FULL ? kSub : jw_arg;
+  constexpr int kALd = kTile + 1, kBLd = kSub + 1;
+  constexpr int kAS = kStageK * kALd, kBS = kStageK * kBLd;
+  __shared__ double stage[2 * (kAS + kBS)];
+  __shared__ double X[kTile][kSub + 1];
   __shared__ double D[kSub][kSub + 1];
-  const int t = threadIdx.x;
-  const long i = (long)j0 + jw + (long)rblock * 256 + t;
-  const bool live = i < ld;
-  double x[kSub];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const long r0 = (long)j0 + jw + (long)rblock * kTile;
+  const int K = j0 - k0;  // a multiple of 32
+  f64x4 acc[2][2];
 #pragma unroll
-  for (int c = 0; c < kSub; ++c) x[c] = (live && c < jw) ? A[i * ld + j0 + c] : 0.0;
-  for (int kc = k0; kc < j0; kc += 64) {
-    const int kw = min(64, j0 - kc);
-    __syncthreads();
-    for (int e = t; e < kSub * 64; e += 256) {
-      const int r = e >> 6, k = e & 63;
-      B[r][k] = (r < jw && k < kw) ? A[(long)(j0 + r) * ld + kc + k] : 0.0;
-    }
-    __syncthreads();
-    if (live) {
-      const double* arow = A + i * ld + kc;
-      for (int k = 0; k < kw; ++k) {
-        const double av = arow[k];
+  for (int ib = 0; ib < 2; ++ib)
 #pragma unroll
-        for (int c = 0; c < kSub; ++c) x[c] -= av * B[c][k];
+    for (int jb = 0; jb < 2; ++jb) acc[ib][jb] = f64x4{0.0, 0.0, 0.0, 0.0};
+  if (K > 0) {
+    // lane t: A rows r0 + t/2, 8 consecutive k (masked at ld); B row t/8 of
+    // the diagonal block, 2 consecutive k (masked at jw)
+    double ra[8], rb[2];
+    const long arow = r0 + (t >> 1);
+    const int brow = t >> 3;
+    auto load = [&](int kk) {
+      const long kb = (long)k0 + kk + (t & 1) * 8;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) ra[q] = arow < ld ? A[arow * ld + kb + q] : 0.0;
+      const long kc = (long)k0 + kk + (t & 7) * 2;
+#pragma unroll
+      for (int q = 0; q < 2; ++q) rb[q] = brow < jw ? A[(long)(j0 + brow) * ld + kc + q] : 0.0;
+    };
+    auto store = [&](double* s) {
+      const int row = t >> 1, kb = (t & 1) * 8;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) s[(kb + q) * kALd + row] = ra[q];
+      double* sb = s + kAS;
+      const int kc = (t & 7) * 2;
+#pragma unroll
+      for (int q = 0; q < 2; ++q) sb[(kc + q) * kBLd + brow] = rb[q];
+    };
+    const int nst = K / kStageK;
+    load(0);
+    store(stage);
+    __syncthreads();
+    for (int s = 0; s < nst; ++s) {
+      double* cur = stage + (s & 1) * (kAS + kBS);
+      double* nxt = stage + ((s + 1) & 1) * (kAS + kBS);
+      if (s + 1 < nst) load((s + 1) * kStageK);
+      const double* As = cur;
+      const double* Bs = cur + kAS;
+#pragma unroll
+      for (int kk = 0; kk < kStageK / 4; ++kk) {
+        const int k = kk * 4 + (lane >> 4);
+        double a[2], b[2];
+#pragma unroll
+        for (int ib = 0; ib < 2; ++ib) a[ib] = As[k * kALd + w * 32 + ib * 16 + (lane & 15)];
+#pragma unroll
+        for (int jb = 0; jb < 2; ++jb) b[jb] = Bs[k * kBLd + jb * 16 + (lane & 15)];
+#pragma unroll
+        for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+          for (int jb = 0; jb < 2; ++jb)
+            acc[ib][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ib], b[jb], acc[ib][jb], 0, 0, 0);
       }
+      if (s + 1 < nst) store(nxt);
+      __syncthreads();
     }
   }
-  __syncthreads();
+  // X = A[rows, j0:j0+jw] - update (accumulator D[l/16 + 4r][l%16] layout)
+#pragma unroll
+  for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+    for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = w * 32 + ib * 16 + (lane >> 4) + 4 * r, c = jb * 16 + (lane & 15);
+        const long gi = r0 + row;
+        X[row][c] = (gi < ld && c < jw) ? A[gi * ld + j0 + c] - acc[ib][jb][r] : 0.0;
+      }
   for (int e = t; e < kSub * kSub; e += 256) {
     const int r = e >> 5, c = e & 31;
     D[r][c] = (r < jw && c <= r) ? A[(long)(j0 + r) * ld + j0 + c] : (r == c ? 1.0 : 0.0);
   }
   __syncthreads();
-  if (!live) return;
+  // forward substitution over all 32 columns: past jw, X is zero and D the
+  // identity, so those columns stay zero and the others are unaffected
+  if (t < kTile) {
+    double x[kSub];
 #pragma unroll
-  for (int c = 0; c < kSub; ++c) {
-    double v = x[c];
+    for (int c = 0; c < kSub; ++c) x[c] = X[t][c];
 #pragma unroll
-    for (int cp = 0; cp < c; ++cp) v -= x[cp] * D[c][cp];
-    x[c] = v / D[c][c];
+    for (int c = 0; c < kSub; ++c) {
+      double v = x[c];
+#pragma unroll
+      for (int cp = 0; cp < c; ++cp) v -= x[cp] * D[c][cp];
+      x[c] = v / D[c][c];
+    }
+#pragma unroll
+    for (int c = 0; c < kSub; ++c) X[t][c] = x[c];
   }
-#pragma unroll
-  for (int c = 0; c < kSub; ++c)
-    if (c < jw) A[i * ld + j0 + c] = x[c];
+  __syncthreads();
+  for (int e = t; e < kTile * kSub; e += 256) {
+    const int row = e >> 5, c = e & 31;
+    const long gi = r0 + row;
+    if (gi < ld && c < jw) A[gi * ld + j0 + c] = X[row][c];
+  }
 }
 
-__global__ __launch_bounds__(256) void chol_trsm_kernel(double* __restrict__ A, int ld, int k0, int j0,
-                                                        int jw, const int* __restrict__ info) {
-  chol_trsm_body(A, ld, k0, j0, jw, info, blockIdx.x);
+template <bool FULL>
+__global__ __launch_bounds__(256) void chol_panel_kernel(double* __restrict__ A, int ld, int k0, int j0, int jw,
+                                                         const int* __restrict__ info) {
+  chol_panel_body<FULL>(A, ld, k0, j0, jw, info, blockIdx.x);
 }
 
 // ------------------------------------------------------------ trailing update
 // C = A[r0:, r0:] (lower 128 x 128 tiles) -= P P^T with P = A[r0:, k0:k0+kw].
+template <bool MASK>
 __device__ __forceinline__ void chol_syrk_body(double* __restrict__ A, int ld, int k0, int kw,
                                                const int* __restrict__ info, long b) {
   if (*info != 0) return;
@@ -202,8 +271,8 @@ __device__ __forceinline__ void chol_syrk_body(double* __restrict__ A, int ld, i
   acc_zero(acc);
   const int nst = (kw + kStageK - 1) / kStageK;
   double ra[8], rb[8];
-  load_rows<true>(A, ld, rowA, k0, ld, (long)k0 + kw, ra);
-  load_rows<true>(A, ld, rowB, k0, ld, (long)k0 + kw, rb);
+  load_rows<MASK>(A, ld, rowA, k0, ld, (long)k0 + kw, ra);
+  load_rows<MASK>(A, ld, rowB, k0, ld, (long)k0 + kw, rb);
   store_rows(lds, ra);
   store_rows(lds + kStageDoubles, rb);
   __syncthreads();
@@ -211,8 +280,8 @@ __device__ __forceinline__ void chol_syrk_body(double* __restrict__ A, int ld, i
     double* cur = lds + (s & 1) * 2 * kStageDoubles;
     double* nxt = lds + ((s + 1) & 1) * 2 * kStageDoubles;
     if (s + 1 < nst) {
-      load_rows<true>(A, ld, rowA, (long)k0 + (s + 1) * kStageK, ld, (long)k0 + kw, ra);
-      load_rows<true>(A, ld, rowB, (long)k0 + (s + 1) * kStageK, ld, (long)k0 + kw, rb);
+      load_rows<MASK>(A, ld, rowA, (long)k0 + (s + 1) * kStageK, ld, (long)k0 + kw, ra);
+      load_rows<MASK>(A, ld, rowB, (long)k0 + (s + 1) * kStageK, ld, (long)k0 + kw, rb);
     }
     mma_stage(cur, cur + kStageDoubles, acc);
     if (s + 1 < nst) {
@@ -232,9 +301,12 @@ __device__ __forceinline__ void chol_syrk_body(double* __restrict__ A, int ld, i
       }
 }
 
+// MASK = false when every 128 x 16 operand tile lies inside the matrix: the
+// tile width is a multiple of 128 (so are ld, k0 + kw and kw).
+template <bool MASK>
 __global__ __launch_bounds__(256) void chol_syrk_kernel(double* __restrict__ A, int ld, int k0, int kw,
                                                         const int* __restrict__ info) {
-  chol_syrk_body(A, ld, k0, kw, info, blockIdx.x);
+  chol_syrk_body<MASK>(A, ld, k0, kw, info, blockIdx.x);
 }
 
 __global__ __launch_bounds__(256) void zero_upper_kernel(double* __restrict__ A, int ld) {
@@ -250,15 +322,22 @@ hipError_t launch_cholesky_f64(int ld, int tile, double* A, int* info, hipStream
       const int jw = min(kSub, k0 + kw - j0);
       hipLaunchKernelGGL(chol_diag_kernel, dim3(1), dim3(256), 0, st, A, ld, k0, j0, jw, info);
       const int rows = ld - (j0 + jw);
-      if (rows > 0)
-        hipLaunchKernelGGL(chol_trsm_kernel, dim3((rows + 255) / 256), dim3(256), 0, st, A, ld, k0,
-                           j0, jw, (const int*)info);
+      if (rows > 0) {
+        const dim3 pg((rows + kTile - 1) / kTile);
+        if (jw == kSub)
+          hipLaunchKernelGGL(chol_panel_kernel<true>, pg, dim3(256), 0, st, A, ld, k0, j0, jw, (const int*)info);
+        else
+          hipLaunchKernelGGL(chol_panel_kernel<false>, pg, dim3(256), 0, st, A, ld, k0, j0, jw, (const int*)info);
+      }
     }
     const int rem = ld - (k0 + kw);
     if (rem > 0) {
       const long nt = (rem + kTile - 1) / kTile;
-      hipLaunchKernelGGL(chol_syrk_kernel, dim3((unsigned)(nt * (nt + 1) / 2)), dim3(256), 0, st, A,
-                         ld, k0, kw, (const int*)info);
+      const dim3 grid((unsigned)(nt * (nt + 1) / 2));
+      if (tile % kTile == 0)
+        hipLaunchKernelGGL(chol_syrk_kernel<false>, grid, dim3(256), 0, st, A, ld, k0, kw, (const int*)info);
+      else
+        hipLaunchKernelGGL(chol_syrk_kernel<true>, grid, dim3(256), 0, st, A, ld, k0, kw, (const int*)info);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -407,9 +486,13 @@ hipError_t launch_cholesky_lp(int prec, int ld, int tile, double* A, int* info, 
       const int jw = min(kSub, k0 + kw - j0);
       hipLaunchKernelGGL(chol_diag_kernel, dim3(1), dim3(256), 0, st, A, ld, k0, j0, jw, info);
       const int rows = ld - (j0 + jw);
-      if (rows > 0)
-        hipLaunchKernelGGL(chol_trsm_kernel, dim3((rows + 255) / 256), dim3(256), 0, st, A, ld, k0,
-                           j0, jw, (const int*)info);
+      if (rows > 0) {
+        const dim3 pg((rows + kTile - 1) / kTile);
+        if (jw == kSub)
+          hipLaunchKernelGGL(chol_panel_kernel<true>, pg, dim3(256), 0, st, A, ld, k0, j0, jw, (const int*)info);
+        else
+          hipLaunchKernelGGL(chol_panel_kernel<false>, pg, dim3(256), 0, st, A, ld, k0, j0, jw, (const int*)info);
+      }
     }
     const int rem = ld - (k0 + kw);
     if (rem > 0) {
@@ -503,8 +586,8 @@ __global__ __launch_bounds__(256) void batch_trsm_kernel(const BatchDesc* __rest
                                                          int k0, int j0, const int* info) {
   const int p = order[blockIdx.y];
   const BatchDesc d = desc[p];
-  if ((long)blockIdx.x * 256 >= (long)d.ld - (j0 + kSub)) return;
-  chol_trsm_body(factor + d.factor_off, d.ld, k0, j0, kSub, info + p, blockIdx.x);
+  if ((long)blockIdx.x * kTile >= (long)d.ld - (j0 + kSub)) return;
+  chol_panel_body<true>(factor + d.factor_off, d.ld, k0, j0, kSub, info + p, blockIdx.x);
 }
 
 __global__ __launch_bounds__(256) void batch_syrk_kernel(const BatchDesc* __restrict__ desc,
@@ -514,7 +597,7 @@ __global__ __launch_bounds__(256) void batch_syrk_kernel(const BatchDesc* __rest
   const BatchDesc d = desc[p];
   const long nt = ((long)d.ld - (k0 + kBatchTile)) / kTile;
   if ((long)blockIdx.x >= nt * (nt + 1) / 2) return;
-  chol_syrk_body(factor + d.factor_off, d.ld, k0, kBatchTile, info + p, blockIdx.x);
+  chol_syrk_body<false>(factor + d.factor_off, d.ld, k0, kBatchTile, info + p, blockIdx.x);
 }
 
 template <class G>
@@ -539,7 +622,7 @@ hipError_t launch_batch_cholesky(int prec, const BatchDesc* desc, const int* ord
       hipLaunchKernelGGL(batch_diag_kernel, dim3(cnt), dim3(256), 0, st, desc, order, factor, k0, j0, info);
       const int rows = ldmax - (j0 + kSub);
       if (rows > 0)
-        hipLaunchKernelGGL(batch_trsm_kernel, dim3((rows + 255) / 256, cnt), dim3(256), 0, st, desc, order,
+        hipLaunchKernelGGL(batch_trsm_kernel, dim3((rows + kTile - 1) / kTile, cnt), dim3(256), 0, st, desc, order,
                            factor, k0, j0, (const int*)info);
     }
     int cnt2 = 0;
