@@ -23,6 +23,7 @@ after a warm-up, outside the timed region):
     python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--no-cpu-baseline] [--no-variants]
     python bench.py --workload tlr64k --tlr-eps 1e-5 --no-variants --no-cpu-baseline
     python bench.py --precision bf16 --no-variants --no-cpu-baseline
+    python bench.py --steps 1 --warmup 0 --no-cpu-baseline --variants batch2000
 """
 from __future__ import annotations
 
@@ -372,6 +373,8 @@ def main() -> int:
     ap.add_argument("--max-rank", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--variants", default="",
+                    help="comma-separated subset of the variants to run (default: all)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -452,8 +455,9 @@ def main() -> int:
                 ("tlr64k", lambda: variant_tlr(dev)),
                 ("batch2000", lambda: variant_batch(dev)),
                 ("grad4096", lambda: variant_grad(dev))]
+        only = {v for v in args.variants.split(",") if v}
         for job in jobs:
-            if job is None:
+            if job is None or (only and job[0] not in only):
                 continue
             name, fn = job
             t0 = time.perf_counter()

@@ -38,7 +38,7 @@ constexpr int kCUs = 256;      // compute units of an MI355X: the persistent gri
 // Rows per sweep block: 0 selects the default (128).
 int sweep_rows(const mvn_options* o) { return (!o || o->sweep_rows == 0) ? 128 : o->sweep_rows; }
 bool sweep_rows_ok(const mvn_options* o) { return !o || o->sweep_rows == 0 || o->sweep_rows == 64 || o->sweep_rows == 128; }
-int max_grid(int rows) { return kCUs * mvn::sweep_wg_per_cu(rows); }
+int max_grid(int rows, int prec) { return kCUs * mvn::sweep_wg_per_cu(rows, prec); }
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 int padded(int n) { return (n + 127) / 128 * 128; }
@@ -120,7 +120,7 @@ ProbLayout prob_layout_ld(int ld, int N, int S, int prec, long zslice, int rows)
   L.ld = ld;
   const long NS = (long)N * S;
   const long chunks = (NS + mvn::sweep_tile_cols() - 1) / mvn::sweep_tile_cols();
-  const int gmax = max_grid(rows);
+  const int gmax = max_grid(rows, prec);
   L.grid = (int)(chunks < gmax ? chunks : gmax);
   L.yslice = mvn::sweep_yslice(prec, L.ld);
   L.zslice = zslice;
@@ -201,7 +201,7 @@ GradLayout grad_layout(int n, int N, int S) {
   L.ld = padded(n);
   const long NS = (long)N * S;
   L.nchunks = (NS + mvn::sweep_tile_cols() - 1) / mvn::sweep_tile_cols();
-  L.grid = (int)(L.nchunks < max_grid(128) ? L.nchunks : max_grid(128));
+  L.grid = (int)(L.nchunks < max_grid(128, 0) ? L.nchunks : max_grid(128, 0));
   const size_t slice = sizeof(double) * (size_t)L.ld * mvn::sweep_tile_cols();
   size_t off = 0;
   L.at = off; off = align_up(off + sizeof(double) * L.ld);
@@ -277,7 +277,7 @@ BatchWs batch_ws(const BatchPlan& P, int count, int N, int S, int prec, int rows
   const long NS = (long)N * S;
   const long chunks = (NS + mvn::sweep_tile_cols() - 1) / mvn::sweep_tile_cols();
   W.items = chunks * count;
-  const int gmax = max_grid(rows);
+  const int gmax = max_grid(rows, prec);
   W.grid = (int)(W.items < gmax ? W.items : gmax);
   size_t off = 0;
   W.at = off; off = align_up(off + sizeof(double) * (size_t)P.sum_n);

@@ -158,10 +158,13 @@ struct SweepLdsSize {
   __shared__ uint64_t lds_lat[G::kRows];                                              \
   const SweepLds sh{lds_T, lds_slab, lds_at, lds_bt, lds_rl, lds_lat}
 
-// Two workgroups per CU for the 128-row shape, three for the 64-row shape.
+// Workgroups per CU: two for the 128-row shape; four for the 64-row shape
+// (38-41 KB of LDS, <= 128 VGPRs), three for its split-BF16 form (47 KB).
 template <class G>
 struct SweepOccupancy {
-  static constexpr int kWG = G::kRows == 128 ? 2 : 3;
+  // LDS of one workgroup (block buffer, slab, per-row constants, work-item slot)
+  static constexpr int kLds = SweepLdsSize<G>::kT * 8 + kSlab * G::kRows * 8 + 4 * G::kRows * 8 + 16;
+  static constexpr int kWG = G::kRows == 128 ? 2 : (4 * kLds <= 160 * 1024 ? 4 : 3);
 };
 
 template <class G>
@@ -201,7 +204,15 @@ __global__ __launch_bounds__(256, SweepOccupancy<G>::kWG) void batch_sweep_kerne
   }
 }
 
-int sweep_wg_per_cu(int rows) { return rows == 64 ? 3 : 2; }
+int sweep_wg_per_cu(int rows, int prec) {
+  if (rows != 64) return 2;
+  switch (prec) {
+    case 0: return SweepOccupancy<GemmF64T<64>>::kWG;
+    case 1: return SweepOccupancy<GemmF32T<64>>::kWG;
+    case 2: return SweepOccupancy<GemmBF16T<1, 64>>::kWG;
+    default: return SweepOccupancy<GemmBF16T<2, 64>>::kWG;
+  }
+}
 
 long sweep_yslice(int prec, int ld) {
   // elements per workgroup slice of the Y scratch, and bytes per element

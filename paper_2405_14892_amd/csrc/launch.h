@@ -76,8 +76,9 @@ hipError_t launch_reduce(const double* ell, int N, int S, double* part, const in
                          const int* bad_limits, double* out, hipStream_t st);
 
 int sweep_tile_cols();
-// Workgroups of the sweep that share one CU for a block-row count (128 or 64).
-int sweep_wg_per_cu(int rows);
+// Workgroups of the sweep that share one CU for a block-row count (128 or 64)
+// and precision.
+int sweep_wg_per_cu(int rows, int prec);
 
 // ---------------------------------------------------------------- batches
 // Per-problem descriptor of a batch (written by the host plan, read on the

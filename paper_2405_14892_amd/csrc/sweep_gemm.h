@@ -7,9 +7,9 @@
 // wave64s; wave w owns rows [w RB/4, (w+1) RB/4) x all 64 columns = RB/64 x 4
 // MFMA blocks of 16 x 16.  K advances in LDS stages, double-buffered; the
 // next stage's global loads are in flight while the current stage's MFMAs
-// run.  The 64-row shape needs about 47 KB of LDS, so three workgroups (three
-// conditioning waves) share a CU instead of two; the 128-row shape reads the
-// sample block Y half as often.
+// run.  The 64-row shape needs 38-47 KB of LDS, so four workgroups (three
+// for split BF16) share a CU instead of two: more conditioning waves at
+// once; the 128-row shape reads the sample block Y half as often.
 //
 //   GemmF64   v_mfma_f64_16x16x4_f64, FP64 operands; stage 16 deep
 //   GemmF32   v_mfma_f32_16x16x4_f32, FP32 operands, FP32 accumulation;
@@ -129,7 +129,9 @@ struct GemmF32T {
   static constexpr int kIB = kRW / 16;
   static constexpr int kK = 32;
   static constexpr int kEA = RB * kK / 256;  // 16 or 8
-  static constexpr int kALd = RB + 4, kBLd = 64 + 4;
+  // (the 64-row shape pads A rows by 2 floats instead of 4 so that four
+  // workgroups fit in the CU's LDS)
+  static constexpr int kALd = RB + (RB == 64 ? 2 : 4), kBLd = 64 + 4;
   static constexpr int kAStage = kK * kALd, kBStage = kK * kBLd;
   static constexpr int kStageBytes = (kAStage + kBStage) * 4;
   struct Acc { f32x4 v[kIB][4]; };
@@ -213,7 +215,9 @@ struct GemmBF16T {
   static constexpr int kRows = RB;
   static constexpr int kRW = RB / 4;
   static constexpr int kIB = kRW / 16;
-  static constexpr int kK = SPLIT == 1 ? 64 : 32;
+  // K per stage: 64 for plain BF16 at 128 rows; 32 otherwise (the 64-row
+  // plain shape then fits four workgroups per CU)
+  static constexpr int kK = (SPLIT == 1 && RB == 128) ? 64 : 32;
   static constexpr int kALd = kK + 8, kBLd = kK + 8;           // row strides (elements)
   static constexpr int kAPlane = RB * kALd, kBPlane = 64 * kBLd;
   static constexpr int kAStage = SPLIT * kAPlane, kBStage = SPLIT * kBPlane;
