@@ -581,34 +581,95 @@ __global__ __launch_bounds__(256) void batch_diag_kernel(const BatchDesc* __rest
   chol_diag_body(factor + d.factor_off, d.ld, k0, j0, kSub, info + p);
 }
 
+// Compact grids for the batched steps: problems of equal padded size (ranks
+// are sorted by size, so they are consecutive) form a group; the host passes
+// per group its first rank, problem count, items per problem and the running
+// item count, and workgroup b finds its (rank, item) by a binary search.
+// Only the items that exist are launched.
+constexpr int kMaxGroups = 32;
+struct BatchGroups {
+  int n;
+  int rank0[kMaxGroups];
+  int count[kMaxGroups];
+  int items[kMaxGroups];
+  int cum[kMaxGroups + 1];
+};
+
+__device__ __forceinline__ void group_item(const BatchGroups& g, int b, int& rank, int& item) {
+  int lo = 0, hi = g.n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (g.cum[mid] <= b) lo = mid;
+    else hi = mid;
+  }
+  const int off = b - g.cum[lo];
+  rank = g.rank0[lo] + off / g.items[lo];
+  item = off % g.items[lo];
+}
+
 __global__ __launch_bounds__(256) void batch_trsm_kernel(const BatchDesc* __restrict__ desc,
                                                          const int* __restrict__ order, double* factor,
-                                                         int k0, int j0, const int* info) {
-  const int p = order[blockIdx.y];
+                                                         int k0, int j0, const int* info, BatchGroups g) {
+  int rank, item;
+  group_item(g, blockIdx.x, rank, item);
+  const int p = order[rank];
   const BatchDesc d = desc[p];
-  if ((long)blockIdx.x * kTile >= (long)d.ld - (j0 + kSub)) return;
-  chol_panel_body<true>(factor + d.factor_off, d.ld, k0, j0, kSub, info + p, blockIdx.x);
+  chol_panel_body<true>(factor + d.factor_off, d.ld, k0, j0, kSub, info + p, item);
 }
 
 __global__ __launch_bounds__(256) void batch_syrk_kernel(const BatchDesc* __restrict__ desc,
                                                          const int* __restrict__ order, double* factor,
-                                                         int k0, const int* info) {
-  const int p = order[blockIdx.y];
+                                                         int k0, const int* info, BatchGroups g) {
+  int rank, item;
+  group_item(g, blockIdx.x, rank, item);
+  const int p = order[rank];
   const BatchDesc d = desc[p];
-  const long nt = ((long)d.ld - (k0 + kBatchTile)) / kTile;
-  if ((long)blockIdx.x >= nt * (nt + 1) / 2) return;
-  chol_syrk_body<false>(factor + d.factor_off, d.ld, k0, kBatchTile, info + p, blockIdx.x);
+  chol_syrk_body<false>(factor + d.factor_off, d.ld, k0, kBatchTile, info + p, item);
 }
 
+// Lower 128 x 64 tiles of the trailing matrix: row tile by holds 2 by + 2
+// of them, so item t has by = floor((sqrt(4 t + 1) - 1) / 2).
 template <class G>
 __global__ __launch_bounds__(256) void batch_syrk_lp_kernel(const BatchDesc* __restrict__ desc,
                                                             const int* __restrict__ order, double* factor,
-                                                            int k0, const int* info) {
-  const int p = order[blockIdx.z];
+                                                            int k0, const int* info, BatchGroups g) {
+  int rank, item;
+  group_item(g, blockIdx.x, rank, item);
+  const int p = order[rank];
   const BatchDesc d = desc[p];
-  const long rem = (long)d.ld - (k0 + kBatchTile);
-  if ((long)blockIdx.x * kCols >= rem || (long)blockIdx.y * kTile >= rem) return;
-  chol_syrk_lp_body<G>(factor + d.factor_off, d.ld, k0, kBatchTile, info + p, blockIdx.x, blockIdx.y);
+  int by = (int)((sqrt(4.0 * item + 1.0) - 1.0) * 0.5);
+  while ((by + 1) * (by + 2) <= item) ++by;
+  while (by * (by + 1) > item) --by;
+  const int bx = item - by * (by + 1);
+  chol_syrk_lp_body<G>(factor + d.factor_off, d.ld, k0, kBatchTile, info + p, bx, by);
+}
+
+// Launches `launch(groups, total)` for the groups of ranks [0, cnt) with
+// items(ld) > 0 work items each, at most kMaxGroups groups per launch.
+template <class Items, class Launch>
+static hipError_t for_groups(const int* ld_rank, int cnt, Items items, Launch launch) {
+  BatchGroups g{};
+  int r = 0;
+  while (r < cnt) {
+    int r1 = r;
+    while (r1 < cnt && ld_rank[r1] == ld_rank[r]) ++r1;
+    const int it = items(ld_rank[r]);
+    if (it > 0) {
+      g.rank0[g.n] = r;
+      g.count[g.n] = r1 - r;
+      g.items[g.n] = it;
+      g.cum[g.n + 1] = g.cum[g.n] + (r1 - r) * it;
+      ++g.n;
+    }
+    r = r1;
+    if (g.n == kMaxGroups || (r >= cnt && g.n > 0)) {
+      launch(g, g.cum[g.n]);
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      g = BatchGroups{};
+    }
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_batch_cholesky(int prec, const BatchDesc* desc, const int* order, const int* ld_rank,
@@ -620,28 +681,46 @@ hipError_t launch_batch_cholesky(int prec, const BatchDesc* desc, const int* ord
     while (cnt < count && ld_rank[cnt] > k0) ++cnt;
     for (int j0 = k0; j0 < k0 + kBatchTile; j0 += kSub) {
       hipLaunchKernelGGL(batch_diag_kernel, dim3(cnt), dim3(256), 0, st, desc, order, factor, k0, j0, info);
-      const int rows = ldmax - (j0 + kSub);
-      if (rows > 0)
-        hipLaunchKernelGGL(batch_trsm_kernel, dim3((rows + kTile - 1) / kTile, cnt), dim3(256), 0, st, desc, order,
-                           factor, k0, j0, (const int*)info);
+      const hipError_t e = for_groups(
+          ld_rank, cnt, [&](int ld) { return (ld - (j0 + kSub) + kTile - 1) / kTile; },
+          [&](const BatchGroups& g, int total) {
+            hipLaunchKernelGGL(batch_trsm_kernel, dim3(total), dim3(256), 0, st, desc, order, factor, k0, j0,
+                               (const int*)info, g);
+          });
+      if (e != hipSuccess) return e;
     }
     int cnt2 = 0;
     while (cnt2 < count && ld_rank[cnt2] > k0 + kBatchTile) ++cnt2;
-    const int rem = ldmax - (k0 + kBatchTile);
-    if (rem > 0 && cnt2 > 0) {
+    if (cnt2 > 0) {
+      hipError_t e;
       if (prec == 0) {
-        const long nt = rem / kTile;
-        hipLaunchKernelGGL(batch_syrk_kernel, dim3((unsigned)(nt * (nt + 1) / 2), cnt2), dim3(256), 0, st, desc,
-                           order, factor, k0, (const int*)info);
+        e = for_groups(
+            ld_rank, cnt2,
+            [&](int ld) {
+              const int nt = (ld - (k0 + kBatchTile)) / kTile;
+              return nt * (nt + 1) / 2;
+            },
+            [&](const BatchGroups& g, int total) {
+              hipLaunchKernelGGL(batch_syrk_kernel, dim3(total), dim3(256), 0, st, desc, order, factor, k0,
+                                 (const int*)info, g);
+            });
       } else {
-        dim3 g(rem / kCols, rem / kTile, cnt2);
-        switch (prec) {
-          case 1: hipLaunchKernelGGL(batch_syrk_lp_kernel<GemmF32>, g, dim3(256), 0, st, desc, order, factor, k0, (const int*)info); break;
-          case 2: hipLaunchKernelGGL(batch_syrk_lp_kernel<GemmBF16>, g, dim3(256), 0, st, desc, order, factor, k0, (const int*)info); break;
-          case 3: hipLaunchKernelGGL(batch_syrk_lp_kernel<GemmBF16x3>, g, dim3(256), 0, st, desc, order, factor, k0, (const int*)info); break;
-          default: return hipErrorInvalidValue;
-        }
+        e = for_groups(
+            ld_rank, cnt2,
+            [&](int ld) {
+              const int nt = (ld - (k0 + kBatchTile)) / kTile;
+              return nt * (nt + 1);
+            },
+            [&](const BatchGroups& g, int total) {
+              const dim3 grid(total);
+              switch (prec) {
+                case 1: hipLaunchKernelGGL(batch_syrk_lp_kernel<GemmF32>, grid, dim3(256), 0, st, desc, order, factor, k0, (const int*)info, g); break;
+                case 2: hipLaunchKernelGGL(batch_syrk_lp_kernel<GemmBF16>, grid, dim3(256), 0, st, desc, order, factor, k0, (const int*)info, g); break;
+                case 3: hipLaunchKernelGGL(batch_syrk_lp_kernel<GemmBF16x3>, grid, dim3(256), 0, st, desc, order, factor, k0, (const int*)info, g); break;
+              }
+            });
       }
+      if (e != hipSuccess) return e;
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

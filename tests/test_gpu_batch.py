@@ -113,3 +113,31 @@ def test_batch_graph_capture_replays_match_eager():
         torch.cuda.synchronize()
         assert torch.equal(plan.out, eager), rep
         del junk
+
+
+def test_batch_more_size_groups_than_one_launch_holds():
+    """34 distinct padded sizes (128 ... 4352): the batched Cholesky steps
+    split their compact grids over two launches; the smallest problems (in the
+    second launch) and the largest ones match the oracle."""
+    sizes = np.array([128 * k - 5 for k in range(1, 35)], dtype=np.int32)
+    rng = np.random.default_rng(21)
+    k = 70
+    locs = workloads.grid_locations(k)
+    idx = np.concatenate([rng.choice(k * k, size=n, replace=False) for n in sizes]).astype(np.int64)
+    off = np.zeros(len(sizes) + 1, dtype=np.int64)
+    off[1:] = np.cumsum(sizes)
+    a = np.full(off[-1], -np.inf)
+    b = rng.normal(0.5, 1.0, off[-1])
+    kern = (1.0, 0.1, 0.5, 1e-4)
+    N, S, seed = 64, 2, 99
+    plan = mvn.mvn_batch_plan(sizes, N, S, opts=mvn.options(tile=128, sweep_rows=64))
+    out = mvn.mvn_prob_batch(plan, idx, locs, kern, a, b, seed=seed)
+    torch.cuda.synchronize()
+    assert torch.all(plan.info == 0)
+    got = out.cpu().numpy()
+    for p in (0, 1, 2, 32, 33):
+        sl = slice(off[p], off[p + 1])
+        L = oracle.cholesky(oracle.covariance(locs[idx[sl]], *kern))
+        ref = oracle.reduce_samples(oracle.sweep(L, a[sl], b[sl], N, S, seed), N, S)
+        print(p, sizes[p], got[p, 0], ref["logP"], flush=True)
+        assert abs(got[p, 0] - ref["logP"]) < 1e-9 * max(1.0, abs(ref["logP"]))
