@@ -56,99 +56,88 @@ hipError_t launch_build_matrix(int n, int ld, const double* sigma, int lds, cons
 }
 
 // ------------------------------------------------------------ diagonal block
-// D = A[j0:j0+jw, j0:j0+jw] - A[j0:j0+jw, k0:j0] A[j0:j0+jw, k0:j0]^T, then
-// D = chol(D) in LDS.  One workgroup of 256 lanes.
-__device__ __forceinline__ void chol_diag_body(double* __restrict__ A, int ld, int k0, int j0, int jw,
+// Factor the jw x jw diagonal block D = A[j0:j0+jw, j0:j0+jw] in place.  The
+// block already holds the updates of every column left of j0: those of
+// earlier tile columns from the trailing updates, those of earlier
+// sub-panels of its own tile column from their panel solves.  One wave: lane
+// r < jw keeps row r of D in registers and column c is finished by the Crout
+// step
+//   s_r = D[r][c] - sum_{k<c} L[r][k] L[c][k],   L[c][c] = sqrt(s_c),
+//   L[r][c] = s_r / L[c][c]  (r > c),
+// row c of L being broadcast from lane c with v_readlane.
+__device__ __forceinline__ double lane_bcast(double v, int l) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+__device__ __forceinline__ void chol_diag_body(double* __restrict__ A, int ld, int j0, int jw,
                                                int* __restrict__ info) {
   if (*info != 0) return;
-  __shared__ double D[kSub][kSub + 1];
-  __shared__ double P[kSub][64 + 1];
-  __shared__ int fail;
-  const int t = threadIdx.x;
-  if (t == 0) fail = 0;
-  // four lower-triangle entries per lane (e = t + 256 q)
-  double s[4];
+  const int r = threadIdx.x & 63;
+  const bool live = r < jw;
+  // rows and columns past jw are those of the identity, so all 32 columns
+  // run (no early exit keeps the row in registers); the first column whose
+  // pivot is not positive is the failure
+  double x[kSub];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int e = t + 256 * q, r = e >> 5, c = e & 31;
-    s[q] = (r < jw && c <= r) ? A[(long)(j0 + r) * ld + j0 + c] : 0.0;
-  }
-  for (int kc = k0; kc < j0; kc += 64) {
-    const int kw = min(64, j0 - kc);
-    __syncthreads();
-    for (int e = t; e < kSub * 64; e += 256) {
-      const int r = e >> 6, k = e & 63;
-      P[r][k] = (r < jw && k < kw) ? A[(long)(j0 + r) * ld + kc + k] : 0.0;
-    }
-    __syncthreads();
+  for (int c = 0; c < kSub; ++c)
+    x[c] = (live && c <= r) ? A[(long)(j0 + r) * ld + j0 + c] : (c == r ? 1.0 : 0.0);
+  int fail = 0;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int e = t + 256 * q, r = e >> 5, c = e & 31;
-      if (r < jw && c <= r) {
-        double acc = 0.0;
-        for (int k = 0; k < kw; ++k) acc += P[r][k] * P[c][k];
-        s[q] -= acc;
-      }
-    }
-  }
-  __syncthreads();
+  for (int c = 0; c < kSub; ++c) {
+    double s = x[c];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int e = t + 256 * q, r = e >> 5, c = e & 31;
-    D[r][c] = (r < jw && c <= r) ? s[q] : 0.0;
-  }
-  __syncthreads();
-  int j = 0;
-  for (; j < jw; ++j) {
-    if (t == 0) {
-      const double piv = D[j][j];
-      if (!(piv > 0.0)) fail = j0 + j + 1;
-      else D[j][j] = sqrt(piv);
-    }
-    __syncthreads();
-    if (fail) break;
-    const double djj = D[j][j];
-    for (int r = j + 1 + t; r < jw; r += 256) D[r][j] /= djj;
-    __syncthreads();
-    for (int e = t; e < kSub * kSub; e += 256) {
-      const int r = e >> 5, c = e & 31;
-      if (c > j && c <= r && r < jw) D[r][c] -= D[r][j] * D[c][j];
-    }
-    __syncthreads();
+    for (int k = 0; k < c; ++k) s -= x[k] * lane_bcast(x[k], c);
+    const double piv = lane_bcast(s, c);  // uniform across the wave
+    if (fail == 0 && c < jw && !(piv > 0.0)) fail = j0 + c + 1;
+    const double d = sqrt(piv);
+    x[c] = r == c ? d : (r > c ? s / d : 0.0);
   }
   if (fail) {
-    if (t == 0) atomicCAS(info, 0, fail);
+    if (r == 0) atomicCAS(info, 0, fail);
     return;
   }
-  for (int e = t; e < kSub * kSub; e += 256) {
-    const int r = e >> 5, c = e & 31;
-    if (r < jw && c <= r) A[(long)(j0 + r) * ld + j0 + c] = D[r][c];
+  if (live) {
+#pragma unroll
+    for (int c = 0; c < kSub; ++c)
+      if (c <= r) A[(long)(j0 + r) * ld + j0 + c] = x[c];
   }
 }
 
-__global__ __launch_bounds__(256) void chol_diag_kernel(double* __restrict__ A, int ld, int k0, int j0,
-                                                        int jw, int* __restrict__ info) {
-  chol_diag_body(A, ld, k0, j0, jw, info);
+// One wave.
+__global__ __launch_bounds__(64) void chol_diag_kernel(double* __restrict__ A, int ld, int j0, int jw,
+                                                       int* __restrict__ info) {
+  chol_diag_body(A, ld, j0, jw, info);
 }
 
 // ------------------------------------------------------------ panel solve
 // Rows i >= j0 + jw, 128 per workgroup: the update
 // X = A[i, j0:j0+jw] - A[i, k0:j0] A[j0:j0+jw, k0:j0]^T on FP64 MFMA (four
-// waves of 32 rows x 32 columns, K staged 16 deep in LDS, double-buffered),
+// waves of 32 rows x 32 columns, K staged 32 deep in LDS, double-buffered),
 // then the forward substitution x <- x L_dd^{-T} one lane per row.
+// Afterwards the finished columns update the diagonal blocks of the later
+// sub-panels of the tile column (rows and columns [q0, q0 + 32), q0 < kend)
+// that lie in this workgroup's rows, D_q -= X_q X_q^T, one wave per block on
+// FP64 MFMA; each diagonal block thus holds all its updates when it is
+// factored.
 // FULL: jw == 32 (every sub-panel except the last of a tile whose width is
-// not a multiple of 32); the constant bound keeps the substitution in
-// registers.
+// not a multiple of 32, which has no later diagonal block); the constant
+// bound keeps the substitution in registers.
+constexpr int kPanelK = 32;  // k per LDS stage of the panel update
+
 template <bool FULL>
 __device__ __forceinline__ void chol_panel_body(double* __restrict__ A, int ld, int k0, int j0, int jw_arg,
-                                                const int* __restrict__ info, int rblock) {
+                                                int kend, const int* __restrict__ info, int rblock) {
   if (*info != 0) return;
   const int jw = FULL ? kSub : jw_arg;
   constexpr int kALd = kTile + 1, kBLd = kSub + 1;
-  constexpr int kAS = kStageK * kALd, kBS = kStageK * kBLd;
+  constexpr int kAS = kPanelK * kALd, kBS = kPanelK * kBLd;
+  static_assert(kTile * (kSub + 1) <= 2 * (kAS + kBS), "X must fit in the stage buffers");
   __shared__ double stage[2 * (kAS + kBS)];
-  __shared__ double X[kTile][kSub + 1];
   __shared__ double D[kSub][kSub + 1];
+  double (*X)[kSub + 1] = reinterpret_cast<double (*)[kSub + 1]>(stage);  // after the K loop
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const long r0 = (long)j0 + jw + (long)rblock * kTile;
   const int K = j0 - k0;  // a multiple of 32
@@ -158,40 +147,40 @@ __device__ __forceinline__ void chol_panel_body(double* __restrict__ A, int ld, 
 #pragma unroll
     for (int jb = 0; jb < 2; ++jb) acc[ib][jb] = f64x4{0.0, 0.0, 0.0, 0.0};
   if (K > 0) {
-    // lane t: A rows r0 + t/2, 8 consecutive k (masked at ld); B row t/8 of
-    // the diagonal block, 2 consecutive k (masked at jw)
-    double ra[8], rb[2];
+    // lane t: A row r0 + t/2, 16 consecutive k (rows at or past ld read as
+    // zero); B row t/8 of the diagonal block, 4 consecutive k (masked at jw)
+    double ra[16], rb[4];
     const long arow = r0 + (t >> 1);
     const int brow = t >> 3;
     auto load = [&](int kk) {
-      const long kb = (long)k0 + kk + (t & 1) * 8;
+      const long kb = (long)k0 + kk + (t & 1) * 16;
 #pragma unroll
-      for (int q = 0; q < 8; ++q) ra[q] = arow < ld ? A[arow * ld + kb + q] : 0.0;
-      const long kc = (long)k0 + kk + (t & 7) * 2;
+      for (int q = 0; q < 16; ++q) ra[q] = arow < ld ? A[arow * ld + kb + q] : 0.0;
+      const long kc = (long)k0 + kk + (t & 7) * 4;
 #pragma unroll
-      for (int q = 0; q < 2; ++q) rb[q] = brow < jw ? A[(long)(j0 + brow) * ld + kc + q] : 0.0;
+      for (int q = 0; q < 4; ++q) rb[q] = brow < jw ? A[(long)(j0 + brow) * ld + kc + q] : 0.0;
     };
     auto store = [&](double* s) {
-      const int row = t >> 1, kb = (t & 1) * 8;
+      const int row = t >> 1, kb = (t & 1) * 16;
 #pragma unroll
-      for (int q = 0; q < 8; ++q) s[(kb + q) * kALd + row] = ra[q];
+      for (int q = 0; q < 16; ++q) s[(kb + q) * kALd + row] = ra[q];
       double* sb = s + kAS;
-      const int kc = (t & 7) * 2;
+      const int kc = (t & 7) * 4;
 #pragma unroll
-      for (int q = 0; q < 2; ++q) sb[(kc + q) * kBLd + brow] = rb[q];
+      for (int q = 0; q < 4; ++q) sb[(kc + q) * kBLd + brow] = rb[q];
     };
-    const int nst = K / kStageK;
+    const int nst = K / kPanelK;
     load(0);
     store(stage);
     __syncthreads();
     for (int s = 0; s < nst; ++s) {
       double* cur = stage + (s & 1) * (kAS + kBS);
       double* nxt = stage + ((s + 1) & 1) * (kAS + kBS);
-      if (s + 1 < nst) load((s + 1) * kStageK);
+      if (s + 1 < nst) load((s + 1) * kPanelK);
       const double* As = cur;
       const double* Bs = cur + kAS;
 #pragma unroll
-      for (int kk = 0; kk < kStageK / 4; ++kk) {
+      for (int kk = 0; kk < kPanelK / 4; ++kk) {
         const int k = kk * 4 + (lane >> 4);
         double a[2], b[2];
 #pragma unroll
@@ -246,27 +235,52 @@ __device__ __forceinline__ void chol_panel_body(double* __restrict__ A, int ld, 
     const long gi = r0 + row;
     if (gi < ld && c < jw) A[gi * ld + j0 + c] = X[row][c];
   }
+  if (FULL) {
+    // the diagonal blocks after j0 + 32 start 32 rows apart, so wave w takes
+    // the one at local row 32 w
+    const long q0 = r0 + 32 * w;
+    if (q0 < kend) {
+      const int hq = (int)min((long)kSub, kend - q0);
+      const int lr = 32 * w;
+      f64x4 dq[3];  // tiles (0, 0), (1, 0), (1, 1)
+#pragma unroll
+      for (int i = 0; i < 3; ++i) dq[i] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int kk = 0; kk < kSub / 4; ++kk) {
+        const int k = kk * 4 + (lane >> 4);
+        const double a0 = X[lr + (lane & 15)][k], a1 = X[lr + 16 + (lane & 15)][k];
+        dq[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, a0, dq[0], 0, 0, 0);
+        dq[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, a0, dq[1], 0, 0, 0);
+        dq[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, a1, dq[2], 0, 0, 0);
+      }
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const int ib = i > 0, jb = i > 1;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = ib * 16 + (lane >> 4) + 4 * r, col = jb * 16 + (lane & 15);
+          if (row < hq && col <= row) A[(q0 + row) * ld + q0 + col] -= dq[i][r];
+        }
+      }
+    }
+  }
 }
 
 template <bool FULL>
 __global__ __launch_bounds__(256) void chol_panel_kernel(double* __restrict__ A, int ld, int k0, int j0, int jw,
-                                                         const int* __restrict__ info) {
-  chol_panel_body<FULL>(A, ld, k0, j0, jw, info, blockIdx.x);
+                                                         int kend, const int* __restrict__ info) {
+  chol_panel_body<FULL>(A, ld, k0, j0, jw, kend, info, blockIdx.x);
 }
 
 // ------------------------------------------------------------ trailing update
-// C = A[r0:, r0:] (lower 128 x 128 tiles) -= P P^T with P = A[r0:, k0:k0+kw].
+// One 128 x 128 lower tile of C = A[rowA:, rowB:] -= P P^T with
+// P = A[:, k0:k0+kw]; only elements with column < clim and column <= row
+// are written.
 template <bool MASK>
 __device__ __forceinline__ void chol_syrk_body(double* __restrict__ A, int ld, int k0, int kw,
-                                               const int* __restrict__ info, long b) {
+                                               const int* __restrict__ info, long rowA, long rowB, long clim) {
   if (*info != 0) return;
   __shared__ double lds[2 * 2 * kStageDoubles];
-  long ti = (long)((sqrt(8.0 * (double)b + 1.0) - 1.0) * 0.5);
-  while ((ti + 1) * (ti + 2) / 2 <= b) ++ti;
-  while (ti * (ti + 1) / 2 > b) --ti;
-  const long tj = b - ti * (ti + 1) / 2;
-  const long r0 = (long)k0 + kw;
-  const long rowA = r0 + ti * kTile, rowB = r0 + tj * kTile;
   Acc acc;
   acc_zero(acc);
   const int nst = (kw + kStageK - 1) / kStageK;
@@ -297,16 +311,37 @@ __device__ __forceinline__ void chol_syrk_body(double* __restrict__ A, int ld, i
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const long gi = rowA + acc_row(ib, r), gj = rowB + acc_col(jb);
-        if (gi < ld && gj < ld && gj <= gi) A[gi * ld + gj] -= acc.v[ib][jb][r];
+        if (gi < ld && gj < clim && gj <= gi) A[gi * ld + gj] -= acc.v[ib][jb][r];
       }
 }
 
-// MASK = false when every 128 x 16 operand tile lies inside the matrix: the
-// tile width is a multiple of 128 (so are ld, k0 + kw and kw).
+// (ti, tj), tj <= ti, of lower tile b in row-major order of the triangle.
+__device__ __forceinline__ void tri_tile(long b, long& ti, long& tj) {
+  ti = (long)((sqrt(8.0 * (double)b + 1.0) - 1.0) * 0.5);
+  while ((ti + 1) * (ti + 2) / 2 <= b) ++ti;
+  while (ti * (ti + 1) / 2 > b) --ti;
+  tj = b - ti * (ti + 1) / 2;
+}
+
+// The lower triangle of tiles of A[r0:, r0:].  MASK = false when every
+// 128 x 16 operand tile lies inside the matrix: the tile width is a multiple
+// of 128 (so are ld, r0, k0 + kw and kw).
 template <bool MASK>
-__global__ __launch_bounds__(256) void chol_syrk_kernel(double* __restrict__ A, int ld, int k0, int kw,
-                                                        const int* __restrict__ info) {
-  chol_syrk_body<MASK>(A, ld, k0, kw, info, blockIdx.x);
+__global__ __launch_bounds__(256, 2) void chol_syrk_kernel(double* __restrict__ A, int ld, int k0, int kw, int r0,
+                                                           const int* __restrict__ info) {
+  long ti, tj;
+  tri_tile(blockIdx.x, ti, tj);
+  chol_syrk_body<MASK>(A, ld, k0, kw, info, r0 + ti * kTile, r0 + tj * kTile, ld);
+}
+
+// Tile column [c1, c2) of the trailing matrix, c1 = k0 + kw: tile (blockIdx.y,
+// blockIdx.x) of A[c1:, c1:c2].
+template <bool MASK>
+__global__ __launch_bounds__(256, 2) void chol_syrk_col_kernel(double* __restrict__ A, int ld, int k0, int kw,
+                                                               int c2, const int* __restrict__ info) {
+  if (blockIdx.x > blockIdx.y) return;
+  const long c1 = (long)k0 + kw;
+  chol_syrk_body<MASK>(A, ld, k0, kw, info, c1 + (long)blockIdx.y * kTile, c1 + (long)blockIdx.x * kTile, c2);
 }
 
 __global__ __launch_bounds__(256) void zero_upper_kernel(double* __restrict__ A, int ld) {
@@ -315,33 +350,111 @@ __global__ __launch_bounds__(256) void zero_upper_kernel(double* __restrict__ A,
   if (i < ld && j < ld && j > i) A[i * ld + j] = 0.0;
 }
 
-hipError_t launch_cholesky_f64(int ld, int tile, double* A, int* info, hipStream_t st) {
+SideStream* side_stream(int slot, hipStream_t st) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex table_mu;
+  static SideStream* table[kMaxDevices][kSideSlots] = {};
+  static bool failed[kMaxDevices][kSideSlots] = {};
+  int dev = 0;
+  if (slot < 0 || slot >= kSideSlots || hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+    return nullptr;
+  std::lock_guard<std::mutex> g(table_mu);
+  if (table[dev][slot] || failed[dev][slot]) return table[dev][slot];
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return nullptr;
+  SideStream* sd = new SideStream();
+  bool ok = hipStreamCreateWithFlags(&sd->s, hipStreamNonBlocking) == hipSuccess;
+  for (int i = 0; ok && i < 3; ++i) ok = hipEventCreateWithFlags(&sd->ev[i], hipEventDisableTiming) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    failed[dev][slot] = true;
+    return nullptr;  // sd and whatever it holds stay allocated: a failure here is not retried
+  }
+  table[dev][slot] = sd;
+  return sd;
+}
+
+// The sub-panel chain of tile column [k0, k0 + kw): factor each 32 x 32
+// diagonal block, then solve (and update) the rows below it.
+static void chol_column(int ld, int k0, int kw, double* A, int* info, hipStream_t st) {
+  const int kend = k0 + kw;
+  for (int j0 = k0; j0 < kend; j0 += kSub) {
+    const int jw = min(kSub, kend - j0);
+    hipLaunchKernelGGL(chol_diag_kernel, dim3(1), dim3(64), 0, st, A, ld, j0, jw, info);
+    const int rows = ld - (j0 + jw);
+    if (rows > 0) {
+      const dim3 pg((rows + kTile - 1) / kTile);
+      if (jw == kSub)
+        hipLaunchKernelGGL(chol_panel_kernel<true>, pg, dim3(256), 0, st, A, ld, k0, j0, jw, kend, (const int*)info);
+      else
+        hipLaunchKernelGGL(chol_panel_kernel<false>, pg, dim3(256), 0, st, A, ld, k0, j0, jw, kend, (const int*)info);
+    }
+  }
+}
+
+// Right-looking over tile columns.  With a side stream (lookahead), the
+// trailing update of tile column k is split: the part that falls on tile
+// column k + 1 runs on the caller's stream, which then goes on with that
+// column's sub-panel chain, while the rest of the trailing matrix is updated
+// on the side stream:
+//   st:   chain(k)  [evP]  wait evR(k-1)  next(k)  chain(k+1) ...
+//   side:                  wait evP  rest(k)  [evR(k)] ...
+// next(k) waits for rest(k-1), which also writes tile column k + 1; the
+// regions written concurrently are disjoint column ranges.
+template <class Next, class Rest>
+static hipError_t right_looking(int ld, int tile, double* A, int* info, hipStream_t st, SideStream* sd,
+                                Next next, Rest rest) {
+  bool pending = false, used = false;  // a rest() on the side stream not yet waited for; any
   for (int k0 = 0; k0 < ld; k0 += tile) {
     const int kw = min(tile, ld - k0);
-    for (int j0 = k0; j0 < k0 + kw; j0 += kSub) {
-      const int jw = min(kSub, k0 + kw - j0);
-      hipLaunchKernelGGL(chol_diag_kernel, dim3(1), dim3(256), 0, st, A, ld, k0, j0, jw, info);
-      const int rows = ld - (j0 + jw);
-      if (rows > 0) {
-        const dim3 pg((rows + kTile - 1) / kTile);
-        if (jw == kSub)
-          hipLaunchKernelGGL(chol_panel_kernel<true>, pg, dim3(256), 0, st, A, ld, k0, j0, jw, (const int*)info);
-        else
-          hipLaunchKernelGGL(chol_panel_kernel<false>, pg, dim3(256), 0, st, A, ld, k0, j0, jw, (const int*)info);
+    chol_column(ld, k0, kw, A, info, st);
+    const int c1 = k0 + kw;
+    if (c1 < ld) {
+      if (!sd) {
+        rest(k0, kw, c1, st);
+      } else {
+        const int c2 = min(c1 + tile, ld);
+        hipEventRecord(sd->ev[0], st);
+        if (pending) hipStreamWaitEvent(st, sd->ev[1], 0);
+        pending = false;
+        next(k0, kw, c2, st);
+        if (c2 < ld) {
+          hipStreamWaitEvent(sd->s, sd->ev[0], 0);
+          rest(k0, kw, c2, sd->s);
+          hipEventRecord(sd->ev[1], sd->s);
+          pending = used = true;
+        }
       }
-    }
-    const int rem = ld - (k0 + kw);
-    if (rem > 0) {
-      const long nt = (rem + kTile - 1) / kTile;
-      const dim3 grid((unsigned)(nt * (nt + 1) / 2));
-      if (tile % kTile == 0)
-        hipLaunchKernelGGL(chol_syrk_kernel<false>, grid, dim3(256), 0, st, A, ld, k0, kw, (const int*)info);
-      else
-        hipLaunchKernelGGL(chol_syrk_kernel<true>, grid, dim3(256), 0, st, A, ld, k0, kw, (const int*)info);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
+  if (used) {
+    hipEventRecord(sd->ev[2], sd->s);
+    hipStreamWaitEvent(st, sd->ev[2], 0);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_cholesky_f64(int ld, int tile, double* A, int* info, hipStream_t st, bool lookahead) {
+  SideStream* sd = (lookahead && ld > 2 * tile) ? side_stream(kSideCholesky, st) : nullptr;
+  std::unique_lock<std::mutex> lock;
+  if (sd) lock = std::unique_lock<std::mutex>(sd->mu);
+  const bool mask = tile % kTile != 0;
+  auto next = [&](int k0, int kw, int c2, hipStream_t s) {
+    const long c1 = (long)k0 + kw;
+    const dim3 grid((unsigned)((c2 - c1 + kTile - 1) / kTile), (unsigned)((ld - c1 + kTile - 1) / kTile));
+    if (mask) hipLaunchKernelGGL(chol_syrk_col_kernel<true>, grid, dim3(256), 0, s, A, ld, k0, kw, c2, (const int*)info);
+    else hipLaunchKernelGGL(chol_syrk_col_kernel<false>, grid, dim3(256), 0, s, A, ld, k0, kw, c2, (const int*)info);
+  };
+  auto rest = [&](int k0, int kw, int r0, hipStream_t s) {
+    const long nt = (ld - r0 + kTile - 1) / kTile;
+    const dim3 grid((unsigned)(nt * (nt + 1) / 2));
+    if (mask) hipLaunchKernelGGL(chol_syrk_kernel<true>, grid, dim3(256), 0, s, A, ld, k0, kw, r0, (const int*)info);
+    else hipLaunchKernelGGL(chol_syrk_kernel<false>, grid, dim3(256), 0, s, A, ld, k0, kw, r0, (const int*)info);
+  };
+  hipError_t e = right_looking(ld, tile, A, info, st, sd, next, rest);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(zero_upper_kernel, dim3(ld / 16, ld / 16), dim3(256), 0, st, A, ld);
   return hipGetLastError();
 }
@@ -417,12 +530,12 @@ struct SyrkStage<GemmBF16T<SPLIT, 128>> {
 };
 
 template <class G>
+// One 128 x 64 tile of C = A[rowA:, colB:] -= P P^T, P = A[:, k0:k0+kw];
+// only elements with column < clim and column <= row are written.
 __device__ __forceinline__ void chol_syrk_lp_body(double* __restrict__ A, int ld, int k0, int kw,
-                                                  const int* __restrict__ info, int bx, int by) {
+                                                  const int* __restrict__ info, long rowA, long colB, long clim) {
   if (*info != 0) return;
   __shared__ __attribute__((aligned(16))) double lds[kTile * kCols];
-  const long r0 = (long)k0 + kw;
-  const long rowA = r0 + (long)by * kTile, colB = r0 + (long)bx * kCols;
   if (colB > rowA + kTile - 1 || rowA >= ld) return;  // tile entirely above the diagonal
   typename G::Acc acc;
   G::zero(acc);
@@ -445,14 +558,23 @@ __device__ __forceinline__ void chol_syrk_lp_body(double* __restrict__ A, int ld
   __syncthreads();
   for (int e = threadIdx.x; e < kTile * kCols; e += 256) {
     const long gi = rowA + e / kCols, gj = colB + e % kCols;
-    if (gi < ld && gj < ld && gj <= gi) A[gi * ld + gj] -= lds[e];
+    if (gi < ld && gj < clim && gj <= gi) A[gi * ld + gj] -= lds[e];
   }
 }
 
+// Tiles (blockIdx.y, blockIdx.x) of A[r0:, r0:].
 template <class G>
-__global__ __launch_bounds__(256) void chol_syrk_lp_kernel(double* __restrict__ A, int ld, int k0, int kw,
+__global__ __launch_bounds__(256) void chol_syrk_lp_kernel(double* __restrict__ A, int ld, int k0, int kw, int r0,
                                                            const int* __restrict__ info) {
-  chol_syrk_lp_body<G>(A, ld, k0, kw, info, blockIdx.x, blockIdx.y);
+  chol_syrk_lp_body<G>(A, ld, k0, kw, info, r0 + (long)blockIdx.y * kTile, r0 + (long)blockIdx.x * kCols, ld);
+}
+
+// Tile column [c1, c2) of the trailing matrix, c1 = k0 + kw.
+template <class G>
+__global__ __launch_bounds__(256) void chol_syrk_lp_col_kernel(double* __restrict__ A, int ld, int k0, int kw, int c2,
+                                                               const int* __restrict__ info) {
+  const long c1 = (long)k0 + kw;
+  chol_syrk_lp_body<G>(A, ld, k0, kw, info, c1 + (long)blockIdx.y * kTile, c1 + (long)blockIdx.x * kCols, c2);
 }
 
 // Low-precision operand copy of the finished factor for the sweep's GEMM:
@@ -479,34 +601,32 @@ __global__ __launch_bounds__(256) void convert_factor_kernel(const double* __res
   if (SPLIT == 2) out[ld * ld + e] = (E)(float)(v - (double)(float)hi);
 }
 
+template <class G>
+static hipError_t cholesky_lp(int ld, int tile, double* A, int* info, hipStream_t st, SideStream* sd) {
+  auto next = [&](int k0, int kw, int c2, hipStream_t s) {
+    const long c1 = (long)k0 + kw;
+    const dim3 grid((unsigned)((c2 - c1 + kCols - 1) / kCols), (unsigned)((ld - c1 + kTile - 1) / kTile));
+    hipLaunchKernelGGL(chol_syrk_lp_col_kernel<G>, grid, dim3(256), 0, s, A, ld, k0, kw, c2, (const int*)info);
+  };
+  auto rest = [&](int k0, int kw, int r0, hipStream_t s) {
+    const dim3 grid((unsigned)((ld - r0 + kCols - 1) / kCols), (unsigned)((ld - r0 + kTile - 1) / kTile));
+    hipLaunchKernelGGL(chol_syrk_lp_kernel<G>, grid, dim3(256), 0, s, A, ld, k0, kw, r0, (const int*)info);
+  };
+  return right_looking(ld, tile, A, info, st, sd, next, rest);
+}
+
 hipError_t launch_cholesky_lp(int prec, int ld, int tile, double* A, int* info, void* low, hipStream_t st) {
-  for (int k0 = 0; k0 < ld; k0 += tile) {
-    const int kw = min(tile, ld - k0);
-    for (int j0 = k0; j0 < k0 + kw; j0 += kSub) {
-      const int jw = min(kSub, k0 + kw - j0);
-      hipLaunchKernelGGL(chol_diag_kernel, dim3(1), dim3(256), 0, st, A, ld, k0, j0, jw, info);
-      const int rows = ld - (j0 + jw);
-      if (rows > 0) {
-        const dim3 pg((rows + kTile - 1) / kTile);
-        if (jw == kSub)
-          hipLaunchKernelGGL(chol_panel_kernel<true>, pg, dim3(256), 0, st, A, ld, k0, j0, jw, (const int*)info);
-        else
-          hipLaunchKernelGGL(chol_panel_kernel<false>, pg, dim3(256), 0, st, A, ld, k0, j0, jw, (const int*)info);
-      }
-    }
-    const int rem = ld - (k0 + kw);
-    if (rem > 0) {
-      dim3 grid((rem + kCols - 1) / kCols, (rem + kTile - 1) / kTile);
-      switch (prec) {
-        case 1: hipLaunchKernelGGL(chol_syrk_lp_kernel<GemmF32>, grid, dim3(256), 0, st, A, ld, k0, kw, (const int*)info); break;
-        case 2: hipLaunchKernelGGL(chol_syrk_lp_kernel<GemmBF16>, grid, dim3(256), 0, st, A, ld, k0, kw, (const int*)info); break;
-        case 3: hipLaunchKernelGGL(chol_syrk_lp_kernel<GemmBF16x3>, grid, dim3(256), 0, st, A, ld, k0, kw, (const int*)info); break;
-        default: return hipErrorInvalidValue;
-      }
-    }
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+  if (prec < 1 || prec > 3) return hipErrorInvalidValue;
+  SideStream* sd = ld > 2 * tile ? side_stream(kSideCholesky, st) : nullptr;
+  std::unique_lock<std::mutex> lock;
+  if (sd) lock = std::unique_lock<std::mutex>(sd->mu);
+  hipError_t e;
+  switch (prec) {
+    case 1: e = cholesky_lp<GemmF32>(ld, tile, A, info, st, sd); break;
+    case 2: e = cholesky_lp<GemmBF16>(ld, tile, A, info, st, sd); break;
+    default: e = cholesky_lp<GemmBF16x3>(ld, tile, A, info, st, sd); break;
   }
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(zero_upper_kernel, dim3(ld / 16, ld / 16), dim3(256), 0, st, A, ld);
   const long tot = (long)ld * ld;
   const dim3 cg((unsigned)((tot + 255) / 256));
@@ -573,12 +693,12 @@ hipError_t launch_batch_build(const BatchDesc* desc, int count, long total_tiles
 
 constexpr int kBatchTile = 128;
 
-__global__ __launch_bounds__(256) void batch_diag_kernel(const BatchDesc* __restrict__ desc,
-                                                         const int* __restrict__ order, double* factor,
-                                                         int k0, int j0, int* info) {
+__global__ __launch_bounds__(64) void batch_diag_kernel(const BatchDesc* __restrict__ desc,
+                                                        const int* __restrict__ order, double* factor, int j0,
+                                                        int* info) {
   const int p = order[blockIdx.x];
   const BatchDesc d = desc[p];
-  chol_diag_body(factor + d.factor_off, d.ld, k0, j0, kSub, info + p);
+  chol_diag_body(factor + d.factor_off, d.ld, j0, kSub, info + p);
 }
 
 // Compact grids for the batched steps: problems of equal padded size (ranks
@@ -614,7 +734,7 @@ __global__ __launch_bounds__(256) void batch_trsm_kernel(const BatchDesc* __rest
   group_item(g, blockIdx.x, rank, item);
   const int p = order[rank];
   const BatchDesc d = desc[p];
-  chol_panel_body<true>(factor + d.factor_off, d.ld, k0, j0, kSub, info + p, item);
+  chol_panel_body<true>(factor + d.factor_off, d.ld, k0, j0, kSub, k0 + kBatchTile, info + p, item);
 }
 
 __global__ __launch_bounds__(256) void batch_syrk_kernel(const BatchDesc* __restrict__ desc,
@@ -624,7 +744,10 @@ __global__ __launch_bounds__(256) void batch_syrk_kernel(const BatchDesc* __rest
   group_item(g, blockIdx.x, rank, item);
   const int p = order[rank];
   const BatchDesc d = desc[p];
-  chol_syrk_body<false>(factor + d.factor_off, d.ld, k0, kBatchTile, info + p, item);
+  long ti, tj;
+  tri_tile(item, ti, tj);
+  const long r0 = (long)k0 + kBatchTile;
+  chol_syrk_body<false>(factor + d.factor_off, d.ld, k0, kBatchTile, info + p, r0 + ti * kTile, r0 + tj * kTile, d.ld);
 }
 
 // Lower 128 x 64 tiles of the trailing matrix: row tile by holds 2 by + 2
@@ -641,7 +764,9 @@ __global__ __launch_bounds__(256) void batch_syrk_lp_kernel(const BatchDesc* __r
   while ((by + 1) * (by + 2) <= item) ++by;
   while (by * (by + 1) > item) --by;
   const int bx = item - by * (by + 1);
-  chol_syrk_lp_body<G>(factor + d.factor_off, d.ld, k0, kBatchTile, info + p, bx, by);
+  const long r0 = (long)k0 + kBatchTile;
+  chol_syrk_lp_body<G>(factor + d.factor_off, d.ld, k0, kBatchTile, info + p, r0 + (long)by * kTile,
+                       r0 + (long)bx * kCols, d.ld);
 }
 
 // Launches `launch(groups, total)` for the groups of ranks [0, cnt) with
@@ -680,7 +805,7 @@ hipError_t launch_batch_cholesky(int prec, const BatchDesc* desc, const int* ord
     int cnt = 0;
     while (cnt < count && ld_rank[cnt] > k0) ++cnt;
     for (int j0 = k0; j0 < k0 + kBatchTile; j0 += kSub) {
-      hipLaunchKernelGGL(batch_diag_kernel, dim3(cnt), dim3(256), 0, st, desc, order, factor, k0, j0, info);
+      hipLaunchKernelGGL(batch_diag_kernel, dim3(cnt), dim3(64), 0, st, desc, order, factor, j0, info);
       const hipError_t e = for_groups(
           ld_rank, cnt, [&](int ld) { return (ld - (j0 + kSub) + kTile - 1) / kTile; },
           [&](const BatchGroups& g, int total) {

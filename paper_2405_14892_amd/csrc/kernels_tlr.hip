@@ -424,7 +424,7 @@ __global__ __launch_bounds__(256) void tlr_trsm_rows_kernel(const double* __rest
 // WT_z = V'^T_jk (V'^T_ik)^T: r_jk x r_ik.  Grid (pairs, rs/128, rs/128):
 // the pair is the fastest grid index, so that the workgroups that have work
 // (mostly tile (0, 0)) are consecutive and spread over all XCDs.
-__global__ __launch_bounds__(256) void tlr_w_kernel(int j, int i0, int k0, int nk, int m, int rs,
+__global__ __launch_bounds__(256, 2) void tlr_w_kernel(int j, int i0, int k0, int nk, int m, int rs,
                                                     const double* __restrict__ Vt, const int* __restrict__ ranks,
                                                     double* __restrict__ WT, const int* __restrict__ info) {
   if (*info != 0) return;
@@ -441,7 +441,7 @@ __global__ __launch_bounds__(256) void tlr_w_kernel(int j, int i0, int k0, int n
 
 // T_z = U_ik W_ijk: m x r_jk (B operand WT_z, K = r_ik); columns r_jk up to
 // the next multiple of 16 are set to zero for the segmented K loop below.
-__global__ __launch_bounds__(256) void tlr_t_kernel(int j, int i0, int k0, int nk, int m, int rs,
+__global__ __launch_bounds__(256, 2) void tlr_t_kernel(int j, int i0, int k0, int nk, int m, int rs,
                                                     const double* __restrict__ U, const int* __restrict__ ranks,
                                                     const double* __restrict__ WT, double* __restrict__ T,
                                                     const int* __restrict__ info) {
@@ -465,7 +465,7 @@ __global__ __launch_bounds__(256) void tlr_t_kernel(int j, int i0, int k0, int n
 // tile (i0 + blockIdx.z, j) per workgroup, K running over the k segments
 // (each rounded up to 16; T_z and U_jk are zero past r_jk).  Of a diagonal
 // tile only the lower blocks are updated.
-__global__ __launch_bounds__(256) void tlr_u_kernel(int j, int i0, int k0, int nk, int m, int rs,
+__global__ __launch_bounds__(256, 2) void tlr_u_kernel(int j, int i0, int k0, int nk, int m, int rs,
                                                     double* __restrict__ tiles, const double* __restrict__ U,
                                                     const int* __restrict__ ranks, const double* __restrict__ T,
                                                     const int* __restrict__ info) {
@@ -540,6 +540,9 @@ hipError_t launch_tlr_build(int n, int m, int nt, const double* sigma, int lds, 
 hipError_t launch_tlr_cholesky(const TlrCholArgs& a, hipStream_t st) {
   const int m = a.m, nt = a.nt, rs = a.rs;
   const unsigned rt = (unsigned)((rs + kTile - 1) / kTile), mt = (unsigned)(m / kTile);
+  SideStream* sd = side_stream(kSideTlr, st);
+  std::unique_lock<std::mutex> lock;
+  if (sd) lock = std::unique_lock<std::mutex>(sd->mu);
   for (int j = 0; j < nt; ++j) {
     // updates of column j from the panels k < j, in launches of at most
     // kTlrPairBatch (i, k) pairs
@@ -562,15 +565,26 @@ hipError_t launch_tlr_cholesky(const TlrCholArgs& a, hipStream_t st) {
         }
       }
     }
+    // the dense factor of the diagonal tile; the cross approximation of the
+    // tiles below does not read it, so with a side stream the two overlap and
+    // join before the row solves
     double* Djj = a.tiles + (long)(j * (j + 1) / 2 + j) * m * m;
-    hipLaunchKernelGGL(tlr_info_copy_kernel, dim3(1), dim3(64), 0, st, (const int*)a.info, a.local_info);
-    hipError_t e = launch_cholesky_f64(m, 128, Djj, a.local_info, st);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(tlr_info_kernel, dim3(1), dim3(64), 0, st, a.info, (const int*)a.local_info, j * m);
     const int P = nt - j - 1;
+    const bool overlap = sd && P > 0;
+    hipStream_t ps = overlap ? sd->s : st;
+    if (overlap) {
+      hipEventRecord(sd->ev[0], st);
+      hipStreamWaitEvent(ps, sd->ev[0], 0);
+    }
+    hipLaunchKernelGGL(tlr_info_copy_kernel, dim3(1), dim3(64), 0, ps, (const int*)a.info, a.local_info);
+    hipError_t e = launch_cholesky_f64(m, 128, Djj, a.local_info, ps, false);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(tlr_info_kernel, dim3(1), dim3(64), 0, ps, a.info, (const int*)a.local_info, j * m);
+    if (overlap) hipEventRecord(sd->ev[1], ps);
     if (P > 0) {
       hipLaunchKernelGGL(tlr_aca_kernel, dim3(P), dim3(256), 0, st, (const double*)a.tiles, j, m, rs, a.rcap,
                          a.eps, a.U, a.Vt, a.ranks, (const int*)a.info);
+      if (overlap) hipStreamWaitEvent(st, sd->ev[1], 0);
       hipLaunchKernelGGL(tlr_trsm_rows_kernel, dim3(P, rs / 4), dim3(256), 0, st, (const double*)a.tiles, j, m, rs,
                          a.Vt, (const int*)a.ranks, (const int*)a.info);
     }

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 namespace mvn {
 
 // Lower triangle of the padded ld x ld matrix A (row-major) from the caller's
@@ -12,9 +14,25 @@ hipError_t launch_build_matrix(int n, int ld, const double* sigma, int lds, cons
                                double sigma2, double beta, double nu, double nugget, double* A,
                                int* info, hipStream_t st);
 
+// A second stream of the current device (default priority, non-blocking)
+// with three events, for work that overlaps the caller's stream inside one
+// library call.  Created on first use and kept until the process ends; each
+// slot is an independent set whose mutex serialises the callers enqueueing
+// on it.  nullptr (run everything on the caller's stream) if it cannot be
+// created, or if it does not exist yet and `st` is being captured.
+struct SideStream {
+  hipStream_t s = nullptr;
+  hipEvent_t ev[3] = {};
+  std::mutex mu;
+};
+constexpr int kSideCholesky = 0, kSideTlr = 1, kSideSlots = 2;
+SideStream* side_stream(int slot, hipStream_t st);
+
 // In-place right-looking tiled Cholesky of the padded matrix; *info gets the
 // 1-based index of the first non-positive pivot.  Upper triangle zeroed.
-hipError_t launch_cholesky_f64(int ld, int tile, double* A, int* info, hipStream_t st);
+// With `lookahead`, the trailing updates off the next tile column run on a
+// side stream concurrently with that column's panel factorisation.
+hipError_t launch_cholesky_f64(int ld, int tile, double* A, int* info, hipStream_t st, bool lookahead = true);
 
 // The same factorisation with the trailing updates in FP32 (prec 1), BF16
 // (2) or split BF16 (3) on MFMA, followed by the low-precision operand copy
