@@ -72,18 +72,13 @@ __device__ __forceinline__ double lane_bcast(double v, int l) {
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-__device__ __forceinline__ void chol_diag_body(double* __restrict__ A, int ld, int j0, int jw,
-                                               int* __restrict__ info) {
-  if (*info != 0) return;
+// Crout factorisation of the block whose lower rows lane r < jw holds in x
+// (rows and columns past jw must be those of the identity, so that all 32
+// columns run: no early exit keeps the row in registers).  Returns the
+// 1-based index in the block of the first column whose pivot is not
+// positive, or 0.
+__device__ __forceinline__ int crout32(double (&x)[kSub], int jw) {
   const int r = threadIdx.x & 63;
-  const bool live = r < jw;
-  // rows and columns past jw are those of the identity, so all 32 columns
-  // run (no early exit keeps the row in registers); the first column whose
-  // pivot is not positive is the failure
-  double x[kSub];
-#pragma unroll
-  for (int c = 0; c < kSub; ++c)
-    x[c] = (live && c <= r) ? A[(long)(j0 + r) * ld + j0 + c] : (c == r ? 1.0 : 0.0);
   int fail = 0;
 #pragma unroll
   for (int c = 0; c < kSub; ++c) {
@@ -91,10 +86,24 @@ __device__ __forceinline__ void chol_diag_body(double* __restrict__ A, int ld, i
 #pragma unroll
     for (int k = 0; k < c; ++k) s -= x[k] * lane_bcast(x[k], c);
     const double piv = lane_bcast(s, c);  // uniform across the wave
-    if (fail == 0 && c < jw && !(piv > 0.0)) fail = j0 + c + 1;
+    if (fail == 0 && c < jw && !(piv > 0.0)) fail = c + 1;
     const double d = sqrt(piv);
     x[c] = r == c ? d : (r > c ? s / d : 0.0);
   }
+  return fail;
+}
+
+__device__ __forceinline__ void chol_diag_body(double* __restrict__ A, int ld, int j0, int jw,
+                                               int* __restrict__ info) {
+  if (*info != 0) return;
+  const int r = threadIdx.x & 63;
+  const bool live = r < jw;
+  double x[kSub];
+#pragma unroll
+  for (int c = 0; c < kSub; ++c)
+    x[c] = (live && c <= r) ? A[(long)(j0 + r) * ld + j0 + c] : (c == r ? 1.0 : 0.0);
+  int fail = crout32(x, jw);
+  if (fail) fail += j0;
   if (fail) {
     if (r == 0) atomicCAS(info, 0, fail);
     return;
@@ -120,8 +129,10 @@ __global__ __launch_bounds__(64) void chol_diag_kernel(double* __restrict__ A, i
 // Afterwards the finished columns update the diagonal blocks of the later
 // sub-panels of the tile column (rows and columns [q0, q0 + 32), q0 < kend)
 // that lie in this workgroup's rows, D_q -= X_q X_q^T, one wave per block on
-// FP64 MFMA; each diagonal block thus holds all its updates when it is
-// factored.
+// FP64 MFMA.  The block right after this sub-panel then holds all its
+// updates, and the wave that updated it (wave 0 of row block 0) also factors
+// it, so only the first diagonal block of a tile column needs a launch of
+// its own.
 // FULL: jw == 32 (every sub-panel except the last of a tile whose width is
 // not a multiple of 32, which has no later diagonal block); the constant
 // bound keeps the substitution in registers.
@@ -129,7 +140,7 @@ constexpr int kPanelK = 32;  // k per LDS stage of the panel update
 
 template <bool FULL>
 __device__ __forceinline__ void chol_panel_body(double* __restrict__ A, int ld, int k0, int j0, int jw_arg,
-                                                int kend, const int* __restrict__ info, int rblock) {
+                                                int kend, int* __restrict__ info, int rblock) {
   if (*info != 0) return;
   const int jw = FULL ? kSub : jw_arg;
   constexpr int kALd = kTile + 1, kBLd = kSub + 1;
@@ -253,13 +264,41 @@ __device__ __forceinline__ void chol_panel_body(double* __restrict__ A, int ld, 
         dq[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, a0, dq[1], 0, 0, 0);
         dq[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, a1, dq[2], 0, 0, 0);
       }
+      if (rblock == 0 && w == 0) {
+        // the next diagonal block: updated rows to LDS (D is free after the
+        // substitution), one row per lane, factored in registers
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
 #pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        const int ib = i > 0, jb = i > 1;
+        for (int i = 0; i < 3; ++i) {
+          const int ib = i > 0, jb = i > 1;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = ib * 16 + (lane >> 4) + 4 * r, col = jb * 16 + (lane & 15);
-          if (row < hq && col <= row) A[(q0 + row) * ld + q0 + col] -= dq[i][r];
+          for (int r = 0; r < 4; ++r) {
+            const int row = ib * 16 + (lane >> 4) + 4 * r, col = jb * 16 + (lane & 15);
+            if (row < hq && col <= row) D[row][col] = A[(q0 + row) * ld + q0 + col] - dq[i][r];
+          }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        const int rr = lane;
+        double x[kSub];
+#pragma unroll
+        for (int c = 0; c < kSub; ++c) x[c] = (rr < hq && c <= rr) ? D[rr & 31][c] : (c == rr ? 1.0 : 0.0);
+        const int fail = crout32(x, hq);
+        if (fail) {
+          if (lane == 0) atomicCAS(info, 0, (int)q0 + fail);
+        } else if (rr < hq) {
+#pragma unroll
+          for (int c = 0; c < kSub; ++c)
+            if (c <= rr) A[(q0 + rr) * ld + q0 + c] = x[c];
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          const int ib = i > 0, jb = i > 1;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = ib * 16 + (lane >> 4) + 4 * r, col = jb * 16 + (lane & 15);
+            if (row < hq && col <= row) A[(q0 + row) * ld + q0 + col] -= dq[i][r];
+          }
         }
       }
     }
@@ -268,11 +307,61 @@ __device__ __forceinline__ void chol_panel_body(double* __restrict__ A, int ld, 
 
 template <bool FULL>
 __global__ __launch_bounds__(256) void chol_panel_kernel(double* __restrict__ A, int ld, int k0, int j0, int jw,
-                                                         int kend, const int* __restrict__ info) {
+                                                         int kend, int* __restrict__ info) {
   chol_panel_body<FULL>(A, ld, k0, j0, jw, kend, info, blockIdx.x);
 }
 
 // ------------------------------------------------------------ trailing update
+// K stages of 8, double-buffered in LDS (2 x 2 x 8 x 129 doubles = 33 KB, so
+// that a panel solve still fits on a CU beside two of these workgroups),
+// global loads issued two stages ahead of their use.
+constexpr int kSyrkK = 8;
+constexpr int kSyrkStage = kSyrkK * kLdsLd;  // doubles, one operand
+
+// Lane t: 4 consecutive k of row t / 2 (zero past ld or klim with MASK).
+template <bool MASK>
+__device__ __forceinline__ void syrk_load(const double* __restrict__ A, long ld, long row0, long k0, long klim,
+                                          double (&r)[4]) {
+  const int t = threadIdx.x;
+  const long row = row0 + (t >> 1), kb = k0 + (t & 1) * 4;
+  const double* p = A + row * ld + kb;
+  if (!MASK) {
+    const double2 v0 = reinterpret_cast<const double2*>(p)[0], v1 = reinterpret_cast<const double2*>(p)[1];
+    r[0] = v0.x;
+    r[1] = v0.y;
+    r[2] = v1.x;
+    r[3] = v1.y;
+  } else {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) r[q] = (row < ld && kb + q < klim) ? p[q] : 0.0;
+  }
+}
+
+__device__ __forceinline__ void syrk_store(double* __restrict__ lds, const double (&r)[4]) {
+  const int t = threadIdx.x, row = t >> 1, kb = (t & 1) * 4;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) lds[(kb + q) * kLdsLd + row] = r[q];
+}
+
+__device__ __forceinline__ void syrk_mma(const double* __restrict__ As, const double* __restrict__ Bs, Acc& acc) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wr = w >> 1, wc = w & 1;
+#pragma unroll
+  for (int kk = 0; kk < kSyrkK / 4; ++kk) {
+    const int krow = (kk * 4 + (lane >> 4)) * kLdsLd;
+    double a[4], b[4];
+#pragma unroll
+    for (int ib = 0; ib < 4; ++ib) a[ib] = As[krow + wr * 64 + ib * 16 + (lane & 15)];
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb) b[jb] = Bs[krow + wc * 64 + jb * 16 + (lane & 15)];
+#pragma unroll
+    for (int ib = 0; ib < 4; ++ib)
+#pragma unroll
+      for (int jb = 0; jb < 4; ++jb)
+        acc.v[ib][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ib], b[jb], acc.v[ib][jb], 0, 0, 0);
+  }
+}
+
 // One 128 x 128 lower tile of C = A[rowA:, rowB:] -= P P^T with
 // P = A[:, k0:k0+kw]; only elements with column < clim and column <= row
 // are written.
@@ -280,29 +369,45 @@ template <bool MASK>
 __device__ __forceinline__ void chol_syrk_body(double* __restrict__ A, int ld, int k0, int kw,
                                                const int* __restrict__ info, long rowA, long rowB, long clim) {
   if (*info != 0) return;
-  __shared__ double lds[2 * 2 * kStageDoubles];
+  __shared__ double lds[2 * 2 * kSyrkStage];
   Acc acc;
   acc_zero(acc);
-  const int nst = (kw + kStageK - 1) / kStageK;
-  double ra[8], rb[8];
-  load_rows<MASK>(A, ld, rowA, k0, ld, (long)k0 + kw, ra);
-  load_rows<MASK>(A, ld, rowB, k0, ld, (long)k0 + kw, rb);
-  store_rows(lds, ra);
-  store_rows(lds + kStageDoubles, rb);
+  const long klim = (long)k0 + kw;
+  const int nst = (kw + kSyrkK - 1) / kSyrkK;
+  // stage s lives in register set s & 1 until it is stored to LDS buffer s & 1
+  double ra0[4], rb0[4], ra1[4], rb1[4];
+  syrk_load<MASK>(A, ld, rowA, k0, klim, ra0);
+  syrk_load<MASK>(A, ld, rowB, k0, klim, rb0);
+  if (nst > 1) {
+    syrk_load<MASK>(A, ld, rowA, (long)k0 + kSyrkK, klim, ra1);
+    syrk_load<MASK>(A, ld, rowB, (long)k0 + kSyrkK, klim, rb1);
+  }
+  syrk_store(lds, ra0);
+  syrk_store(lds + kSyrkStage, rb0);
+  if (nst > 2) {
+    syrk_load<MASK>(A, ld, rowA, (long)k0 + 2 * kSyrkK, klim, ra0);
+    syrk_load<MASK>(A, ld, rowB, (long)k0 + 2 * kSyrkK, klim, rb0);
+  }
   __syncthreads();
-  for (int s = 0; s < nst; ++s) {
-    double* cur = lds + (s & 1) * 2 * kStageDoubles;
-    double* nxt = lds + ((s + 1) & 1) * 2 * kStageDoubles;
+  // step s: MFMAs of stage s, then stage s + 1 (register set (s + 1) & 1) to
+  // the other LDS buffer and stage s + 3 loaded into the set just freed
+  auto step = [&](int s, double (&ra)[4], double (&rb)[4]) {
+    const double* cur = lds + (s & 1) * 2 * kSyrkStage;
+    double* nxt = lds + ((s + 1) & 1) * 2 * kSyrkStage;
+    syrk_mma(cur, cur + kSyrkStage, acc);
     if (s + 1 < nst) {
-      load_rows<MASK>(A, ld, rowA, (long)k0 + (s + 1) * kStageK, ld, (long)k0 + kw, ra);
-      load_rows<MASK>(A, ld, rowB, (long)k0 + (s + 1) * kStageK, ld, (long)k0 + kw, rb);
-    }
-    mma_stage(cur, cur + kStageDoubles, acc);
-    if (s + 1 < nst) {
-      store_rows(nxt, ra);
-      store_rows(nxt + kStageDoubles, rb);
+      syrk_store(nxt, ra);
+      syrk_store(nxt + kSyrkStage, rb);
+      if (s + 3 < nst) {
+        syrk_load<MASK>(A, ld, rowA, (long)k0 + (long)(s + 3) * kSyrkK, klim, ra);
+        syrk_load<MASK>(A, ld, rowB, (long)k0 + (long)(s + 3) * kSyrkK, klim, rb);
+      }
     }
     __syncthreads();
+  };
+  for (int s = 0; s < nst; s += 2) {
+    step(s, ra1, rb1);
+    if (s + 1 < nst) step(s + 1, ra0, rb0);
   }
 #pragma unroll
   for (int ib = 0; ib < 4; ++ib)
@@ -324,7 +429,7 @@ __device__ __forceinline__ void tri_tile(long b, long& ti, long& tj) {
 }
 
 // The lower triangle of tiles of A[r0:, r0:].  MASK = false when every
-// 128 x 16 operand tile lies inside the matrix: the tile width is a multiple
+// 128 x 8 operand tile lies inside the matrix: the tile width is a multiple
 // of 128 (so are ld, r0, k0 + kw and kw).
 template <bool MASK>
 __global__ __launch_bounds__(256, 2) void chol_syrk_kernel(double* __restrict__ A, int ld, int k0, int kw, int r0,
@@ -374,20 +479,21 @@ SideStream* side_stream(int slot, hipStream_t st) {
   return sd;
 }
 
-// The sub-panel chain of tile column [k0, k0 + kw): factor each 32 x 32
-// diagonal block, then solve (and update) the rows below it.
+// The sub-panel chain of tile column [k0, k0 + kw): factor its first 32 x 32
+// diagonal block, then per sub-panel solve (and update) the rows below it;
+// each panel solve also factors the next diagonal block.
 static void chol_column(int ld, int k0, int kw, double* A, int* info, hipStream_t st) {
   const int kend = k0 + kw;
+  hipLaunchKernelGGL(chol_diag_kernel, dim3(1), dim3(64), 0, st, A, ld, k0, min(kSub, kw), info);
   for (int j0 = k0; j0 < kend; j0 += kSub) {
     const int jw = min(kSub, kend - j0);
-    hipLaunchKernelGGL(chol_diag_kernel, dim3(1), dim3(64), 0, st, A, ld, j0, jw, info);
-    const int rows = ld - (j0 + jw);
+    const int rows = ld - (j0 + jw);  // zero only for the last sub-panel of the matrix
     if (rows > 0) {
       const dim3 pg((rows + kTile - 1) / kTile);
       if (jw == kSub)
-        hipLaunchKernelGGL(chol_panel_kernel<true>, pg, dim3(256), 0, st, A, ld, k0, j0, jw, kend, (const int*)info);
+        hipLaunchKernelGGL(chol_panel_kernel<true>, pg, dim3(256), 0, st, A, ld, k0, j0, jw, kend, info);
       else
-        hipLaunchKernelGGL(chol_panel_kernel<false>, pg, dim3(256), 0, st, A, ld, k0, j0, jw, kend, (const int*)info);
+        hipLaunchKernelGGL(chol_panel_kernel<false>, pg, dim3(256), 0, st, A, ld, k0, j0, jw, kend, info);
     }
   }
 }
@@ -729,7 +835,7 @@ __device__ __forceinline__ void group_item(const BatchGroups& g, int b, int& ran
 
 __global__ __launch_bounds__(256) void batch_trsm_kernel(const BatchDesc* __restrict__ desc,
                                                          const int* __restrict__ order, double* factor,
-                                                         int k0, int j0, const int* info, BatchGroups g) {
+                                                         int k0, int j0, int* info, BatchGroups g) {
   int rank, item;
   group_item(g, blockIdx.x, rank, item);
   const int p = order[rank];
@@ -805,12 +911,13 @@ hipError_t launch_batch_cholesky(int prec, const BatchDesc* desc, const int* ord
     int cnt = 0;
     while (cnt < count && ld_rank[cnt] > k0) ++cnt;
     for (int j0 = k0; j0 < k0 + kBatchTile; j0 += kSub) {
-      hipLaunchKernelGGL(batch_diag_kernel, dim3(cnt), dim3(64), 0, st, desc, order, factor, j0, info);
+      if (j0 == k0)
+        hipLaunchKernelGGL(batch_diag_kernel, dim3(cnt), dim3(64), 0, st, desc, order, factor, j0, info);
       const hipError_t e = for_groups(
           ld_rank, cnt, [&](int ld) { return (ld - (j0 + kSub) + kTile - 1) / kTile; },
           [&](const BatchGroups& g, int total) {
-            hipLaunchKernelGGL(batch_trsm_kernel, dim3(total), dim3(256), 0, st, desc, order, factor, k0, j0,
-                               (const int*)info, g);
+            hipLaunchKernelGGL(batch_trsm_kernel, dim3(total), dim3(256), 0, st, desc, order, factor, k0, j0, info,
+                               g);
           });
       if (e != hipSuccess) return e;
     }
