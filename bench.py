@@ -110,10 +110,12 @@ class Problem:
         self.mu = f64(w.mu) if w.mu is not None else None
         self.fb = mvn.mvn_factor_bytes(n, opts)
         self.cwb = mvn.mvn_cholesky_workspace_bytes(n, opts)
-        self.wsb = mvn.mvn_prob_workspace_bytes(n, N, S, opts)
+        self.tlr = opts.tlr_eps > 0
+        # a TLR workspace is sized for the factor's ranks, after the first factorisation
+        self.wsb = 0 if self.tlr else mvn.mvn_prob_workspace_bytes(n, N, S, opts)
         self.fbuf = torch.empty(self.fb, dtype=torch.uint8, device=dev)
         self.cws = torch.empty(max(self.cwb, 1), dtype=torch.uint8, device=dev)
-        self.ws = torch.empty(self.wsb, dtype=torch.uint8, device=dev)
+        self.ws = None if self.tlr else torch.empty(self.wsb, dtype=torch.uint8, device=dev)
         self.out = torch.empty(4 + S, dtype=torch.float64, device=dev)
         self.fac = _lib.MvnFactor()
         self.stream = torch.cuda.current_stream(dev)
@@ -132,6 +134,12 @@ class Problem:
                                            ctypes.byref(self.opts), P(self.fbuf), self.fb, P(self.cws), self.cwb,
                                            ctypes.byref(self.fac), self.sp))
         e[1].record(self.stream)
+        if self.ws is None:
+            out = ctypes.c_size_t(0)
+            self.lib.check(self.h.mvn_prob_workspace_bytes_factor(ctypes.byref(self.fac), w.N, w.S,
+                                                                  ctypes.byref(self.opts), ctypes.byref(out), self.sp))
+            self.wsb = out.value
+            self.ws = torch.empty(self.wsb, dtype=torch.uint8, device=self.dev)
         self.lib.check(self.h.mvn_prob(ctypes.byref(self.fac), P(self.a), P(self.b), P(self.mu), w.N, w.S,
                                        ctypes.c_uint64(w.seed), ctypes.byref(self.opts), P(self.ws), self.wsb,
                                        P(self.out), None, self.sp))

@@ -108,7 +108,15 @@ typedef struct mvn_factor {
   int reserved1;
 } mvn_factor;
 
-/* Sizes.  All return 0 on success and write the byte count. */
+/* Sizes.  All return 0 on success and write the byte count.
+ * mvn_prob_workspace_bytes with TLR options (tlr_eps > 0) returns a size
+ * that holds any factor built with those options (every tile at the rank
+ * stride), usually far more than needed; mvn_prob_workspace_bytes_factor
+ * returns the size for a given factor: for a TLR factor it reads the ranks
+ * back, which synchronises `stream` (the stream the factor was built on);
+ * for a dense factor it equals mvn_prob_workspace_bytes(f->n, ...) and does
+ * not touch the device.  With a smaller TLR workspace mvn_prob runs as many
+ * persistent sweep workgroups as fit (slower, same result). */
 int mvn_factor_bytes(int n, const mvn_options* opts, size_t* bytes);
 int mvn_cholesky_workspace_bytes(int n, const mvn_options* opts, size_t* bytes);
 int mvn_prob_workspace_bytes(int n, int N, int S, const mvn_options* opts, size_t* bytes);
@@ -149,8 +157,14 @@ int mvn_cholesky(int n, const double* d_sigma, int ld_sigma, const double* d_loc
  * opts->precision selects the arithmetic of the limit-update GEMM: MVN_FP64
  * always, or the precision the factor was built with.  For a TLR factor
  * (FP64 only) the update of tile-row i is sum_j U_ij (Vt_ij Y_j) plus the
- * dense diagonal tile; the workspace query must then be given options with
- * the factor's tile, max_rank and tlr_eps > 0.
+ * dense diagonal tile: once the samples of tile j are known, Vt_ij Y_j is
+ * formed for all i > j in one stacked product, and the update of tile-row i
+ * is one product with the ranks packed along K.  The call reads the ranks
+ * back and copies its index tables to the workspace, synchronising `stream`
+ * twice (it cannot be captured in a graph); the workspace size comes from
+ * mvn_prob_workspace_bytes_factor (or the TLR bound of
+ * mvn_prob_workspace_bytes), and too small a workspace to hold one sweep
+ * workgroup is an error.
  * The QMC point of sample (s, j) in dimension i is
  *   w = ((j*A_i + D_{s,i} mod 2^64) >> 11 + 1/2) 2^-53 with
  *   A_i = floor(frac(sqrt(p_{i+1})) 2^64) (p_k the k-th prime) and
@@ -158,6 +172,9 @@ int mvn_cholesky(int n, const double* d_sigma, int ld_sigma, const double* d_loc
 int mvn_prob(const mvn_factor* f, const double* d_a, const double* d_b, const double* d_mu,
              int N, int S, uint64_t seed, const mvn_options* opts,
              void* ws, size_t ws_bytes, double* d_out, double* d_ell, hipStream_t stream);
+
+int mvn_prob_workspace_bytes_factor(const mvn_factor* f, int N, int S, const mvn_options* opts,
+                                    size_t* bytes, hipStream_t stream);
 
 /* Gradient of log P-hat at fixed QMC points (the same estimator and points
  * as mvn_prob): reverse-mode differentiation of the recurrence of Eq. (sov1),

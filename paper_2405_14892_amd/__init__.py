@@ -15,7 +15,8 @@ from . import _lib
 from ._lib import (MVN_BF16, MVN_BF16X3, MVN_FACTOR_TLR, MVN_FP32, MVN_FP64, MvnError,  # noqa: F401
                    MvnFactor, MvnMatern, MvnOptions, options)
 
-__all__ = ["mvn_factor_bytes", "mvn_cholesky_workspace_bytes", "mvn_prob_workspace_bytes", "mvn_cholesky", "mvn_prob", "Factor",
+__all__ = ["mvn_factor_bytes", "mvn_cholesky_workspace_bytes", "mvn_prob_workspace_bytes",
+           "mvn_prob_workspace_bytes_factor", "mvn_cholesky", "mvn_prob", "Factor",
            "mvn_prob_grad_workspace_bytes", "mvn_prob_grad", "MVNLogProb", "BatchPlan",
            "mvn_batch_plan", "mvn_prob_batch",
            "options", "MvnError", "MVN_FP64", "MVN_FP32", "MVN_BF16", "MVN_BF16X3", "library_path"]
@@ -61,6 +62,15 @@ def mvn_prob_workspace_bytes(n: int, N: int, S: int, opts: MvnOptions | None = N
     out = ctypes.c_size_t(0)
     _lib.check(_lib.lib().mvn_prob_workspace_bytes(n, N, S, ctypes.byref(opts or options()),
                                                    ctypes.byref(out)))
+    return out.value
+
+
+def mvn_prob_workspace_bytes_factor(f: "Factor", N: int, S: int, opts: MvnOptions | None = None) -> int:
+    """Workspace of mvn_prob for this factor (for a TLR factor the ranks are
+    read back, which synchronises the current stream)."""
+    out = ctypes.c_size_t(0)
+    _lib.check(_lib.lib().mvn_prob_workspace_bytes_factor(ctypes.byref(f.handle), N, S, ctypes.byref(opts or options()),
+                                                          ctypes.byref(out), _stream(f.device)))
     return out.value
 
 
@@ -166,7 +176,7 @@ def mvn_prob(f: Factor, a, b, mu=None, N: int = 1000, S: int = 10, seed: int = 1
     dev = f.device
     ta, tb = _dev_f64(a, dev), _dev_f64(b, dev)
     tm = _dev_f64(mu, dev) if mu is not None else None
-    wsb = mvn_prob_workspace_bytes(f.n, N, S, opts)
+    wsb = mvn_prob_workspace_bytes_factor(f, N, S, opts) if f.is_tlr else mvn_prob_workspace_bytes(f.n, N, S, opts)
     if workspace is None or workspace.numel() < wsb:
         workspace = torch.empty(wsb, dtype=torch.uint8, device=dev)
     out = torch.empty(4 + S, dtype=torch.float64, device=dev)

@@ -172,7 +172,7 @@ def tune_tlr(n: int, locs, kern: tuple, a, b, mu=None, N: int = 1000, S: int = 1
     candidate (the tile changes both).
 
     Returns {"tile", "total_s": {tile: s}, "key"}."""
-    from . import mvn_cholesky, mvn_prob, mvn_prob_workspace_bytes
+    from . import mvn_cholesky, mvn_prob, mvn_prob_workspace_bytes_factor
     timer = timer or event_timer
     tiles = [t for t in tiles if t % 128 == 0 and t <= 1024 and max_rank <= min(256, t)]
     key = f"tlr:{_device_name()}:n={n}:N={N}:S={S}:eps={tlr_eps:g}:rank={max_rank}:tiles={tiles}"
@@ -186,9 +186,9 @@ def tune_tlr(n: int, locs, kern: tuple, a, b, mu=None, N: int = 1000, S: int = 1
         state = {}
 
         def run(o=o, state=state):
-            if "ws" not in state:
-                state["ws"] = _workspace(mvn_prob_workspace_bytes(n, N, S, o), device)
             f = mvn_cholesky(n, locs=locs, kern=kern, opts=o, device=device)
+            if "ws" not in state:  # sized for the ranks of the first (untimed) factorisation
+                state["ws"] = _workspace(mvn_prob_workspace_bytes_factor(f, N, S, o), device)
             return mvn_prob(f, a, b, mu, N=N, S=S, seed=seed, opts=o, workspace=state["ws"])
 
         times[str(t)] = timer(run, reps)

@@ -13,6 +13,7 @@
 
 #include "../../include/mvn.h"
 #include "launch.h"
+#include "tlr_tables.h"
 
 namespace {
 
@@ -188,7 +189,56 @@ int tlr_opts_check(const mvn_options* o) {
 
 bool is_tlr(const mvn_options* o) { return o && o->tlr_eps > 0; }
 
-long tlr_zslice(const TlrGeom& G) { return (long)(G.nt > 1 ? G.nt - 1 : 1) * G.rs * mvn::sweep_tile_cols(); }
+// Workspace of a TLR probability call: the common part of prob_layout_ld (up
+// to the invalid-limit flag), the sweep's index tables (tlr_tables.h) and
+// packed operands, then per persistent workgroup its Y slice (ld x 64) and Z
+// slice (kpad x 64).  ksum = sum of the ranks, kpad = packed K of all
+// tile-rows.  avail > 0: as many workgroups as fit in avail bytes (grid 0
+// when not even one does); avail == 0: the full grid.
+struct TlrProbLayout {
+  ProbLayout base;
+  size_t zcol, kpad0, kval, vrow0, ucol0, kk, zdst, vpack, upack, fixed, yscr, zscr, total;
+  long yslice, zslice;
+  int grid;
+};
+
+TlrProbLayout tlr_prob_layout(int ld, int m, int nt, int N, int S, long ksum, long kpad, size_t avail) {
+  TlrProbLayout L{};
+  L.base = prob_layout_ld(ld, N, S, MVN_FP64, 0, 128);
+  const size_t np = (size_t)nt * (nt - 1) / 2;
+  size_t off = L.base.yscr;
+  L.zcol = off; off = align_up(off + sizeof(long) * (nt + 1));
+  L.kpad0 = off; off = align_up(off + sizeof(long) * (nt + 1));
+  L.kval = off; off = align_up(off + sizeof(int) * nt);
+  L.vrow0 = off; off = align_up(off + sizeof(long) * (np > 0 ? np : 1));
+  L.ucol0 = off; off = align_up(off + sizeof(long) * (np > 0 ? np : 1));
+  L.kk = off; off = align_up(off + sizeof(int) * (np > 0 ? np : 1));
+  L.zdst = off; off = align_up(off + sizeof(long) * (size_t)(ksum > 0 ? ksum : 1));
+  L.vpack = off; off = align_up(off + sizeof(double) * (size_t)(ksum + 128) * m);
+  L.upack = off; off = align_up(off + sizeof(double) * (size_t)m * (size_t)(kpad > 0 ? kpad : 1));
+  L.fixed = off;
+  L.yslice = (long)ld * mvn::sweep_tile_cols();
+  L.zslice = (kpad > 0 ? kpad : 1) * (long)mvn::sweep_tile_cols();
+  const size_t per = align_up(sizeof(double) * (size_t)L.yslice) + align_up(sizeof(double) * (size_t)L.zslice);
+  long g = L.base.grid;
+  if (avail > 0) g = avail < L.fixed ? 0 : std::min<long>(g, (long)((avail - L.fixed) / per));
+  L.grid = (int)g;
+  L.yscr = L.fixed;
+  L.zscr = align_up(L.yscr + sizeof(double) * (size_t)L.grid * (size_t)L.yslice);
+  L.total = align_up(L.zscr + sizeof(double) * (size_t)L.grid * (size_t)L.zslice);
+  return L;
+}
+
+// Ranks of a TLR factor, read back with a synchronisation of `stream`.
+hipError_t tlr_read_ranks(const mvn_factor* f, std::vector<int>& r, hipStream_t stream) {
+  const int nt = f->ld / f->tile;
+  const long np = (long)nt * (nt - 1) / 2;
+  r.assign(np > 0 ? np : 1, 0);
+  if (np == 0) return hipSuccess;
+  hipError_t e = hipMemcpyAsync(r.data(), f->ranks, sizeof(int) * np, hipMemcpyDeviceToHost, stream);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(stream);
+}
 
 struct GradLayout {
   size_t at, bt, lat, ell, part, bad, yscr, sfw, sbar, gpart, mz, scale, total;
@@ -335,13 +385,32 @@ int mvn_prob_workspace_bytes(int n, int N, int S, const mvn_options* opts, size_
   const int prec = opts ? opts->precision : MVN_FP64;
   if (!prec_ok(prec)) return fail(-4, "unknown precision %d", prec);
   if (is_tlr(opts)) {
+    // every tile at the rank stride: enough for any factor with these options
     if (tlr_opts_check(opts)) return -4;
     const TlrGeom G = tlr_geom(n, opts->tile, opts->max_rank);
-    *bytes = prob_layout_ld(G.ld, N, S, MVN_FP64, tlr_zslice(G), 128).total;
+    const long kmax = G.npanels * G.rs;
+    *bytes = tlr_prob_layout(G.ld, G.m, G.nt, N, S, kmax, kmax, 0).total;
     return 0;
   }
   if (!sweep_rows_ok(opts)) return fail(-4, "sweep_rows must be 0, 64 or 128 (got %d)", opts->sweep_rows);
   *bytes = prob_layout(n, N, S, prec, sweep_rows(opts)).total;
+  return 0;
+}
+
+int mvn_prob_workspace_bytes_factor(const mvn_factor* f, int N, int S, const mvn_options* opts, size_t* bytes,
+                                    hipStream_t stream) {
+  if (!f || !f->L || f->n < 1) return fail(-1, "invalid factor handle");
+  if (!(f->flags & MVN_FACTOR_TLR)) return mvn_prob_workspace_bytes(f->n, N, S, opts, bytes);
+  if (N < 1) return fail(-2, "N must be >= 1 (got %d)", N);
+  if (S < 1) return fail(-3, "S must be >= 1 (got %d)", S);
+  if (!bytes) return fail(-5, "bytes is NULL");
+  if (!f->ranks || f->tile < 128 || f->ld % f->tile != 0) return fail(-1, "invalid factor handle");
+  std::vector<int> ranks;
+  const hipError_t e = tlr_read_ranks(f, ranks, stream);
+  if (e != hipSuccess) return hip_fail(e, "rank read-back");
+  const int nt = f->ld / f->tile;
+  const mvn::TlrTables T = mvn::build_tlr_tables(nt, f->rank_stride, ranks.data());
+  *bytes = tlr_prob_layout(f->ld, f->tile, nt, N, S, T.ksum, T.kpad0[nt], 0).total;
   return 0;
 }
 
@@ -475,33 +544,75 @@ int mvn_prob(const mvn_factor* f, const double* d_a, const double* d_b, const do
   if (!prec_ok(prec)) return fail(-8, "unknown precision %d", prec);
   if (tlr) {
     if (prec != MVN_FP64) return fail(-8, "the TLR sweep is FP64");
-    const int n = f->n, m = f->tile, nt = f->ld / f->tile, rs = f->rank_stride;
-    const long zs = (long)(nt > 1 ? nt - 1 : 1) * rs * mvn::sweep_tile_cols();
-    const ProbLayout Lay = prob_layout_ld(f->ld, N, S, MVN_FP64, zs, 128);
     if (!ws) return fail(-9, "workspace is NULL");
-    if (ws_bytes < Lay.total) return fail(-10, "workspace too small: %zu < %zu", ws_bytes, Lay.total);
     if (!d_out) return fail(-11, "output is NULL");
+    const int n = f->n, m = f->tile, nt = f->ld / f->tile, rs = f->rank_stride;
+    const int np = nt * (nt - 1) / 2;
+    std::vector<int> ranks;
+    hipError_t e = tlr_read_ranks(f, ranks, stream);
+    if (e != hipSuccess) return hip_fail(e, "rank read-back");
+    const mvn::TlrTables T = mvn::build_tlr_tables(nt, rs, ranks.data());
+    const TlrProbLayout Lay = tlr_prob_layout(f->ld, m, nt, N, S, T.ksum, T.kpad0[nt], ws_bytes);
+    if (Lay.grid < 1) {
+      const size_t full = tlr_prob_layout(f->ld, m, nt, N, S, T.ksum, T.kpad0[nt], 0).total;
+      return fail(-10, "workspace too small: %zu bytes hold no sweep workgroup (%zu for the full grid)", ws_bytes,
+                  full);
+    }
     const uint64_t* lat = lattice_table(n);
     if (!lat) return fail(-1, "could not build the lattice table for n = %d", n);
     char* w = (char*)ws;
-    double* at = (double*)(w + Lay.at);
-    double* bt = (double*)(w + Lay.bt);
-    uint64_t* dlat = (uint64_t*)(w + Lay.lat);
-    double* ell = d_ell ? d_ell : (double*)(w + Lay.ell);
-    double* part = (double*)(w + Lay.part);
-    int* bad = (int*)(w + Lay.bad);
-    hipError_t e = hipMemcpyAsync(dlat, lat, sizeof(uint64_t) * n, hipMemcpyHostToDevice, stream);
+    // index tables: one host image of the workspace range [zcol, vpack)
+    std::vector<char> img(Lay.vpack - Lay.zcol, 0);
+    auto put = [&](size_t off, const void* src, size_t bytes) {
+      if (bytes) memcpy(img.data() + (off - Lay.zcol), src, bytes);
+    };
+    put(Lay.zcol, T.zcol.data(), sizeof(long) * (nt + 1));
+    put(Lay.kpad0, T.kpad0.data(), sizeof(long) * (nt + 1));
+    put(Lay.kval, T.kval.data(), sizeof(int) * nt);
+    put(Lay.vrow0, T.vrow0.data(), sizeof(long) * np);
+    put(Lay.ucol0, T.ucol0.data(), sizeof(long) * np);
+    put(Lay.kk, T.k.data(), sizeof(int) * np);
+    put(Lay.zdst, T.zdst.data(), sizeof(long) * (size_t)T.ksum);
+    e = hipMemcpyAsync(w + Lay.zcol, img.data(), img.size(), hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) return hip_fail(e, "table copy");
+    e = hipStreamSynchronize(stream);  // img is freed on return
+    if (e != hipSuccess) return hip_fail(e, "table copy");
+    double* at = (double*)(w + Lay.base.at);
+    double* bt = (double*)(w + Lay.base.bt);
+    uint64_t* dlat = (uint64_t*)(w + Lay.base.lat);
+    double* ell = d_ell ? d_ell : (double*)(w + Lay.base.ell);
+    double* part = (double*)(w + Lay.base.part);
+    int* bad = (int*)(w + Lay.base.bad);
+    e = hipMemcpyAsync(dlat, lat, sizeof(uint64_t) * n, hipMemcpyHostToDevice, stream);
     if (e != hipSuccess) return hip_fail(e, "lattice copy");
     e = mvn::launch_prob_setup(n, f->ld, d_a, d_b, d_mu, at, bt, bad, stream);
     if (e != hipSuccess) return hip_fail(e, "setup");
+    mvn::TlrPackArgs pa{};
+    pa.U = f->U;
+    pa.Vt = f->Vt;
+    pa.m = m;
+    pa.rs = rs;
+    pa.np = np;
+    pa.kk = (const int*)(w + Lay.kk);
+    pa.vrow0 = (const long*)(w + Lay.vrow0);
+    pa.ucol0 = (const long*)(w + Lay.ucol0);
+    pa.kpad0 = (const long*)(w + Lay.kpad0);
+    pa.kval = (const int*)(w + Lay.kval);
+    pa.ksum = T.ksum;
+    pa.Vpack = (double*)(w + Lay.vpack);
+    pa.Upack = (double*)(w + Lay.upack);
+    e = mvn::launch_tlr_pack(pa, stream);
+    if (e != hipSuccess) return hip_fail(e, "tlr pack");
     mvn::TlrSweepArgs ta{};
     ta.tiles = f->L;
-    ta.U = f->U;
-    ta.Vt = f->Vt;
-    ta.ranks = f->ranks;
+    ta.Vpack = pa.Vpack;
+    ta.Upack = pa.Upack;
+    ta.zcol = (const long*)(w + Lay.zcol);
+    ta.kpad0 = pa.kpad0;
+    ta.kval = pa.kval;
+    ta.zdst = (const long*)(w + Lay.zdst);
     ta.m = m;
     ta.nt = nt;
-    ta.rs = rs;
     ta.n = n;
     ta.at = at;
     ta.bt = bt;

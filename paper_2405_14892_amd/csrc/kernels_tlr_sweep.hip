@@ -16,14 +16,83 @@
 
 namespace mvn {
 
+// ------------------------------------------------------------ operand packing
+// Once per probability call the low-rank factors are copied into the order
+// the sweep reads them (tlr_tables.h): the V' rows of every tile (i, j),
+// i > j, stacked by tile column j in order of i (Vpack, then 128 zero rows so
+// that a 128-row MFMA tile may run past the last column), and per tile-row i
+// the U columns of its tiles side by side (Upack_i, m x Kpad_i, zero columns
+// up to the multiple of 16).
+
+// Block (p, c): pair p's rows of V' (k_p rows of m doubles), a slice of
+// them; block p == np clears the zero tail.
+__global__ __launch_bounds__(256) void tlr_pack_v_kernel(const double* __restrict__ Vt, int m, int rs, int np,
+                                                         const int* __restrict__ kk,
+                                                         const long* __restrict__ vrow0, long ksum,
+                                                         double* __restrict__ Vpack) {
+  const int p = blockIdx.x;
+  if (p == np) {
+    for (long e = (long)blockIdx.y * 256 + threadIdx.x; e < 128L * m; e += 256L * gridDim.y)
+      Vpack[ksum * m + e] = 0.0;
+    return;
+  }
+  const long cnt = (long)kk[p] * m;
+  const double* src = Vt + (long)p * rs * m;
+  double* dst = Vpack + vrow0[p] * m;
+  for (long e = (long)blockIdx.y * 256 + threadIdx.x; e < cnt; e += 256L * gridDim.y) dst[e] = src[e];
+}
+
+// Block (p, rb): rows rb*64 .. rb*64+63 of pair p = (i, j): U_ij[:, 0:k_p]
+// into Upack_i at column ucol0[p]; the block of the pair (i, i - 1) also
+// clears the padding columns [K_i, Kpad_i).
+__global__ __launch_bounds__(256) void tlr_pack_u_kernel(const double* __restrict__ U, int m, int rs,
+                                                         const int* __restrict__ kk,
+                                                         const long* __restrict__ ucol0,
+                                                         const long* __restrict__ kpad0,
+                                                         const int* __restrict__ kval,
+                                                         double* __restrict__ Upack) {
+  const int p = blockIdx.x;
+  int i = (int)((1.0 + sqrt(1.0 + 8.0 * (double)p)) * 0.5);
+  while (i * (i - 1) / 2 > p) --i;
+  while ((i + 1) * i / 2 <= p) ++i;
+  const int j = p - i * (i - 1) / 2;
+  const long Kp = kpad0[i + 1] - kpad0[i];
+  double* dst = Upack + kpad0[i] * m;
+  const double* src = U + (long)p * m * rs;
+  const int r0 = blockIdx.y * 64, kp = kk[p];
+  const long c0 = ucol0[p];
+  for (int e = threadIdx.x; e < 64 * kp; e += 256) {
+    const int row = r0 + e / kp, q = e % kp;
+    dst[(long)row * Kp + c0 + q] = src[(long)row * rs + q];
+  }
+  if (j == i - 1) {
+    const int kv = kval[i], pw = (int)(Kp - kv);
+    for (int e = threadIdx.x; e < 64 * pw; e += 256) {
+      const int row = r0 + e / pw, q = e % pw;
+      dst[(long)row * Kp + kv + q] = 0.0;
+    }
+  }
+}
+
+hipError_t launch_tlr_pack(const TlrPackArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(tlr_pack_v_kernel, dim3(a.np + 1, 16), dim3(256), 0, st, a.Vt, a.m, a.rs, a.np, a.kk, a.vrow0,
+                     a.ksum, a.Vpack);
+  if (a.np > 0)
+    hipLaunchKernelGGL(tlr_pack_u_kernel, dim3(a.np, a.m / 64), dim3(256), 0, st, a.U, a.m, a.rs, a.kk, a.ucol0,
+                       a.kpad0, a.kval, a.Upack);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------ TLR sweep
-// Rows [r0, r0 + 32) of Z = V'^T Y_j (rows at or past rs are dropped): a
-// 32 x 64 product with K = m split over the four waves, wave w taking
-// k = 64 s + 16 w .. 64 s + 16 w + 15 of every 64-deep stage; the four
-// partial products are summed through LDS.  Used for ranks <= 64, where a
-// 128-row MFMA tile would be mostly zero rows.  lds: 8192 doubles.
-__device__ __forceinline__ void z_rows32(const double* __restrict__ Vp, int m, int r0, const double* __restrict__ Yj,
-                         double* __restrict__ Zj, int rs, double* lds) {
+// Rows [r0, r0 + 32) of the stacked product V_j^T Y_j (rows at or past M
+// are dropped; row rho goes to Z row zdst[rho]): a 32 x 64 product with
+// K = m split over the four waves, wave w taking k = 64 s + 16 w ..
+// 64 s + 16 w + 15 of every 64-deep stage; the four partial products are
+// summed through LDS.  Used for the last <= 64 rows of a tile column, where
+// a 128-row MFMA tile would be mostly padding.  lds: 8192 doubles.
+__device__ __forceinline__ void z_rows32(const double* __restrict__ Vj, int m, long r0, const double* __restrict__ Yj,
+                                         double* __restrict__ Z, const long* __restrict__ zdst, long M,
+                                         double* lds) {
   constexpr int kALd = 32 + 1, kBLd = 64 + 1;
   constexpr int kAW = 16 * kALd, kBW = 16 * kBLd;  // one wave's A / B slice
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -38,7 +107,7 @@ __device__ __forceinline__ void z_rows32(const double* __restrict__ Vp, int m, i
   double ra[8], rb[16];
   // lane t loads 8 k of A row t / 8 and 16 columns of B row t / 4
   auto load = [&](int s) {
-    const double2* pa = reinterpret_cast<const double2*>(Vp + (long)(r0 + (t >> 3)) * m + s * 64 + (t & 7) * 8);
+    const double2* pa = reinterpret_cast<const double2*>(Vj + (r0 + (t >> 3)) * m + s * 64 + (t & 7) * 8);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const double2 v = pa[q];
@@ -92,20 +161,25 @@ __device__ __forceinline__ void z_rows32(const double* __restrict__ Vp, int m, i
       for (int q = 0; q < 4; ++q)
         part[w * 2048 + (ib * 16 + (lane >> 4) + 4 * q) * kCols + jb * 16 + (lane & 15)] = acc[ib][jb][q];
   __syncthreads();
-  for (int e = t; e < 32 * kCols; e += 256)
-    if (r0 + e / kCols < rs) Zj[(long)r0 * kCols + e] = (part[e] + part[2048 + e]) + (part[4096 + e] + part[6144 + e]);
+  for (int e = t; e < 32 * kCols; e += 256) {
+    const long rho = r0 + e / kCols;
+    if (rho < M)
+      Z[zdst[rho] * kCols + (e & (kCols - 1))] = (part[e] + part[2048 + e]) + (part[4096 + e] + part[6144 + e]);
+  }
   __syncthreads();
 }
 
-
 // The sweep of one 64-column chunk through a TLR factor.  For tile-row i:
-//   Z_ij = V'^T_ij Y_j for j < i                       (r_ij x 64, FP64 MFMA,
-//                                                      K = m)
 //   for each 128-row block b of the tile:
-//     S_b = sum_{j<i} U_ij[b, :] Z_ij + L_ii[b, <b] Y_i[<b]   (one K loop
-//                                                      over all terms)
-//     conditioning of the block with the dense L_ii, as in the dense sweep.
-// Z lives in the workgroup's slice of the Z scratch ((nt - 1) x rs x 64).
+//     S_b = [U_i0 .. U_i,i-1][b, :] [Z_i0; ..] + L_ii[b, <b] Y_i[<b]
+//         (one K loop: the packed low-rank products, then the dense part)
+//     conditioning of the block with the dense L_ii, as in the dense sweep;
+//   then, Y_i being known, the stacked product of tile column i:
+//     [Z_(i+1)i; Z_(i+2)i; ..] = [V'_(i+1)i^T; V'_(i+2)i^T; ..] Y_i
+//         (M = sum of the column's ranks, K = m; FP64 MFMA), whose rows are
+//         stored at their places in the packed Z of the tile-rows below.
+// Z lives in the workgroup's slice of the Z scratch (Kpad_total x 64), whose
+// padding rows are cleared once and never written.
 __global__ __launch_bounds__(256, 2) void tlr_sweep_kernel(TlrSweepArgs p) {
   using G = GemmF64;
   static_assert(2 * G::kStageBytes <= kTile * kCols * 8, "GEMM stages must fit in the block buffer");
@@ -114,13 +188,16 @@ __global__ __launch_bounds__(256, 2) void tlr_sweep_kernel(TlrSweepArgs p) {
   __shared__ double c_at[kTile], c_bt[kTile], c_rl[kTile];
   __shared__ uint64_t c_lat[kTile];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  const int m = p.m, rs = p.rs;
+  const int m = p.m;
   const long NS = (long)p.N * p.S;
   const long nchunks = (NS + kCols - 1) / kCols;
   double* Y = p.yscr + (long)blockIdx.x * p.yslice;
   double* Z = p.zscr + (long)blockIdx.x * p.zslice;
   char* stage0 = (char*)lds_T;
   char* stage1 = (char*)lds_T + G::kStageBytes;
+
+  for (int i = 1; i < p.nt; ++i)
+    for (long e = (p.kpad0[i] + p.kval[i]) * kCols + t; e < p.kpad0[i + 1] * kCols; e += 256) Z[e] = 0.0;
 
   for (long chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x) {
     const long col = chunk * kCols + lane;
@@ -131,42 +208,10 @@ __global__ __launch_bounds__(256, 2) void tlr_sweep_kernel(TlrSweepArgs p) {
     LogProd prod{1.0, 0};
     for (int ti = 0; ti < p.nt; ++ti) {
       const long g0 = (long)ti * m;
-      const long prow = (long)ti * (ti - 1) / 2;  // panel index of (ti, 0)
-      // ---- Z_ij = V'^T_ij Y_j, j < ti
-      for (int tj = 0; tj < ti; ++tj) {
-        const int rk = abs(p.ranks[prow + tj]);
-        const double* Vp = p.Vt + (prow + tj) * (long)rs * m;
-        const double* Yj = Y + (long)tj * m * kCols;
-        double* Zj = Z + (long)tj * rs * kCols;
-        if (rk <= 64) {
-          for (int r0 = 0; r0 < rk; r0 += 32) z_rows32(Vp, m, r0, Yj, Zj, rs, lds_T);
-          continue;
-        }
-        for (int r0 = 0; r0 < rk; r0 += kTile) {
-          G::Acc acc;
-          G::zero(acc);
-          const int nst = m / G::kK;
-          G::Regs rg;
-          G::load(Vp, m, 0, r0, 0, Yj, m, rg);
-          G::store(stage0, rg);
-          __syncthreads();
-          for (int s = 0; s < nst; ++s) {
-            const bool odd = s & 1;
-            if (s + 1 < nst) G::load(Vp, m, 0, r0, (long)(s + 1) * G::kK, Yj, m, rg);
-            G::mma(odd ? stage1 : stage0, acc);
-            if (s + 1 < nst) G::store(odd ? stage0 : stage1, rg);
-            __syncthreads();
-          }
-          G::to_block(acc, lds_T);
-          __syncthreads();
-          for (int e = t; e < kTile * kCols; e += 256)
-            if (r0 + e / kCols < rs) Zj[(long)r0 * kCols + e] = lds_T[e];
-          __syncthreads();
-        }
-      }
-      // K stages of the low-rank terms of this tile-row
-      int nst_lr = 0;
-      for (int tj = 0; tj < ti; ++tj) nst_lr += (abs(p.ranks[prow + tj]) + G::kK - 1) / G::kK;
+      const long kp0 = p.kpad0[ti], Kp = p.kpad0[ti + 1] - kp0;
+      const int nst_lr = (int)(Kp / G::kK);
+      const double* Ui = p.Upack + kp0 * m;  // m x Kp
+      const double* Zi = Z + kp0 * kCols;
       const double* D = p.tiles + ((long)ti * (ti + 1) / 2 + ti) * (long)m * m;
       for (int b0 = 0; b0 < m && g0 + b0 < p.n; b0 += kTile) {
         const int rows = (int)min((long)kTile, p.n - (g0 + b0));
@@ -174,19 +219,9 @@ __global__ __launch_bounds__(256, 2) void tlr_sweep_kernel(TlrSweepArgs p) {
         G::zero(acc);
         const int nst = nst_lr + b0 / G::kK;
         if (nst > 0) {
-          int cj = 0, ck = 0;  // cursor over the low-rank stages: panel (ti, cj), stage ck
           auto load_stage = [&](int s, G::Regs& rg) {
-            if (s < nst_lr) {
-              while (ck * G::kK >= abs(p.ranks[prow + cj])) {
-                ++cj;
-                ck = 0;
-              }
-              G::load(p.U + (prow + cj) * (long)m * rs, rs, 0, b0, (long)ck * G::kK,
-                      Z + (long)cj * rs * kCols, rs, rg);
-              ++ck;
-            } else {
-              G::load(D, m, 0, b0, (long)(s - nst_lr) * G::kK, Y + g0 * kCols, m, rg);
-            }
+            if (s < nst_lr) G::load(Ui, Kp, 0, b0, (long)s * G::kK, Zi, Kp, rg);
+            else G::load(D, m, 0, b0, (long)(s - nst_lr) * G::kK, Y + g0 * kCols, m, rg);
           };
           G::Regs rg;
           load_stage(0, rg);
@@ -214,6 +249,38 @@ __global__ __launch_bounds__(256, 2) void tlr_sweep_kernel(TlrSweepArgs p) {
         __syncthreads();
         for (int e = t; e < rows * kCols; e += 256) Y[(g0 + b0) * kCols + e] = lds_T[e];
         __syncthreads();
+      }
+      // ---- stacked product of tile column ti
+      if (ti + 1 < p.nt) {
+        const long z0 = p.zcol[ti], M = p.zcol[ti + 1] - z0;
+        const double* Vj = p.Vpack + z0 * m;
+        const double* Yj = Y + g0 * kCols;
+        const long* zd = p.zdst + z0;
+        long r0 = 0;
+        for (; M - r0 > 64; r0 += kTile) {
+          G::Acc acc;
+          G::zero(acc);
+          const int nst = m / G::kK;
+          G::Regs rg;
+          G::load(Vj, m, 0, r0, 0, Yj, m, rg);
+          G::store(stage0, rg);
+          __syncthreads();
+          for (int s = 0; s < nst; ++s) {
+            const bool odd = s & 1;
+            if (s + 1 < nst) G::load(Vj, m, 0, r0, (long)(s + 1) * G::kK, Yj, m, rg);
+            G::mma(odd ? stage1 : stage0, acc);
+            if (s + 1 < nst) G::store(odd ? stage0 : stage1, rg);
+            __syncthreads();
+          }
+          G::to_block(acc, lds_T);
+          __syncthreads();
+          for (int e = t; e < kTile * kCols; e += 256) {
+            const long rho = r0 + e / kCols;
+            if (rho < M) Z[zd[rho] * kCols + (e & (kCols - 1))] = lds_T[e];
+          }
+          __syncthreads();
+        }
+        for (; r0 < M; r0 += 32) z_rows32(Vj, m, r0, Yj, Z, zd, M, lds_T);
       }
     }
     if (valid) p.ell[col] = logprod_log(prod);

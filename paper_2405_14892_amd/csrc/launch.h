@@ -177,12 +177,32 @@ struct TlrCholArgs {
 };
 hipError_t launch_tlr_cholesky(const TlrCholArgs& a, hipStream_t st);
 
+// Packing of the low-rank factors for the sweep (index tables from
+// tlr_tables.h, on the device).
+struct TlrPackArgs {
+  const double* U;      // factor: per pair m x rs
+  const double* Vt;     // factor: per pair rs x m
+  int m, rs, np;
+  const int* kk;        // per pair: rank used
+  const long* vrow0;    // per pair: first stacked V' row
+  const long* ucol0;    // per pair: first packed column within its tile-row
+  const long* kpad0;    // nt + 1
+  const int* kval;      // nt
+  long ksum;
+  double* Vpack;        // (ksum + 128) x m
+  double* Upack;        // m x kpad0[nt], tile-row i at m * kpad0[i]
+};
+hipError_t launch_tlr_pack(const TlrPackArgs& a, hipStream_t st);
+
 struct TlrSweepArgs {
-  const double* tiles;
-  const double* U;
-  const double* Vt;
-  const int* ranks;
-  int m, nt, rs, n;
+  const double* tiles;  // factor tiles (the dense diagonal tiles are read)
+  const double* Vpack;
+  const double* Upack;
+  const long* zcol;     // nt + 1: first stacked V' row of tile column j
+  const long* kpad0;    // nt + 1: first packed K index (Z row) of tile-row i
+  const int* kval;      // nt: K_i, rows [K_i, Kpad_i) of tile-row i are padding
+  const long* zdst;     // ksum: Z row of stacked V' row
+  int m, nt, n;
   const double* at;
   const double* bt;
   const uint64_t* lattice;
@@ -190,7 +210,7 @@ struct TlrSweepArgs {
   int N, S, periodize;
   double* yscr;     // grid x (nt m) x 64
   long yslice;
-  double* zscr;     // grid x (nt - 1) x rs x 64
+  double* zscr;     // grid x kpad0[nt] x 64
   long zslice;
   double* ell;
   int grid;

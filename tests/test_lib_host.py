@@ -183,3 +183,70 @@ def test_mixed_conditioning_step_close_to_oracle(harness):
     fin = np.isfinite(ol)
     assert np.array_equal(fin, np.isfinite(gl))
     assert np.max(np.abs(gl[fin] - ol[fin])) < 1e-5
+
+
+@pytest.fixture(scope="module")
+def tables_exe(tmp_path_factory):
+    exe = str(tmp_path_factory.mktemp("t") / "tlr_tables_dump")
+    src = os.path.join(ROOT, "tests", "host", "tlr_tables_dump.cpp")
+    subprocess.run(["g++", "-O1", "-std=c++17", "-o", exe, src], check=True)
+    return exe
+
+
+def _tables(exe, nt, rs, ranks):
+    txt = f"{nt} {rs}\n" + " ".join(str(int(r)) for r in ranks) + "\n"
+    out = subprocess.run([exe], input=txt, capture_output=True, text=True, check=True).stdout
+    res = {}
+    for line in out.strip().split("\n"):
+        name, *vals = line.split()
+        res[name] = np.array([int(v) for v in vals], dtype=np.int64)
+    return res
+
+
+@pytest.mark.parametrize("nt,rs,seed", [(1, 16, 0), (2, 16, 1), (7, 32, 2), (12, 48, 3)])
+def test_tlr_sweep_tables(tables_exe, nt, rs, seed):
+    """The TLR sweep's packing: V' rows stacked by tile column in order of the
+    tile-row, U columns of a tile-row packed in order of the tile column and
+    padded to 16, and the map from stacked rows to packed rows a bijection
+    onto the unpadded rows (every product lands where its tile-row reads it)."""
+    rng = np.random.default_rng(seed)
+    npairs = nt * (nt - 1) // 2
+    ranks = rng.integers(0, rs + 1, npairs)
+    ranks[rng.random(npairs) < 0.3] = 0
+    ranks[rng.random(npairs) < 0.2] *= -1  # capped tiles carry a negative rank
+    if npairs:
+        ranks[0] = -(2 ** 31)  # a garbage rank is clipped to the stride
+    T = _tables(tables_exe, nt, rs, ranks)
+    k = np.minimum(np.abs(ranks.astype(np.int64)), rs)
+    pair = lambda i, j: i * (i - 1) // 2 + j
+    if npairs:
+        assert np.array_equal(T["k"], k)
+    assert T["ksum"][0] == k.sum()
+    # stacked V' rows: column j holds pairs (j+1, j), (j+2, j), ... in order
+    row = 0
+    for j in range(nt):
+        assert T["zcol"][j] == row
+        for i in range(j + 1, nt):
+            assert T["vrow0"][pair(i, j)] == row
+            row += k[pair(i, j)]
+    assert T["zcol"][nt] == row
+    # packed K of tile-row i: pairs (i, 0), (i, 1), ... then zero padding to 16
+    for i in range(nt):
+        c = 0
+        for j in range(i):
+            assert T["ucol0"][pair(i, j)] == c
+            c += k[pair(i, j)]
+        assert T["kval"][i] == c
+        width = T["kpad0"][i + 1] - T["kpad0"][i]
+        assert width % 16 == 0 and c <= width < c + 16
+    assert T["kpad0"][0] == 0
+    # zdst: stacked row -> packed row, a bijection onto the unpadded rows
+    want = []
+    for i in range(nt):
+        want.extend(range(T["kpad0"][i], T["kpad0"][i] + T["kval"][i]))
+    assert sorted(T["zdst"].tolist()) == want
+    for i in range(1, nt):
+        for j in range(i):
+            p = pair(i, j)
+            for q in range(k[p]):
+                assert T["zdst"][T["vrow0"][p] + q] == T["kpad0"][i] + T["ucol0"][p] + q
