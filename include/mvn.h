@@ -55,10 +55,12 @@ typedef struct mvn_options {
                      /* [128, 1024]                                           */
   int precision;     /* mvn_precision (TLR factors: MVN_FP64 only)            */
   int periodize;     /* 1 = baker's transform of the QMC points, 0 = off       */
-  int sweep_rows;    /* rows per block of the dense and batched sweeps: 128    */
-                     /* (two workgroups per CU) or 64 (three: more sample     */
-                     /* columns conditioned at once, Y read twice as often); */
-                     /* 0 = 128.  The TLR and adjoint sweeps use 128          */
+  int sweep_rows;    /* rows per block of the dense, batched and TLR sweeps:  */
+                     /* 128 (two workgroups per CU) or 64 (four, three for   */
+                     /* split BF16: more sample columns conditioned at once, */
+                     /* Y read twice as often); 0 = 128 for dense factors    */
+                     /* and batches, 64 for TLR factors.  The adjoint sweep  */
+                     /* uses 128                                             */
   double tlr_eps;    /* > 0: tile low-rank factor (Section III-E): every      */
                      /* off-diagonal tile is compressed to U V^T with         */
                      /* ||A_ij - U V^T||_F <= tlr_eps (absolute).  <= 0: dense */

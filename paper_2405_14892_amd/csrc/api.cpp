@@ -38,6 +38,10 @@ constexpr int kCUs = 256;      // compute units of an MI355X: the persistent gri
 
 // Rows per sweep block: 0 selects the default (128).
 int sweep_rows(const mvn_options* o) { return (!o || o->sweep_rows == 0) ? 128 : o->sweep_rows; }
+// The TLR sweep's blocks: its GEMMs are short (packed ranks plus the dense
+// part of one tile), so conditioning dominates and 64-row blocks (four
+// workgroups per CU) are the default.
+int tlr_sweep_rows(const mvn_options* o) { return (!o || o->sweep_rows == 0) ? 64 : o->sweep_rows; }
 bool sweep_rows_ok(const mvn_options* o) { return !o || o->sweep_rows == 0 || o->sweep_rows == 64 || o->sweep_rows == 128; }
 int max_grid(int rows, int prec) { return kCUs * mvn::sweep_wg_per_cu(rows, prec); }
 
@@ -193,8 +197,9 @@ bool is_tlr(const mvn_options* o) { return o && o->tlr_eps > 0; }
 // to the invalid-limit flag), the sweep's index tables (tlr_tables.h) and
 // packed operands, then per persistent workgroup its Y slice (ld x 64) and Z
 // slice (kpad x 64).  ksum = sum of the ranks, kpad = packed K of all
-// tile-rows.  avail > 0: as many workgroups as fit in avail bytes (grid 0
-// when not even one does); avail == 0: the full grid.
+// tile-rows, rows = sweep block rows (the grid's workgroups per CU).
+// avail > 0: as many workgroups as fit in avail bytes (grid 0 when not even
+// one does); avail == 0: the full grid.
 struct TlrProbLayout {
   ProbLayout base;
   size_t zcol, kpad0, kval, vrow0, ucol0, kk, zdst, vpack, upack, fixed, yscr, zscr, total;
@@ -202,9 +207,9 @@ struct TlrProbLayout {
   int grid;
 };
 
-TlrProbLayout tlr_prob_layout(int ld, int m, int nt, int N, int S, long ksum, long kpad, size_t avail) {
+TlrProbLayout tlr_prob_layout(int ld, int m, int nt, int N, int S, long ksum, long kpad, int rows, size_t avail) {
   TlrProbLayout L{};
-  L.base = prob_layout_ld(ld, N, S, MVN_FP64, 0, 128);
+  L.base = prob_layout_ld(ld, N, S, MVN_FP64, 0, rows);
   const size_t np = (size_t)nt * (nt - 1) / 2;
   size_t off = L.base.yscr;
   L.zcol = off; off = align_up(off + sizeof(long) * (nt + 1));
@@ -387,9 +392,10 @@ int mvn_prob_workspace_bytes(int n, int N, int S, const mvn_options* opts, size_
   if (is_tlr(opts)) {
     // every tile at the rank stride: enough for any factor with these options
     if (tlr_opts_check(opts)) return -4;
+    if (!sweep_rows_ok(opts)) return fail(-4, "sweep_rows must be 0, 64 or 128 (got %d)", opts->sweep_rows);
     const TlrGeom G = tlr_geom(n, opts->tile, opts->max_rank);
     const long kmax = G.npanels * G.rs;
-    *bytes = tlr_prob_layout(G.ld, G.m, G.nt, N, S, kmax, kmax, 0).total;
+    *bytes = tlr_prob_layout(G.ld, G.m, G.nt, N, S, kmax, kmax, tlr_sweep_rows(opts), 0).total;
     return 0;
   }
   if (!sweep_rows_ok(opts)) return fail(-4, "sweep_rows must be 0, 64 or 128 (got %d)", opts->sweep_rows);
@@ -405,12 +411,13 @@ int mvn_prob_workspace_bytes_factor(const mvn_factor* f, int N, int S, const mvn
   if (S < 1) return fail(-3, "S must be >= 1 (got %d)", S);
   if (!bytes) return fail(-5, "bytes is NULL");
   if (!f->ranks || f->tile < 128 || f->ld % f->tile != 0) return fail(-1, "invalid factor handle");
+  if (!sweep_rows_ok(opts)) return fail(-4, "sweep_rows must be 0, 64 or 128 (got %d)", opts->sweep_rows);
   std::vector<int> ranks;
   const hipError_t e = tlr_read_ranks(f, ranks, stream);
   if (e != hipSuccess) return hip_fail(e, "rank read-back");
   const int nt = f->ld / f->tile;
   const mvn::TlrTables T = mvn::build_tlr_tables(nt, f->rank_stride, ranks.data());
-  *bytes = tlr_prob_layout(f->ld, f->tile, nt, N, S, T.ksum, T.kpad0[nt], 0).total;
+  *bytes = tlr_prob_layout(f->ld, f->tile, nt, N, S, T.ksum, T.kpad0[nt], tlr_sweep_rows(opts), 0).total;
   return 0;
 }
 
@@ -544,6 +551,8 @@ int mvn_prob(const mvn_factor* f, const double* d_a, const double* d_b, const do
   if (!prec_ok(prec)) return fail(-8, "unknown precision %d", prec);
   if (tlr) {
     if (prec != MVN_FP64) return fail(-8, "the TLR sweep is FP64");
+    if (!sweep_rows_ok(opts)) return fail(-8, "sweep_rows must be 0, 64 or 128 (got %d)", opts->sweep_rows);
+    const int rows = tlr_sweep_rows(opts);
     if (!ws) return fail(-9, "workspace is NULL");
     if (!d_out) return fail(-11, "output is NULL");
     const int n = f->n, m = f->tile, nt = f->ld / f->tile, rs = f->rank_stride;
@@ -552,9 +561,9 @@ int mvn_prob(const mvn_factor* f, const double* d_a, const double* d_b, const do
     hipError_t e = tlr_read_ranks(f, ranks, stream);
     if (e != hipSuccess) return hip_fail(e, "rank read-back");
     const mvn::TlrTables T = mvn::build_tlr_tables(nt, rs, ranks.data());
-    const TlrProbLayout Lay = tlr_prob_layout(f->ld, m, nt, N, S, T.ksum, T.kpad0[nt], ws_bytes);
+    const TlrProbLayout Lay = tlr_prob_layout(f->ld, m, nt, N, S, T.ksum, T.kpad0[nt], rows, ws_bytes);
     if (Lay.grid < 1) {
-      const size_t full = tlr_prob_layout(f->ld, m, nt, N, S, T.ksum, T.kpad0[nt], 0).total;
+      const size_t full = tlr_prob_layout(f->ld, m, nt, N, S, T.ksum, T.kpad0[nt], rows, 0).total;
       return fail(-10, "workspace too small: %zu bytes hold no sweep workgroup (%zu for the full grid)", ws_bytes,
                   full);
     }
@@ -627,6 +636,7 @@ int mvn_prob(const mvn_factor* f, const double* d_a, const double* d_b, const do
     ta.zslice = Lay.zslice;
     ta.ell = ell;
     ta.grid = Lay.grid;
+    ta.rows = rows;
     e = mvn::launch_tlr_sweep(ta, stream);
     if (e != hipSuccess) return hip_fail(e, "tlr sweep");
     e = mvn::launch_reduce(ell, N, S, part, f->info, bad, d_out, stream);

@@ -144,13 +144,6 @@ __device__ __forceinline__ void sweep_chunk(const SweepLds& sh, const double* __
   if (valid) ell[col] = logprod_log(prod);
 }
 
-// LDS of one workgroup for policy G: the block buffer holds RB x 64 FP64 or
-// the two GEMM stages, whichever is larger.
-template <class G>
-struct SweepLdsSize {
-  static constexpr int kT = G::kRows * kCols > G::kStageBytes / 4 ? G::kRows * kCols : G::kStageBytes / 4;
-};
-
 #define MVN_SWEEP_LDS(G)                                                              \
   __shared__ __attribute__((aligned(16))) double lds_T[SweepLdsSize<G>::kT];          \
   __shared__ double lds_slab[kSlab * G::kRows];                                       \

@@ -170,23 +170,28 @@ __device__ __forceinline__ void z_rows32(const double* __restrict__ Vj, int m, l
 }
 
 // The sweep of one 64-column chunk through a TLR factor.  For tile-row i:
-//   for each 128-row block b of the tile:
+//   for each RB-row block b of the tile:
 //     S_b = [U_i0 .. U_i,i-1][b, :] [Z_i0; ..] + L_ii[b, <b] Y_i[<b]
 //         (one K loop: the packed low-rank products, then the dense part)
 //     conditioning of the block with the dense L_ii, as in the dense sweep;
 //   then, Y_i being known, the stacked product of tile column i:
 //     [Z_(i+1)i; Z_(i+2)i; ..] = [V'_(i+1)i^T; V'_(i+2)i^T; ..] Y_i
-//         (M = sum of the column's ranks, K = m; FP64 MFMA), whose rows are
-//         stored at their places in the packed Z of the tile-rows below.
+//         (M = sum of the column's ranks, K = m; FP64 MFMA in RB-row tiles,
+//         with 32-row split-K products for the last <= 64 rows when RB is
+//         128), whose rows are stored at their places in the packed Z of the
+//         tile-rows below.
 // Z lives in the workgroup's slice of the Z scratch (Kpad_total x 64), whose
-// padding rows are cleared once and never written.
-__global__ __launch_bounds__(256, 2) void tlr_sweep_kernel(TlrSweepArgs p) {
-  using G = GemmF64;
-  static_assert(2 * G::kStageBytes <= kTile * kCols * 8, "GEMM stages must fit in the block buffer");
-  __shared__ __attribute__((aligned(16))) double lds_T[kTile * kCols];
-  __shared__ double lds_slab[kSlab * kTile];
-  __shared__ double c_at[kTile], c_bt[kTile], c_rl[kTile];
-  __shared__ uint64_t c_lat[kTile];
+// padding rows are cleared once and never written.  RB = 128: two
+// workgroups per CU; RB = 64: four (more sample chunks conditioned at once).
+template <int RB>
+__global__ __launch_bounds__(256, RB == 128 ? 2 : 4) void tlr_sweep_kernel(TlrSweepArgs p) {
+  using G = GemmF64T<RB>;
+  constexpr int kT = SweepLdsSize<G>::kT;
+  static_assert(RB == 64 || kT >= 8192, "the 32-row split-K product needs 8192 doubles");
+  __shared__ __attribute__((aligned(16))) double lds_T[kT];
+  __shared__ double lds_slab[kSlab * RB];
+  __shared__ double c_at[RB], c_bt[RB], c_rl[RB];
+  __shared__ uint64_t c_lat[RB];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int m = p.m;
   const long NS = (long)p.N * p.S;
@@ -213,17 +218,17 @@ __global__ __launch_bounds__(256, 2) void tlr_sweep_kernel(TlrSweepArgs p) {
       const double* Ui = p.Upack + kp0 * m;  // m x Kp
       const double* Zi = Z + kp0 * kCols;
       const double* D = p.tiles + ((long)ti * (ti + 1) / 2 + ti) * (long)m * m;
-      for (int b0 = 0; b0 < m && g0 + b0 < p.n; b0 += kTile) {
-        const int rows = (int)min((long)kTile, p.n - (g0 + b0));
-        G::Acc acc;
+      for (int b0 = 0; b0 < m && g0 + b0 < p.n; b0 += RB) {
+        const int rows = (int)min((long)RB, p.n - (g0 + b0));
+        typename G::Acc acc;
         G::zero(acc);
         const int nst = nst_lr + b0 / G::kK;
         if (nst > 0) {
-          auto load_stage = [&](int s, G::Regs& rg) {
+          auto load_stage = [&](int s, typename G::Regs& rg) {
             if (s < nst_lr) G::load(Ui, Kp, 0, b0, (long)s * G::kK, Zi, Kp, rg);
             else G::load(D, m, 0, b0, (long)(s - nst_lr) * G::kK, Y + g0 * kCols, m, rg);
           };
-          G::Regs rg;
+          typename G::Regs rg;
           load_stage(0, rg);
           G::store(stage0, rg);
           __syncthreads();
@@ -243,9 +248,10 @@ __global__ __launch_bounds__(256, 2) void tlr_sweep_kernel(TlrSweepArgs p) {
           c_rl[t] = 1.0 / D[(long)(b0 + t) * m + b0 + t];
           c_lat[t] = p.lattice[g];
         }
-        prod = condition_block((lds_f64*)lds_T, (lds_f64*)lds_slab, (const lds_f64*)c_at, (const lds_f64*)c_bt,
-                               (const lds_f64*)c_rl, (const lds_u64*)c_lat, D, m, b0, rows, p.n, jpt, sidx,
-                               p.seed, p.periodize, valid, prod, nullptr, (int)g0);
+        prod = condition_block<false, RB>((lds_f64*)lds_T, (lds_f64*)lds_slab, (const lds_f64*)c_at,
+                                          (const lds_f64*)c_bt, (const lds_f64*)c_rl, (const lds_u64*)c_lat, D, m,
+                                          b0, rows, p.n, jpt, sidx, p.seed, p.periodize, valid, prod, nullptr,
+                                          (int)g0);
         __syncthreads();
         for (int e = t; e < rows * kCols; e += 256) Y[(g0 + b0) * kCols + e] = lds_T[e];
         __syncthreads();
@@ -257,11 +263,11 @@ __global__ __launch_bounds__(256, 2) void tlr_sweep_kernel(TlrSweepArgs p) {
         const double* Yj = Y + g0 * kCols;
         const long* zd = p.zdst + z0;
         long r0 = 0;
-        for (; M - r0 > 64; r0 += kTile) {
-          G::Acc acc;
+        for (; M - r0 > (RB == 128 ? 64 : 0); r0 += RB) {
+          typename G::Acc acc;
           G::zero(acc);
           const int nst = m / G::kK;
-          G::Regs rg;
+          typename G::Regs rg;
           G::load(Vj, m, 0, r0, 0, Yj, m, rg);
           G::store(stage0, rg);
           __syncthreads();
@@ -274,13 +280,14 @@ __global__ __launch_bounds__(256, 2) void tlr_sweep_kernel(TlrSweepArgs p) {
           }
           G::to_block(acc, lds_T);
           __syncthreads();
-          for (int e = t; e < kTile * kCols; e += 256) {
+          for (int e = t; e < RB * kCols; e += 256) {
             const long rho = r0 + e / kCols;
             if (rho < M) Z[zd[rho] * kCols + (e & (kCols - 1))] = lds_T[e];
           }
           __syncthreads();
         }
-        for (; r0 < M; r0 += 32) z_rows32(Vj, m, r0, Yj, Z, zd, M, lds_T);
+        if constexpr (RB == 128)
+          for (; r0 < M; r0 += 32) z_rows32(Vj, m, r0, Yj, Z, zd, M, lds_T);
       }
     }
     if (valid) p.ell[col] = logprod_log(prod);
@@ -288,7 +295,8 @@ __global__ __launch_bounds__(256, 2) void tlr_sweep_kernel(TlrSweepArgs p) {
 }
 
 hipError_t launch_tlr_sweep(const TlrSweepArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(tlr_sweep_kernel, dim3(a.grid), dim3(256), 0, st, a);
+  if (a.rows == 64) hipLaunchKernelGGL(tlr_sweep_kernel<64>, dim3(a.grid), dim3(256), 0, st, a);
+  else hipLaunchKernelGGL(tlr_sweep_kernel<128>, dim3(a.grid), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 

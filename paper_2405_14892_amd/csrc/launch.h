@@ -214,6 +214,7 @@ struct TlrSweepArgs {
   long zslice;
   double* ell;
   int grid;
+  int rows;         // rows per sweep block: 128 (two workgroups per CU) or 64 (four)
 };
 hipError_t launch_tlr_sweep(const TlrSweepArgs& a, hipStream_t st);
 

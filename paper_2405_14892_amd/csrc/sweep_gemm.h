@@ -335,4 +335,11 @@ using GemmF32 = GemmF32T<128>;
 using GemmBF16 = GemmBF16T<1, 128>;
 using GemmBF16x3 = GemmBF16T<2, 128>;
 
+// LDS block buffer of a sweep workgroup for policy G (doubles): RB x 64 FP64
+// or the two GEMM stages, whichever is larger.
+template <class G>
+struct SweepLdsSize {
+  static constexpr int kT = G::kRows * kCols > G::kStageBytes / 4 ? G::kRows * kCols : G::kStageBytes / 4;
+};
+
 }  // namespace mvn

@@ -52,19 +52,19 @@ def _factor(n, locs, kern, tile, eps, max_rank):
     return f
 
 
-def _prob(f, a, b, N, S, seed, tile, eps, max_rank):
-    opts = mvn.options(tile=tile, tlr_eps=eps, max_rank=max_rank)
+def _prob(f, a, b, N, S, seed, tile, eps, max_rank, rows=0):
+    opts = mvn.options(tile=tile, tlr_eps=eps, max_rank=max_rank, sweep_rows=rows)
     r = mvn.mvn_prob(f, a, b, None, N=N, S=S, seed=seed, opts=opts, return_ell=True)
     torch.cuda.synchronize()
     return r
 
 
-@pytest.mark.parametrize("n,tile", [(1000, 128), (700, 256)])
-def test_tlr_exact_limit_matches_dense_oracle(n, tile):
+@pytest.mark.parametrize("n,tile,rows", [(1000, 128, 128), (700, 256, 128), (700, 256, 64)])
+def test_tlr_exact_limit_matches_dense_oracle(n, tile, rows):
     """eps = 1e-13 with the cap at the tile edge: the factor and every
     sample's log-product agree with the dense oracle (n ragged against the
-    tile and the 128-row blocks; N*S ragged against the 64-column chunks)."""
-    print(f"tlr exact limit n={n} tile={tile}", flush=True)
+    tile and the sweep blocks; N*S ragged against the 64-column chunks)."""
+    print(f"tlr exact limit n={n} tile={tile} rows={rows}", flush=True)
     locs, kern, a, b = _tlr_inputs(32, n)
     rcap = min(tile, 256)
     f = _factor(n, locs, kern, tile, 1e-13, rcap)
@@ -74,13 +74,36 @@ def test_tlr_exact_limit_matches_dense_oracle(n, tile):
     L = _dense_from_tlr(f)
     assert np.max(np.abs(L - Lref)) < 1e-10
     N, S, seed = 777, 2, 4242
-    r = _prob(f, a, b, N, S, seed, tile, 1e-13, rcap)
+    r = _prob(f, a, b, N, S, seed, tile, 1e-13, rcap, rows)
     at, bt = oracle.centre(a, b)
     ell_ref = oracle.sweep(Lref, at, bt, N, S, seed)
     ell = r["ell"].cpu().numpy()
     assert np.max(np.abs(ell - ell_ref)) < 1e-8
     ref = oracle.reduce_samples(ell_ref, N, S)
     assert abs(r["logP"].item() - ref["logP"]) < 1e-9 * max(1.0, abs(ref["logP"]))
+
+
+@pytest.mark.parametrize("rows", [128, 64])
+def test_tlr_sweep_matches_oracle_on_the_compressed_factor(rows):
+    """At a working accuracy (ranks from near zero on far tiles to some tens
+    on adjacent ones, a partial last tile of 20 rows), the TLR sweep equals,
+    sample by sample, the oracle's sweep through the dense L assembled from
+    the same compressed factor: the stacked and packed products change
+    nothing but the rounding."""
+    n, tile, eps, rcap = 1300, 128, 1e-5, 128
+    print(f"tlr sweep on compressed factor rows={rows}", flush=True)
+    locs, kern, a, b = _tlr_inputs(40, n, seed=81, beta=0.05)
+    f = _factor(n, locs, kern, tile, eps, rcap)
+    assert f.info() == 0
+    ranks = f.ranks().cpu().numpy()
+    assert ranks.max() > 16 and len(set(ranks.tolist())) > 5, ranks
+    L = _dense_from_tlr(f)
+    N, S, seed = 300, 3, 515
+    r = _prob(f, a, b, N, S, seed, tile, eps, rcap, rows)
+    at, bt = oracle.centre(a, b)
+    ell_ref = oracle.sweep(L, at, bt, N, S, seed)
+    ell = r["ell"].cpu().numpy()
+    assert np.max(np.abs(ell - ell_ref)) < 1e-8
 
 
 def test_tlr_tile_accuracy_ranks_and_probability():
