@@ -195,18 +195,23 @@ __device__ __forceinline__ double residual_norm2(const double* __restrict__ A, i
   return block_sum(res2, sv);
 }
 
-// Partially pivoted cross approximation of panel tile (k + 1 + blockIdx.x, k),
-// one workgroup per tile.  Each step takes the residual row at the pivot row,
+// Partially pivoted cross approximation of panel tile (k + 1 + i0 + blockIdx.x,
+// k), one workgroup per tile.  Each step takes the residual row at the pivot row,
 // the pivot column at its largest entry among unused columns, the residual
 // column there, and the next pivot row at that column's largest entry among
 // unused rows.  When ||u|| ||v|| <= eps / 2 (or the rank reaches the cap) the
 // exact residual ||A - U V^T||_F is formed, and the approximation is accepted
 // only if it is <= eps; otherwise the crosses continue.  A row whose residual
 // vanishes is skipped; if every row has been used the approximation is exact.
-__global__ __launch_bounds__(256) void tlr_aca_kernel(const double* __restrict__ tiles, int k, int m, int rs,
-                                                      int rcap, double eps, double* __restrict__ U,
+// Lane t owns columns (row residual) and rows (column residual) 4t .. 4t + 3,
+// read as 16-byte pairs; the columns of U are also kept transposed in the
+// workgroup's slot of Ut (rs x m) for that.  The residuals are summed in the
+// same order as with any other lane mapping, and ties in the pivot search go
+// to the lowest index, so the crosses do not depend on the mapping.
+__global__ __launch_bounds__(256) void tlr_aca_kernel(const double* __restrict__ tiles, int k, int i0, int m,
+                                                      int rs, int rcap, double eps, double* __restrict__ U,
                                                       double* __restrict__ Vt, int* __restrict__ ranks,
-                                                      const int* __restrict__ info) {
+                                                      double* __restrict__ Ut, const int* __restrict__ info) {
   if (*info != 0) return;
   __shared__ double row[kTlrMaxTile];
   __shared__ unsigned char urow[kTlrMaxTile], ucol[kTlrMaxTile];
@@ -216,8 +221,9 @@ __global__ __launch_bounds__(256) void tlr_aca_kernel(const double* __restrict__
   __shared__ double lds[4 * kStageDoubles];
   __shared__ double uq[kTlrMaxRank];  // U row irow, then V^T column jp
   const int t = threadIdx.x;
-  const long i = k + 1 + blockIdx.x;
+  const long i = k + 1 + i0 + blockIdx.x;
   const double* A = tiles + tri_lo(i, k) * (long)m * m;
+  double* Utp = Ut + (long)blockIdx.x * rs * m;
   const long pid = tri_st(i, k);
   double* Up = U + pid * (long)m * rs;
   double* Vp = Vt + pid * (long)rs * m;
@@ -230,35 +236,37 @@ __global__ __launch_bounds__(256) void tlr_aca_kernel(const double* __restrict__
   int r = 0, irow = 0, flag = 0, next_check = 0;
   for (int guard = 0; guard < 2 * m; ++guard) {
     bool check = false;
-    // residual row irow (lane t holds columns t, t + 256, t + 512, t + 768)
+    // residual row irow: lane t holds columns 4t .. 4t + 3 (lanes past m / 4
+    // idle), read as 16-byte pairs so that each load instruction moves 1 KB
+    const bool act = 4 * t < m;
     double best = -1.0;
     int bj = 0;
     {
-      // columns past m (m < 1024) are computed on column m - 1 and dropped,
-      // so the loads carry no branches and stay in flight together
-      double v[4];
-      int jc[4];
-#pragma unroll
-      for (int jj = 0; jj < 4; ++jj) {
-        jc[jj] = min(t + 256 * jj, m - 1);
-        v[jj] = A[(long)irow * m + jc[jj]];
+      double v[4] = {0.0, 0.0, 0.0, 0.0};
+      if (act) {
+        const double2* pa = reinterpret_cast<const double2*>(A + (long)irow * m + 4 * t);
+        const double2 a0 = pa[0], a1 = pa[1];
+        v[0] = a0.x; v[1] = a0.y; v[2] = a1.x; v[3] = a1.y;
       }
       if (t < r) uq[t] = Up[(long)irow * rs + t];
       __syncthreads();
+      if (act) {
 #pragma unroll 8
-      for (int q = 0; q < r; ++q) {
-        const double u = uq[q];
-        const double* vq = Vp + (long)q * m;
+        for (int q = 0; q < r; ++q) {
+          const double u = uq[q];
+          const double2* pv = reinterpret_cast<const double2*>(Vp + (long)q * m + 4 * t);
+          const double2 b0 = pv[0], b1 = pv[1];
+          v[0] -= u * b0.x;
+          v[1] -= u * b0.y;
+          v[2] -= u * b1.x;
+          v[3] -= u * b1.y;
+        }
 #pragma unroll
-        for (int jj = 0; jj < 4; ++jj) v[jj] -= u * vq[jc[jj]];
-      }
-#pragma unroll
-      for (int jj = 0; jj < 4; ++jj) {
-        const int j = t + 256 * jj;
-        if (j < m) {
-          row[j] = v[jj];
-          if (!ucol[j] && fabs(v[jj]) > best) {
-            best = fabs(v[jj]);
+        for (int c = 0; c < 4; ++c) {
+          const int j = 4 * t + c;
+          row[j] = v[c];
+          if (!ucol[j] && fabs(v[c]) > best) {
+            best = fabs(v[c]);
             bj = j;
           }
         }
@@ -293,40 +301,52 @@ __global__ __launch_bounds__(256) void tlr_aca_kernel(const double* __restrict__
     }
     double nu2 = 0.0, nv2 = 0.0;
     const double p = row[jp];
-    for (int j = t; j < m; j += 256) {
-      const double v = row[j] / p;
-      Vp[(long)r * m + j] = v;
-      nv2 += v * v;
+    if (act) {
+      double2 w0, w1;
+      w0.x = row[4 * t] / p;
+      w0.y = row[4 * t + 1] / p;
+      w1.x = row[4 * t + 2] / p;
+      w1.y = row[4 * t + 3] / p;
+      double2* pv = reinterpret_cast<double2*>(Vp + (long)r * m + 4 * t);
+      pv[0] = w0;
+      pv[1] = w1;
+      nv2 = (w0.x * w0.x + w0.y * w0.y) + (w1.x * w1.x + w1.y * w1.y);
     }
-    // residual column jp (U_(:, r)); next pivot row
+    // residual column jp (U_(:, r)), lane t holding rows 4t .. 4t + 3 and
+    // reading the earlier columns of U from their transposed copy; next
+    // pivot row
     double cb = -1.0;
     int bi = 0;
     {
-      double v[4];
-      const double* ur[4];
+      double v[4] = {0.0, 0.0, 0.0, 0.0};
+      if (act) {
 #pragma unroll
-      for (int jj = 0; jj < 4; ++jj) {
-        const int ic = min(t + 256 * jj, m - 1);
-        v[jj] = A[(long)ic * m + jp];
-        ur[jj] = Up + (long)ic * rs;
+        for (int c = 0; c < 4; ++c) v[c] = A[(long)(4 * t + c) * m + jp];
       }
       __syncthreads();  // every lane is done with uq (row residual)
       if (t < r) uq[t] = Vp[(long)t * m + jp];
       __syncthreads();
+      if (act) {
 #pragma unroll 8
-      for (int q = 0; q < r; ++q) {
-        const double vq = uq[q];
+        for (int q = 0; q < r; ++q) {
+          const double vq = uq[q];
+          const double2* pu = reinterpret_cast<const double2*>(Utp + (long)q * m + 4 * t);
+          const double2 u0 = pu[0], u1 = pu[1];
+          v[0] -= u0.x * vq;
+          v[1] -= u0.y * vq;
+          v[2] -= u1.x * vq;
+          v[3] -= u1.y * vq;
+        }
+        double2* pw = reinterpret_cast<double2*>(Utp + (long)r * m + 4 * t);
+        pw[0] = double2{v[0], v[1]};
+        pw[1] = double2{v[2], v[3]};
 #pragma unroll
-        for (int jj = 0; jj < 4; ++jj) v[jj] -= ur[jj][q] * vq;
-      }
-#pragma unroll
-      for (int jj = 0; jj < 4; ++jj) {
-        const int ii = t + 256 * jj;
-        if (ii < m) {
-          Up[(long)ii * rs + r] = v[jj];
-          nu2 += v[jj] * v[jj];
-          if (!urow[ii] && fabs(v[jj]) > cb) {
-            cb = fabs(v[jj]);
+        for (int c = 0; c < 4; ++c) {
+          const int ii = 4 * t + c;
+          Up[(long)ii * rs + r] = v[c];
+          nu2 += v[c] * v[c];
+          if (!urow[ii] && fabs(v[c]) > cb) {
+            cb = fabs(v[c]);
             bi = ii;
           }
         }
@@ -582,8 +602,12 @@ hipError_t launch_tlr_cholesky(const TlrCholArgs& a, hipStream_t st) {
     hipLaunchKernelGGL(tlr_info_kernel, dim3(1), dim3(64), 0, ps, a.info, (const int*)a.local_info, j * m);
     if (overlap) hipEventRecord(sd->ev[1], ps);
     if (P > 0) {
-      hipLaunchKernelGGL(tlr_aca_kernel, dim3(P), dim3(256), 0, st, (const double*)a.tiles, j, m, rs, a.rcap,
-                         a.eps, a.U, a.Vt, a.ranks, (const int*)a.info);
+      // the T workspace (idle between the updates of two tile columns) holds
+      // the transposed U columns, kTlrPairBatch tiles per launch
+      const int pb = (int)std::min<long>(P, kTlrPairBatch);
+      for (int i0 = 0; i0 < P; i0 += pb)
+        hipLaunchKernelGGL(tlr_aca_kernel, dim3(std::min(pb, P - i0)), dim3(256), 0, st, (const double*)a.tiles, j,
+                           i0, m, rs, a.rcap, a.eps, a.U, a.Vt, a.ranks, a.T, (const int*)a.info);
       if (overlap) hipStreamWaitEvent(st, sd->ev[1], 0);
       hipLaunchKernelGGL(tlr_trsm_rows_kernel, dim3(P, rs / 4), dim3(256), 0, st, (const double*)a.tiles, j, m, rs,
                          a.Vt, (const int*)a.ranks, (const int*)a.info);
