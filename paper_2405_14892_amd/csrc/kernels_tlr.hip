@@ -199,9 +199,11 @@ __device__ __forceinline__ double residual_norm2(const double* __restrict__ A, i
 // k), one workgroup per tile.  Each step takes the residual row at the pivot row,
 // the pivot column at its largest entry among unused columns, the residual
 // column there, and the next pivot row at that column's largest entry among
-// unused rows.  When ||u|| ||v|| <= eps / 2 (or the rank reaches the cap) the
+// unused rows.  When ||u|| ||v|| <= eps / 4 (or the rank reaches the cap) the
 // exact residual ||A - U V^T||_F is formed, and the approximation is accepted
-// only if it is <= eps; otherwise the crosses continue.  A row whose residual
+// only if it is <= eps; otherwise the crosses continue and the next check
+// waits max(2, r / 8) crosses.  (A first check at eps / 2 usually fails on
+// the adjacent tiles and its retry lands past the needed rank.)  A row whose residual
 // vanishes is skipped; if every row has been used the approximation is exact.
 // Lane t owns columns (row residual) and rows (column residual) 4t .. 4t + 3,
 // read as 16-byte pairs; the columns of U are also kept transposed in the
@@ -363,7 +365,7 @@ __global__ __launch_bounds__(256) void tlr_aca_kernel(const double* __restrict__
     } else {
       check = true;  // every row used
     }
-    if ((sqrt(nu2 * nv2) <= 0.5 * eps && r >= next_check) || r == rcap) check = true;
+    if ((sqrt(nu2 * nv2) <= 0.25 * eps && r >= next_check) || r == rcap) check = true;
     if (!check) continue;
     // exact residual; after a failed check the next one waits a few crosses
     const double res2 = residual_norm2(A, m, Up, rs, Vp, (r + 15) & ~15, lds, sv);
