@@ -138,7 +138,7 @@ __global__ __launch_bounds__(256, 2) void grad_kernel(GradArgs p) {
         c_rl[t] = 1.0 / p.L[g * ld + g];
         c_lat[t] = p.lattice[g];
       }
-      prod = condition_block((lds_f64*)lds, (lds_f64*)slab, (const lds_f64*)c_at, (const lds_f64*)c_bt,
+      prod = condition_block<false, kTile, false>((lds_f64*)lds, (lds_f64*)slab, (const lds_f64*)c_at, (const lds_f64*)c_bt,
                              (const lds_f64*)c_rl, (const lds_u64*)c_lat, p.L, ld, i0, rows, p.n, jpt,
                              sidx, p.seed, p.periodize, valid, prod, owner ? Sf : nullptr);
       __syncthreads();

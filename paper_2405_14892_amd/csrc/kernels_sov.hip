@@ -155,8 +155,9 @@ __device__ __forceinline__ void sweep_chunk(const SweepLds& sh, const double* __
 // (38-41 KB of LDS, <= 128 VGPRs), three for its split-BF16 form (47 KB).
 template <class G>
 struct SweepOccupancy {
-  // LDS of one workgroup (block buffer, slab, per-row constants, work-item slot)
-  static constexpr int kLds = SweepLdsSize<G>::kT * 8 + kSlab * G::kRows * 8 + 4 * G::kRows * 8 + 16;
+  // LDS of one workgroup (block buffer, slab, per-row constants, work-item
+  // slot, AS 241 coefficient table)
+  static constexpr int kLds = SweepLdsSize<G>::kT * 8 + kSlab * G::kRows * 8 + 4 * G::kRows * 8 + 16 + 48 * 8;
   static constexpr int kWG = G::kRows == 128 ? 2 : (4 * kLds <= 160 * 1024 ? 4 : 3);
 };
 

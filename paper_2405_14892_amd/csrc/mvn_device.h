@@ -52,31 +52,58 @@ MVN_HD double log_ncdf_lower(double x) {
 // coefficients and evaluates one rational with one division, so a wave whose
 // lanes fall in different ranges does not run every branch (the result is
 // the same, operation for operation, as evaluating the lane's own branch).
+//
+// kAs241[g] = coefficients of range g (0 central, 1 near tail, 2 far tail):
+// numerator n0 .. n7, denominator d1 .. d7 (d0 = 1), one zero of padding.
+constexpr double kAs241[3][16] = {
+    {3.3871328727963666080e+0, 1.3314166789178437745e+2, 1.9715909503065514427e+3, 1.3731693765509461125e+4,
+     4.5921953931549871457e+4, 6.7265770927008700853e+4, 3.3430575583588128105e+4, 2.5090809287301226727e+3,
+     4.2313330701600911252e+1, 6.8718700749205790830e+2, 5.3941960214247511077e+3, 2.1213794301586595867e+4,
+     3.9307895800092710610e+4, 2.8729085735721942674e+4, 5.2264952788528545610e+3, 0.0},
+    {1.42343711074968357734e+0, 4.63033784615654529590e+0, 5.76949722146069140550e+0, 3.64784832476320460504e+0,
+     1.27045825245236838258e+0, 2.41780725177450611770e-1, 2.27238449892691845833e-2, 7.74545014278341407640e-4,
+     2.05319162663775882187e+0, 1.67638483018380384940e+0, 6.89767334985100004550e-1, 1.48103976427480074590e-1,
+     1.51986665636164571966e-2, 5.47593808499534494600e-4, 1.05075007164441684324e-9, 0.0},
+    {6.65790464350110377720e+0, 5.46378491116411436990e+0, 1.78482653991729133580e+0, 2.96560571828504891230e-1,
+     2.65321895265761230930e-2, 1.24266094738807843860e-3, 2.71155556874348757815e-5, 2.01033439929228813265e-7,
+     5.99832206555887937690e-1, 1.36929880922735805310e-1, 1.48753612908506148525e-2, 7.86869131145613259100e-4,
+     1.84631831751005468180e-5, 1.42151175831644588870e-7, 2.04426310338993978564e-15, 0.0}};
+
+// The rational of range g in x from coefficient row c (16 entries as above).
+template <class C>
+MVN_HD void as241_rational(C c, double x, double& num, double& den) {
+  num = (((((((c[7] * x + c[6]) * x + c[5]) * x + c[4]) * x + c[3]) * x + c[2]) * x + c[1]) * x + c[0]);
+  den = (((((((c[14] * x + c[13]) * x + c[12]) * x + c[11]) * x + c[10]) * x + c[9]) * x + c[8]) * x + 1.0);
+}
+
+// Coefficients chosen per lane with selects between literal constants.
 MVN_HD double ninv_lower(double p) {
   const double q = p - 0.5;
   const bool central = fabs(q) <= 0.425;
   const double rt = central ? 1.0 : sqrt(-log(p));
   const bool near = rt <= 5.0;
   const double x = central ? 0.180625 - q * q : (near ? rt - 1.6 : rt - 5.0);
-#define MVN_SEL(c, n, f) (central ? (c) : (near ? (n) : (f)))
-  const double n7 = MVN_SEL(2.5090809287301226727e+3, 7.74545014278341407640e-4, 2.01033439929228813265e-7);
-  const double n6 = MVN_SEL(3.3430575583588128105e+4, 2.27238449892691845833e-2, 2.71155556874348757815e-5);
-  const double n5 = MVN_SEL(6.7265770927008700853e+4, 2.41780725177450611770e-1, 1.24266094738807843860e-3);
-  const double n4 = MVN_SEL(4.5921953931549871457e+4, 1.27045825245236838258e+0, 2.65321895265761230930e-2);
-  const double n3 = MVN_SEL(1.3731693765509461125e+4, 3.64784832476320460504e+0, 2.96560571828504891230e-1);
-  const double n2 = MVN_SEL(1.9715909503065514427e+3, 5.76949722146069140550e+0, 1.78482653991729133580e+0);
-  const double n1 = MVN_SEL(1.3314166789178437745e+2, 4.63033784615654529590e+0, 5.46378491116411436990e+0);
-  const double n0 = MVN_SEL(3.3871328727963666080e+0, 1.42343711074968357734e+0, 6.65790464350110377720e+0);
-  const double d7 = MVN_SEL(5.2264952788528545610e+3, 1.05075007164441684324e-9, 2.04426310338993978564e-15);
-  const double d6 = MVN_SEL(2.8729085735721942674e+4, 5.47593808499534494600e-4, 1.42151175831644588870e-7);
-  const double d5 = MVN_SEL(3.9307895800092710610e+4, 1.51986665636164571966e-2, 1.84631831751005468180e-5);
-  const double d4 = MVN_SEL(2.1213794301586595867e+4, 1.48103976427480074590e-1, 7.86869131145613259100e-4);
-  const double d3 = MVN_SEL(5.3941960214247511077e+3, 6.89767334985100004550e-1, 1.48753612908506148525e-2);
-  const double d2 = MVN_SEL(6.8718700749205790830e+2, 1.67638483018380384940e+0, 1.36929880922735805310e-1);
-  const double d1 = MVN_SEL(4.2313330701600911252e+1, 2.05319162663775882187e+0, 5.99832206555887937690e-1);
-#undef MVN_SEL
-  const double num = (((((((n7 * x + n6) * x + n5) * x + n4) * x + n3) * x + n2) * x + n1) * x + n0);
-  const double den = (((((((d7 * x + d6) * x + d5) * x + d4) * x + d3) * x + d2) * x + d1) * x + 1.0);
+  double c[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) c[k] = central ? kAs241[0][k] : (near ? kAs241[1][k] : kAs241[2][k]);
+  double num, den;
+  as241_rational(c, x, num, den);
+  const double r = (central ? q * num : num) / den;
+  return central ? r : -r;
+}
+
+// The same with the coefficients read from a copy of kAs241 (48 doubles,
+// e.g. in LDS): one row address per lane instead of 31 two-way selects of
+// 64-bit constants.  Same operations, same result.
+template <class T>
+MVN_HD double ninv_lower_tab(double p, T tab) {
+  const double q = p - 0.5;
+  const bool central = fabs(q) <= 0.425;
+  const double rt = central ? 1.0 : sqrt(-log(p));
+  const bool near = rt <= 5.0;
+  const double x = central ? 0.180625 - q * q : (near ? rt - 1.6 : rt - 5.0);
+  double num, den;
+  as241_rational(tab + (central ? 0 : (near ? 16 : 32)), x, num, den);
   const double r = (central ? q * num : num) / den;
   return central ? r : -r;
 }
@@ -127,7 +154,9 @@ MVN_HD_COLD Step deep_tail(double lo, double hi, double u) {
 }
 
 // One conditioning step (see header comment).  w in (0,1); cw = 1 - w.
-MVN_HD Step condition_step(double alpha, double beta, double w, double cw) {
+// ninv(p) is Phi^-1 on (0, 1/2] (ninv_lower or ninv_lower_tab).
+template <class NInv>
+MVN_HD Step condition_step_with(double alpha, double beta, double w, double cw, NInv ninv) {
   const bool refl = alpha > 0.0;
   const double lo = refl ? -beta : alpha;
   const double hi = refl ? -alpha : beta;
@@ -146,7 +175,7 @@ MVN_HD Step condition_step(double alpha, double beta, double w, double cw) {
     // one Phi^-1 evaluation: the argument is chosen first, so lanes of a
     // wave that take different sides do not run the function twice
     const bool low = p <= 0.5;
-    const double t = ninv_lower(low ? p : qb + v * d);
+    const double t = ninv(low ? p : qb + v * d);
     st.y = low ? t : -t;
     st.m = d;
     st.e = 0;
@@ -160,6 +189,10 @@ MVN_HD Step condition_step(double alpha, double beta, double w, double cw) {
   }
   if (refl) st.y = -st.y;
   return st;
+}
+
+MVN_HD Step condition_step(double alpha, double beta, double w, double cw) {
+  return condition_step_with(alpha, beta, w, cw, [](double x) { return ninv_lower(x); });
 }
 
 // ---------------------------------------------------------------- the step, reduced precision
@@ -193,7 +226,8 @@ MVN_HD float ninv_lower_f32(float p) {
 // bit cancels).  Every other lane (lower tails, narrow intervals) takes the
 // FP64 step.  The factor d is returned in
 // FP64 and accumulated in log space as in the FP64 step.
-MVN_HD Step condition_step_mixed(double alpha, double beta, double w, double cw) {
+template <class NInv>
+MVN_HD Step condition_step_mixed_with(double alpha, double beta, double w, double cw, NInv ninv) {
   const bool refl = alpha > 0.0;
   const double lo = refl ? -beta : alpha;
   const double hi = refl ? -alpha : beta;
@@ -215,8 +249,12 @@ MVN_HD Step condition_step_mixed(double alpha, double beta, double w, double cw)
     st.m = (double)d;
     if (refl) st.y = -st.y;
   }
-  if (!ok) st = condition_step(alpha, beta, w, cw);
+  if (!ok) st = condition_step_with(alpha, beta, w, cw, ninv);
   return st;
+}
+
+MVN_HD Step condition_step_mixed(double alpha, double beta, double w, double cw) {
+  return condition_step_mixed_with(alpha, beta, w, cw, [](double x) { return ninv_lower(x); });
 }
 
 // Running product of the d_i as m * 2^e with m renormalised into [1/2, 1)

@@ -29,7 +29,9 @@ typedef __attribute__((address_space(3))) uint64_t lds_u64;
 // This file is compiled without machine loop-invariant code motion: hoisting
 // the step's ~60 polynomial constants out of the row loop would pin them in
 // registers next to the GEMM's accumulators and force spills (build.py).
-template <bool MIXED = false, int SL = kTile>
+// TAB: the AS 241 coefficients from a 384-byte LDS table (else selected
+// between constants; for kernels whose LDS is already at its budget).
+template <bool MIXED = false, int SL = kTile, bool TAB = true>
 __device__ __forceinline__ LogProd condition_block(
     lds_f64* T, lds_f64* slab, const lds_f64* c_at, const lds_f64* c_bt, const lds_f64* c_rl,
     const lds_u64* c_lat, const double* __restrict__ L, long ld, int i0, int rows, int n,
@@ -37,6 +39,19 @@ __device__ __forceinline__ LogProd condition_block(
     double* __restrict__ s_out = nullptr, int goff = 0) {
   const int t = threadIdx.x, lane = t & 63;
   const bool owner = (t >> 6) == 0;
+  // the AS 241 coefficient rows in LDS, written by wave 1 (ordered before
+  // wave 0's first read by the slab loop's barrier)
+  const lds_f64* tab = nullptr;
+  if constexpr (TAB) {
+    __shared__ double ninv_tab[48];
+    if ((t >> 6) == 1) {
+#pragma unroll
+      for (int e = 0; e < 48; ++e)
+        if (lane == e) ninv_tab[e] = kAs241[e / 16][e % 16];
+    }
+    tab = (const lds_f64*)ninv_tab;
+  }
+  const auto ninv = [tab](double x) { return TAB ? ninv_lower_tab(x, tab) : ninv_lower(x); };
   for (int q = 0; q < rows; q += kSlab) {
     __syncthreads();
     for (int e = t; e < kSlab * SL; e += 256) {
@@ -71,8 +86,8 @@ __device__ __forceinline__ LogProd condition_block(
         const double beta = (c_bt[i] - sum) * rl;
         const uint64_t g = (uint64_t)(goff + i0 + i);
         const double w = richtmyer(jpt, c_lat[i], splitmix64(seed, sidx * (uint64_t)n + g), periodize);
-        const Step st = MIXED ? condition_step_mixed(alpha, beta, w, 1.0 - w)
-                              : condition_step(alpha, beta, w, 1.0 - w);
+        const Step st = MIXED ? condition_step_mixed_with(alpha, beta, w, 1.0 - w, ninv)
+                              : condition_step_with(alpha, beta, w, 1.0 - w, ninv);
         T[i * kCols + lane] = valid ? st.y : 0.0;
         logprod_mul(prod, st);
       }

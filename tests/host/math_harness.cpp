@@ -24,6 +24,10 @@ int main() {
     if (!strcmp(op, "ninv")) {
       scanf("%lf", &x);
       printf("%.17g\n", mvn::ninv_lower(x));
+    } else if (!strcmp(op, "ninvtab")) {  // table form == select form, bit for bit
+      scanf("%lf", &x);
+      const double a = mvn::ninv_lower(x), b = mvn::ninv_lower_tab(x, &mvn::kAs241[0][0]);
+      printf("%d\n", memcmp(&a, &b, sizeof a) == 0 ? 1 : 0);
     } else if (!strcmp(op, "ninvlog")) {
       scanf("%lf", &x);
       printf("%.17g\n", mvn::ninv_log(x));

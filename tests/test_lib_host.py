@@ -78,6 +78,15 @@ def test_as241_inverse_normal_matches_scipy(harness):
     assert rel.max() < 2e-15
 
 
+def test_as241_table_form_equals_select_form(harness):
+    """The sweeps read the AS 241 coefficients from an LDS copy of the table;
+    the result must be the select form's, bit for bit, in all three ranges."""
+    ps = np.concatenate([np.logspace(-300, -0.31, 1500), np.linspace(0.07, 0.5, 500),
+                         [1e-300, 0.075, 0.0750001, 0.5, np.exp(-25.0), np.exp(-25.0) * 1.0000001]])
+    got = _run(harness, [f"ninvtab {float(p)!r}" for p in ps])
+    assert len(got) == len(ps) and all(v == "1" for v in got)
+
+
 def test_conditioning_step_matches_oracle(harness):
     from oracle import sov
     rng = np.random.default_rng(0)
