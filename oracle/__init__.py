@@ -17,6 +17,8 @@ What it computes, in the paper's order (arXiv 2405.14892):
 * ``grad``        - forward-mode (tangent) sweep and central finite
                     differences of log P at fixed QMC points.
 * ``tlr``         - per-tile truncated-SVD compression (Section III-E).
+* ``crd``         - the nested-set probabilities of confidence-region
+                    detection (Section III-A, Algorithm 1) from one sweep.
 
 Parity pins (tests under ``tests/test_oracle_*.py``) tie each function to
 closed forms, library special cases, invariants and brute force.
@@ -27,3 +29,4 @@ from .qmc import first_primes, lattice, splitmix64, shifts, points  # noqa: F401
 from .sov import centre, condition, sweep, reduce_samples, mvn_prob  # noqa: F401
 from .grad import tangent_sweep, logp_directional, logp_fd  # noqa: F401
 from .tlr import compress_tile, tlr_cholesky, tlr_dense  # noqa: F401
+from .crd import sweep_prefix, prefix_probs, exceedance_order  # noqa: F401
