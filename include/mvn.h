@@ -178,6 +178,29 @@ int mvn_prob(const mvn_factor* f, const double* d_a, const double* d_b, const do
 int mvn_prob_workspace_bytes_factor(const mvn_factor* f, int N, int S, const mvn_options* opts,
                                     size_t* bytes, hipStream_t stream);
 
+/* Nested-set probabilities of confidence-region detection (Section III-A,
+ * Algorithm 1), for the sites in the factor's order (the caller orders them,
+ * e.g. by decreasing marginal exceedance probability, before building the
+ * factor): log P-hat(a_i <= X_i <= b_i, i < k) for every k = 1..n from ONE
+ * sweep.  The running product d_1 .. d_k of every sample is a sample of the
+ * k-site problem, because the leading k x k block of L is the Cholesky factor
+ * of the leading block of Sigma; the sweep records it after every row.  Same
+ * estimator, QMC points and limits as mvn_prob (the last entry is mvn_prob's
+ * log P-hat up to rounding), so P-hat of the first k sites uses the n-site
+ * problem's points for its k dimensions.
+ *   N         >= 64 (a chunk of 64 consecutive samples then meets at most two
+ *             shifts)
+ *   d_prefix  device, 2n doubles: [2(k-1)] log P-hat of the first k sites,
+ *             [2(k-1) + 1] its relative standard error over the shifts (NaN
+ *             if S == 1).  All NaN if the factor's info != 0 or a limit is
+ *             NaN / a > b.
+ * Dense factors only (any precision the factor holds, as for mvn_prob); the
+ * workspace holds mvn_prob's plus n x ceil(N S / 64) x 4 + n S doubles. */
+int mvn_prob_prefix_workspace_bytes(int n, int N, int S, const mvn_options* opts, size_t* bytes);
+int mvn_prob_prefix(const mvn_factor* f, const double* d_a, const double* d_b, const double* d_mu,
+                    int N, int S, uint64_t seed, const mvn_options* opts, void* ws, size_t ws_bytes,
+                    double* d_prefix, hipStream_t stream);
+
 /* Gradient of log P-hat at fixed QMC points (the same estimator and points
  * as mvn_prob): reverse-mode differentiation of the recurrence of Eq. (sov1),
  * with checkpointed shifts s_i instead of stored y.  FP64.

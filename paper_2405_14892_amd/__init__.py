@@ -9,6 +9,7 @@ variables with randomised Richtmyer QMC, as parallelised in arXiv 2405.14892
 from __future__ import annotations
 
 import ctypes
+import math
 from dataclasses import dataclass
 
 from . import _lib
@@ -17,6 +18,7 @@ from ._lib import (MVN_BF16, MVN_BF16X3, MVN_FACTOR_TLR, MVN_FP32, MVN_FP64, Mvn
 
 __all__ = ["mvn_factor_bytes", "mvn_cholesky_workspace_bytes", "mvn_prob_workspace_bytes",
            "mvn_prob_workspace_bytes_factor", "mvn_cholesky", "mvn_prob", "Factor",
+           "mvn_prob_prefix_workspace_bytes", "mvn_prob_prefix", "confidence_region",
            "mvn_prob_grad_workspace_bytes", "mvn_prob_grad", "MVNLogProb", "BatchPlan",
            "mvn_batch_plan", "mvn_prob_batch",
            "options", "MvnError", "MVN_FP64", "MVN_FP32", "MVN_BF16", "MVN_BF16X3", "library_path"]
@@ -190,6 +192,64 @@ def mvn_prob(f: Factor, a, b, mu=None, N: int = 1000, S: int = 10, seed: int = 1
     if return_ell:
         res["ell"] = ell
     return res
+
+
+def mvn_prob_prefix_workspace_bytes(n: int, N: int, S: int, opts: MvnOptions | None = None) -> int:
+    out = ctypes.c_size_t(0)
+    _lib.check(_lib.lib().mvn_prob_prefix_workspace_bytes(n, N, S, ctypes.byref(opts or options()),
+                                                          ctypes.byref(out)))
+    return out.value
+
+
+def mvn_prob_prefix(f: Factor, a, b, mu=None, N: int = 1000, S: int = 10, seed: int = 1,
+                    opts: MvnOptions | None = None, workspace=None):
+    """log P-hat of the first k sites, k = 1..n, from one sweep (the
+    nested sets of confidence-region detection; sites in the factor's order).
+    Returns a dict of device tensors: logP[n], rel_stderr[n]."""
+    torch = _torch()
+    opts = opts or options()
+    dev = f.device
+    ta, tb = _dev_f64(a, dev), _dev_f64(b, dev)
+    tm = _dev_f64(mu, dev) if mu is not None else None
+    wsb = mvn_prob_prefix_workspace_bytes(f.n, N, S, opts)
+    if workspace is None or workspace.numel() < wsb:
+        workspace = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    out = torch.empty(2 * f.n, dtype=torch.float64, device=dev)
+    code = _lib.lib().mvn_prob_prefix(ctypes.byref(f.handle), _ptr(ta), _ptr(tb), _ptr(tm), N, S,
+                                      ctypes.c_uint64(seed), ctypes.byref(opts), _ptr(workspace), wsb, _ptr(out),
+                                      _stream(dev))
+    _lib.check(code)
+    return {"logP": out[0::2], "rel_stderr": out[1::2], "out": out, "_keep": (ta, tb, tm, workspace)}
+
+
+def confidence_region(locs, kern: tuple, mu, u: float, alpha: float = 0.05, N: int = 1000, S: int = 10,
+                      seed: int = 1, opts: MvnOptions | None = None, device="cuda"):
+    """Positive excursion set of a Gaussian field at level u with joint
+    probability >= 1 - alpha (Section III-A, Algorithm 1): the sites in order
+    of decreasing marginal exceedance probability P(X_i > u), the factor of
+    Sigma in that order, and one nested-set sweep of the event X_i > u.
+    The excursion function of the k-th site in that order is P-hat of the
+    first k sites; the region is the longest prefix whose P-hat >= 1 - alpha.
+    kern = (sigma2, beta, nu, nugget).  Returns a dict with ``order``,
+    ``logP`` (per prefix), ``excursion`` (per site, in the caller's site
+    order) and ``region`` (site indices)."""
+    import numpy as np
+    from scipy.special import ndtr
+    sigma2, beta, nu, nugget = kern
+    locs = np.asarray(locs, dtype=np.float64)
+    mu = np.asarray(mu, dtype=np.float64)
+    n = len(mu)
+    sd = math.sqrt(sigma2 + nugget)
+    order = np.argsort(-ndtr((mu - u) / sd), kind="stable")
+    opts = opts or options()
+    f = mvn_cholesky(n, locs=locs[order], kern=kern, opts=opts, device=device)
+    r = mvn_prob_prefix(f, np.full(n, float(u)), np.full(n, np.inf), mu[order], N=N, S=S, seed=seed, opts=opts)
+    logp = r["logP"].cpu().numpy()
+    excursion = np.empty(n)
+    excursion[order] = np.exp(logp)
+    k = int(np.sum(np.exp(logp) >= 1.0 - alpha))  # the prefixes do not increase
+    return {"order": order, "logP": logp, "rel_stderr": r["rel_stderr"].cpu().numpy(), "excursion": excursion,
+            "region": np.sort(order[:k]), "info": f.info()}
 
 
 def mvn_prob_grad_workspace_bytes(n: int, N: int, S: int, opts: MvnOptions | None = None) -> int:

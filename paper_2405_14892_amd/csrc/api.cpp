@@ -148,6 +148,26 @@ ProbLayout prob_layout(int n, int N, int S, int prec, int rows) {
   return prob_layout_ld(padded(n), N, S, prec, 0, rows);
 }
 
+// Workspace of a nested-set call: the probability workspace, then the
+// running-product partials of the prefix sweep (n x nchunks x 4 doubles) and
+// the per-shift estimates of every prefix (n x S doubles).
+struct PrefixLayout {
+  ProbLayout base;
+  size_t part, lps, total;
+  long nchunks;
+};
+
+PrefixLayout prefix_layout(int n, int N, int S, int prec, int rows) {
+  PrefixLayout P{};
+  P.base = prob_layout(n, N, S, prec, rows);
+  P.nchunks = ((long)N * S + mvn::sweep_tile_cols() - 1) / mvn::sweep_tile_cols();
+  size_t off = P.base.total;
+  P.part = off; off = align_up(off + sizeof(double) * 4 * (size_t)n * (size_t)P.nchunks);
+  P.lps = off; off = align_up(off + sizeof(double) * (size_t)n * (size_t)S);
+  P.total = off;
+  return P;
+}
+
 // ---------------------------------------------------------------- tile low rank
 // Factor buffer of a TLR factor: tiles | info | U | Vt (+128 rows) | ranks.
 struct TlrGeom {
@@ -348,6 +368,56 @@ BatchWs batch_ws(const BatchPlan& P, int count, int N, int S, int prec, int rows
   return W;
 }
 
+// The dense sweep and reduction of mvn_prob into a validated workspace; with
+// prefix (the partials of a nested-set call) the sweep also records the
+// running products of every row and no full reduction is launched.
+int dense_sweep(const mvn_factor* f, const double* d_a, const double* d_b, const double* d_mu, int N, int S,
+                uint64_t seed, const mvn_options* opts, void* ws, const ProbLayout& Lay, double* d_ell,
+                double* prefix, double* d_out, hipStream_t stream) {
+  const int n = f->n;
+  const int prec = opts->precision;
+  const int rows = sweep_rows(opts);
+  const uint64_t* lat = lattice_table(n);
+  if (!lat) return fail(-1, "could not build the lattice table for n = %d", n);
+  char* w = (char*)ws;
+  double* at = (double*)(w + Lay.at);
+  double* bt = (double*)(w + Lay.bt);
+  uint64_t* dlat = (uint64_t*)(w + Lay.lat);
+  double* ell = d_ell ? d_ell : (double*)(w + Lay.ell);
+  double* part = (double*)(w + Lay.part);
+  int* bad = (int*)(w + Lay.bad);
+  void* yscr = (void*)(w + Lay.yscr);
+  hipError_t e = hipMemcpyAsync(dlat, lat, sizeof(uint64_t) * n, hipMemcpyHostToDevice, stream);
+  if (e != hipSuccess) return hip_fail(e, "lattice copy");
+  e = mvn::launch_prob_setup(n, f->ld, d_a, d_b, d_mu, at, bt, bad, stream);
+  if (e != hipSuccess) return hip_fail(e, "setup");
+  mvn::SweepArgs sa{};
+  sa.L = f->L;
+  sa.Llow = prec == MVN_FP64 ? (const void*)f->L : f->L_low;
+  sa.prec = prec;
+  sa.yslice = mvn::sweep_yslice(prec, f->ld);
+  sa.ld = f->ld;
+  sa.n = n;
+  sa.at = at;
+  sa.bt = bt;
+  sa.lattice = dlat;
+  sa.seed = seed;
+  sa.N = N;
+  sa.S = S;
+  sa.periodize = opts->periodize ? 1 : 0;
+  sa.yscr = yscr;
+  sa.ell = ell;
+  sa.grid = Lay.grid;
+  sa.rows = rows;
+  sa.prefix = prefix;
+  e = mvn::launch_sweep(sa, stream);
+  if (e != hipSuccess) return hip_fail(e, "sweep");
+  if (prefix) return 0;
+  e = mvn::launch_reduce(ell, N, S, part, f->info, bad, d_out, stream);
+  if (e != hipSuccess) return hip_fail(e, "reduce");
+  return 0;
+}
+
 }  // namespace
 
 extern "C" {
@@ -400,6 +470,50 @@ int mvn_prob_workspace_bytes(int n, int N, int S, const mvn_options* opts, size_
   }
   if (!sweep_rows_ok(opts)) return fail(-4, "sweep_rows must be 0, 64 or 128 (got %d)", opts->sweep_rows);
   *bytes = prob_layout(n, N, S, prec, sweep_rows(opts)).total;
+  return 0;
+}
+
+int mvn_prob_prefix_workspace_bytes(int n, int N, int S, const mvn_options* opts, size_t* bytes) {
+  if (n < 1) return fail(-1, "n must be >= 1 (got %d)", n);
+  if (N < 64) return fail(-2, "the nested-set sweep needs N >= 64 (got %d)", N);
+  if (S < 1) return fail(-3, "S must be >= 1 (got %d)", S);
+  if (!bytes) return fail(-5, "bytes is NULL");
+  const int prec = opts ? opts->precision : MVN_FP64;
+  if (!prec_ok(prec)) return fail(-4, "unknown precision %d", prec);
+  if (is_tlr(opts)) return fail(-4, "the nested-set sweep takes dense factors");
+  if (!sweep_rows_ok(opts)) return fail(-4, "sweep_rows must be 0, 64 or 128 (got %d)", opts->sweep_rows);
+  *bytes = prefix_layout(n, N, S, prec, sweep_rows(opts)).total;
+  return 0;
+}
+
+int mvn_prob_prefix(const mvn_factor* f, const double* d_a, const double* d_b, const double* d_mu, int N, int S,
+                    uint64_t seed, const mvn_options* opts, void* ws, size_t ws_bytes, double* d_prefix,
+                    hipStream_t stream) {
+  if (!f || !f->L || !f->info || f->n < 1) return fail(-1, "invalid factor handle");
+  if (f->flags & MVN_FACTOR_TLR) return fail(-1, "the nested-set sweep takes dense factors");
+  if (f->ld != padded(f->n)) return fail(-1, "invalid factor handle");
+  if (!d_a) return fail(-2, "lower limits are NULL");
+  if (!d_b) return fail(-3, "upper limits are NULL");
+  if (N < 64) return fail(-5, "the nested-set sweep needs N >= 64 (got %d)", N);
+  if (S < 1) return fail(-6, "S must be >= 1 (got %d)", S);
+  if ((long)N * S > (long)INT32_MAX * 64) return fail(-5, "N*S too large");
+  if (!opts) return fail(-8, "options are required");
+  const int prec = opts->precision;
+  if (!prec_ok(prec)) return fail(-8, "unknown precision %d", prec);
+  if (prec != MVN_FP64 && (prec != f->precision || !f->L_low))
+    return fail(-8, "the factor holds no operand copy for precision %d (built with %d)", prec, f->precision);
+  if (!sweep_rows_ok(opts)) return fail(-8, "sweep_rows must be 0, 64 or 128 (got %d)", opts->sweep_rows);
+  const PrefixLayout P = prefix_layout(f->n, N, S, prec, sweep_rows(opts));
+  if (!ws) return fail(-9, "workspace is NULL");
+  if (ws_bytes < P.total) return fail(-10, "workspace too small: %zu < %zu", ws_bytes, P.total);
+  if (!d_prefix) return fail(-11, "output is NULL");
+  char* w = (char*)ws;
+  double* part = (double*)(w + P.part);
+  const int rc = dense_sweep(f, d_a, d_b, d_mu, N, S, seed, opts, ws, P.base, nullptr, part, nullptr, stream);
+  if (rc) return rc;
+  const hipError_t e = mvn::launch_prefix_reduce(part, P.nchunks, f->n, N, S, (double*)(w + P.lps), f->info,
+                                                 (const int*)(w + P.base.bad), d_prefix, stream);
+  if (e != hipSuccess) return hip_fail(e, "prefix reduce");
   return 0;
 }
 
@@ -646,49 +760,11 @@ int mvn_prob(const mvn_factor* f, const double* d_a, const double* d_b, const do
   if (prec != MVN_FP64 && (prec != f->precision || !f->L_low))
     return fail(-8, "the factor holds no operand copy for precision %d (built with %d)", prec, f->precision);
   if (!sweep_rows_ok(opts)) return fail(-8, "sweep_rows must be 0, 64 or 128 (got %d)", opts->sweep_rows);
-  const int n = f->n;
-  const int rows = sweep_rows(opts);
-  const ProbLayout Lay = prob_layout(n, N, S, prec, rows);
+  const ProbLayout Lay = prob_layout(f->n, N, S, prec, sweep_rows(opts));
   if (!ws) return fail(-9, "workspace is NULL");
   if (ws_bytes < Lay.total) return fail(-10, "workspace too small: %zu < %zu", ws_bytes, Lay.total);
   if (!d_out) return fail(-11, "output is NULL");
-  const uint64_t* lat = lattice_table(n);
-  if (!lat) return fail(-1, "could not build the lattice table for n = %d", n);
-  char* w = (char*)ws;
-  double* at = (double*)(w + Lay.at);
-  double* bt = (double*)(w + Lay.bt);
-  uint64_t* dlat = (uint64_t*)(w + Lay.lat);
-  double* ell = d_ell ? d_ell : (double*)(w + Lay.ell);
-  double* part = (double*)(w + Lay.part);
-  int* bad = (int*)(w + Lay.bad);
-  void* yscr = (void*)(w + Lay.yscr);
-  hipError_t e = hipMemcpyAsync(dlat, lat, sizeof(uint64_t) * n, hipMemcpyHostToDevice, stream);
-  if (e != hipSuccess) return hip_fail(e, "lattice copy");
-  e = mvn::launch_prob_setup(n, f->ld, d_a, d_b, d_mu, at, bt, bad, stream);
-  if (e != hipSuccess) return hip_fail(e, "setup");
-  mvn::SweepArgs sa{};
-  sa.L = f->L;
-  sa.Llow = prec == MVN_FP64 ? (const void*)f->L : f->L_low;
-  sa.prec = prec;
-  sa.yslice = mvn::sweep_yslice(prec, f->ld);
-  sa.ld = f->ld;
-  sa.n = n;
-  sa.at = at;
-  sa.bt = bt;
-  sa.lattice = dlat;
-  sa.seed = seed;
-  sa.N = N;
-  sa.S = S;
-  sa.periodize = opts->periodize ? 1 : 0;
-  sa.yscr = yscr;
-  sa.ell = ell;
-  sa.grid = Lay.grid;
-  sa.rows = rows;
-  e = mvn::launch_sweep(sa, stream);
-  if (e != hipSuccess) return hip_fail(e, "sweep");
-  e = mvn::launch_reduce(ell, N, S, part, f->info, bad, d_out, stream);
-  if (e != hipSuccess) return hip_fail(e, "reduce");
-  return 0;
+  return dense_sweep(f, d_a, d_b, d_mu, N, S, seed, opts, ws, Lay, d_ell, nullptr, d_out, stream);
 }
 
 int mvn_prob_grad(const mvn_factor* f, const double* d_a, const double* d_b, const double* d_mu,

@@ -84,13 +84,14 @@ struct SweepLds {
 // The whole sweep of one 64-column chunk of one problem: for every RB-row
 // block, the GEMM (step 1), the conditioning (step 2) and the y write-back
 // (step 3).  Writes l of the chunk's valid samples to ell[col].
-template <class G>
+template <class G, bool PREFIX = false>
 __device__ __forceinline__ void sweep_chunk(const SweepLds& sh, const double* __restrict__ L,
                                             const typename G::E* __restrict__ Lg, long lplane, long ld, int n,
                                             const double* __restrict__ at, const double* __restrict__ bt,
                                             const uint64_t* __restrict__ lattice, uint64_t seed, int N, int S,
                                             int periodize, typename G::E* __restrict__ Y,
-                                            double* __restrict__ ell, long chunk) {
+                                            double* __restrict__ ell, long chunk,
+                                            double* __restrict__ prefix = nullptr) {
   constexpr int RB = G::kRows;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const long NS = (long)N * S;
@@ -102,6 +103,7 @@ __device__ __forceinline__ void sweep_chunk(const SweepLds& sh, const double* __
   const uint64_t sidx = valid ? (uint64_t)(col / N) : 0;
   const uint64_t jpt = valid ? (uint64_t)(col % N) + 1 : 1;
   LogProd prod{1.0, 0};
+  const PrefixOut pre{prefix, (NS + kCols - 1) / kCols, chunk, (uint64_t)(chunk * kCols / N)};
 
   for (int i0 = 0; i0 < n; i0 += RB) {
     const int rows = min(RB, n - i0);
@@ -132,10 +134,10 @@ __device__ __forceinline__ void sweep_chunk(const SweepLds& sh, const double* __
       sh.c_lat[t] = lattice[g];
     }
     // ---- step 2: conditioning of the diagonal block
-    prod = condition_block<!std::is_same<typename G::E, double>::value, RB>(
+    prod = condition_block<!std::is_same<typename G::E, double>::value, RB, true, PREFIX>(
         (lds_f64*)sh.T, (lds_f64*)sh.slab, (const lds_f64*)sh.c_at, (const lds_f64*)sh.c_bt,
         (const lds_f64*)sh.c_rl, (const lds_u64*)sh.c_lat, L, ld, i0, rows, n, jpt, sidx, seed, periodize, valid,
-        prod);
+        prod, nullptr, 0, pre);
     __syncthreads();
     // ---- step 3: y block -> scratch (in the GEMM's operand type)
     G::put_y(sh.T, Y, ld, i0, rows);
@@ -161,15 +163,15 @@ struct SweepOccupancy {
   static constexpr int kWG = G::kRows == 128 ? 2 : (4 * kLds <= 160 * 1024 ? 4 : 3);
 };
 
-template <class G>
+template <class G, bool PREFIX = false>
 __global__ __launch_bounds__(256, SweepOccupancy<G>::kWG) void sweep_kernel(SweepArgs p) {
   using E = typename G::E;
   MVN_SWEEP_LDS(G);
   const long nchunks = ((long)p.N * p.S + kCols - 1) / kCols;
   E* Y = (E*)p.yscr + (long)blockIdx.x * p.yslice;
   for (long chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x)
-    sweep_chunk<G>(sh, p.L, (const E*)p.Llow, (long)p.ld * p.ld, p.ld, p.n, p.at, p.bt, p.lattice, p.seed,
-                   p.N, p.S, p.periodize, Y, p.ell, chunk);
+    sweep_chunk<G, PREFIX>(sh, p.L, (const E*)p.Llow, (long)p.ld * p.ld, p.ld, p.n, p.at, p.bt, p.lattice,
+                           p.seed, p.N, p.S, p.periodize, Y, p.ell, chunk, p.prefix);
 }
 
 // Batches: work items (problem rank, chunk) in order of decreasing problem
@@ -215,26 +217,31 @@ long sweep_yslice(int prec, int ld) {
 
 int sweep_elem_bytes(int prec) { return prec == 0 ? 8 : prec == 1 ? 4 : 2; }
 
-hipError_t launch_sweep(const SweepArgs& a, hipStream_t st) {
+template <bool PREFIX>
+static hipError_t launch_sweep_t(const SweepArgs& a, hipStream_t st) {
   const dim3 g(a.grid), b(256);
   if (a.rows == 64) {
     switch (a.prec) {
-      case 0: hipLaunchKernelGGL(sweep_kernel<GemmF64T<64>>, g, b, 0, st, a); break;
-      case 1: hipLaunchKernelGGL(sweep_kernel<GemmF32T<64>>, g, b, 0, st, a); break;
-      case 2: hipLaunchKernelGGL((sweep_kernel<GemmBF16T<1, 64>>), g, b, 0, st, a); break;
-      case 3: hipLaunchKernelGGL((sweep_kernel<GemmBF16T<2, 64>>), g, b, 0, st, a); break;
+      case 0: hipLaunchKernelGGL((sweep_kernel<GemmF64T<64>, PREFIX>), g, b, 0, st, a); break;
+      case 1: hipLaunchKernelGGL((sweep_kernel<GemmF32T<64>, PREFIX>), g, b, 0, st, a); break;
+      case 2: hipLaunchKernelGGL((sweep_kernel<GemmBF16T<1, 64>, PREFIX>), g, b, 0, st, a); break;
+      case 3: hipLaunchKernelGGL((sweep_kernel<GemmBF16T<2, 64>, PREFIX>), g, b, 0, st, a); break;
       default: return hipErrorInvalidValue;
     }
   } else {
     switch (a.prec) {
-      case 0: hipLaunchKernelGGL(sweep_kernel<GemmF64>, g, b, 0, st, a); break;
-      case 1: hipLaunchKernelGGL(sweep_kernel<GemmF32>, g, b, 0, st, a); break;
-      case 2: hipLaunchKernelGGL(sweep_kernel<GemmBF16>, g, b, 0, st, a); break;
-      case 3: hipLaunchKernelGGL(sweep_kernel<GemmBF16x3>, g, b, 0, st, a); break;
+      case 0: hipLaunchKernelGGL((sweep_kernel<GemmF64, PREFIX>), g, b, 0, st, a); break;
+      case 1: hipLaunchKernelGGL((sweep_kernel<GemmF32, PREFIX>), g, b, 0, st, a); break;
+      case 2: hipLaunchKernelGGL((sweep_kernel<GemmBF16, PREFIX>), g, b, 0, st, a); break;
+      case 3: hipLaunchKernelGGL((sweep_kernel<GemmBF16x3, PREFIX>), g, b, 0, st, a); break;
       default: return hipErrorInvalidValue;
     }
   }
   return hipGetLastError();
+}
+
+hipError_t launch_sweep(const SweepArgs& a, hipStream_t st) {
+  return a.prefix ? launch_sweep_t<true>(a, st) : launch_sweep_t<false>(a, st);
 }
 
 // ------------------------------------------------------------ reduction
@@ -327,6 +334,79 @@ hipError_t launch_reduce(const double* ell, int N, int S, double* part, const in
   hipLaunchKernelGGL(lse_partial_kernel, dim3(S), dim3(256), 0, st, ell, N, part);
   hipLaunchKernelGGL(lse_final_kernel, dim3(1), dim3(64), 0, st, (const double*)part, N, S,
                      info_factor, bad_limits, out);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ nested sets
+// Per (row, shift): the running products of the shift's N samples after the
+// row, summed exactly over the chunk partials of prefix_row in chunk order;
+// lps = log(sum 2^E / N), the shift's estimate of P(first row + 1 sites).
+__global__ __launch_bounds__(256) void prefix_shift_kernel(const double* __restrict__ part, long nchunks, int n,
+                                                           int N, int S, double* __restrict__ lps) {
+  const long id = (long)blockIdx.x * 256 + threadIdx.x;
+  if (id >= (long)n * S) return;
+  const long row = id / S;
+  const int s = (int)(id % S);
+  const long c_lo = (long)s * N / kCols, c_hi = ((long)(s + 1) * N - 1) / kCols;
+  int E = kNoExp;
+  double sum = 0.0;
+  for (long c = c_lo; c <= c_hi; ++c) {
+    const int slot = (c * kCols / N == s) ? 0 : 1;
+    const double* d = part + (row * nchunks + c) * 4 + 2 * slot;
+    const double v = d[1];
+    if (!(v > 0.0)) continue;
+    const int e = (int)d[0];
+    if (e > E) {
+      sum = ldexp(sum, E - e) + v;
+      E = e;
+    } else {
+      sum += ldexp(v, e - E);
+    }
+  }
+  lps[id] = sum > 0.0 ? log(sum) + (double)E * kLn2 - log((double)N) : -INFINITY;
+}
+
+// Per row: the mean over shifts in log space and the relative standard
+// error over shifts, as for the full estimate (lse_final_body).
+__global__ __launch_bounds__(256) void prefix_final_kernel(const double* __restrict__ lps, int n, int S,
+                                                           const int* __restrict__ info_factor,
+                                                           const int* __restrict__ bad,
+                                                           double* __restrict__ out) {
+  const long row = (long)blockIdx.x * 256 + threadIdx.x;
+  if (row >= n) return;
+  if ((info_factor && *info_factor != 0) || (bad && *bad != INT_MAX)) {
+    out[2 * row] = NAN;
+    out[2 * row + 1] = NAN;
+    return;
+  }
+  const double* l = lps + row * S;
+  double mx = -INFINITY;
+  for (int s = 0; s < S; ++s) mx = fmax(mx, l[s]);
+  double sum = 0.0;
+  if (mx > -INFINITY)
+    for (int s = 0; s < S; ++s) sum += exp(l[s] - mx);
+  out[2 * row] = (mx > -INFINITY) ? mx + log(sum) - log((double)S) : -INFINITY;
+  if (S > 1 && mx > -INFINITY) {
+    const double mean = sum / S;
+    double var = 0.0;
+    for (int s = 0; s < S; ++s) {
+      const double d = exp(l[s] - mx) - mean;
+      var += d * d;
+    }
+    var /= (S - 1);
+    out[2 * row + 1] = sqrt(var / S) / mean;
+  } else {
+    out[2 * row + 1] = NAN;
+  }
+}
+
+hipError_t launch_prefix_reduce(const double* part, long nchunks, int n, int N, int S, double* lps,
+                                const int* info_factor, const int* bad_limits, double* out, hipStream_t st) {
+  const long tot = (long)n * S;
+  hipLaunchKernelGGL(prefix_shift_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, part, nchunks, n,
+                     N, S, lps);
+  hipLaunchKernelGGL(prefix_final_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                     (const double*)lps, n, S, info_factor, bad_limits, out);
   return hipGetLastError();
 }
 

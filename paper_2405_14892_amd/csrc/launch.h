@@ -56,6 +56,7 @@ struct SweepArgs {
   double* ell;             // N*S per-sample log-products
   int grid;                // persistent workgroups
   int rows;                // rows per sweep block: 128 (two workgroups per CU) or 64 (three)
+  double* prefix;          // nullptr, or n x nchunks x 4 partials of the running products per row
 };
 
 // Setup of one probability call: centred limits and the invalid-limit flag.
@@ -63,6 +64,10 @@ hipError_t launch_prob_setup(int n, int ld, const double* a, const double* b, co
                              double* at, double* bt, int* bad, hipStream_t st);
 
 hipError_t launch_sweep(const SweepArgs& a, hipStream_t st);
+// log P-hat of every nested set (first k sites) and its relative standard
+// error over shifts from the partials of a prefix sweep: out[2k], out[2k+1].
+hipError_t launch_prefix_reduce(const double* part, long nchunks, int n, int N, int S, double* lps,
+                                const int* info_factor, const int* bad_limits, double* out, hipStream_t st);
 long sweep_yslice(int prec, int ld);
 int sweep_elem_bytes(int prec);
 

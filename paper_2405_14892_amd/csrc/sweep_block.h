@@ -15,6 +15,47 @@ constexpr int kSlab = 8;  // rows of the diagonal block of L staged per LDS slab
 typedef __attribute__((address_space(3))) double lds_f64;
 typedef __attribute__((address_space(3))) uint64_t lds_u64;
 
+// Running products of every row for the nested-set probabilities of
+// confidence-region detection (Section III-A, Algorithm 1): after row r the
+// wave's samples' products m 2^e are summed exactly in base 2, split by
+// shift (slot 0: the chunk's first shift, slot 1: the next one; a chunk of
+// 64 consecutive samples meets at most two shifts when N >= 64), and stored
+// as (E, v) with sum = v 2^E at part[(r * nchunks + chunk) * 4 + 2 slot].
+struct PrefixOut {
+  double* part;
+  long nchunks, chunk;
+  uint64_t s_first;
+};
+
+constexpr int kNoExp = -(1 << 30);  // exponent of an empty sum
+
+__device__ __forceinline__ void prefix_row(const LogProd& prod, bool valid, uint64_t sidx, const PrefixOut& pre,
+                                           long row) {
+  const bool live = valid && prod.m > 0.0;
+  const bool first = sidx == pre.s_first;
+  int e0 = (live && first) ? prod.e : kNoExp;
+  int e1 = (live && !first) ? prod.e : kNoExp;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    e0 = max(e0, __shfl_xor(e0, off));
+    e1 = max(e1, __shfl_xor(e1, off));
+  }
+  double v0 = (live && first) ? ldexp(prod.m, prod.e - e0) : 0.0;
+  double v1 = (live && !first) ? ldexp(prod.m, prod.e - e1) : 0.0;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    v0 += __shfl_xor(v0, off);
+    v1 += __shfl_xor(v1, off);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    double* d = pre.part + (row * pre.nchunks + pre.chunk) * 4;
+    d[0] = (double)e0;
+    d[1] = v0;
+    d[2] = (double)e1;
+    d[3] = v1;
+  }
+}
+
 // Step 2 of the sweep for one 128-row block, called by all 256 lanes once per
 // block: rows of the diagonal block of L are staged 8 at a time in LDS (all
 // lanes), and wave 0 (lane = sample column) runs the recurrence
@@ -31,12 +72,13 @@ typedef __attribute__((address_space(3))) uint64_t lds_u64;
 // registers next to the GEMM's accumulators and force spills (build.py).
 // TAB: the AS 241 coefficients from a 384-byte LDS table (else selected
 // between constants; for kernels whose LDS is already at its budget).
-template <bool MIXED = false, int SL = kTile, bool TAB = true>
+// PREFIX: the running products of every row go to pre (prefix_row).
+template <bool MIXED = false, int SL = kTile, bool TAB = true, bool PREFIX = false>
 __device__ __forceinline__ LogProd condition_block(
     lds_f64* T, lds_f64* slab, const lds_f64* c_at, const lds_f64* c_bt, const lds_f64* c_rl,
     const lds_u64* c_lat, const double* __restrict__ L, long ld, int i0, int rows, int n,
     uint64_t jpt, uint64_t sidx, uint64_t seed, int periodize, bool valid, LogProd prod,
-    double* __restrict__ s_out = nullptr, int goff = 0) {
+    double* __restrict__ s_out = nullptr, int goff = 0, PrefixOut pre = PrefixOut{}) {
   const int t = threadIdx.x, lane = t & 63;
   const bool owner = (t >> 6) == 0;
   // the AS 241 coefficient rows in LDS, written by wave 1 (ordered before
@@ -90,6 +132,7 @@ __device__ __forceinline__ LogProd condition_block(
                               : condition_step_with(alpha, beta, w, 1.0 - w, ninv);
         T[i * kCols + lane] = valid ? st.y : 0.0;
         logprod_mul(prod, st);
+        if constexpr (PREFIX) prefix_row(prod, valid, sidx, pre, (long)(goff + i0 + i));
       }
     }
   }

@@ -1,0 +1,118 @@
+"""Nested-set probabilities of confidence-region detection (Section III-A,
+Algorithm 1) through the C ABI: every prefix log P-hat of one sweep against
+the oracle's running products (oracle.prefix_probs) on identical QMC points,
+FP64 to 1e-10 relative; the last prefix against the full estimate; mixed
+precision against the same call's full estimate; rejections; and the
+confidence region of a small field against the one the oracle's prefixes
+give."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2405_14892_amd as mvn
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _field(k, n, seed, beta=0.1, nu=0.5, nugget=1e-8, u=0.0):
+    rng = np.random.default_rng(seed)
+    locs = workloads.grid_locations(k)[:n]
+    mu = workloads.gp_draw_grid(k, 1.0, beta, nu, nugget, rng)[0][:n]
+    return locs, (1.0, beta, nu, nugget), mu
+
+
+@pytest.mark.parametrize("n,tile,N,S,rows", [(400, 100, 10000, 10, 128), (333, 128, 100, 3, 128),
+                                              (333, 128, 100, 3, 64), (70, 64, 64, 1, 128)])
+def test_prefix_matches_oracle(n, tile, N, S, rows):
+    """N = 100: chunks of 64 samples straddle the shift boundaries; S = 1:
+    no standard error."""
+    print(f"prefix n={n} tile={tile} N={N} S={S} rows={rows}", flush=True)
+    locs, kern, mu = _field(20, n, seed=31 + n)
+    a, b = np.full(n, -np.inf), -mu
+    opts = mvn.options(tile=tile, sweep_rows=rows)
+    f = mvn.mvn_cholesky(n, locs=locs, kern=kern, opts=opts, device=DEV)
+    seed = 1234
+    r = mvn.mvn_prob_prefix(f, a, b, None, N=N, S=S, seed=seed, opts=opts)
+    full = mvn.mvn_prob(f, a, b, None, N=N, S=S, seed=seed, opts=opts)
+    torch.cuda.synchronize()
+    logp = r["logP"].cpu().numpy()
+    rel = r["rel_stderr"].cpu().numpy()
+    L = oracle.cholesky(oracle.covariance(locs, *kern))
+    at, bt = oracle.centre(a, b)
+    ref = oracle.prefix_probs(L, at, bt, N, S, seed)
+    err = np.abs(logp - ref["logP"]) / np.maximum(1.0, np.abs(ref["logP"]))
+    print(f"max rel err {err.max():.3e}; last prefix {logp[-1]} full {full['logP'].item()}", flush=True)
+    assert err.max() < 1e-10
+    if S > 1:
+        np.testing.assert_allclose(rel, ref["rel_stderr"], rtol=1e-8, atol=1e-14)
+    else:
+        assert np.all(np.isnan(rel))
+    assert np.all(np.diff(logp) <= 1e-12)
+    assert abs(logp[-1] - full["logP"].item()) < 1e-12 * max(1.0, abs(logp[-1]))
+
+
+@pytest.mark.parametrize("prec", [mvn.MVN_FP32, mvn.MVN_BF16X3])
+def test_prefix_mixed_precision_last_equals_full(prec):
+    n = 300
+    locs, kern, mu = _field(20, n, seed=5)
+    a, b = np.full(n, -np.inf), 0.5 - mu
+    opts = mvn.options(tile=128, precision=prec)
+    f = mvn.mvn_cholesky(n, locs=locs, kern=kern, opts=opts, device=DEV)
+    r = mvn.mvn_prob_prefix(f, a, b, None, N=500, S=4, seed=7, opts=opts)
+    full = mvn.mvn_prob(f, a, b, None, N=500, S=4, seed=7, opts=opts)
+    torch.cuda.synchronize()
+    logp = r["logP"].cpu().numpy()
+    assert abs(logp[-1] - full["logP"].item()) < 1e-12 * max(1.0, abs(logp[-1]))
+    # first prefix: d_1 does not depend on the points
+    sd = math.sqrt(kern[0] + kern[3])
+    assert abs(logp[0] - math.log(0.5 * math.erfc(-b[0] / sd / math.sqrt(2.0)))) < 1e-6
+
+
+def test_prefix_rejections_and_invalid_limits():
+    n = 50
+    locs, kern, mu = _field(10, n, seed=3)
+    opts = mvn.options(tile=64)
+    f = mvn.mvn_cholesky(n, locs=locs, kern=kern, opts=opts, device=DEV)
+    a, b = np.full(n, -np.inf), -mu
+    with pytest.raises(mvn.MvnError) as e:  # from the workspace query (argument 2) or the call (5)
+        mvn.mvn_prob_prefix(f, a, b, N=63, S=2, seed=1, opts=opts)
+    assert e.value.code in (-2, -5) and "N >= 64" in str(e.value)
+    bad = b.copy()
+    bad[7] = np.nan
+    r = mvn.mvn_prob_prefix(f, a, bad, N=64, S=2, seed=1, opts=opts)
+    torch.cuda.synchronize()
+    assert torch.all(torch.isnan(r["out"]))
+    t = mvn.mvn_cholesky(n, locs=locs, kern=kern, opts=mvn.options(tile=128, tlr_eps=1e-6, max_rank=64),
+                         device=DEV)
+    with pytest.raises(mvn.MvnError) as e:
+        mvn.mvn_prob_prefix(t, a, b, N=64, S=2, seed=1, opts=mvn.options(tile=128))
+    assert e.value.code == -1
+
+
+def test_confidence_region_matches_oracle_prefixes():
+    """Algorithm 1 on a 24 x 24 field: the region is the longest prefix (in
+    order of marginal exceedance) whose joint probability >= 1 - alpha; the
+    same order, factor and points through the oracle give the same region."""
+    k, u, alpha = 24, 0.3, 0.1
+    n = k * k
+    locs, kern, mu = _field(k, n, seed=77, beta=0.08)
+    N, S, seed = 2000, 8, 99
+    res = mvn.confidence_region(locs, kern, mu, u, alpha=alpha, N=N, S=S, seed=seed,
+                                opts=mvn.options(tile=128), device=DEV)
+    assert res["info"] == 0
+    order = oracle.exceedance_order(mu, np.full(n, math.sqrt(kern[0] + kern[3])), u)
+    assert np.array_equal(res["order"], order)
+    L = oracle.cholesky(oracle.covariance(locs[order], *kern))
+    at, bt = oracle.centre(np.full(n, u), np.full(n, np.inf), mu[order])
+    ref = oracle.prefix_probs(L, at, bt, N, S, seed)
+    np.testing.assert_allclose(res["logP"], ref["logP"], rtol=1e-10, atol=1e-12)
+    kref = int(np.sum(np.exp(ref["logP"]) >= 1 - alpha))
+    assert np.array_equal(res["region"], np.sort(order[:kref]))
+    print(f"region size {kref} of {n}", flush=True)
+    assert 0 < kref < n
