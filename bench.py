@@ -346,6 +346,53 @@ def variant_autotune_dense(w, dev) -> dict:
     return res
 
 
+def variant_crd(dev) -> dict:
+    """Confidence-region detection (Section III-A, Algorithm 1) on the
+    16384-site field: sites ordered by marginal exceedance of u = 0.5, the
+    factor in that order, and one nested-set sweep giving log P-hat of every
+    prefix; beside it the full-estimate sweep on the same factor.  The cost
+    of one call per nested set is estimated from the sweep's k^2 work."""
+    import math
+    import numpy as np
+    import torch
+    import paper_2405_14892_amd as mvn
+    import workloads
+    from scipy.special import ndtr
+    w = workloads.make_workload("prec16k")
+    u = 0.5
+    field = w.extra["field"]  # the mean field of the workload's GP draw
+    kern = (w.sigma2, w.beta, w.nu, w.nugget)
+    order = np.argsort(-ndtr((field - u) / math.sqrt(w.sigma2 + w.nugget)), kind="stable")
+    opts = mvn.options(tile=w.tile)
+    st = torch.cuda.current_stream(dev)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    a, b, mu = np.full(w.n, u), np.full(w.n, np.inf), field[order]
+    mvn.mvn_prob_prefix(mvn.mvn_cholesky(w.n, locs=w.locs[order], kern=kern, opts=opts, device=dev), a, b, mu,
+                        N=64, S=2, seed=w.seed, opts=opts)  # warm-up
+    torch.cuda.synchronize()
+    ev[0].record(st)
+    f = mvn.mvn_cholesky(w.n, locs=w.locs[order], kern=kern, opts=opts, device=dev)
+    ev[1].record(st)
+    r = mvn.mvn_prob_prefix(f, a, b, mu, N=w.N, S=w.S, seed=w.seed, opts=opts)
+    ev[2].record(st)
+    full = mvn.mvn_prob(f, a, b, mu, N=w.N, S=w.S, seed=w.seed, opts=opts)
+    ev[3].record(st)
+    torch.cuda.synchronize()
+    logp = r["logP"].cpu().numpy()
+    p = np.exp(logp)
+    prefix_ms, full_ms = ev[1].elapsed_time(ev[2]), ev[2].elapsed_time(ev[3])
+    per_set_s = full_ms * 1e-3 * sum((k / w.n) ** 2 for k in range(1, w.n + 1))
+    return {"cholesky_ms": ev[0].elapsed_time(ev[1]), "prefix_sweep_ms": prefix_ms, "full_sweep_ms": full_ms,
+            "prefix_overhead": prefix_ms / full_ms - 1.0, "info": f.info(),
+            "last_prefix_minus_full_logP": float(logp[-1] - full["logP"].item()),
+            "region_size": {str(al): int(np.sum(p >= 1 - al)) for al in (0.01, 0.05, 0.1)},
+            "excursion_at_100_1000_4000": [float(p[99]), float(p[999]), float(p[3999])],
+            "one_call_per_set_s_estimated": per_set_s,
+            "speedup_vs_one_call_per_set_estimated": per_set_s / (prefix_ms * 1e-3),
+            "config": (f"prec16k field, u={u}, event X > u, sites by marginal exceedance, N={w.N} x S={w.S}, "
+                       f"tile {w.tile}, FP64; one-call-per-set cost = full sweep time x sum_k (k/n)^2")}
+
+
 def variant_grad(dev) -> dict:
     import torch
     import paper_2405_14892_amd as mvn
@@ -470,7 +517,8 @@ def main() -> int:
                 ("oracle400", lambda: variant_oracle400(dev)),
                 ("tlr64k", lambda: variant_tlr(dev)),
                 ("batch2000", lambda: variant_batch(dev)),
-                ("grad4096", lambda: variant_grad(dev))]
+                ("grad4096", lambda: variant_grad(dev)),
+                ("crd16k", lambda: variant_crd(dev))]
         only = {v for v in args.variants.split(",") if v}
         for job in jobs:
             if job is None or (only and job[0] not in only):
