@@ -194,9 +194,13 @@ int mvn_prob_workspace_bytes_factor(const mvn_factor* f, int N, int S, const mvn
  *             [2(k-1) + 1] its relative standard error over the shifts (NaN
  *             if S == 1).  All NaN if the factor's info != 0 or a limit is
  *             NaN / a > b.
- * Dense factors only (any precision the factor holds, as for mvn_prob); the
- * workspace holds mvn_prob's plus n x ceil(N S / 64) x 4 + n S doubles. */
-int mvn_prob_prefix_workspace_bytes(int n, int N, int S, const mvn_options* opts, size_t* bytes);
+ * Dense factors (any precision the factor holds) and TLR factors (FP64), as
+ * for mvn_prob.  The workspace holds n x ceil(N S / 64) x 4 + n S doubles,
+ * then mvn_prob's; mvn_prob_prefix_workspace_bytes gives its size for the
+ * factor (for a TLR factor it reads the ranks back, synchronising `stream`,
+ * and mvn_prob_prefix synchronises as mvn_prob does). */
+int mvn_prob_prefix_workspace_bytes(const mvn_factor* f, int N, int S, const mvn_options* opts, size_t* bytes,
+                                    hipStream_t stream);
 int mvn_prob_prefix(const mvn_factor* f, const double* d_a, const double* d_b, const double* d_mu,
                     int N, int S, uint64_t seed, const mvn_options* opts, void* ws, size_t ws_bytes,
                     double* d_prefix, hipStream_t stream);

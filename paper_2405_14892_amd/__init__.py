@@ -194,10 +194,12 @@ def mvn_prob(f: Factor, a, b, mu=None, N: int = 1000, S: int = 10, seed: int = 1
     return res
 
 
-def mvn_prob_prefix_workspace_bytes(n: int, N: int, S: int, opts: MvnOptions | None = None) -> int:
+def mvn_prob_prefix_workspace_bytes(f: Factor, N: int, S: int, opts: MvnOptions | None = None) -> int:
+    """Workspace of mvn_prob_prefix for this factor (for a TLR factor the
+    ranks are read back, which synchronises the current stream)."""
     out = ctypes.c_size_t(0)
-    _lib.check(_lib.lib().mvn_prob_prefix_workspace_bytes(n, N, S, ctypes.byref(opts or options()),
-                                                          ctypes.byref(out)))
+    _lib.check(_lib.lib().mvn_prob_prefix_workspace_bytes(ctypes.byref(f.handle), N, S, ctypes.byref(opts or options()),
+                                                          ctypes.byref(out), _stream(f.device)))
     return out.value
 
 
@@ -211,7 +213,7 @@ def mvn_prob_prefix(f: Factor, a, b, mu=None, N: int = 1000, S: int = 10, seed: 
     dev = f.device
     ta, tb = _dev_f64(a, dev), _dev_f64(b, dev)
     tm = _dev_f64(mu, dev) if mu is not None else None
-    wsb = mvn_prob_prefix_workspace_bytes(f.n, N, S, opts)
+    wsb = mvn_prob_prefix_workspace_bytes(f, N, S, opts)
     if workspace is None or workspace.numel() < wsb:
         workspace = torch.empty(wsb, dtype=torch.uint8, device=dev)
     out = torch.empty(2 * f.n, dtype=torch.float64, device=dev)

@@ -148,20 +148,18 @@ ProbLayout prob_layout(int n, int N, int S, int prec, int rows) {
   return prob_layout_ld(padded(n), N, S, prec, 0, rows);
 }
 
-// Workspace of a nested-set call: the probability workspace, then the
-// running-product partials of the prefix sweep (n x nchunks x 4 doubles) and
-// the per-shift estimates of every prefix (n x S doubles).
-struct PrefixLayout {
-  ProbLayout base;
+// Front of the workspace of a nested-set call: the running-product partials
+// of the prefix sweep (n x nchunks x 4 doubles) and the per-shift estimates
+// of every prefix (n x S doubles); the probability workspace follows.
+struct PrefixRegion {
   size_t part, lps, total;
   long nchunks;
 };
 
-PrefixLayout prefix_layout(int n, int N, int S, int prec, int rows) {
-  PrefixLayout P{};
-  P.base = prob_layout(n, N, S, prec, rows);
+PrefixRegion prefix_region(int n, int N, int S) {
+  PrefixRegion P{};
   P.nchunks = ((long)N * S + mvn::sweep_tile_cols() - 1) / mvn::sweep_tile_cols();
-  size_t off = P.base.total;
+  size_t off = 0;
   P.part = off; off = align_up(off + sizeof(double) * 4 * (size_t)n * (size_t)P.nchunks);
   P.lps = off; off = align_up(off + sizeof(double) * (size_t)n * (size_t)S);
   P.total = off;
@@ -418,6 +416,109 @@ int dense_sweep(const mvn_factor* f, const double* d_a, const double* d_b, const
   return 0;
 }
 
+// The TLR sweep and reduction of mvn_prob (options validated by the
+// caller): reads the ranks back, lays out and fills the index tables and
+// packed operands in ws, sweeps and reduces.  With prefix (the partials of a
+// nested-set call) the sweep also records the running products of every row,
+// no full reduction is launched, and *bad_out gets the invalid-limit flag.
+int tlr_sweep_call(const mvn_factor* f, const double* d_a, const double* d_b, const double* d_mu, int N, int S,
+                   uint64_t seed, const mvn_options* opts, void* ws, size_t ws_bytes, double* d_ell,
+                   double* prefix, double* d_out, hipStream_t stream, const int** bad_out) {
+  const int rows = tlr_sweep_rows(opts);
+  const int n = f->n, m = f->tile, nt = f->ld / f->tile, rs = f->rank_stride;
+  const int np = nt * (nt - 1) / 2;
+  std::vector<int> ranks;
+  hipError_t e = tlr_read_ranks(f, ranks, stream);
+  if (e != hipSuccess) return hip_fail(e, "rank read-back");
+  const mvn::TlrTables T = mvn::build_tlr_tables(nt, rs, ranks.data());
+  const TlrProbLayout Lay = tlr_prob_layout(f->ld, m, nt, N, S, T.ksum, T.kpad0[nt], rows, ws_bytes);
+  if (Lay.grid < 1) {
+    const size_t full = tlr_prob_layout(f->ld, m, nt, N, S, T.ksum, T.kpad0[nt], rows, 0).total;
+    return fail(-10, "workspace too small: %zu bytes hold no sweep workgroup (%zu for the full grid)", ws_bytes,
+                full);
+  }
+  const uint64_t* lat = lattice_table(n);
+  if (!lat) return fail(-1, "could not build the lattice table for n = %d", n);
+  char* w = (char*)ws;
+  // index tables: one host image of the workspace range [zcol, vpack)
+  std::vector<char> img(Lay.vpack - Lay.zcol, 0);
+  auto put = [&](size_t off, const void* src, size_t bytes) {
+    if (bytes) memcpy(img.data() + (off - Lay.zcol), src, bytes);
+  };
+  put(Lay.zcol, T.zcol.data(), sizeof(long) * (nt + 1));
+  put(Lay.kpad0, T.kpad0.data(), sizeof(long) * (nt + 1));
+  put(Lay.kval, T.kval.data(), sizeof(int) * nt);
+  put(Lay.vrow0, T.vrow0.data(), sizeof(long) * np);
+  put(Lay.ucol0, T.ucol0.data(), sizeof(long) * np);
+  put(Lay.kk, T.k.data(), sizeof(int) * np);
+  put(Lay.zdst, T.zdst.data(), sizeof(long) * (size_t)T.ksum);
+  e = hipMemcpyAsync(w + Lay.zcol, img.data(), img.size(), hipMemcpyHostToDevice, stream);
+  if (e != hipSuccess) return hip_fail(e, "table copy");
+  e = hipStreamSynchronize(stream);  // img is freed on return
+  if (e != hipSuccess) return hip_fail(e, "table copy");
+  double* at = (double*)(w + Lay.base.at);
+  double* bt = (double*)(w + Lay.base.bt);
+  uint64_t* dlat = (uint64_t*)(w + Lay.base.lat);
+  double* ell = d_ell ? d_ell : (double*)(w + Lay.base.ell);
+  double* part = (double*)(w + Lay.base.part);
+  int* bad = (int*)(w + Lay.base.bad);
+  e = hipMemcpyAsync(dlat, lat, sizeof(uint64_t) * n, hipMemcpyHostToDevice, stream);
+  if (e != hipSuccess) return hip_fail(e, "lattice copy");
+  e = mvn::launch_prob_setup(n, f->ld, d_a, d_b, d_mu, at, bt, bad, stream);
+  if (e != hipSuccess) return hip_fail(e, "setup");
+  mvn::TlrPackArgs pa{};
+  pa.U = f->U;
+  pa.Vt = f->Vt;
+  pa.m = m;
+  pa.rs = rs;
+  pa.np = np;
+  pa.kk = (const int*)(w + Lay.kk);
+  pa.vrow0 = (const long*)(w + Lay.vrow0);
+  pa.ucol0 = (const long*)(w + Lay.ucol0);
+  pa.kpad0 = (const long*)(w + Lay.kpad0);
+  pa.kval = (const int*)(w + Lay.kval);
+  pa.ksum = T.ksum;
+  pa.Vpack = (double*)(w + Lay.vpack);
+  pa.Upack = (double*)(w + Lay.upack);
+  e = mvn::launch_tlr_pack(pa, stream);
+  if (e != hipSuccess) return hip_fail(e, "tlr pack");
+  mvn::TlrSweepArgs ta{};
+  ta.tiles = f->L;
+  ta.Vpack = pa.Vpack;
+  ta.Upack = pa.Upack;
+  ta.zcol = (const long*)(w + Lay.zcol);
+  ta.kpad0 = pa.kpad0;
+  ta.kval = pa.kval;
+  ta.zdst = (const long*)(w + Lay.zdst);
+  ta.m = m;
+  ta.nt = nt;
+  ta.n = n;
+  ta.at = at;
+  ta.bt = bt;
+  ta.lattice = dlat;
+  ta.seed = seed;
+  ta.N = N;
+  ta.S = S;
+  ta.periodize = opts->periodize ? 1 : 0;
+  ta.yscr = (double*)(w + Lay.yscr);
+  ta.yslice = Lay.yslice;
+  ta.zscr = (double*)(w + Lay.zscr);
+  ta.zslice = Lay.zslice;
+  ta.ell = ell;
+  ta.grid = Lay.grid;
+  ta.rows = rows;
+  ta.prefix = prefix;
+  e = mvn::launch_tlr_sweep(ta, stream);
+  if (e != hipSuccess) return hip_fail(e, "tlr sweep");
+  if (prefix) {
+    *bad_out = bad;
+    return 0;
+  }
+  e = mvn::launch_reduce(ell, N, S, part, f->info, bad, d_out, stream);
+  if (e != hipSuccess) return hip_fail(e, "reduce");
+  return 0;
+}
+
 }  // namespace
 
 extern "C" {
@@ -473,50 +574,6 @@ int mvn_prob_workspace_bytes(int n, int N, int S, const mvn_options* opts, size_
   return 0;
 }
 
-int mvn_prob_prefix_workspace_bytes(int n, int N, int S, const mvn_options* opts, size_t* bytes) {
-  if (n < 1) return fail(-1, "n must be >= 1 (got %d)", n);
-  if (N < 64) return fail(-2, "the nested-set sweep needs N >= 64 (got %d)", N);
-  if (S < 1) return fail(-3, "S must be >= 1 (got %d)", S);
-  if (!bytes) return fail(-5, "bytes is NULL");
-  const int prec = opts ? opts->precision : MVN_FP64;
-  if (!prec_ok(prec)) return fail(-4, "unknown precision %d", prec);
-  if (is_tlr(opts)) return fail(-4, "the nested-set sweep takes dense factors");
-  if (!sweep_rows_ok(opts)) return fail(-4, "sweep_rows must be 0, 64 or 128 (got %d)", opts->sweep_rows);
-  *bytes = prefix_layout(n, N, S, prec, sweep_rows(opts)).total;
-  return 0;
-}
-
-int mvn_prob_prefix(const mvn_factor* f, const double* d_a, const double* d_b, const double* d_mu, int N, int S,
-                    uint64_t seed, const mvn_options* opts, void* ws, size_t ws_bytes, double* d_prefix,
-                    hipStream_t stream) {
-  if (!f || !f->L || !f->info || f->n < 1) return fail(-1, "invalid factor handle");
-  if (f->flags & MVN_FACTOR_TLR) return fail(-1, "the nested-set sweep takes dense factors");
-  if (f->ld != padded(f->n)) return fail(-1, "invalid factor handle");
-  if (!d_a) return fail(-2, "lower limits are NULL");
-  if (!d_b) return fail(-3, "upper limits are NULL");
-  if (N < 64) return fail(-5, "the nested-set sweep needs N >= 64 (got %d)", N);
-  if (S < 1) return fail(-6, "S must be >= 1 (got %d)", S);
-  if ((long)N * S > (long)INT32_MAX * 64) return fail(-5, "N*S too large");
-  if (!opts) return fail(-8, "options are required");
-  const int prec = opts->precision;
-  if (!prec_ok(prec)) return fail(-8, "unknown precision %d", prec);
-  if (prec != MVN_FP64 && (prec != f->precision || !f->L_low))
-    return fail(-8, "the factor holds no operand copy for precision %d (built with %d)", prec, f->precision);
-  if (!sweep_rows_ok(opts)) return fail(-8, "sweep_rows must be 0, 64 or 128 (got %d)", opts->sweep_rows);
-  const PrefixLayout P = prefix_layout(f->n, N, S, prec, sweep_rows(opts));
-  if (!ws) return fail(-9, "workspace is NULL");
-  if (ws_bytes < P.total) return fail(-10, "workspace too small: %zu < %zu", ws_bytes, P.total);
-  if (!d_prefix) return fail(-11, "output is NULL");
-  char* w = (char*)ws;
-  double* part = (double*)(w + P.part);
-  const int rc = dense_sweep(f, d_a, d_b, d_mu, N, S, seed, opts, ws, P.base, nullptr, part, nullptr, stream);
-  if (rc) return rc;
-  const hipError_t e = mvn::launch_prefix_reduce(part, P.nchunks, f->n, N, S, (double*)(w + P.lps), f->info,
-                                                 (const int*)(w + P.base.bad), d_prefix, stream);
-  if (e != hipSuccess) return hip_fail(e, "prefix reduce");
-  return 0;
-}
-
 int mvn_prob_workspace_bytes_factor(const mvn_factor* f, int N, int S, const mvn_options* opts, size_t* bytes,
                                     hipStream_t stream) {
   if (!f || !f->L || f->n < 1) return fail(-1, "invalid factor handle");
@@ -534,6 +591,66 @@ int mvn_prob_workspace_bytes_factor(const mvn_factor* f, int N, int S, const mvn
   *bytes = tlr_prob_layout(f->ld, f->tile, nt, N, S, T.ksum, T.kpad0[nt], tlr_sweep_rows(opts), 0).total;
   return 0;
 }
+
+int mvn_prob_prefix_workspace_bytes(const mvn_factor* f, int N, int S, const mvn_options* opts, size_t* bytes,
+                                    hipStream_t stream) {
+  if (!f || !f->L || f->n < 1) return fail(-1, "invalid factor handle");
+  if (N < 64) return fail(-2, "the nested-set sweep needs N >= 64 (got %d)", N);
+  if (S < 1) return fail(-3, "S must be >= 1 (got %d)", S);
+  if (!bytes) return fail(-5, "bytes is NULL");
+  size_t rest = 0;
+  const int rc = mvn_prob_workspace_bytes_factor(f, N, S, opts, &rest, stream);
+  if (rc) return rc;
+  *bytes = prefix_region(f->n, N, S).total + rest;
+  return 0;
+}
+
+int mvn_prob_prefix(const mvn_factor* f, const double* d_a, const double* d_b, const double* d_mu, int N, int S,
+                    uint64_t seed, const mvn_options* opts, void* ws, size_t ws_bytes, double* d_prefix,
+                    hipStream_t stream) {
+  if (!f || !f->L || !f->info || f->n < 1) return fail(-1, "invalid factor handle");
+  const bool tlr = (f->flags & MVN_FACTOR_TLR) != 0;
+  if (tlr ? (f->tile < 128 || f->tile % 128 != 0 || f->ld % f->tile != 0 || f->ld < f->n || f->ld - f->n >= f->tile ||
+             !f->U || !f->Vt || !f->ranks || f->rank_stride < 16 || f->rank_stride % 16 != 0)
+          : f->ld != padded(f->n))
+    return fail(-1, "invalid factor handle");
+  if (!d_a) return fail(-2, "lower limits are NULL");
+  if (!d_b) return fail(-3, "upper limits are NULL");
+  if (N < 64) return fail(-5, "the nested-set sweep needs N >= 64 (got %d)", N);
+  if (S < 1) return fail(-6, "S must be >= 1 (got %d)", S);
+  if ((long)N * S > (long)INT32_MAX * 64) return fail(-5, "N*S too large");
+  if (!opts) return fail(-8, "options are required");
+  const int prec = opts->precision;
+  if (!prec_ok(prec)) return fail(-8, "unknown precision %d", prec);
+  if (tlr && prec != MVN_FP64) return fail(-8, "the TLR sweep is FP64");
+  if (!tlr && prec != MVN_FP64 && (prec != f->precision || !f->L_low))
+    return fail(-8, "the factor holds no operand copy for precision %d (built with %d)", prec, f->precision);
+  if (!sweep_rows_ok(opts)) return fail(-8, "sweep_rows must be 0, 64 or 128 (got %d)", opts->sweep_rows);
+  const PrefixRegion R = prefix_region(f->n, N, S);
+  if (!ws) return fail(-9, "workspace is NULL");
+  if (ws_bytes < R.total) return fail(-10, "workspace too small: %zu < %zu", ws_bytes, R.total);
+  if (!d_prefix) return fail(-11, "output is NULL");
+  char* w = (char*)ws;
+  double* part = (double*)(w + R.part);
+  void* rest = w + R.total;
+  const size_t rest_bytes = ws_bytes - R.total;
+  const int* bad = nullptr;
+  int rc;
+  if (tlr) {
+    rc = tlr_sweep_call(f, d_a, d_b, d_mu, N, S, seed, opts, rest, rest_bytes, nullptr, part, nullptr, stream, &bad);
+  } else {
+    const ProbLayout Lay = prob_layout(f->n, N, S, prec, sweep_rows(opts));
+    if (rest_bytes < Lay.total) return fail(-10, "workspace too small: %zu < %zu", ws_bytes, R.total + Lay.total);
+    bad = (const int*)((char*)rest + Lay.bad);
+    rc = dense_sweep(f, d_a, d_b, d_mu, N, S, seed, opts, rest, Lay, nullptr, part, nullptr, stream);
+  }
+  if (rc) return rc;
+  const hipError_t e = mvn::launch_prefix_reduce(part, R.nchunks, f->n, N, S, (double*)(w + R.lps), f->info, bad,
+                                                 d_prefix, stream);
+  if (e != hipSuccess) return hip_fail(e, "prefix reduce");
+  return 0;
+}
+
 
 int mvn_prob_grad_workspace_bytes(int n, int N, int S, const mvn_options* opts, size_t* bytes) {
   if (n < 1) return fail(-1, "n must be >= 1 (got %d)", n);
@@ -666,96 +783,9 @@ int mvn_prob(const mvn_factor* f, const double* d_a, const double* d_b, const do
   if (tlr) {
     if (prec != MVN_FP64) return fail(-8, "the TLR sweep is FP64");
     if (!sweep_rows_ok(opts)) return fail(-8, "sweep_rows must be 0, 64 or 128 (got %d)", opts->sweep_rows);
-    const int rows = tlr_sweep_rows(opts);
     if (!ws) return fail(-9, "workspace is NULL");
     if (!d_out) return fail(-11, "output is NULL");
-    const int n = f->n, m = f->tile, nt = f->ld / f->tile, rs = f->rank_stride;
-    const int np = nt * (nt - 1) / 2;
-    std::vector<int> ranks;
-    hipError_t e = tlr_read_ranks(f, ranks, stream);
-    if (e != hipSuccess) return hip_fail(e, "rank read-back");
-    const mvn::TlrTables T = mvn::build_tlr_tables(nt, rs, ranks.data());
-    const TlrProbLayout Lay = tlr_prob_layout(f->ld, m, nt, N, S, T.ksum, T.kpad0[nt], rows, ws_bytes);
-    if (Lay.grid < 1) {
-      const size_t full = tlr_prob_layout(f->ld, m, nt, N, S, T.ksum, T.kpad0[nt], rows, 0).total;
-      return fail(-10, "workspace too small: %zu bytes hold no sweep workgroup (%zu for the full grid)", ws_bytes,
-                  full);
-    }
-    const uint64_t* lat = lattice_table(n);
-    if (!lat) return fail(-1, "could not build the lattice table for n = %d", n);
-    char* w = (char*)ws;
-    // index tables: one host image of the workspace range [zcol, vpack)
-    std::vector<char> img(Lay.vpack - Lay.zcol, 0);
-    auto put = [&](size_t off, const void* src, size_t bytes) {
-      if (bytes) memcpy(img.data() + (off - Lay.zcol), src, bytes);
-    };
-    put(Lay.zcol, T.zcol.data(), sizeof(long) * (nt + 1));
-    put(Lay.kpad0, T.kpad0.data(), sizeof(long) * (nt + 1));
-    put(Lay.kval, T.kval.data(), sizeof(int) * nt);
-    put(Lay.vrow0, T.vrow0.data(), sizeof(long) * np);
-    put(Lay.ucol0, T.ucol0.data(), sizeof(long) * np);
-    put(Lay.kk, T.k.data(), sizeof(int) * np);
-    put(Lay.zdst, T.zdst.data(), sizeof(long) * (size_t)T.ksum);
-    e = hipMemcpyAsync(w + Lay.zcol, img.data(), img.size(), hipMemcpyHostToDevice, stream);
-    if (e != hipSuccess) return hip_fail(e, "table copy");
-    e = hipStreamSynchronize(stream);  // img is freed on return
-    if (e != hipSuccess) return hip_fail(e, "table copy");
-    double* at = (double*)(w + Lay.base.at);
-    double* bt = (double*)(w + Lay.base.bt);
-    uint64_t* dlat = (uint64_t*)(w + Lay.base.lat);
-    double* ell = d_ell ? d_ell : (double*)(w + Lay.base.ell);
-    double* part = (double*)(w + Lay.base.part);
-    int* bad = (int*)(w + Lay.base.bad);
-    e = hipMemcpyAsync(dlat, lat, sizeof(uint64_t) * n, hipMemcpyHostToDevice, stream);
-    if (e != hipSuccess) return hip_fail(e, "lattice copy");
-    e = mvn::launch_prob_setup(n, f->ld, d_a, d_b, d_mu, at, bt, bad, stream);
-    if (e != hipSuccess) return hip_fail(e, "setup");
-    mvn::TlrPackArgs pa{};
-    pa.U = f->U;
-    pa.Vt = f->Vt;
-    pa.m = m;
-    pa.rs = rs;
-    pa.np = np;
-    pa.kk = (const int*)(w + Lay.kk);
-    pa.vrow0 = (const long*)(w + Lay.vrow0);
-    pa.ucol0 = (const long*)(w + Lay.ucol0);
-    pa.kpad0 = (const long*)(w + Lay.kpad0);
-    pa.kval = (const int*)(w + Lay.kval);
-    pa.ksum = T.ksum;
-    pa.Vpack = (double*)(w + Lay.vpack);
-    pa.Upack = (double*)(w + Lay.upack);
-    e = mvn::launch_tlr_pack(pa, stream);
-    if (e != hipSuccess) return hip_fail(e, "tlr pack");
-    mvn::TlrSweepArgs ta{};
-    ta.tiles = f->L;
-    ta.Vpack = pa.Vpack;
-    ta.Upack = pa.Upack;
-    ta.zcol = (const long*)(w + Lay.zcol);
-    ta.kpad0 = pa.kpad0;
-    ta.kval = pa.kval;
-    ta.zdst = (const long*)(w + Lay.zdst);
-    ta.m = m;
-    ta.nt = nt;
-    ta.n = n;
-    ta.at = at;
-    ta.bt = bt;
-    ta.lattice = dlat;
-    ta.seed = seed;
-    ta.N = N;
-    ta.S = S;
-    ta.periodize = opts->periodize ? 1 : 0;
-    ta.yscr = (double*)(w + Lay.yscr);
-    ta.yslice = Lay.yslice;
-    ta.zscr = (double*)(w + Lay.zscr);
-    ta.zslice = Lay.zslice;
-    ta.ell = ell;
-    ta.grid = Lay.grid;
-    ta.rows = rows;
-    e = mvn::launch_tlr_sweep(ta, stream);
-    if (e != hipSuccess) return hip_fail(e, "tlr sweep");
-    e = mvn::launch_reduce(ell, N, S, part, f->info, bad, d_out, stream);
-    if (e != hipSuccess) return hip_fail(e, "reduce");
-    return 0;
+    return tlr_sweep_call(f, d_a, d_b, d_mu, N, S, seed, opts, ws, ws_bytes, d_ell, nullptr, d_out, stream, nullptr);
   }
   if (prec != MVN_FP64 && (prec != f->precision || !f->L_low))
     return fail(-8, "the factor holds no operand copy for precision %d (built with %d)", prec, f->precision);

@@ -183,7 +183,7 @@ __device__ __forceinline__ void z_rows32(const double* __restrict__ Vj, int m, l
 // Z lives in the workgroup's slice of the Z scratch (Kpad_total x 64), whose
 // padding rows are cleared once and never written.  RB = 128: two
 // workgroups per CU; RB = 64: four (more sample chunks conditioned at once).
-template <int RB>
+template <int RB, bool PREFIX = false>
 __global__ __launch_bounds__(256, RB == 128 ? 2 : 4) void tlr_sweep_kernel(TlrSweepArgs p) {
   using G = GemmF64T<RB>;
   constexpr int kT = SweepLdsSize<G>::kT;
@@ -211,6 +211,7 @@ __global__ __launch_bounds__(256, RB == 128 ? 2 : 4) void tlr_sweep_kernel(TlrSw
     const uint64_t sidx = valid ? (uint64_t)(col / p.N) : 0;
     const uint64_t jpt = valid ? (uint64_t)(col % p.N) + 1 : 1;
     LogProd prod{1.0, 0};
+    const PrefixOut pre{p.prefix, nchunks, chunk, (uint64_t)(chunk * kCols / p.N)};
     for (int ti = 0; ti < p.nt; ++ti) {
       const long g0 = (long)ti * m;
       const long kp0 = p.kpad0[ti], Kp = p.kpad0[ti + 1] - kp0;
@@ -248,10 +249,10 @@ __global__ __launch_bounds__(256, RB == 128 ? 2 : 4) void tlr_sweep_kernel(TlrSw
           c_rl[t] = 1.0 / D[(long)(b0 + t) * m + b0 + t];
           c_lat[t] = p.lattice[g];
         }
-        prod = condition_block<false, RB>((lds_f64*)lds_T, (lds_f64*)lds_slab, (const lds_f64*)c_at,
-                                          (const lds_f64*)c_bt, (const lds_f64*)c_rl, (const lds_u64*)c_lat, D, m,
-                                          b0, rows, p.n, jpt, sidx, p.seed, p.periodize, valid, prod, nullptr,
-                                          (int)g0);
+        prod = condition_block<false, RB, true, PREFIX>((lds_f64*)lds_T, (lds_f64*)lds_slab, (const lds_f64*)c_at,
+                                                        (const lds_f64*)c_bt, (const lds_f64*)c_rl,
+                                                        (const lds_u64*)c_lat, D, m, b0, rows, p.n, jpt, sidx, p.seed,
+                                                        p.periodize, valid, prod, nullptr, (int)g0, pre);
         __syncthreads();
         for (int e = t; e < rows * kCols; e += 256) Y[(g0 + b0) * kCols + e] = lds_T[e];
         __syncthreads();
@@ -295,8 +296,14 @@ __global__ __launch_bounds__(256, RB == 128 ? 2 : 4) void tlr_sweep_kernel(TlrSw
 }
 
 hipError_t launch_tlr_sweep(const TlrSweepArgs& a, hipStream_t st) {
-  if (a.rows == 64) hipLaunchKernelGGL(tlr_sweep_kernel<64>, dim3(a.grid), dim3(256), 0, st, a);
-  else hipLaunchKernelGGL(tlr_sweep_kernel<128>, dim3(a.grid), dim3(256), 0, st, a);
+  const dim3 g(a.grid), b(256);
+  if (a.prefix) {
+    if (a.rows == 64) hipLaunchKernelGGL((tlr_sweep_kernel<64, true>), g, b, 0, st, a);
+    else hipLaunchKernelGGL((tlr_sweep_kernel<128, true>), g, b, 0, st, a);
+  } else {
+    if (a.rows == 64) hipLaunchKernelGGL((tlr_sweep_kernel<64, false>), g, b, 0, st, a);
+    else hipLaunchKernelGGL((tlr_sweep_kernel<128, false>), g, b, 0, st, a);
+  }
   return hipGetLastError();
 }
 

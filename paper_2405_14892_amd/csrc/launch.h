@@ -220,6 +220,7 @@ struct TlrSweepArgs {
   double* ell;
   int grid;
   int rows;         // rows per sweep block: 128 (two workgroups per CU) or 64 (four)
+  double* prefix;   // nullptr, or n x nchunks x 4 partials of the running products per row
 };
 hipError_t launch_tlr_sweep(const TlrSweepArgs& a, hipStream_t st);
 

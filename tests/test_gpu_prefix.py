@@ -4,7 +4,8 @@ the oracle's running products (oracle.prefix_probs) on identical QMC points,
 FP64 to 1e-10 relative; the last prefix against the full estimate; mixed
 precision against the same call's full estimate; rejections; and the
 confidence region of a small field against the one the oracle's prefixes
-give."""
+give.  Nested sets through a TLR factor against the oracle on the dense
+factor assembled from the same compressed tiles."""
 import math
 
 import numpy as np
@@ -90,9 +91,55 @@ def test_prefix_rejections_and_invalid_limits():
     assert torch.all(torch.isnan(r["out"]))
     t = mvn.mvn_cholesky(n, locs=locs, kern=kern, opts=mvn.options(tile=128, tlr_eps=1e-6, max_rank=64),
                          device=DEV)
-    with pytest.raises(mvn.MvnError) as e:
-        mvn.mvn_prob_prefix(t, a, b, N=64, S=2, seed=1, opts=mvn.options(tile=128))
-    assert e.value.code == -1
+    with pytest.raises(mvn.MvnError) as e:  # the TLR sweep is FP64 only
+        mvn.mvn_prob_prefix(t, a, b, N=64, S=2, seed=1, opts=mvn.options(tile=128, precision=mvn.MVN_FP32))
+    assert e.value.code == -8
+
+
+def _dense_from_tlr(f):
+    """Dense L assembled on the host from the TLR buffers (tiles, U, Vt)."""
+    m, nt, n = f.handle.tile, f.nt, f.n
+    tiles = f.tiles().cpu().numpy()
+    U, Vt = f.U().cpu().numpy(), f.Vt().cpu().numpy()
+    L = np.zeros((nt * m, nt * m))
+    for i in range(nt):
+        L[i * m:(i + 1) * m, i * m:(i + 1) * m] = np.tril(tiles[i * (i + 1) // 2 + i])
+        for k in range(i):
+            p = i * (i - 1) // 2 + k
+            L[i * m:(i + 1) * m, k * m:(k + 1) * m] = U[p] @ Vt[p]
+    return L[:n, :n]
+
+
+@pytest.mark.parametrize("rows", [64, 128])
+def test_prefix_on_tlr_factor_matches_oracle(rows):
+    """Nested sets through the tile low-rank sweep (ranks of some tens, a
+    partial last tile): every prefix against the oracle's running products
+    through the dense L assembled from the same compressed factor, and the
+    last prefix against the TLR full estimate."""
+    n, tile, N, S, seed = 1100, 128, 300, 3, 919
+    print(f"tlr prefix rows={rows}", flush=True)
+    rng = np.random.default_rng(44)
+    perm = workloads.morton_permutation(40)
+    locs = workloads.grid_locations(40)[perm][:n]
+    mu = workloads.gp_draw_grid(40, 1.0, 0.05, 0.5, 1e-8, rng)[0][perm][:n]
+    kern = (1.0, 0.05, 0.5, 1e-8)
+    a, b = np.full(n, -np.inf), -mu
+    opts = mvn.options(tile=tile, tlr_eps=1e-5, max_rank=128, sweep_rows=rows)
+    f = mvn.mvn_cholesky(n, locs=locs, kern=kern, opts=opts, device=DEV)
+    r = mvn.mvn_prob_prefix(f, a, b, None, N=N, S=S, seed=seed, opts=opts)
+    full = mvn.mvn_prob(f, a, b, None, N=N, S=S, seed=seed, opts=opts)
+    torch.cuda.synchronize()
+    assert f.info() == 0
+    assert f.ranks().cpu().numpy().max() > 16
+    logp = r["logP"].cpu().numpy()
+    L = _dense_from_tlr(f)
+    at, bt = oracle.centre(a, b)
+    ref = oracle.prefix_probs(L, at, bt, N, S, seed)
+    err = np.abs(logp - ref["logP"]) / np.maximum(1.0, np.abs(ref["logP"]))
+    print(f"max rel err {err.max():.3e}; last {logp[-1]} full {full['logP'].item()}", flush=True)
+    assert err.max() < 1e-9
+    np.testing.assert_allclose(r["rel_stderr"].cpu().numpy(), ref["rel_stderr"], rtol=1e-6, atol=1e-12)
+    assert abs(logp[-1] - full["logP"].item()) < 1e-12 * max(1.0, abs(logp[-1]))
 
 
 def test_confidence_region_matches_oracle_prefixes():
