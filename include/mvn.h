@@ -205,6 +205,35 @@ int mvn_prob_prefix(const mvn_factor* f, const double* d_a, const double* d_b, c
                     int N, int S, uint64_t seed, const mvn_options* opts, void* ws, size_t ws_bytes,
                     double* d_prefix, hipStream_t stream);
 
+/* Monte Carlo check of nested-set probabilities (Section IV-B, the check of
+ * detected confidence regions by direct sampling): M fields X = mu + L Z
+ * from the fitted distribution, for the sites in the factor's order, and for
+ * each nested set (the first k sites) the number of fields inside the limits
+ * on all of its sites.  Z is standard normal from a counter-based generator:
+ *   Z[i, j] = Phi^-1(U),  U = ((SplitMix64 output j n + i from state `seed`)
+ *             >> 11) + 1/2) 2^-53          (site i, sample j; 0-based)
+ * so a sample can be redrawn on its own.  FP64 (dense factors of any
+ * precision: their FP64 L is used).
+ *   d_a, d_b  device, n doubles: the limits; the interval is closed, a NaN
+ *             limit never holds
+ *   d_mu      device mean (n doubles) or NULL for zero
+ *   M         >= 1 samples
+ *   d_first   device, M ints, or NULL: per sample, the first site (0-based)
+ *             with X outside [a, b], n if none; -1 if the factor's info != 0
+ *   d_count   device, n int64: [k - 1] = number of samples inside the limits
+ *             on the first k sites (= number with first failure >= k);
+ *             all -1 if the factor's info != 0
+ * A sample is followed only until it fails, and a group of 64 samples stops
+ * when all of them have: the work is that of the leading rows of L the
+ * samples reach.  opts->sweep_rows: rows per block, 0 = 128, or 64.
+ * TLR factors are rejected (-1).  The workspace is
+ * mvn_mc_prefix_workspace_bytes; nothing is allocated and the stream is not
+ * synchronised.  Returns 0 or a negative argument position. */
+int mvn_mc_prefix_workspace_bytes(int n, int M, const mvn_options* opts, size_t* bytes);
+int mvn_mc_prefix(const mvn_factor* f, const double* d_a, const double* d_b, const double* d_mu, int M,
+                  uint64_t seed, const mvn_options* opts, void* ws, size_t ws_bytes, int* d_first,
+                  int64_t* d_count, hipStream_t stream);
+
 /* Gradient of log P-hat at fixed QMC points (the same estimator and points
  * as mvn_prob): reverse-mode differentiation of the recurrence of Eq. (sov1),
  * with checkpointed shifts s_i instead of stored y.  FP64.

@@ -19,6 +19,7 @@ from ._lib import (MVN_BF16, MVN_BF16X3, MVN_FACTOR_TLR, MVN_FP32, MVN_FP64, Mvn
 __all__ = ["mvn_factor_bytes", "mvn_cholesky_workspace_bytes", "mvn_prob_workspace_bytes",
            "mvn_prob_workspace_bytes_factor", "mvn_cholesky", "mvn_prob", "Factor",
            "mvn_prob_prefix_workspace_bytes", "mvn_prob_prefix", "confidence_region",
+           "mvn_mc_prefix_workspace_bytes", "mvn_mc_prefix",
            "mvn_prob_grad_workspace_bytes", "mvn_prob_grad", "MVNLogProb", "BatchPlan",
            "mvn_batch_plan", "mvn_prob_batch",
            "options", "MvnError", "MVN_FP64", "MVN_FP32", "MVN_BF16", "MVN_BF16X3", "library_path"]
@@ -224,8 +225,38 @@ def mvn_prob_prefix(f: Factor, a, b, mu=None, N: int = 1000, S: int = 10, seed: 
     return {"logP": out[0::2], "rel_stderr": out[1::2], "out": out, "_keep": (ta, tb, tm, workspace)}
 
 
+def mvn_mc_prefix_workspace_bytes(n: int, M: int, opts: MvnOptions | None = None) -> int:
+    out = ctypes.c_size_t(0)
+    _lib.check(_lib.lib().mvn_mc_prefix_workspace_bytes(n, M, ctypes.byref(opts or options()), ctypes.byref(out)))
+    return out.value
+
+
+def mvn_mc_prefix(f: Factor, a, b, mu=None, M: int = 50000, seed: int = 1, opts: MvnOptions | None = None,
+                  workspace=None, return_first: bool = True):
+    """Monte Carlo check of the nested sets: M fields X = mu + L Z, per
+    sample the first site outside [a, b] (n if none), per prefix k the
+    number of samples inside on the first k sites.  Returns a dict of device
+    tensors: count[n] (int64), first[M] (int32, if asked)."""
+    torch = _torch()
+    opts = opts or options()
+    dev = f.device
+    ta, tb = _dev_f64(a, dev), _dev_f64(b, dev)
+    tm = _dev_f64(mu, dev) if mu is not None else None
+    wsb = mvn_mc_prefix_workspace_bytes(f.n, M, opts)
+    if workspace is None or workspace.numel() < wsb:
+        workspace = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    count = torch.empty(f.n, dtype=torch.int64, device=dev)
+    first = torch.empty(M, dtype=torch.int32, device=dev) if return_first else None
+    code = _lib.lib().mvn_mc_prefix(ctypes.byref(f.handle), _ptr(ta), _ptr(tb), _ptr(tm), M, ctypes.c_uint64(seed),
+                                    ctypes.byref(opts), _ptr(workspace), wsb, _ptr(first), _ptr(count),
+                                    _stream(dev))
+    _lib.check(code)
+    return {"count": count, "first": first, "_keep": (ta, tb, tm, workspace)}
+
+
 def confidence_region(locs, kern: tuple, mu, u: float, alpha: float = 0.05, N: int = 1000, S: int = 10,
-                      seed: int = 1, opts: MvnOptions | None = None, device="cuda"):
+                      seed: int = 1, opts: MvnOptions | None = None, device="cuda", mc_samples: int = 0,
+                      mc_seed: int = 2):
     """Positive excursion set of a Gaussian field at level u with joint
     probability >= 1 - alpha (Section III-A, Algorithm 1): the sites in order
     of decreasing marginal exceedance probability P(X_i > u), the factor of
@@ -234,7 +265,11 @@ def confidence_region(locs, kern: tuple, mu, u: float, alpha: float = 0.05, N: i
     first k sites; the region is the longest prefix whose P-hat >= 1 - alpha.
     kern = (sigma2, beta, nu, nugget).  Returns a dict with ``order``,
     ``logP`` (per prefix), ``excursion`` (per site, in the caller's site
-    order) and ``region`` (site indices)."""
+    order) and ``region`` (site indices).  With mc_samples > 0 (dense
+    factors) the region is checked by direct sampling on the same factor
+    (Section IV-B): ``mc_p`` is the fraction of sampled fields above u on
+    the first k sites, per k, and ``mc_p_region`` that fraction for the
+    region, expected near 1 - alpha."""
     import numpy as np
     from scipy.special import ndtr
     sigma2, beta, nu, nugget = kern
@@ -250,8 +285,15 @@ def confidence_region(locs, kern: tuple, mu, u: float, alpha: float = 0.05, N: i
     excursion = np.empty(n)
     excursion[order] = np.exp(logp)
     k = int(np.sum(np.exp(logp) >= 1.0 - alpha))  # the prefixes do not increase
-    return {"order": order, "logP": logp, "rel_stderr": r["rel_stderr"].cpu().numpy(), "excursion": excursion,
-            "region": np.sort(order[:k]), "info": f.info()}
+    out = {"order": order, "logP": logp, "rel_stderr": r["rel_stderr"].cpu().numpy(), "excursion": excursion,
+           "region": np.sort(order[:k]), "info": f.info()}
+    if mc_samples > 0:
+        m = mvn_mc_prefix(f, np.full(n, float(u)), np.full(n, np.inf), mu[order], M=mc_samples, seed=mc_seed,
+                          opts=opts, return_first=False)
+        p = m["count"].cpu().numpy() / float(mc_samples)
+        out["mc_p"] = p
+        out["mc_p_region"] = float(p[k - 1]) if k > 0 else 1.0
+    return out
 
 
 def mvn_prob_grad_workspace_bytes(n: int, N: int, S: int, opts: MvnOptions | None = None) -> int:

@@ -55,6 +55,9 @@ SIGNATURES = {
                                                  POINTER(c_size_t), c_void_p]),
     "mvn_prob_prefix": (c_int, [POINTER(MvnFactor), c_void_p, c_void_p, c_void_p, c_int, c_int, c_uint64,
                                 POINTER(MvnOptions), c_void_p, c_size_t, c_void_p, c_void_p]),
+    "mvn_mc_prefix_workspace_bytes": (c_int, [c_int, c_int, POINTER(MvnOptions), POINTER(c_size_t)]),
+    "mvn_mc_prefix": (c_int, [POINTER(MvnFactor), c_void_p, c_void_p, c_void_p, c_int, c_uint64,
+                              POINTER(MvnOptions), c_void_p, c_size_t, c_void_p, c_void_p, c_void_p]),
     "mvn_cholesky": (c_int, [c_int, c_void_p, c_int, c_void_p, POINTER(MvnMatern), POINTER(MvnOptions),
                              c_void_p, c_size_t, c_void_p, c_size_t, POINTER(MvnFactor), c_void_p]),
     "mvn_prob": (c_int, [POINTER(MvnFactor), c_void_p, c_void_p, c_void_p, c_int, c_int, c_uint64,

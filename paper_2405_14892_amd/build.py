@@ -20,14 +20,15 @@ LIB = os.path.join(HERE, "libmvn.so")
 ARCH = os.environ.get("MVN_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["api.cpp", "kernels_chol.hip", "kernels_sov.hip", "kernels_grad.hip", "kernels_tlr.hip",
-           "kernels_tlr_sweep.hip"]
+           "kernels_tlr_sweep.hip", "kernels_mc.hip"]
 
 # Per-file extra flags.  The sweep inlines the FP64 conditioning step into
 # its row loop; machine loop-invariant code motion would hoist the step's
 # ~60 materialised 64-bit constants out of that loop and spill registers.
 EXTRA_FLAGS = {"kernels_sov.hip": ["-mllvm", "-disable-machine-licm"],
                "kernels_grad.hip": ["-mllvm", "-disable-machine-licm"],
-               "kernels_tlr_sweep.hip": ["-mllvm", "-disable-machine-licm"]}
+               "kernels_tlr_sweep.hip": ["-mllvm", "-disable-machine-licm"],
+               "kernels_mc.hip": ["-mllvm", "-disable-machine-licm"]}
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -166,6 +166,31 @@ PrefixRegion prefix_region(int n, int N, int S) {
   return P;
 }
 
+// Workspace of a Monte Carlo check: first-failure bins, the work counter and
+// the per-workgroup Z scratch.
+struct McLayout {
+  size_t hist, counter, yscr, total;
+  int grid, rows;
+  long yslice;
+};
+
+int mc_rows(const mvn_options* o) { return (!o || o->sweep_rows == 0) ? 128 : o->sweep_rows; }
+
+McLayout mc_layout(int n, long M, int rows) {
+  McLayout L{};
+  L.rows = rows;
+  const long chunks = (M + mvn::sweep_tile_cols() - 1) / mvn::sweep_tile_cols();
+  const long gmax = (long)kCUs * mvn::mc_wg_per_cu(rows);
+  L.grid = (int)(chunks < gmax ? chunks : gmax);
+  L.yslice = (long)padded(n) * mvn::sweep_tile_cols();
+  size_t off = 0;
+  L.hist = off; off = align_up(off + sizeof(unsigned long long) * ((size_t)n + 1));
+  L.counter = off; off = align_up(off + sizeof(unsigned long long));
+  L.yscr = off; off = align_up(off + sizeof(double) * (size_t)L.grid * (size_t)L.yslice);
+  L.total = off;
+  return L;
+}
+
 // ---------------------------------------------------------------- tile low rank
 // Factor buffer of a TLR factor: tiles | info | U | Vt (+128 rows) | ranks.
 struct TlrGeom {
@@ -648,6 +673,53 @@ int mvn_prob_prefix(const mvn_factor* f, const double* d_a, const double* d_b, c
   const hipError_t e = mvn::launch_prefix_reduce(part, R.nchunks, f->n, N, S, (double*)(w + R.lps), f->info, bad,
                                                  d_prefix, stream);
   if (e != hipSuccess) return hip_fail(e, "prefix reduce");
+  return 0;
+}
+
+int mvn_mc_prefix_workspace_bytes(int n, int M, const mvn_options* opts, size_t* bytes) {
+  if (n < 1) return fail(-1, "n must be >= 1 (got %d)", n);
+  if (M < 1) return fail(-2, "M must be >= 1 (got %d)", M);
+  if (!sweep_rows_ok(opts)) return fail(-3, "sweep_rows must be 0, 64 or 128 (got %d)", opts->sweep_rows);
+  if (!bytes) return fail(-4, "bytes is NULL");
+  *bytes = mc_layout(n, M, mc_rows(opts)).total;
+  return 0;
+}
+
+int mvn_mc_prefix(const mvn_factor* f, const double* d_a, const double* d_b, const double* d_mu, int M,
+                  uint64_t seed, const mvn_options* opts, void* ws, size_t ws_bytes, int* d_first, int64_t* d_count,
+                  hipStream_t stream) {
+  if (!f || !f->L || !f->info || f->n < 1) return fail(-1, "invalid factor handle");
+  if (f->flags & MVN_FACTOR_TLR) return fail(-1, "the Monte Carlo check needs a dense factor");
+  if (f->ld != padded(f->n)) return fail(-1, "invalid factor handle");
+  if (!d_a) return fail(-2, "lower limits are NULL");
+  if (!d_b) return fail(-3, "upper limits are NULL");
+  if (M < 1) return fail(-5, "M must be >= 1 (got %d)", M);
+  if (!sweep_rows_ok(opts)) return fail(-7, "sweep_rows must be 0, 64 or 128 (got %d)", opts->sweep_rows);
+  const McLayout Lay = mc_layout(f->n, M, mc_rows(opts));
+  if (!ws) return fail(-8, "workspace is NULL");
+  if (ws_bytes < Lay.total) return fail(-9, "workspace too small: %zu < %zu", ws_bytes, Lay.total);
+  if (!d_count) return fail(-11, "count output is NULL");
+  char* w = (char*)ws;
+  mvn::McArgs a{};
+  a.L = f->L;
+  a.ld = f->ld;
+  a.n = f->n;
+  a.a = d_a;
+  a.b = d_b;
+  a.mu = d_mu;
+  a.seed = seed;
+  a.M = M;
+  a.yscr = (double*)(w + Lay.yscr);
+  a.yslice = Lay.yslice;
+  a.first = d_first;
+  a.hist = (unsigned long long*)(w + Lay.hist);
+  a.counter = (unsigned long long*)(w + Lay.counter);
+  a.count = (long long*)d_count;
+  a.info = f->info;
+  a.grid = Lay.grid;
+  a.rows = Lay.rows;
+  const hipError_t e = mvn::launch_mc(a, stream);
+  if (e != hipSuccess) return hip_fail(e, "Monte Carlo check");
   return 0;
 }
 

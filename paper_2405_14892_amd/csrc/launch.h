@@ -40,6 +40,31 @@ hipError_t launch_cholesky_f64(int ld, int tile, double* A, int* info, hipStream
 hipError_t launch_cholesky_lp(int prec, int ld, int tile, double* A, int* info, void* low,
                               hipStream_t st);
 
+// Monte Carlo check of nested sets: fields X = mu + L Z (dense FP64 factor),
+// per sample the first site outside [a, b] (n if none), and per prefix the
+// number of samples inside on all of its sites.
+struct McArgs {
+  const double* L;
+  int ld;
+  int n;
+  const double* a;           // n limits each (device); mu may be nullptr
+  const double* b;
+  const double* mu;
+  uint64_t seed;             // Z[i, j] from SplitMix64 output j n + i of this state
+  long M;                    // samples
+  double* yscr;              // per-workgroup Z scratch, grid x yslice doubles
+  long yslice;               // ld x 64
+  int* first;                // M (or nullptr)
+  unsigned long long* hist;  // n + 1 bins of first failures (cleared here)
+  unsigned long long* counter;  // work-item counter (cleared here)
+  long long* count;          // n: samples inside the limits on sites 0..k
+  const int* info;           // factor status: != 0 gives first = -1, count = -1
+  int grid;                  // workgroups
+  int rows;                  // 64 or 128 rows per block
+};
+int mc_wg_per_cu(int rows);
+hipError_t launch_mc(const McArgs& a, hipStream_t st);
+
 struct SweepArgs {
   const double* L;         // FP64 factor (diagonal blocks, pivots)
   const void* Llow;        // factor in the GEMM's operand type (== L for FP64)

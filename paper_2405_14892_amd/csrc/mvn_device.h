@@ -295,6 +295,14 @@ MVN_HD uint64_t splitmix64(uint64_t seed, uint64_t k) {
   return z ^ (z >> 31);
 }
 
+// Standard normal number k from the counter-based stream of `seed`:
+// Phi^-1(U), U = ((SplitMix64 output k) >> 11) + 1/2) 2^-53, Phi^-1 by AS 241
+// (the upper half by symmetry; 1 - U is exact there).
+MVN_HD double normal_from_counter(uint64_t seed, uint64_t k) {
+  const double u = ((double)(splitmix64(seed, k) >> 11) + 0.5) * 0x1.0p-53;
+  return u <= 0.5 ? ninv_lower(u) : -ninv_lower(1.0 - u);
+}
+
 // Richtmyer point j (1-based) of dimension with generator A and shift D.
 MVN_HD double richtmyer(uint64_t j, uint64_t A, uint64_t D, int periodize) {
   const uint64_t x = j * A + D;

@@ -50,6 +50,10 @@ int main() {
       unsigned long long seed, k;
       scanf("%llu %llu", &seed, &k);
       printf("%llu\n", (unsigned long long)mvn::splitmix64(seed, k));
+    } else if (!strcmp(op, "mcn")) {  // normal number k of the counter-based stream
+      unsigned long long seed, k;
+      scanf("%llu %llu", &seed, &k);
+      printf("%.17g\n", mvn::normal_from_counter(seed, k));
     }
   }
   return 0;

@@ -108,6 +108,35 @@ def test_splitmix64_matches_published_outputs(harness):
     assert got == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
 
 
+def test_counter_normals_match_oracle_draws(harness):
+    """The device's normal draws (AS 241 on the SplitMix64 uniform) against
+    the oracle's (scipy's inverse normal on the same uniform), over sites
+    and samples of a 7-site field, tails included."""
+    from oracle import mc
+    n, cols, seed = 7, np.array([0, 1, 5, 1000, 123456]), 99
+    ref = mc.normals(seed, n, cols)
+    lines = [f"mcn {seed} {int(j) * n + i}" for j in cols for i in range(n)]
+    got = np.array([float(v) for v in _run(harness, lines)]).reshape(len(cols), n).T
+    np.testing.assert_allclose(got, ref, rtol=2e-15, atol=1e-15)
+    # deep tail: the smallest and largest uniforms the stream can give
+    z = [float(v) for v in _run(harness, ["ninv 5.551115123125783e-17"])]
+    assert abs(z[0] - sp.ndtri(2.0 ** -54)) < 1e-13
+
+
+def test_mc_workspace_query_needs_no_device():
+    n, M = 1000, 50_000
+    ws = mvn.mvn_mc_prefix_workspace_bytes(n, M)
+    # per-workgroup Z scratch (1024 x 64 doubles for n = 1000) for min(chunks, 512) workgroups
+    # (128-row blocks, two per CU; 64-row blocks: four per CU)
+    assert ws >= min((M + 63) // 64, 256 * 2) * 1024 * 64 * 8 + (n + 1) * 8
+    ws64 = mvn.mvn_mc_prefix_workspace_bytes(n, M, mvn.options(sweep_rows=64))
+    assert ws64 >= min((M + 63) // 64, 256 * 4) * 1024 * 64 * 8 + (n + 1) * 8
+    assert mvn.mvn_mc_prefix_workspace_bytes(n, 64) >= 1024 * 64 * 8
+    with pytest.raises(mvn.MvnError) as e:
+        mvn.mvn_mc_prefix_workspace_bytes(0, 10)
+    assert e.value.code == -1
+
+
 def test_ctypes_structs_match_the_c_header(tmp_path):
     """sizeof / offsetof of the public structs, from the C compiler, equal the
     ctypes mirrors the binding passes by reference."""
