@@ -44,7 +44,11 @@ typedef enum { MVN_FP64 = 0, MVN_FP32 = 1, MVN_BF16 = 2, MVN_BF16X3 = 3 } mvn_pr
 /* Matern covariance parameters (Section III-C, Eq. for C(h; theta)):
  * C(h) = sigma2 / (2^(nu-1) Gamma(nu)) (h/beta)^nu K_nu(h/beta), plus
  * nugget on the diagonal.  The paper calls the range "a"; here it is beta.
- * Supported nu: 0.5 and 1.5 (closed forms). */
+ * Any 0 < nu <= 20: nu = 0.5, 1.5, 2.5 by the closed forms of K_nu at
+ * half-integer order; other nu by the trapezoidal rule on the integral
+ * K_nu(x) = int_0^inf exp(-x cosh t) cosh(nu t) dt, relative accuracy about
+ * 1e-14 (up to 1e-13 where the result is below 1e-250).  Other values are
+ * rejected with the position of the kernel argument. */
 typedef struct mvn_matern {
   double sigma2, beta, nu, nugget;
 } mvn_matern;

@@ -48,6 +48,11 @@ int max_grid(int rows, int prec) { return kCUs * mvn::sweep_wg_per_cu(rows, prec
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 int padded(int n) { return (n + 127) / 128 * 128; }
 
+// Kernel parameters for the build kernels (unused when Sigma is given).
+mvn::Matern matern_of(const mvn_matern* k) {
+  return k ? mvn::make_matern(k->sigma2, k->beta, k->nu, k->nugget) : mvn::make_matern(1.0, 1.0, 0.5, 0.0);
+}
+
 int elem_bytes_low(int prec) { return prec == MVN_FP32 ? 4 : prec == MVN_BF16 ? 2 : prec == MVN_BF16X3 ? 4 : 0; }
 bool prec_ok(int prec) { return prec >= MVN_FP64 && prec <= MVN_BF16X3; }
 
@@ -743,10 +748,9 @@ int mvn_cholesky(int n, const double* d_sigma, int ld_sigma, const double* d_loc
   if (!d_sigma) {
     if (!d_locs) return fail(-4, "either sigma or locations are required");
     if (!kern) return fail(-5, "kernel parameters are required with locations");
-    if (!(kern->nu == 0.5 || kern->nu == 1.5))
-      return fail(-5, "Matern smoothness nu must be 0.5 or 1.5 (got %g)", kern->nu);
-    if (!(kern->sigma2 > 0) || !(kern->beta > 0) || !(kern->nugget >= 0))
-      return fail(-5, "Matern parameters need sigma2 > 0, beta > 0, nugget >= 0");
+    if (!mvn::matern_ok(kern->sigma2, kern->beta, kern->nu, kern->nugget))
+      return fail(-5, "Matern parameters need sigma2 > 0, beta > 0, 0 < nu <= 20, nugget >= 0 (got %g, %g, %g, %g)",
+                  kern->sigma2, kern->beta, kern->nu, kern->nugget);
   }
   if (!opts) return fail(-6, "options are required");
   int bad_tile = 0;
@@ -777,9 +781,8 @@ int mvn_cholesky(int n, const double* d_sigma, int ld_sigma, const double* d_loc
     out->ranks = (int*)(fb + G.ranks);
     out->tlr_eps = opts->tlr_eps;
     out->max_rank = opts->max_rank;
-    hipError_t e = mvn::launch_tlr_build(n, G.m, G.nt, d_sigma, ld_sigma, d_locs, kern ? kern->sigma2 : 0,
-                                         kern ? kern->beta : 1, kern ? kern->nu : 0.5, kern ? kern->nugget : 0,
-                                         out->L, out->info, stream);
+    hipError_t e = mvn::launch_tlr_build(n, G.m, G.nt, d_sigma, ld_sigma, d_locs, matern_of(kern), out->L,
+                                         out->info, stream);
     if (e != hipSuccess) return hip_fail(e, "tlr build");
     mvn::TlrCholArgs a{};
     a.tiles = out->L;
@@ -825,9 +828,7 @@ int mvn_cholesky(int n, const double* d_sigma, int ld_sigma, const double* d_loc
   out->tlr_eps = 0;
   out->max_rank = 0;
   out->reserved1 = 0;
-  hipError_t e = mvn::launch_build_matrix(n, ld, d_sigma, ld_sigma, d_locs, kern ? kern->sigma2 : 0,
-                                          kern ? kern->beta : 1, kern ? kern->nu : 0.5,
-                                          kern ? kern->nugget : 0, L, info, stream);
+  hipError_t e = mvn::launch_build_matrix(n, ld, d_sigma, ld_sigma, d_locs, matern_of(kern), L, info, stream);
   if (e != hipSuccess) return hip_fail(e, "build_matrix");
   e = opts->precision == MVN_FP64 ? mvn::launch_cholesky_f64(ld, opts->tile, L, info, stream)
                                   : mvn::launch_cholesky_lp(opts->precision, ld, opts->tile, L, info, low, stream);
@@ -961,9 +962,8 @@ int mvn_prob_batch(int count, const int* n_p, const void* d_plan, const int64_t*
   if (!d_plan) return fail(-3, "plan is NULL");
   if (!d_idx) return fail(-4, "location indices are NULL");
   if (!d_locs) return fail(-5, "locations are NULL");
-  if (!kern || !(kern->nu == 0.5 || kern->nu == 1.5) || !(kern->sigma2 > 0) || !(kern->beta > 0) ||
-      !(kern->nugget >= 0))
-    return fail(-6, "Matern parameters need nu in {0.5, 1.5}, sigma2 > 0, beta > 0, nugget >= 0");
+  if (!kern || !mvn::matern_ok(kern->sigma2, kern->beta, kern->nu, kern->nugget))
+    return fail(-6, "Matern parameters need sigma2 > 0, beta > 0, 0 < nu <= 20, nugget >= 0");
   if (!d_a) return fail(-7, "lower limits are NULL");
   if (!d_b) return fail(-8, "upper limits are NULL");
   if (N < 1) return fail(-10, "N must be >= 1 (got %d)", N);
@@ -998,8 +998,7 @@ int mvn_prob_batch(int count, const int* n_p, const void* d_plan, const int64_t*
   unsigned long long* counter = (unsigned long long*)(w + W.counter);
   hipError_t e = hipMemcpyAsync(dlat, lat, sizeof(uint64_t) * P.ldmax, hipMemcpyHostToDevice, stream);
   if (e != hipSuccess) return hip_fail(e, "lattice copy");
-  e = mvn::launch_batch_build(desc, count, P.total_tiles, d_idx, d_locs, kern->sigma2, kern->beta, kern->nu,
-                              kern->nugget, factor, d_info, stream);
+  e = mvn::launch_batch_build(desc, count, P.total_tiles, d_idx, d_locs, matern_of(kern), factor, d_info, stream);
   if (e != hipSuccess) return hip_fail(e, "batch build");
   e = mvn::launch_batch_cholesky(prec, desc, order, P.ld_rank.data(), count, factor, d_info, low,
                                  P.factor_elems, stream);

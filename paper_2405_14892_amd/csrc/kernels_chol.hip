@@ -24,8 +24,7 @@ constexpr int kSub = 32;  // sub-panel width
 // ------------------------------------------------------------ covariance
 __global__ __launch_bounds__(256) void build_matrix_kernel(int n, int ld, const double* __restrict__ sigma,
                                                            int lds, const double* __restrict__ locs,
-                                                           double sigma2, double beta, double nu,
-                                                           double nugget, double* __restrict__ A,
+                                                           Matern mk, double* __restrict__ A,
                                                            int* __restrict__ info) {
   if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *info = 0;
   const long i = (long)blockIdx.y * 16 + (threadIdx.x >> 4);
@@ -39,19 +38,16 @@ __global__ __launch_bounds__(256) void build_matrix_kernel(int n, int ld, const 
   } else {
     const double dx = locs[2 * i] - locs[2 * j];
     const double dy = locs[2 * i + 1] - locs[2 * j + 1];
-    const double z = sqrt(dx * dx + dy * dy) / beta;
-    v = (nu == 0.5) ? sigma2 * exp(-z) : sigma2 * (1.0 + z) * exp(-z);
-    if (i == j) v += nugget;
+    v = matern_cov(mk, sqrt(dx * dx + dy * dy));
+    if (i == j) v += mk.nugget;
   }
   A[i * ld + j] = v;
 }
 
-hipError_t launch_build_matrix(int n, int ld, const double* sigma, int lds, const double* locs,
-                               double sigma2, double beta, double nu, double nugget, double* A,
-                               int* info, hipStream_t st) {
+hipError_t launch_build_matrix(int n, int ld, const double* sigma, int lds, const double* locs, const Matern& mk,
+                               double* A, int* info, hipStream_t st) {
   dim3 grid(ld / 16, ld / 16);
-  hipLaunchKernelGGL(build_matrix_kernel, grid, dim3(256), 0, st, n, ld, sigma, lds, locs, sigma2,
-                     beta, nu, nugget, A, info);
+  hipLaunchKernelGGL(build_matrix_kernel, grid, dim3(256), 0, st, n, ld, sigma, lds, locs, mk, A, info);
   return hipGetLastError();
 }
 
@@ -757,8 +753,7 @@ __device__ __forceinline__ int batch_find(const BatchDesc* desc, int count, long
 
 __global__ __launch_bounds__(256) void batch_build_kernel(const BatchDesc* __restrict__ desc, int count,
                                                           const int64_t* __restrict__ idx,
-                                                          const double* __restrict__ locs, double sigma2,
-                                                          double beta, double nu, double nugget,
+                                                          const double* __restrict__ locs, Matern mk,
                                                           double* __restrict__ factor, int* __restrict__ info) {
   const long b = blockIdx.x;
   const int p = batch_find(desc, count, b);
@@ -781,19 +776,17 @@ __global__ __launch_bounds__(256) void batch_build_kernel(const BatchDesc* __res
       const long gi = ix[i], gj = ix[j];
       const double dx = locs[2 * gi] - locs[2 * gj];
       const double dy = locs[2 * gi + 1] - locs[2 * gj + 1];
-      const double z = sqrt(dx * dx + dy * dy) / beta;
-      v = (nu == 0.5) ? sigma2 * exp(-z) : sigma2 * (1.0 + z) * exp(-z);
-      if (i == j) v += nugget;
+      v = matern_cov(mk, sqrt(dx * dx + dy * dy));
+      if (i == j) v += mk.nugget;
     }
     A[i * d.ld + j] = v;
   }
 }
 
 hipError_t launch_batch_build(const BatchDesc* desc, int count, long total_tiles, const int64_t* idx,
-                              const double* locs, double sigma2, double beta, double nu, double nugget,
-                              double* factor, int* info, hipStream_t st) {
+                              const double* locs, const Matern& mk, double* factor, int* info, hipStream_t st) {
   hipLaunchKernelGGL(batch_build_kernel, dim3((unsigned)total_tiles), dim3(256), 0, st, desc, count, idx,
-                     locs, sigma2, beta, nu, nugget, factor, info);
+                     locs, mk, factor, info);
   return hipGetLastError();
 }
 

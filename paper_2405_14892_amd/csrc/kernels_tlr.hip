@@ -57,8 +57,7 @@ __device__ __forceinline__ void tri_inverse(long b, long& i, long& j) {
 // ------------------------------------------------------------ build
 // One 64 x 64 sub-block of one lower tile per workgroup; clears *info.
 __global__ __launch_bounds__(256) void tlr_build_kernel(int n, int m, const double* __restrict__ sigma, int lds,
-                                                        const double* __restrict__ locs, double sigma2,
-                                                        double beta, double nu, double nugget,
+                                                        const double* __restrict__ locs, Matern mk,
                                                         double* __restrict__ tiles, int* __restrict__ info) {
   const long per = (long)(m / 64) * (m / 64);
   const long t = blockIdx.x / per, sb = blockIdx.x % per;
@@ -78,9 +77,8 @@ __global__ __launch_bounds__(256) void tlr_build_kernel(int n, int m, const doub
     } else {
       const double dx = locs[2 * i] - locs[2 * j];
       const double dy = locs[2 * i + 1] - locs[2 * j + 1];
-      const double z = sqrt(dx * dx + dy * dy) / beta;
-      v = (nu == 0.5) ? sigma2 * exp(-z) : sigma2 * (1.0 + z) * exp(-z);
-      if (i == j) v += nugget;
+      v = matern_cov(mk, sqrt(dx * dx + dy * dy));
+      if (i == j) v += mk.nugget;
     }
     A[lr * m + lc] = v;
   }
@@ -551,11 +549,10 @@ __global__ void tlr_info_kernel(int* __restrict__ info, const int* __restrict__ 
 }
 
 hipError_t launch_tlr_build(int n, int m, int nt, const double* sigma, int lds, const double* locs,
-                            double sigma2, double beta, double nu, double nugget, double* tiles, int* info,
-                            hipStream_t st) {
+                            const Matern& mk, double* tiles, int* info, hipStream_t st) {
   const long sub = (long)(m / 64) * (m / 64) * ((long)nt * (nt + 1) / 2);
-  hipLaunchKernelGGL(tlr_build_kernel, dim3((unsigned)sub), dim3(256), 0, st, n, m, sigma, lds, locs, sigma2,
-                     beta, nu, nugget, tiles, info);
+  hipLaunchKernelGGL(tlr_build_kernel, dim3((unsigned)sub), dim3(256), 0, st, n, m, sigma, lds, locs, mk, tiles,
+                     info);
   return hipGetLastError();
 }
 

@@ -5,14 +5,15 @@
 
 #include <mutex>
 
+#include "matern.h"
+
 namespace mvn {
 
 // Lower triangle of the padded ld x ld matrix A (row-major) from the caller's
 // Sigma (row stride lds) or from locations with the Matern kernel; rows and
 // columns n..ld-1 become the identity.  Also clears *info.
-hipError_t launch_build_matrix(int n, int ld, const double* sigma, int lds, const double* locs,
-                               double sigma2, double beta, double nu, double nugget, double* A,
-                               int* info, hipStream_t st);
+hipError_t launch_build_matrix(int n, int ld, const double* sigma, int lds, const double* locs, const Matern& mk,
+                               double* A, int* info, hipStream_t st);
 
 // A second stream of the current device (default priority, non-blocking)
 // with three events, for work that overlaps the caller's stream inside one
@@ -145,8 +146,7 @@ static_assert(sizeof(BatchDesc) == 40, "descriptor layout");
 // problem (one 64 x 64 tile per workgroup, flat over all problems); clears
 // info[p].
 hipError_t launch_batch_build(const BatchDesc* desc, int count, long total_tiles, const int64_t* idx,
-                              const double* locs, double sigma2, double beta, double nu, double nugget,
-                              double* factor, int* info, hipStream_t st);
+                              const double* locs, const Matern& mk, double* factor, int* info, hipStream_t st);
 
 // Tiled Cholesky (tile 128) of every problem, one launch per step for all
 // problems that still have that step.  ld_rank[r] is the padded size of the
@@ -190,8 +190,7 @@ constexpr long kTlrPairBatch = 256; // tile pairs per update launch (sizes the W
 // Lower tiles of Sigma (tile-major, m x m each, identity past n) from the
 // caller's Sigma or from locations with the Matern kernel; clears *info.
 hipError_t launch_tlr_build(int n, int m, int nt, const double* sigma, int lds, const double* locs,
-                            double sigma2, double beta, double nu, double nugget, double* tiles, int* info,
-                            hipStream_t st);
+                            const Matern& mk, double* tiles, int* info, hipStream_t st);
 
 struct TlrCholArgs {
   double* tiles;     // nt(nt+1)/2 tiles of m x m

@@ -1,0 +1,70 @@
+// Matern covariance of arXiv 2405.14892, Section III-C (the equation for
+// C(||h||; theta)), as printed: C(h) = sigma^2 / (2^(nu-1) Gamma(nu))
+// (h/beta)^nu K_nu(h/beta), C(0) = sigma^2, with K_nu the modified Bessel
+// function of the second kind.  (The paper calls the range "a".)
+//
+// nu = 1/2, 3/2, 5/2 use the closed forms of K_nu at half-integer order:
+// sigma^2 e^-z, sigma^2 (1 + z) e^-z, sigma^2 (1 + z + z^2/3) e^-z.
+// Any other nu evaluates K_nu from its integral representation
+//   K_nu(x) = int_0^inf exp(-x cosh t) cosh(nu t) dt          (DLMF 10.32.9)
+// by the trapezoidal rule.  The integrand is entire and decays
+// double-exponentially, so the rule converges exponentially in 1/h
+// (Trefethen and Weideman, SIAM Review 56, 2014); its width shrinks like
+// 1/sqrt(x) for large x, hence the step h = 0.15 min(1, 1/sqrt(x)).  All
+// terms are positive (no cancellation).  To stay in range for small x and
+// large nu, the sum is formed in units of the integrand's maximum, at
+// t* = asinh(nu / x), and the covariance is assembled in log space.
+// Relative accuracy about 1e-14 for 0 < nu <= 20 (checked against
+// high-precision values).
+#pragma once
+#include <math.h>
+
+#include "mvn_device.h"
+
+namespace mvn {
+
+struct Matern {
+  double sigma2, beta, nu, nugget;
+  double scale;  // sigma^2 / (2^(nu-1) Gamma(nu)), formed on the host
+};
+
+// log(e^x K_nu(x)) for x > 0, nu >= 0.
+MVN_HD double log_bessel_k_scaled(double nu, double x) {
+  const double h = 0.15 * fmin(1.0, 1.0 / sqrt(x));
+  const double tp = asinh(nu / x);
+  const double shp = sinh(0.5 * tp);
+  const double c = nu * tp - 2.0 * x * shp * shp;  // log of the largest exp(nu t - x (cosh t - 1))
+  // t = 0 carries weight 1/2: cosh(0) = 1, cosh t - 1 = 0
+  double s = 0.5 * exp(-c);
+  for (int k = 1; k < (1 << 14); ++k) {
+    const double t = k * h;
+    const double sh = sinh(0.5 * t);
+    const double g = -2.0 * x * sh * sh - c;  // x (cosh t - 1) = 2 x sinh^2(t/2)
+    const double term = 0.5 * (exp(g + nu * t) + exp(g - nu * t));
+    s += term;
+    if (t > tp && term < 1e-17 * s) break;
+  }
+  return c + log(h * s);
+}
+
+// C(h) without the nugget.
+MVN_HD double matern_cov(const Matern& k, double h) {
+  const double z = h / k.beta;
+  if (k.nu == 0.5) return k.sigma2 * exp(-z);
+  if (k.nu == 1.5) return k.sigma2 * (1.0 + z) * exp(-z);
+  if (k.nu == 2.5) return k.sigma2 * (1.0 + z + z * z / 3.0) * exp(-z);
+  if (!(z > 0.0)) return k.sigma2;
+  return k.scale * exp(k.nu * log(z) - z + log_bessel_k_scaled(k.nu, z));
+}
+
+// Parameters accepted: sigma^2 > 0, beta > 0, 0 < nu <= 20, nugget >= 0.
+inline bool matern_ok(double sigma2, double beta, double nu, double nugget) {
+  return sigma2 > 0 && beta > 0 && nu > 0 && nu <= 20 && nugget >= 0 && isfinite(sigma2) && isfinite(beta) &&
+         isfinite(nugget);
+}
+
+inline Matern make_matern(double sigma2, double beta, double nu, double nugget) {
+  return Matern{sigma2, beta, nu, nugget, sigma2 / (exp2(nu - 1.0) * tgamma(nu))};
+}
+
+}  // namespace mvn

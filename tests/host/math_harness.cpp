@@ -15,6 +15,7 @@ static double host_erfcx(double x) {
 }
 __host__ double erfcx(double x) { return host_erfcx(x); }
 
+#include "../../paper_2405_14892_amd/csrc/matern.h"
 #include "../../paper_2405_14892_amd/csrc/mvn_device.h"
 
 int main() {
@@ -50,6 +51,13 @@ int main() {
       unsigned long long seed, k;
       scanf("%llu %llu", &seed, &k);
       printf("%llu\n", (unsigned long long)mvn::splitmix64(seed, k));
+    } else if (!strcmp(op, "lkv")) {  // log(e^x K_nu(x))
+      scanf("%lf %lf", &x, &y);
+      printf("%.17g\n", mvn::log_bessel_k_scaled(x, y));
+    } else if (!strcmp(op, "matern")) {  // sigma2 beta nu h
+      double s2, be, nu, hh;
+      scanf("%lf %lf %lf %lf", &s2, &be, &nu, &hh);
+      printf("%.17g\n", mvn::matern_cov(mvn::make_matern(s2, be, nu, 0.0), hh));
     } else if (!strcmp(op, "mcn")) {  // normal number k of the counter-based stream
       unsigned long long seed, k;
       scanf("%llu %llu", &seed, &k);

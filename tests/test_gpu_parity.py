@@ -154,9 +154,10 @@ def test_prob_invalid_limits_give_nan():
 def test_host_validation_rejects_bad_arguments():
     n = 20
     locs, kern = _matern_case(n, 1)
-    with pytest.raises(mvn.MvnError) as e:
-        mvn.mvn_cholesky(n, locs=locs, kern=(1.0, 0.1, 2.5, 0.0), device=DEV)
-    assert e.value.code == -5
+    for bad_nu in (0.0, -1.0, 25.0, float("nan")):
+        with pytest.raises(mvn.MvnError) as e:
+            mvn.mvn_cholesky(n, locs=locs, kern=(1.0, 0.1, bad_nu, 0.0), device=DEV)
+        assert e.value.code == -5
     with pytest.raises(mvn.MvnError):
         mvn.mvn_cholesky(n, locs=locs, kern=kern, opts=mvn.options(tile=10), device=DEV)
     f = mvn.mvn_cholesky(n, locs=locs, kern=kern, opts=mvn.options(tile=16), device=DEV)

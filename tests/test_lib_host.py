@@ -123,6 +123,31 @@ def test_counter_normals_match_oracle_draws(harness):
     assert abs(z[0] - sp.ndtri(2.0 ** -54)) < 1e-13
 
 
+def test_matern_general_nu_matches_oracle_and_high_precision(harness):
+    """The device covariance (trapezoidal rule on the integral form of
+    K_nu, compiled for the host) against the oracle (scipy's K_nu, about
+    1e-13) and 40-digit values, at smoothness values off the closed forms,
+    distances from 1e-7 to 60 ranges; the closed forms at nu = 1/2, 3/2, 5/2."""
+    import oracle
+    mp = pytest.importorskip("mpmath")
+    mp.mp.dps = 40
+    beta = 0.05
+    hs = np.concatenate([[1e-7, 1e-5], np.logspace(-3.5, np.log10(3.0), 25)])
+    for nu in (0.05, 0.3, 0.7, 1.0, 1.2, 1.43391, 2.0, 2.5, 3.3, 7.0, 0.5, 1.5):
+        lines = [f"matern 1.3 {beta!r} {nu!r} {float(h)!r}" for h in hs]
+        got = np.array([float(v) for v in _run(harness, lines)])
+        ref = oracle.matern(hs, 1.3, beta, nu)
+        ok = ref > 1e-250
+        np.testing.assert_allclose(got[ok], ref[ok], rtol=5e-13, atol=0, err_msg=f"nu={nu}")
+        for h, g in list(zip(hs, got))[::4]:
+            z = mp.mpf(float(h)) / mp.mpf(beta)
+            hp = 1.3 * z ** nu * mp.besselk(nu, z) / (mp.mpf(2) ** (nu - 1) * mp.gamma(nu))
+            if float(hp) > 1e-250:
+                assert abs(g / float(hp) - 1) < 1e-13, (nu, h)
+    # h = 0 gives sigma^2 for every nu
+    assert [float(v) for v in _run(harness, ["matern 1.3 0.05 1.43391 0", "matern 1.3 0.05 0.3 0"])] == [1.3, 1.3]
+
+
 def test_mc_workspace_query_needs_no_device():
     n, M = 1000, 50_000
     ws = mvn.mvn_mc_prefix_workspace_bytes(n, M)

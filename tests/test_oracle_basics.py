@@ -38,6 +38,32 @@ def test_matern_closed_forms_match_bessel_formula(nu):
     assert oracle.matern(np.array([0.0]), sigma2, beta, nu)[0] == sigma2
 
 
+def test_matern_bessel_branch_at_nu_5_2_is_the_closed_form():
+    """nu = 5/2 is not special-cased in the oracle, so it takes the K_nu
+    branch; the printed formula reduces to sigma^2 (1 + z + z^2/3) e^{-z}
+    there (K_{5/2}(z) = sqrt(pi/(2z)) e^{-z} (1 + 3/z + 3/z^2))."""
+    h = np.linspace(1e-3, 2.0, 300)
+    sigma2, beta = 0.8, 0.21
+    z = h / beta
+    np.testing.assert_allclose(oracle.matern(h, sigma2, beta, 2.5), sigma2 * (1 + z + z * z / 3) * np.exp(-z),
+                               rtol=1e-13, atol=0)
+
+
+def test_matern_general_nu_against_high_precision():
+    """The K_nu branch against 40-digit values (mpmath, independent of
+    scipy's Bessel routines) at the smoothness fitted to the paper's wind
+    data (1.43391) and at 0.7."""
+    mp = pytest.importorskip("mpmath")
+    mp.mp.dps = 40
+    for nu, beta in ((1.43391, 0.005069), (0.7, 0.1)):
+        h = np.array([1e-5, 1e-3, 0.004, 0.02, 0.1, 0.7])
+        got = oracle.matern(h, 1.0, beta, nu)
+        for hv, g in zip(h, got):
+            z = mp.mpf(hv) / mp.mpf(beta)
+            ref = z ** nu * mp.besselk(nu, z) / (mp.mpf(2) ** (nu - 1) * mp.gamma(nu))
+            assert abs(g / float(ref) - 1) < 1e-12, (nu, hv)
+
+
 def test_matern_general_nu_limit():
     """General-nu branch: C(0) = sigma^2 and continuity at h -> 0."""
     c = oracle.matern(np.array([0.0, 1e-9]), 2.0, 0.1, 1.2)
