@@ -19,6 +19,8 @@ What it computes, in the paper's order (arXiv 2405.14892):
 * ``tlr``         - per-tile truncated-SVD compression (Section III-E).
 * ``crd``         - the nested-set probabilities of confidence-region
                     detection (Section III-A, Algorithm 1) from one sweep.
+* ``posterior``   - the posterior covariance and mean of a field observed
+                    with noise at some sites (Section IV-A).
 * ``mc``          - the Monte Carlo check of detected regions (Section IV-B):
                     fields X = mu + L Z and, per nested set, the samples that
                     meet the event on all of its sites.
@@ -33,4 +35,4 @@ from .sov import centre, condition, sweep, reduce_samples, mvn_prob  # noqa: F40
 from .grad import tangent_sweep, logp_directional, logp_fd  # noqa: F401
 from .tlr import compress_tile, tlr_cholesky, tlr_dense  # noqa: F401
 from .crd import sweep_prefix, prefix_probs, exceedance_order  # noqa: F401
-from . import mc  # noqa: F401
+from . import mc, posterior  # noqa: F401
