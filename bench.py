@@ -423,6 +423,63 @@ def variant_crd(dev) -> dict:
                        f"Monte Carlo check: {M} fields X = mu + L Z on the same factor")}
 
 
+def variant_posterior(dev) -> dict:
+    """Confidence regions on the posterior of Section IV-A at the paper's
+    synthetic size: 40 000 grid sites, 6 250 noisy observations (noise sd
+    0.5), exponential kernel with range 0.033 / 0.1 / 0.234; QMC size
+    10 000 (N = 1000 x S = 10); threshold u = 0.5.  Per range: the posterior
+    (bordered partial factorisation), the factor of Sigma_post in exceedance
+    order, the nested-set sweep, and the Monte Carlo check (50 000 fields)."""
+    import numpy as np
+    import torch
+    import paper_2405_14892_amd as mvn
+    import workloads
+    from scipy.special import ndtr
+    u, N, S, M, tile = 0.5, 1000, 10, 50000, 512
+    opts = mvn.options(tile=tile)
+    st = torch.cuda.current_stream(dev)
+    out = {}
+    for beta in (0.033, 0.1, 0.234):
+        d = workloads.make_posterior(beta=beta)
+        kern = (d.sigma2, d.beta, d.nu, d.nugget)
+        n = d.locs.shape[0]
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+        torch.cuda.synchronize()
+        ev[0].record(st)
+        post = mvn.mvn_posterior(d.locs, kern, d.obs, d.y, d.noise_sd ** 2, opts=opts, device=dev)
+        ev[1].record(st)
+        mu_post = post["mu_post"].cpu().numpy()
+        sd_post = np.sqrt(np.maximum(post["var_post"].cpu().numpy(), 0))
+        order = np.argsort(-ndtr((mu_post - u) / sd_post), kind="stable")
+        e2 = torch.cuda.Event(enable_timing=True)
+        e2.record(st)
+        f = mvn.mvn_cholesky_permuted(post["sigma_post"], order, opts=opts)
+        ev[2].record(st)
+        a, b, mo = np.full(n, u), np.full(n, np.inf), mu_post[order]
+        r = mvn.mvn_prob_prefix(f, a, b, mo, N=N, S=S, seed=7, opts=opts)
+        ev[3].record(st)
+        m = mvn.mvn_mc_prefix(f, a, b, mo, M=M, seed=8, opts=opts, return_first=False)
+        ev[4].record(st)
+        torch.cuda.synchronize()
+        p = np.exp(r["logP"].cpu().numpy())
+        cnt = m["count"].cpu().numpy()
+        regions = {}
+        for al in (0.01, 0.05, 0.1):
+            k = int(np.sum(p >= 1 - al))
+            pm = float(cnt[k - 1]) / M if k else 1.0
+            regions[str(al)] = {"region": k, "p_qmc": float(p[k - 1]) if k else 1.0, "p_mc": pm,
+                                "one_minus_alpha_minus_p_mc": 1 - al - pm}
+        out[f"beta{beta}"] = {"posterior_ms": ev[0].elapsed_time(ev[1]), "factor_ms": e2.elapsed_time(ev[2]),
+                              "prefix_sweep_ms": ev[2].elapsed_time(ev[3]), "mc_check_ms": ev[3].elapsed_time(ev[4]),
+                              "info": [post["info"], f.info()], "marginal_above_0.95": int(np.sum(
+                                  ndtr((mu_post - u) / sd_post) >= 0.95)), "regions": regions}
+        del post, f, r, m
+        torch.cuda.empty_cache()
+    out["config"] = (f"40000 grid sites, 6250 observations, noise sd 0.5, exponential kernel sigma2 1, nugget 1e-8; "
+                     f"u = {u}, N = {N} x S = {S}, tile {tile}, FP64; Monte Carlo check {M} fields")
+    return out
+
+
 def variant_grad(dev) -> dict:
     import torch
     import paper_2405_14892_amd as mvn
@@ -548,7 +605,8 @@ def main() -> int:
                 ("tlr64k", lambda: variant_tlr(dev)),
                 ("batch2000", lambda: variant_batch(dev)),
                 ("grad4096", lambda: variant_grad(dev)),
-                ("crd16k", lambda: variant_crd(dev))]
+                ("crd16k", lambda: variant_crd(dev)),
+                ("post40k", lambda: variant_posterior(dev))]
         only = {v for v in args.variants.split(",") if v}
         for job in jobs:
             if job is None or (only and job[0] not in only):

@@ -209,6 +209,52 @@ int mvn_prob_prefix(const mvn_factor* f, const double* d_a, const double* d_b, c
                     int N, int S, uint64_t seed, const mvn_options* opts, void* ws, size_t ws_bytes,
                     double* d_prefix, hipStream_t stream);
 
+/* Factor P Sigma P^T: Sigma given by its lower triangle (device, row stride
+ * ld_sigma; the upper triangle is not read), factored in the site order
+ * h_perm (host, n entries, a permutation of 0..n-1, checked): row i of the
+ * factor is site h_perm[i].  This is how a confidence region orders a given
+ * Sigma (Algorithm 1: sites by decreasing marginal exceedance probability)
+ * before the nested-set sweep.  Options, factor buffer and result as for
+ * mvn_cholesky (dense in any precision, or TLR); the workspace is
+ * mvn_cholesky_permuted_workspace_bytes (mvn_cholesky's plus n int64).
+ * Copies h_perm to the device and synchronises `stream` first. */
+int mvn_cholesky_permuted_workspace_bytes(int n, const mvn_options* opts, size_t* bytes);
+int mvn_cholesky_permuted(int n, const double* d_sigma, int ld_sigma, const int64_t* h_perm,
+                          const mvn_options* opts, void* factor_buf, size_t factor_bytes, void* ws,
+                          size_t ws_bytes, mvn_factor* out, hipStream_t stream);
+
+/* Posterior of a Gaussian field x ~ N(mu, Sigma) at n sites, observed at m
+ * of them with noise: y = A x + eps, eps ~ N(0, noise_var I), A the m x n
+ * indicator matrix of the sites h_obs (Section IV-A, the equations for
+ * Sigma_post and mu_post, which then replace Sigma and mu in Algorithm 1).
+ * Sigma is the Matern covariance of d_locs (n x 2, device) with kern (the
+ * nugget is part of Sigma).  Computed as the Woodbury form
+ *   Sigma_post = Sigma - C^T K^-1 C,  mu_post = mu + C^T K^-1 (y - mu_o),
+ *   K = Sigma_oo + noise_var I,  C = Sigma_o.,
+ * by one tiled Cholesky factorisation of the bordered matrix
+ * [K C 0; C^T Sigma 0; (y - mu_o)^T 0 1] stopped after the observation
+ * columns: its trailing block is Sigma_post and -(mu_post - mu).  FP64.
+ *   d_mu         prior mean (n, device) or NULL for zero
+ *   h_obs        host, m site indices in 0..n-1 (checked); a site may repeat
+ *   d_y          device, m observations
+ *   noise_var    > 0
+ *   opts         tile of the factorisation (precision must be FP64)
+ *   d_mu_post    device, n (or NULL): posterior mean
+ *   d_var_post   device, n (or NULL): posterior marginal variance
+ *   d_info       device int: 0, or k > 0 if the k-th leading minor of K is
+ *                not positive (then the outputs are NaN)
+ *   sigma_post   receives a pointer to Sigma_post inside the workspace:
+ *                lower triangle, row stride *ld_sigma_post, valid until the
+ *                workspace is reused; pass it to mvn_cholesky_permuted
+ * Workspace: mvn_posterior_workspace_bytes ((m' + n + 1)^2 doubles, m' = m
+ * rounded up to the tile).  Copies h_obs to the device and synchronises
+ * `stream` first. */
+int mvn_posterior_workspace_bytes(int n, int m, const mvn_options* opts, size_t* bytes);
+int mvn_posterior(int n, const double* d_locs, const double* d_mu, int m, const int64_t* h_obs,
+                  const double* d_y, const mvn_matern* kern, double noise_var, const mvn_options* opts,
+                  void* ws, size_t ws_bytes, double* d_mu_post, double* d_var_post, int* d_info,
+                  double** sigma_post, int* ld_sigma_post, hipStream_t stream);
+
 /* Monte Carlo check of nested-set probabilities (Section IV-B, the check of
  * detected confidence regions by direct sampling): M fields X = mu + L Z
  * from the fitted distribution, for the sites in the factor's order, and for

@@ -19,7 +19,8 @@ from ._lib import (MVN_BF16, MVN_BF16X3, MVN_FACTOR_TLR, MVN_FP32, MVN_FP64, Mvn
 __all__ = ["mvn_factor_bytes", "mvn_cholesky_workspace_bytes", "mvn_prob_workspace_bytes",
            "mvn_prob_workspace_bytes_factor", "mvn_cholesky", "mvn_prob", "Factor",
            "mvn_prob_prefix_workspace_bytes", "mvn_prob_prefix", "confidence_region",
-           "mvn_mc_prefix_workspace_bytes", "mvn_mc_prefix",
+           "mvn_mc_prefix_workspace_bytes", "mvn_mc_prefix", "mvn_cholesky_permuted", "mvn_posterior",
+           "posterior_confidence_region",
            "mvn_prob_grad_workspace_bytes", "mvn_prob_grad", "MVNLogProb", "BatchPlan",
            "mvn_batch_plan", "mvn_prob_batch",
            "options", "MvnError", "MVN_FP64", "MVN_FP32", "MVN_BF16", "MVN_BF16X3", "library_path"]
@@ -170,6 +171,71 @@ def mvn_cholesky(n: int, sigma=None, locs=None, kern: tuple | None = None,
     return f
 
 
+def mvn_cholesky_permuted(sigma, perm, opts: MvnOptions | None = None) -> Factor:
+    """Factor of P Sigma P^T (row i = site perm[i]) from the lower triangle
+    of ``sigma``: a float64 device tensor n x n with unit column stride (any
+    row stride, e.g. the posterior's view into its workspace)."""
+    import numpy as np
+    torch = _torch()
+    opts = opts or options()
+    n = sigma.shape[0]
+    if sigma.dtype != torch.float64 or sigma.stride(1) != 1 or sigma.shape[1] != n:
+        raise MvnError(-2, "sigma must be a float64 n x n tensor with unit column stride")
+    dev = sigma.device
+    hp = np.ascontiguousarray(np.asarray(perm, dtype=np.int64))
+    if hp.shape != (n,):
+        raise MvnError(-4, "perm must have n entries")
+    fb = mvn_factor_bytes(n, opts)
+    wb = ctypes.c_size_t(0)
+    _lib.check(_lib.lib().mvn_cholesky_permuted_workspace_bytes(n, ctypes.byref(opts), ctypes.byref(wb)))
+    buf = torch.empty(fb, dtype=torch.uint8, device=dev)
+    ws = torch.empty(wb.value, dtype=torch.uint8, device=dev)
+    h = MvnFactor()
+    code = _lib.lib().mvn_cholesky_permuted(n, _ptr(sigma), sigma.stride(0), hp.ctypes.data_as(ctypes.c_void_p),
+                                            ctypes.byref(opts), _ptr(buf), fb, _ptr(ws), wb.value, ctypes.byref(h),
+                                            _stream(dev))
+    _lib.check(code)
+    f = Factor(h, buf, dev)
+    f._keep = (sigma, ws)
+    return f
+
+
+def mvn_posterior(locs, kern: tuple, obs, y, noise_var: float, mu=None, opts: MvnOptions | None = None,
+                  device="cuda") -> dict:
+    """Posterior of the field N(mu, Sigma(locs; kern)) given y = x[obs] +
+    N(0, noise_var) (Section IV-A).  Returns device tensors ``mu_post``,
+    ``var_post``, ``sigma_post`` (n x n view of the lower triangle, valid as
+    long as the returned dict is kept) and the host int ``info``."""
+    import numpy as np
+    torch = _torch()
+    opts = opts or options()
+    lc = _dev_f64(locs, device)
+    n = lc.shape[0]
+    ho = np.ascontiguousarray(np.asarray(obs, dtype=np.int64))
+    m = ho.size
+    ty = _dev_f64(y, device)
+    tm = _dev_f64(mu, device) if mu is not None else None
+    wb = ctypes.c_size_t(0)
+    _lib.check(_lib.lib().mvn_posterior_workspace_bytes(n, m, ctypes.byref(opts), ctypes.byref(wb)))
+    ws = torch.empty((wb.value + 7) // 8 * 8, dtype=torch.uint8, device=device)
+    mu_post = torch.empty(n, dtype=torch.float64, device=device)
+    var_post = torch.empty(n, dtype=torch.float64, device=device)
+    info = torch.empty(1, dtype=torch.int32, device=device)
+    sp_ptr, ld = ctypes.c_void_p(0), ctypes.c_int(0)
+    km = MvnMatern(*kern)
+    code = _lib.lib().mvn_posterior(n, _ptr(lc), _ptr(tm), m, ho.ctypes.data_as(ctypes.c_void_p), _ptr(ty),
+                                    ctypes.byref(km), float(noise_var), ctypes.byref(opts), _ptr(ws), wb.value,
+                                    _ptr(mu_post), _ptr(var_post), _ptr(info), ctypes.byref(sp_ptr),
+                                    ctypes.byref(ld), _stream(device))
+    _lib.check(code)
+    off = sp_ptr.value - ws.data_ptr()
+    assert off % 8 == 0
+    flat = ws.view(torch.float64)
+    sigma_post = flat[off // 8: off // 8 + (n - 1) * ld.value + n].as_strided((n, n), (ld.value, 1))
+    return {"mu_post": mu_post, "var_post": var_post, "sigma_post": sigma_post,
+            "info": int(info.item()), "_keep": (lc, ty, tm, ws)}
+
+
 def mvn_prob(f: Factor, a, b, mu=None, N: int = 1000, S: int = 10, seed: int = 1,
              opts: MvnOptions | None = None, return_ell: bool = False, workspace=None):
     """SOV estimate of P(a <= X <= b).  Returns a dict of device tensors:
@@ -290,6 +356,48 @@ def confidence_region(locs, kern: tuple, mu, u: float, alpha: float = 0.05, N: i
     if mc_samples > 0:
         m = mvn_mc_prefix(f, np.full(n, float(u)), np.full(n, np.inf), mu[order], M=mc_samples, seed=mc_seed,
                           opts=opts, return_first=False)
+        p = m["count"].cpu().numpy() / float(mc_samples)
+        out["mc_p"] = p
+        out["mc_p_region"] = float(p[k - 1]) if k > 0 else 1.0
+    return out
+
+
+def posterior_confidence_region(locs, kern: tuple, obs, y, noise_var: float, u: float, alpha: float = 0.05,
+                                mu=None, N: int = 1000, S: int = 10, seed: int = 1,
+                                opts: MvnOptions | None = None, device="cuda", mc_samples: int = 0,
+                                mc_seed: int = 2) -> dict:
+    """Algorithm 1 on the posterior of Section IV-A: Sigma_post and mu_post
+    from the observations, the sites ordered by decreasing posterior
+    marginal exceedance probability of u, the factor of Sigma_post in that
+    order (dense, or TLR with opts.tlr_eps > 0), one nested-set sweep, and
+    optionally the Monte Carlo check (dense).  Returns the keys of
+    confidence_region plus ``mu_post`` and ``sd_post`` (caller's order)."""
+    import numpy as np
+    from scipy.special import ndtr
+    opts = opts or options()
+    po = options(tile=opts.tile)  # the posterior itself is FP64 and dense
+    post = mvn_posterior(locs, kern, obs, y, noise_var, mu=mu, opts=po, device=device)
+    if post["info"] != 0:
+        raise MvnError(-7, f"observation covariance not positive definite (pivot {post['info']})")
+    mu_post = post["mu_post"].cpu().numpy()
+    sd_post = np.sqrt(np.maximum(post["var_post"].cpu().numpy(), 0.0))
+    n = mu_post.size
+    with np.errstate(divide="ignore", invalid="ignore"):
+        pm = ndtr(np.where(sd_post > 0, (mu_post - u) / sd_post, np.where(mu_post > u, np.inf, -np.inf)))
+    order = np.argsort(-pm, kind="stable")
+    f = mvn_cholesky_permuted(post["sigma_post"], order, opts=opts)
+    mo = mu_post[order]
+    r = mvn_prob_prefix(f, np.full(n, float(u)), np.full(n, np.inf), mo, N=N, S=S, seed=seed, opts=opts)
+    logp = r["logP"].cpu().numpy()
+    excursion = np.empty(n)
+    excursion[order] = np.exp(logp)
+    k = int(np.sum(np.exp(logp) >= 1.0 - alpha))
+    out = {"order": order, "logP": logp, "rel_stderr": r["rel_stderr"].cpu().numpy(), "excursion": excursion,
+           "region": np.sort(order[:k]), "info": f.info(), "mu_post": mu_post, "sd_post": sd_post,
+           "marginal": pm}
+    if mc_samples > 0:
+        m = mvn_mc_prefix(f, np.full(n, float(u)), np.full(n, np.inf), mo, M=mc_samples, seed=mc_seed, opts=opts,
+                          return_first=False)
         p = m["count"].cpu().numpy() / float(mc_samples)
         out["mc_p"] = p
         out["mc_p_region"] = float(p[k - 1]) if k > 0 else 1.0

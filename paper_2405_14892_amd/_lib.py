@@ -55,6 +55,13 @@ SIGNATURES = {
                                                  POINTER(c_size_t), c_void_p]),
     "mvn_prob_prefix": (c_int, [POINTER(MvnFactor), c_void_p, c_void_p, c_void_p, c_int, c_int, c_uint64,
                                 POINTER(MvnOptions), c_void_p, c_size_t, c_void_p, c_void_p]),
+    "mvn_cholesky_permuted_workspace_bytes": (c_int, [c_int, POINTER(MvnOptions), POINTER(c_size_t)]),
+    "mvn_cholesky_permuted": (c_int, [c_int, c_void_p, c_int, c_void_p, POINTER(MvnOptions), c_void_p, c_size_t,
+                                      c_void_p, c_size_t, POINTER(MvnFactor), c_void_p]),
+    "mvn_posterior_workspace_bytes": (c_int, [c_int, c_int, POINTER(MvnOptions), POINTER(c_size_t)]),
+    "mvn_posterior": (c_int, [c_int, c_void_p, c_void_p, c_int, c_void_p, c_void_p, POINTER(MvnMatern), c_double,
+                              POINTER(MvnOptions), c_void_p, c_size_t, c_void_p, c_void_p, c_void_p,
+                              POINTER(c_void_p), POINTER(c_int), c_void_p]),
     "mvn_mc_prefix_workspace_bytes": (c_int, [c_int, c_int, POINTER(MvnOptions), POINTER(c_size_t)]),
     "mvn_mc_prefix": (c_int, [POINTER(MvnFactor), c_void_p, c_void_p, c_void_p, c_int, c_uint64,
                               POINTER(MvnOptions), c_void_p, c_size_t, c_void_p, c_void_p, c_void_p]),

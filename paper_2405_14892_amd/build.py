@@ -20,7 +20,7 @@ LIB = os.path.join(HERE, "libmvn.so")
 ARCH = os.environ.get("MVN_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["api.cpp", "kernels_chol.hip", "kernels_sov.hip", "kernels_grad.hip", "kernels_tlr.hip",
-           "kernels_tlr_sweep.hip", "kernels_mc.hip"]
+           "kernels_tlr_sweep.hip", "kernels_mc.hip", "kernels_post.hip"]
 
 # Per-file extra flags.  The sweep inlines the FP64 conditioning step into
 # its row loop; machine loop-invariant code motion would hoist the step's

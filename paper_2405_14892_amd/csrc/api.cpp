@@ -739,10 +739,12 @@ int mvn_prob_grad_workspace_bytes(int n, int N, int S, const mvn_options* opts, 
   return 0;
 }
 
-int mvn_cholesky(int n, const double* d_sigma, int ld_sigma, const double* d_locs,
-                 const mvn_matern* kern, const mvn_options* opts, void* factor_buf,
-                 size_t factor_bytes, void* ws, size_t ws_bytes, mvn_factor* out,
-                 hipStream_t stream) {
+namespace {
+
+// mvn_cholesky, with Sigma optionally read in the order d_perm (device).
+int cholesky_impl(int n, const double* d_sigma, int ld_sigma, const int64_t* d_perm, const double* d_locs,
+                  const mvn_matern* kern, const mvn_options* opts, void* factor_buf, size_t factor_bytes, void* ws,
+                  size_t ws_bytes, mvn_factor* out, hipStream_t stream) {
   if (n < 1) return fail(-1, "n must be >= 1 (got %d)", n);
   if (d_sigma && ld_sigma < n) return fail(-3, "ld_sigma %d < n %d", ld_sigma, n);
   if (!d_sigma) {
@@ -781,7 +783,7 @@ int mvn_cholesky(int n, const double* d_sigma, int ld_sigma, const double* d_loc
     out->ranks = (int*)(fb + G.ranks);
     out->tlr_eps = opts->tlr_eps;
     out->max_rank = opts->max_rank;
-    hipError_t e = mvn::launch_tlr_build(n, G.m, G.nt, d_sigma, ld_sigma, d_locs, matern_of(kern), out->L,
+    hipError_t e = mvn::launch_tlr_build(n, G.m, G.nt, d_sigma, ld_sigma, d_perm, d_locs, matern_of(kern), out->L,
                                          out->info, stream);
     if (e != hipSuccess) return hip_fail(e, "tlr build");
     mvn::TlrCholArgs a{};
@@ -828,11 +830,138 @@ int mvn_cholesky(int n, const double* d_sigma, int ld_sigma, const double* d_loc
   out->tlr_eps = 0;
   out->max_rank = 0;
   out->reserved1 = 0;
-  hipError_t e = mvn::launch_build_matrix(n, ld, d_sigma, ld_sigma, d_locs, matern_of(kern), L, info, stream);
+  hipError_t e =
+      mvn::launch_build_matrix(n, ld, d_sigma, ld_sigma, d_perm, d_locs, matern_of(kern), L, info, stream);
   if (e != hipSuccess) return hip_fail(e, "build_matrix");
   e = opts->precision == MVN_FP64 ? mvn::launch_cholesky_f64(ld, opts->tile, L, info, stream)
                                   : mvn::launch_cholesky_lp(opts->precision, ld, opts->tile, L, info, low, stream);
   if (e != hipSuccess) return hip_fail(e, "cholesky");
+  return 0;
+}
+
+// Layout of a posterior workspace: observation indices, then the bordered
+// matrix (observations padded to the tile, sites, the data row).
+struct PostLayout {
+  size_t obs, B, total;
+  long mpad, ld;
+};
+
+PostLayout post_layout(int n, int m, int tile) {
+  PostLayout P{};
+  P.mpad = ((long)m + tile - 1) / tile * tile;
+  P.ld = (P.mpad + n + 1 + 127) / 128 * 128;
+  size_t off = 0;
+  P.obs = off; off = align_up(off + sizeof(int64_t) * (size_t)m);
+  P.B = off; off = align_up(off + sizeof(double) * (size_t)P.ld * (size_t)P.ld);
+  P.total = off;
+  return P;
+}
+
+}  // namespace
+
+int mvn_cholesky(int n, const double* d_sigma, int ld_sigma, const double* d_locs, const mvn_matern* kern,
+                 const mvn_options* opts, void* factor_buf, size_t factor_bytes, void* ws, size_t ws_bytes,
+                 mvn_factor* out, hipStream_t stream) {
+  return cholesky_impl(n, d_sigma, ld_sigma, nullptr, d_locs, kern, opts, factor_buf, factor_bytes, ws, ws_bytes, out,
+                       stream);
+}
+
+int mvn_cholesky_permuted_workspace_bytes(int n, const mvn_options* opts, size_t* bytes) {
+  if (!bytes) return fail(-3, "bytes is NULL");
+  size_t base = 0;
+  const int rc = mvn_cholesky_workspace_bytes(n, opts, &base);
+  if (rc) return rc;
+  *bytes = align_up(base) + align_up(sizeof(int64_t) * (size_t)n);
+  return 0;
+}
+
+int mvn_cholesky_permuted(int n, const double* d_sigma, int ld_sigma, const int64_t* h_perm, const mvn_options* opts,
+                          void* factor_buf, size_t factor_bytes, void* ws, size_t ws_bytes, mvn_factor* out,
+                          hipStream_t stream) {
+  if (n < 1) return fail(-1, "n must be >= 1 (got %d)", n);
+  if (!d_sigma) return fail(-2, "sigma is NULL");
+  if (ld_sigma < n) return fail(-3, "ld_sigma %d < n %d", ld_sigma, n);
+  if (!h_perm) return fail(-4, "perm is NULL");
+  {
+    std::vector<char> seen((size_t)n, 0);
+    for (int i = 0; i < n; ++i) {
+      const int64_t q = h_perm[i];
+      if (q < 0 || q >= n || seen[(size_t)q]) return fail(-4, "perm is not a permutation of 0..n-1 (entry %d)", i);
+      seen[(size_t)q] = 1;
+    }
+  }
+  if (!opts) return fail(-5, "options are required");
+  size_t base = 0, need = 0;
+  int rc = mvn_cholesky_workspace_bytes(n, opts, &base);
+  if (rc) return -5;  // the options are bad; the message is set
+  rc = mvn_cholesky_permuted_workspace_bytes(n, opts, &need);
+  if (rc) return -5;
+  if (!ws) return fail(-8, "workspace is NULL");
+  if (ws_bytes < need) return fail(-9, "workspace too small: %zu < %zu", ws_bytes, need);
+  int64_t* d_perm = (int64_t*)((char*)ws + align_up(base));
+  hipError_t e = hipMemcpyAsync(d_perm, h_perm, sizeof(int64_t) * (size_t)n, hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);  // h_perm may be pageable and short-lived
+  if (e != hipSuccess) return hip_fail(e, "permutation copy");
+  rc = cholesky_impl(n, d_sigma, ld_sigma, d_perm, nullptr, nullptr, opts, factor_buf, factor_bytes, ws, base, out,
+                     stream);
+  // argument positions of mvn_cholesky_permuted
+  return rc == -7 ? -6 : rc == -8 ? -7 : rc == -9 ? -8 : rc == -10 ? -9 : rc == -11 ? -10 : rc == -6 ? -5 : rc;
+}
+
+int mvn_posterior_workspace_bytes(int n, int m, const mvn_options* opts, size_t* bytes) {
+  if (n < 1) return fail(-1, "n must be >= 1 (got %d)", n);
+  if (m < 1) return fail(-2, "m must be >= 1 (got %d)", m);
+  int bad_tile = 0;
+  if (!opts || !opts_ok(opts, &bad_tile)) return fail(-3, "options with a valid tile are required");
+  if (!bytes) return fail(-4, "bytes is NULL");
+  *bytes = post_layout(n, m, opts->tile).total;
+  return 0;
+}
+
+int mvn_posterior(int n, const double* d_locs, const double* d_mu, int m, const int64_t* h_obs, const double* d_y,
+                  const mvn_matern* kern, double noise_var, const mvn_options* opts, void* ws, size_t ws_bytes,
+                  double* d_mu_post, double* d_var_post, int* d_info, double** sigma_post, int* ld_sigma_post,
+                  hipStream_t stream) {
+  if (n < 1) return fail(-1, "n must be >= 1 (got %d)", n);
+  if (!d_locs) return fail(-2, "locations are NULL");
+  if (m < 1) return fail(-4, "m must be >= 1 (got %d)", m);
+  if (!h_obs) return fail(-5, "observation indices are NULL");
+  for (int k = 0; k < m; ++k)
+    if (h_obs[k] < 0 || h_obs[k] >= n) return fail(-5, "observation %d indexes site %lld of %d", k, (long long)h_obs[k], n);
+  if (!d_y) return fail(-6, "observations are NULL");
+  if (!kern || !mvn::matern_ok(kern->sigma2, kern->beta, kern->nu, kern->nugget))
+    return fail(-7, "Matern parameters need sigma2 > 0, beta > 0, 0 < nu <= 20, nugget >= 0");
+  if (!(noise_var > 0) || !isfinite(noise_var)) return fail(-8, "noise variance must be > 0 (got %g)", noise_var);
+  int bad_tile = 0;
+  if (!opts || !opts_ok(opts, &bad_tile)) return fail(-9, "options with a valid tile are required");
+  if (opts->precision != MVN_FP64) return fail(-9, "the posterior is computed in FP64");
+  const PostLayout P = post_layout(n, m, opts->tile);
+  if ((long)P.ld > INT32_MAX) return fail(-1, "n + m too large");
+  if (!ws) return fail(-10, "workspace is NULL");
+  if (ws_bytes < P.total) return fail(-11, "workspace too small: %zu < %zu", ws_bytes, P.total);
+  if (!d_info) return fail(-14, "info is NULL");
+  char* w = (char*)ws;
+  int64_t* d_obs = (int64_t*)(w + P.obs);
+  hipError_t e = hipMemcpyAsync(d_obs, h_obs, sizeof(int64_t) * (size_t)m, hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);  // h_obs may be pageable and short-lived
+  if (e != hipSuccess) return hip_fail(e, "observation index copy");
+  mvn::PosteriorArgs a{};
+  a.B = (double*)(w + P.B);
+  a.ld = P.ld;
+  a.n = n;
+  a.m = m;
+  a.mpad = P.mpad;
+  a.obs = d_obs;
+  a.locs = d_locs;
+  a.y = d_y;
+  a.mu = d_mu;
+  a.mk = matern_of(kern);
+  a.noise_var = noise_var;
+  a.info = d_info;
+  e = mvn::launch_posterior(a, opts->tile, d_mu_post, d_var_post, stream);
+  if (e != hipSuccess) return hip_fail(e, "posterior");
+  if (sigma_post) *sigma_post = a.B + P.mpad * P.ld + P.mpad;
+  if (ld_sigma_post) *ld_sigma_post = (int)P.ld;
   return 0;
 }
 

@@ -23,9 +23,9 @@ constexpr int kSub = 32;  // sub-panel width
 
 // ------------------------------------------------------------ covariance
 __global__ __launch_bounds__(256) void build_matrix_kernel(int n, int ld, const double* __restrict__ sigma,
-                                                           int lds, const double* __restrict__ locs,
-                                                           Matern mk, double* __restrict__ A,
-                                                           int* __restrict__ info) {
+                                                           int lds, const int64_t* __restrict__ perm,
+                                                           const double* __restrict__ locs, Matern mk,
+                                                           double* __restrict__ A, int* __restrict__ info) {
   if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *info = 0;
   const long i = (long)blockIdx.y * 16 + (threadIdx.x >> 4);
   const long j = (long)blockIdx.x * 16 + (threadIdx.x & 15);
@@ -34,7 +34,8 @@ __global__ __launch_bounds__(256) void build_matrix_kernel(int n, int ld, const 
   if (i >= n || j >= n) {
     v = (i == j) ? 1.0 : 0.0;
   } else if (sigma) {
-    v = sigma[i * lds + j];
+    const long pi = perm ? perm[i] : i, pj = perm ? perm[j] : j;
+    v = pi >= pj ? sigma[pi * lds + pj] : sigma[pj * lds + pi];
   } else {
     const double dx = locs[2 * i] - locs[2 * j];
     const double dy = locs[2 * i + 1] - locs[2 * j + 1];
@@ -44,10 +45,10 @@ __global__ __launch_bounds__(256) void build_matrix_kernel(int n, int ld, const 
   A[i * ld + j] = v;
 }
 
-hipError_t launch_build_matrix(int n, int ld, const double* sigma, int lds, const double* locs, const Matern& mk,
-                               double* A, int* info, hipStream_t st) {
+hipError_t launch_build_matrix(int n, int ld, const double* sigma, int lds, const int64_t* perm, const double* locs,
+                               const Matern& mk, double* A, int* info, hipStream_t st) {
   dim3 grid(ld / 16, ld / 16);
-  hipLaunchKernelGGL(build_matrix_kernel, grid, dim3(256), 0, st, n, ld, sigma, lds, locs, mk, A, info);
+  hipLaunchKernelGGL(build_matrix_kernel, grid, dim3(256), 0, st, n, ld, sigma, lds, perm, locs, mk, A, info);
   return hipGetLastError();
 }
 
@@ -505,9 +506,10 @@ static void chol_column(int ld, int k0, int kw, double* A, int* info, hipStream_
 // regions written concurrently are disjoint column ranges.
 template <class Next, class Rest>
 static hipError_t right_looking(int ld, int tile, double* A, int* info, hipStream_t st, SideStream* sd,
-                                Next next, Rest rest) {
+                                Next next, Rest rest, int kstop = 0) {
   bool pending = false, used = false;  // a rest() on the side stream not yet waited for; any
-  for (int k0 = 0; k0 < ld; k0 += tile) {
+  const int kend = kstop > 0 ? kstop : ld;
+  for (int k0 = 0; k0 < kend; k0 += tile) {
     const int kw = min(tile, ld - k0);
     chol_column(ld, k0, kw, A, info, st);
     const int c1 = k0 + kw;
@@ -538,7 +540,7 @@ static hipError_t right_looking(int ld, int tile, double* A, int* info, hipStrea
   return hipGetLastError();
 }
 
-hipError_t launch_cholesky_f64(int ld, int tile, double* A, int* info, hipStream_t st, bool lookahead) {
+hipError_t launch_cholesky_f64(int ld, int tile, double* A, int* info, hipStream_t st, bool lookahead, int kstop) {
   SideStream* sd = (lookahead && ld > 2 * tile) ? side_stream(kSideCholesky, st) : nullptr;
   std::unique_lock<std::mutex> lock;
   if (sd) lock = std::unique_lock<std::mutex>(sd->mu);
@@ -555,7 +557,7 @@ hipError_t launch_cholesky_f64(int ld, int tile, double* A, int* info, hipStream
     if (mask) hipLaunchKernelGGL(chol_syrk_kernel<true>, grid, dim3(256), 0, s, A, ld, k0, kw, r0, (const int*)info);
     else hipLaunchKernelGGL(chol_syrk_kernel<false>, grid, dim3(256), 0, s, A, ld, k0, kw, r0, (const int*)info);
   };
-  hipError_t e = right_looking(ld, tile, A, info, st, sd, next, rest);
+  hipError_t e = right_looking(ld, tile, A, info, st, sd, next, rest, kstop);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(zero_upper_kernel, dim3(ld / 16, ld / 16), dim3(256), 0, st, A, ld);
   return hipGetLastError();

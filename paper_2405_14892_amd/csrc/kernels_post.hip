@@ -1,0 +1,85 @@
+// Posterior of a Gaussian field observed with noise at m of its n sites
+// (arXiv 2405.14892, Section IV-A, the equations for Sigma_post and
+// mu_post), by one partial Cholesky factorisation of a bordered matrix.
+//
+// With K = Sigma_oo + sigma_eps^2 I (the observed sites), C = Sigma_o. (m x
+// n) and r = y - mu_o, the Woodbury form of the two equations reads
+//   Sigma_post = Sigma - C^T K^-1 C,   mu_post = mu + C^T K^-1 r.
+// Both are Schur complements of K in
+//        [ K    C      0 ]      rows 0 .. m'-1   (observations, padded)
+//   B =  [ C^T  Sigma  * ]      rows m' .. m'+n-1 (sites)
+//        [ r^T  0      1 ]      row  m'+n         (data)
+// (lower triangle stored): factoring only the first m' columns (L_K, then
+// W = L_K^-1 C and v = L_K^-1 r below it) leaves in the trailing block
+//   Sigma - W^T W = Sigma_post           on the sites,
+//   0 - v^T W     = -(mu_post - mu)^T    on the data row.
+// So the posterior costs one K factorisation, one panel solve and one
+// trailing update of the site block: the library's tiled Cholesky stopped
+// after m' columns.  The observations are padded to m' (a multiple of the
+// Cholesky tile) with identity rows and columns, which decouple.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "launch.h"
+#include "matern.h"
+
+namespace mvn {
+
+namespace {
+
+__device__ __forceinline__ double& B_at(const PosteriorArgs& p, long i, long j) { return p.B[i * p.ld + j]; }
+
+// Lower triangle of B, 16 x 16 elements per workgroup; clears *info.
+__global__ __launch_bounds__(256) void posterior_build_kernel(PosteriorArgs p) {
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *p.info = 0;
+  const long i = (long)blockIdx.y * 16 + (threadIdx.x >> 4);
+  const long j = (long)blockIdx.x * 16 + (threadIdx.x & 15);
+  if (i >= p.ld || j > i) return;
+  const long mp = p.mpad, e = p.mpad + p.n;  // first site row, data row
+  auto site = [&](long r) -> long { return r < mp ? p.obs[r] : r - mp; };  // site index of an observation/site row
+  auto cov = [&](long a, long b) {  // Sigma between sites a and b (nugget on equal sites)
+    const double dx = p.locs[2 * a] - p.locs[2 * b];
+    const double dy = p.locs[2 * a + 1] - p.locs[2 * b + 1];
+    return matern_cov(p.mk, sqrt(dx * dx + dy * dy)) + (a == b ? p.mk.nugget : 0.0);
+  };
+  double v;
+  const bool obs_i = i < p.m, obs_j = j < p.m;
+  const bool pad_i = (i >= p.m && i < mp) || i > e, pad_j = (j >= p.m && j < mp) || j > e;
+  if (pad_i || pad_j) {
+    v = (i == j) ? 1.0 : 0.0;
+  } else if (i == e) {
+    v = (j == e) ? 1.0 : (obs_j ? p.y[j] - (p.mu ? p.mu[p.obs[j]] : 0.0) : 0.0);
+  } else {
+    // both rows are observations or sites (i >= j)
+    v = cov(site(i), site(j));
+    if (obs_i && i == j) v += p.noise_var;
+  }
+  B_at(p, i, j) = v;
+}
+
+__global__ __launch_bounds__(256) void posterior_moments_kernel(PosteriorArgs p, double* __restrict__ mu_post,
+                                                                double* __restrict__ var_post) {
+  const long j = (long)blockIdx.x * 256 + threadIdx.x;
+  if (j >= p.n) return;
+  const long mp = p.mpad, e = p.mpad + p.n;
+  const bool ok = *p.info == 0;
+  if (mu_post) mu_post[j] = ok ? (p.mu ? p.mu[j] : 0.0) - B_at(p, e, mp + j) : NAN;
+  if (var_post) var_post[j] = ok ? B_at(p, mp + j, mp + j) : NAN;
+}
+
+}  // namespace
+
+hipError_t launch_posterior(const PosteriorArgs& p, int tile, double* mu_post, double* var_post, hipStream_t st) {
+  const dim3 grid((unsigned)(p.ld / 16), (unsigned)(p.ld / 16));
+  hipLaunchKernelGGL(posterior_build_kernel, grid, dim3(256), 0, st, p);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // the first m' columns only; a non-positive pivot of K lands in *info
+  e = launch_cholesky_f64((int)p.ld, tile, p.B, p.info, st, true, (int)p.mpad);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(posterior_moments_kernel, dim3((unsigned)((p.n + 255) / 256)), dim3(256), 0, st, p, mu_post,
+                     var_post);
+  return hipGetLastError();
+}
+
+}  // namespace mvn

@@ -57,6 +57,7 @@ __device__ __forceinline__ void tri_inverse(long b, long& i, long& j) {
 // ------------------------------------------------------------ build
 // One 64 x 64 sub-block of one lower tile per workgroup; clears *info.
 __global__ __launch_bounds__(256) void tlr_build_kernel(int n, int m, const double* __restrict__ sigma, int lds,
+                                                        const int64_t* __restrict__ perm,
                                                         const double* __restrict__ locs, Matern mk,
                                                         double* __restrict__ tiles, int* __restrict__ info) {
   const long per = (long)(m / 64) * (m / 64);
@@ -73,7 +74,8 @@ __global__ __launch_bounds__(256) void tlr_build_kernel(int n, int m, const doub
     if (i >= n || j >= n) {
       v = (i == j) ? 1.0 : 0.0;
     } else if (sigma) {
-      v = i >= j ? sigma[i * lds + j] : sigma[j * lds + i];
+      const long pi = perm ? perm[i] : i, pj = perm ? perm[j] : j;
+      v = pi >= pj ? sigma[pi * lds + pj] : sigma[pj * lds + pi];
     } else {
       const double dx = locs[2 * i] - locs[2 * j];
       const double dy = locs[2 * i + 1] - locs[2 * j + 1];
@@ -548,11 +550,11 @@ __global__ void tlr_info_kernel(int* __restrict__ info, const int* __restrict__ 
   if (threadIdx.x == 0 && *local != 0 && *info == 0) *info = *local + offset;
 }
 
-hipError_t launch_tlr_build(int n, int m, int nt, const double* sigma, int lds, const double* locs,
-                            const Matern& mk, double* tiles, int* info, hipStream_t st) {
+hipError_t launch_tlr_build(int n, int m, int nt, const double* sigma, int lds, const int64_t* perm,
+                            const double* locs, const Matern& mk, double* tiles, int* info, hipStream_t st) {
   const long sub = (long)(m / 64) * (m / 64) * ((long)nt * (nt + 1) / 2);
-  hipLaunchKernelGGL(tlr_build_kernel, dim3((unsigned)sub), dim3(256), 0, st, n, m, sigma, lds, locs, mk, tiles,
-                     info);
+  hipLaunchKernelGGL(tlr_build_kernel, dim3((unsigned)sub), dim3(256), 0, st, n, m, sigma, lds, perm, locs, mk,
+                     tiles, info);
   return hipGetLastError();
 }
 

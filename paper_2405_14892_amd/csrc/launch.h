@@ -12,8 +12,10 @@ namespace mvn {
 // Lower triangle of the padded ld x ld matrix A (row-major) from the caller's
 // Sigma (row stride lds) or from locations with the Matern kernel; rows and
 // columns n..ld-1 become the identity.  Also clears *info.
-hipError_t launch_build_matrix(int n, int ld, const double* sigma, int lds, const double* locs, const Matern& mk,
-                               double* A, int* info, hipStream_t st);
+// With perm (device, n entries, a permutation checked on the host) the
+// matrix is Sigma[perm[i]][perm[j]], read from Sigma's lower triangle.
+hipError_t launch_build_matrix(int n, int ld, const double* sigma, int lds, const int64_t* perm, const double* locs,
+                               const Matern& mk, double* A, int* info, hipStream_t st);
 
 // A second stream of the current device (default priority, non-blocking)
 // with three events, for work that overlaps the caller's stream inside one
@@ -33,7 +35,11 @@ SideStream* side_stream(int slot, hipStream_t st);
 // 1-based index of the first non-positive pivot.  Upper triangle zeroed.
 // With `lookahead`, the trailing updates off the next tile column run on a
 // side stream concurrently with that column's panel factorisation.
-hipError_t launch_cholesky_f64(int ld, int tile, double* A, int* info, hipStream_t st, bool lookahead = true);
+// With kstop > 0 (a multiple of tile) only the first kstop columns are
+// factored; the trailing block then holds the Schur complement, with every
+// update of those columns applied (upper triangle still zeroed).
+hipError_t launch_cholesky_f64(int ld, int tile, double* A, int* info, hipStream_t st, bool lookahead = true,
+                               int kstop = 0);
 
 // The same factorisation with the trailing updates in FP32 (prec 1), BF16
 // (2) or split BF16 (3) on MFMA, followed by the low-precision operand copy
@@ -65,6 +71,24 @@ struct McArgs {
 };
 int mc_wg_per_cu(int rows);
 hipError_t launch_mc(const McArgs& a, hipStream_t st);
+
+// Posterior of a field observed with noise at m sites: the bordered matrix
+// [K C 0; C^T Sigma *; r^T 0 1] (ld x ld, lower triangle), factored over its
+// first mpad columns (the m observations padded with identity).
+struct PosteriorArgs {
+  double* B;
+  long ld;                 // >= mpad + n + 1, a multiple of 16
+  int n, m;
+  long mpad;               // m rounded up to the Cholesky tile
+  const int64_t* obs;      // m site indices (device, checked on the host)
+  const double* locs;      // n x 2
+  const double* y;         // m observations
+  const double* mu;        // n prior means, or nullptr
+  Matern mk;
+  double noise_var;
+  int* info;               // non-positive pivot of K (1-based), 0 if none
+};
+hipError_t launch_posterior(const PosteriorArgs& p, int tile, double* mu_post, double* var_post, hipStream_t st);
 
 struct SweepArgs {
   const double* L;         // FP64 factor (diagonal blocks, pivots)
@@ -189,8 +213,8 @@ constexpr long kTlrPairBatch = 256; // tile pairs per update launch (sizes the W
 
 // Lower tiles of Sigma (tile-major, m x m each, identity past n) from the
 // caller's Sigma or from locations with the Matern kernel; clears *info.
-hipError_t launch_tlr_build(int n, int m, int nt, const double* sigma, int lds, const double* locs,
-                            const Matern& mk, double* tiles, int* info, hipStream_t st);
+hipError_t launch_tlr_build(int n, int m, int nt, const double* sigma, int lds, const int64_t* perm,
+                            const double* locs, const Matern& mk, double* tiles, int* info, hipStream_t st);
 
 struct TlrCholArgs {
   double* tiles;     // nt(nt+1)/2 tiles of m x m

@@ -227,3 +227,31 @@ def make_batch(count: int = 2000, n_min: int = 50, n_max: int = 4096, k: int = 6
         idx[off[p]:off[p + 1]] = order
         b[off[p]:off[p + 1]] = (f[order] - u) if positive_excursion else (u - f[order])
     return BatchWorkload(locs, s2, beta, nu, nug, n_p, off, idx, a, b, us, N, S, seed + 1)
+
+
+@dataclass
+class PosteriorData:
+    """Synthetic observations of one Gaussian field draw: the k x k grid
+    sites, the field x, m observed sites (distinct, random) and y = x[obs] +
+    N(0, noise_sd^2).  The shape of the paper's synthetic posterior problems:
+    40 000 sites, 6 250 observations, noise sd 0.5, exponential kernel
+    (nu = 1/2) with range 0.033, 0.1 or 0.234."""
+    locs: np.ndarray
+    x: np.ndarray
+    obs: np.ndarray
+    y: np.ndarray
+    sigma2: float
+    beta: float
+    nu: float
+    nugget: float
+    noise_sd: float
+
+
+def make_posterior(k: int = 200, m: int = 6250, beta: float = 0.1, noise_sd: float = 0.5, nu: float = 0.5,
+                   sigma2: float = 1.0, nugget: float = 1e-8, seed: int = 2405) -> PosteriorData:
+    rng = np.random.default_rng(seed)
+    locs = grid_locations(k)
+    x = gp_draw_grid(k, sigma2, beta, nu, nugget, rng)[0]
+    obs = np.sort(rng.choice(k * k, m, replace=False)).astype(np.int64)
+    y = x[obs] + noise_sd * rng.standard_normal(m)
+    return PosteriorData(locs, x, obs, y, sigma2, beta, nu, nugget, noise_sd)
