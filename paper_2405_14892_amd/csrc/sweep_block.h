@@ -94,13 +94,48 @@ __device__ __forceinline__ LogProd condition_block(
     tab = (const lds_f64*)ninv_tab;
   }
   const auto ninv = [tab](double x) { return TAB ? ninv_lower_tab(x, tab) : ninv_lower(x); };
-  for (int q = 0; q < rows; q += kSlab) {
-    __syncthreads();
-    for (int e = t; e < kSlab * SL; e += 256) {
-      const int ii = e / SL, k = e % SL;
-      slab[e] = (q + ii < rows && k < q + ii) ? L[(long)(i0 + q + ii) * ld + i0 + k] : 0.0;
+  // Slabs of the diagonal block.  128-row blocks: waves 1-3 fetch slab q + 1
+  // into registers while wave 0 runs the rows of slab q, so the recurrence
+  // does not wait on global memory (the LDS holds one slab; two barriers per
+  // slab).  64-row blocks (four workgroups per CU, no register headroom):
+  // every lane loads the slab between the two barriers.
+  constexpr bool kPF = SL >= 128;
+  constexpr int kPer = kPF ? (kSlab * SL + 191) / 192 : 1;  // slab elements per fetching lane
+  double pf[kPer];
+  const int u = t - 64;  // fetching lane, 0..191 in waves 1-3
+  const auto fetch = [&](int q) {
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      const int e = u + 192 * j, ii = e / SL, k = e % SL;
+      pf[j] = (e < kSlab * SL && q + ii < rows && k < q + ii) ? L[(long)(i0 + q + ii) * ld + i0 + k] : 0.0;
     }
-    __syncthreads();
+  };
+  const auto put = [&]() {
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      const int e = u + 192 * j;
+      if (e < kSlab * SL) slab[e] = pf[j];
+    }
+  };
+  if constexpr (kPF) {
+    __syncthreads();  // T and the per-row constants are complete; slab is free
+    if (!owner) {
+      fetch(0);
+      put();
+    }
+  }
+  for (int q = 0; q < rows; q += kSlab) {
+    if constexpr (kPF) {
+      __syncthreads();  // slab q in LDS
+      if (!owner && q + kSlab < rows) fetch(q + kSlab);
+    } else {
+      __syncthreads();
+      for (int e = t; e < kSlab * SL; e += 256) {
+        const int ii = e / SL, k = e % SL;
+        slab[e] = (q + ii < rows && k < q + ii) ? L[(long)(i0 + q + ii) * ld + i0 + k] : 0.0;
+      }
+      __syncthreads();
+    }
     if (owner) {
       const int iend = min(q + kSlab, rows);
       for (int i = q; i < iend; ++i) {
@@ -133,6 +168,12 @@ __device__ __forceinline__ LogProd condition_block(
         T[i * kCols + lane] = valid ? st.y : 0.0;
         logprod_mul(prod, st);
         if constexpr (PREFIX) prefix_row(prod, valid, sidx, pre, (long)(goff + i0 + i));
+      }
+    }
+    if constexpr (kPF) {
+      if (q + kSlab < rows) {
+        __syncthreads();  // wave 0 is done with slab q
+        if (!owner) put();
       }
     }
   }
