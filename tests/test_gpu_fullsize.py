@@ -12,12 +12,22 @@ through properties that hold at any size.
   (whose factor and sweep are the ones checked above) to 1e-7 relative.
 * 2000 confidence-region problems (FP64, 64-row sweep blocks as tuned):
   sampled problems against the oracle, all samples, 1e-10.
+* The Monte Carlo check on the 16384-site factor (50 000 fields, as the
+  benchmark draws): sampled samples' first failing sites against the
+  oracle's fields through its own factor; the counts against the first
+  failures.
+* The posterior at 40 000 sites and 6 250 observations (tile 512): mu_post,
+  variances and Sigma_post at sampled sites against the oracle's kriging
+  form, 1e-9; the factor of Sigma_post in exceedance order reproduces
+  sampled entries of the permuted Sigma_post (L L^T at any size).
 """
 import numpy as np
 import pytest
 import torch
 
 import oracle
+from oracle import mc as omc
+from oracle import posterior as opost
 import paper_2405_14892_amd as mvn
 import workloads
 
@@ -46,6 +56,20 @@ def test_prec16k_full_size_factor_and_sampled_columns():
     rel = np.abs(ell[cols] - ref) / np.maximum(1.0, np.abs(ref))
     print("prec16k: sampled l", ref, "max rel", rel.max(), flush=True)
     assert rel.max() < 1e-10
+    # the Monte Carlo check on the same factor, at the benchmark's 50 000 fields
+    M = 50000
+    m = mvn.mvn_mc_prefix(f, w.a, w.b, w.mu, M=M, seed=w.seed + 1, opts=opts)
+    first = m["first"].cpu().numpy()
+    count = m["count"].cpu().numpy()
+    np.testing.assert_array_equal(count, omc.prefix_counts(first, w.n))
+    mc_cols = np.array([0, 63, 64, 777, M // 2, M - 1])
+    X = omc.fields(L, w.mu, w.seed + 1, mc_cols)
+    ref_first = omc.first_failure(X, w.a, w.b)
+    print("prec16k: Monte Carlo first failures", first[mc_cols], ref_first, flush=True)
+    bad = np.nonzero(first[mc_cols] != ref_first)[0]
+    for j in bad:  # only where the deciding value sits on a limit to rounding
+        k = min(first[mc_cols][j], ref_first[j])
+        assert min(abs(X[k, j] - w.a[k]), abs(X[k, j] - w.b[k])) < 1e-9
 
 
 def test_tlr64k_full_size_properties():
@@ -99,3 +123,41 @@ def test_batch2000_full_size_sampled_problems():
         ref = oracle.reduce_samples(oracle.sweep(L, bw.a[sl], bw.b[sl], bw.N, bw.S, bw.seed), bw.N, bw.S)
         print(f"problem {p} n={bw.n_p[p]} logP {out[p, 0]} oracle {ref['logP']}", flush=True)
         assert abs(out[p, 0] - ref["logP"]) < 1e-10 * max(1.0, abs(ref["logP"]))
+
+
+def test_post40k_full_size_sampled_sites():
+    d = workloads.make_posterior(beta=0.1)
+    kern = (d.sigma2, d.beta, d.nu, d.nugget)
+    n = d.locs.shape[0]
+    opts = mvn.options(tile=512)
+    print("post40k: GPU posterior", flush=True)
+    post = mvn.mvn_posterior(d.locs, kern, d.obs, d.y, d.noise_sd ** 2, opts=opts)
+    torch.cuda.synchronize()
+    assert post["info"] == 0
+    sites = np.array([0, 1, int(d.obs[0]), int(d.obs[-1]), 12345, 20000, n - 1])
+    print("post40k: oracle at sampled sites", flush=True)
+    ref = opost.posterior_at(d.locs, kern, None, d.obs, d.y, d.noise_sd ** 2, sites)
+    mu_post = post["mu_post"].cpu().numpy()
+    var_post = post["var_post"].cpu().numpy()
+    err_m = np.max(np.abs(mu_post[sites] - ref["mu_post"]))
+    err_v = np.max(np.abs(var_post[sites] - ref["var_post"]))
+    S = post["sigma_post"]
+    got = np.array([[S[max(i, j), min(i, j)].item() for j in sites] for i in sites])
+    err_s = np.max(np.abs(got - ref["sigma_post"]))
+    print(f"post40k: max error mu {err_m:.2e} var {err_v:.2e} Sigma {err_s:.2e}", flush=True)
+    assert err_m < 1e-9 and err_v < 1e-9 and err_s < 1e-9
+    # the factor in exceedance order (u = 0.5) reproduces the permuted entries
+    from scipy.special import ndtr
+    order = np.argsort(-ndtr((mu_post - 0.5) / np.sqrt(var_post)), kind="stable")
+    f = mvn.mvn_cholesky_permuted(S, order, opts=opts)
+    torch.cuda.synchronize()
+    assert f.info() == 0
+    rows = [0, 1, 4095, 20000, n - 1]
+    Lr = {i: f.L()[i, : i + 1].cpu().numpy() for i in rows}
+    for i in rows:
+        for j in rows:
+            if j <= i:
+                lhs = float(Lr[i][: j + 1] @ Lr[j][: j + 1])
+                a, b = int(order[i]), int(order[j])
+                rhs = S[max(a, b), min(a, b)].item()
+                assert abs(lhs - rhs) < 1e-10, (i, j, lhs, rhs)

@@ -87,3 +87,22 @@ def test_moments_of_joint_draws():
     assert np.all(np.abs(cov - S) < 5 * se + 1e-12)
     cross = res.T @ Y / R
     assert np.all(np.abs(cross) < 5 * np.sqrt(np.outer(np.diag(S), np.diag(Sig)[obs] + t2) / R))
+
+
+def test_spot_form_equals_the_full_equations():
+    """The spot-check routine (kriging form on the observed sites only)
+    against the full equations at every site, with a repeated observation."""
+    rng = np.random.default_rng(12)
+    n, t2 = 45, 0.3
+    locs = rng.uniform(0, 1, (n, 2))
+    kern = (1.1, 0.25, 1.5, 1e-4)
+    Sig = oracle.covariance(locs, *kern)
+    obs = np.array([3, 7, 7, 20, 44, 0])
+    y = rng.normal(0, 1, obs.size)
+    mu = rng.normal(0, 0.5, n)
+    S, m = op.posterior(Sig, mu, obs, y, t2)
+    sites = np.array([0, 5, 7, 30, 44])
+    spot = op.posterior_at(locs, kern, mu, obs, y, t2, sites)
+    np.testing.assert_allclose(spot["mu_post"], m[sites], atol=1e-10)
+    np.testing.assert_allclose(spot["var_post"], np.diag(S)[sites], atol=1e-10)
+    np.testing.assert_allclose(spot["sigma_post"], S[np.ix_(sites, sites)], atol=1e-10)
