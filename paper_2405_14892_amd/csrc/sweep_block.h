@@ -56,6 +56,40 @@ __device__ __forceinline__ void prefix_row(const LogProd& prod, bool valid, uint
   }
 }
 
+// 128-row blocks run the in-block recurrence in 32-row sub-blocks: once
+// sub-block rows [c0, c0 + 32) hold y, every wave adds L_rr(r, c0:c0+32) y
+// to the rows r >= c0 + 32 of T on MFMA (16-row tiles, tile b on wave b mod
+// 4), so wave 0's dot product per row only runs over its own sub-block.
+constexpr int kCondSub = 32;
+
+__device__ __forceinline__ void subblock_update(lds_f64* T, const double* __restrict__ L, long ld, int i0, int c0,
+                                                int rows) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r0 = c0 + kCondSub;
+  const int nblk = (rows - r0 + 15) / 16;
+  for (int b = w; b < nblk; b += 4) {
+    const int rb = r0 + 16 * b;
+    f64x4 acc[4];
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[jb][r] = T[(rb + (lane >> 4) + 4 * r) * kCols + jb * 16 + (lane & 15)];
+    const double* Lr = L + (long)(i0 + rb + (lane & 15)) * ld + i0 + c0 + (lane >> 4);
+#pragma unroll
+    for (int kk = 0; kk < kCondSub / 4; ++kk) {
+      const double a = Lr[4 * kk];
+      const int k = c0 + 4 * kk + (lane >> 4);
+#pragma unroll
+      for (int jb = 0; jb < 4; ++jb)
+        acc[jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, T[k * kCols + jb * 16 + (lane & 15)], acc[jb], 0, 0, 0);
+    }
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) T[(rb + (lane >> 4) + 4 * r) * kCols + jb * 16 + (lane & 15)] = acc[jb][r];
+  }
+}
+
 // Step 2 of the sweep for one 128-row block, called by all 256 lanes once per
 // block: rows of the diagonal block of L are staged 8 at a time in LDS (all
 // lanes), and wave 0 (lane = sample column) runs the recurrence
@@ -146,7 +180,9 @@ __device__ __forceinline__ LogProd condition_block(
         const lds_f64* Tk = T + lane;
         double s0 = T[i * kCols + lane], s1 = 0.0, s2 = 0.0, s3 = 0.0;
         const int kend = (i + 7) & ~7;
-        for (int k = 0; k < kend; k += 8) {
+        // 128-row blocks: earlier sub-blocks are already folded into T
+        const int kbeg = kPF ? (i & ~(kCondSub - 1)) : 0;
+        for (int k = kbeg; k < kend; k += 8) {
           s0 += Li[k] * Tk[k * kCols];
           s1 += Li[k + 1] * Tk[(k + 1) * kCols];
           s2 += Li[k + 2] * Tk[(k + 2) * kCols];
@@ -172,8 +208,9 @@ __device__ __forceinline__ LogProd condition_block(
     }
     if constexpr (kPF) {
       if (q + kSlab < rows) {
-        __syncthreads();  // wave 0 is done with slab q
+        __syncthreads();  // wave 0 is done with slab q (and rows <= q + 7 hold y)
         if (!owner) put();
+        if ((q + kSlab) % kCondSub == 0) subblock_update(T, L, ld, i0, q + kSlab - kCondSub, rows);
       }
     }
   }
