@@ -56,7 +56,7 @@ __device__ __forceinline__ void prefix_row(const LogProd& prod, bool valid, uint
   }
 }
 
-// 128-row blocks run the in-block recurrence in 32-row sub-blocks: once
+// The in-block recurrence runs in 32-row sub-blocks: once
 // sub-block rows [c0, c0 + 32) hold y, every wave adds L_rr(r, c0:c0+32) y
 // to the rows r >= c0 + 32 of T on MFMA (16-row tiles, tile b on wave b mod
 // 4), so wave 0's dot product per row only runs over its own sub-block.
@@ -163,7 +163,8 @@ __device__ __forceinline__ LogProd condition_block(
       __syncthreads();  // slab q in LDS
       if (!owner && q + kSlab < rows) fetch(q + kSlab);
     } else {
-      __syncthreads();
+      __syncthreads();  // rows < q hold y
+      if (q > 0 && q % kCondSub == 0) subblock_update(T, L, ld, i0, q - kCondSub, rows);
       for (int e = t; e < kSlab * SL; e += 256) {
         const int ii = e / SL, k = e % SL;
         slab[e] = (q + ii < rows && k < q + ii) ? L[(long)(i0 + q + ii) * ld + i0 + k] : 0.0;
@@ -180,8 +181,8 @@ __device__ __forceinline__ LogProd condition_block(
         const lds_f64* Tk = T + lane;
         double s0 = T[i * kCols + lane], s1 = 0.0, s2 = 0.0, s3 = 0.0;
         const int kend = (i + 7) & ~7;
-        // 128-row blocks: earlier sub-blocks are already folded into T
-        const int kbeg = kPF ? (i & ~(kCondSub - 1)) : 0;
+        // earlier sub-blocks are already folded into T
+        const int kbeg = i & ~(kCondSub - 1);
         for (int k = kbeg; k < kend; k += 8) {
           s0 += Li[k] * Tk[k * kCols];
           s1 += Li[k + 1] * Tk[(k + 1) * kCols];
