@@ -331,9 +331,10 @@ def confidence_region(locs, kern: tuple, mu, u: float, alpha: float = 0.05, N: i
     first k sites; the region is the longest prefix whose P-hat >= 1 - alpha.
     kern = (sigma2, beta, nu, nugget).  Returns a dict with ``order``,
     ``logP`` (per prefix), ``excursion`` (per site, in the caller's site
-    order) and ``region`` (site indices).  With mc_samples > 0 (dense
-    factors) the region is checked by direct sampling on the same factor
-    (Section IV-B): ``mc_p`` is the fraction of sampled fields above u on
+    order) and ``region`` (site indices).  With mc_samples > 0 the region
+    is checked by direct sampling of the fitted distribution (Section IV-B;
+    through the dense factor of the same ordered Sigma, also when the
+    regions came from a TLR factor): ``mc_p`` is the fraction of sampled fields above u on
     the first k sites, per k, and ``mc_p_region`` that fraction for the
     region, expected near 1 - alpha."""
     import numpy as np
@@ -354,8 +355,12 @@ def confidence_region(locs, kern: tuple, mu, u: float, alpha: float = 0.05, N: i
     out = {"order": order, "logP": logp, "rel_stderr": r["rel_stderr"].cpu().numpy(), "excursion": excursion,
            "region": np.sort(order[:k]), "info": f.info()}
     if mc_samples > 0:
-        m = mvn_mc_prefix(f, np.full(n, float(u)), np.full(n, np.inf), mu[order], M=mc_samples, seed=mc_seed,
-                          opts=opts, return_first=False)
+        # the check samples the fitted distribution itself: through the dense factor of the same
+        # ordered Sigma when the regions came from a TLR factor
+        fm = f if not f.is_tlr else mvn_cholesky(n, locs=locs[order], kern=kern, opts=options(tile=opts.tile),
+                                                 device=device)
+        m = mvn_mc_prefix(fm, np.full(n, float(u)), np.full(n, np.inf), mu[order], M=mc_samples, seed=mc_seed,
+                          opts=options(tile=opts.tile), return_first=False)
         p = m["count"].cpu().numpy() / float(mc_samples)
         out["mc_p"] = p
         out["mc_p_region"] = float(p[k - 1]) if k > 0 else 1.0
@@ -370,7 +375,7 @@ def posterior_confidence_region(locs, kern: tuple, obs, y, noise_var: float, u: 
     from the observations, the sites ordered by decreasing posterior
     marginal exceedance probability of u, the factor of Sigma_post in that
     order (dense, or TLR with opts.tlr_eps > 0), one nested-set sweep, and
-    optionally the Monte Carlo check (dense).  Returns the keys of
+    optionally the Monte Carlo check (through the dense factor).  Returns the keys of
     confidence_region plus ``mu_post`` and ``sd_post`` (caller's order)."""
     import numpy as np
     from scipy.special import ndtr
@@ -396,8 +401,9 @@ def posterior_confidence_region(locs, kern: tuple, obs, y, noise_var: float, u: 
            "region": np.sort(order[:k]), "info": f.info(), "mu_post": mu_post, "sd_post": sd_post,
            "marginal": pm}
     if mc_samples > 0:
-        m = mvn_mc_prefix(f, np.full(n, float(u)), np.full(n, np.inf), mo, M=mc_samples, seed=mc_seed, opts=opts,
-                          return_first=False)
+        fm = f if not f.is_tlr else mvn_cholesky_permuted(post["sigma_post"], order, opts=options(tile=opts.tile))
+        m = mvn_mc_prefix(fm, np.full(n, float(u)), np.full(n, np.inf), mo, M=mc_samples, seed=mc_seed,
+                          opts=options(tile=opts.tile), return_first=False)
         p = m["count"].cpu().numpy() / float(mc_samples)
         out["mc_p"] = p
         out["mc_p_region"] = float(p[k - 1]) if k > 0 else 1.0

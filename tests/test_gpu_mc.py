@@ -166,3 +166,19 @@ def test_confidence_region_carries_its_check():
     print(f"region {kreg}: qmc {p_qmc} mc {res['mc_p_region']} (1 - alpha = {1 - alpha})", flush=True)
     assert abs(res["mc_p_region"] - p_qmc) < tol
     assert p_qmc >= 1 - alpha
+
+
+def test_confidence_region_from_a_tlr_factor_carries_its_check():
+    """Regions from a TLR factor are checked against the fitted
+    distribution itself (dense factor of the same ordered Sigma)."""
+    k, u, alpha, M = 30, 0.3, 0.1, 40000
+    locs, kern, mu = _field(k, k * k, seed=77, beta=0.08)
+    res = mvn.confidence_region(locs, kern, mu, u, alpha=alpha, N=4000, S=10, seed=5,
+                                opts=mvn.options(tile=128, tlr_eps=1e-6, max_rank=128), device=DEV,
+                                mc_samples=M, mc_seed=6)
+    kreg = res["region"].size
+    assert 0 < kreg < k * k
+    p_qmc = math.exp(res["logP"][kreg - 1])
+    tol = 5.0 * math.sqrt(p_qmc * (1 - p_qmc) / M) + 5.0 * p_qmc * res["rel_stderr"][kreg - 1] + 1e-4
+    print(f"TLR region {kreg}: qmc {p_qmc} mc {res['mc_p_region']}", flush=True)
+    assert abs(res["mc_p_region"] - p_qmc) < tol
