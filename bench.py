@@ -539,9 +539,9 @@ def main() -> int:
                           "copies": 3}))
         return 0
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on exactly one GPU; the path shards over "
-                                   "sample columns across GPUs by design but multi-GPU runs are not "
-                                   "part of this build", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU: the library has no multi-GPU "
+                                   "path (it would shard over sample columns, each GPU holding its own "
+                                   "factor)", "n_gpus": args.gpus}))
         return 2
 
     import torch
