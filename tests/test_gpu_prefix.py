@@ -163,3 +163,26 @@ def test_confidence_region_matches_oracle_prefixes():
     assert np.array_equal(res["region"], np.sort(order[:kref]))
     print(f"region size {kref} of {n}", flush=True)
     assert 0 < kref < n
+
+
+@pytest.mark.parametrize("prec", [mvn.MVN_FP32, mvn.MVN_BF16X3])
+def test_prefix_mixed_precision_every_prefix_within_1e4(prec):
+    """Reduced-precision nested sets against the FP64 oracle's on the same
+    points: |P-hat - P-hat_oracle| <= 1e-4 for every prefix (the mixed
+    precision bar, stated where P = O(1); the deep prefixes are smaller)."""
+    n, N, S, seed = 400, 2000, 4, 71
+    locs, kern, mu = _field(20, n, seed=13)
+    order = oracle.exceedance_order(mu, np.full(n, math.sqrt(kern[0] + kern[3])), 0.2)
+    locs, mu = locs[order], mu[order]
+    a, b = np.full(n, 0.2), np.full(n, np.inf)
+    opts = mvn.options(tile=128, precision=prec)
+    f = mvn.mvn_cholesky(n, locs=locs, kern=kern, opts=opts, device=DEV)
+    r = mvn.mvn_prob_prefix(f, a, b, mu, N=N, S=S, seed=seed, opts=opts)
+    torch.cuda.synchronize()
+    p = np.exp(r["logP"].cpu().numpy())
+    L = oracle.cholesky(oracle.covariance(locs, *kern))
+    at, bt = oracle.centre(a, b, mu)
+    ref = np.exp(oracle.prefix_probs(L, at, bt, N, S, seed)["logP"])
+    err = np.abs(p - ref)
+    print(f"prec {prec}: max |dP| {err.max():.2e} (P from {ref.max():.3f} down to {ref.min():.2e})", flush=True)
+    assert err.max() <= 1e-4
