@@ -891,21 +891,26 @@ int mvn_cholesky_permuted(int n, const double* d_sigma, int ld_sigma, const int6
     }
   }
   if (!opts) return fail(-5, "options are required");
-  size_t base = 0, need = 0;
-  int rc = mvn_cholesky_workspace_bytes(n, opts, &base);
-  if (rc) return -5;  // the options are bad; the message is set
-  rc = mvn_cholesky_permuted_workspace_bytes(n, opts, &need);
-  if (rc) return -5;
+  int bad_tile = 0;
+  if (!opts_ok(opts, &bad_tile)) return fail(-5, "tile must be >= 16 and a multiple of 4 (got %d)", opts->tile);
+  if (!prec_ok(opts->precision)) return fail(-5, "unknown precision %d", opts->precision);
+  if (is_tlr(opts) && tlr_opts_check(opts)) return -5;
+  size_t base = 0, need = 0, fbytes = 0;
+  if (mvn_cholesky_workspace_bytes(n, opts, &base) || mvn_cholesky_permuted_workspace_bytes(n, opts, &need) ||
+      mvn_factor_bytes(n, opts, &fbytes))
+    return -5;  // the options are bad; the message is set
+  if (!factor_buf) return fail(-6, "factor buffer is NULL");
+  if (factor_bytes < fbytes) return fail(-7, "factor buffer too small: %zu < %zu", factor_bytes, fbytes);
   if (!ws) return fail(-8, "workspace is NULL");
   if (ws_bytes < need) return fail(-9, "workspace too small: %zu < %zu", ws_bytes, need);
+  if (!out) return fail(-10, "out is NULL");
   int64_t* d_perm = (int64_t*)((char*)ws + align_up(base));
   hipError_t e = hipMemcpyAsync(d_perm, h_perm, sizeof(int64_t) * (size_t)n, hipMemcpyHostToDevice, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);  // h_perm may be pageable and short-lived
   if (e != hipSuccess) return hip_fail(e, "permutation copy");
-  rc = cholesky_impl(n, d_sigma, ld_sigma, d_perm, nullptr, nullptr, opts, factor_buf, factor_bytes, ws, base, out,
-                     stream);
-  // argument positions of mvn_cholesky_permuted
-  return rc == -7 ? -6 : rc == -8 ? -7 : rc == -9 ? -8 : rc == -10 ? -9 : rc == -11 ? -10 : rc == -6 ? -5 : rc;
+  // every argument is valid here, so the shared implementation only enqueues
+  return cholesky_impl(n, d_sigma, ld_sigma, d_perm, nullptr, nullptr, opts, factor_buf, factor_bytes, ws, base,
+                       out, stream);
 }
 
 int mvn_posterior_workspace_bytes(int n, int m, const mvn_options* opts, size_t* bytes) {
