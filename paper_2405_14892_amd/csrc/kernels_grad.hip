@@ -107,8 +107,8 @@ __global__ __launch_bounds__(256, 2) void grad_kernel(GradArgs p) {
     const long col = chunk * kCols + lane;
     const bool owner = wv == 0;
     const bool valid = owner && col < NS;
-    const uint64_t sidx = valid ? (uint64_t)(col / p.N) : 0;
-    const uint64_t jpt = valid ? (uint64_t)(col % p.N) + 1 : 1;
+    const uint64_t sidx = col < NS ? (uint64_t)(col / p.N) : 0;  // every lane: its own column
+    const uint64_t jpt = col < NS ? (uint64_t)(col % p.N) + 1 : 1;
     LogProd prod{1.0, 0};
 
     // ================= forward pass (the probability sweep, keeping s_i)

@@ -100,8 +100,8 @@ __device__ __forceinline__ void sweep_chunk(const SweepLds& sh, const double* __
   const long col = chunk * kCols + lane;
   const bool owner = wv == 0;
   const bool valid = owner && col < NS;
-  const uint64_t sidx = valid ? (uint64_t)(col / N) : 0;
-  const uint64_t jpt = valid ? (uint64_t)(col % N) + 1 : 1;
+  const uint64_t sidx = col < NS ? (uint64_t)(col / N) : 0;  // every lane: its own column
+  const uint64_t jpt = col < NS ? (uint64_t)(col % N) + 1 : 1;
   LogProd prod{1.0, 0};
   const PrefixOut pre{prefix, (NS + kCols - 1) / kCols, chunk, (uint64_t)(chunk * kCols / N)};
 

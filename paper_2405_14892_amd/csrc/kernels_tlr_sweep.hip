@@ -208,8 +208,8 @@ __global__ __launch_bounds__(256, RB == 128 ? 2 : 4) void tlr_sweep_kernel(TlrSw
     const long col = chunk * kCols + lane;
     const bool owner = wv == 0;
     const bool valid = owner && col < NS;
-    const uint64_t sidx = valid ? (uint64_t)(col / p.N) : 0;
-    const uint64_t jpt = valid ? (uint64_t)(col % p.N) + 1 : 1;
+    const uint64_t sidx = col < NS ? (uint64_t)(col / p.N) : 0;  // every lane: its own column
+    const uint64_t jpt = col < NS ? (uint64_t)(col % p.N) + 1 : 1;
     LogProd prod{1.0, 0};
     const PrefixOut pre{p.prefix, nchunks, chunk, (uint64_t)(chunk * kCols / p.N)};
     for (int ti = 0; ti < p.nt; ++ti) {

@@ -133,22 +133,44 @@ __device__ __forceinline__ LogProd condition_block(
   // does not wait on global memory (the LDS holds one slab; two barriers per
   // slab).  64-row blocks (four workgroups per CU, no register headroom):
   // every lane loads the slab between the two barriers.
+  // The slab of a 128-row block holds the 8 rows' entries in the columns of
+  // their 32-row sub-block (all that wave 0's dot products read), then the
+  // rows' QMC points for the 64 sample columns, which waves 1-3 compute
+  // ahead (every lane's jpt and sidx are its own column's).
   constexpr bool kPF = SL >= 128;
-  constexpr int kPer = kPF ? (kSlab * SL + 191) / 192 : 1;  // slab elements per fetching lane
-  double pf[kPer];
-  const int u = t - 64;  // fetching lane, 0..191 in waves 1-3
+  constexpr int kSlabL = kSlab * kCondSub;                   // L part of a slab
+  constexpr int kPerL = kPF ? (kSlabL + 191) / 192 : 1;      // L entries per fetching lane
+  constexpr int kPerW = (kSlab + 2) / 3;                     // QMC rows per fetching wave
+  static_assert(!kPF || kSlabL + kSlab * kCols <= kSlab * SL, "slab too small for the QMC points");
+  double pf[kPerL], pw[kPerW];
+  const int u = t - 64;         // fetching lane, 0..191 in waves 1-3
+  const int wf = (t >> 6) - 1;  // fetching wave, 0..2
   const auto fetch = [&](int q) {
+    const int kb = q & ~(kCondSub - 1);
 #pragma unroll
-    for (int j = 0; j < kPer; ++j) {
-      const int e = u + 192 * j, ii = e / SL, k = e % SL;
-      pf[j] = (e < kSlab * SL && q + ii < rows && k < q + ii) ? L[(long)(i0 + q + ii) * ld + i0 + k] : 0.0;
+    for (int j = 0; j < kPerL; ++j) {
+      const int e = u + 192 * j, ii = e / kCondSub, k = kb + e % kCondSub;
+      pf[j] = (e < kSlabL && q + ii < rows && k < q + ii) ? L[(long)(i0 + q + ii) * ld + i0 + k] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < kPerW; ++j) {
+      const int ii = wf + 3 * j;
+      pw[j] = (ii < kSlab && q + ii < rows)
+                  ? richtmyer(jpt, c_lat[q + ii], splitmix64(seed, sidx * (uint64_t)n + (uint64_t)(goff + i0 + q + ii)),
+                              periodize)
+                  : 0.0;
     }
   };
   const auto put = [&]() {
 #pragma unroll
-    for (int j = 0; j < kPer; ++j) {
+    for (int j = 0; j < kPerL; ++j) {
       const int e = u + 192 * j;
-      if (e < kSlab * SL) slab[e] = pf[j];
+      if (e < kSlabL) slab[e] = pf[j];
+    }
+#pragma unroll
+    for (int j = 0; j < kPerW; ++j) {
+      const int ii = wf + 3 * j;
+      if (ii < kSlab) slab[kSlabL + ii * kCols + lane] = pw[j];
     }
   };
   if constexpr (kPF) {
@@ -177,12 +199,13 @@ __device__ __forceinline__ LogProd condition_block(
         // the slab row is zero from column i on, so the sum runs to a
         // multiple of 8 with four independent partial sums (the LDS reads
         // then pipeline)
-        const lds_f64* Li = slab + (i - q) * SL;
         const lds_f64* Tk = T + lane;
         double s0 = T[i * kCols + lane], s1 = 0.0, s2 = 0.0, s3 = 0.0;
         const int kend = (i + 7) & ~7;
         // earlier sub-blocks are already folded into T
         const int kbeg = i & ~(kCondSub - 1);
+        // slab row of i, indexed by block column (128-row slabs start at column kbeg)
+        const lds_f64* Li = kPF ? slab + (i - q) * kCondSub - kbeg : slab + (i - q) * SL;
         for (int k = kbeg; k < kend; k += 8) {
           s0 += Li[k] * Tk[k * kCols];
           s1 += Li[k + 1] * Tk[(k + 1) * kCols];
@@ -199,7 +222,8 @@ __device__ __forceinline__ LogProd condition_block(
         const double alpha = (c_at[i] - sum) * rl;
         const double beta = (c_bt[i] - sum) * rl;
         const uint64_t g = (uint64_t)(goff + i0 + i);
-        const double w = richtmyer(jpt, c_lat[i], splitmix64(seed, sidx * (uint64_t)n + g), periodize);
+        const double w = kPF ? (double)slab[kSlabL + (i - q) * kCols + lane]
+                             : richtmyer(jpt, c_lat[i], splitmix64(seed, sidx * (uint64_t)n + g), periodize);
         const Step st = MIXED ? condition_step_mixed_with(alpha, beta, w, 1.0 - w, ninv)
                               : condition_step_with(alpha, beta, w, 1.0 - w, ninv);
         T[i * kCols + lane] = valid ? st.y : 0.0;
