@@ -29,24 +29,53 @@ struct PrefixOut {
 
 constexpr int kNoExp = -(1 << 30);  // exponent of an empty sum
 
+// Wave64 reductions on DPP moves (no LDS crossbar): xor 1 and 2 inside each
+// quad, the half-row and row mirrors (8- and 16-lane groups), then the row
+// 15 / lane 31 broadcasts that fold rows 0-1 into 1 and 0-1 into 2-3; lane 63
+// ends with the whole wave, read back as a uniform value.  Lanes of a row
+// that a broadcast does not write take the identity.
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ int dpp_i32(int old, int v) {
+  return __builtin_amdgcn_update_dpp(old, v, CTRL, ROWS, 0xF, false);
+}
+
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ double dpp_f64(double v) {  // identity 0.0 (all bits zero)
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = dpp_i32<CTRL, ROWS>(0, (int)b), hi = dpp_i32<CTRL, ROWS>(0, (int)(b >> 32));
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ int wave_max_i32(int x) {
+  x = max(x, dpp_i32<0xB1>(kNoExp, x));        // quad_perm [1, 0, 3, 2]
+  x = max(x, dpp_i32<0x4E>(kNoExp, x));        // quad_perm [2, 3, 0, 1]
+  x = max(x, dpp_i32<0x141>(kNoExp, x));       // row_half_mirror
+  x = max(x, dpp_i32<0x140>(kNoExp, x));       // row_mirror
+  x = max(x, dpp_i32<0x142, 0xA>(kNoExp, x));  // row_bcast15 into rows 1 and 3
+  x = max(x, dpp_i32<0x143, 0xC>(kNoExp, x));  // row_bcast31 into rows 2 and 3
+  return __builtin_amdgcn_readlane(x, 63);
+}
+
+__device__ __forceinline__ double wave_sum_f64(double x) {
+  x += dpp_f64<0xB1>(x);
+  x += dpp_f64<0x4E>(x);
+  x += dpp_f64<0x141>(x);
+  x += dpp_f64<0x140>(x);
+  x += dpp_f64<0x142, 0xA>(x);
+  x += dpp_f64<0x143, 0xC>(x);
+  const long long b = __builtin_bit_cast(long long, x);
+  const int lo = __builtin_amdgcn_readlane((int)b, 63), hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
 __device__ __forceinline__ void prefix_row(const LogProd& prod, bool valid, uint64_t sidx, const PrefixOut& pre,
                                            long row) {
   const bool live = valid && prod.m > 0.0;
   const bool first = sidx == pre.s_first;
-  int e0 = (live && first) ? prod.e : kNoExp;
-  int e1 = (live && !first) ? prod.e : kNoExp;
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    e0 = max(e0, __shfl_xor(e0, off));
-    e1 = max(e1, __shfl_xor(e1, off));
-  }
-  double v0 = (live && first) ? ldexp(prod.m, prod.e - e0) : 0.0;
-  double v1 = (live && !first) ? ldexp(prod.m, prod.e - e1) : 0.0;
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    v0 += __shfl_xor(v0, off);
-    v1 += __shfl_xor(v1, off);
-  }
+  const int e0 = wave_max_i32((live && first) ? prod.e : kNoExp);
+  const int e1 = wave_max_i32((live && !first) ? prod.e : kNoExp);
+  const double v0 = wave_sum_f64((live && first) ? ldexp(prod.m, prod.e - e0) : 0.0);
+  const double v1 = wave_sum_f64((live && !first) ? ldexp(prod.m, prod.e - e1) : 0.0);
   if ((threadIdx.x & 63) == 0) {
     double* d = pre.part + (row * pre.nchunks + pre.chunk) * 4;
     d[0] = (double)e0;
