@@ -508,6 +508,12 @@ template <class Next, class Rest>
 static hipError_t right_looking(int ld, int tile, double* A, int* info, hipStream_t st, SideStream* sd,
                                 Next next, Rest rest, int kstop = 0) {
   bool pending = false, used = false;  // a rest() on the side stream not yet waited for; any
+  // on an error, let the side stream drain before returning, so that none of
+  // its kernels still writes A once the caller sees the failure
+  auto fail = [&](hipError_t e) {
+    if (used) (void)hipStreamSynchronize(sd->s);
+    return e;
+  };
   const int kend = kstop > 0 ? kstop : ld;
   for (int k0 = 0; k0 < kend; k0 += tile) {
     const int kw = min(tile, ld - k0);
@@ -518,24 +524,29 @@ static hipError_t right_looking(int ld, int tile, double* A, int* info, hipStrea
         rest(k0, kw, c1, st);
       } else {
         const int c2 = min(c1 + tile, ld);
-        hipEventRecord(sd->ev[0], st);
-        if (pending) hipStreamWaitEvent(st, sd->ev[1], 0);
+        hipError_t e = hipEventRecord(sd->ev[0], st);
+        if (e == hipSuccess && pending) e = hipStreamWaitEvent(st, sd->ev[1], 0);
+        if (e != hipSuccess) return fail(e);
         pending = false;
         next(k0, kw, c2, st);
         if (c2 < ld) {
-          hipStreamWaitEvent(sd->s, sd->ev[0], 0);
+          used = true;
+          e = hipStreamWaitEvent(sd->s, sd->ev[0], 0);
+          if (e != hipSuccess) return fail(e);
           rest(k0, kw, c2, sd->s);
-          hipEventRecord(sd->ev[1], sd->s);
-          pending = used = true;
+          e = hipEventRecord(sd->ev[1], sd->s);
+          if (e != hipSuccess) return fail(e);
+          pending = true;
         }
       }
     }
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (e != hipSuccess) return fail(e);
   }
   if (used) {
-    hipEventRecord(sd->ev[2], sd->s);
-    hipStreamWaitEvent(st, sd->ev[2], 0);
+    hipError_t e = hipEventRecord(sd->ev[2], sd->s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, sd->ev[2], 0);
+    if (e != hipSuccess) return fail(e);
   }
   return hipGetLastError();
 }

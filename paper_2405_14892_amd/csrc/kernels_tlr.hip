@@ -593,15 +593,25 @@ hipError_t launch_tlr_cholesky(const TlrCholArgs& a, hipStream_t st) {
     const int P = nt - j - 1;
     const bool overlap = sd && P > 0;
     hipStream_t ps = overlap ? sd->s : st;
+    // on an error, let the side stream drain before returning, so that none
+    // of its kernels still writes the tiles once the caller sees the failure
+    auto fail = [&](hipError_t e) {
+      if (overlap) (void)hipStreamSynchronize(ps);
+      return e;
+    };
     if (overlap) {
-      hipEventRecord(sd->ev[0], st);
-      hipStreamWaitEvent(ps, sd->ev[0], 0);
+      hipError_t e = hipEventRecord(sd->ev[0], st);
+      if (e == hipSuccess) e = hipStreamWaitEvent(ps, sd->ev[0], 0);
+      if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(tlr_info_copy_kernel, dim3(1), dim3(64), 0, ps, (const int*)a.info, a.local_info);
     hipError_t e = launch_cholesky_f64(m, 128, Djj, a.local_info, ps, false);
-    if (e != hipSuccess) return e;
+    if (e != hipSuccess) return fail(e);
     hipLaunchKernelGGL(tlr_info_kernel, dim3(1), dim3(64), 0, ps, a.info, (const int*)a.local_info, j * m);
-    if (overlap) hipEventRecord(sd->ev[1], ps);
+    if (overlap) {
+      e = hipEventRecord(sd->ev[1], ps);
+      if (e != hipSuccess) return fail(e);
+    }
     if (P > 0) {
       // the T workspace (idle between the updates of two tile columns) holds
       // the transposed U columns, kTlrPairBatch tiles per launch
@@ -609,12 +619,15 @@ hipError_t launch_tlr_cholesky(const TlrCholArgs& a, hipStream_t st) {
       for (int i0 = 0; i0 < P; i0 += pb)
         hipLaunchKernelGGL(tlr_aca_kernel, dim3(std::min(pb, P - i0)), dim3(256), 0, st, (const double*)a.tiles, j,
                            i0, m, rs, a.rcap, a.eps, a.U, a.Vt, a.ranks, a.T, (const int*)a.info);
-      if (overlap) hipStreamWaitEvent(st, sd->ev[1], 0);
+      if (overlap) {
+        e = hipStreamWaitEvent(st, sd->ev[1], 0);
+        if (e != hipSuccess) return fail(e);
+      }
       hipLaunchKernelGGL(tlr_trsm_rows_kernel, dim3(P, rs / 4), dim3(256), 0, st, (const double*)a.tiles, j, m, rs,
                          a.Vt, (const int*)a.ranks, (const int*)a.info);
     }
     e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (e != hipSuccess) return fail(e);
   }
   return hipGetLastError();
 }
