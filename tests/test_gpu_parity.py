@@ -39,6 +39,21 @@ def test_cholesky_from_locations_matches_oracle(n, tile):
     assert np.all(np.triu(L, 1) == 0)
 
 
+def test_cholesky_many_tile_columns_matches_oracle():
+    """4500 sites, tile 128: 36 tile columns, so 34 side-stream trailing
+    updates (595 tiles in the first) overlap the sub-panel chains."""
+    n, tile = 4500, 128
+    print(f"cholesky n={n} tile={tile}", flush=True)
+    locs, kern = _matern_case(n, 7, nu=0.5, beta=0.1, nugget=1e-4)
+    f = mvn.mvn_cholesky(n, locs=locs, kern=kern, opts=mvn.options(tile=tile), device=DEV)
+    torch.cuda.synchronize()
+    assert f.info() == 0
+    L = f.L().cpu().numpy()
+    ref = oracle.cholesky(oracle.covariance(locs, *kern))
+    assert np.max(np.abs(L - ref)) < 1e-12
+    assert np.all(np.triu(L, 1) == 0)
+
+
 def test_cholesky_from_sigma_and_not_spd():
     rng = np.random.default_rng(3)
     m = rng.standard_normal((300, 300))
