@@ -11,7 +11,8 @@
  *     all others are host pointers.  The library never allocates device
  *     memory: callers size buffers with the *_bytes queries and pass them in.
  *   - Calls are asynchronous on the given stream and return after host-side
- *     validation and enqueue.  Results are ready when the stream reaches them.
+ *     validation and enqueue, except where an entry point's comment says it
+ *     synchronises the stream.  Results are ready when the stream reaches them.
  *   - Return value 0 = enqueued.  A negative value -k means argument k
  *     (1-based) is invalid; nothing was enqueued.  -1000 - e means a HIP
  *     runtime error e at launch.  mvn_last_error() gives a message.
