@@ -24,14 +24,20 @@ from .sov import condition, reduce_samples
 
 
 def sweep_prefix(L: np.ndarray, at: np.ndarray, bt: np.ndarray, N: int, S: int, seed: int,
-                 periodize: bool = False) -> np.ndarray:
+                 periodize: bool = False, dim: int | None = None) -> np.ndarray:
     """Running log-products: ell[k, c] = sum_{i <= k} log d_i of sample c,
     for every row k (the recurrence of ``sov.sweep``, recorded after each
-    row)."""
+    row).  ``dim``: the dimension of the problem whose leading rows L, at
+    and bt are (default: L's own); it fixes the QMC shifts, which are
+    numbered s * dim + i, so the first rows of a large problem can be
+    evaluated without the rest."""
     n = L.shape[0]
+    dim = n if dim is None else int(dim)
+    if dim < n:
+        raise ValueError("dim must be at least the number of rows")
     cols = np.arange(N * S, dtype=np.int64)
     A = lattice(n)
-    D = shifts(seed, n, S)
+    D = shifts(seed, dim, S)
     Y = np.zeros((n, cols.size))
     run = np.zeros(cols.size)
     ell = np.zeros((n, cols.size))
@@ -50,11 +56,12 @@ def sweep_prefix(L: np.ndarray, at: np.ndarray, bt: np.ndarray, N: int, S: int, 
 
 
 def prefix_probs(L: np.ndarray, at: np.ndarray, bt: np.ndarray, N: int, S: int, seed: int,
-                 periodize: bool = False) -> dict:
+                 periodize: bool = False, dim: int | None = None) -> dict:
     """log P-hat(S_k) for k = 1..n (index k - 1) and its relative standard
     error over the S shifts (NaN for S == 1), each reduced exactly as the
-    full estimate (mean over a shift's N points, then over shifts)."""
-    ell = sweep_prefix(L, at, bt, N, S, seed, periodize)
+    full estimate (mean over a shift's N points, then over shifts).
+    ``dim`` as in ``sweep_prefix``."""
+    ell = sweep_prefix(L, at, bt, N, S, seed, periodize, dim)
     n = ell.shape[0]
     logp = np.empty(n)
     rel = np.empty(n)

@@ -6,6 +6,9 @@ through properties that hold at any size.
   the oracle's Cholesky, and the per-sample log-products l of sampled sample
   columns against the oracle's sweep of those columns (1e-10 relative, the
   FP64 bar).
+* Confidence-region detection on the same field (sites in exceedance
+  order, one nested-set sweep): the first 200 nested-set probabilities
+  against the oracle's from the leading block, 1e-10 relative.
 * 65536 sites, tile low rank (tile 1024, eps = 1e-5, max_rank 256): sampled
   panel tiles meet ||A - L_ik L_kk^T||_F <= eps on the tile compressed and
   have at least the SVD eps-rank; log P-hat agrees with the dense FP64 path
@@ -70,6 +73,41 @@ def test_prec16k_full_size_factor_and_sampled_columns():
     for j in bad:  # only where the deciding value sits on a limit to rounding
         k = min(first[mc_cols][j], ref_first[j])
         assert min(abs(X[k, j] - w.a[k]), abs(X[k, j] - w.b[k])) < 1e-9
+
+
+def test_crd16k_full_size_leading_nested_sets():
+    """Confidence-region detection on the 16384-site field as the benchmark
+    runs it (sites in order of marginal exceedance of u = 0.5, tile 512,
+    N = 20000 x S = 10, 128-row blocks): the first 200 nested-set log P-hat
+    of the one sweep against the oracle's from the leading 200 x 200 block
+    of the ordered covariance, with the shifts of the 16384-site problem
+    (1e-10 relative, the FP64 bar); the last nested set is the full
+    estimate."""
+    import math
+    w = workloads.make_workload("prec16k")
+    u, K = 0.5, 200
+    kern = (w.sigma2, w.beta, w.nu, w.nugget)
+    field = w.extra["field"]
+    order = oracle.exceedance_order(field, np.full(w.n, math.sqrt(w.sigma2 + w.nugget)), u)
+    a, b, mu = np.full(w.n, u), np.full(w.n, np.inf), field[order]
+    opts = mvn.options(tile=w.tile)
+    print("crd16k: GPU", flush=True)
+    f = mvn.mvn_cholesky(w.n, locs=w.locs[order], kern=kern, opts=opts)
+    r = mvn.mvn_prob_prefix(f, a, b, mu, N=w.N, S=w.S, seed=w.seed, opts=opts)
+    full = mvn.mvn_prob(f, a, b, mu, N=w.N, S=w.S, seed=w.seed, opts=opts)
+    torch.cuda.synchronize()
+    assert f.info() == 0
+    logp = r["logP"].cpu().numpy()
+    full_logp = full["logP"].item()
+    del f, r, full
+    print("crd16k: oracle on the leading block", flush=True)
+    Lk = oracle.cholesky(oracle.covariance(w.locs[order][:K], *kern))
+    at, bt = oracle.centre(a[:K], b[:K], mu[:K])
+    ref = oracle.prefix_probs(Lk, at, bt, w.N, w.S, w.seed, dim=w.n)["logP"]
+    rel = np.abs(logp[:K] - ref) / np.maximum(1.0, np.abs(ref))
+    print("crd16k: log P of nested sets 1, 10, 200:", logp[[0, 9, K - 1]], "max rel", rel.max(), flush=True)
+    assert rel.max() < 1e-10
+    assert abs(logp[-1] - full_logp) <= 1e-12 * max(1.0, abs(full_logp))
 
 
 def test_tlr64k_full_size_properties():

@@ -81,3 +81,28 @@ def test_exceedance_order():
     sd = np.array([1.0, 2.0, 1.0, 1.0])
     # P(X > 0.5): 1 - Phi((0.5 - mu) / sd) = 0.309, 0.599, 0.067, 0.691
     assert oracle.exceedance_order(mu, sd, 0.5).tolist() == [3, 1, 0, 2]
+
+
+def test_leading_rows_of_a_larger_problem():
+    """The first k nested sets of an n-site problem from its leading k x k
+    block alone, with dim = n numbering the shifts: equal, bit for bit, to
+    the first k entries of the full n-site computation; without dim the
+    shifts (and so the estimates) differ; dim below the row count is an
+    error."""
+    n, k, N, S, seed = 30, 11, 131, 3, 17
+    rng = np.random.default_rng(4)
+    sig = _ar1(n, 0.7)
+    a = rng.uniform(-2.0, 0.0, n)
+    b = rng.uniform(0.2, 2.0, n)
+    L = oracle.cholesky(sig)
+    full = oracle.prefix_probs(L, a, b, N=N, S=S, seed=seed)["logP"]
+    lead = oracle.prefix_probs(L[:k, :k], a[:k], b[:k], N=N, S=S, seed=seed, dim=n)["logP"]
+    assert np.array_equal(lead, full[:k])
+    own = oracle.prefix_probs(L[:k, :k], a[:k], b[:k], N=N, S=S, seed=seed)["logP"]
+    assert not np.array_equal(own, full[:k])
+    try:
+        oracle.prefix_probs(L[:k, :k], a[:k], b[:k], N=N, S=S, seed=seed, dim=k - 1)
+    except ValueError:
+        pass
+    else:
+        raise AssertionError("dim below the row count was accepted")
