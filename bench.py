@@ -349,7 +349,7 @@ def variant_autotune_dense(w, dev) -> dict:
 
 
 def variant_crd(dev) -> dict:
-    """Confidence-region detection (Section III-A, Algorithm 1) on the
+    """Confidence-region detection (Section III-C with Algorithm 1 of Section IV-A) on the
     16384-site field: sites ordered by marginal exceedance of u = 0.5, the
     factor in that order, and one nested-set sweep giving log P-hat of every
     prefix; beside it the full-estimate sweep on the same factor.  The cost
@@ -384,7 +384,7 @@ def variant_crd(dev) -> dict:
     p = np.exp(logp)
     prefix_ms, full_ms = ev[1].elapsed_time(ev[2]), ev[2].elapsed_time(ev[3])
     per_set_s = full_ms * 1e-3 * sum((k / w.n) ** 2 for k in range(1, w.n + 1))
-    # Monte Carlo check of the regions (Section IV-B): M fields on the same factor
+    # Monte Carlo check of the regions (Section V-C): M fields on the same factor
     M = 50000
     mc = {}
     for rows in (64, 128):
@@ -426,7 +426,7 @@ def variant_crd(dev) -> dict:
 
 
 def variant_posterior(dev) -> dict:
-    """Confidence regions on the posterior of Section IV-A at the paper's
+    """Confidence regions on the posterior of Section V-B at the paper's
     synthetic size: 40 000 grid sites, 6 250 noisy observations (noise sd
     0.5), exponential kernel with range 0.033 / 0.1 / 0.234; QMC size
     10 000 (N = 1000 x S = 10); threshold u = 0.5.  Per range: the posterior

@@ -42,7 +42,7 @@ extern "C" {
  *   hi*hi + hi*lo + lo*hi accumulated (about 16 significant bits). */
 typedef enum { MVN_FP64 = 0, MVN_FP32 = 1, MVN_BF16 = 2, MVN_BF16X3 = 3 } mvn_precision;
 
-/* Matern covariance parameters (Section III-C, Eq. for C(h; theta)):
+/* Matern covariance parameters (Section IV-A, Eq. for C(h; theta)):
  * C(h) = sigma2 / (2^(nu-1) Gamma(nu)) (h/beta)^nu K_nu(h/beta), plus
  * nugget on the diagonal.  The paper calls the range "a"; here it is beta.
  * Any 0 < nu <= 20: nu = 0.5, 1.5, 2.5 by the closed forms of K_nu at
@@ -183,8 +183,8 @@ int mvn_prob(const mvn_factor* f, const double* d_a, const double* d_b, const do
 int mvn_prob_workspace_bytes_factor(const mvn_factor* f, int N, int S, const mvn_options* opts,
                                     size_t* bytes, hipStream_t stream);
 
-/* Nested-set probabilities of confidence-region detection (Section III-A,
- * Algorithm 1), for the sites in the factor's order (the caller orders them,
+/* Nested-set probabilities of confidence-region detection (Section III-C with
+ * Algorithm 1 of Section IV-A), for the sites in the factor's order (the caller orders them,
  * e.g. by decreasing marginal exceedance probability, before building the
  * factor): log P-hat(a_i <= X_i <= b_i, i < k) for every k = 1..n from ONE
  * sweep.  The running product d_1 .. d_k of every sample is a sample of the
@@ -226,7 +226,7 @@ int mvn_cholesky_permuted(int n, const double* d_sigma, int ld_sigma, const int6
 
 /* Posterior of a Gaussian field x ~ N(mu, Sigma) at n sites, observed at m
  * of them with noise: y = A x + eps, eps ~ N(0, noise_var I), A the m x n
- * indicator matrix of the sites h_obs (Section IV-A, the equations for
+ * indicator matrix of the sites h_obs (Section V-B, the equations for
  * Sigma_post and mu_post, which then replace Sigma and mu in Algorithm 1).
  * Sigma is the Matern covariance of d_locs (n x 2, device) with kern (the
  * nugget is part of Sigma).  Computed as the Woodbury form
@@ -256,7 +256,7 @@ int mvn_posterior(int n, const double* d_locs, const double* d_mu, int m, const 
                   void* ws, size_t ws_bytes, double* d_mu_post, double* d_var_post, int* d_info,
                   double** sigma_post, int* ld_sigma_post, hipStream_t stream);
 
-/* Monte Carlo check of nested-set probabilities (Section IV-B, the check of
+/* Monte Carlo check of nested-set probabilities (Section V-C, the check of
  * detected confidence regions by direct sampling): M fields X = mu + L Z
  * from the fitted distribution, for the sites in the factor's order, and for
  * each nested set (the first k sites) the number of fields inside the limits

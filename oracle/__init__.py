@@ -7,7 +7,7 @@ does, and it imports nothing from the library.
 
 What it computes, in the paper's order (arXiv 2405.14892):
 
-* ``covariance``  - Matern covariance of Section III-C (Eq. for C(h; theta)).
+* ``covariance``  - Matern covariance of Section IV-A (Eq. for C(h; theta)).
 * ``cholesky``    - Sigma = L L^T, the factorisation step of Algorithm 1.
 * ``qmc``         - randomised Richtmyer lattice points that play the role of
                     the uniform matrix R of Algorithm 2.
@@ -18,10 +18,10 @@ What it computes, in the paper's order (arXiv 2405.14892):
                     differences of log P at fixed QMC points.
 * ``tlr``         - per-tile truncated-SVD compression (Section III-E).
 * ``crd``         - the nested-set probabilities of confidence-region
-                    detection (Section III-A, Algorithm 1) from one sweep.
+                    detection (Section III-C with Algorithm 1 of Section IV-A) from one sweep.
 * ``posterior``   - the posterior covariance and mean of a field observed
-                    with noise at some sites (Section IV-A).
-* ``mc``          - the Monte Carlo check of detected regions (Section IV-B):
+                    with noise at some sites (Section V-B).
+* ``mc``          - the Monte Carlo check of detected regions (Section V-C):
                     fields X = mu + L Z and, per nested set, the samples that
                     meet the event on all of its sites.
 

@@ -1,4 +1,4 @@
-"""Matern covariance (paper Section III-C, Eq. for C(||h||; theta)).
+"""Matern covariance (paper Section IV-A, Eq. for C(||h||; theta)).
 
 C(h) = sigma^2 / (2^(nu-1) Gamma(nu)) (h/beta)^nu K_nu(h/beta),  C(0) = sigma^2.
 

@@ -1,7 +1,7 @@
 """Nested-set probabilities of confidence-region detection, from one SOV
 sweep (test infrastructure: see the package header).
 
-Section III-A (Algorithm 1) detects the excursion region of a Gaussian field
+Section III-C with Algorithm 1 of Section IV-A detects the excursion region of a Gaussian field
 by ordering the sites by marginal exceedance probability and evaluating
 P(X_i in [a_i, b_i] for i in S_k) for the nested sets S_k = {first k sites},
 k = 1..n.  With the sites in that order, the SOV recurrence of Eq. (sov1) for

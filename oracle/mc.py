@@ -1,7 +1,7 @@
 """Monte Carlo check of nested-set probabilities (test infrastructure: see
 the package header).
 
-Section IV-B validates detected confidence regions by plain Monte Carlo:
+Section V-C validates detected confidence regions by plain Monte Carlo:
 draw fields from the fitted distribution, X = mu + L Z with Z standard
 normal and L the Cholesky factor of Sigma, and take the fraction of fields
 that meet the event on every site of the region.  Since the regions of

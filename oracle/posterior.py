@@ -1,7 +1,7 @@
 """Posterior of a Gaussian field given noisy observations of some of its
 sites (test infrastructure: see the package header).
 
-Section IV-A builds its synthetic confidence-region problems from a field
+Section V-B builds its synthetic confidence-region problems from a field
 x ~ N(mu, Sigma) observed at m of its n sites with additive noise
 N(0, sigma_eps^2): y = A x + eps, A the m x n indicator matrix of the
 observed sites.  The posterior of x given y is Gaussian with (the two

@@ -203,7 +203,7 @@ def mvn_cholesky_permuted(sigma, perm, opts: MvnOptions | None = None) -> Factor
 def mvn_posterior(locs, kern: tuple, obs, y, noise_var: float, mu=None, opts: MvnOptions | None = None,
                   device="cuda") -> dict:
     """Posterior of the field N(mu, Sigma(locs; kern)) given y = x[obs] +
-    N(0, noise_var) (Section IV-A).  Returns device tensors ``mu_post``,
+    N(0, noise_var) (Section V-B).  Returns device tensors ``mu_post``,
     ``var_post``, ``sigma_post`` (n x n view of the lower triangle, valid as
     long as the returned dict is kept) and the host int ``info``."""
     import numpy as np
@@ -324,7 +324,7 @@ def confidence_region(locs, kern: tuple, mu, u: float, alpha: float = 0.05, N: i
                       seed: int = 1, opts: MvnOptions | None = None, device="cuda", mc_samples: int = 0,
                       mc_seed: int = 2):
     """Positive excursion set of a Gaussian field at level u with joint
-    probability >= 1 - alpha (Section III-A, Algorithm 1): the sites in order
+    probability >= 1 - alpha (Section III-C with Algorithm 1 of Section IV-A): the sites in order
     of decreasing marginal exceedance probability P(X_i > u), the factor of
     Sigma in that order, and one nested-set sweep of the event X_i > u.
     The excursion function of the k-th site in that order is P-hat of the
@@ -332,7 +332,7 @@ def confidence_region(locs, kern: tuple, mu, u: float, alpha: float = 0.05, N: i
     kern = (sigma2, beta, nu, nugget).  Returns a dict with ``order``,
     ``logP`` (per prefix), ``excursion`` (per site, in the caller's site
     order) and ``region`` (site indices).  With mc_samples > 0 the region
-    is checked by direct sampling of the fitted distribution (Section IV-B;
+    is checked by direct sampling of the fitted distribution (Section V-C;
     through the dense factor of the same ordered Sigma, also when the
     regions came from a TLR factor): ``mc_p`` is the fraction of sampled fields above u on
     the first k sites, per k, and ``mc_p_region`` that fraction for the
@@ -371,7 +371,7 @@ def posterior_confidence_region(locs, kern: tuple, obs, y, noise_var: float, u: 
                                 mu=None, N: int = 1000, S: int = 10, seed: int = 1,
                                 opts: MvnOptions | None = None, device="cuda", mc_samples: int = 0,
                                 mc_seed: int = 2) -> dict:
-    """Algorithm 1 on the posterior of Section IV-A: Sigma_post and mu_post
+    """Algorithm 1 on the posterior of Section V-B: Sigma_post and mu_post
     from the observations, the sites ordered by decreasing posterior
     marginal exceedance probability of u, the factor of Sigma_post in that
     order (dense, or TLR with opts.tlr_eps > 0), one nested-set sweep, and

@@ -1,5 +1,5 @@
 // Monte Carlo check of detected confidence regions (arXiv 2405.14892,
-// Section IV-B): fields X = mu + L Z drawn from the fitted distribution, and
+// Section V-C): fields X = mu + L Z drawn from the fitted distribution, and
 // for every sample the first site (in the factor's order) where X leaves
 // [a, b].  Because the regions of Algorithm 1 are nested (the first k sites
 // in exceedance order), that one index per sample gives the Monte Carlo

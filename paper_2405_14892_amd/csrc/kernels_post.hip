@@ -1,5 +1,5 @@
 // Posterior of a Gaussian field observed with noise at m of its n sites
-// (arXiv 2405.14892, Section IV-A, the equations for Sigma_post and
+// (arXiv 2405.14892, Section V-B, the equations for Sigma_post and
 // mu_post), by one partial Cholesky factorisation of a bordered matrix.
 //
 // With K = Sigma_oo + sigma_eps^2 I (the observed sites), C = Sigma_o. (m x

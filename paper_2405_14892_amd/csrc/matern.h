@@ -1,4 +1,4 @@
-// Matern covariance of arXiv 2405.14892, Section III-C (the equation for
+// Matern covariance of arXiv 2405.14892, Section IV-A (the equation for
 // C(||h||; theta)), as printed: C(h) = sigma^2 / (2^(nu-1) Gamma(nu))
 // (h/beta)^nu K_nu(h/beta), C(0) = sigma^2, with K_nu the modified Bessel
 // function of the second kind.  (The paper calls the range "a".)

@@ -16,7 +16,7 @@ typedef __attribute__((address_space(3))) double lds_f64;
 typedef __attribute__((address_space(3))) uint64_t lds_u64;
 
 // Running products of every row for the nested-set probabilities of
-// confidence-region detection (Section III-A, Algorithm 1): after row r the
+// confidence-region detection (Section III-C with Algorithm 1 of Section IV-A): after row r the
 // wave's samples' products m 2^e are summed exactly in base 2, split by
 // shift (slot 0: the chunk's first shift, slot 1: the next one; a chunk of
 // 64 consecutive samples meets at most two shifts when N >= 64), and stored

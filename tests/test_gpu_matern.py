@@ -1,4 +1,4 @@
-"""General-smoothness Matern covariance (Section III-C, the equation for
+"""General-smoothness Matern covariance (Section IV-A, the equation for
 C(||h||; theta), K_nu of any order) on the GPU: the dense factor of Sigma
 built from locations against the oracle's (scipy's K_nu) for smoothness
 values off the closed forms, among them the one fitted to the paper's wind

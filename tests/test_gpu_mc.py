@@ -1,4 +1,4 @@
-"""Monte Carlo check of nested sets (Section IV-B) through the C ABI: every
+"""Monte Carlo check of nested sets (Section V-C) through the C ABI: every
 sample's first failing site against the oracle's draws of the same fields
 (counter-based normals, so the same Z on both sides), over ragged sizes,
 both block shapes, samples that fail early (the chunk stops) and samples
@@ -154,7 +154,7 @@ def test_rejections():
 
 def test_confidence_region_carries_its_check():
     """The region's Monte Carlo fraction against its QMC probability (the
-    check of Section IV-B: near 1 - alpha)."""
+    check of Section V-C: near 1 - alpha)."""
     k, u, alpha, M = 30, 0.3, 0.1, 40000
     locs, kern, mu = _field(k, k * k, seed=77, beta=0.08)
     res = mvn.confidence_region(locs, kern, mu, u, alpha=alpha, N=4000, S=10, seed=5,

@@ -1,4 +1,4 @@
-"""Posterior of a field observed with noise (Section IV-A) through the C
+"""Posterior of a field observed with noise (Section V-B) through the C
 ABI: Sigma_post, mu_post and the marginal variances from one partial
 factorisation of the bordered matrix against the oracle's literal
 equations; the factor of Sigma_post in a given site order against the

@@ -1,5 +1,5 @@
-"""Nested-set probabilities of confidence-region detection (Section III-A,
-Algorithm 1) through the C ABI: every prefix log P-hat of one sweep against
+"""Nested-set probabilities of confidence-region detection (Section III-C with
+Algorithm 1 of Section IV-A) through the C ABI: every prefix log P-hat of one sweep against
 the oracle's running products (oracle.prefix_probs) on identical QMC points,
 FP64 to 1e-10 relative; the last prefix against the full estimate; mixed
 precision against the same call's full estimate; rejections; and the

@@ -28,7 +28,7 @@ def _read_pairs(name):
 # ---------------------------------------------------------------- covariance
 @pytest.mark.parametrize("nu", [0.5, 1.5])
 def test_matern_closed_forms_match_bessel_formula(nu):
-    """nu=1/2, 3/2 closed forms equal the printed K_nu formula (Section III-C)."""
+    """nu=1/2, 3/2 closed forms equal the printed K_nu formula (Section IV-A)."""
     h = np.linspace(1e-4, 3.0, 500)
     sigma2, beta = 1.7, 0.13
     z = h / beta

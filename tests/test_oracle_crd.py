@@ -1,4 +1,4 @@
-"""Pins of the oracle's nested-set probabilities (Section III-A, Algorithm 1:
+"""Pins of the oracle's nested-set probabilities (Section III-C with Algorithm 1 of Section IV-A:
 P(S_k) for the first k sites, from the running products of one sweep):
 exact first prefix, exact products for independent sites, closed-form
 orthant probabilities for the two- and three-site prefixes, monotonicity,

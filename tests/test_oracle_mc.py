@@ -1,4 +1,4 @@
-"""Pins of the oracle's Monte Carlo check of nested sets (Section IV-B: the
+"""Pins of the oracle's Monte Carlo check of nested sets (Section V-C: the
 fraction of fields X = mu + L Z inside the limits on every site of a set):
 the counter layout of the draws against published SplitMix64 outputs, the
 distribution of the normals, independent sites, the two- and three-site

@@ -1,4 +1,4 @@
-"""Pins of the oracle's posterior (Section IV-A: Sigma_post and mu_post of a
+"""Pins of the oracle's posterior (Section V-B: Sigma_post and mu_post of a
 field observed with noise at some sites): the scalar conjugate normal case,
 the kriging (Woodbury) form, the noiseless limit (the conditional Gaussian
 of the unobserved sites, variance zero at the observed ones), repeated
