@@ -42,6 +42,24 @@ extern "C" {
  *   hi*hi + hi*lo + lo*hi accumulated (about 16 significant bits). */
 typedef enum { MVN_FP64 = 0, MVN_FP32 = 1, MVN_BF16 = 2, MVN_BF16X3 = 3 } mvn_precision;
 
+/* Trailing-update arithmetic of a dense factorisation whose precision is
+ * not MVN_FP64 (the sweep's GEMM always uses `precision`; the paper names
+ * mixed precision for these updates as future work, Section VII).
+ *   MVN_CHOL_ADAPTIVE (default): a tile-wise precision map.  The update of
+ *     trailing tile (i, j) by tile column k, L_ik L_jk^T, runs in the reduced
+ *     type when its rounding-error bound u ||L_ik||_F ||L_jk||_F (u: the
+ *     type's unit roundoff plus K 2^-24 for FP32 accumulation over the
+ *     tile's K products) is at most chol_tol * max_i Sigma_ii, otherwise in
+ *     FP32 when FP32's bound is, otherwise in FP64.  Tiles next to the
+ *     diagonal, whose panel blocks carry the factor's mass, stay precise.
+ *   MVN_CHOL_UNIFORM: every trailing update in the reduced type (loses
+ *     positive definiteness on ill-conditioned Sigma: a BF16 factorisation of
+ *     a Matern 3/2 field on a 128 x 128 grid with condition number about 4e6
+ *     fails at pivot 517).
+ *   MVN_CHOL_FP64: the factorisation in FP64; the reduced type is used only
+ *     by the sweep's limit-update GEMM. */
+typedef enum { MVN_CHOL_ADAPTIVE = 0, MVN_CHOL_UNIFORM = 1, MVN_CHOL_FP64 = 2 } mvn_chol_mode;
+
 /* Matern covariance parameters (Section IV-A, Eq. for C(h; theta)):
  * C(h) = sigma2 / (2^(nu-1) Gamma(nu)) (h/beta)^nu K_nu(h/beta), plus
  * nugget on the diagonal.  The paper calls the range "a"; here it is beta.
@@ -70,14 +88,17 @@ typedef struct mvn_options {
                      /* off-diagonal tile is compressed to U V^T with         */
                      /* ||A_ij - U V^T||_F <= tlr_eps (absolute).  <= 0: dense */
   int max_rank;      /* TLR rank cap, 1 .. min(256, tile)                      */
-  int reserved1;
+  int chol_mode;     /* mvn_chol_mode (dense factors, precision != MVN_FP64)   */
+  double chol_tol;   /* MVN_CHOL_ADAPTIVE: error bound per tile update,        */
+                     /* relative to max_i Sigma_ii; <= 0 selects 1e-9          */
 } mvn_options;
 
 /* Factor handle, filled by mvn_cholesky.  Plain data; copy freely.
  * opts->precision selects the trailing-update arithmetic and which operand
  * copy of L is kept for the sweep.  *info (device int) is 0 on success or
  * k > 0 if the leading minor of order k is not positive definite (LAPACK
- * dpotrf convention).
+ * dpotrf convention), or -1 if the site permutation of
+ * mvn_cholesky_permuted was not a permutation.
  *
  * Dense factor (flags == 0): L is row-major with leading dimension ld (>= n,
  * a multiple of 128); rows and columns n..ld-1 hold the identity so blocked
@@ -112,7 +133,10 @@ typedef struct mvn_factor {
   int* ranks;       /* device, TLR only                                        */
   double tlr_eps;   /* TLR accuracy the factor was built with                  */
   int max_rank;     /* TLR rank cap                                            */
-  int reserved1;
+  int chol_mode;    /* mvn_chol_mode the dense factor was built with           */
+  unsigned long long* update_counts;  /* device, 3 counters (dense factors):   */
+                    /* trailing tile updates run in FP64, FP32 and the reduced */
+                    /* type by the adaptive map (all zero in the other modes)  */
 } mvn_factor;
 
 /* Sizes.  All return 0 on success and write the byte count.
@@ -120,8 +144,8 @@ typedef struct mvn_factor {
  * that holds any factor built with those options (every tile at the rank
  * stride), usually far more than needed; mvn_prob_workspace_bytes_factor
  * returns the size for a given factor: for a TLR factor it reads the ranks
- * back, which synchronises `stream` (the stream the factor was built on);
- * for a dense factor it equals mvn_prob_workspace_bytes(f->n, ...) and does
+ * back, which synchronises `stream` (the stream the factor was built on;
+ * query once, outside any graph capture); for a dense factor it equals mvn_prob_workspace_bytes(f->n, ...) and does
  * not touch the device.  With a smaller TLR workspace mvn_prob runs as many
  * persistent sweep workgroups as fit (slower, same result). */
 int mvn_factor_bytes(int n, const mvn_options* opts, size_t* bytes);
@@ -166,12 +190,16 @@ int mvn_cholesky(int n, const double* d_sigma, int ld_sigma, const double* d_loc
  * (FP64 only) the update of tile-row i is sum_j U_ij (Vt_ij Y_j) plus the
  * dense diagonal tile: once the samples of tile j are known, Vt_ij Y_j is
  * formed for all i > j in one stacked product, and the update of tile-row i
- * is one product with the ranks packed along K.  The call reads the ranks
- * back and copies its index tables to the workspace, synchronising `stream`
- * twice (it cannot be captured in a graph); the workspace size comes from
- * mvn_prob_workspace_bytes_factor (or the TLR bound of
- * mvn_prob_workspace_bytes), and too small a workspace to hold one sweep
- * workgroup is an error.
+ * is one product with the ranks packed along K.  The index tables of those
+ * products and the layout of the rank-dependent part of the workspace are
+ * built on the device from the factor's ranks, so the call reads nothing
+ * back and can be captured in a graph.  Its workspace size comes from
+ * mvn_prob_workspace_bytes_factor (which reads the ranks back) or the TLR
+ * bound of mvn_prob_workspace_bytes; the sweep runs as many persistent
+ * workgroups as the workspace holds for the actual ranks.  A workspace below
+ * the size of the rank-independent part plus one workgroup at rank zero is
+ * rejected (-10); one that holds no workgroup for the actual ranks gives NaN
+ * outputs.
  * The QMC point of sample (s, j) in dimension i is
  *   w = ((j*A_i + D_{s,i} mod 2^64) >> 11 + 1/2) 2^-53 with
  *   A_i = floor(frac(sqrt(p_{i+1})) 2^64) (p_k the k-th prime) and
@@ -202,8 +230,8 @@ int mvn_prob_workspace_bytes_factor(const mvn_factor* f, int N, int S, const mvn
  * Dense factors (any precision the factor holds) and TLR factors (FP64), as
  * for mvn_prob.  The workspace holds n x ceil(N S / 64) x 4 + n S doubles,
  * then mvn_prob's; mvn_prob_prefix_workspace_bytes gives its size for the
- * factor (for a TLR factor it reads the ranks back, synchronising `stream`,
- * and mvn_prob_prefix synchronises as mvn_prob does). */
+ * factor (for a TLR factor it reads the ranks back, synchronising `stream`;
+ * mvn_prob_prefix itself does not). */
 int mvn_prob_prefix_workspace_bytes(const mvn_factor* f, int N, int S, const mvn_options* opts, size_t* bytes,
                                     hipStream_t stream);
 int mvn_prob_prefix(const mvn_factor* f, const double* d_a, const double* d_b, const double* d_mu,
@@ -212,21 +240,23 @@ int mvn_prob_prefix(const mvn_factor* f, const double* d_a, const double* d_b, c
 
 /* Factor P Sigma P^T: Sigma given by its lower triangle (device, row stride
  * ld_sigma; the upper triangle is not read), factored in the site order
- * h_perm (host, n entries, a permutation of 0..n-1, checked): row i of the
- * factor is site h_perm[i].  This is how a confidence region orders a given
- * Sigma (Algorithm 1: sites by decreasing marginal exceedance probability)
- * before the nested-set sweep.  Options, factor buffer and result as for
- * mvn_cholesky (dense in any precision, or TLR); the workspace is
- * mvn_cholesky_permuted_workspace_bytes (mvn_cholesky's plus n int64).
- * Copies h_perm to the device and synchronises `stream` first. */
+ * d_perm (device, n int64 entries): row i of the factor is site d_perm[i].
+ * This is how a confidence region orders a given Sigma (Algorithm 1: sites
+ * by decreasing marginal exceedance probability) before the nested-set
+ * sweep.  Options, factor buffer and result as for mvn_cholesky (dense in
+ * any precision, or TLR); the workspace is
+ * mvn_cholesky_permuted_workspace_bytes (mvn_cholesky's plus n ints and a
+ * flag).  d_perm is checked on the device: if it is not a permutation of
+ * 0..n-1, *info is -1 and every output computed from the factor is NaN.
+ * Asynchronous; nothing is read back. */
 int mvn_cholesky_permuted_workspace_bytes(int n, const mvn_options* opts, size_t* bytes);
-int mvn_cholesky_permuted(int n, const double* d_sigma, int ld_sigma, const int64_t* h_perm,
+int mvn_cholesky_permuted(int n, const double* d_sigma, int ld_sigma, const int64_t* d_perm,
                           const mvn_options* opts, void* factor_buf, size_t factor_bytes, void* ws,
                           size_t ws_bytes, mvn_factor* out, hipStream_t stream);
 
 /* Posterior of a Gaussian field x ~ N(mu, Sigma) at n sites, observed at m
  * of them with noise: y = A x + eps, eps ~ N(0, noise_var I), A the m x n
- * indicator matrix of the sites h_obs (Section V-B, the equations for
+ * indicator matrix of the sites d_obs (Section V-B, the equations for
  * Sigma_post and mu_post, which then replace Sigma and mu in Algorithm 1).
  * Sigma is the Matern covariance of d_locs (n x 2, device) with kern (the
  * nugget is part of Sigma).  Computed as the Woodbury form
@@ -236,22 +266,24 @@ int mvn_cholesky_permuted(int n, const double* d_sigma, int ld_sigma, const int6
  * [K C 0; C^T Sigma 0; (y - mu_o)^T 0 1] stopped after the observation
  * columns: its trailing block is Sigma_post and -(mu_post - mu).  FP64.
  *   d_mu         prior mean (n, device) or NULL for zero
- *   h_obs        host, m site indices in 0..n-1 (checked); a site may repeat
+ *   d_obs        device, m int64 site indices in 0..n-1; a site may repeat.
+ *                Checked on the device: an index out of range gives
+ *                *d_info = -1 and NaN outputs
  *   d_y          device, m observations
  *   noise_var    > 0
  *   opts         tile of the factorisation (precision must be FP64)
  *   d_mu_post    device, n (or NULL): posterior mean
  *   d_var_post   device, n (or NULL): posterior marginal variance
  *   d_info       device int: 0, or k > 0 if the k-th leading minor of K is
- *                not positive (then the outputs are NaN)
+ *                not positive, or -1 for a bad index (then the outputs are
+ *                NaN)
  *   sigma_post   receives a pointer to Sigma_post inside the workspace:
  *                lower triangle, row stride *ld_sigma_post, valid until the
  *                workspace is reused; pass it to mvn_cholesky_permuted
  * Workspace: mvn_posterior_workspace_bytes ((m' + n + 1)^2 doubles, m' = m
- * rounded up to the tile).  Copies h_obs to the device and synchronises
- * `stream` first. */
+ * rounded up to the tile).  Asynchronous; nothing is read back. */
 int mvn_posterior_workspace_bytes(int n, int m, const mvn_options* opts, size_t* bytes);
-int mvn_posterior(int n, const double* d_locs, const double* d_mu, int m, const int64_t* h_obs,
+int mvn_posterior(int n, const double* d_locs, const double* d_mu, int m, const int64_t* d_obs,
                   const double* d_y, const mvn_matern* kern, double noise_var, const mvn_options* opts,
                   void* ws, size_t ws_bytes, double* d_mu_post, double* d_var_post, int* d_info,
                   double** sigma_post, int* ld_sigma_post, hipStream_t stream);

@@ -13,8 +13,8 @@ import math
 from dataclasses import dataclass
 
 from . import _lib
-from ._lib import (MVN_BF16, MVN_BF16X3, MVN_FACTOR_TLR, MVN_FP32, MVN_FP64, MvnError,  # noqa: F401
-                   MvnFactor, MvnMatern, MvnOptions, options)
+from ._lib import (MVN_BF16, MVN_BF16X3, MVN_CHOL_ADAPTIVE, MVN_CHOL_FP64, MVN_CHOL_UNIFORM,  # noqa: F401
+                   MVN_FACTOR_TLR, MVN_FP32, MVN_FP64, MvnError, MvnFactor, MvnMatern, MvnOptions, options)
 
 __all__ = ["mvn_factor_bytes", "mvn_cholesky_workspace_bytes", "mvn_prob_workspace_bytes",
            "mvn_prob_workspace_bytes_factor", "mvn_cholesky", "mvn_prob", "Factor",
@@ -23,7 +23,8 @@ __all__ = ["mvn_factor_bytes", "mvn_cholesky_workspace_bytes", "mvn_prob_workspa
            "posterior_confidence_region",
            "mvn_prob_grad_workspace_bytes", "mvn_prob_grad", "MVNLogProb", "BatchPlan",
            "mvn_batch_plan", "mvn_prob_batch",
-           "options", "MvnError", "MVN_FP64", "MVN_FP32", "MVN_BF16", "MVN_BF16X3", "library_path"]
+           "options", "MvnError", "MVN_FP64", "MVN_FP32", "MVN_BF16", "MVN_BF16X3", "MVN_CHOL_ADAPTIVE",
+           "MVN_CHOL_UNIFORM", "MVN_CHOL_FP64", "library_path"]
 
 
 def library_path() -> str:
@@ -115,6 +116,15 @@ class Factor:
         torch = _torch()
         return int(self._view(self.handle.info, 1, torch.int32).item())
 
+    def update_counts(self) -> dict:
+        """Trailing tile updates by arithmetic (dense factors; the adaptive
+        precision map's choices, all zero in the other modes)."""
+        torch = _torch()
+        if self.is_tlr or not self.handle.update_counts:
+            return {"fp64": 0, "fp32": 0, "reduced": 0}
+        c = self._view(self.handle.update_counts, 3, torch.int64).cpu().tolist()
+        return {"fp64": c[0], "fp32": c[1], "reduced": c[2]}
+
     # ---- tile low-rank buffers (raw device views, layouts as in mvn.h)
     @property
     def nt(self) -> int:
@@ -182,8 +192,8 @@ def mvn_cholesky_permuted(sigma, perm, opts: MvnOptions | None = None) -> Factor
     if sigma.dtype != torch.float64 or sigma.stride(1) != 1 or sigma.shape[1] != n:
         raise MvnError(-2, "sigma must be a float64 n x n tensor with unit column stride")
     dev = sigma.device
-    hp = np.ascontiguousarray(np.asarray(perm, dtype=np.int64))
-    if hp.shape != (n,):
+    dp = torch.as_tensor(np.asarray(perm.cpu() if hasattr(perm, "cpu") else perm, dtype=np.int64)).to(dev)
+    if dp.shape != (n,):
         raise MvnError(-4, "perm must have n entries")
     fb = mvn_factor_bytes(n, opts)
     wb = ctypes.c_size_t(0)
@@ -191,12 +201,12 @@ def mvn_cholesky_permuted(sigma, perm, opts: MvnOptions | None = None) -> Factor
     buf = torch.empty(fb, dtype=torch.uint8, device=dev)
     ws = torch.empty(wb.value, dtype=torch.uint8, device=dev)
     h = MvnFactor()
-    code = _lib.lib().mvn_cholesky_permuted(n, _ptr(sigma), sigma.stride(0), hp.ctypes.data_as(ctypes.c_void_p),
+    code = _lib.lib().mvn_cholesky_permuted(n, _ptr(sigma), sigma.stride(0), _ptr(dp),
                                             ctypes.byref(opts), _ptr(buf), fb, _ptr(ws), wb.value, ctypes.byref(h),
                                             _stream(dev))
     _lib.check(code)
     f = Factor(h, buf, dev)
-    f._keep = (sigma, ws)
+    f._keep = (sigma, ws, dp)
     return f
 
 
@@ -211,8 +221,8 @@ def mvn_posterior(locs, kern: tuple, obs, y, noise_var: float, mu=None, opts: Mv
     opts = opts or options()
     lc = _dev_f64(locs, device)
     n = lc.shape[0]
-    ho = np.ascontiguousarray(np.asarray(obs, dtype=np.int64))
-    m = ho.size
+    do = torch.as_tensor(np.ascontiguousarray(np.asarray(obs, dtype=np.int64))).to(device)
+    m = do.numel()
     ty = _dev_f64(y, device)
     tm = _dev_f64(mu, device) if mu is not None else None
     wb = ctypes.c_size_t(0)
@@ -223,7 +233,7 @@ def mvn_posterior(locs, kern: tuple, obs, y, noise_var: float, mu=None, opts: Mv
     info = torch.empty(1, dtype=torch.int32, device=device)
     sp_ptr, ld = ctypes.c_void_p(0), ctypes.c_int(0)
     km = MvnMatern(*kern)
-    code = _lib.lib().mvn_posterior(n, _ptr(lc), _ptr(tm), m, ho.ctypes.data_as(ctypes.c_void_p), _ptr(ty),
+    code = _lib.lib().mvn_posterior(n, _ptr(lc), _ptr(tm), m, _ptr(do), _ptr(ty),
                                     ctypes.byref(km), float(noise_var), ctypes.byref(opts), _ptr(ws), wb.value,
                                     _ptr(mu_post), _ptr(var_post), _ptr(info), ctypes.byref(sp_ptr),
                                     ctypes.byref(ld), _stream(device))
@@ -233,21 +243,27 @@ def mvn_posterior(locs, kern: tuple, obs, y, noise_var: float, mu=None, opts: Mv
     flat = ws.view(torch.float64)
     sigma_post = flat[off // 8: off // 8 + (n - 1) * ld.value + n].as_strided((n, n), (ld.value, 1))
     return {"mu_post": mu_post, "var_post": var_post, "sigma_post": sigma_post,
-            "info": int(info.item()), "_keep": (lc, ty, tm, ws)}
+            "info": int(info.item()), "_keep": (lc, ty, tm, ws, do)}
 
 
 def mvn_prob(f: Factor, a, b, mu=None, N: int = 1000, S: int = 10, seed: int = 1,
              opts: MvnOptions | None = None, return_ell: bool = False, workspace=None):
     """SOV estimate of P(a <= X <= b).  Returns a dict of device tensors:
-    logP, P, stderr, rel_stderr, logP_s[S] (and ell[N*S] if asked)."""
+    logP, P, stderr, rel_stderr, logP_s[S] (and ell[N*S] if asked).
+    For a TLR factor a given workspace is used as it is (sizing one reads the
+    ranks back; the call itself does not, so it can be graph-captured)."""
     torch = _torch()
     opts = opts or options()
     dev = f.device
     ta, tb = _dev_f64(a, dev), _dev_f64(b, dev)
     tm = _dev_f64(mu, dev) if mu is not None else None
-    wsb = mvn_prob_workspace_bytes_factor(f, N, S, opts) if f.is_tlr else mvn_prob_workspace_bytes(f.n, N, S, opts)
-    if workspace is None or workspace.numel() < wsb:
-        workspace = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    if f.is_tlr and workspace is not None:
+        wsb = workspace.numel()
+    else:
+        wsb = (mvn_prob_workspace_bytes_factor(f, N, S, opts) if f.is_tlr
+               else mvn_prob_workspace_bytes(f.n, N, S, opts))
+        if workspace is None or workspace.numel() < wsb:
+            workspace = torch.empty(wsb, dtype=torch.uint8, device=dev)
     out = torch.empty(4 + S, dtype=torch.float64, device=dev)
     ell = torch.empty(N * S, dtype=torch.float64, device=dev) if return_ell else None
     code = _lib.lib().mvn_prob(ctypes.byref(f.handle), _ptr(ta), _ptr(tb), _ptr(tm), N, S,
@@ -445,20 +461,26 @@ def _make_autograd():
 
     class MVNLogProb(torch.autograd.Function):
         """log P(a <= X <= b), X ~ N(mu, L L^T), as a differentiable function
-        of (a, b, mu) at fixed QMC points.  forward calls mvn_prob_grad (the
-        adjoint sweep runs with the forward sweep, on the same points) and
-        saves the gradients; backward scales them by the incoming gradient."""
+        of (a, b, mu) at fixed QMC points.  When a gradient is needed, forward
+        calls mvn_prob_grad (the adjoint sweep runs with the forward sweep, on
+        the same points) and saves the gradients, which backward scales by
+        the incoming gradient; otherwise it runs only the forward sweep
+        (mvn_prob).  `opts` selects the arithmetic of the sweep's GEMMs (the
+        factor's precision or FP64)."""
 
         @staticmethod
-        def forward(ctx, a, b, mu, factor, N, S, seed):
-            r = mvn_prob_grad(factor, a.detach(), b.detach(), mu.detach(), N=N, S=S, seed=seed)
+        def forward(ctx, a, b, mu, factor, N, S, seed, opts=None):
+            if not any(ctx.needs_input_grad[:3]):
+                r = mvn_prob(factor, a.detach(), b.detach(), mu.detach(), N=N, S=S, seed=seed, opts=opts)
+                return r["logP"].clone().to(a.dtype)
+            r = mvn_prob_grad(factor, a.detach(), b.detach(), mu.detach(), N=N, S=S, seed=seed, opts=opts)
             ctx.save_for_backward(r["da"], r["db"], r["dmu"])
             return r["logP"].clone().to(a.dtype)
 
         @staticmethod
         def backward(ctx, g):
             da, db, dmu = ctx.saved_tensors
-            return g * da, g * db, g * dmu, None, None, None, None
+            return g * da, g * db, g * dmu, None, None, None, None, None
 
     return MVNLogProb
 

@@ -15,6 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmvn.so")
 
 MVN_FP64, MVN_FP32, MVN_BF16, MVN_BF16X3 = 0, 1, 2, 3
+MVN_CHOL_ADAPTIVE, MVN_CHOL_UNIFORM, MVN_CHOL_FP64 = 0, 1, 2
 
 
 class MvnMatern(ctypes.Structure):
@@ -23,7 +24,7 @@ class MvnMatern(ctypes.Structure):
 
 class MvnOptions(ctypes.Structure):
     _fields_ = [("tile", c_int), ("precision", c_int), ("periodize", c_int), ("sweep_rows", c_int),
-                ("tlr_eps", c_double), ("max_rank", c_int), ("reserved1", c_int)]
+                ("tlr_eps", c_double), ("max_rank", c_int), ("chol_mode", c_int), ("chol_tol", c_double)]
 
 
 MVN_FACTOR_TLR = 1
@@ -33,7 +34,8 @@ class MvnFactor(ctypes.Structure):
     _fields_ = [("n", c_int), ("ld", c_int), ("precision", c_int), ("flags", c_int),
                 ("L", c_void_p), ("info", c_void_p), ("L_low", c_void_p),
                 ("tile", c_int), ("rank_stride", c_int), ("U", c_void_p), ("Vt", c_void_p),
-                ("ranks", c_void_p), ("tlr_eps", c_double), ("max_rank", c_int), ("reserved1", c_int)]
+                ("ranks", c_void_p), ("tlr_eps", c_double), ("max_rank", c_int), ("chol_mode", c_int),
+                ("update_counts", c_void_p)]
 
 
 class MvnError(RuntimeError):
@@ -105,5 +107,6 @@ def check(code: int) -> None:
 
 
 def options(tile: int = 256, precision: int = MVN_FP64, periodize: bool = False,
-            tlr_eps: float = 0.0, max_rank: int = 0, sweep_rows: int = 0) -> MvnOptions:
-    return MvnOptions(tile, precision, 1 if periodize else 0, sweep_rows, tlr_eps, max_rank, 0)
+            tlr_eps: float = 0.0, max_rank: int = 0, sweep_rows: int = 0, chol_mode: int = MVN_CHOL_ADAPTIVE,
+            chol_tol: float = 0.0) -> MvnOptions:
+    return MvnOptions(tile, precision, 1 if periodize else 0, sweep_rows, tlr_eps, max_rank, chol_mode, chol_tol)

@@ -53,6 +53,11 @@ mvn::Matern matern_of(const mvn_matern* k) {
   return k ? mvn::make_matern(k->sigma2, k->beta, k->nu, k->nugget) : mvn::make_matern(1.0, 1.0, 0.5, 0.0);
 }
 
+// Header of a dense factor buffer, after L: info (int), max diag(Sigma) at
+// +8, the adaptive map's three update counters at +16, and two slots of
+// ld/128 + 1 panel block norms at +64.
+size_t dense_header_bytes(int ld) { return align_up(64 + sizeof(double) * 2 * ((size_t)ld / 128 + 1)); }
+
 int elem_bytes_low(int prec) { return prec == MVN_FP32 ? 4 : prec == MVN_BF16 ? 2 : prec == MVN_BF16X3 ? 4 : 0; }
 bool prec_ok(int prec) { return prec >= MVN_FP64 && prec <= MVN_BF16X3; }
 
@@ -95,7 +100,9 @@ int g_lat_n = 0;
 const uint64_t* lattice_table(int n) {
   std::lock_guard<std::mutex> lk(g_lat_mu);
   if (n <= g_lat_n) return g_lat_host;
-  int want = n < 4096 ? 4096 : n;
+  // the first table already covers 131072 dimensions, so that later calls
+  // (possibly under graph capture) up to that size allocate nothing
+  int want = n < (1 << 17) ? (1 << 17) : n;
   // sieve enough primes: p_k < k (ln k + ln ln k) for k >= 6
   const double lw = log((double)want + 16);
   size_t limit = (size_t)(want * (lw + log(lw) + 3)) + 64;
@@ -125,14 +132,25 @@ struct ProbLayout {
 
 // Workspace of one probability call.  ld is the factor's leading dimension
 // (rows of the Y scratch); zslice > 0 adds the TLR Z scratch (FP64).
-ProbLayout prob_layout_ld(int ld, int N, int S, int prec, long zslice, int rows) {
+// wide: the 128-column FP64 sweep (persistent workgroups, each owning whole
+// 32-column slices; Y slice ld x 128).
+ProbLayout prob_layout_ld(int ld, int N, int S, int prec, long zslice, int rows, bool wide = false,
+                          int gcap = 0) {
   ProbLayout L{};
   L.ld = ld;
   const long NS = (long)N * S;
-  const long chunks = (NS + mvn::sweep_tile_cols() - 1) / mvn::sweep_tile_cols();
-  const int gmax = max_grid(rows, prec);
-  L.grid = (int)(chunks < gmax ? chunks : gmax);
-  L.yslice = mvn::sweep_yslice(prec, L.ld);
+  if (wide) {  // two workgroups per CU
+    const long slices = (NS + 31) / 32;
+    const int gmax = 2 * kCUs;
+    L.grid = (int)(slices < gmax ? slices : gmax);
+    L.yslice = (long)L.ld * mvn::wide_sweep_cols();
+  } else {
+    const long chunks = (NS + mvn::sweep_tile_cols() - 1) / mvn::sweep_tile_cols();
+    const int gmax = max_grid(rows, prec);
+    L.grid = (int)(chunks < gmax ? chunks : gmax);
+    L.yslice = mvn::sweep_yslice(prec, L.ld);
+  }
+  if (gcap > 0 && L.grid > gcap) L.grid = gcap;
   L.zslice = zslice;
   size_t off = 0;
   L.at = off; off = align_up(off + sizeof(double) * L.ld);
@@ -149,8 +167,17 @@ ProbLayout prob_layout_ld(int ld, int N, int S, int prec, long zslice, int rows)
   return L;
 }
 
-ProbLayout prob_layout(int n, int N, int S, int prec, int rows) {
-  return prob_layout_ld(padded(n), N, S, prec, 0, rows);
+// The dense sweep's workspace; `prefix`: for a nested-set sweep (which keeps
+// the 64-column kernel).
+// The 128-column sweep needs enough samples for full passes (a workgroup
+// per 128 columns on every CU slot); with fewer, the 64-column sweep reads
+// the factor no more often and runs more workgroups.
+bool use_wide(int prec, int rows, bool prefix, long NS) {
+  return prec == MVN_FP64 && rows == 128 && !prefix && NS >= 2L * kCUs * mvn::wide_sweep_cols();
+}
+
+ProbLayout prob_layout(int n, int N, int S, int prec, int rows, bool prefix = false) {
+  return prob_layout_ld(padded(n), N, S, prec, 0, rows, use_wide(prec, rows, prefix, (long)N * S));
 }
 
 // Front of the workspace of a nested-set call: the running-product partials
@@ -242,43 +269,43 @@ int tlr_opts_check(const mvn_options* o) {
 bool is_tlr(const mvn_options* o) { return o && o->tlr_eps > 0; }
 
 // Workspace of a TLR probability call: the common part of prob_layout_ld (up
-// to the invalid-limit flag), the sweep's index tables (tlr_tables.h) and
-// packed operands, then per persistent workgroup its Y slice (ld x 64) and Z
-// slice (kpad x 64).  ksum = sum of the ranks, kpad = packed K of all
-// tile-rows, rows = sweep block rows (the grid's workgroups per CU).
-// avail > 0: as many workgroups as fit in avail bytes (grid 0 when not even
-// one does); avail == 0: the full grid.
+// to the invalid-limit flag), the sweep's index tables (tlr_tables.h, built
+// on the device from the ranks) and the device header of the rank-dependent
+// region, then that region: the packed operands, and per persistent
+// workgroup its Y slice (ld x 64) and Z slice (kpad x 64).  The fixed part
+// depends only on the factor's geometry (zdst is sized for every tile at
+// the rank stride); the region's layout is computed on the device
+// (TlrSweepHdr), and `dyn_bytes(ksum, kpad, grid)` gives the size it needs
+// for given ranks and workgroups, the same arithmetic as the device's.
 struct TlrProbLayout {
   ProbLayout base;
-  size_t zcol, kpad0, kval, vrow0, ucol0, kk, zdst, vpack, upack, fixed, yscr, zscr, total;
-  long yslice, zslice;
-  int grid;
+  size_t kk, zcol, kpad0, kval, vrow0, ucol0, zdst, hdr, fixed;
+  long yslice;
+  int grid;  // launch grid (the device runs as many as the region holds)
+  size_t dyn_bytes(long ksum, long kpad, long g, int m) const {
+    const size_t kp = kpad > 0 ? (size_t)kpad : 1;
+    const size_t ysc = align_up(8 * (size_t)(ksum + 128) * m) + align_up(8 * (size_t)m * kp);
+    return ysc + (size_t)g * (align_up(8 * (size_t)yslice) + align_up(8 * kp * mvn::sweep_tile_cols()));
+  }
 };
 
-TlrProbLayout tlr_prob_layout(int ld, int m, int nt, int N, int S, long ksum, long kpad, int rows, size_t avail) {
+TlrProbLayout tlr_prob_layout(int ld, int nt, int rs, int N, int S, int rows) {
   TlrProbLayout L{};
   L.base = prob_layout_ld(ld, N, S, MVN_FP64, 0, rows);
   const size_t np = (size_t)nt * (nt - 1) / 2;
+  const size_t np1 = np > 0 ? np : 1;
   size_t off = L.base.yscr;
+  L.kk = off; off = align_up(off + sizeof(int) * np1);
   L.zcol = off; off = align_up(off + sizeof(long) * (nt + 1));
   L.kpad0 = off; off = align_up(off + sizeof(long) * (nt + 1));
   L.kval = off; off = align_up(off + sizeof(int) * nt);
-  L.vrow0 = off; off = align_up(off + sizeof(long) * (np > 0 ? np : 1));
-  L.ucol0 = off; off = align_up(off + sizeof(long) * (np > 0 ? np : 1));
-  L.kk = off; off = align_up(off + sizeof(int) * (np > 0 ? np : 1));
-  L.zdst = off; off = align_up(off + sizeof(long) * (size_t)(ksum > 0 ? ksum : 1));
-  L.vpack = off; off = align_up(off + sizeof(double) * (size_t)(ksum + 128) * m);
-  L.upack = off; off = align_up(off + sizeof(double) * (size_t)m * (size_t)(kpad > 0 ? kpad : 1));
+  L.vrow0 = off; off = align_up(off + sizeof(long) * np1);
+  L.ucol0 = off; off = align_up(off + sizeof(long) * np1);
+  L.zdst = off; off = align_up(off + sizeof(long) * np1 * rs);
+  L.hdr = off; off = align_up(off + sizeof(mvn::TlrSweepHdr));
   L.fixed = off;
   L.yslice = (long)ld * mvn::sweep_tile_cols();
-  L.zslice = (kpad > 0 ? kpad : 1) * (long)mvn::sweep_tile_cols();
-  const size_t per = align_up(sizeof(double) * (size_t)L.yslice) + align_up(sizeof(double) * (size_t)L.zslice);
-  long g = L.base.grid;
-  if (avail > 0) g = avail < L.fixed ? 0 : std::min<long>(g, (long)((avail - L.fixed) / per));
-  L.grid = (int)g;
-  L.yscr = L.fixed;
-  L.zscr = align_up(L.yscr + sizeof(double) * (size_t)L.grid * (size_t)L.yslice);
-  L.total = align_up(L.zscr + sizeof(double) * (size_t)L.grid * (size_t)L.zslice);
+  L.grid = L.base.grid;
   return L;
 }
 
@@ -399,31 +426,38 @@ BatchWs batch_ws(const BatchPlan& P, int count, int N, int S, int prec, int rows
 // The dense sweep and reduction of mvn_prob into a validated workspace; with
 // prefix (the partials of a nested-set call) the sweep also records the
 // running products of every row and no full reduction is launched.
+// dlat_dev: a lattice table already on the device (at least n entries), or
+// nullptr to copy the host table into the workspace.
 int dense_sweep(const mvn_factor* f, const double* d_a, const double* d_b, const double* d_mu, int N, int S,
                 uint64_t seed, const mvn_options* opts, void* ws, const ProbLayout& Lay, double* d_ell,
-                double* prefix, double* d_out, hipStream_t stream) {
+                double* prefix, double* d_out, hipStream_t stream, const uint64_t* dlat_dev = nullptr) {
   const int n = f->n;
   const int prec = opts->precision;
   const int rows = sweep_rows(opts);
-  const uint64_t* lat = lattice_table(n);
-  if (!lat) return fail(-1, "could not build the lattice table for n = %d", n);
   char* w = (char*)ws;
   double* at = (double*)(w + Lay.at);
   double* bt = (double*)(w + Lay.bt);
-  uint64_t* dlat = (uint64_t*)(w + Lay.lat);
+  const uint64_t* dlat = dlat_dev;
   double* ell = d_ell ? d_ell : (double*)(w + Lay.ell);
   double* part = (double*)(w + Lay.part);
   int* bad = (int*)(w + Lay.bad);
   void* yscr = (void*)(w + Lay.yscr);
-  hipError_t e = hipMemcpyAsync(dlat, lat, sizeof(uint64_t) * n, hipMemcpyHostToDevice, stream);
-  if (e != hipSuccess) return hip_fail(e, "lattice copy");
+  hipError_t e;
+  if (!dlat) {
+    const uint64_t* lat = lattice_table(n);
+    if (!lat) return fail(-1, "could not build the lattice table for n = %d", n);
+    uint64_t* dl = (uint64_t*)(w + Lay.lat);
+    e = hipMemcpyAsync(dl, lat, sizeof(uint64_t) * n, hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) return hip_fail(e, "lattice copy");
+    dlat = dl;
+  }
   e = mvn::launch_prob_setup(n, f->ld, d_a, d_b, d_mu, at, bt, bad, stream);
   if (e != hipSuccess) return hip_fail(e, "setup");
   mvn::SweepArgs sa{};
   sa.L = f->L;
   sa.Llow = prec == MVN_FP64 ? (const void*)f->L : f->L_low;
   sa.prec = prec;
-  sa.yslice = mvn::sweep_yslice(prec, f->ld);
+  sa.yslice = Lay.yslice;
   sa.ld = f->ld;
   sa.n = n;
   sa.at = at;
@@ -438,6 +472,7 @@ int dense_sweep(const mvn_factor* f, const double* d_a, const double* d_b, const
   sa.grid = Lay.grid;
   sa.rows = rows;
   sa.prefix = prefix;
+  sa.wide = use_wide(prec, rows, prefix != nullptr, (long)N * S) ? 1 : 0;
   e = mvn::launch_sweep(sa, stream);
   if (e != hipSuccess) return hip_fail(e, "sweep");
   if (prefix) return 0;
@@ -447,79 +482,80 @@ int dense_sweep(const mvn_factor* f, const double* d_a, const double* d_b, const
 }
 
 // The TLR sweep and reduction of mvn_prob (options validated by the
-// caller): reads the ranks back, lays out and fills the index tables and
-// packed operands in ws, sweeps and reduces.  With prefix (the partials of a
-// nested-set call) the sweep also records the running products of every row,
-// no full reduction is launched, and *bad_out gets the invalid-limit flag.
+// caller): the index tables and the layout of the rank-dependent region are
+// built on the device from the factor's ranks (nothing is read back and the
+// stream is not synchronised), the low-rank factors are packed, the sweep
+// runs as many persistent workgroups as the workspace holds, and the
+// reduction follows.  With prefix (the partials of a nested-set call) the
+// sweep also records the running products of every row, no full reduction
+// is launched, and *bad_out gets the invalid-limit flag.
 int tlr_sweep_call(const mvn_factor* f, const double* d_a, const double* d_b, const double* d_mu, int N, int S,
                    uint64_t seed, const mvn_options* opts, void* ws, size_t ws_bytes, double* d_ell,
                    double* prefix, double* d_out, hipStream_t stream, const int** bad_out) {
   const int rows = tlr_sweep_rows(opts);
   const int n = f->n, m = f->tile, nt = f->ld / f->tile, rs = f->rank_stride;
   const int np = nt * (nt - 1) / 2;
-  std::vector<int> ranks;
-  hipError_t e = tlr_read_ranks(f, ranks, stream);
-  if (e != hipSuccess) return hip_fail(e, "rank read-back");
-  const mvn::TlrTables T = mvn::build_tlr_tables(nt, rs, ranks.data());
-  const TlrProbLayout Lay = tlr_prob_layout(f->ld, m, nt, N, S, T.ksum, T.kpad0[nt], rows, ws_bytes);
-  if (Lay.grid < 1) {
-    const size_t full = tlr_prob_layout(f->ld, m, nt, N, S, T.ksum, T.kpad0[nt], rows, 0).total;
-    return fail(-10, "workspace too small: %zu bytes hold no sweep workgroup (%zu for the full grid)", ws_bytes,
-                full);
-  }
+  const TlrProbLayout Lay = tlr_prob_layout(f->ld, nt, rs, N, S, rows);
+  const size_t least = Lay.fixed + Lay.dyn_bytes(0, 0, 1, m);
+  if (ws_bytes < least)
+    return fail(-10, "workspace too small: %zu bytes hold no sweep workgroup (at least %zu)", ws_bytes, least);
   const uint64_t* lat = lattice_table(n);
   if (!lat) return fail(-1, "could not build the lattice table for n = %d", n);
   char* w = (char*)ws;
-  // index tables: one host image of the workspace range [zcol, vpack)
-  std::vector<char> img(Lay.vpack - Lay.zcol, 0);
-  auto put = [&](size_t off, const void* src, size_t bytes) {
-    if (bytes) memcpy(img.data() + (off - Lay.zcol), src, bytes);
-  };
-  put(Lay.zcol, T.zcol.data(), sizeof(long) * (nt + 1));
-  put(Lay.kpad0, T.kpad0.data(), sizeof(long) * (nt + 1));
-  put(Lay.kval, T.kval.data(), sizeof(int) * nt);
-  put(Lay.vrow0, T.vrow0.data(), sizeof(long) * np);
-  put(Lay.ucol0, T.ucol0.data(), sizeof(long) * np);
-  put(Lay.kk, T.k.data(), sizeof(int) * np);
-  put(Lay.zdst, T.zdst.data(), sizeof(long) * (size_t)T.ksum);
-  e = hipMemcpyAsync(w + Lay.zcol, img.data(), img.size(), hipMemcpyHostToDevice, stream);
-  if (e != hipSuccess) return hip_fail(e, "table copy");
-  e = hipStreamSynchronize(stream);  // img is freed on return
-  if (e != hipSuccess) return hip_fail(e, "table copy");
   double* at = (double*)(w + Lay.base.at);
   double* bt = (double*)(w + Lay.base.bt);
   uint64_t* dlat = (uint64_t*)(w + Lay.base.lat);
   double* ell = d_ell ? d_ell : (double*)(w + Lay.base.ell);
   double* part = (double*)(w + Lay.base.part);
   int* bad = (int*)(w + Lay.base.bad);
-  e = hipMemcpyAsync(dlat, lat, sizeof(uint64_t) * n, hipMemcpyHostToDevice, stream);
+  mvn::TlrSweepHdr* hdr = (mvn::TlrSweepHdr*)(w + Lay.hdr);
+  char* dyn = w + Lay.fixed;
+  hipError_t e = hipMemcpyAsync(dlat, lat, sizeof(uint64_t) * n, hipMemcpyHostToDevice, stream);
   if (e != hipSuccess) return hip_fail(e, "lattice copy");
   e = mvn::launch_prob_setup(n, f->ld, d_a, d_b, d_mu, at, bt, bad, stream);
   if (e != hipSuccess) return hip_fail(e, "setup");
+  mvn::TlrTableArgs tb{};
+  tb.ranks = f->ranks;
+  tb.nt = nt;
+  tb.rs = rs;
+  tb.m = m;
+  tb.yslice = Lay.yslice;
+  tb.grid_max = Lay.grid;
+  tb.dyn_bytes = ws_bytes - Lay.fixed;
+  tb.kk = (int*)(w + Lay.kk);
+  tb.zcol = (long*)(w + Lay.zcol);
+  tb.kpad0 = (long*)(w + Lay.kpad0);
+  tb.kval = (int*)(w + Lay.kval);
+  tb.vrow0 = (long*)(w + Lay.vrow0);
+  tb.ucol0 = (long*)(w + Lay.ucol0);
+  tb.zdst = (long*)(w + Lay.zdst);
+  tb.hdr = hdr;
+  tb.bad = bad;
+  e = mvn::launch_tlr_tables(tb, stream);
+  if (e != hipSuccess) return hip_fail(e, "tlr tables");
   mvn::TlrPackArgs pa{};
   pa.U = f->U;
   pa.Vt = f->Vt;
   pa.m = m;
   pa.rs = rs;
   pa.np = np;
-  pa.kk = (const int*)(w + Lay.kk);
-  pa.vrow0 = (const long*)(w + Lay.vrow0);
-  pa.ucol0 = (const long*)(w + Lay.ucol0);
-  pa.kpad0 = (const long*)(w + Lay.kpad0);
-  pa.kval = (const int*)(w + Lay.kval);
-  pa.ksum = T.ksum;
-  pa.Vpack = (double*)(w + Lay.vpack);
-  pa.Upack = (double*)(w + Lay.upack);
+  pa.kk = tb.kk;
+  pa.vrow0 = tb.vrow0;
+  pa.ucol0 = tb.ucol0;
+  pa.kpad0 = tb.kpad0;
+  pa.kval = tb.kval;
+  pa.hdr = hdr;
+  pa.dyn = dyn;
   e = mvn::launch_tlr_pack(pa, stream);
   if (e != hipSuccess) return hip_fail(e, "tlr pack");
   mvn::TlrSweepArgs ta{};
   ta.tiles = f->L;
-  ta.Vpack = pa.Vpack;
-  ta.Upack = pa.Upack;
-  ta.zcol = (const long*)(w + Lay.zcol);
-  ta.kpad0 = pa.kpad0;
-  ta.kval = pa.kval;
-  ta.zdst = (const long*)(w + Lay.zdst);
+  ta.hdr = hdr;
+  ta.dyn = dyn;
+  ta.zcol = tb.zcol;
+  ta.kpad0 = tb.kpad0;
+  ta.kval = tb.kval;
+  ta.zdst = tb.zdst;
   ta.m = m;
   ta.nt = nt;
   ta.n = n;
@@ -530,10 +566,7 @@ int tlr_sweep_call(const mvn_factor* f, const double* d_a, const double* d_b, co
   ta.N = N;
   ta.S = S;
   ta.periodize = opts->periodize ? 1 : 0;
-  ta.yscr = (double*)(w + Lay.yscr);
   ta.yslice = Lay.yslice;
-  ta.zscr = (double*)(w + Lay.zscr);
-  ta.zslice = Lay.zslice;
   ta.ell = ell;
   ta.grid = Lay.grid;
   ta.rows = rows;
@@ -567,8 +600,11 @@ int mvn_factor_bytes(int n, const mvn_options* opts, size_t* bytes) {
     *bytes = tlr_geom(n, opts->tile, opts->max_rank).total;
     return 0;
   }
+  if (opts && (opts->chol_mode < MVN_CHOL_ADAPTIVE || opts->chol_mode > MVN_CHOL_FP64))
+    return fail(-2, "unknown chol_mode %d", opts->chol_mode);
   const size_t ld = padded(n);
-  *bytes = align_up(sizeof(double) * ld * ld) + kAlign + align_up((size_t)elem_bytes_low(prec) * ld * ld);
+  *bytes = align_up(sizeof(double) * ld * ld) + dense_header_bytes((int)ld) +
+           align_up((size_t)elem_bytes_low(prec) * ld * ld);
   return 0;
 }
 
@@ -596,7 +632,8 @@ int mvn_prob_workspace_bytes(int n, int N, int S, const mvn_options* opts, size_
     if (!sweep_rows_ok(opts)) return fail(-4, "sweep_rows must be 0, 64 or 128 (got %d)", opts->sweep_rows);
     const TlrGeom G = tlr_geom(n, opts->tile, opts->max_rank);
     const long kmax = G.npanels * G.rs;
-    *bytes = tlr_prob_layout(G.ld, G.m, G.nt, N, S, kmax, kmax, tlr_sweep_rows(opts), 0).total;
+    const TlrProbLayout L = tlr_prob_layout(G.ld, G.nt, G.rs, N, S, tlr_sweep_rows(opts));
+    *bytes = L.fixed + L.dyn_bytes(kmax, kmax, L.grid, G.m);
     return 0;
   }
   if (!sweep_rows_ok(opts)) return fail(-4, "sweep_rows must be 0, 64 or 128 (got %d)", opts->sweep_rows);
@@ -618,7 +655,8 @@ int mvn_prob_workspace_bytes_factor(const mvn_factor* f, int N, int S, const mvn
   if (e != hipSuccess) return hip_fail(e, "rank read-back");
   const int nt = f->ld / f->tile;
   const mvn::TlrTables T = mvn::build_tlr_tables(nt, f->rank_stride, ranks.data());
-  *bytes = tlr_prob_layout(f->ld, f->tile, nt, N, S, T.ksum, T.kpad0[nt], tlr_sweep_rows(opts), 0).total;
+  const TlrProbLayout L = tlr_prob_layout(f->ld, nt, f->rank_stride, N, S, tlr_sweep_rows(opts));
+  *bytes = L.fixed + L.dyn_bytes(T.ksum, T.kpad0[nt], L.grid, f->tile);
   return 0;
 }
 
@@ -669,7 +707,7 @@ int mvn_prob_prefix(const mvn_factor* f, const double* d_a, const double* d_b, c
   if (tlr) {
     rc = tlr_sweep_call(f, d_a, d_b, d_mu, N, S, seed, opts, rest, rest_bytes, nullptr, part, nullptr, stream, &bad);
   } else {
-    const ProbLayout Lay = prob_layout(f->n, N, S, prec, sweep_rows(opts));
+    const ProbLayout Lay = prob_layout(f->n, N, S, prec, sweep_rows(opts), true);
     if (rest_bytes < Lay.total) return fail(-10, "workspace too small: %zu < %zu", ws_bytes, R.total + Lay.total);
     bad = (const int*)((char*)rest + Lay.bad);
     rc = dense_sweep(f, d_a, d_b, d_mu, N, S, seed, opts, rest, Lay, nullptr, part, nullptr, stream);
@@ -741,10 +779,11 @@ int mvn_prob_grad_workspace_bytes(int n, int N, int S, const mvn_options* opts, 
 
 namespace {
 
-// mvn_cholesky, with Sigma optionally read in the order d_perm (device).
-int cholesky_impl(int n, const double* d_sigma, int ld_sigma, const int64_t* d_perm, const double* d_locs,
-                  const mvn_matern* kern, const mvn_options* opts, void* factor_buf, size_t factor_bytes, void* ws,
-                  size_t ws_bytes, mvn_factor* out, hipStream_t stream) {
+// mvn_cholesky, with Sigma optionally read in the order d_perm (device;
+// perm_bad: the flag of its device check).
+int cholesky_impl(int n, const double* d_sigma, int ld_sigma, const int64_t* d_perm, const int* perm_bad,
+                  const double* d_locs, const mvn_matern* kern, const mvn_options* opts, void* factor_buf,
+                  size_t factor_bytes, void* ws, size_t ws_bytes, mvn_factor* out, hipStream_t stream) {
   if (n < 1) return fail(-1, "n must be >= 1 (got %d)", n);
   if (d_sigma && ld_sigma < n) return fail(-3, "ld_sigma %d < n %d", ld_sigma, n);
   if (!d_sigma) {
@@ -783,7 +822,7 @@ int cholesky_impl(int n, const double* d_sigma, int ld_sigma, const int64_t* d_p
     out->ranks = (int*)(fb + G.ranks);
     out->tlr_eps = opts->tlr_eps;
     out->max_rank = opts->max_rank;
-    hipError_t e = mvn::launch_tlr_build(n, G.m, G.nt, d_sigma, ld_sigma, d_perm, d_locs, matern_of(kern), out->L,
+    hipError_t e = mvn::launch_tlr_build(n, G.m, G.nt, d_sigma, ld_sigma, d_perm, perm_bad, d_locs, matern_of(kern), out->L,
                                          out->info, stream);
     if (e != hipSuccess) return hip_fail(e, "tlr build");
     mvn::TlrCholArgs a{};
@@ -809,12 +848,13 @@ int cholesky_impl(int n, const double* d_sigma, int ld_sigma, const int64_t* d_p
   if (!factor_buf) return fail(-7, "factor buffer is NULL");
   if (factor_bytes < need) return fail(-8, "factor buffer too small: %zu < %zu", factor_bytes, need);
   if (!out) return fail(-11, "out is NULL");
+  if (opts->chol_mode < MVN_CHOL_ADAPTIVE || opts->chol_mode > MVN_CHOL_FP64)
+    return fail(-6, "unknown chol_mode %d", opts->chol_mode);
   const int ld = padded(n);
   double* L = (double*)factor_buf;
-  int* info = (int*)((char*)factor_buf + align_up(sizeof(double) * (size_t)ld * ld));
-  void* low = opts->precision == MVN_FP64
-                  ? nullptr
-                  : (char*)factor_buf + align_up(sizeof(double) * (size_t)ld * ld) + kAlign;
+  char* hdr = (char*)factor_buf + align_up(sizeof(double) * (size_t)ld * ld);
+  int* info = (int*)hdr;
+  void* low = opts->precision == MVN_FP64 ? nullptr : hdr + dense_header_bytes(ld);
   out->n = n;
   out->ld = ld;
   out->precision = opts->precision;
@@ -829,12 +869,21 @@ int cholesky_impl(int n, const double* d_sigma, int ld_sigma, const int64_t* d_p
   out->ranks = nullptr;
   out->tlr_eps = 0;
   out->max_rank = 0;
-  out->reserved1 = 0;
-  hipError_t e =
-      mvn::launch_build_matrix(n, ld, d_sigma, ld_sigma, d_perm, d_locs, matern_of(kern), L, info, stream);
+  out->chol_mode = opts->precision == MVN_FP64 ? MVN_CHOL_FP64 : opts->chol_mode;
+  out->update_counts = (unsigned long long*)(hdr + 16);
+  hipError_t e = mvn::launch_clear_u64(out->update_counts, 3, stream);
+  if (e != hipSuccess) return hip_fail(e, "counter clear");
+  e = mvn::launch_build_matrix(n, ld, d_sigma, ld_sigma, d_perm, perm_bad, d_locs, matern_of(kern), L, info, stream);
   if (e != hipSuccess) return hip_fail(e, "build_matrix");
-  e = opts->precision == MVN_FP64 ? mvn::launch_cholesky_f64(ld, opts->tile, L, info, stream)
-                                  : mvn::launch_cholesky_lp(opts->precision, ld, opts->tile, L, info, low, stream);
+  if (opts->precision == MVN_FP64) {
+    e = mvn::launch_cholesky_f64(ld, opts->tile, L, info, stream);
+  } else {
+    mvn::LpMap map{(double*)(hdr + 64), (double*)(hdr + 8), out->update_counts,
+                   opts->chol_tol > 0 ? opts->chol_tol : 1e-9};
+    e = mvn::launch_cholesky_lp(opts->precision, ld, opts->tile, L, info, low, stream,
+                                opts->chol_mode == MVN_CHOL_ADAPTIVE ? &map : nullptr,
+                                opts->chol_mode == MVN_CHOL_FP64);
+  }
   if (e != hipSuccess) return hip_fail(e, "cholesky");
   return 0;
 }
@@ -851,7 +900,7 @@ PostLayout post_layout(int n, int m, int tile) {
   P.mpad = ((long)m + tile - 1) / tile * tile;
   P.ld = (P.mpad + n + 1 + 127) / 128 * 128;
   size_t off = 0;
-  P.obs = off; off = align_up(off + sizeof(int64_t) * (size_t)m);
+  P.obs = off; off = align_up(off + sizeof(int));  // the observation index check's flag
   P.B = off; off = align_up(off + sizeof(double) * (size_t)P.ld * (size_t)P.ld);
   P.total = off;
   return P;
@@ -862,8 +911,8 @@ PostLayout post_layout(int n, int m, int tile) {
 int mvn_cholesky(int n, const double* d_sigma, int ld_sigma, const double* d_locs, const mvn_matern* kern,
                  const mvn_options* opts, void* factor_buf, size_t factor_bytes, void* ws, size_t ws_bytes,
                  mvn_factor* out, hipStream_t stream) {
-  return cholesky_impl(n, d_sigma, ld_sigma, nullptr, d_locs, kern, opts, factor_buf, factor_bytes, ws, ws_bytes, out,
-                       stream);
+  return cholesky_impl(n, d_sigma, ld_sigma, nullptr, nullptr, d_locs, kern, opts, factor_buf, factor_bytes, ws,
+                       ws_bytes, out, stream);
 }
 
 int mvn_cholesky_permuted_workspace_bytes(int n, const mvn_options* opts, size_t* bytes) {
@@ -871,25 +920,18 @@ int mvn_cholesky_permuted_workspace_bytes(int n, const mvn_options* opts, size_t
   size_t base = 0;
   const int rc = mvn_cholesky_workspace_bytes(n, opts, &base);
   if (rc) return rc;
-  *bytes = align_up(base) + align_up(sizeof(int64_t) * (size_t)n);
+  // the permutation check: a flag and one int per site
+  *bytes = align_up(base) + kAlign + align_up(sizeof(int) * (size_t)n);
   return 0;
 }
 
-int mvn_cholesky_permuted(int n, const double* d_sigma, int ld_sigma, const int64_t* h_perm, const mvn_options* opts,
+int mvn_cholesky_permuted(int n, const double* d_sigma, int ld_sigma, const int64_t* d_perm, const mvn_options* opts,
                           void* factor_buf, size_t factor_bytes, void* ws, size_t ws_bytes, mvn_factor* out,
                           hipStream_t stream) {
   if (n < 1) return fail(-1, "n must be >= 1 (got %d)", n);
   if (!d_sigma) return fail(-2, "sigma is NULL");
   if (ld_sigma < n) return fail(-3, "ld_sigma %d < n %d", ld_sigma, n);
-  if (!h_perm) return fail(-4, "perm is NULL");
-  {
-    std::vector<char> seen((size_t)n, 0);
-    for (int i = 0; i < n; ++i) {
-      const int64_t q = h_perm[i];
-      if (q < 0 || q >= n || seen[(size_t)q]) return fail(-4, "perm is not a permutation of 0..n-1 (entry %d)", i);
-      seen[(size_t)q] = 1;
-    }
-  }
+  if (!d_perm) return fail(-4, "perm is NULL");
   if (!opts) return fail(-5, "options are required");
   int bad_tile = 0;
   if (!opts_ok(opts, &bad_tile)) return fail(-5, "tile must be >= 16 and a multiple of 4 (got %d)", opts->tile);
@@ -904,12 +946,12 @@ int mvn_cholesky_permuted(int n, const double* d_sigma, int ld_sigma, const int6
   if (!ws) return fail(-8, "workspace is NULL");
   if (ws_bytes < need) return fail(-9, "workspace too small: %zu < %zu", ws_bytes, need);
   if (!out) return fail(-10, "out is NULL");
-  int64_t* d_perm = (int64_t*)((char*)ws + align_up(base));
-  hipError_t e = hipMemcpyAsync(d_perm, h_perm, sizeof(int64_t) * (size_t)n, hipMemcpyHostToDevice, stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(stream);  // h_perm may be pageable and short-lived
-  if (e != hipSuccess) return hip_fail(e, "permutation copy");
+  int* flag = (int*)((char*)ws + align_up(base));
+  int* seen = (int*)((char*)ws + align_up(base) + kAlign);
+  const hipError_t e = mvn::launch_index_check(d_perm, n, n, seen, flag, stream);
+  if (e != hipSuccess) return hip_fail(e, "permutation check");
   // every argument is valid here, so the shared implementation only enqueues
-  return cholesky_impl(n, d_sigma, ld_sigma, d_perm, nullptr, nullptr, opts, factor_buf, factor_bytes, ws, base,
+  return cholesky_impl(n, d_sigma, ld_sigma, d_perm, flag, nullptr, nullptr, opts, factor_buf, factor_bytes, ws, base,
                        out, stream);
 }
 
@@ -923,16 +965,14 @@ int mvn_posterior_workspace_bytes(int n, int m, const mvn_options* opts, size_t*
   return 0;
 }
 
-int mvn_posterior(int n, const double* d_locs, const double* d_mu, int m, const int64_t* h_obs, const double* d_y,
+int mvn_posterior(int n, const double* d_locs, const double* d_mu, int m, const int64_t* d_obs, const double* d_y,
                   const mvn_matern* kern, double noise_var, const mvn_options* opts, void* ws, size_t ws_bytes,
                   double* d_mu_post, double* d_var_post, int* d_info, double** sigma_post, int* ld_sigma_post,
                   hipStream_t stream) {
   if (n < 1) return fail(-1, "n must be >= 1 (got %d)", n);
   if (!d_locs) return fail(-2, "locations are NULL");
   if (m < 1) return fail(-4, "m must be >= 1 (got %d)", m);
-  if (!h_obs) return fail(-5, "observation indices are NULL");
-  for (int k = 0; k < m; ++k)
-    if (h_obs[k] < 0 || h_obs[k] >= n) return fail(-5, "observation %d indexes site %lld of %d", k, (long long)h_obs[k], n);
+  if (!d_obs) return fail(-5, "observation indices are NULL");
   if (!d_y) return fail(-6, "observations are NULL");
   if (!kern || !mvn::matern_ok(kern->sigma2, kern->beta, kern->nu, kern->nugget))
     return fail(-7, "Matern parameters need sigma2 > 0, beta > 0, 0 < nu <= 20, nugget >= 0");
@@ -946,11 +986,8 @@ int mvn_posterior(int n, const double* d_locs, const double* d_mu, int m, const 
   if (ws_bytes < P.total) return fail(-11, "workspace too small: %zu < %zu", ws_bytes, P.total);
   if (!d_info) return fail(-14, "info is NULL");
   char* w = (char*)ws;
-  int64_t* d_obs = (int64_t*)(w + P.obs);
-  hipError_t e = hipMemcpyAsync(d_obs, h_obs, sizeof(int64_t) * (size_t)m, hipMemcpyHostToDevice, stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(stream);  // h_obs may be pageable and short-lived
-  if (e != hipSuccess) return hip_fail(e, "observation index copy");
   mvn::PosteriorArgs a{};
+  a.obs_bad = (const int*)(w + P.obs);
   a.B = (double*)(w + P.B);
   a.ld = P.ld;
   a.n = n;
@@ -963,7 +1000,7 @@ int mvn_posterior(int n, const double* d_locs, const double* d_mu, int m, const 
   a.mk = matern_of(kern);
   a.noise_var = noise_var;
   a.info = d_info;
-  e = mvn::launch_posterior(a, opts->tile, d_mu_post, d_var_post, stream);
+  const hipError_t e = mvn::launch_posterior(a, opts->tile, d_mu_post, d_var_post, stream);
   if (e != hipSuccess) return hip_fail(e, "posterior");
   if (sigma_post) *sigma_post = a.B + P.mpad * P.ld + P.mpad;
   if (ld_sigma_post) *ld_sigma_post = (int)P.ld;
@@ -1015,7 +1052,10 @@ int mvn_prob_grad(const mvn_factor* f, const double* d_a, const double* d_b, con
   if (N < 1) return fail(-5, "N must be >= 1 (got %d)", N);
   if (S < 1) return fail(-6, "S must be >= 1 (got %d)", S);
   if (!opts) return fail(-8, "options are required");
-  if (opts->precision != MVN_FP64) return fail(-8, "the adjoint sweep is FP64");
+  const int prec = opts->precision;
+  if (!prec_ok(prec)) return fail(-8, "unknown precision %d", prec);
+  if (prec != MVN_FP64 && (prec != f->precision || !f->L_low))
+    return fail(-8, "the factor holds no operand copy for precision %d (built with %d)", prec, f->precision);
   const int n = f->n;
   const GradLayout Lay = grad_layout(n, N, S);
   if (!ws) return fail(-9, "workspace is NULL");
@@ -1036,6 +1076,8 @@ int mvn_prob_grad(const mvn_factor* f, const double* d_a, const double* d_b, con
   if (e != hipSuccess) return hip_fail(e, "setup");
   mvn::GradArgs ga{};
   ga.L = f->L;
+  ga.Llow = prec == MVN_FP64 ? (const void*)f->L : f->L_low;
+  ga.prec = prec;
   ga.ld = f->ld;
   ga.n = n;
   ga.at = at;

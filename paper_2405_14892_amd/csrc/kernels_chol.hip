@@ -13,6 +13,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "gemm_f64.h"
 #include "launch.h"
 #include "sweep_gemm.h"
@@ -21,17 +23,53 @@ namespace mvn {
 
 constexpr int kSub = 32;  // sub-panel width
 
+// ------------------------------------------------------------ index arrays
+// Device check of a caller's index array (a site permutation or the
+// observed sites): every entry in [0, range), and with `seen` (range ints)
+// no entry twice.  *flag = 1 on a bad entry; kernels that would index
+// through the array read it only when *flag == 0.
+__global__ __launch_bounds__(256) void index_clear_kernel(int* __restrict__ seen, long range, int* __restrict__ flag) {
+  const long k = (long)blockIdx.x * 256 + threadIdx.x;
+  if (k == 0) *flag = 0;
+  if (seen && k < range) seen[k] = 0;
+}
+
+__global__ __launch_bounds__(256) void index_check_kernel(const int64_t* __restrict__ idx, long count, long range,
+                                                          int* __restrict__ seen, int* __restrict__ flag) {
+  const long k = (long)blockIdx.x * 256 + threadIdx.x;
+  if (k >= count) return;
+  const int64_t q = idx[k];
+  if (q < 0 || q >= range) {
+    atomicExch(flag, 1);
+  } else if (seen && atomicExch(seen + q, 1) != 0) {
+    atomicExch(flag, 1);
+  }
+}
+
+hipError_t launch_index_check(const int64_t* idx, long count, long range, int* seen, int* flag, hipStream_t st) {
+  const long c = count > range ? count : range;
+  hipLaunchKernelGGL(index_clear_kernel, dim3((unsigned)((c + 255) / 256)), dim3(256), 0, st, seen, range, flag);
+  if (count > 0)
+    hipLaunchKernelGGL(index_check_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, idx, count, range,
+                       seen, flag);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------ covariance
+// perm_bad (with perm): the permutation check's flag; when set the matrix
+// is the identity and *info = -1.
 __global__ __launch_bounds__(256) void build_matrix_kernel(int n, int ld, const double* __restrict__ sigma,
                                                            int lds, const int64_t* __restrict__ perm,
+                                                           const int* __restrict__ perm_bad,
                                                            const double* __restrict__ locs, Matern mk,
                                                            double* __restrict__ A, int* __restrict__ info) {
-  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *info = 0;
+  const bool bad = perm && perm_bad && *perm_bad != 0;
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *info = bad ? -1 : 0;
   const long i = (long)blockIdx.y * 16 + (threadIdx.x >> 4);
   const long j = (long)blockIdx.x * 16 + (threadIdx.x & 15);
   if (i >= ld || j > i) return;
   double v;
-  if (i >= n || j >= n) {
+  if (i >= n || j >= n || bad) {
     v = (i == j) ? 1.0 : 0.0;
   } else if (sigma) {
     const long pi = perm ? perm[i] : i, pj = perm ? perm[j] : j;
@@ -45,10 +83,22 @@ __global__ __launch_bounds__(256) void build_matrix_kernel(int n, int ld, const 
   A[i * ld + j] = v;
 }
 
-hipError_t launch_build_matrix(int n, int ld, const double* sigma, int lds, const int64_t* perm, const double* locs,
-                               const Matern& mk, double* A, int* info, hipStream_t st) {
+__global__ __launch_bounds__(256) void clear_u64_kernel(unsigned long long* __restrict__ p, long n) {
+  const long i = (long)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = 0ull;
+}
+
+hipError_t launch_clear_u64(unsigned long long* p, long n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(clear_u64_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_build_matrix(int n, int ld, const double* sigma, int lds, const int64_t* perm, const int* perm_bad,
+                               const double* locs, const Matern& mk, double* A, int* info, hipStream_t st) {
   dim3 grid(ld / 16, ld / 16);
-  hipLaunchKernelGGL(build_matrix_kernel, grid, dim3(256), 0, st, n, ld, sigma, lds, perm, locs, mk, A, info);
+  hipLaunchKernelGGL(build_matrix_kernel, grid, dim3(256), 0, st, n, ld, sigma, lds, perm, perm_bad, locs, mk, A,
+                     info);
   return hipGetLastError();
 }
 
@@ -460,10 +510,11 @@ SideStream* side_stream(int slot, hipStream_t st) {
   int dev = 0;
   if (slot < 0 || slot >= kSideSlots || hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
     return nullptr;
-  std::lock_guard<std::mutex> g(table_mu);
-  if (table[dev][slot] || failed[dev][slot]) return table[dev][slot];
+  // a call being captured into a graph runs on the caller's stream alone
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return nullptr;
+  std::lock_guard<std::mutex> g(table_mu);
+  if (table[dev][slot] || failed[dev][slot]) return table[dev][slot];
   SideStream* sd = new SideStream();
   bool ok = hipStreamCreateWithFlags(&sd->s, hipStreamNonBlocking) == hipSuccess;
   for (int i = 0; ok && i < 3; ++i) ok = hipEventCreateWithFlags(&sd->ev[i], hipEventDisableTiming) == hipSuccess;
@@ -504,9 +555,15 @@ static void chol_column(int ld, int k0, int kw, double* A, int* info, hipStream_
 //   side:                  wait evP  rest(k)  [evR(k)] ...
 // next(k) waits for rest(k-1), which also writes tile column k + 1; the
 // regions written concurrently are disjoint column ranges.
-template <class Next, class Rest>
+struct NoPost {
+  void operator()(int, int, hipStream_t) const {}
+};
+
+// post(k0, kw, st) runs on the caller's stream after each tile column's
+// sub-panel chain, before any of that column's trailing updates.
+template <class Next, class Rest, class Post = NoPost>
 static hipError_t right_looking(int ld, int tile, double* A, int* info, hipStream_t st, SideStream* sd,
-                                Next next, Rest rest, int kstop = 0) {
+                                Next next, Rest rest, int kstop = 0, Post post = Post()) {
   bool pending = false, used = false;  // a rest() on the side stream not yet waited for; any
   // on an error, let the side stream drain before returning, so that none of
   // its kernels still writes A once the caller sees the failure
@@ -518,6 +575,7 @@ static hipError_t right_looking(int ld, int tile, double* A, int* info, hipStrea
   for (int k0 = 0; k0 < kend; k0 += tile) {
     const int kw = min(tile, ld - k0);
     chol_column(ld, k0, kw, A, info, st);
+    post(k0, kw, st);
     const int c1 = k0 + kw;
     if (c1 < ld) {
       if (!sd) {
@@ -644,14 +702,42 @@ struct SyrkStage<GemmBF16T<SPLIT, 128>> {
   }
 };
 
+// FP64 operands on the sweep's FP64 policy (the precise path of the
+// adaptive map): A rows 8 consecutive k per lane, B rows 4.
+template <>
+struct SyrkStage<GemmF64T<128>> {
+  using G = GemmF64T<128>;
+  struct Regs { double a[8]; double b[4]; };
+  static __device__ __forceinline__ void load(const double* A, long ld, long ra0, long rb0, long k0,
+                                              long klim, Regs& r) {
+    const int t = threadIdx.x;
+    const long row = ra0 + (t >> 1), kb = k0 + (t & 1) * 8;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) r.a[q] = (row < ld && kb + q < klim) ? A[row * ld + kb + q] : 0.0;
+    const long cr = rb0 + (t >> 2), kc = k0 + (t & 3) * 4;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) r.b[q] = (cr < ld && kc + q < klim) ? A[cr * ld + kc + q] : 0.0;
+  }
+  static __device__ __forceinline__ void store(void* stage, const Regs& r) {
+    double* As = (double*)stage;
+    double* Bs = As + G::kAStage;
+    const int t = threadIdx.x;
+    const int row = t >> 1, kb = (t & 1) * 8;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) As[(kb + q) * G::kALd + row] = r.a[q];
+    const int c = t >> 2, kc = (t & 3) * 4;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) Bs[(kc + q) * G::kBLd + c] = r.b[q];
+  }
+};
+
+// One 128 x 64 tile of C = A[rowA:, colB:] -= P P^T in policy G's
+// arithmetic, P = A[:, k0:k0+kw]; only elements with column < clim and
+// column <= row are written.  The caller has checked info and that the tile
+// reaches the lower triangle.
 template <class G>
-// One 128 x 64 tile of C = A[rowA:, colB:] -= P P^T, P = A[:, k0:k0+kw];
-// only elements with column < clim and column <= row are written.
-__device__ __forceinline__ void chol_syrk_lp_body(double* __restrict__ A, int ld, int k0, int kw,
-                                                  const int* __restrict__ info, long rowA, long colB, long clim) {
-  if (*info != 0) return;
-  __shared__ __attribute__((aligned(16))) double lds[kTile * kCols];
-  if (colB > rowA + kTile - 1 || rowA >= ld) return;  // tile entirely above the diagonal
+__device__ __forceinline__ void syrk_lp_tile(double* __restrict__ A, double* lds, int ld, int k0, int kw,
+                                             long rowA, long colB, long clim) {
   typename G::Acc acc;
   G::zero(acc);
   const long klim = (long)k0 + kw;
@@ -677,19 +763,99 @@ __device__ __forceinline__ void chol_syrk_lp_body(double* __restrict__ A, int ld
   }
 }
 
+// Tile-wise precision map of the trailing updates (adaptive mode).  The
+// update of tile (i, j) by tile column k subtracts L_ik L_jk^T; rounding its
+// operands to a type with unit roundoff u (and accumulating K products in
+// FP32) perturbs it by at most about u_K ||L_ik||_F ||L_jk||_F, u_K = u +
+// K 2^-24.  A tile runs in the reduced type when that bound is at most
+// tol * max_i Sigma_ii, else in FP32 when FP32's bound is, else in FP64;
+// near-diagonal tiles, whose panel blocks carry most of the factor's mass,
+// therefore stay precise and far tiles with small panel norms do not.
+// norms[b] = ||L[r0 + 128 b : r0 + 128 (b + 1), k0 : k0 + kw]||_F for the
+// step's rows r0 = k0 + kw (a 64-row B block lies inside one of them).
+struct PrecMap {
+  const double* norms;        // nullptr: uniform precision (policy G everywhere)
+  const double* dmax;         // max diagonal of Sigma (device)
+  unsigned long long* counts; // tile updates per path: [0] FP64, [1] FP32, [2] reduced type
+  long r0;
+  double tol, u_low, u_f32;
+};
+
+template <class G>
+__device__ __forceinline__ void chol_syrk_lp_body(double* __restrict__ A, int ld, int k0, int kw,
+                                                  const int* __restrict__ info, long rowA, long colB, long clim,
+                                                  const PrecMap& pm) {
+  if (*info != 0) return;
+  __shared__ __attribute__((aligned(16))) double lds[kTile * kCols];
+  if (colB > rowA + kTile - 1 || rowA >= ld) return;  // tile entirely above the diagonal
+  if (!pm.norms) {
+    syrk_lp_tile<G>(A, lds, ld, k0, kw, rowA, colB, clim);
+    return;
+  }
+  const double bnd = pm.norms[(rowA - pm.r0) >> 7] * pm.norms[(colB - pm.r0) >> 7];
+  const double thr = pm.tol * *pm.dmax;
+  const int path = bnd * pm.u_low <= thr ? 2 : (bnd * pm.u_f32 <= thr ? 1 : 0);
+  if (threadIdx.x == 0) atomicAdd(pm.counts + path, 1ull);
+  if (path == 2) syrk_lp_tile<G>(A, lds, ld, k0, kw, rowA, colB, clim);
+  else if (path == 1) syrk_lp_tile<GemmF32>(A, lds, ld, k0, kw, rowA, colB, clim);
+  else syrk_lp_tile<GemmF64T<128>>(A, lds, ld, k0, kw, rowA, colB, clim);
+}
+
+// Block norms of the finished tile column for the precision map: workgroup b
+// covers rows r0 + 128 b .. + 127 of columns [k0, k0 + kw).
+__global__ __launch_bounds__(256) void panel_norm_kernel(const double* __restrict__ A, int ld, int k0, int kw,
+                                                         int r0, const int* __restrict__ info,
+                                                         double* __restrict__ norms) {
+  if (*info != 0) return;
+  __shared__ double red[256];
+  const long rb = (long)r0 + (long)blockIdx.x * 128;
+  double s = 0.0;
+  for (int e = threadIdx.x; e < 128 * kw; e += 256) {
+    const long row = rb + e / kw;
+    if (row < ld) {
+      const double v = A[row * ld + k0 + e % kw];
+      s += v * v;
+    }
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) norms[blockIdx.x] = sqrt(red[0]);
+}
+
+// max_i A_ii of the matrix about to be factored; clears the path counters.
+__global__ __launch_bounds__(1024) void diag_max_kernel(const double* __restrict__ A, int ld,
+                                                        double* __restrict__ dmax,
+                                                        unsigned long long* __restrict__ counts) {
+  __shared__ double red[1024];
+  double m = 0.0;
+  for (int i = threadIdx.x; i < ld; i += 1024) m = fmax(m, A[(long)i * ld + i]);
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int h = 512; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + h]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *dmax = red[0];
+  if (threadIdx.x < 3) counts[threadIdx.x] = 0ull;
+}
+
 // Tiles (blockIdx.y, blockIdx.x) of A[r0:, r0:].
 template <class G>
 __global__ __launch_bounds__(256) void chol_syrk_lp_kernel(double* __restrict__ A, int ld, int k0, int kw, int r0,
-                                                           const int* __restrict__ info) {
-  chol_syrk_lp_body<G>(A, ld, k0, kw, info, r0 + (long)blockIdx.y * kTile, r0 + (long)blockIdx.x * kCols, ld);
+                                                           const int* __restrict__ info, PrecMap pm) {
+  chol_syrk_lp_body<G>(A, ld, k0, kw, info, r0 + (long)blockIdx.y * kTile, r0 + (long)blockIdx.x * kCols, ld, pm);
 }
 
 // Tile column [c1, c2) of the trailing matrix, c1 = k0 + kw.
 template <class G>
 __global__ __launch_bounds__(256) void chol_syrk_lp_col_kernel(double* __restrict__ A, int ld, int k0, int kw, int c2,
-                                                               const int* __restrict__ info) {
+                                                               const int* __restrict__ info, PrecMap pm) {
   const long c1 = (long)k0 + kw;
-  chol_syrk_lp_body<G>(A, ld, k0, kw, info, c1 + (long)blockIdx.y * kTile, c1 + (long)blockIdx.x * kCols, c2);
+  chol_syrk_lp_body<G>(A, ld, k0, kw, info, c1 + (long)blockIdx.y * kTile, c1 + (long)blockIdx.x * kCols, c2, pm);
 }
 
 // Low-precision operand copy of the finished factor for the sweep's GEMM:
@@ -716,41 +882,92 @@ __global__ __launch_bounds__(256) void convert_factor_kernel(const double* __res
   if (SPLIT == 2) out[ld * ld + e] = (E)(float)(v - (double)(float)hi);
 }
 
+// Unit roundoff of a tile update's products in policy G's type, with the
+// FP32 accumulation of K products (worst case).
 template <class G>
-static hipError_t cholesky_lp(int ld, int tile, double* A, int* info, hipStream_t st, SideStream* sd) {
+static double unit_roundoff(int kw) {
+  const double acc = ldexp((double)kw, -24);
+  if (std::is_same<G, GemmF32>::value) return ldexp(1.0, -23) + acc;
+  if (std::is_same<G, GemmBF16>::value) return ldexp(1.0, -8) + acc;
+  return ldexp(1.0, -15) + acc;  // split BF16: hi*hi + hi*lo + lo*hi
+}
+
+template <class G>
+static hipError_t cholesky_lp(int ld, int tile, double* A, int* info, hipStream_t st, SideStream* sd,
+                              const LpMap* map) {
+  // panel norms of step k in slot k & 1: the rest of step k (side stream)
+  // may still read them while step k + 1 writes the other slot; step k + 2
+  // runs after next(k + 1), which waits for rest(k)
+  const long nslot = ld / 128 + 1;
+  auto pm_of = [&](int k0, int kw) {
+    PrecMap pm{};
+    if (map) {
+      pm.norms = map->norms + (long)(((k0 / tile) & 1)) * nslot;
+      pm.dmax = map->dmax;
+      pm.counts = map->counts;
+      pm.r0 = (long)k0 + kw;
+      pm.tol = map->tol;
+      pm.u_low = unit_roundoff<G>(kw);
+      pm.u_f32 = unit_roundoff<GemmF32>(kw);
+    }
+    return pm;
+  };
+  auto post = [&](int k0, int kw, hipStream_t s) {
+    if (!map) return;
+    const int r0 = k0 + kw;
+    if (r0 >= ld) return;
+    hipLaunchKernelGGL(panel_norm_kernel, dim3((unsigned)((ld - r0 + 127) / 128)), dim3(256), 0, s, (const double*)A,
+                       ld, k0, kw, r0, (const int*)info, map->norms + (long)((k0 / tile) & 1) * nslot);
+  };
   auto next = [&](int k0, int kw, int c2, hipStream_t s) {
     const long c1 = (long)k0 + kw;
     const dim3 grid((unsigned)((c2 - c1 + kCols - 1) / kCols), (unsigned)((ld - c1 + kTile - 1) / kTile));
-    hipLaunchKernelGGL(chol_syrk_lp_col_kernel<G>, grid, dim3(256), 0, s, A, ld, k0, kw, c2, (const int*)info);
+    hipLaunchKernelGGL(chol_syrk_lp_col_kernel<G>, grid, dim3(256), 0, s, A, ld, k0, kw, c2, (const int*)info,
+                       pm_of(k0, kw));
   };
   auto rest = [&](int k0, int kw, int r0, hipStream_t s) {
     const dim3 grid((unsigned)((ld - r0 + kCols - 1) / kCols), (unsigned)((ld - r0 + kTile - 1) / kTile));
-    hipLaunchKernelGGL(chol_syrk_lp_kernel<G>, grid, dim3(256), 0, s, A, ld, k0, kw, r0, (const int*)info);
+    hipLaunchKernelGGL(chol_syrk_lp_kernel<G>, grid, dim3(256), 0, s, A, ld, k0, kw, r0, (const int*)info,
+                       pm_of(k0, kw));
   };
-  return right_looking(ld, tile, A, info, st, sd, next, rest);
+  if (map)
+    hipLaunchKernelGGL(diag_max_kernel, dim3(1), dim3(1024), 0, st, (const double*)A, ld, map->dmax, map->counts);
+  return right_looking(ld, tile, A, info, st, sd, next, rest, 0, post);
 }
 
-hipError_t launch_cholesky_lp(int prec, int ld, int tile, double* A, int* info, void* low, hipStream_t st) {
+// Low-precision operand copy of the finished factor (prec 1..3).
+static hipError_t convert_factor(int prec, int ld, const double* A, void* low, hipStream_t st) {
+  const long tot = (long)ld * ld;
+  const dim3 cg((unsigned)((tot + 255) / 256));
+  switch (prec) {
+    case 1: hipLaunchKernelGGL((convert_factor_kernel<float, 1>), cg, dim3(256), 0, st, A, (long)ld, (float*)low); break;
+    case 2: hipLaunchKernelGGL((convert_factor_kernel<__bf16, 1>), cg, dim3(256), 0, st, A, (long)ld, (__bf16*)low); break;
+    case 3: hipLaunchKernelGGL((convert_factor_kernel<__bf16, 2>), cg, dim3(256), 0, st, A, (long)ld, (__bf16*)low); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_cholesky_lp(int prec, int ld, int tile, double* A, int* info, void* low, hipStream_t st,
+                              const LpMap* map, bool fp64_factor) {
   if (prec < 1 || prec > 3) return hipErrorInvalidValue;
+  if (fp64_factor) {
+    hipError_t e = launch_cholesky_f64(ld, tile, A, info, st);
+    if (e != hipSuccess) return e;
+    return convert_factor(prec, ld, A, low, st);
+  }
   SideStream* sd = ld > 2 * tile ? side_stream(kSideCholesky, st) : nullptr;
   std::unique_lock<std::mutex> lock;
   if (sd) lock = std::unique_lock<std::mutex>(sd->mu);
   hipError_t e;
   switch (prec) {
-    case 1: e = cholesky_lp<GemmF32>(ld, tile, A, info, st, sd); break;
-    case 2: e = cholesky_lp<GemmBF16>(ld, tile, A, info, st, sd); break;
-    default: e = cholesky_lp<GemmBF16x3>(ld, tile, A, info, st, sd); break;
+    case 1: e = cholesky_lp<GemmF32>(ld, tile, A, info, st, sd, map); break;
+    case 2: e = cholesky_lp<GemmBF16>(ld, tile, A, info, st, sd, map); break;
+    default: e = cholesky_lp<GemmBF16x3>(ld, tile, A, info, st, sd, map); break;
   }
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(zero_upper_kernel, dim3(ld / 16, ld / 16), dim3(256), 0, st, A, ld);
-  const long tot = (long)ld * ld;
-  const dim3 cg((unsigned)((tot + 255) / 256));
-  switch (prec) {
-    case 1: hipLaunchKernelGGL((convert_factor_kernel<float, 1>), cg, dim3(256), 0, st, (const double*)A, (long)ld, (float*)low); break;
-    case 2: hipLaunchKernelGGL((convert_factor_kernel<__bf16, 1>), cg, dim3(256), 0, st, (const double*)A, (long)ld, (__bf16*)low); break;
-    case 3: hipLaunchKernelGGL((convert_factor_kernel<__bf16, 2>), cg, dim3(256), 0, st, (const double*)A, (long)ld, (__bf16*)low); break;
-  }
-  return hipGetLastError();
+  return convert_factor(prec, ld, A, low, st);
 }
 
 // ------------------------------------------------------------ batches
@@ -878,7 +1095,7 @@ __global__ __launch_bounds__(256) void batch_syrk_lp_kernel(const BatchDesc* __r
   const int bx = item - by * (by + 1);
   const long r0 = (long)k0 + kBatchTile;
   chol_syrk_lp_body<G>(factor + d.factor_off, d.ld, k0, kBatchTile, info + p, r0 + (long)by * kTile,
-                       r0 + (long)bx * kCols, d.ld);
+                       r0 + (long)bx * kCols, d.ld, PrecMap{});
 }
 
 // Launches `launch(groups, total)` for the groups of ranks [0, cnt) with

@@ -80,8 +80,17 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
+// G: the forward pass's limit-update GEMM (FP64, or FP32 / BF16 / split BF16
+// on the factor's operand copy with FP32 accumulation; Y in G's operand
+// type).  The reverse GEMM is FP64 on the FP64 factor in every mode, and
+// the conditioning step is the FP64 one, so the reverse pass differentiates
+// exactly the forward recurrence it recomputes from the stored shifts.
+template <class G>
 __global__ __launch_bounds__(256, 2) void grad_kernel(GradArgs p) {
-  using G = GemmF64;
+  using E = typename G::E;
+  using R = GemmF64;  // reverse GEMM
+  static_assert(2 * G::kStageBytes <= kTile * kCols * 8 && 2 * R::kStageBytes <= kTile * kCols * 8,
+                "GEMM stages fit the block buffer");
   __shared__ __attribute__((aligned(16))) double lds[kTile * kCols];
   __shared__ double slab[kSlab * kTile];
   __shared__ double c_at[kTile], c_bt[kTile], c_rl[kTile];
@@ -92,11 +101,15 @@ __global__ __launch_bounds__(256, 2) void grad_kernel(GradArgs p) {
   const long nchunks = (NS + kCols - 1) / kCols;
   const long ld = p.ld;
   const long slice = ld * kCols;
-  double* Y = p.yscr + (long)blockIdx.x * slice;
+  E* Y = (E*)(p.yscr + (long)blockIdx.x * slice);
+  const E* Lg = (const E*)p.Llow;
+  const long lplane = ld * ld;
   double* Sf = p.sfw + (long)blockIdx.x * slice;
   double* Sb = p.sbar + (long)blockIdx.x * slice;
   char* stage0 = (char*)lds;
   char* stage1 = (char*)lds + G::kStageBytes;
+  char* rstage0 = (char*)lds;
+  char* rstage1 = (char*)lds + R::kStageBytes;
   const int nblk = (p.n + kTile - 1) / kTile;
 
   // rows n..ld-1 of the s-bar scratch are read by the reverse GEMMs (as
@@ -114,17 +127,17 @@ __global__ __launch_bounds__(256, 2) void grad_kernel(GradArgs p) {
     // ================= forward pass (the probability sweep, keeping s_i)
     for (int i0 = 0; i0 < p.n; i0 += kTile) {
       const int rows = min(kTile, p.n - i0);
-      G::Acc acc;
+      typename G::Acc acc;
       G::zero(acc);
       if (i0 > 0) {
         const int nst = i0 / G::kK;
-        G::Regs r;
-        G::load(p.L, ld, 0, i0, 0, Y, ld, r);
+        typename G::Regs r;
+        G::load(Lg, ld, lplane, i0, 0, Y, ld, r);
         G::store(stage0, r);
         __syncthreads();
         for (int s = 0; s < nst; ++s) {
           const bool odd = s & 1;
-          if (s + 1 < nst) G::load(p.L, ld, 0, i0, (long)(s + 1) * G::kK, Y, ld, r);
+          if (s + 1 < nst) G::load(Lg, ld, lplane, i0, (long)(s + 1) * G::kK, Y, ld, r);
           G::mma(odd ? stage1 : stage0, acc);
           if (s + 1 < nst) G::store(odd ? stage0 : stage1, r);
           __syncthreads();
@@ -165,33 +178,33 @@ __global__ __launch_bounds__(256, 2) void grad_kernel(GradArgs p) {
     for (int r = nblk - 1; r >= 0; --r) {
       const int i0 = r * kTile;
       const int rows = min(kTile, p.n - i0);
-      G::Acc acc;
-      G::zero(acc);
+      R::Acc acc;
+      R::zero(acc);
       // ---- Y-bar of the block from the later blocks: K over rows j >= i0 + 128
       const long j0 = (long)i0 + kTile;
-      const int nst = (int)((ld - j0) / G::kK);
+      const int nst = (int)((ld - j0) / R::kK);
       if (nst > 0) {
         double ra[8], rb[4];
         RevOperand::load(p.L, ld, j0, i0, ra);
         load_sbar(Sb, j0, rb);
-        RevOperand::store((double*)stage0, ra);
-        store_sbar((double*)stage0, rb);
+        RevOperand::store((double*)rstage0, ra);
+        store_sbar((double*)rstage0, rb);
         __syncthreads();
         for (int s = 0; s < nst; ++s) {
           const bool odd = s & 1;
           if (s + 1 < nst) {
-            RevOperand::load(p.L, ld, j0 + (long)(s + 1) * G::kK, i0, ra);
-            load_sbar(Sb, j0 + (long)(s + 1) * G::kK, rb);
+            RevOperand::load(p.L, ld, j0 + (long)(s + 1) * R::kK, i0, ra);
+            load_sbar(Sb, j0 + (long)(s + 1) * R::kK, rb);
           }
-          G::mma(odd ? stage1 : stage0, acc);
+          R::mma(odd ? rstage1 : rstage0, acc);
           if (s + 1 < nst) {
-            RevOperand::store((double*)(odd ? stage0 : stage1), ra);
-            store_sbar((double*)(odd ? stage0 : stage1), rb);
+            RevOperand::store((double*)(odd ? rstage0 : rstage1), ra);
+            store_sbar((double*)(odd ? rstage0 : rstage1), rb);
           }
           __syncthreads();
         }
       }
-      G::to_block(acc, lds);
+      R::to_block(acc, lds);
       if (t < rows) {
         const long g = i0 + t;
         c_at[t] = p.at[g];
@@ -330,7 +343,13 @@ __global__ __launch_bounds__(256) void grad_sum_kernel(const double* __restrict_
 
 hipError_t launch_grad(const GradArgs& a, const int* info_factor, const int* bad, double* scale,
                        double* da, double* db, double* dmu, hipStream_t st) {
-  hipLaunchKernelGGL(grad_kernel, dim3(a.grid), dim3(256), 0, st, a);
+  switch (a.prec) {
+    case 0: hipLaunchKernelGGL(grad_kernel<GemmF64>, dim3(a.grid), dim3(256), 0, st, a); break;
+    case 1: hipLaunchKernelGGL(grad_kernel<GemmF32>, dim3(a.grid), dim3(256), 0, st, a); break;
+    case 2: hipLaunchKernelGGL(grad_kernel<GemmBF16>, dim3(a.grid), dim3(256), 0, st, a); break;
+    case 3: hipLaunchKernelGGL(grad_kernel<GemmBF16x3>, dim3(a.grid), dim3(256), 0, st, a); break;
+    default: return hipErrorInvalidValue;
+  }
   const long nchunks = ((long)a.N * a.S + kCols - 1) / kCols;
   hipLaunchKernelGGL(grad_scale_kernel, dim3(1), dim3(256), 0, st, (const double*)a.mz, nchunks, scale);
   hipLaunchKernelGGL(grad_sum_kernel, dim3((a.n + 255) / 256), dim3(256), 0, st, (const double*)a.gpart,

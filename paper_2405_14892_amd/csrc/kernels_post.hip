@@ -29,12 +29,18 @@ namespace {
 
 __device__ __forceinline__ double& B_at(const PosteriorArgs& p, long i, long j) { return p.B[i * p.ld + j]; }
 
-// Lower triangle of B, 16 x 16 elements per workgroup; clears *info.
+// Lower triangle of B, 16 x 16 elements per workgroup; clears *info (-1
+// and the identity when an observed-site index is out of range).
 __global__ __launch_bounds__(256) void posterior_build_kernel(PosteriorArgs p) {
-  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *p.info = 0;
+  const bool bad = *p.obs_bad != 0;
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *p.info = bad ? -1 : 0;
   const long i = (long)blockIdx.y * 16 + (threadIdx.x >> 4);
   const long j = (long)blockIdx.x * 16 + (threadIdx.x & 15);
   if (i >= p.ld || j > i) return;
+  if (bad) {
+    B_at(p, i, j) = (i == j) ? 1.0 : 0.0;
+    return;
+  }
   const long mp = p.mpad, e = p.mpad + p.n;  // first site row, data row
   auto site = [&](long r) -> long { return r < mp ? p.obs[r] : r - mp; };  // site index of an observation/site row
   auto cov = [&](long a, long b) {  // Sigma between sites a and b (nugget on equal sites)
@@ -71,8 +77,10 @@ __global__ __launch_bounds__(256) void posterior_moments_kernel(PosteriorArgs p,
 
 hipError_t launch_posterior(const PosteriorArgs& p, int tile, double* mu_post, double* var_post, hipStream_t st) {
   const dim3 grid((unsigned)(p.ld / 16), (unsigned)(p.ld / 16));
+  hipError_t e = launch_index_check(p.obs, p.m, p.n, nullptr, const_cast<int*>(p.obs_bad), st);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(posterior_build_kernel, grid, dim3(256), 0, st, p);
-  hipError_t e = hipGetLastError();
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
   // the first m' columns only; a non-positive pivot of K lands in *info
   e = launch_cholesky_f64((int)p.ld, tile, p.B, p.info, st, true, (int)p.mpad);

@@ -58,11 +58,13 @@ __device__ __forceinline__ void tri_inverse(long b, long& i, long& j) {
 // One 64 x 64 sub-block of one lower tile per workgroup; clears *info.
 __global__ __launch_bounds__(256) void tlr_build_kernel(int n, int m, const double* __restrict__ sigma, int lds,
                                                         const int64_t* __restrict__ perm,
+                                                        const int* __restrict__ perm_bad,
                                                         const double* __restrict__ locs, Matern mk,
                                                         double* __restrict__ tiles, int* __restrict__ info) {
   const long per = (long)(m / 64) * (m / 64);
   const long t = blockIdx.x / per, sb = blockIdx.x % per;
-  if (blockIdx.x == 0 && threadIdx.x == 0) *info = 0;
+  const bool bad = perm && perm_bad && *perm_bad != 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *info = bad ? -1 : 0;
   long ti, tj;
   tri_inverse(t, ti, tj);
   const long r0 = (sb / (m / 64)) * 64, c0 = (sb % (m / 64)) * 64;
@@ -71,7 +73,7 @@ __global__ __launch_bounds__(256) void tlr_build_kernel(int n, int m, const doub
     const long lr = r0 + (e >> 6), lc = c0 + (e & 63);
     const long i = ti * m + lr, j = tj * m + lc;
     double v;
-    if (i >= n || j >= n) {
+    if (i >= n || j >= n || bad) {
       v = (i == j) ? 1.0 : 0.0;
     } else if (sigma) {
       const long pi = perm ? perm[i] : i, pj = perm ? perm[j] : j;
@@ -551,10 +553,11 @@ __global__ void tlr_info_kernel(int* __restrict__ info, const int* __restrict__ 
 }
 
 hipError_t launch_tlr_build(int n, int m, int nt, const double* sigma, int lds, const int64_t* perm,
-                            const double* locs, const Matern& mk, double* tiles, int* info, hipStream_t st) {
+                            const int* perm_bad, const double* locs, const Matern& mk, double* tiles, int* info,
+                            hipStream_t st) {
   const long sub = (long)(m / 64) * (m / 64) * ((long)nt * (nt + 1) / 2);
-  hipLaunchKernelGGL(tlr_build_kernel, dim3((unsigned)sub), dim3(256), 0, st, n, m, sigma, lds, perm, locs, mk,
-                     tiles, info);
+  hipLaunchKernelGGL(tlr_build_kernel, dim3((unsigned)sub), dim3(256), 0, st, n, m, sigma, lds, perm, perm_bad,
+                     locs, mk, tiles, info);
   return hipGetLastError();
 }
 

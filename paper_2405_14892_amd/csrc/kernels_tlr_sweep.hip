@@ -16,6 +16,89 @@
 
 namespace mvn {
 
+// ------------------------------------------------------------ index tables
+// The tables of tlr_tables.h (stacked V' rows by tile column, packed K of
+// every tile-row, the Z row of every stacked row), built from the ranks on
+// the device so that a call never reads them back; then the layout of the
+// rank-dependent region (packed operands, then per workgroup a Y and a Z
+// slice) and how many workgroups it holds.  One workgroup; pair p = (i, j),
+// i > j, has index i (i - 1) / 2 + j.
+__device__ __forceinline__ long align256(long x) { return (x + 255) / 256 * 256; }
+
+__global__ __launch_bounds__(1024) void tlr_tables_kernel(TlrTableArgs a) {
+  const int t = threadIdx.x, nt = a.nt;
+  const long np = (long)nt * (nt - 1) / 2;
+  for (long p = t; p < np; p += 1024) {
+    const long r = a.ranks[p] < 0 ? -(long)a.ranks[p] : (long)a.ranks[p];
+    a.kk[p] = (int)(r > a.rs ? a.rs : r);
+  }
+  __syncthreads();
+  // per tile column j: the sum of its ranks (zcol[j + 1] holds it for now);
+  // per tile-row i: the sum of its ranks, and each pair's column within it
+  for (int j = t; j < nt; j += 1024) {
+    long c = 0;
+    for (int i = j + 1; i < nt; ++i) c += a.kk[(long)i * (i - 1) / 2 + j];
+    a.zcol[j + 1] = c;
+  }
+  for (int i = t; i < nt; i += 1024) {
+    long c = 0;
+    for (int j = 0; j < i; ++j) {
+      const long p = (long)i * (i - 1) / 2 + j;
+      a.ucol0[p] = c;
+      c += a.kk[p];
+    }
+    a.kval[i] = (int)c;
+  }
+  __syncthreads();
+  if (t == 0) {
+    a.zcol[0] = 0;
+    a.kpad0[0] = 0;
+    for (int j = 0; j < nt; ++j) {
+      a.zcol[j + 1] += a.zcol[j];
+      a.kpad0[j + 1] = a.kpad0[j] + ((long)a.kval[j] + 15) / 16 * 16;
+    }
+    TlrSweepHdr h{};
+    h.ksum = a.zcol[nt];
+    h.kpad = a.kpad0[nt];
+    const long m = a.m;
+    h.vpack = 0;
+    h.upack = align256(8 * (h.ksum + 128) * m);
+    h.yscr = align256(h.upack + 8 * m * (h.kpad > 0 ? h.kpad : 1));
+    h.zslice = (h.kpad > 0 ? h.kpad : 1) * kCols;
+    const long per = align256(8 * a.yslice) + align256(8 * h.zslice);
+    const long room = (long)a.dyn_bytes - h.yscr;
+    long g = room > 0 ? room / per : 0;
+    if (g > a.grid_max) g = a.grid_max;
+    h.grid = g;
+    h.zscr = align256(h.yscr + 8 * g * a.yslice);
+    *a.hdr = h;
+    if (g < 1) *a.bad = 0;  // no sweep workgroup fits: the reduction reports NaN
+  }
+  __syncthreads();
+  // first stacked row of each pair, then every stacked row's Z row
+  for (int j = t; j < nt; j += 1024) {
+    long row = a.zcol[j];
+    for (int i = j + 1; i < nt; ++i) {
+      const long p = (long)i * (i - 1) / 2 + j;
+      a.vrow0[p] = row;
+      row += a.kk[p];
+    }
+  }
+  __syncthreads();
+  for (long p = t; p < np; p += 1024) {
+    int i = (int)((1.0 + sqrt(1.0 + 8.0 * (double)p)) * 0.5);
+    while ((long)i * (i - 1) / 2 > p) --i;
+    while ((long)(i + 1) * i / 2 <= p) ++i;
+    const long base = a.kpad0[i] + a.ucol0[p], r0 = a.vrow0[p];
+    for (int q = 0; q < a.kk[p]; ++q) a.zdst[r0 + q] = base + q;
+  }
+}
+
+hipError_t launch_tlr_tables(const TlrTableArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(tlr_tables_kernel, dim3(1), dim3(1024), 0, st, a);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------ operand packing
 // Once per probability call the low-rank factors are copied into the order
 // the sweep reads them (tlr_tables.h): the V' rows of every tile (i, j),
@@ -28,9 +111,12 @@ namespace mvn {
 // them; block p == np clears the zero tail.
 __global__ __launch_bounds__(256) void tlr_pack_v_kernel(const double* __restrict__ Vt, int m, int rs, int np,
                                                          const int* __restrict__ kk,
-                                                         const long* __restrict__ vrow0, long ksum,
-                                                         double* __restrict__ Vpack) {
+                                                         const long* __restrict__ vrow0,
+                                                         const TlrSweepHdr* __restrict__ hdr, char* dyn) {
   const int p = blockIdx.x;
+  const long ksum = hdr->ksum;
+  if (hdr->grid < 1) return;
+  double* Vpack = (double*)(dyn + hdr->vpack);
   if (p == np) {
     for (long e = (long)blockIdx.y * 256 + threadIdx.x; e < 128L * m; e += 256L * gridDim.y)
       Vpack[ksum * m + e] = 0.0;
@@ -50,7 +136,9 @@ __global__ __launch_bounds__(256) void tlr_pack_u_kernel(const double* __restric
                                                          const long* __restrict__ ucol0,
                                                          const long* __restrict__ kpad0,
                                                          const int* __restrict__ kval,
-                                                         double* __restrict__ Upack) {
+                                                         const TlrSweepHdr* __restrict__ hdr, char* dyn) {
+  if (hdr->grid < 1) return;
+  double* Upack = (double*)(dyn + hdr->upack);
   const int p = blockIdx.x;
   int i = (int)((1.0 + sqrt(1.0 + 8.0 * (double)p)) * 0.5);
   while (i * (i - 1) / 2 > p) --i;
@@ -76,10 +164,10 @@ __global__ __launch_bounds__(256) void tlr_pack_u_kernel(const double* __restric
 
 hipError_t launch_tlr_pack(const TlrPackArgs& a, hipStream_t st) {
   hipLaunchKernelGGL(tlr_pack_v_kernel, dim3(a.np + 1, 16), dim3(256), 0, st, a.Vt, a.m, a.rs, a.np, a.kk, a.vrow0,
-                     a.ksum, a.Vpack);
+                     a.hdr, a.dyn);
   if (a.np > 0)
     hipLaunchKernelGGL(tlr_pack_u_kernel, dim3(a.np, a.m / 64), dim3(256), 0, st, a.U, a.m, a.rs, a.kk, a.ucol0,
-                       a.kpad0, a.kval, a.Upack);
+                       a.kpad0, a.kval, a.hdr, a.dyn);
   return hipGetLastError();
 }
 
@@ -196,15 +284,19 @@ __global__ __launch_bounds__(256, RB == 128 ? 2 : 4) void tlr_sweep_kernel(TlrSw
   const int m = p.m;
   const long NS = (long)p.N * p.S;
   const long nchunks = (NS + kCols - 1) / kCols;
-  double* Y = p.yscr + (long)blockIdx.x * p.yslice;
-  double* Z = p.zscr + (long)blockIdx.x * p.zslice;
+  const TlrSweepHdr h = *p.hdr;
+  if ((long)blockIdx.x >= h.grid) return;  // the workspace holds h.grid workgroups
+  const double* Vpack = (const double*)(p.dyn + h.vpack);
+  const double* Upack = (const double*)(p.dyn + h.upack);
+  double* Y = (double*)(p.dyn + h.yscr) + (long)blockIdx.x * p.yslice;
+  double* Z = (double*)(p.dyn + h.zscr) + (long)blockIdx.x * h.zslice;
   char* stage0 = (char*)lds_T;
   char* stage1 = (char*)lds_T + G::kStageBytes;
 
   for (int i = 1; i < p.nt; ++i)
     for (long e = (p.kpad0[i] + p.kval[i]) * kCols + t; e < p.kpad0[i + 1] * kCols; e += 256) Z[e] = 0.0;
 
-  for (long chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x) {
+  for (long chunk = blockIdx.x; chunk < nchunks; chunk += h.grid) {
     const long col = chunk * kCols + lane;
     const bool owner = wv == 0;
     const bool valid = owner && col < NS;
@@ -216,7 +308,7 @@ __global__ __launch_bounds__(256, RB == 128 ? 2 : 4) void tlr_sweep_kernel(TlrSw
       const long g0 = (long)ti * m;
       const long kp0 = p.kpad0[ti], Kp = p.kpad0[ti + 1] - kp0;
       const int nst_lr = (int)(Kp / G::kK);
-      const double* Ui = p.Upack + kp0 * m;  // m x Kp
+      const double* Ui = Upack + kp0 * m;  // m x Kp
       const double* Zi = Z + kp0 * kCols;
       const double* D = p.tiles + ((long)ti * (ti + 1) / 2 + ti) * (long)m * m;
       for (int b0 = 0; b0 < m && g0 + b0 < p.n; b0 += RB) {
@@ -260,7 +352,7 @@ __global__ __launch_bounds__(256, RB == 128 ? 2 : 4) void tlr_sweep_kernel(TlrSw
       // ---- stacked product of tile column ti
       if (ti + 1 < p.nt) {
         const long z0 = p.zcol[ti], M = p.zcol[ti + 1] - z0;
-        const double* Vj = p.Vpack + z0 * m;
+        const double* Vj = Vpack + z0 * m;
         const double* Yj = Y + g0 * kCols;
         const long* zd = p.zdst + z0;
         long r0 = 0;

@@ -12,17 +12,26 @@ namespace mvn {
 // Lower triangle of the padded ld x ld matrix A (row-major) from the caller's
 // Sigma (row stride lds) or from locations with the Matern kernel; rows and
 // columns n..ld-1 become the identity.  Also clears *info.
-// With perm (device, n entries, a permutation checked on the host) the
-// matrix is Sigma[perm[i]][perm[j]], read from Sigma's lower triangle.
-hipError_t launch_build_matrix(int n, int ld, const double* sigma, int lds, const int64_t* perm, const double* locs,
-                               const Matern& mk, double* A, int* info, hipStream_t st);
+// With perm (device, n entries, checked by launch_index_check, whose flag is
+// perm_bad) the matrix is Sigma[perm[i]][perm[j]], read from Sigma's lower
+// triangle; a bad permutation gives the identity and *info = -1.
+hipError_t launch_build_matrix(int n, int ld, const double* sigma, int lds, const int64_t* perm, const int* perm_bad,
+                               const double* locs, const Matern& mk, double* A, int* info, hipStream_t st);
+
+// Device check of an index array: entries in [0, range) and, with `seen`
+// (range ints of scratch), no entry twice; *flag = 0 if so, else 1.
+hipError_t launch_index_check(const int64_t* idx, long count, long range, int* seen, int* flag, hipStream_t st);
+
+// Zero n 64-bit words with a kernel (not a memset node, so that a caller may
+// capture the call in a graph).
+hipError_t launch_clear_u64(unsigned long long* p, long n, hipStream_t st);
 
 // A second stream of the current device (default priority, non-blocking)
 // with three events, for work that overlaps the caller's stream inside one
 // library call.  Created on first use and kept until the process ends; each
 // slot is an independent set whose mutex serialises the callers enqueueing
 // on it.  nullptr (run everything on the caller's stream) if it cannot be
-// created, or if it does not exist yet and `st` is being captured.
+// created or `st` is being captured into a graph.
 struct SideStream {
   hipStream_t s = nullptr;
   hipEvent_t ev[3] = {};
@@ -41,11 +50,24 @@ SideStream* side_stream(int slot, hipStream_t st);
 hipError_t launch_cholesky_f64(int ld, int tile, double* A, int* info, hipStream_t st, bool lookahead = true,
                                int kstop = 0);
 
+// Device state of the adaptive precision map of the mixed factorisation:
+// two slots of ld/128 + 1 panel block norms, max diag(Sigma), and the number
+// of tile updates run in FP64 / FP32 / the reduced type.
+struct LpMap {
+  double* norms;
+  double* dmax;
+  unsigned long long* counts;
+  double tol;  // error bound per tile update relative to max diag(Sigma)
+};
+
 // The same factorisation with the trailing updates in FP32 (prec 1), BF16
 // (2) or split BF16 (3) on MFMA, followed by the low-precision operand copy
 // of L for the sweep (`low`: ld*ld floats, ld*ld BF16, or two BF16 planes).
+// map != nullptr: each tile update picks FP64, FP32 or the reduced type by
+// its rounding-error bound (adaptive precision map); nullptr: every update in
+// the reduced type.  fp64_factor: FP64 factorisation, then the copy.
 hipError_t launch_cholesky_lp(int prec, int ld, int tile, double* A, int* info, void* low,
-                              hipStream_t st);
+                              hipStream_t st, const LpMap* map, bool fp64_factor);
 
 // Monte Carlo check of nested sets: fields X = mu + L Z (dense FP64 factor),
 // per sample the first site outside [a, b] (n if none), and per prefix the
@@ -80,7 +102,8 @@ struct PosteriorArgs {
   long ld;                 // >= mpad + n + 1, a multiple of 16
   int n, m;
   long mpad;               // m rounded up to the Cholesky tile
-  const int64_t* obs;      // m site indices (device, checked on the host)
+  const int64_t* obs;      // m site indices (device)
+  const int* obs_bad;      // flag of the device check of obs (out of range: identity, *info = -1)
   const double* locs;      // n x 2
   const double* y;         // m observations
   const double* mu;        // n prior means, or nullptr
@@ -107,6 +130,7 @@ struct SweepArgs {
   int grid;                // persistent workgroups
   int rows;                // rows per sweep block: 128 (two workgroups per CU) or 64 (three)
   double* prefix;          // nullptr, or n x nchunks x 4 partials of the running products per row
+  int wide;                // FP64, 128 rows, no prefix: the 128-column sweep (yslice = ld x 128)
 };
 
 // Setup of one probability call: centred limits and the invalid-limit flag.
@@ -114,6 +138,9 @@ hipError_t launch_prob_setup(int n, int ld, const double* a, const double* b, co
                              double* at, double* bt, int* bad, hipStream_t st);
 
 hipError_t launch_sweep(const SweepArgs& a, hipStream_t st);
+// The FP64 sweep with 128 sample columns per workgroup (kernels_sov_wide.hip).
+hipError_t launch_wide_sweep(const SweepArgs& a, hipStream_t st);
+int wide_sweep_cols();
 // log P-hat of every nested set (first k sites) and its relative standard
 // error over shifts from the partials of a prefix sweep: out[2k], out[2k+1].
 hipError_t launch_prefix_reduce(const double* part, long nchunks, int n, int N, int S, double* lps,
@@ -122,7 +149,9 @@ long sweep_yslice(int prec, int ld);
 int sweep_elem_bytes(int prec);
 
 struct GradArgs {
-  const double* L;
+  const double* L;         // FP64 factor (diagonal blocks, pivots, the reverse GEMM)
+  const void* Llow;        // forward GEMM operand (== L for FP64; planes ld*ld apart for split BF16)
+  int prec;                // forward GEMM arithmetic: 0 FP64, 1 FP32, 2 BF16, 3 split BF16
   int ld;
   int n;
   const double* at;
@@ -214,7 +243,8 @@ constexpr long kTlrPairBatch = 256; // tile pairs per update launch (sizes the W
 // Lower tiles of Sigma (tile-major, m x m each, identity past n) from the
 // caller's Sigma or from locations with the Matern kernel; clears *info.
 hipError_t launch_tlr_build(int n, int m, int nt, const double* sigma, int lds, const int64_t* perm,
-                            const double* locs, const Matern& mk, double* tiles, int* info, hipStream_t st);
+                            const int* perm_bad, const double* locs, const Matern& mk, double* tiles, int* info,
+                            hipStream_t st);
 
 struct TlrCholArgs {
   double* tiles;     // nt(nt+1)/2 tiles of m x m
@@ -230,8 +260,45 @@ struct TlrCholArgs {
 };
 hipError_t launch_tlr_cholesky(const TlrCholArgs& a, hipStream_t st);
 
-// Packing of the low-rank factors for the sweep (index tables from
-// tlr_tables.h, on the device).
+// Layout of the rank-dependent part of a TLR probability workspace,
+// computed on the device from the factor's ranks (no read-back): byte
+// offsets from the start of that part, and how many persistent sweep
+// workgroups its size holds.
+struct TlrSweepHdr {
+  long ksum;     // stacked V' rows (sum of the ranks)
+  long kpad;     // packed K of all tile-rows (Z rows)
+  long vpack;    // (ksum + 128) x m doubles
+  long upack;    // m x kpad doubles
+  long yscr;     // grid x yslice doubles
+  long zscr;     // grid x zslice doubles
+  long zslice;   // kpad x 64
+  long grid;     // workgroups that fit (0: not even one; the call's outputs are NaN)
+};
+
+// Index tables of the sweep (the layout of tlr_tables.h) and the header,
+// from the ranks, by one workgroup.  dyn_bytes: size of the rank-dependent
+// region; grid_max: the launch grid of the sweep; yslice: doubles of a
+// workgroup's Y slice.  Sets *bad = 0 when no workgroup fits.
+struct TlrTableArgs {
+  const int* ranks;     // nt (nt - 1) / 2
+  int nt, rs, m;
+  long yslice;
+  long grid_max;
+  size_t dyn_bytes;
+  int* kk;              // per pair: rank used (|rank| clipped to rs)
+  long* zcol;           // nt + 1
+  long* kpad0;          // nt + 1
+  int* kval;            // nt
+  long* vrow0;          // per pair
+  long* ucol0;          // per pair
+  long* zdst;           // np * rs (the first ksum entries are used)
+  TlrSweepHdr* hdr;
+  int* bad;
+};
+hipError_t launch_tlr_tables(const TlrTableArgs& a, hipStream_t st);
+
+// Packing of the low-rank factors for the sweep (into the rank-dependent
+// region `dyn` at the header's offsets).
 struct TlrPackArgs {
   const double* U;      // factor: per pair m x rs
   const double* Vt;     // factor: per pair rs x m
@@ -241,16 +308,15 @@ struct TlrPackArgs {
   const long* ucol0;    // per pair: first packed column within its tile-row
   const long* kpad0;    // nt + 1
   const int* kval;      // nt
-  long ksum;
-  double* Vpack;        // (ksum + 128) x m
-  double* Upack;        // m x kpad0[nt], tile-row i at m * kpad0[i]
+  const TlrSweepHdr* hdr;
+  char* dyn;
 };
 hipError_t launch_tlr_pack(const TlrPackArgs& a, hipStream_t st);
 
 struct TlrSweepArgs {
   const double* tiles;  // factor tiles (the dense diagonal tiles are read)
-  const double* Vpack;
-  const double* Upack;
+  const TlrSweepHdr* hdr;  // Vpack, Upack, Y and Z scratch at its offsets from dyn
+  char* dyn;
   const long* zcol;     // nt + 1: first stacked V' row of tile column j
   const long* kpad0;    // nt + 1: first packed K index (Z row) of tile-row i
   const int* kval;      // nt: K_i, rows [K_i, Kpad_i) of tile-row i are padding
@@ -261,12 +327,9 @@ struct TlrSweepArgs {
   const uint64_t* lattice;
   uint64_t seed;
   int N, S, periodize;
-  double* yscr;     // grid x (nt m) x 64
-  long yslice;
-  double* zscr;     // grid x kpad0[nt] x 64
-  long zslice;
+  long yslice;      // (nt m) x 64
   double* ell;
-  int grid;
+  int grid;         // launch grid (workgroups past hdr->grid leave at once)
   int rows;         // rows per sweep block: 128 (two workgroups per CU) or 64 (four)
   double* prefix;   // nullptr, or n x nchunks x 4 partials of the running products per row
 };

@@ -106,3 +106,75 @@ def test_autograd_function_backward():
     assert torch.allclose(ta.grad, 2.0 * r["da"]) and torch.allclose(tb.grad, 2.0 * r["db"])
     assert torch.allclose(tm.grad, 2.0 * r["dmu"])
     assert abs(lp.item() - r["logP"].item()) == 0.0
+
+
+@pytest.mark.parametrize("n", [3, 4, 6, 8])
+def test_gradient_against_closed_form_dP_db_small_n(n):
+    """The differentiation workload's first n sites (a = mu - 3, b = mu + u):
+    dP/db_i = P-hat * d log P-hat / d b_i from the adjoint sweep against the
+    closed form phi((b_i - mu_i)/sigma_i)/sigma_i * P(conditional box), the
+    conditional probability by exact quadrature at n = 3 and SciPy's
+    Genz-Bretz integration above, within the QMC error; and every d/db_i
+    against a central finite difference of the GPU's own log P-hat
+    (h = 1e-5), 1e-5 relative."""
+    from gradref import dP_db
+    w = workloads.make_workload("grad4096")
+    idx = np.arange(n)
+    locs, a, b, mu = w.locs[idx], w.a[idx].copy(), w.b[idx].copy(), w.mu[idx].copy()
+    kern = (w.sigma2, w.beta, w.nu, w.nugget)
+    sig = oracle.covariance(locs, *kern)
+    N, S, seed = 20000, 10, w.seed
+    print(f"closed form n={n}", flush=True)
+    f = mvn.mvn_cholesky(n, locs=locs, kern=kern, opts=mvn.options(tile=16))
+    r = mvn.mvn_prob_grad(f, a, b, mu, N=N, S=S, seed=seed)
+    torch.cuda.synchronize()
+    P = r["P"].item()
+    gb = r["db"].cpu().numpy()
+    for i in range(n):
+        exact = dP_db(sig, mu, a, b, i)
+        got = P * gb[i]
+        print(f"  i={i}: GPU {got:.8e} closed form {exact:.8e}", flush=True)
+        # the QMC error of the derivative at N S = 200 000 (from the oracle on
+        # the same points: at most 0.7% relative or 5e-5 absolute where the
+        # conditional box probability is tiny)
+        assert abs(got - exact) <= 1e-2 * abs(exact) + 2e-4, (i, got, exact)
+
+    def logp(bb):
+        q = mvn.mvn_prob(f, a, bb, mu, N=N, S=S, seed=seed)
+        torch.cuda.synchronize()
+        return q["logP"].item()
+    h = 1e-5
+    for i in range(n):
+        e = np.zeros(n)
+        e[i] = h
+        fd = (logp(b + e) - logp(b - e)) / (2 * h)
+        assert gb[i] == pytest.approx(fd, rel=1e-5, abs=1e-9)
+
+
+@pytest.mark.parametrize("prec,bound", [(mvn.MVN_FP32, 1e-4), (mvn.MVN_BF16X3, 1e-3), (mvn.MVN_BF16, 0.3)])
+def test_mixed_precision_adjoint_error_statement(prec, bound):
+    """The adjoint with the forward GEMM in a reduced type (factor in FP64,
+    the type's operand copy for the sweep; reverse GEMM and conditioning in
+    FP64): log P-hat and the directional derivative along random directions
+    against the oracle's FP64 tangent sweep on identical points.  The bars
+    state the error of each type (relative, measured well below them); they
+    are not parity."""
+    locs, a, b, mu, kern, seed = _case(300, seed=3)
+    n, N, S = 300, 800, 2
+    o = mvn.options(tile=64, precision=prec, chol_mode=mvn.MVN_CHOL_FP64)
+    f = mvn.mvn_cholesky(n, locs=locs, kern=kern, opts=o)
+    r = mvn.mvn_prob_grad(f, a, b, mu, N=N, S=S, seed=seed, opts=o)
+    torch.cuda.synchronize()
+    L = oracle.cholesky(oracle.covariance(locs, *kern))
+    at, bt = oracle.centre(a, b, mu)
+    rng = np.random.default_rng(8)
+    da, db = r["da"].cpu().numpy(), r["db"].cpu().numpy()
+    for _ in range(2):
+        va, vb = rng.standard_normal(n), rng.standard_normal(n)
+        logp, dd = ograd.logp_directional(L, at, bt, va, vb, N, S, seed)
+        got = float(da @ va + db @ vb)
+        rel = abs(got - dd) / abs(dd)
+        print(f"precision {prec}: log P {r['logP'].item():.10f} (oracle {logp:.10f}), directional {got:.8e} "
+              f"(oracle {dd:.8e}), rel {rel:.2e}", flush=True)
+        assert rel < bound
+        assert abs(r["logP"].item() - logp) < bound * abs(logp)

@@ -33,12 +33,16 @@ def cases():
     return out
 
 
+MODES = [mvn.MVN_CHOL_ADAPTIVE, mvn.MVN_CHOL_UNIFORM, mvn.MVN_CHOL_FP64]
+
+
+@pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("prec", [mvn.MVN_FP32, mvn.MVN_BF16, mvn.MVN_BF16X3])
-def test_mixed_precision_probability_within_1e4(cases, prec):
+def test_mixed_precision_probability_within_1e4(cases, prec, mode):
     for locs, a, b, kern, L, N, S, seed, ell, ref in cases:
         n = len(a)
-        print(f"prec {prec} n={n} P={ref['P']:.4g}", flush=True)
-        o = mvn.options(tile=64, precision=prec)
+        print(f"prec {prec} chol_mode {mode} n={n} P={ref['P']:.4g}", flush=True)
+        o = mvn.options(tile=64, precision=prec, chol_mode=mode)
         f = mvn.mvn_cholesky(n, locs=locs, kern=kern, opts=o)
         r = mvn.mvn_prob(f, a, b, None, N=N, S=S, seed=seed, opts=o, return_ell=True)
         torch.cuda.synchronize()
@@ -57,10 +61,37 @@ def test_mixed_factor_keeps_fp64_factor_accuracy_bounds(cases):
     locs, a, b, kern, L, *_ = cases[1]
     n = len(a)
     for prec, bound in ((mvn.MVN_FP32, 5e-6), (mvn.MVN_BF16X3, 1e-4), (mvn.MVN_BF16, 3e-2)):
-        f = mvn.mvn_cholesky(n, locs=locs, kern=kern, opts=mvn.options(tile=64, precision=prec))
-        torch.cuda.synchronize()
-        assert f.info() == 0
-        assert np.max(np.abs(f.L().cpu().numpy() - L)) < bound, prec
+        for mode in MODES:
+            f = mvn.mvn_cholesky(n, locs=locs, kern=kern, opts=mvn.options(tile=64, precision=prec, chol_mode=mode))
+            torch.cuda.synchronize()
+            assert f.info() == 0
+            err = np.max(np.abs(f.L().cpu().numpy() - L))
+            print(f"prec {prec} chol_mode {mode}: max |L - L_oracle| {err:.3e}, {f.update_counts()}", flush=True)
+            assert err < (1e-10 if mode == mvn.MVN_CHOL_FP64 else bound), (prec, mode)
+
+
+def test_adaptive_map_picks_reduced_type_for_far_tiles_only():
+    """Two clusters of sites far apart (covariance between them about
+    1e-304): an update of a tile whose rows lie in the other cluster than the
+    panel's has a panel block of norm about 1e-304 and runs in the reduced
+    type, while tiles inside the panel's cluster stay FP64 or FP32; the
+    cross-cluster block of the factor stays negligible and the factor is
+    within 1e-5 of the oracle's."""
+    rng = np.random.default_rng(5)
+    m = 320
+    locs = np.concatenate([rng.uniform(0, 0.2, (m, 2)), rng.uniform(0, 0.2, (m, 2)) + 50.0])
+    kern = (1.0, 0.1, 0.5, 1e-6)
+    L = oracle.cholesky(oracle.covariance(locs, *kern))
+    f = mvn.mvn_cholesky(2 * m, locs=locs, kern=kern,
+                         opts=mvn.options(tile=64, precision=mvn.MVN_BF16, chol_mode=mvn.MVN_CHOL_ADAPTIVE))
+    torch.cuda.synchronize()
+    assert f.info() == 0
+    c = f.update_counts()
+    print("update counts", c, flush=True)
+    assert c["reduced"] > 0 and c["fp64"] > 0
+    Lg = f.L().cpu().numpy()
+    assert np.max(np.abs(Lg[m:, :m])) < 1e-250
+    assert np.max(np.abs(Lg - L)) < 1e-5
 
 
 def test_fp64_sweep_on_a_mixed_factor_is_rejected_only_for_other_precisions(cases):

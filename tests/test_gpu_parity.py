@@ -111,6 +111,33 @@ def test_prob_full_dense400_workload(rows):
     assert np.max(np.abs(r["ell"].cpu().numpy() - ell_ref)) < 1e-9
 
 
+@pytest.mark.parametrize("n,N,S", [(257, 57341, 2), (300, 33000, 4), (300, 150, 1), (520, 1000, 7)])
+def test_prob_wide_sweep_pass_shapes(n, N, S):
+    """The FP64 sweeps' column distributions.  With at least 65536 samples
+    the 128-column sweep runs: N*S = 114682 gives every workgroup seven
+    32-column slices (a 128-column pass, a 64-column pass and a 32-column
+    pass, the last slice ragged), 132000 gives 8 or 9; 150 and 7000 samples
+    take the 64-column sweep.  n = 257 leaves a one-row last block.  Sampled
+    columns of every workgroup against the oracle, 1e-9."""
+    w = workloads.make_workload("grad4096")
+    idx = np.arange(n)
+    locs = w.locs[idx]
+    kern = (w.sigma2, w.beta, w.nu, w.nugget)
+    print(f"wide sweep n={n} N={N} S={S}", flush=True)
+    f = mvn.mvn_cholesky(n, locs=locs, kern=kern, opts=mvn.options(tile=64), device=DEV)
+    r = mvn.mvn_prob(f, w.a[idx], w.b[idx], w.mu[idx], N=N, S=S, seed=w.seed, opts=mvn.options(tile=64),
+                     return_ell=True)
+    torch.cuda.synchronize()
+    L = oracle.cholesky(oracle.covariance(locs, *kern))
+    at, bt = oracle.centre(w.a[idx], w.b[idx], w.mu[idx])
+    NS = N * S
+    cols = np.unique(np.concatenate([np.arange(0, NS, 13), np.arange(max(0, NS - 70), NS)]))
+    ell_ref = oracle.sweep(L, at, bt, N, S, w.seed, cols=cols)
+    ell = r["ell"].cpu().numpy()
+    assert np.max(np.abs(ell[cols] - ell_ref)) < 1e-9
+    assert np.all(np.isfinite(ell))
+
+
 def test_prob_finite_limits_with_mean_and_periodize():
     """Finite two-sided limits, a mean vector, nu = 3/2, the baker's transform."""
     w = workloads.make_workload("grad4096")

@@ -100,14 +100,18 @@ def test_posterior_confidence_region_matches_oracle():
 
 
 def test_rejections():
+    """Host-checked arguments return their position; the device index arrays
+    (observed sites, site permutation) are checked on the device: a bad entry
+    gives info = -1 and NaN outputs, with nothing read back by the call."""
     n, m = 50, 5
     locs, kern, obs, y, mu, noise = _problem(10, n, m, seed=1)
     o = mvn.options(tile=64)
-    bad = obs.copy()
-    bad[0] = n
-    with pytest.raises(mvn.MvnError) as e:
-        mvn.mvn_posterior(locs, kern, bad, y, noise, opts=o, device=DEV)
-    assert e.value.code == -5
+    for badval in (n, -1):
+        bad = obs.copy()
+        bad[0] = badval
+        post = mvn.mvn_posterior(locs, kern, bad, y, noise, opts=o, device=DEV)
+        assert post["info"] == -1
+        assert torch.all(torch.isnan(post["mu_post"])) and torch.all(torch.isnan(post["var_post"]))
     with pytest.raises(mvn.MvnError) as e:
         mvn.mvn_posterior(locs, kern, obs, y, 0.0, opts=o, device=DEV)
     assert e.value.code == -8
@@ -115,8 +119,17 @@ def test_rejections():
         mvn.mvn_posterior(locs, kern, obs, y, noise, opts=mvn.options(tile=64, precision=mvn.MVN_FP32), device=DEV)
     assert e.value.code == -9
     post = mvn.mvn_posterior(locs, kern, obs, y, noise, opts=o, device=DEV)
-    perm = np.arange(n)
-    perm[3] = 4
-    with pytest.raises(mvn.MvnError) as e:
-        mvn.mvn_cholesky_permuted(post["sigma_post"], perm, opts=o)
-    assert e.value.code == -4
+    assert post["info"] == 0
+    for tlr in (False, True):
+        oo = mvn.options(tile=128, tlr_eps=1e-6, max_rank=64) if tlr else o
+        for broken in ("repeat", "range"):
+            perm = np.arange(n)
+            perm[3] = 4 if broken == "repeat" else n + 7
+            f = mvn.mvn_cholesky_permuted(post["sigma_post"], perm, opts=oo)
+            torch.cuda.synchronize()
+            assert f.info() == -1, (tlr, broken)
+            r = mvn.mvn_prob(f, np.full(n, -np.inf), np.zeros(n), N=64, S=1, seed=1, opts=oo)
+            assert torch.isnan(r["logP"])
+        f = mvn.mvn_cholesky_permuted(post["sigma_post"], np.arange(n)[::-1].copy(), opts=oo)
+        torch.cuda.synchronize()
+        assert f.info() == 0

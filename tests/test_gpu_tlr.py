@@ -209,3 +209,49 @@ def test_tlr_factor_rejected_where_unsupported():
     assert e.value.code == -8
     with pytest.raises(mvn.MvnError):
         f.L()
+
+
+def test_tlr_sweep_graph_capture_replays_match_eager():
+    """A TLR probability call reads nothing back (its index tables and the
+    layout of its workspace are built on the device from the ranks), so it can
+    be captured in a graph: every replay, with eager work in between, equals
+    the eager result bit for bit; a workspace too small for one sweep
+    workgroup once the ranks are known gives NaN outputs, not a fault."""
+    locs, kern, a, b = _tlr_inputs(32, 900)
+    f = _factor(900, locs, kern, 256, 1e-5, 64)
+    opts = mvn.options(tile=256, tlr_eps=1e-5, max_rank=64)
+    N, S = 500, 3
+    wsb = mvn.mvn_prob_workspace_bytes_factor(f, N, S, opts)
+    ws = torch.empty(wsb, dtype=torch.uint8, device=DEV)
+    ta, tb = torch.as_tensor(a, device=DEV), torch.as_tensor(b, device=DEV)
+    r = mvn.mvn_prob(f, ta, tb, None, N=N, S=S, seed=5, opts=opts, workspace=ws)
+    torch.cuda.synchronize()
+    eager = r["out"].clone()
+    assert torch.isfinite(eager[0])
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            rg = mvn.mvn_prob(f, ta, tb, None, N=N, S=S, seed=5, opts=opts, workspace=ws)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        rg["out"].fill_(0.0)
+        junk = torch.randn(1 << 20, device=DEV).sum()  # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(rg["out"], eager), rep
+        del junk
+    # the fixed part of the workspace plus a rank-dependent region too small
+    # for the packed factors and one workgroup: accepted on the host (the
+    # ranks are not read back), NaN on the device
+    fixed = mvn.mvn_prob_workspace_bytes_factor(f, 64, 1, opts)
+    small = torch.empty(fixed // 2 + (1 << 20), dtype=torch.uint8, device=DEV)
+    try:
+        q = mvn.mvn_prob(f, ta, tb, None, N=64, S=1, seed=5, opts=opts, workspace=small)
+        torch.cuda.synchronize()
+        assert torch.isnan(q["out"][0])
+    except mvn.MvnError as e:
+        assert e.code == -10

@@ -86,3 +86,68 @@ def test_bivariate_closed_form_dP_db():
     cond = sp.ndtr((b[1] - m) / sc) - sp.ndtr((a[1] - m) / sc)
     exact = st.norm.pdf(b[0] / s1) / s1 * cond
     assert dP == pytest.approx(exact, rel=5e-3)
+
+
+def _box_problem(n, seed):
+    rng = np.random.default_rng(seed)
+    sig = oracle.covariance(rng.uniform(size=(n, 2)), 1.0, 0.3, 1.5, 1e-6)
+    mu = rng.normal(0.0, 0.3, n)
+    a = mu - rng.uniform(0.5, 2.5, n)
+    b = mu + rng.uniform(0.2, 2.0, n)
+    return sig, mu, a, b
+
+
+def _dP_db_estimate(L, at, bt, i, N, S, seed):
+    """dP/db_i from the oracle's tangent sweep, with its standard error over
+    the S shifts."""
+    n = L.shape[0]
+    e = np.zeros(n)
+    e[i] = 1.0
+    ell, dell = grad.tangent_sweep(L, at, bt, np.zeros(n), e, N, S, seed)
+    p = np.exp(ell).reshape(S, N)
+    dp = (np.exp(ell) * dell).reshape(S, N).mean(axis=1)
+    return dp.mean(), dp.std(ddof=1) / math.sqrt(S), p.mean()
+
+
+def test_closed_form_box2_quadrature_matches_scipy():
+    """The quadrature helper against SciPy's bivariate normal CDF."""
+    from gradref import box2_quad
+    m = np.array([0.3, -0.2])
+    C = np.array([[1.1, 0.5], [0.5, 0.7]])
+    a, b = np.array([-0.9, -1.3]), np.array([1.2, 0.4])
+    ref = st.multivariate_normal.cdf(b, mean=m, cov=C, lower_limit=a, abseps=1e-12, releps=1e-12)
+    assert box2_quad(m, C, a, b) == pytest.approx(ref, abs=1e-9)
+
+
+def test_closed_form_dP_db_exact_at_n3():
+    """n = 3: the oracle's derivative of the estimator (tangent sweep times
+    P-hat) equals the closed form phi/sigma * P(bivariate conditional box),
+    the latter by exact quadrature, for every coordinate, within the QMC
+    error of N S = 200 000 samples."""
+    from gradref import dP_db
+    sig, mu, a, b = _box_problem(3, seed=11)
+    L = oracle.cholesky(sig)
+    at, bt = oracle.centre(a, b, mu)
+    N, S, seed = 20000, 10, 5
+    for i in range(3):
+        est, se, _ = _dP_db_estimate(L, at, bt, i, N, S, seed)
+        exact = dP_db(sig, mu, a, b, i)
+        assert abs(est - exact) <= max(5 * se, 2e-4 * abs(exact)), (i, est, exact, se)
+        assert est == pytest.approx(exact, rel=2e-3)
+
+
+@pytest.mark.parametrize("n", [4, 5, 6, 7, 8])
+def test_closed_form_dP_db_statistical_n4_to_8(n):
+    """n = 4..8: the oracle's dP/db_i within five standard errors (over the
+    shifts) of the closed form with the conditional probability from SciPy's
+    Genz-Bretz integration (absolute error 1e-9 requested)."""
+    from gradref import dP_db
+    sig, mu, a, b = _box_problem(n, seed=20 + n)
+    L = oracle.cholesky(sig)
+    at, bt = oracle.centre(a, b, mu)
+    N, S, seed = 4000, 10, 7 + n
+    for i in (0, n // 2, n - 1):
+        est, se, _ = _dP_db_estimate(L, at, bt, i, N, S, seed)
+        exact = dP_db(sig, mu, a, b, i)
+        assert abs(est - exact) <= 5 * se + 1e-6, (n, i, est, exact, se)
+
