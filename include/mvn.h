@@ -211,6 +211,27 @@ int mvn_prob(const mvn_factor* f, const double* d_a, const double* d_b, const do
 int mvn_prob_workspace_bytes_factor(const mvn_factor* f, int N, int S, const mvn_options* opts,
                                     size_t* bytes, hipStream_t stream);
 
+/* mvn_prob for callers that cannot allocate device memory (code under
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same estimator, arguments and outputs as mvn_prob, with the
+ * workspace taken from a 256 MiB device array inside the library instead of
+ * a caller buffer.  Each GPU the library runs on holds its own copy of the
+ * array until the process ends; the first call on a device looks up its
+ * address and copies the QMC lattice table into it (a synchronous copy), and
+ * later calls only enqueue kernels.  Nothing is allocated.
+ *   Dense factors only (any precision the factor holds), n <= 131072.  The
+ *   sweep runs as many persistent workgroups as the array holds (fewer than
+ *   mvn_prob for large n: slower, same result); a problem whose single
+ *   workgroup does not fit (about n * (1 KiB + 24 B) + 8 N S bytes with
+ *   d_ell == NULL) is rejected with -5.
+ *   Every call on one GPU shares that GPU's array: calls that overlap on one
+ *   GPU (different streams, or threads) race and must be serialised by the
+ *   caller.  Each call writes every scratch entry it reads, so no clearing
+ *   is needed between calls. */
+int mvn_prob_static(const mvn_factor* f, const double* d_a, const double* d_b, const double* d_mu,
+                    int N, int S, uint64_t seed, const mvn_options* opts, double* d_out,
+                    double* d_ell, hipStream_t stream);
+
 /* Nested-set probabilities of confidence-region detection (Section III-C with
  * Algorithm 1 of Section IV-A), for the sites in the factor's order (the caller orders them,
  * e.g. by decreasing marginal exceedance probability, before building the

@@ -17,7 +17,7 @@ from ._lib import (MVN_BF16, MVN_BF16X3, MVN_CHOL_ADAPTIVE, MVN_CHOL_FP64, MVN_C
                    MVN_FACTOR_TLR, MVN_FP32, MVN_FP64, MvnError, MvnFactor, MvnMatern, MvnOptions, options)
 
 __all__ = ["mvn_factor_bytes", "mvn_cholesky_workspace_bytes", "mvn_prob_workspace_bytes",
-           "mvn_prob_workspace_bytes_factor", "mvn_cholesky", "mvn_prob", "Factor",
+           "mvn_prob_workspace_bytes_factor", "mvn_cholesky", "mvn_prob", "mvn_prob_static", "Factor",
            "mvn_prob_prefix_workspace_bytes", "mvn_prob_prefix", "confidence_region",
            "mvn_mc_prefix_workspace_bytes", "mvn_mc_prefix", "mvn_cholesky_permuted", "mvn_posterior",
            "posterior_confidence_region",
@@ -272,6 +272,28 @@ def mvn_prob(f: Factor, a, b, mu=None, N: int = 1000, S: int = 10, seed: int = 1
     _lib.check(code)
     res = {"logP": out[0], "P": out[1], "stderr": out[2], "rel_stderr": out[3], "logP_s": out[4:],
            "out": out, "_keep": (ta, tb, tm, workspace)}
+    if return_ell:
+        res["ell"] = ell
+    return res
+
+
+def mvn_prob_static(f: Factor, a, b, mu=None, N: int = 1000, S: int = 10, seed: int = 1,
+                    opts: MvnOptions | None = None, return_ell: bool = False):
+    """mvn_prob with the workspace inside the library (no device allocation
+    by the library; the outputs are still the caller's tensors).  Same
+    results as mvn_prob."""
+    torch = _torch()
+    opts = opts or options()
+    dev = f.device
+    ta, tb = _dev_f64(a, dev), _dev_f64(b, dev)
+    tm = _dev_f64(mu, dev) if mu is not None else None
+    out = torch.empty(4 + S, dtype=torch.float64, device=dev)
+    ell = torch.empty(N * S, dtype=torch.float64, device=dev) if return_ell else None
+    code = _lib.lib().mvn_prob_static(ctypes.byref(f.handle), _ptr(ta), _ptr(tb), _ptr(tm), N, S,
+                                      ctypes.c_uint64(seed), ctypes.byref(opts), _ptr(out), _ptr(ell), _stream(dev))
+    _lib.check(code)
+    res = {"logP": out[0], "P": out[1], "stderr": out[2], "rel_stderr": out[3], "logP_s": out[4:],
+           "out": out, "_keep": (ta, tb, tm)}
     if return_ell:
         res["ell"] = ell
     return res

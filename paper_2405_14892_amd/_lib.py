@@ -71,6 +71,8 @@ SIGNATURES = {
                              c_void_p, c_size_t, c_void_p, c_size_t, POINTER(MvnFactor), c_void_p]),
     "mvn_prob": (c_int, [POINTER(MvnFactor), c_void_p, c_void_p, c_void_p, c_int, c_int, c_uint64,
                          POINTER(MvnOptions), c_void_p, c_size_t, c_void_p, c_void_p, c_void_p]),
+    "mvn_prob_static": (c_int, [POINTER(MvnFactor), c_void_p, c_void_p, c_void_p, c_int, c_int, c_uint64,
+                                POINTER(MvnOptions), c_void_p, c_void_p, c_void_p]),
     "mvn_prob_grad_workspace_bytes": (c_int, [c_int, c_int, c_int, POINTER(MvnOptions), POINTER(c_size_t)]),
     "mvn_prob_grad": (c_int, [POINTER(MvnFactor), c_void_p, c_void_p, c_void_p, c_int, c_int, c_uint64,
                               POINTER(MvnOptions), c_void_p, c_size_t, c_void_p, c_void_p, c_void_p,

@@ -1041,6 +1041,105 @@ int mvn_prob(const mvn_factor* f, const double* d_a, const double* d_b, const do
   return dense_sweep(f, d_a, d_b, d_mu, N, S, seed, opts, ws, Lay, d_ell, nullptr, d_out, stream);
 }
 
+// ---------------------------------------------------------------- no-allocation variant
+}  // extern "C"
+
+namespace {
+
+// The device memory of mvn_prob_static: one file-scope array per GPU, held
+// until the process ends.  In host code `scratch` names a host-side stand-in;
+// its device address comes from hipGetSymbolAddress, once per device.
+constexpr size_t kStaticBytes = (size_t)256 << 20;
+constexpr int kStaticMaxN = 1 << 17;  // lattice entries kept at the front of scratch
+constexpr size_t kStaticLat = (size_t)kStaticMaxN * sizeof(uint64_t);
+static __device__ __align__(256) unsigned char scratch[kStaticBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+unsigned char* g_static_ptr[kMaxDevices] = {};
+
+// Host copy of the lattice table for kStaticMaxN dimensions, built once in
+// static storage (no allocation): the sieve runs over a fixed bound above
+// p_131072 = 1742537.
+constexpr size_t kStaticSieve = 1800000;
+uint8_t g_static_comp[kStaticSieve];
+uint64_t g_static_lat[kStaticMaxN];
+bool g_static_lat_ready = false;
+
+bool static_lattice_build() {
+  int cnt = 0;
+  for (size_t v = 2; v < kStaticSieve && cnt < kStaticMaxN; ++v) {
+    if (g_static_comp[v]) continue;
+    g_static_lat[cnt++] = frac_sqrt_2p64(v);
+    for (size_t m = v * v; m < kStaticSieve; m += v) g_static_comp[m] = 1;
+  }
+  return cnt == kStaticMaxN;
+}
+
+// Device address of this device's scratch (set up on the first call on the
+// device: symbol address, then the lattice table copied to its front).
+int static_scratch(unsigned char** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(-1, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_static_mu);
+  if (!g_static_ptr[dev]) {
+    if (!g_static_lat_ready) {
+      if (!static_lattice_build()) return fail(-1, "could not build the lattice table");
+      g_static_lat_ready = true;
+    }
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    e = hipMemcpy(ptr, g_static_lat, kStaticLat, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "lattice copy to scratch");
+    g_static_ptr[dev] = (unsigned char*)ptr;
+  }
+  *out = g_static_ptr[dev];
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mvn_prob_static(const mvn_factor* f, const double* d_a, const double* d_b, const double* d_mu, int N, int S,
+                    uint64_t seed, const mvn_options* opts, double* d_out, double* d_ell, hipStream_t stream) {
+  if (!f || !f->L || !f->info || f->n < 1) return fail(-1, "invalid factor handle");
+  if (f->flags & MVN_FACTOR_TLR) return fail(-1, "mvn_prob_static takes dense factors");
+  if (f->ld != padded(f->n)) return fail(-1, "invalid factor handle");
+  if (f->n > kStaticMaxN) return fail(-1, "n = %d exceeds the static limit %d", f->n, kStaticMaxN);
+  if (!d_a) return fail(-2, "lower limits are NULL");
+  if (!d_b) return fail(-3, "upper limits are NULL");
+  if (N < 1) return fail(-5, "N must be >= 1 (got %d)", N);
+  if (S < 1) return fail(-6, "S must be >= 1 (got %d)", S);
+  if ((long)N * S > (long)INT32_MAX * 64) return fail(-5, "N*S too large");
+  if (!opts) return fail(-8, "options are required");
+  const int prec = opts->precision;
+  if (!prec_ok(prec)) return fail(-8, "unknown precision %d", prec);
+  if (prec != MVN_FP64 && (prec != f->precision || !f->L_low))
+    return fail(-8, "the factor holds no operand copy for precision %d (built with %d)", prec, f->precision);
+  if (!sweep_rows_ok(opts)) return fail(-8, "sweep_rows must be 0, 64 or 128 (got %d)", opts->sweep_rows);
+  if (!d_out) return fail(-9, "output is NULL");
+  const int rows = sweep_rows(opts);
+  const bool wide = use_wide(prec, rows, false, (long)N * S);
+  // as many persistent workgroups as the scratch holds
+  const ProbLayout one = prob_layout_ld(padded(f->n), N, S, prec, 0, rows, wide, 1);
+  const size_t per = align_up((size_t)mvn::sweep_elem_bytes(prec) * (size_t)one.yslice);
+  const size_t avail = kStaticBytes - kStaticLat;
+  if (one.total > avail)
+    return fail(-5, "problem needs %zu bytes of scratch, the static limit is %zu (n = %d, N*S = %ld)", one.total,
+                avail, f->n, (long)N * S);
+  const int gcap = (int)std::min<size_t>((avail - one.total) / per + 1, (size_t)INT32_MAX);
+  const ProbLayout Lay = prob_layout_ld(padded(f->n), N, S, prec, 0, rows, wide, gcap);
+  unsigned char* base = nullptr;
+  const int rc = static_scratch(&base);
+  if (rc) return rc;
+  return dense_sweep(f, d_a, d_b, d_mu, N, S, seed, opts, base + kStaticLat, Lay, d_ell, nullptr, d_out, stream,
+                     (const uint64_t*)base);
+}
+
 int mvn_prob_grad(const mvn_factor* f, const double* d_a, const double* d_b, const double* d_mu,
                   int N, int S, uint64_t seed, const mvn_options* opts, void* ws, size_t ws_bytes,
                   double* d_out, double* d_da, double* d_db, double* d_dmu, hipStream_t stream) {
