@@ -46,13 +46,13 @@ METRIC = "MVN probs/sec + effective TFLOP/s (Cholesky+SOV) at stated error vs FP
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0, "bf16x3": 2500.0}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3}
 
-# HBM bytes per sweep launch on the 16384-site FP64 workload from rocprofv3
-# FETCH_SIZE x2 + WRITE_SIZE x1 (factors from a 1 GiB copy; the summary is
-# profiles/sweep_kernel_f64_prec16k.md), valid only for the kernel sources
-# they were measured on (checked by hash).
-TRAFFIC_SOURCES = ["paper_2405_14892_amd/csrc/kernels_sov.hip", "paper_2405_14892_amd/csrc/mvn_device.h",
-                   "paper_2405_14892_amd/csrc/sweep_gemm.h", "paper_2405_14892_amd/csrc/sweep_block.h"]
-TRAFFIC_MEASURED = {"prec16k": ("3402d69b9e7f593f", 4.3031e12)}
+# HBM bytes per sweep launch on the 65536-site dense FP64 workload from
+# rocprofv3 FETCH_SIZE x2 + WRITE_SIZE x1 (factors from a 1 GiB copy; the
+# summary is profiles/sweep_kernel_f64_dense64k.md), valid only for the
+# kernel sources they were measured on (checked by hash).
+TRAFFIC_SOURCES = ["paper_2405_14892_amd/csrc/kernels_sov_wide.hip", "paper_2405_14892_amd/csrc/mvn_device.h",
+                   "paper_2405_14892_amd/csrc/sweep_block.h", "paper_2405_14892_amd/csrc/gemm_f64.h"]
+TRAFFIC_MEASURED = {"tlr64k": ("3c6ca3c1befe5288", 3.0042e13)}
 
 
 def _traffic(workload: str):
@@ -634,7 +634,9 @@ def main() -> int:
     chol_flops, sov_flops = _flops(n, N * S)
     sweep_tf = sov_flops / (r["sov_ms"] * 1e-3) / 1e12
     peak = PEAK_TFLOPS["fp64" if tlr else args.precision]
+    wide = not tlr and args.precision == "fp64" and N * S >= 65536
     kernel = ("tlr_sweep_kernel (TLR SOV update + conditioning)" if tlr else
+              "wide_sweep_kernel (128-column FP64 SOV GEMM + conditioning)" if wide else
               "sweep_kernel (SOV GEMM + conditioning)")
     line = {
         "metric": METRIC,
@@ -659,7 +661,7 @@ def main() -> int:
         "result": {"logP": r["logP"], "P": r["P"], "rel_stderr": r["rel_stderr"], "info": r["info"]},
         "roofline": {"bound": "mfma", "kernel": kernel, "achieved": sweep_tf, "peak": peak, "unit": "TFLOP/s",
                      "frac": sweep_tf / peak,
-                     "traffic": None if (tlr or args.precision != "fp64") else _traffic(args.workload),
+                     "traffic": _traffic(args.workload) if wide else None,
                      "algorithmic_flops_per_launch": sov_flops,
                      "note": "achieved = n(n-1)*N*S dense-equivalent flops / event time of the mvn_prob call"},
     }
