@@ -340,12 +340,12 @@ def variant_batch(dev) -> dict:
         sov_f = float(np.sum(bw.n_p.astype(np.float64) * (bw.n_p - 1))) * NS
         res_c = {}
         for name in ("fp32", "bf16", "bf16x3", "fp64"):
-            if not excursion and name in ("fp32", "bf16"):
+            if not excursion and name != "fp64":
                 tuned = autotune.tune_batch(sizes, idx, locs, kern, a, b, N=bw.N, S=bw.S, seed=bw.seed,
                                             precision=PRECISIONS[name], device=dev)
                 rows, tune_s = tuned["sweep_rows"], tuned["batch_s"]
             elif not excursion:
-                rows, tune_s = 64, None  # (both measured fastest with 64-row blocks)
+                rows, tune_s = 64, None  # (FP64 runs the four-wave sweep with 64-row blocks only)
             else:
                 rows, tune_s = out["b=u-mu"][name]["sweep_rows"], None
             plan = mvn.mvn_batch_plan(sizes, bw.N, bw.S, mvn.options(tile=128, precision=PRECISIONS[name],

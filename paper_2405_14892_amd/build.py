@@ -19,7 +19,8 @@ OBJ = os.path.join(ROOT, "_build", "obj")
 LIB = os.path.join(HERE, "libmvn.so")
 ARCH = os.environ.get("MVN_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["api.cpp", "kernels_chol.hip", "kernels_sov.hip", "kernels_sov_wide.hip", "kernels_grad.hip",
+SOURCES = ["api.cpp", "kernels_chol.hip", "kernels_sov.hip", "kernels_sov_wide.hip", "kernels_sov_quad.hip",
+           "kernels_grad.hip",
            "kernels_tlr.hip", "kernels_tlr_sweep.hip", "kernels_mc.hip", "kernels_post.hip"]
 
 # Per-file extra flags.  The sweep inlines the FP64 conditioning step into
@@ -27,6 +28,7 @@ SOURCES = ["api.cpp", "kernels_chol.hip", "kernels_sov.hip", "kernels_sov_wide.h
 # ~60 materialised 64-bit constants out of that loop and spill registers.
 EXTRA_FLAGS = {"kernels_sov.hip": ["-mllvm", "-disable-machine-licm"],
                "kernels_sov_wide.hip": ["-mllvm", "-disable-machine-licm"],
+               "kernels_sov_quad.hip": ["-mllvm", "-disable-machine-licm"],
                "kernels_grad.hip": ["-mllvm", "-disable-machine-licm"],
                "kernels_tlr_sweep.hip": ["-mllvm", "-disable-machine-licm"],
                "kernels_mc.hip": ["-mllvm", "-disable-machine-licm"]}

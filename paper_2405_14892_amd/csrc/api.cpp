@@ -130,20 +130,29 @@ struct ProbLayout {
   long yslice, zslice;
 };
 
+// Which dense sweep kernel runs a call.
+enum SweepKind { kSweep64 = 0, kSweepWide = 1, kSweepQuad = 2 };
+
 // Workspace of one probability call.  ld is the factor's leading dimension
 // (rows of the Y scratch); zslice > 0 adds the TLR Z scratch (FP64).
-// wide: the 128-column FP64 sweep (persistent workgroups, each owning whole
-// 32-column slices; Y slice ld x 128).
-ProbLayout prob_layout_ld(int ld, int N, int S, int prec, long zslice, int rows, bool wide = false,
+// kSweepWide: the 128-column FP64 sweep (persistent workgroups, each owning
+// whole 32-column slices; Y slice ld x 128); kSweepQuad: 256 columns per
+// workgroup, four conditioning waves.
+ProbLayout prob_layout_ld(int ld, int N, int S, int prec, long zslice, int rows, int kind = kSweep64,
                           int gcap = 0) {
   ProbLayout L{};
   L.ld = ld;
   const long NS = (long)N * S;
-  if (wide) {  // two workgroups per CU
+  if (kind == kSweepWide) {
     const long slices = (NS + 31) / 32;
-    const int gmax = 2 * kCUs;
+    const int gmax = mvn::wide_sweep_wg_per_cu() * kCUs;
     L.grid = (int)(slices < gmax ? slices : gmax);
     L.yslice = (long)L.ld * mvn::wide_sweep_cols();
+  } else if (kind == kSweepQuad) {
+    const long chunks = (NS + mvn::quad_sweep_cols() - 1) / mvn::quad_sweep_cols();
+    const int gmax = mvn::quad_wg_per_cu(prec, rows) * kCUs;
+    L.grid = (int)(chunks < gmax ? chunks : gmax);
+    L.yslice = mvn::quad_yslice(prec, L.ld);
   } else {
     const long chunks = (NS + mvn::sweep_tile_cols() - 1) / mvn::sweep_tile_cols();
     const int gmax = max_grid(rows, prec);
@@ -173,11 +182,24 @@ ProbLayout prob_layout_ld(int ld, int N, int S, int prec, long zslice, int rows,
 // per 128 columns on every CU slot); with fewer, the 64-column sweep reads
 // the factor no more often and runs more workgroups.
 bool use_wide(int prec, int rows, bool prefix, long NS) {
-  return prec == MVN_FP64 && rows == 128 && !prefix && NS >= 2L * kCUs * mvn::wide_sweep_cols();
+  return prec == MVN_FP64 && rows == 128 && !prefix &&
+         NS >= (long)mvn::wide_sweep_wg_per_cu() * kCUs * mvn::wide_sweep_cols();
+}
+
+// Reduced-precision operands with 128-row blocks run the four-wave sweep
+// when its 256-column chunks fill every workgroup slot (measured on the
+// 16384-site problem: BF16 282 against 456 ms, split BF16 976 against 1065,
+// FP32 579 against 604; the FP64 and few-sample sweeps are faster with 64
+// columns per workgroup).
+int sweep_kind(int prec, int rows, bool prefix, long NS) {
+  if (use_wide(prec, rows, prefix, NS)) return kSweepWide;
+  const long chunks = (NS + mvn::quad_sweep_cols() - 1) / mvn::quad_sweep_cols();
+  if (prec != MVN_FP64 && rows == 128 && chunks >= (long)kCUs * mvn::quad_wg_per_cu(prec, rows)) return kSweepQuad;
+  return kSweep64;
 }
 
 ProbLayout prob_layout(int n, int N, int S, int prec, int rows, bool prefix = false) {
-  return prob_layout_ld(padded(n), N, S, prec, 0, rows, use_wide(prec, rows, prefix, (long)N * S));
+  return prob_layout_ld(padded(n), N, S, prec, 0, rows, sweep_kind(prec, rows, prefix, (long)N * S));
 }
 
 // Front of the workspace of a nested-set call: the running-product partials
@@ -399,16 +421,23 @@ size_t batch_factor_bytes(const BatchPlan& P, int prec) {
 struct BatchWs {
   size_t at, bt, lat, ell, part, bad, counter, yscr, total;
   int grid;
-  long items;
+  long items, yslice;
 };
+
+// The batch sweep with four conditioning waves per workgroup (256 columns
+// per work item), except FP64 with 128-row blocks (the 64-column sweep).
+bool batch_quad(int prec, int rows) { return rows == 64 || prec != MVN_FP64; }
 
 BatchWs batch_ws(const BatchPlan& P, int count, int N, int S, int prec, int rows) {
   BatchWs W{};
   const long NS = (long)N * S;
-  const long chunks = (NS + mvn::sweep_tile_cols() - 1) / mvn::sweep_tile_cols();
+  const bool quad = batch_quad(prec, rows);
+  const int cols = quad ? mvn::quad_sweep_cols() : mvn::sweep_tile_cols();
+  const long chunks = (NS + cols - 1) / cols;
   W.items = chunks * count;
-  const int gmax = max_grid(rows, prec);
+  const int gmax = quad ? kCUs * mvn::quad_wg_per_cu(prec, rows) : max_grid(rows, prec);
   W.grid = (int)(W.items < gmax ? W.items : gmax);
+  W.yslice = quad ? mvn::quad_yslice(prec, P.ldmax) : mvn::sweep_yslice(prec, P.ldmax);
   size_t off = 0;
   W.at = off; off = align_up(off + sizeof(double) * (size_t)P.sum_n);
   W.bt = off; off = align_up(off + sizeof(double) * (size_t)P.sum_n);
@@ -418,7 +447,7 @@ BatchWs batch_ws(const BatchPlan& P, int count, int N, int S, int prec, int rows
   W.bad = off; off = align_up(off + sizeof(int) * (size_t)count);
   W.counter = off; off = align_up(off + sizeof(unsigned long long));
   W.yscr = off;
-  off = align_up(off + (size_t)mvn::sweep_elem_bytes(prec) * (size_t)W.grid * mvn::sweep_yslice(prec, P.ldmax));
+  off = align_up(off + (size_t)mvn::sweep_elem_bytes(prec) * (size_t)W.grid * W.yslice);
   W.total = off;
   return W;
 }
@@ -472,7 +501,9 @@ int dense_sweep(const mvn_factor* f, const double* d_a, const double* d_b, const
   sa.grid = Lay.grid;
   sa.rows = rows;
   sa.prefix = prefix;
-  sa.wide = use_wide(prec, rows, prefix != nullptr, (long)N * S) ? 1 : 0;
+  const int kind = sweep_kind(prec, rows, prefix != nullptr, (long)N * S);
+  sa.wide = kind == kSweepWide ? 1 : 0;
+  sa.quad = kind == kSweepQuad ? 1 : 0;
   e = mvn::launch_sweep(sa, stream);
   if (e != hipSuccess) return hip_fail(e, "sweep");
   if (prefix) return 0;
@@ -1123,16 +1154,16 @@ int mvn_prob_static(const mvn_factor* f, const double* d_a, const double* d_b, c
   if (!sweep_rows_ok(opts)) return fail(-8, "sweep_rows must be 0, 64 or 128 (got %d)", opts->sweep_rows);
   if (!d_out) return fail(-9, "output is NULL");
   const int rows = sweep_rows(opts);
-  const bool wide = use_wide(prec, rows, false, (long)N * S);
+  const int kind = sweep_kind(prec, rows, false, (long)N * S);
   // as many persistent workgroups as the scratch holds
-  const ProbLayout one = prob_layout_ld(padded(f->n), N, S, prec, 0, rows, wide, 1);
+  const ProbLayout one = prob_layout_ld(padded(f->n), N, S, prec, 0, rows, kind, 1);
   const size_t per = align_up((size_t)mvn::sweep_elem_bytes(prec) * (size_t)one.yslice);
   const size_t avail = kStaticBytes - kStaticLat;
   if (one.total > avail)
     return fail(-5, "problem needs %zu bytes of scratch, the static limit is %zu (n = %d, N*S = %ld)", one.total,
                 avail, f->n, (long)N * S);
   const int gcap = (int)std::min<size_t>((avail - one.total) / per + 1, (size_t)INT32_MAX);
-  const ProbLayout Lay = prob_layout_ld(padded(f->n), N, S, prec, 0, rows, wide, gcap);
+  const ProbLayout Lay = prob_layout_ld(padded(f->n), N, S, prec, 0, rows, kind, gcap);
   unsigned char* base = nullptr;
   const int rc = static_scratch(&base);
   if (rc) return rc;
@@ -1294,14 +1325,14 @@ int mvn_prob_batch(int count, const int* n_p, const void* d_plan, const int64_t*
   a.periodize = opts->periodize ? 1 : 0;
   a.prec = prec;
   a.yscr = (void*)(w + W.yscr);
-  a.yslice = mvn::sweep_yslice(prec, P.ldmax);
+  a.yslice = W.yslice;
   a.ell = ell;
   a.counter = counter;
   a.total_items = W.items;
   a.lplane = P.factor_elems;
   a.grid = W.grid;
   a.rows = sweep_rows(opts);
-  e = mvn::launch_batch_sweep(a, stream);
+  e = batch_quad(prec, a.rows) ? mvn::launch_quad_batch_sweep(a, stream) : mvn::launch_batch_sweep(a, stream);
   if (e != hipSuccess) return hip_fail(e, "batch sweep");
   e = mvn::launch_batch_reduce(ell, count, N, S, part, d_info, bad, d_out, stream);
   if (e != hipSuccess) return hip_fail(e, "batch reduce");

@@ -242,6 +242,7 @@ static hipError_t launch_sweep_t(const SweepArgs& a, hipStream_t st) {
 
 hipError_t launch_sweep(const SweepArgs& a, hipStream_t st) {
   if (a.wide) return launch_wide_sweep(a, st);
+  if (a.quad) return launch_quad_sweep(a, st);
   return a.prefix ? launch_sweep_t<true>(a, st) : launch_sweep_t<false>(a, st);
 }
 

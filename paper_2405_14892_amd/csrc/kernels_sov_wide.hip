@@ -54,6 +54,7 @@ static_assert(kWSub * kWC + kWSub * kWSub + (kWR - kWSub) * kWSub <= kWLds,
               "the sub-block buffers alias the GEMM stages");
 
 int wide_sweep_cols() { return kWC; }
+int wide_sweep_wg_per_cu() { return 2; }
 
 // Columns of workgroup g of G: whole 32-column slices, contiguous.
 __device__ __forceinline__ long wide_col_start(long g, long G, long NS) {
@@ -281,9 +282,6 @@ __global__ __launch_bounds__(256, 2) void wide_sweep_kernel(SweepArgs p) {
     for (int e = 0; e < 48; ++e)
       if (lane == e) ninv_tab[e] = kAs241[e / 16][e % 16];
   }
-  // An (empty) statement that names an accumulation register: without one
-  // the compiler keeps MFMA accumulators in the 256 architectural registers
-  // and spills; with it the accumulators may live in the AGPRs as well.
   const WideShared sh{lds, c_at, c_bt, c_rl, c_lat, ninv_tab};
   const long NS = (long)p.N * p.S;
   double* __restrict__ Y = (double*)p.yscr + (long)blockIdx.x * p.yslice;

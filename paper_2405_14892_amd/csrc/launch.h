@@ -131,6 +131,7 @@ struct SweepArgs {
   int rows;                // rows per sweep block: 128 (two workgroups per CU) or 64 (three)
   double* prefix;          // nullptr, or n x nchunks x 4 partials of the running products per row
   int wide;                // FP64, 128 rows, no prefix: the 128-column sweep (yslice = ld x 128)
+  int quad;                // the 256-column sweep with four conditioning waves (yslice = quad_yslice)
 };
 
 // Setup of one probability call: centred limits and the invalid-limit flag.
@@ -141,6 +142,7 @@ hipError_t launch_sweep(const SweepArgs& a, hipStream_t st);
 // The FP64 sweep with 128 sample columns per workgroup (kernels_sov_wide.hip).
 hipError_t launch_wide_sweep(const SweepArgs& a, hipStream_t st);
 int wide_sweep_cols();
+int wide_sweep_wg_per_cu();
 // log P-hat of every nested set (first k sites) and its relative standard
 // error over shifts from the partials of a prefix sweep: out[2k], out[2k+1].
 hipError_t launch_prefix_reduce(const double* part, long nchunks, int n, int N, int S, double* lps,
@@ -232,6 +234,14 @@ hipError_t launch_batch_setup(const BatchDesc* desc, int count, int nmax, const 
                               const double* mu, double* at, double* bt, int* bad,
                               unsigned long long* counter, hipStream_t st);
 hipError_t launch_batch_sweep(const BatchSweepArgs& a, hipStream_t st);
+// The sweeps with 256 sample columns per workgroup and four conditioning
+// waves (kernels_sov_quad.hip): dense (SweepArgs with yslice = quad_yslice)
+// and batched; 64-row blocks, or 128 for the reduced precisions.
+hipError_t launch_quad_sweep(const SweepArgs& a, hipStream_t st);
+hipError_t launch_quad_batch_sweep(const BatchSweepArgs& a, hipStream_t st);
+int quad_sweep_cols();
+int quad_wg_per_cu(int prec, int rows);
+long quad_yslice(int prec, int ld);
 hipError_t launch_batch_reduce(const double* ell, int count, int N, int S, double* part, const int* info,
                                const int* bad, double* out, hipStream_t st);
 

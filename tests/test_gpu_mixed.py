@@ -105,3 +105,46 @@ def test_fp64_sweep_on_a_mixed_factor_is_rejected_only_for_other_precisions(case
     with pytest.raises(mvn.MvnError) as e:
         mvn.mvn_prob(f, a, b, None, N=256, S=2, seed=1, opts=mvn.options(tile=64, precision=mvn.MVN_BF16))
     assert e.value.code == -8
+
+
+@pytest.fixture(scope="module")
+def quad_case():
+    """260 sites of a 20 x 20 grid (two full 128-row blocks and a 4-row
+    one), exponential kernel, P(X <= 2.5 everywhere) = O(1); N x S = 65600 x
+    2 = 131200 samples (512.5 chunks of 256: the reduced-precision sweep with
+    four conditioning waves, last chunk ragged)."""
+    g = np.linspace(0.0, 1.0, 20)
+    locs = np.stack(np.meshgrid(g, g, indexing="ij"), -1).reshape(-1, 2)[:260].copy()
+    kern = (1.0, 0.1, 0.5, 1e-8)
+    n = len(locs)
+    a, b = np.full(n, -np.inf), np.full(n, 2.5)
+    N, S, seed = 65600, 2, 23
+    L = oracle.cholesky(oracle.covariance(locs, *kern))
+    ell = oracle.sweep(L, a, b, N, S, seed)
+    pref = oracle.prefix_probs(L, a, b, N, S, seed)
+    return locs, kern, a, b, N, S, seed, ell, oracle.reduce_samples(ell, N, S), pref
+
+
+@pytest.mark.parametrize("prec,bound", [(mvn.MVN_FP32, 1e-4), (mvn.MVN_BF16X3, 1e-4), (mvn.MVN_BF16, 3e-3)])
+def test_four_wave_sweep_within_bound_full_and_nested(quad_case, prec, bound):
+    """The 256-column sweep (128-row blocks, enough samples to fill every
+    workgroup slot) against the oracle on the same points: |P - P_oracle|
+    within the mixed-precision bar for FP32 and split BF16 (the plain BF16
+    error stated), for the full estimate and for every nested set; the last
+    nested set equals the full estimate."""
+    locs, kern, a, b, N, S, seed, ell, ref, pref = quad_case
+    n = len(a)
+    o = mvn.options(tile=128, precision=prec, sweep_rows=128)
+    f = mvn.mvn_cholesky(n, locs=locs, kern=kern, opts=o)
+    r = mvn.mvn_prob(f, a, b, None, N=N, S=S, seed=seed, opts=o, return_ell=True)
+    p = mvn.mvn_prob_prefix(f, a, b, None, N=N, S=S, seed=seed, opts=o)
+    torch.cuda.synchronize()
+    assert f.info() == 0
+    dP = abs(r["P"].item() - ref["P"])
+    dell = float(np.max(np.abs(r["ell"].cpu().numpy() - ell)))
+    lp = p["logP"].cpu().numpy()
+    dpre = float(np.max(np.abs(np.exp(lp) - np.exp(pref["logP"]))))
+    print(f"prec {prec}: P {ref['P']:.4f}, |dP| {dP:.2e}, max |d ell| {dell:.2e}, nested max |dP| {dpre:.2e}",
+          flush=True)
+    assert dP <= bound and dpre <= bound
+    assert abs(lp[-1] - r["logP"].item()) < 1e-12 * max(1.0, abs(lp[-1]))
