@@ -267,6 +267,38 @@ def variant_oracle400(dev) -> dict:
     return out
 
 
+def _tlr_dense_sweep(p, w, dev) -> dict:
+    """The configuration of Section IV-C on the TLR factor held by Problem p:
+    the factor written out dense (mvn_tlr_dense), then the dense FP64 sweep
+    (one timed call; its kernels are warm from the dense steps).  Frees p's
+    TLR sweep workspace first."""
+    import torch
+    mvn, lib, h, P = p.mvn, p.lib, p.h, p._p
+    p.ws = None
+    _free()
+    nb = ctypes.c_size_t(0)
+    lib.check(h.mvn_tlr_dense_bytes(ctypes.byref(p.fac), ctypes.byref(nb)))
+    dbuf = torch.empty(nb.value, dtype=torch.uint8, device=dev)
+    dfac = lib.MvnFactor()
+    dopts = mvn.options(tile=1024)
+    wsb = mvn.mvn_prob_workspace_bytes(w.n, w.N, w.S, dopts)
+    ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    out = torch.empty(4 + w.S, dtype=torch.float64, device=dev)
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    torch.cuda.synchronize()
+    e[0].record(p.stream)
+    lib.check(h.mvn_tlr_dense(ctypes.byref(p.fac), P(dbuf), nb.value, ctypes.byref(dfac), p.sp))
+    e[1].record(p.stream)
+    lib.check(h.mvn_prob(ctypes.byref(dfac), P(p.a), P(p.b), P(p.mu), w.N, w.S, ctypes.c_uint64(w.seed),
+                         ctypes.byref(dopts), P(ws), wsb, P(out), None, p.sp))
+    e[2].record(p.stream)
+    torch.cuda.synchronize()
+    res = out.cpu().numpy()
+    del dbuf, ws
+    _free()
+    return {"expand_ms": e[0].elapsed_time(e[1]), "sov_ms": e[1].elapsed_time(e[2]), "logP": float(res[0])}
+
+
 def variant_tlr(dev, dense=None) -> dict:
     """The 65536-site problem with a tile low-rank factor at 1e-5 and 1e-7,
     each timed over 3 steps after a warm-up (default sweep block shape),
@@ -291,6 +323,7 @@ def variant_tlr(dev, dense=None) -> dict:
         p = Problem(w, mvn.options(tile=w.tile, tlr_eps=eps, max_rank=256), dev)
         r = p.run(3, 1)
         ranks, ld = np.abs(p.ranks()), p.fac.ld
+        dsw = _tlr_dense_sweep(p, w, dev)
         del p
         _free()
         m = w.tile
@@ -306,6 +339,12 @@ def variant_tlr(dev, dense=None) -> dict:
             "sweep_speedup_vs_dense": dense["sov_ms"] / r["sov_ms"],
             "effective_tflops": (chol_f + sov_f) / (r["wall_ms"] * 1e-3) / 1e12,
             "sweep_executed_tflops": sweep_exec / (r["sov_ms"] * 1e-3) / 1e12,
+            "tlr_cholesky_dense_sweep": {
+                "expand_ms": dsw["expand_ms"], "sov_ms": dsw["sov_ms"],
+                "wall_ms": r["cholesky_ms"] + dsw["expand_ms"] + dsw["sov_ms"],
+                "speedup_vs_dense": dense["wall_ms"] / (r["cholesky_ms"] + dsw["expand_ms"] + dsw["sov_ms"]),
+                "abs_dlogP_vs_tlr_sweep": abs(dsw["logP"] - r["logP"]),
+                "note": "TLR factorisation, factor written out dense, dense FP64 sweep (one timed call)"},
             "ranks": {"mean": float(ranks.mean()), "max": int(ranks.max()),
                       "adjacent_mean": float(np.mean([ranks[i * (i - 1) // 2 + i - 1] for i in range(1, nt)])),
                       "histogram_by_16": np.bincount(np.minimum(ranks // 16, 16)).tolist()}}

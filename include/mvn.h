@@ -259,6 +259,22 @@ int mvn_prob_prefix(const mvn_factor* f, const double* d_a, const double* d_b, c
                     int N, int S, uint64_t seed, const mvn_options* opts, void* ws, size_t ws_bytes,
                     double* d_prefix, hipStream_t stream);
 
+/* The TLR factor in dense form: the configuration of Section IV-C, where
+ * the factorisation is tile low-rank (Section III-E) and the SOV sweep of
+ * Algorithm 2 runs on dense tiles.  Writes L into d_buf as a dense FP64
+ * factor, row-major with leading dimension ld = n rounded up to 128:
+ * diagonal tiles copied, off-diagonal tiles L_ij = U_ij V'^T_ij (FP64 MFMA),
+ * identity past n; the upper triangle is not written (no sweep reads it).
+ * *out receives a dense FP64 factor handle on d_buf that shares f's info
+ * (so a failed TLR factorisation still gives NaN results); it stays valid
+ * while d_buf and f's buffer live.  Pass it to mvn_prob / mvn_prob_prefix
+ * with a dense workspace (mvn_prob_workspace_bytes with tlr_eps = 0).
+ *   d_buf / bytes   device memory, at least mvn_tlr_dense_bytes
+ * Returns -1 if f is not a TLR factor, -2 / -3 for a NULL or short buffer,
+ * -4 for a NULL out.  Asynchronous on `stream`; nothing is read back. */
+int mvn_tlr_dense_bytes(const mvn_factor* f, size_t* bytes);
+int mvn_tlr_dense(const mvn_factor* f, void* d_buf, size_t bytes, mvn_factor* out, hipStream_t stream);
+
 /* Factor P Sigma P^T: Sigma given by its lower triangle (device, row stride
  * ld_sigma; the upper triangle is not read), factored in the site order
  * d_perm (device, n int64 entries): row i of the factor is site d_perm[i].

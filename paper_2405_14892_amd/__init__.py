@@ -19,7 +19,7 @@ from ._lib import (MVN_BF16, MVN_BF16X3, MVN_CHOL_ADAPTIVE, MVN_CHOL_FP64, MVN_C
 __all__ = ["mvn_factor_bytes", "mvn_cholesky_workspace_bytes", "mvn_prob_workspace_bytes",
            "mvn_prob_workspace_bytes_factor", "mvn_cholesky", "mvn_prob", "mvn_prob_static", "Factor",
            "mvn_prob_prefix_workspace_bytes", "mvn_prob_prefix", "confidence_region",
-           "mvn_mc_prefix_workspace_bytes", "mvn_mc_prefix", "mvn_cholesky_permuted", "mvn_posterior",
+           "mvn_mc_prefix_workspace_bytes", "mvn_mc_prefix", "mvn_cholesky_permuted", "mvn_tlr_dense", "mvn_posterior",
            "posterior_confidence_region",
            "mvn_prob_grad_workspace_bytes", "mvn_prob_grad", "MVNLogProb", "BatchPlan",
            "mvn_batch_plan", "mvn_prob_batch",
@@ -114,7 +114,8 @@ class Factor:
 
     def info(self) -> int:
         torch = _torch()
-        return int(self._view(self.handle.info, 1, torch.int32).item())
+        owner = getattr(self, "_info_owner", None) or self  # a dense form shares its TLR factor's info
+        return int(owner._view(self.handle.info, 1, torch.int32).item())
 
     def update_counts(self) -> dict:
         """Trailing tile updates by arithmetic (dense factors; the adaptive
@@ -179,6 +180,26 @@ def mvn_cholesky(n: int, sigma=None, locs=None, kern: tuple | None = None,
     f = Factor(h, buf, device)
     f._keep = (s, lc, ws)  # inputs and workspace must outlive the asynchronous launch
     return f
+
+
+def mvn_tlr_dense(f: Factor) -> Factor:
+    """The TLR factor ``f`` written out as a dense FP64 factor (diagonal
+    tiles copied, L_ij = U_ij V'^T_ij below them), for the dense SOV sweep
+    after a TLR factorisation (the configuration of Section IV-C).  The
+    result shares f's info and keeps f alive."""
+    torch = _torch()
+    if not f.is_tlr:
+        raise MvnError(-1, "not a TLR factor")
+    nb = ctypes.c_size_t(0)
+    _lib.check(_lib.lib().mvn_tlr_dense_bytes(ctypes.byref(f.handle), ctypes.byref(nb)))
+    buf = torch.empty(nb.value, dtype=torch.uint8, device=f.device)
+    h = MvnFactor()
+    _lib.check(_lib.lib().mvn_tlr_dense(ctypes.byref(f.handle), _ptr(buf), nb.value, ctypes.byref(h),
+                                        _stream(f.device)))
+    d = Factor(h, buf, f.device)
+    d._keep = (f,)
+    d._info_owner = f
+    return d
 
 
 def mvn_cholesky_permuted(sigma, perm, opts: MvnOptions | None = None) -> Factor:

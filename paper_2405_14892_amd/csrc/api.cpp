@@ -1072,6 +1072,39 @@ int mvn_prob(const mvn_factor* f, const double* d_a, const double* d_b, const do
   return dense_sweep(f, d_a, d_b, d_mu, N, S, seed, opts, ws, Lay, d_ell, nullptr, d_out, stream);
 }
 
+int mvn_tlr_dense_bytes(const mvn_factor* f, size_t* bytes) {
+  if (!bytes) return fail(-2, "bytes is NULL");
+  if (!f || !(f->flags & MVN_FACTOR_TLR) || f->n < 1) return fail(-1, "not a TLR factor handle");
+  const size_t ld = (size_t)padded(f->n);
+  *bytes = sizeof(double) * ld * ld;
+  return 0;
+}
+
+int mvn_tlr_dense(const mvn_factor* f, void* d_buf, size_t bytes, mvn_factor* out, hipStream_t stream) {
+  if (!f || !(f->flags & MVN_FACTOR_TLR) || !f->L || !f->info || f->n < 1 || f->tile < 128 || f->tile % 128 != 0 ||
+      f->ld % f->tile != 0 || f->ld < f->n || !f->U || !f->Vt || !f->ranks || f->rank_stride < 16 ||
+      f->rank_stride % 16 != 0)
+    return fail(-1, "not a TLR factor handle");
+  if (!d_buf) return fail(-2, "buffer is NULL");
+  const long ld = padded(f->n);
+  if (bytes < sizeof(double) * (size_t)ld * (size_t)ld)
+    return fail(-3, "buffer too small: %zu < %zu", bytes, sizeof(double) * (size_t)ld * (size_t)ld);
+  if (!out) return fail(-4, "output handle is NULL");
+  const hipError_t e = mvn::launch_tlr_expand(f->n, f->tile, f->ld / f->tile, f->rank_stride, f->L, f->U, f->Vt,
+                                              f->ranks, (double*)d_buf, ld, stream);
+  if (e != hipSuccess) return hip_fail(e, "TLR expansion");
+  mvn_factor d{};
+  d.n = f->n;
+  d.ld = (int)ld;
+  d.precision = MVN_FP64;
+  d.flags = 0;
+  d.L = (double*)d_buf;
+  d.info = f->info;
+  d.chol_mode = MVN_CHOL_FP64;
+  *out = d;
+  return 0;
+}
+
 // ---------------------------------------------------------------- no-allocation variant
 }  // extern "C"
 

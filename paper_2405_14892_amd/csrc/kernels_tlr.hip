@@ -552,6 +552,83 @@ __global__ void tlr_info_kernel(int* __restrict__ info, const int* __restrict__ 
   if (threadIdx.x == 0 && *local != 0 && *info == 0) *info = *local + offset;
 }
 
+// ------------------------------------------------------------ dense form
+// The TLR factor written out as a dense row-major factor (leading dimension
+// ldd <= nt m): one 128 x 128 block per workgroup.  A diagonal tile's block
+// is copied (identity past n, as the tiles hold it); an off-diagonal tile's
+// block is U_ij V'^T_ij on FP64 MFMA with K the rank rounded up to 16 (U's
+// columns past the rank are zero), zero past n.  Blocks above the diagonal
+// are not written (the sweep reads only the lower triangle).
+__global__ __launch_bounds__(256) void tlr_expand_kernel(int n, int m, int rs, const double* __restrict__ tiles,
+                                                         const double* __restrict__ U, const double* __restrict__ Vt,
+                                                         const int* __restrict__ ranks, double* __restrict__ D,
+                                                         long ldd) {
+  __shared__ __attribute__((aligned(16))) double lds[4 * kStageDoubles];
+  const int sb = m / kTile;
+  long ti, tj;
+  tri_inverse(blockIdx.x, ti, tj);
+  const int br = blockIdx.y / sb, bc = blockIdx.y % sb;
+  const long R0 = ti * m + (long)br * kTile, C0 = tj * m + (long)bc * kTile;
+  if (R0 >= ldd || C0 >= ldd || (ti == tj && bc > br)) return;  // uniform per workgroup
+  const int t = threadIdx.x;
+  if (ti == tj) {
+    const double* src = tiles + tri_lo(ti, ti) * (long)m * m + (long)br * kTile * m + (long)bc * kTile;
+    for (int e = t; e < kTile * kTile; e += 256) {
+      const int r = e / kTile, c = e % kTile;
+      if (R0 + r < ldd && C0 + c < ldd) D[(R0 + r) * ldd + C0 + c] = src[(long)r * m + c];
+    }
+    return;
+  }
+  const long pid = tri_st(ti, tj);
+  const int r = abs(ranks[pid]);
+  const int K = min(rs, (r + 15) & ~15);
+  const double* Up = U + pid * (long)m * rs;
+  const double* Vp = Vt + pid * (long)rs * m + (long)bc * kTile;
+  Acc acc;
+  acc_zero(acc);
+  const int nst = K / kStageK;
+  if (nst > 0) {
+    double ra[8], rb[8];
+    load_rows<false>(Up, rs, (long)br * kTile, 0, 0, 0, ra);
+    load_cols(Vp, m, 0, rb);
+    store_rows(lds, ra);
+    store_cols(lds + kStageDoubles, rb);
+    __syncthreads();
+    for (int s = 0; s < nst; ++s) {
+      double* cur = lds + (s & 1) * 2 * kStageDoubles;
+      double* nxt = lds + ((s + 1) & 1) * 2 * kStageDoubles;
+      if (s + 1 < nst) {
+        load_rows<false>(Up, rs, (long)br * kTile, (long)(s + 1) * kStageK, 0, 0, ra);
+        load_cols(Vp, m, (long)(s + 1) * kStageK, rb);
+      }
+      mma_stage(cur, cur + kStageDoubles, acc);
+      if (s + 1 < nst) {
+        store_rows(nxt, ra);
+        store_cols(nxt + kStageDoubles, rb);
+      }
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int ib = 0; ib < 4; ++ib)
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const long gi = R0 + acc_row(ib, q), gj = C0 + acc_col(jb);
+        if (gi < ldd && gj < ldd) D[gi * ldd + gj] = (gi < n && gj < n) ? acc.v[ib][jb][q] : 0.0;
+      }
+}
+
+hipError_t launch_tlr_expand(int n, int m, int nt, int rs, const double* tiles, const double* U, const double* Vt,
+                             const int* ranks, double* D, long ldd, hipStream_t st) {
+  const long ntiles = (long)nt * (nt + 1) / 2;
+  const unsigned sb = (unsigned)(m / kTile);
+  hipLaunchKernelGGL(tlr_expand_kernel, dim3((unsigned)ntiles, sb * sb), dim3(256), 0, st, n, m, rs, tiles, U, Vt,
+                     ranks, D, ldd);
+  return hipGetLastError();
+}
+
 hipError_t launch_tlr_build(int n, int m, int nt, const double* sigma, int lds, const int64_t* perm,
                             const int* perm_bad, const double* locs, const Matern& mk, double* tiles, int* info,
                             hipStream_t st) {

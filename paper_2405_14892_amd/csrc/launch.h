@@ -269,6 +269,11 @@ struct TlrCholArgs {
   double eps;
 };
 hipError_t launch_tlr_cholesky(const TlrCholArgs& a, hipStream_t st);
+// The TLR factor as a dense row-major lower factor D (ldd x ldd, ldd <= nt m):
+// diagonal tiles copied, off-diagonal tiles U_ij V'^T_ij, zero / identity
+// past n; the upper triangle is not written.
+hipError_t launch_tlr_expand(int n, int m, int nt, int rs, const double* tiles, const double* U, const double* Vt,
+                             const int* ranks, double* D, long ldd, hipStream_t st);
 
 // Layout of the rank-dependent part of a TLR probability workspace,
 // computed on the device from the factor's ranks (no read-back): byte

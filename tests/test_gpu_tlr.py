@@ -256,3 +256,37 @@ def test_tlr_sweep_graph_capture_replays_match_eager():
     q = mvn.mvn_prob(f, ta, tb, None, N=64, S=1, seed=5, opts=opts, workspace=exact)
     torch.cuda.synchronize()
     assert torch.isfinite(q["out"][0])
+
+
+@pytest.mark.parametrize("n,tile", [(1300, 128), (700, 256)])
+def test_tlr_dense_form_and_dense_sweep(n, tile):
+    """The TLR factor in dense form (the configuration of Section IV-C: TLR
+    factorisation, dense SOV sweep): the written factor equals the one
+    assembled on the host from the same tiles, U and V'^T; the dense sweep on
+    it equals, sample by sample, the oracle's sweep through that factor; and
+    with enough samples for the 128-column FP64 sweep it equals the TLR
+    sweep of the same factor (the same products in a different order)."""
+    eps, rcap = 1e-5, 128
+    print(f"tlr dense form n={n} tile={tile}", flush=True)
+    locs, kern, a, b = _tlr_inputs(40, n, seed=83, beta=0.05)
+    f = _factor(n, locs, kern, tile, eps, rcap)
+    assert f.info() == 0
+    d = mvn.mvn_tlr_dense(f)
+    torch.cuda.synchronize()
+    assert not d.is_tlr and d.info() == 0 and d.ld == (n + 127) // 128 * 128
+    L = _dense_from_tlr(f)
+    Ld = d.L().cpu().numpy()
+    assert np.max(np.abs(np.tril(Ld) - L)) < 1e-13
+    N, S, seed = 300, 3, 616
+    r = mvn.mvn_prob(d, a, b, None, N=N, S=S, seed=seed, opts=mvn.options(tile=tile), return_ell=True)
+    torch.cuda.synchronize()
+    at, bt = oracle.centre(a, b)
+    ell_ref = oracle.sweep(L, at, bt, N, S, seed)
+    assert np.max(np.abs(r["ell"].cpu().numpy() - ell_ref)) < 1e-8
+    N, S = 33000, 2  # N * S >= 65536: the 128-column sweep
+    rd = mvn.mvn_prob(d, a, b, None, N=N, S=S, seed=seed, opts=mvn.options(tile=tile), return_ell=True)
+    rt = _prob(f, a, b, N, S, seed, tile, eps, rcap)
+    dl = np.max(np.abs(rd["ell"].cpu().numpy() - rt["ell"].cpu().numpy()))
+    print(f"  dense-form vs TLR sweep: max |d ell| {dl:.2e}", flush=True)
+    assert dl < 1e-8
+    assert abs(rd["logP"].item() - rt["logP"].item()) < 1e-9 * max(1.0, abs(rt["logP"].item()))
