@@ -46,13 +46,13 @@ METRIC = "MVN probs/sec + effective TFLOP/s (Cholesky+SOV) at stated error vs FP
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0, "bf16x3": 2500.0}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3}
 
-# HBM bytes per sweep launch on the 65536-site dense FP64 workload from
-# rocprofv3 FETCH_SIZE x2 + WRITE_SIZE x1 (factors from a 1 GiB copy; the
-# summary is profiles/sweep_kernel_f64_dense64k.md), valid only for the
-# kernel sources they were measured on (checked by hash).
+# HBM bytes per sweep launch on the dense FP64 workloads from rocprofv3
+# FETCH_SIZE x2 + WRITE_SIZE x1 (factors from a 1 GiB copy; the summaries are
+# profiles/sweep_kernel_f64_dense64k.md and sweep_kernel_f64_prec16k.md),
+# valid only for the kernel sources they were measured on (checked by hash).
 TRAFFIC_SOURCES = ["paper_2405_14892_amd/csrc/kernels_sov_wide.hip", "paper_2405_14892_amd/csrc/mvn_device.h",
                    "paper_2405_14892_amd/csrc/sweep_block.h", "paper_2405_14892_amd/csrc/gemm_f64.h"]
-TRAFFIC_MEASURED = {"tlr64k": ("3c6ca3c1befe5288", 3.0042e13)}
+TRAFFIC_MEASURED = {"tlr64k": ("577b5c4ccdc95436", 7.2924e12), "prec16k": ("577b5c4ccdc95436", 9.148e11)}
 
 
 def _traffic(workload: str):
@@ -673,9 +673,9 @@ def main() -> int:
     chol_flops, sov_flops = _flops(n, N * S)
     sweep_tf = sov_flops / (r["sov_ms"] * 1e-3) / 1e12
     peak = PEAK_TFLOPS["fp64" if tlr else args.precision]
-    wide = not tlr and args.precision == "fp64" and N * S >= 65536
+    wide = not tlr and args.precision == "fp64" and N * S >= 32768
     kernel = ("tlr_sweep_kernel (TLR SOV update + conditioning)" if tlr else
-              "wide_sweep_kernel (128-column FP64 SOV GEMM + conditioning)" if wide else
+              "wide_sweep_kernel (256-row x 128-column FP64 SOV GEMM + conditioning)" if wide else
               "sweep_kernel (SOV GEMM + conditioning)")
     line = {
         "metric": METRIC,

@@ -348,7 +348,173 @@ struct QuadStage {
   }
 };
 
-// The whole sweep of one 256-column chunk of one problem.
+// This lane's sample column and its QMC indices.
+struct QuadLane {
+  int c;           // column within the chunk (64 w + lane)
+  long col;        // global sample column
+  bool valid;
+  uint64_t sidx, jpt;
+  PrefixOut pre;   // the wave's 64 columns as a chunk of the nested-set partials
+  long chunk64;
+};
+
+__device__ __forceinline__ QuadLane quad_lane(long chunk, int N, int S, double* prefix) {
+  QuadLane q;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const long NS = (long)N * S;
+  q.c = 64 * w + lane;
+  q.col = chunk * kQC + q.c;
+  q.valid = q.col < NS;
+  q.sidx = q.valid ? (uint64_t)(q.col / N) : 0;
+  q.jpt = q.valid ? (uint64_t)(q.col % N) + 1 : 1;
+  q.chunk64 = chunk * 4 + w;
+  q.pre = PrefixOut{prefix, (NS + 63) / 64, q.chunk64, (uint64_t)(q.chunk64 * 64 / N)};
+  return q;
+}
+
+template <class P>
+__device__ __forceinline__ void quad_zero(typename P::AccV (&acc)[P::kRows / 16][4]) {
+#pragma unroll
+  for (int ib = 0; ib < P::kRows / 16; ++ib)
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[ib][jb][r] = 0;
+}
+
+// acc += the product of nst LDS stages; load(s, regs) fetches stage s.  Ends
+// with a barrier (the stages are free again).
+template <class P, class Load>
+__device__ __forceinline__ void quad_gemm(const QuadShared& sh, typename P::AccV (&acc)[P::kRows / 16][4], int nst,
+                                          Load load) {
+  if (nst <= 0) return;
+  char* stage0 = sh.region;
+  char* stage1 = sh.region + (P::kStages == 2 ? P::kStageBytes : 0);
+  typename P::Regs rg;
+  load(0, rg);
+  P::store(stage0, rg);
+  __syncthreads();
+  for (int s = 0; s < nst; ++s) {
+    const bool odd = s & 1;
+    if (s + 1 < nst) load(s + 1, rg);
+    P::mma(odd ? stage1 : stage0, acc);
+    if (s + 1 < nst) {
+      if (P::kStages == 1) __syncthreads();  // every wave is done with the stage
+      P::store(odd ? stage0 : stage1, rg);
+    }
+    __syncthreads();
+  }
+}
+
+// Steps 2-3 for one block of `rows` rows whose S is in acc: the block's
+// diagonal block of L at Ld (leading dimension ld), global first row g0
+// (the QMC dimension and the row of the limits, the lattice and Y), y to
+// the Y scratch.  Ends with a barrier.
+template <class P, bool PREFIX>
+__device__ __forceinline__ void quad_condition(const QuadShared& sh, typename P::AccV (&acc)[P::kRows / 16][4],
+                                               const double* __restrict__ Ld, long ld, int rows, long g0,
+                                               const double* __restrict__ at, const double* __restrict__ bt,
+                                               const uint64_t* __restrict__ lattice, uint64_t seed, int n,
+                                               int periodize, typename P::E* __restrict__ Y, long ldy,
+                                               const QuadLane& ln, LogProd& prod) {
+  using F = typename P::F;
+  constexpr int NB = P::kRows / 16;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int c = ln.c;
+  double* T = (double*)sh.region;                                   // kQS x kQC
+  char* bufs = sh.region + kQS * kQC * 8;                           // two triangle + fold buffers
+  const auto tri_buf = [bufs](int b) { return (double*)(bufs + b * QuadLds<P>::kBuf); };
+  const auto col_buf = [bufs](int b) { return (F*)(bufs + b * QuadLds<P>::kBuf + QuadLds<P>::kTri * 8); };
+  const auto ninv = [&sh](double x) { return ninv_lower_tab(x, sh.tab); };
+  // the first sub-block's part of L and the per-row constants
+  QuadStage<P> stg;
+  stg.fetch(Ld, ld, 0, rows);
+  stg.put(tri_buf(0), col_buf(0), 0);
+  if (t < rows) {
+    const long g = g0 + t;
+    sh.c_at[t] = at[g];
+    sh.c_bt[t] = bt[g];
+    sh.c_rl[t] = 1.0 / Ld[(long)t * ld + t];
+    sh.c_lat[t] = lattice[g];
+  }
+#pragma unroll 1
+  for (int q = 0; q < NB; ++q) {
+    const int r0 = q * kQS;
+    if (r0 >= rows) break;  // uniform
+    const int rq = min(kQS, rows - r0);
+    __syncthreads();  // buffer q % 2 is written; every wave is done with buffer (q + 1) % 2
+    const bool more = r0 + kQS < rows;
+    if (more) stg.fetch(Ld, ld, r0 + kQS, rows);  // in flight during the conditioning
+    const double* Ltri = tri_buf(q & 1);
+    const F* Lcol = col_buf(q & 1);
+    // S rows of the sub-block -> T (accumulator block ib == q)
+#pragma unroll
+    for (int ib = 0; ib < NB; ++ib) {
+      if (ib == q) {
+#pragma unroll
+        for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            T[P::row_of(lane, r) * kQC + 64 * w + 16 * jb + (lane & 15)] = (double)acc[ib][jb][r];
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int i = 0; i < rq; ++i) {
+      const double* Li = Ltri + i * kQS;
+      const double* Tc = T + c;
+      double s0 = Tc[i * kQC], s1 = 0.0, s2 = 0.0, s3 = 0.0;
+      const int kend = (i + 3) & ~3;  // the triangle row is zero from column i on
+      for (int k = 0; k < kend; k += 4) {
+        s0 += Li[k] * Tc[k * kQC];
+        s1 += Li[k + 1] * Tc[(k + 1) * kQC];
+        s2 += Li[k + 2] * Tc[(k + 2) * kQC];
+        s3 += Li[k + 3] * Tc[(k + 3) * kQC];
+      }
+      const double sum = (s0 + s1) + (s2 + s3);
+      const int ri = r0 + i;
+      const double rl = sh.c_rl[ri];
+      const double alpha = (sh.c_at[ri] - sum) * rl;
+      const double beta = (sh.c_bt[ri] - sum) * rl;
+      const uint64_t gi = (uint64_t)(g0 + ri);
+      const double wq = richtmyer(ln.jpt, sh.c_lat[ri], splitmix64(seed, ln.sidx * (uint64_t)n + gi), periodize);
+      const Step st = P::kMixed ? condition_step_mixed_with(alpha, beta, wq, 1.0 - wq, ninv)
+                                : condition_step_with(alpha, beta, wq, 1.0 - wq, ninv);
+      T[i * kQC + c] = ln.valid ? st.y : 0.0;
+      logprod_mul(prod, st);
+      if constexpr (PREFIX) {
+        if (ln.chunk64 < ln.pre.nchunks) prefix_row(prod, ln.valid, ln.sidx, ln.pre, (long)gi);  // uniform per wave
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // later rows += L[later rows, sub-block] y_sub (K = 16)
+#pragma unroll
+    for (int ib = 1; ib < NB; ++ib) {
+      if (ib > q && 16 * ib < rows) {
+#pragma unroll
+        for (int kk = 0; kk < kQS / 4; ++kk) {
+          const int k = 4 * kk + (lane >> 4);
+          const F a = Lcol[(16 * ib - r0 - kQS + (lane & 15)) * kQS + k];
+#pragma unroll
+          for (int jb = 0; jb < 4; ++jb)
+            acc[ib][jb] = P::fold(a, (F)T[k * kQC + 64 * w + 16 * jb + (lane & 15)], acc[ib][jb]);
+        }
+      }
+    }
+    // y of the sub-block -> the Y scratch (rows past n are never read)
+    P::put_y(T, Y, ldy, (int)(g0 + r0), c);
+    if (more) stg.put(tri_buf((q + 1) & 1), col_buf((q + 1) & 1), r0 + kQS);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+  __syncthreads();  // the next stages overwrite T and the buffers
+}
+
+// The whole sweep of one 256-column chunk of one problem with a dense factor.
 template <class P, bool PREFIX>
 __device__ __forceinline__ void quad_chunk(const QuadShared& sh, const double* __restrict__ L,
                                            const typename P::E* __restrict__ Lg, long lplane, long ld, int n,
@@ -356,144 +522,21 @@ __device__ __forceinline__ void quad_chunk(const QuadShared& sh, const double* _
                                            const uint64_t* __restrict__ lattice, uint64_t seed, int N, int S,
                                            int periodize, typename P::E* __restrict__ Y,
                                            double* __restrict__ ell, long chunk, double* __restrict__ prefix) {
-  using F = typename P::F;
-  using AccV = typename P::AccV;
   constexpr int RB = P::kRows;
-  constexpr int NB = RB / 16;
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const long NS = (long)N * S;
-  char* stage0 = sh.region;
-  char* stage1 = sh.region + (P::kStages == 2 ? P::kStageBytes : 0);
-  double* T = (double*)sh.region;                                   // kQS x kQC
-  char* bufs = sh.region + kQS * kQC * 8;                           // two triangle + fold buffers
-  const auto tri_buf = [bufs](int b) { return (double*)(bufs + b * QuadLds<P>::kBuf); };
-  const auto col_buf = [bufs](int b) { return (F*)(bufs + b * QuadLds<P>::kBuf + QuadLds<P>::kTri * 8); };
-  const int c = 64 * w + lane;                                      // this lane's column of the chunk
-  const long col = chunk * kQC + c;
-  const bool valid = col < NS;
-  const uint64_t sidx = valid ? (uint64_t)(col / N) : 0;
-  const uint64_t jpt = valid ? (uint64_t)(col % N) + 1 : 1;
-  const long chunk64 = chunk * 4 + w;
-  const PrefixOut pre{prefix, (NS + 63) / 64, chunk64, (uint64_t)(chunk64 * 64 / N)};
-  const auto ninv = [&sh](double x) { return ninv_lower_tab(x, sh.tab); };
+  const QuadLane ln = quad_lane(chunk, N, S, prefix);
   LogProd prod{1.0, 0};
   for (int i0 = 0; i0 < n; i0 += RB) {
     const int rows = min(RB, n - i0);
-    AccV acc[NB][4];
-#pragma unroll
-    for (int ib = 0; ib < NB; ++ib)
-#pragma unroll
-      for (int jb = 0; jb < 4; ++jb)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) acc[ib][jb][r] = 0;
+    typename P::AccV acc[RB / 16][4];
+    quad_zero<P>(acc);
     // ---- step 1: S = L[i0:i0+RB, 0:i0] Y[0:i0, chunk]
-    if (i0 > 0) {
-      const int nst = i0 / P::kK;
-      typename P::Regs rg;
-      P::load(Lg, ld, lplane, i0, 0, Y, ld, rg);
-      P::store(stage0, rg);
-      __syncthreads();
-      for (int s = 0; s < nst; ++s) {
-        const bool odd = s & 1;
-        if (s + 1 < nst) P::load(Lg, ld, lplane, i0, (long)(s + 1) * P::kK, Y, ld, rg);
-        P::mma(odd ? stage1 : stage0, acc);
-        if (s + 1 < nst) {
-          if (P::kStages == 1) __syncthreads();  // every wave is done with the stage
-          P::store(odd ? stage0 : stage1, rg);
-        }
-        __syncthreads();
-      }
-    }
-    // ---- the first sub-block's part of L and the per-row constants
-    const double* Ld = L + (long)i0 * ld + i0;
-    QuadStage<P> stg;
-    stg.fetch(Ld, ld, 0, rows);
-    stg.put(tri_buf(0), col_buf(0), 0);
-    if (t < rows) {
-      const long g = i0 + t;
-      sh.c_at[t] = at[g];
-      sh.c_bt[t] = bt[g];
-      sh.c_rl[t] = 1.0 / L[g * ld + g];
-      sh.c_lat[t] = lattice[g];
-    }
-    // ---- steps 2-3 per 16-row sub-block, on the wave's own columns
-#pragma unroll 1
-    for (int q = 0; q < NB; ++q) {
-      const int r0 = q * kQS;
-      if (r0 >= rows) break;  // uniform
-      const int rq = min(kQS, rows - r0);
-      __syncthreads();  // buffer q % 2 is written; every wave is done with buffer (q + 1) % 2
-      const bool more = r0 + kQS < rows;
-      if (more) stg.fetch(Ld, ld, r0 + kQS, rows);  // in flight during the conditioning
-      const double* Ltri = tri_buf(q & 1);
-      const F* Lcol = col_buf(q & 1);
-      // S rows of the sub-block -> T (accumulator block ib == q)
-#pragma unroll
-      for (int ib = 0; ib < NB; ++ib) {
-        if (ib == q) {
-#pragma unroll
-          for (int jb = 0; jb < 4; ++jb)
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-              T[P::row_of(lane, r) * kQC + 64 * w + 16 * jb + (lane & 15)] = (double)acc[ib][jb][r];
-        }
-      }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      for (int i = 0; i < rq; ++i) {
-        const double* Li = Ltri + i * kQS;
-        const double* Tc = T + c;
-        double s0 = Tc[i * kQC], s1 = 0.0, s2 = 0.0, s3 = 0.0;
-        const int kend = (i + 3) & ~3;  // the triangle row is zero from column i on
-        for (int k = 0; k < kend; k += 4) {
-          s0 += Li[k] * Tc[k * kQC];
-          s1 += Li[k + 1] * Tc[(k + 1) * kQC];
-          s2 += Li[k + 2] * Tc[(k + 2) * kQC];
-          s3 += Li[k + 3] * Tc[(k + 3) * kQC];
-        }
-        const double sum = (s0 + s1) + (s2 + s3);
-        const int ri = r0 + i;
-        const double rl = sh.c_rl[ri];
-        const double alpha = (sh.c_at[ri] - sum) * rl;
-        const double beta = (sh.c_bt[ri] - sum) * rl;
-        const uint64_t gi = (uint64_t)(i0 + ri);
-        const double wq = richtmyer(jpt, sh.c_lat[ri], splitmix64(seed, sidx * (uint64_t)n + gi), periodize);
-        const Step st = P::kMixed ? condition_step_mixed_with(alpha, beta, wq, 1.0 - wq, ninv)
-                                  : condition_step_with(alpha, beta, wq, 1.0 - wq, ninv);
-        T[i * kQC + c] = valid ? st.y : 0.0;
-        logprod_mul(prod, st);
-        if constexpr (PREFIX) {
-          if (chunk64 < pre.nchunks) prefix_row(prod, valid, sidx, pre, (long)(i0 + ri));  // uniform per wave
-        }
-      }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      // later rows += L[later rows, sub-block] y_sub (K = 16)
-#pragma unroll
-      for (int ib = 1; ib < NB; ++ib) {
-        if (ib > q && 16 * ib < rows) {
-#pragma unroll
-          for (int kk = 0; kk < kQS / 4; ++kk) {
-            const int k = 4 * kk + (lane >> 4);
-            const F a = Lcol[(16 * ib - r0 - kQS + (lane & 15)) * kQS + k];
-#pragma unroll
-            for (int jb = 0; jb < 4; ++jb)
-              acc[ib][jb] = P::fold(a, (F)T[k * kQC + 64 * w + 16 * jb + (lane & 15)], acc[ib][jb]);
-          }
-        }
-      }
-      // y of the sub-block -> the Y scratch (rows past n are never read)
-      P::put_y(T, Y, ld, i0 + r0, c);
-      if (more) stg.put(tri_buf((q + 1) & 1), col_buf((q + 1) & 1), r0 + kQS);
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    }
-    __syncthreads();  // the next block's stages overwrite T and the buffers
+    quad_gemm<P>(sh, acc, i0 / P::kK, [&](int s, typename P::Regs& rg) {
+      P::load(Lg, ld, lplane, i0, (long)s * P::kK, Y, ld, rg);
+    });
+    quad_condition<P, PREFIX>(sh, acc, L + (long)i0 * ld + i0, ld, rows, i0, at, bt, lattice, seed, n, periodize, Y,
+                              ld, ln, prod);
   }
-  if (valid) ell[col] = logprod_log(prod);
+  if (ln.valid) ell[ln.col] = logprod_log(prod);
 }
 
 #define MVN_QUAD_LDS(P)                                                               \

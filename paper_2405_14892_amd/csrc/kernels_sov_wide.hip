@@ -1,14 +1,17 @@
-// The dense FP64 SOV sweep (Algorithms 2-3 with Eq. (sov1)) with 128-row
-// blocks and 128 sample columns per workgroup, two workgroups per CU.
+// The dense FP64 SOV sweep (Algorithms 2-3 with Eq. (sov1)) with 256-row
+// blocks and 128 sample columns per workgroup of eight waves, one workgroup
+// per CU.
 //
 // The limit-update GEMM S = L[r-block, 0:i0] Y[0:i0, cols] streams the
-// factor once per workgroup pass; with 128 columns per pass instead of the
-// other FP64 sweep's 64, the factor is read half as often.  The
-// accumulators of the 128 x 128 block stay in the waves' registers through
-// the in-block recurrence instead of going through a 128 x 128 LDS block
-// (which would leave room for one workgroup per CU):
-//   * in a full pass wave w holds S for all 128 rows x its 32 columns
-//     [32 w, 32 w + 32);
+// factor once per workgroup pass and the sample block Y once per block row.
+// With 128 columns per pass the factor is read half as often as by the
+// 64-column sweep, and with 256-row blocks the Y scratch half as often as
+// with 128-row ones: 48 KB of operands per K stage of a 256 x 128 x 16
+// product instead of 64 KB for two 128 x 128 x 16 ones.  The accumulators of
+// the 256 x 128 block (64 doubles per lane, as for two 128 x 128 blocks of
+// four waves) stay in the waves' registers through the in-block recurrence:
+//   * in a full pass waves 2s and 2s + 1 hold S for the 128-row halves of
+//     block x columns [32 s, 32 s + 32);
 //   * the block is conditioned in 32-row sub-blocks: the waves write the
 //     sub-block's rows of S to LDS, waves 0 and 1 (one lane per sample
 //     column, 64 columns each) run the recurrence
@@ -18,7 +21,8 @@
 //     L[later rows, sub-block] y_sub to its later rows' accumulators on MFMA,
 //     so a row's dot product runs over its own sub-block only;
 //   * y of the sub-block goes to the workgroup's Y scratch ([ld][128]).
-// The other workgroup on the CU runs its GEMM while one conditions.
+// Eight waves give two per SIMD, as two four-wave workgroups would, but they
+// share one copy of each L stage.
 //
 // Columns are dealt to the workgroups in contiguous ranges of whole
 // 32-column slices, as evenly as the slice count allows.  A workgroup sweeps
@@ -26,11 +30,11 @@
 // one of one slice; in those the waves of a slice split its rows, so all
 // four SIMDs still share the MFMA work.
 //
-// Measured against the 64-column sweep on one box: 8.78 s against 9.05 s on
-// the 65536-site field, equal (1.09 s) on the 16384-site one.  A 256 x 128
-// block at one workgroup per CU (accumulators in AGPRs) was slower (9.52 s
-// and 1.27 s): with one wave per SIMD the MFMA pipeline drains at every LDS
-// stage and during the conditioning.
+// Measured on one box: 7.79 s on the 65536-site field (70% of the FP64 MFMA
+// peak) against 8.61 s for 128 x 128 blocks at two four-wave workgroups per
+// CU, 1.09 s against 1.10 s on the 16384-site one; 128 x 256 blocks of eight
+// waves (the factor read a quarter as often, Y as often as with 128-row
+// blocks) took 9.74 s and 1.06 s.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -42,8 +46,9 @@
 
 namespace mvn {
 
+constexpr int kWT = 512;                // threads per workgroup (8 waves)
 constexpr int kWC = 128;                // sample columns of a full pass
-constexpr int kWR = 128;                // rows per block
+constexpr int kWR = 256;                // rows per block
 constexpr int kWSub = 32;               // rows per conditioning sub-block
 constexpr int kWK = 16;                 // K per LDS stage
 constexpr int kWALd = kWR + 1;          // LDS row stride of the L stage (doubles)
@@ -54,7 +59,7 @@ static_assert(kWSub * kWC + kWSub * kWSub + (kWR - kWSub) * kWSub <= kWLds,
               "the sub-block buffers alias the GEMM stages");
 
 int wide_sweep_cols() { return kWC; }
-int wide_sweep_wg_per_cu() { return 2; }
+int wide_sweep_wg_per_cu() { return 1; }
 
 // Columns of workgroup g of G: whole 32-column slices, contiguous.
 __device__ __forceinline__ long wide_col_start(long g, long G, long NS) {
@@ -73,14 +78,14 @@ struct WideShared {
 };
 
 // One pass over `ncols` (<= 32 * NSL) columns starting at global column cb,
-// NSL = 4, 2 or 1 slices of 32 columns: the 4 / NSL waves of a slice split
+// NSL = 4, 2 or 1 slices of 32 columns: the 8 / NSL waves of a slice split
 // its kWR block rows, wave w holding rows [RW (w % WPS), + RW) of slice
-// w / WPS (full pass: all rows of slice w).
+// w / WPS.
 template <int NSL>
 __device__ __forceinline__ void wide_pass(const WideShared& sh, const SweepArgs& p, double* __restrict__ Y, long cb,
                                           int ncols) {
   static_assert(NSL == 4 || NSL == 2 || NSL == 1, "slices per pass");
-  constexpr int WPS = 4 / NSL;                   // waves per slice
+  constexpr int WPS = 8 / NSL;                   // waves per slice
   constexpr int RW = kWR / WPS;                  // rows per wave
   constexpr int NIB = RW / 16;
   constexpr int BC = 32 * NSL;                   // columns staged per K step
@@ -117,9 +122,9 @@ __device__ __forceinline__ void wide_pass(const WideShared& sh, const SweepArgs&
       const int nst = i0 / kWK;
       // lane t: A row t / 2, k (t % 2) * 8 .. + 8; B: k t / (BC / 8), columns
       // (t % (BC / 8)) * 8 .. + 8
-      constexpr int kBLanes = BC / 8 * kWK;  // lanes that load B (all 256 in a full pass)
+      constexpr int kBLanes = BC / 8 * kWK;  // lanes that load B (256 of the 512 in a full pass)
       // (ld is a multiple of the block rows; the clamp only guards it)
-      constexpr int kEA = kWR * kWK / 256;  // A doubles per lane
+      constexpr int kEA = kWR * kWK / kWT;  // A doubles per lane
       const double* pa = L + (long)min((long)(i0 + t / (kWK / kEA)), ld - 1) * ld + (t % (kWK / kEA)) * kEA;
       const double* pb = Y + (long)(t / (BC / 8)) * kWC + (t % (BC / 8)) * 8;
       double ra[kEA], rb[8];
@@ -207,12 +212,12 @@ __device__ __forceinline__ void wide_pass(const WideShared& sh, const SweepArgs&
       }
       // the sub-block's triangle of L and the rows below it, sub-block columns
       const double* Lq = L + (long)(i0 + r0) * ld + i0 + r0;
-      for (int e = t; e < kWSub * kWSub; e += 256) {
+      for (int e = t; e < kWSub * kWSub; e += kWT) {
         const int ii = e / kWSub, k = e % kWSub;
         Ltri[e] = k < ii ? Lq[(long)ii * ld + k] : 0.0;
       }
       const int below = kWR - r0 - kWSub;
-      for (int e = t; e < below * kWSub; e += 256) {
+      for (int e = t; e < below * kWSub; e += kWT) {
         const int ii = e / kWSub, k = e % kWSub;
         Lcol[e] = i0 + r0 + kWSub + ii < ld ? Lq[(long)(kWSub + ii) * ld + k] : 0.0;
       }
@@ -261,7 +266,7 @@ __device__ __forceinline__ void wide_pass(const WideShared& sh, const SweepArgs&
         }
       }
       // y of the sub-block -> Y scratch rows i0 + r0 .. (the pass's columns)
-      for (int e = t; e < kWSub * BC / 2; e += 256) {
+      for (int e = t; e < kWSub * BC / 2; e += kWT) {
         const int r = e / (BC / 2), c2 = e % (BC / 2);
         reinterpret_cast<double2*>(Y + (long)(i0 + r0 + r) * kWC)[c2] = reinterpret_cast<const double2*>(T + r * kWC)[c2];
       }
@@ -271,7 +276,7 @@ __device__ __forceinline__ void wide_pass(const WideShared& sh, const SweepArgs&
   if (valid) p.ell[gcol] = logprod_log(prod);
 }
 
-__global__ __launch_bounds__(256, 2) void wide_sweep_kernel(SweepArgs p) {
+__global__ __launch_bounds__(kWT, 1) void wide_sweep_kernel(SweepArgs p) {
   __shared__ __attribute__((aligned(16))) double lds[kWLds];
   __shared__ double c_at[kWR], c_bt[kWR], c_rl[kWR];
   __shared__ uint64_t c_lat[kWR];
@@ -297,7 +302,7 @@ __global__ __launch_bounds__(256, 2) void wide_sweep_kernel(SweepArgs p) {
 }
 
 hipError_t launch_wide_sweep(const SweepArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(wide_sweep_kernel, dim3(a.grid), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(wide_sweep_kernel, dim3(a.grid), dim3(kWT), 0, st, a);
   return hipGetLastError();
 }
 
