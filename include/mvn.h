@@ -259,6 +259,23 @@ int mvn_prob_prefix(const mvn_factor* f, const double* d_a, const double* d_b, c
                     int N, int S, uint64_t seed, const mvn_options* opts, void* ws, size_t ws_bytes,
                     double* d_prefix, hipStream_t stream);
 
+/* The site order of Algorithm 1 (Section IV-A) for confidence-region
+ * detection: sites by decreasing marginal exceedance probability
+ * p_i = Phi((mu_i - u) / sqrt(var_i)), ties by increasing site index (a
+ * variance <= 0 gives p_i = 1 if mu_i > u, else 0).  For a posterior the
+ * inputs are mvn_posterior's mu_post and var_post, and d_perm goes straight
+ * to mvn_cholesky_permuted, so the workflow never reads back.
+ *   d_mu, d_var  device, n doubles
+ *   d_perm       device output, n int64 site indices; all -1 if a variance
+ *                is NaN or a mean is not finite
+ *   d_p          device output, n doubles (p_i in site order), or NULL
+ *   ws           device workspace of mvn_exceedance_order_workspace_bytes
+ *                (16 bytes per element of the next power of two >= n)
+ * A bitonic sort on the device; asynchronous on `stream`. */
+int mvn_exceedance_order_workspace_bytes(int n, size_t* bytes);
+int mvn_exceedance_order(int n, const double* d_mu, const double* d_var, double u, int64_t* d_perm, double* d_p,
+                         void* ws, size_t ws_bytes, hipStream_t stream);
+
 /* The TLR factor in dense form: the configuration of Section IV-C, where
  * the factorisation is tile low-rank (Section III-E) and the SOV sweep of
  * Algorithm 2 runs on dense tiles.  Writes L into d_buf as a dense FP64

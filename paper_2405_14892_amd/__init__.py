@@ -19,7 +19,7 @@ from ._lib import (MVN_BF16, MVN_BF16X3, MVN_CHOL_ADAPTIVE, MVN_CHOL_FP64, MVN_C
 __all__ = ["mvn_factor_bytes", "mvn_cholesky_workspace_bytes", "mvn_prob_workspace_bytes",
            "mvn_prob_workspace_bytes_factor", "mvn_cholesky", "mvn_prob", "mvn_prob_static", "Factor",
            "mvn_prob_prefix_workspace_bytes", "mvn_prob_prefix", "confidence_region",
-           "mvn_mc_prefix_workspace_bytes", "mvn_mc_prefix", "mvn_cholesky_permuted", "mvn_tlr_dense", "mvn_posterior",
+           "mvn_mc_prefix_workspace_bytes", "mvn_mc_prefix", "mvn_cholesky_permuted", "mvn_tlr_dense", "mvn_exceedance_order", "mvn_posterior",
            "posterior_confidence_region",
            "mvn_prob_grad_workspace_bytes", "mvn_prob_grad", "MVNLogProb", "BatchPlan",
            "mvn_batch_plan", "mvn_prob_batch",
@@ -213,7 +213,10 @@ def mvn_cholesky_permuted(sigma, perm, opts: MvnOptions | None = None) -> Factor
     if sigma.dtype != torch.float64 or sigma.stride(1) != 1 or sigma.shape[1] != n:
         raise MvnError(-2, "sigma must be a float64 n x n tensor with unit column stride")
     dev = sigma.device
-    dp = torch.as_tensor(np.asarray(perm.cpu() if hasattr(perm, "cpu") else perm, dtype=np.int64)).to(dev)
+    if isinstance(perm, torch.Tensor) and perm.device == dev and perm.dtype == torch.int64:
+        dp = perm.contiguous()  # a device order (mvn_exceedance_order) is used as it is, no read-back
+    else:
+        dp = torch.as_tensor(np.asarray(perm.cpu() if hasattr(perm, "cpu") else perm, dtype=np.int64)).to(dev)
     if dp.shape != (n,):
         raise MvnError(-4, "perm must have n entries")
     fb = mvn_factor_bytes(n, opts)
@@ -426,6 +429,27 @@ def confidence_region(locs, kern: tuple, mu, u: float, alpha: float = 0.05, N: i
     return out
 
 
+def mvn_exceedance_order(mu, var, u: float, device="cuda"):
+    """Sites by decreasing marginal exceedance probability Phi((mu - u) /
+    sqrt(var)), ties by index (Algorithm 1's order), computed on the device.
+    Returns device tensors (perm int64, p float64 in site order)."""
+    torch = _torch()
+    tm = _dev_f64(mu, device)
+    tv = _dev_f64(var, device)
+    n = tm.numel()
+    if tv.numel() != n:
+        raise MvnError(-3, "mu and var must have the same length")
+    wb = ctypes.c_size_t(0)
+    _lib.check(_lib.lib().mvn_exceedance_order_workspace_bytes(n, ctypes.byref(wb)))
+    ws = torch.empty(wb.value, dtype=torch.uint8, device=tm.device)
+    perm = torch.empty(n, dtype=torch.int64, device=tm.device)
+    p = torch.empty(n, dtype=torch.float64, device=tm.device)
+    _lib.check(_lib.lib().mvn_exceedance_order(n, _ptr(tm), _ptr(tv), float(u), _ptr(perm), _ptr(p), _ptr(ws),
+                                               wb.value, _stream(tm.device)))
+    perm._keep = (tm, tv, ws)
+    return perm, p
+
+
 def posterior_confidence_region(locs, kern: tuple, obs, y, noise_var: float, u: float, alpha: float = 0.05,
                                 mu=None, N: int = 1000, S: int = 10, seed: int = 1,
                                 opts: MvnOptions | None = None, device="cuda", mc_samples: int = 0,
@@ -437,22 +461,26 @@ def posterior_confidence_region(locs, kern: tuple, obs, y, noise_var: float, u: 
     optionally the Monte Carlo check (through the dense factor).  Returns the keys of
     confidence_region plus ``mu_post`` and ``sd_post`` (caller's order)."""
     import numpy as np
-    from scipy.special import ndtr
+    torch = _torch()
     opts = opts or options()
     po = options(tile=opts.tile)  # the posterior itself is FP64 and dense
     post = mvn_posterior(locs, kern, obs, y, noise_var, mu=mu, opts=po, device=device)
     if post["info"] != 0:
         raise MvnError(-7, f"observation covariance not positive definite (pivot {post['info']})")
+    n = post["mu_post"].numel()
+    # the order, the permuted factor and the nested-set sweep stay on the device
+    dorder, dpm = mvn_exceedance_order(post["mu_post"], post["var_post"], u, device=device)
+    f = mvn_cholesky_permuted(post["sigma_post"], dorder, opts=opts)
+    dmo = post["mu_post"][dorder]
+    r = mvn_prob_prefix(f, torch.full((n,), float(u), dtype=torch.float64, device=dmo.device),
+                        torch.full((n,), float("inf"), dtype=torch.float64, device=dmo.device), dmo, N=N, S=S,
+                        seed=seed, opts=opts)
+    logp = r["logP"].cpu().numpy()
+    order = dorder.cpu().numpy()
+    pm = dpm.cpu().numpy()
     mu_post = post["mu_post"].cpu().numpy()
     sd_post = np.sqrt(np.maximum(post["var_post"].cpu().numpy(), 0.0))
-    n = mu_post.size
-    with np.errstate(divide="ignore", invalid="ignore"):
-        pm = ndtr(np.where(sd_post > 0, (mu_post - u) / sd_post, np.where(mu_post > u, np.inf, -np.inf)))
-    order = np.argsort(-pm, kind="stable")
-    f = mvn_cholesky_permuted(post["sigma_post"], order, opts=opts)
     mo = mu_post[order]
-    r = mvn_prob_prefix(f, np.full(n, float(u)), np.full(n, np.inf), mo, N=N, S=S, seed=seed, opts=opts)
-    logp = r["logP"].cpu().numpy()
     excursion = np.empty(n)
     excursion[order] = np.exp(logp)
     k = int(np.sum(np.exp(logp) >= 1.0 - alpha))

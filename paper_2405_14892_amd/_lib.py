@@ -83,6 +83,9 @@ SIGNATURES = {
     "mvn_prob_batch": (c_int, [c_int, c_void_p, c_void_p, c_void_p, c_void_p, POINTER(MvnMatern), c_void_p,
                                c_void_p, c_void_p, c_int, c_int, c_uint64, POINTER(MvnOptions), c_void_p,
                                c_size_t, c_void_p, c_size_t, c_void_p, c_void_p, c_void_p]),
+    "mvn_exceedance_order_workspace_bytes": (c_int, [c_int, POINTER(c_size_t)]),
+    "mvn_exceedance_order": (c_int, [c_int, c_void_p, c_void_p, c_double, c_void_p, c_void_p, c_void_p, c_size_t,
+                                     c_void_p]),
     "mvn_tlr_dense_bytes": (c_int, [POINTER(MvnFactor), POINTER(c_size_t)]),
     "mvn_tlr_dense": (c_int, [POINTER(MvnFactor), c_void_p, c_size_t, POINTER(MvnFactor), c_void_p]),
     "mvn_last_error": (ctypes.c_char_p, []),

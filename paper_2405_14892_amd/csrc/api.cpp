@@ -1072,6 +1072,41 @@ int mvn_prob(const mvn_factor* f, const double* d_a, const double* d_b, const do
   return dense_sweep(f, d_a, d_b, d_mu, N, S, seed, opts, ws, Lay, d_ell, nullptr, d_out, stream);
 }
 
+size_t exceed_ws(int n, size_t* key, size_t* idx, size_t* bad) {
+  const size_t npad = (size_t)mvn::exceedance_npad(n);
+  size_t off = 0;
+  *key = off; off = align_up(off + sizeof(double) * npad);
+  *idx = off; off = align_up(off + sizeof(int64_t) * npad);
+  *bad = off; off = align_up(off + sizeof(int));
+  return off;
+}
+
+int mvn_exceedance_order_workspace_bytes(int n, size_t* bytes) {
+  if (n < 1) return fail(-1, "n must be >= 1 (got %d)", n);
+  if (!bytes) return fail(-2, "bytes is NULL");
+  size_t k, i, b;
+  *bytes = exceed_ws(n, &k, &i, &b);
+  return 0;
+}
+
+int mvn_exceedance_order(int n, const double* d_mu, const double* d_var, double u, int64_t* d_perm, double* d_p,
+                         void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (n < 1) return fail(-1, "n must be >= 1 (got %d)", n);
+  if (!d_mu) return fail(-2, "mean is NULL");
+  if (!d_var) return fail(-3, "variances are NULL");
+  if (!isfinite(u)) return fail(-4, "u must be finite");
+  if (!d_perm) return fail(-5, "output permutation is NULL");
+  size_t k, i, b;
+  const size_t need = exceed_ws(n, &k, &i, &b);
+  if (!ws) return fail(-7, "workspace is NULL");
+  if (ws_bytes < need) return fail(-8, "workspace too small: %zu < %zu", ws_bytes, need);
+  char* w = (char*)ws;
+  const hipError_t e = mvn::launch_exceedance_order(n, d_mu, d_var, u, (double*)(w + k), (int64_t*)(w + i),
+                                                    (int*)(w + b), d_p, d_perm, stream);
+  if (e != hipSuccess) return hip_fail(e, "exceedance order");
+  return 0;
+}
+
 int mvn_tlr_dense_bytes(const mvn_factor* f, size_t* bytes) {
   if (!bytes) return fail(-2, "bytes is NULL");
   if (!f || !(f->flags & MVN_FACTOR_TLR) || f->n < 1) return fail(-1, "not a TLR factor handle");

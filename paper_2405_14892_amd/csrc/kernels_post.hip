@@ -90,4 +90,84 @@ hipError_t launch_posterior(const PosteriorArgs& p, int tile, double* mu_post, d
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------ exceedance order
+// The site order of Algorithm 1 (Section IV-A): decreasing marginal
+// exceedance probability p_i = Phi((mu_i - u) / sd_i), ties by increasing
+// site index.  Keys are the pairs (-p_i, i) in ascending lexicographic order,
+// which makes the order total; they are sorted by a bitonic network over
+// npad = the next power of two (padding keys (+inf, i) sort last), one
+// launch per compare-exchange stage, each thread owning one pair of
+// elements.  A variance <= 0 gives p = 1 if mu_i > u, else 0; a NaN
+// variance or a non-finite mean sets *bad.
+__global__ __launch_bounds__(256) void exceed_keys_kernel(int n, long npad, const double* __restrict__ mu,
+                                                          const double* __restrict__ var, double u,
+                                                          double* __restrict__ key, int64_t* __restrict__ idx,
+                                                          double* __restrict__ p_out, int* __restrict__ bad) {
+  const long i = (long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= npad) return;
+  if (i < n) {
+    const double v = var[i], m = mu[i];
+    const bool ok = !isnan(v) && isfinite(m);
+    // a variance at or below zero (a site known exactly, up to rounding) gives p = 1 above u, else 0
+    const double p = !ok ? NAN
+                         : v > 0.0 ? 0.5 * erfc(-(m - u) / sqrt(v) * 0.70710678118654752440)
+                                   : (m > u ? 1.0 : 0.0);
+    if (!ok) atomicExch(bad, 1);
+    key[i] = ok ? -p : INFINITY;
+    if (p_out) p_out[i] = p;
+  } else {
+    key[i] = INFINITY;
+  }
+  idx[i] = i;
+}
+
+__global__ __launch_bounds__(256) void bitonic_step_kernel(long npad, long j, long k, double* __restrict__ key,
+                                                           int64_t* __restrict__ idx) {
+  const long t = (long)blockIdx.x * 256 + threadIdx.x;  // one per pair
+  if (t >= npad / 2) return;
+  const long i = 2 * t - (t & (j - 1));  // the lower element: bit log2(j) clear
+  const long l = i + j;
+  const bool up = (i & k) == 0;          // ascending block
+  const double ki = key[i], kl = key[l];
+  const int64_t ii = idx[i], il = idx[l];
+  const bool gt = ki > kl || (ki == kl && ii > il);
+  if (gt == up) {
+    key[i] = kl;
+    key[l] = ki;
+    idx[i] = il;
+    idx[l] = ii;
+  }
+}
+
+__global__ void exceed_flag_kernel(int* __restrict__ bad) {
+  if (threadIdx.x == 0) *bad = 0;
+}
+
+__global__ __launch_bounds__(256) void exceed_out_kernel(int n, const int64_t* __restrict__ idx,
+                                                         const int* __restrict__ bad, int64_t* __restrict__ perm) {
+  const long i = (long)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) perm[i] = *bad ? -1 : idx[i];
+}
+
+long exceedance_npad(int n) {
+  long p = 1;
+  while (p < n) p <<= 1;
+  return p;
+}
+
+hipError_t launch_exceedance_order(int n, const double* mu, const double* var, double u, double* key, int64_t* idx,
+                                   int* bad, double* p_out, int64_t* perm, hipStream_t st) {
+  const long npad = exceedance_npad(n);
+  hipLaunchKernelGGL(exceed_flag_kernel, dim3(1), dim3(64), 0, st, bad);
+  hipLaunchKernelGGL(exceed_keys_kernel, dim3((unsigned)((npad + 255) / 256)), dim3(256), 0, st, n, npad, mu, var, u,
+                     key, idx, p_out, bad);
+  const unsigned g = (unsigned)((npad / 2 + 255) / 256);
+  for (long k = 2; k <= npad; k <<= 1)
+    for (long j = k >> 1; j > 0; j >>= 1)
+      hipLaunchKernelGGL(bitonic_step_kernel, dim3(g > 0 ? g : 1), dim3(256), 0, st, npad, j, k, key, idx);
+  hipLaunchKernelGGL(exceed_out_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, (const int64_t*)idx,
+                     (const int*)bad, perm);
+  return hipGetLastError();
+}
+
 }  // namespace mvn

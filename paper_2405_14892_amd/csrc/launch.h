@@ -112,6 +112,13 @@ struct PosteriorArgs {
   int* info;               // non-positive pivot of K (1-based), 0 if none
 };
 hipError_t launch_posterior(const PosteriorArgs& p, int tile, double* mu_post, double* var_post, hipStream_t st);
+// Sites by decreasing Phi((mu_i - u) / sqrt(var_i)), ties by index, into perm
+// (n entries; all -1 if a variance is not positive or an input is not
+// finite); key / idx: npad scratch entries each (npad = the next power of
+// two >= n), bad: one int; p_out (n, optional) receives the probabilities.
+long exceedance_npad(int n);
+hipError_t launch_exceedance_order(int n, const double* mu, const double* var, double u, double* key, int64_t* idx,
+                                   int* bad, double* p_out, int64_t* perm, hipStream_t st);
 
 struct SweepArgs {
   const double* L;         // FP64 factor (diagonal blocks, pivots)

@@ -133,3 +133,34 @@ def test_rejections():
         f = mvn.mvn_cholesky_permuted(post["sigma_post"], np.arange(n)[::-1].copy(), opts=oo)
         torch.cuda.synchronize()
         assert f.info() == 0
+
+
+def test_exceedance_order_on_the_device():
+    """Algorithm 1's order computed on the device: equal to the oracle's
+    (decreasing Phi((mu - u) / sd), ties by index) on 5000 sites with exact
+    ties, zero variances (p = 1 above u, else 0) and a non-power-of-two
+    size; p to 1e-15 against the oracle's; a NaN variance gives all -1."""
+    rng = np.random.default_rng(9)
+    n, u = 5000, 0.3
+    mu = rng.normal(0.0, 1.0, n)
+    var = rng.uniform(0.05, 2.0, n)
+    mu[100:120], var[100:120] = 0.7, 0.5        # 20 exact ties
+    mu[200:210], var[200:210] = 1.0, 0.0        # known above u: p = 1
+    mu[300:310], var[300:310] = -1.0, 0.0       # known below u: p = 0
+    perm, p = mvn.mvn_exceedance_order(mu, var, u, device=DEV)
+    torch.cuda.synchronize()
+    sd = np.sqrt(np.maximum(var, 0.0))
+    with np.errstate(divide="ignore", invalid="ignore"):
+        ref_order = oracle.exceedance_order(mu, sd, u)
+    from scipy.special import ndtr
+    with np.errstate(divide="ignore", invalid="ignore"):
+        pref = ndtr(np.where(sd > 0, (mu - u) / sd, np.where(mu > u, np.inf, -np.inf)))
+    got = perm.cpu().numpy()
+    assert np.array_equal(np.sort(got), np.arange(n))
+    assert np.array_equal(got, ref_order)
+    np.testing.assert_allclose(p.cpu().numpy(), pref, rtol=1e-14, atol=1e-300)
+    var[7] = np.nan
+    perm, _ = mvn.mvn_exceedance_order(mu, var, u, device=DEV)
+    assert np.all(perm.cpu().numpy() == -1)
+    perm, p = mvn.mvn_exceedance_order(np.array([2.0]), np.array([1.0]), u, device=DEV)
+    assert perm.cpu().numpy().tolist() == [0]
