@@ -299,6 +299,42 @@ def _tlr_dense_sweep(p, w, dev) -> dict:
     return {"expand_ms": e[0].elapsed_time(e[1]), "sov_ms": e[1].elapsed_time(e[2]), "logP": float(res[0])}
 
 
+def _tlr_compact_sweep(p, w, dev) -> dict:
+    """The TLR factor held by Problem p cut to its ranks (mvn_tlr_compact),
+    then 3 timed TLR sweeps through it after a warm-up: the factor and
+    workspace sizes beside those of the full factor."""
+    import torch
+    lib, h, P = p.lib, p.h, p._p
+    nb = ctypes.c_size_t(0)
+    lib.check(h.mvn_tlr_compact_bytes(ctypes.byref(p.fac), ctypes.byref(nb), p.sp))
+    cbuf = torch.empty(nb.value, dtype=torch.uint8, device=dev)
+    cfac = lib.MvnFactor()
+    lib.check(h.mvn_tlr_compact(ctypes.byref(p.fac), P(cbuf), nb.value, ctypes.byref(cfac), p.sp))
+    wsb = ctypes.c_size_t(0)
+    lib.check(h.mvn_prob_workspace_bytes_factor(ctypes.byref(cfac), w.N, w.S, ctypes.byref(p.opts),
+                                                ctypes.byref(wsb), p.sp))
+    p.ws = None
+    _free()
+    ws = torch.empty(wsb.value, dtype=torch.uint8, device=dev)
+    out = torch.empty(4 + w.S, dtype=torch.float64, device=dev)
+    ms = []
+    for it in range(4):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        torch.cuda.synchronize()
+        e[0].record(p.stream)
+        lib.check(h.mvn_prob(ctypes.byref(cfac), P(p.a), P(p.b), P(p.mu), w.N, w.S, ctypes.c_uint64(w.seed),
+                             ctypes.byref(p.opts), P(ws), wsb.value, P(out), None, p.sp))
+        e[1].record(p.stream)
+        torch.cuda.synchronize()
+        if it > 0:
+            ms.append(e[0].elapsed_time(e[1]))
+    res = out.cpu().numpy()
+    del cbuf, ws
+    _free()
+    return {"factor_bytes_full": p.fb, "factor_bytes_compact": nb.value, "workspace_bytes": wsb.value,
+            "sov_ms": sorted(ms)[len(ms) // 2], "logP": float(res[0])}
+
+
 def variant_tlr(dev, dense=None) -> dict:
     """The 65536-site problem with a tile low-rank factor at 1e-5 and 1e-7,
     each timed over 3 steps after a warm-up (default sweep block shape),
@@ -323,6 +359,8 @@ def variant_tlr(dev, dense=None) -> dict:
         p = Problem(w, mvn.options(tile=w.tile, tlr_eps=eps, max_rank=256), dev)
         r = p.run(3, 1)
         ranks, ld = np.abs(p.ranks()), p.fac.ld
+        full_ws = p.wsb
+        csw = _tlr_compact_sweep(p, w, dev)
         dsw = _tlr_dense_sweep(p, w, dev)
         del p
         _free()
@@ -339,6 +377,11 @@ def variant_tlr(dev, dense=None) -> dict:
             "sweep_speedup_vs_dense": dense["sov_ms"] / r["sov_ms"],
             "effective_tflops": (chol_f + sov_f) / (r["wall_ms"] * 1e-3) / 1e12,
             "sweep_executed_tflops": sweep_exec / (r["sov_ms"] * 1e-3) / 1e12,
+            "compact_factor": {
+                "factor_bytes_full": csw["factor_bytes_full"], "factor_bytes_compact": csw["factor_bytes_compact"],
+                "workspace_bytes_full": full_ws, "workspace_bytes_compact": csw["workspace_bytes"],
+                "sov_ms": csw["sov_ms"], "abs_dlogP_vs_full": abs(csw["logP"] - r["logP"]),
+                "note": "diagonal tiles and U, V'^T at the actual ranks (mvn_tlr_compact); median of 3 sweeps"},
             "tlr_cholesky_dense_sweep": {
                 "expand_ms": dsw["expand_ms"], "sov_ms": dsw["sov_ms"],
                 "wall_ms": r["cholesky_ms"] + dsw["expand_ms"] + dsw["sov_ms"],

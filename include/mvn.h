@@ -116,11 +116,22 @@ typedef struct mvn_options {
  *   ranks  device int per panel; negative when max_rank stopped the
  *          compression before the residual reached tlr_eps. */
 #define MVN_FACTOR_TLR 1
+/* Compact TLR factor (flags == MVN_FACTOR_TLR | MVN_FACTOR_TLR_COMPACT, from
+ * mvn_tlr_compact): only what the sweep reads, at the actual ranks.
+ *   L      the nt diagonal tiles, tile i at i m^2 doubles (row-major, m)
+ *   Vt     the V'^T rows of every panel (i, j), i > j, stacked by tile
+ *          column j in order of i (sum of the ranks rows of m doubles), then
+ *          128 zero rows
+ *   U      per tile-row i the U columns of its panels side by side (m rows
+ *          of Kpad_i doubles, Kpad_i = the sum of the row's ranks rounded up
+ *          to 16, zero columns past it), tile-rows one after another
+ *   ranks  as above (a copy) */
+#define MVN_FACTOR_TLR_COMPACT 2
 typedef struct mvn_factor {
   int n;
   int ld;           /* dense: padded n; TLR: nt * tile                         */
   int precision;    /* arithmetic the factor was built with (mvn_precision)    */
-  int flags;        /* MVN_FACTOR_TLR or 0                                     */
+  int flags;        /* 0, MVN_FACTOR_TLR, or MVN_FACTOR_TLR | ..._COMPACT     */
   double* L;        /* device: dense ld*ld doubles, or the TLR tiles           */
   int* info;        /* device, 1 int                                           */
   void* L_low;      /* device copy of L as the sweep's GEMM operand: ld*ld     */
@@ -275,6 +286,21 @@ int mvn_prob_prefix(const mvn_factor* f, const double* d_a, const double* d_b, c
 int mvn_exceedance_order_workspace_bytes(int n, size_t* bytes);
 int mvn_exceedance_order(int n, const double* d_mu, const double* d_var, double u, int64_t* d_perm, double* d_p,
                          void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* A TLR factor with its storage cut to the ranks (the representation of
+ * Section III-E keeps only the diagonal tiles and the low-rank factors):
+ * the diagonal tiles and U, V'^T packed at the actual ranks in the order the
+ * sweep reads them (layout at MVN_FACTOR_TLR_COMPACT), about 2 m^2 per tile
+ * column plus 16 m bytes per unit of rank instead of nt(nt+1)/2 dense tiles
+ * and U, V'^T at the rank stride.  mvn_prob and mvn_prob_prefix accept the
+ * compact factor and give bit-identical results (they read the packed
+ * factors directly instead of packing them per call); mvn_tlr_dense does
+ * not take it.  Both calls read the ranks back, which synchronises `stream`
+ * (a one-time step after the factorisation); *out shares nothing with f,
+ * whose buffer may then be freed.
+ *   d_buf / bytes   device memory, at least mvn_tlr_compact_bytes */
+int mvn_tlr_compact_bytes(const mvn_factor* f, size_t* bytes, hipStream_t stream);
+int mvn_tlr_compact(const mvn_factor* f, void* d_buf, size_t bytes, mvn_factor* out, hipStream_t stream);
 
 /* The TLR factor in dense form: the configuration of Section IV-C, where
  * the factorisation is tile low-rank (Section III-E) and the SOV sweep of

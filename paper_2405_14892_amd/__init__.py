@@ -19,7 +19,7 @@ from ._lib import (MVN_BF16, MVN_BF16X3, MVN_CHOL_ADAPTIVE, MVN_CHOL_FP64, MVN_C
 __all__ = ["mvn_factor_bytes", "mvn_cholesky_workspace_bytes", "mvn_prob_workspace_bytes",
            "mvn_prob_workspace_bytes_factor", "mvn_cholesky", "mvn_prob", "mvn_prob_static", "Factor",
            "mvn_prob_prefix_workspace_bytes", "mvn_prob_prefix", "confidence_region",
-           "mvn_mc_prefix_workspace_bytes", "mvn_mc_prefix", "mvn_cholesky_permuted", "mvn_tlr_dense", "mvn_exceedance_order", "mvn_posterior",
+           "mvn_mc_prefix_workspace_bytes", "mvn_mc_prefix", "mvn_cholesky_permuted", "mvn_tlr_dense", "mvn_tlr_compact", "mvn_exceedance_order", "mvn_posterior",
            "posterior_confidence_region",
            "mvn_prob_grad_workspace_bytes", "mvn_prob_grad", "MVNLogProb", "BatchPlan",
            "mvn_batch_plan", "mvn_prob_batch",
@@ -97,6 +97,14 @@ class Factor:
     @property
     def is_tlr(self) -> bool:
         return bool(self.handle.flags & MVN_FACTOR_TLR)
+
+    @property
+    def is_compact(self) -> bool:
+        return bool(self.handle.flags & _lib.MVN_FACTOR_TLR_COMPACT)
+
+    def nbytes(self) -> int:
+        """Bytes of the device buffer that holds the factor."""
+        return self.buffer.numel()
 
     def _view(self, ptr: int, count: int, dtype):
         torch = _torch()
@@ -180,6 +188,23 @@ def mvn_cholesky(n: int, sigma=None, locs=None, kern: tuple | None = None,
     f = Factor(h, buf, device)
     f._keep = (s, lc, ws)  # inputs and workspace must outlive the asynchronous launch
     return f
+
+
+def mvn_tlr_compact(f: Factor) -> Factor:
+    """The TLR factor ``f`` with its storage cut to the ranks: the diagonal
+    tiles and U, V'^T packed at the actual ranks (reads the ranks back, which
+    synchronises the current stream).  The result owns its own buffer; f
+    may be dropped afterwards."""
+    torch = _torch()
+    if not f.is_tlr or f.is_compact:
+        raise MvnError(-1, "not a full TLR factor")
+    nb = ctypes.c_size_t(0)
+    _lib.check(_lib.lib().mvn_tlr_compact_bytes(ctypes.byref(f.handle), ctypes.byref(nb), _stream(f.device)))
+    buf = torch.empty(nb.value, dtype=torch.uint8, device=f.device)
+    h = MvnFactor()
+    _lib.check(_lib.lib().mvn_tlr_compact(ctypes.byref(f.handle), _ptr(buf), nb.value, ctypes.byref(h),
+                                          _stream(f.device)))
+    return Factor(h, buf, f.device)
 
 
 def mvn_tlr_dense(f: Factor) -> Factor:

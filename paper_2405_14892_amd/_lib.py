@@ -28,6 +28,7 @@ class MvnOptions(ctypes.Structure):
 
 
 MVN_FACTOR_TLR = 1
+MVN_FACTOR_TLR_COMPACT = 2
 
 
 class MvnFactor(ctypes.Structure):
@@ -86,6 +87,8 @@ SIGNATURES = {
     "mvn_exceedance_order_workspace_bytes": (c_int, [c_int, POINTER(c_size_t)]),
     "mvn_exceedance_order": (c_int, [c_int, c_void_p, c_void_p, c_double, c_void_p, c_void_p, c_void_p, c_size_t,
                                      c_void_p]),
+    "mvn_tlr_compact_bytes": (c_int, [POINTER(MvnFactor), POINTER(c_size_t), c_void_p]),
+    "mvn_tlr_compact": (c_int, [POINTER(MvnFactor), c_void_p, c_size_t, POINTER(MvnFactor), c_void_p]),
     "mvn_tlr_dense_bytes": (c_int, [POINTER(MvnFactor), POINTER(c_size_t)]),
     "mvn_tlr_dense": (c_int, [POINTER(MvnFactor), c_void_p, c_size_t, POINTER(MvnFactor), c_void_p]),
     "mvn_last_error": (ctypes.c_char_p, []),

@@ -303,16 +303,20 @@ struct TlrProbLayout {
   ProbLayout base;
   size_t kk, zcol, kpad0, kval, vrow0, ucol0, zdst, hdr, fixed;
   long yslice;
-  int grid;  // launch grid (the device runs as many as the region holds)
+  int grid;       // launch grid (the device runs as many as the region holds)
+  bool ext_pack;  // compact factor: the packed operands are the factor's, not in the region
   size_t dyn_bytes(long ksum, long kpad, long g, int m) const {
     const size_t kp = kpad > 0 ? (size_t)kpad : 1;
-    const size_t ysc = align_up(8 * (size_t)(ksum + 128) * m) + align_up(8 * (size_t)m * kp);
+    const size_t ysc = ext_pack ? 0 : align_up(8 * (size_t)(ksum + 128) * m) + align_up(8 * (size_t)m * kp);
     return ysc + (size_t)g * (align_up(8 * (size_t)yslice) + align_up(8 * kp * mvn::sweep_tile_cols()));
   }
 };
 
-TlrProbLayout tlr_prob_layout(int ld, int nt, int rs, int N, int S, int rows) {
+bool is_compact(const mvn_factor* f) { return (f->flags & MVN_FACTOR_TLR_COMPACT) != 0; }
+
+TlrProbLayout tlr_prob_layout(int ld, int nt, int rs, int N, int S, int rows, bool ext_pack = false) {
   TlrProbLayout L{};
+  L.ext_pack = ext_pack;
   L.base = prob_layout_ld(ld, N, S, MVN_FP64, 0, rows);
   const size_t np = (size_t)nt * (nt - 1) / 2;
   const size_t np1 = np > 0 ? np : 1;
@@ -526,7 +530,8 @@ int tlr_sweep_call(const mvn_factor* f, const double* d_a, const double* d_b, co
   const int rows = tlr_sweep_rows(opts);
   const int n = f->n, m = f->tile, nt = f->ld / f->tile, rs = f->rank_stride;
   const int np = nt * (nt - 1) / 2;
-  const TlrProbLayout Lay = tlr_prob_layout(f->ld, nt, rs, N, S, rows);
+  const bool compact = is_compact(f);
+  const TlrProbLayout Lay = tlr_prob_layout(f->ld, nt, rs, N, S, rows, compact);
   const size_t least = Lay.fixed + Lay.dyn_bytes(0, 0, 1, m);
   if (ws_bytes < least)
     return fail(-10, "workspace too small: %zu bytes hold no sweep workgroup (at least %zu)", ws_bytes, least);
@@ -550,6 +555,7 @@ int tlr_sweep_call(const mvn_factor* f, const double* d_a, const double* d_b, co
   tb.nt = nt;
   tb.rs = rs;
   tb.m = m;
+  tb.ext_pack = compact ? 1 : 0;
   tb.yslice = Lay.yslice;
   tb.grid_max = Lay.grid;
   tb.dyn_bytes = ws_bytes - Lay.fixed;
@@ -577,8 +583,10 @@ int tlr_sweep_call(const mvn_factor* f, const double* d_a, const double* d_b, co
   pa.kval = tb.kval;
   pa.hdr = hdr;
   pa.dyn = dyn;
-  e = mvn::launch_tlr_pack(pa, stream);
-  if (e != hipSuccess) return hip_fail(e, "tlr pack");
+  if (!compact) {
+    e = mvn::launch_tlr_pack(pa, stream);
+    if (e != hipSuccess) return hip_fail(e, "tlr pack");
+  }
   mvn::TlrSweepArgs ta{};
   ta.tiles = f->L;
   ta.hdr = hdr;
@@ -602,6 +610,9 @@ int tlr_sweep_call(const mvn_factor* f, const double* d_a, const double* d_b, co
   ta.grid = Lay.grid;
   ta.rows = rows;
   ta.prefix = prefix;
+  ta.vpack_ext = compact ? f->Vt : nullptr;
+  ta.upack_ext = compact ? f->U : nullptr;
+  ta.diag_compact = compact ? 1 : 0;
   e = mvn::launch_tlr_sweep(ta, stream);
   if (e != hipSuccess) return hip_fail(e, "tlr sweep");
   if (prefix) {
@@ -686,7 +697,7 @@ int mvn_prob_workspace_bytes_factor(const mvn_factor* f, int N, int S, const mvn
   if (e != hipSuccess) return hip_fail(e, "rank read-back");
   const int nt = f->ld / f->tile;
   const mvn::TlrTables T = mvn::build_tlr_tables(nt, f->rank_stride, ranks.data());
-  const TlrProbLayout L = tlr_prob_layout(f->ld, nt, f->rank_stride, N, S, tlr_sweep_rows(opts));
+  const TlrProbLayout L = tlr_prob_layout(f->ld, nt, f->rank_stride, N, S, tlr_sweep_rows(opts), is_compact(f));
   *bytes = L.fixed + L.dyn_bytes(T.ksum, T.kpad0[nt], L.grid, f->tile);
   return 0;
 }
@@ -1107,16 +1118,139 @@ int mvn_exceedance_order(int n, const double* d_mu, const double* d_var, double 
   return 0;
 }
 
+// Compact TLR factor: info | ranks | diagonal tiles | V' rows (ksum + 128) x m |
+// U columns m x kpad | the sweep's index tables (built there once, by the
+// same kernel as per call, to place the packed operands).
+struct TlrCompactLayout {
+  size_t info, ranks, diag, vpack, upack, kk, zcol, kpad0, kval, vrow0, ucol0, zdst, hdr, flag, total;
+};
+
+TlrCompactLayout tlr_compact_layout(int nt, int m, int rs, long ksum, long kpad) {
+  TlrCompactLayout L{};
+  const size_t np = (size_t)nt * (nt - 1) / 2, np1 = np > 0 ? np : 1;
+  size_t off = 0;
+  L.info = off; off = align_up(off + sizeof(int));
+  L.ranks = off; off = align_up(off + sizeof(int) * np1);
+  L.diag = off; off = align_up(off + sizeof(double) * (size_t)nt * m * m);
+  L.vpack = off;  // the tables kernel puts U at the next 256-byte boundary after V'
+  L.upack = off + align_up(8 * (size_t)(ksum + 128) * m);
+  off = align_up(L.upack + 8 * (size_t)m * (size_t)(kpad > 0 ? kpad : 1));
+  L.kk = off; off = align_up(off + sizeof(int) * np1);
+  L.zcol = off; off = align_up(off + sizeof(long) * (nt + 1));
+  L.kpad0 = off; off = align_up(off + sizeof(long) * (nt + 1));
+  L.kval = off; off = align_up(off + sizeof(int) * nt);
+  L.vrow0 = off; off = align_up(off + sizeof(long) * np1);
+  L.ucol0 = off; off = align_up(off + sizeof(long) * np1);
+  L.zdst = off; off = align_up(off + sizeof(long) * np1 * rs);
+  L.hdr = off; off = align_up(off + sizeof(mvn::TlrSweepHdr));
+  L.flag = off; off = align_up(off + sizeof(int));
+  L.total = off;
+  return L;
+}
+
+bool full_tlr_ok(const mvn_factor* f) {
+  return f && (f->flags & MVN_FACTOR_TLR) && !is_compact(f) && f->L && f->info && f->n >= 1 && f->tile >= 128 &&
+         f->tile % 128 == 0 && f->ld % f->tile == 0 && f->ld >= f->n && f->U && f->Vt && f->ranks &&
+         f->rank_stride >= 16 && f->rank_stride % 16 == 0;
+}
+
+int tlr_compact_plan(const mvn_factor* f, TlrCompactLayout* L, hipStream_t stream) {
+  std::vector<int> ranks;
+  const hipError_t e = tlr_read_ranks(f, ranks, stream);
+  if (e != hipSuccess) return hip_fail(e, "rank read-back");
+  const int nt = f->ld / f->tile;
+  const mvn::TlrTables T = mvn::build_tlr_tables(nt, f->rank_stride, ranks.data());
+  *L = tlr_compact_layout(nt, f->tile, f->rank_stride, T.ksum, T.kpad0[nt]);
+  return 0;
+}
+
+int mvn_tlr_compact_bytes(const mvn_factor* f, size_t* bytes, hipStream_t stream) {
+  if (!full_tlr_ok(f)) return fail(-1, "not a full TLR factor handle");
+  if (!bytes) return fail(-2, "bytes is NULL");
+  TlrCompactLayout L;
+  const int rc = tlr_compact_plan(f, &L, stream);
+  if (rc) return rc;
+  *bytes = L.total;
+  return 0;
+}
+
+int mvn_tlr_compact(const mvn_factor* f, void* d_buf, size_t bytes, mvn_factor* out, hipStream_t stream) {
+  if (!full_tlr_ok(f)) return fail(-1, "not a full TLR factor handle");
+  if (!d_buf) return fail(-2, "buffer is NULL");
+  if (!out) return fail(-4, "output handle is NULL");
+  TlrCompactLayout L;
+  const int rc = tlr_compact_plan(f, &L, stream);
+  if (rc) return rc;
+  if (bytes < L.total) return fail(-3, "buffer too small: %zu < %zu", bytes, L.total);
+  const int m = f->tile, nt = f->ld / f->tile, rs = f->rank_stride;
+  const int np = nt * (nt - 1) / 2;
+  char* b = (char*)d_buf;
+  hipError_t e = hipMemcpyAsync(b + L.info, f->info, sizeof(int), hipMemcpyDeviceToDevice, stream);
+  if (e == hipSuccess && np > 0)
+    e = hipMemcpyAsync(b + L.ranks, f->ranks, sizeof(int) * np, hipMemcpyDeviceToDevice, stream);
+  for (int i = 0; i < nt && e == hipSuccess; ++i)
+    e = hipMemcpyAsync(b + L.diag + sizeof(double) * (size_t)i * m * m,
+                       f->L + ((size_t)i * (i + 1) / 2 + i) * (size_t)m * m, sizeof(double) * (size_t)m * m,
+                       hipMemcpyDeviceToDevice, stream);
+  if (e != hipSuccess) return hip_fail(e, "compact copy");
+  mvn::TlrTableArgs tb{};
+  tb.ranks = f->ranks;
+  tb.nt = nt;
+  tb.rs = rs;
+  tb.m = m;
+  tb.ext_pack = 0;  // the packed operands at the header's offsets from the compact V' start
+  tb.yslice = 0;
+  tb.grid_max = 1;
+  tb.dyn_bytes = (size_t)1 << 62;  // only sizes the (unused) sweep grid, which stays 1
+  tb.kk = (int*)(b + L.kk);
+  tb.zcol = (long*)(b + L.zcol);
+  tb.kpad0 = (long*)(b + L.kpad0);
+  tb.kval = (int*)(b + L.kval);
+  tb.vrow0 = (long*)(b + L.vrow0);
+  tb.ucol0 = (long*)(b + L.ucol0);
+  tb.zdst = (long*)(b + L.zdst);
+  tb.hdr = (mvn::TlrSweepHdr*)(b + L.hdr);
+  tb.bad = (int*)(b + L.flag);  // written only when no sweep workgroup fits, never here
+  e = mvn::launch_tlr_tables(tb, stream);
+  if (e != hipSuccess) return hip_fail(e, "tlr tables");
+  mvn::TlrPackArgs pa{};
+  pa.U = f->U;
+  pa.Vt = f->Vt;
+  pa.m = m;
+  pa.rs = rs;
+  pa.np = np;
+  pa.kk = tb.kk;
+  pa.vrow0 = tb.vrow0;
+  pa.ucol0 = tb.ucol0;
+  pa.kpad0 = tb.kpad0;
+  pa.kval = tb.kval;
+  pa.hdr = tb.hdr;
+  pa.dyn = b + L.vpack;
+  e = mvn::launch_tlr_pack(pa, stream);
+  if (e != hipSuccess) return hip_fail(e, "tlr pack");
+  mvn_factor c = *f;
+  c.flags = MVN_FACTOR_TLR | MVN_FACTOR_TLR_COMPACT;
+  c.L = (double*)(b + L.diag);
+  c.info = (int*)(b + L.info);
+  c.U = (double*)(b + L.upack);
+  c.Vt = (double*)(b + L.vpack);
+  c.ranks = (int*)(b + L.ranks);
+  c.L_low = nullptr;
+  c.update_counts = nullptr;
+  *out = c;
+  return 0;
+}
+
 int mvn_tlr_dense_bytes(const mvn_factor* f, size_t* bytes) {
   if (!bytes) return fail(-2, "bytes is NULL");
-  if (!f || !(f->flags & MVN_FACTOR_TLR) || f->n < 1) return fail(-1, "not a TLR factor handle");
+  if (!f || !(f->flags & MVN_FACTOR_TLR) || is_compact(f) || f->n < 1) return fail(-1, "not a full TLR factor handle");
   const size_t ld = (size_t)padded(f->n);
   *bytes = sizeof(double) * ld * ld;
   return 0;
 }
 
 int mvn_tlr_dense(const mvn_factor* f, void* d_buf, size_t bytes, mvn_factor* out, hipStream_t stream) {
-  if (!f || !(f->flags & MVN_FACTOR_TLR) || !f->L || !f->info || f->n < 1 || f->tile < 128 || f->tile % 128 != 0 ||
+  if (!f || !(f->flags & MVN_FACTOR_TLR) || is_compact(f) || !f->L || !f->info || f->n < 1 || f->tile < 128 || f->tile % 128 != 0 ||
       f->ld % f->tile != 0 || f->ld < f->n || !f->U || !f->Vt || !f->ranks || f->rank_stride < 16 ||
       f->rank_stride % 16 != 0)
     return fail(-1, "not a TLR factor handle");

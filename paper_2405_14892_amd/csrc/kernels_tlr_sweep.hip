@@ -62,8 +62,8 @@ __global__ __launch_bounds__(1024) void tlr_tables_kernel(TlrTableArgs a) {
     h.kpad = a.kpad0[nt];
     const long m = a.m;
     h.vpack = 0;
-    h.upack = align256(8 * (h.ksum + 128) * m);
-    h.yscr = align256(h.upack + 8 * m * (h.kpad > 0 ? h.kpad : 1));
+    h.upack = a.ext_pack ? 0 : align256(8 * (h.ksum + 128) * m);
+    h.yscr = a.ext_pack ? 0 : align256(h.upack + 8 * m * (h.kpad > 0 ? h.kpad : 1));
     h.zslice = (h.kpad > 0 ? h.kpad : 1) * kCols;
     const long per = align256(8 * a.yslice) + align256(8 * h.zslice);
     const long room = (long)a.dyn_bytes - h.yscr;
@@ -286,8 +286,8 @@ __global__ __launch_bounds__(256, RB == 128 ? 2 : 4) void tlr_sweep_kernel(TlrSw
   const long nchunks = (NS + kCols - 1) / kCols;
   const TlrSweepHdr h = *p.hdr;
   if ((long)blockIdx.x >= h.grid) return;  // the workspace holds h.grid workgroups
-  const double* Vpack = (const double*)(p.dyn + h.vpack);
-  const double* Upack = (const double*)(p.dyn + h.upack);
+  const double* Vpack = p.vpack_ext ? p.vpack_ext : (const double*)(p.dyn + h.vpack);
+  const double* Upack = p.upack_ext ? p.upack_ext : (const double*)(p.dyn + h.upack);
   double* Y = (double*)(p.dyn + h.yscr) + (long)blockIdx.x * p.yslice;
   double* Z = (double*)(p.dyn + h.zscr) + (long)blockIdx.x * h.zslice;
   char* stage0 = (char*)lds_T;
@@ -310,7 +310,7 @@ __global__ __launch_bounds__(256, RB == 128 ? 2 : 4) void tlr_sweep_kernel(TlrSw
       const int nst_lr = (int)(Kp / G::kK);
       const double* Ui = Upack + kp0 * m;  // m x Kp
       const double* Zi = Z + kp0 * kCols;
-      const double* D = p.tiles + ((long)ti * (ti + 1) / 2 + ti) * (long)m * m;
+      const double* D = p.tiles + (p.diag_compact ? (long)ti : (long)ti * (ti + 1) / 2 + ti) * (long)m * m;
       for (int b0 = 0; b0 < m && g0 + b0 < p.n; b0 += RB) {
         const int rows = (int)min((long)RB, p.n - (g0 + b0));
         typename G::Acc acc;

@@ -304,6 +304,7 @@ struct TlrSweepHdr {
 struct TlrTableArgs {
   const int* ranks;     // nt (nt - 1) / 2
   int nt, rs, m;
+  int ext_pack;         // the packed operands live in the factor (compact): no room for them in dyn
   long yslice;
   long grid_max;
   size_t dyn_bytes;
@@ -354,6 +355,9 @@ struct TlrSweepArgs {
   int grid;         // launch grid (workgroups past hdr->grid leave at once)
   int rows;         // rows per sweep block: 128 (two workgroups per CU) or 64 (four)
   double* prefix;   // nullptr, or n x nchunks x 4 partials of the running products per row
+  const double* vpack_ext;  // compact factor: its packed V' rows and U columns (else nullptr:
+  const double* upack_ext;  //   the copies in dyn at the header's offsets)
+  int diag_compact;         // diagonal tile i at i m^2 (compact) instead of (i(i+1)/2 + i) m^2
 };
 hipError_t launch_tlr_sweep(const TlrSweepArgs& a, hipStream_t st);
 

@@ -290,3 +290,42 @@ def test_tlr_dense_form_and_dense_sweep(n, tile):
     print(f"  dense-form vs TLR sweep: max |d ell| {dl:.2e}", flush=True)
     assert dl < 1e-8
     assert abs(rd["logP"].item() - rt["logP"].item()) < 1e-9 * max(1.0, abs(rt["logP"].item()))
+
+
+@pytest.mark.parametrize("n,tile,rows", [(1300, 128, 64), (700, 256, 128)])
+def test_tlr_compact_factor(n, tile, rows):
+    """The compact TLR factor (diagonal tiles and U, V'^T at the actual
+    ranks): its buffer is what the ranks need, a sweep through it is bit for
+    bit the sweep through the full factor (the same packed operands, read
+    from the factor instead of packed per call), full and nested, also after
+    the full factor is dropped; the dense form refuses it."""
+    eps, rcap = 1e-5, 128
+    print(f"tlr compact n={n} tile={tile} rows={rows}", flush=True)
+    locs, kern, a, b = _tlr_inputs(40, n, seed=85, beta=0.05)
+    f = _factor(n, locs, kern, tile, eps, rcap)
+    assert f.info() == 0
+    ranks = np.abs(f.ranks().cpu().numpy())
+    c = mvn.mvn_tlr_compact(f)
+    torch.cuda.synchronize()
+    assert c.is_tlr and c.is_compact and c.info() == 0
+    m, nt, k = tile, f.nt, int(ranks.sum())
+    # diagonal tiles, V' rows (+128 zero rows), U columns (each tile-row padded to 16), the Z index table
+    bound = 8 * (nt * m * m + (k + 128) * m + m * (k + 16 * nt) + len(ranks) * rcap) + 2**16
+    print(f"  full factor {f.nbytes() / 2**20:.1f} MiB, compact {c.nbytes() / 2**20:.1f} MiB "
+          f"(bound {bound / 2**20:.1f} MiB)", flush=True)
+    assert c.nbytes() <= bound and c.nbytes() < f.nbytes() / 2
+    N, S, seed = 300, 3, 717
+    opts = mvn.options(tile=tile, tlr_eps=eps, max_rank=rcap, sweep_rows=rows)
+    rf = mvn.mvn_prob(f, a, b, None, N=N, S=S, seed=seed, opts=opts, return_ell=True)
+    pf = mvn.mvn_prob_prefix(f, a, b, None, N=N, S=S, seed=seed, opts=opts)
+    torch.cuda.synchronize()
+    ell_f, lp_f = rf["ell"].cpu().numpy(), pf["logP"].cpu().numpy()
+    del f, rf, pf
+    torch.cuda.empty_cache()
+    rc = mvn.mvn_prob(c, a, b, None, N=N, S=S, seed=seed, opts=opts, return_ell=True)
+    pc = mvn.mvn_prob_prefix(c, a, b, None, N=N, S=S, seed=seed, opts=opts)
+    torch.cuda.synchronize()
+    assert np.array_equal(rc["ell"].cpu().numpy(), ell_f)
+    assert np.array_equal(pc["logP"].cpu().numpy(), lp_f)
+    with pytest.raises(mvn.MvnError):
+        mvn.mvn_tlr_dense(c)
