@@ -83,7 +83,12 @@ typedef struct mvn_options {
                      /* split BF16: more sample columns conditioned at once, */
                      /* Y read twice as often); 0 = 128 for dense factors    */
                      /* and batches, 64 for TLR factors.  The adjoint sweep  */
-                     /* uses 128                                             */
+                     /* uses 128.  32 (dense FP64 mvn_prob, mvn_prob_prefix, */
+                     /* mvn_prob_static): the narrow sweep, 16 sample        */
+                     /* columns per workgroup (32 above 20480 samples), the  */
+                     /* next block's GEMM overlapped with the recurrence;    */
+                     /* 0 selects it for dense FP64 calls with N*S <= 20480  */
+                     /* and N*S*n <= 4.5e7                                   */
   double tlr_eps;    /* > 0: tile low-rank factor (Section III-E): every      */
                      /* off-diagonal tile is compressed to U V^T with         */
                      /* ||A_ij - U V^T||_F <= tlr_eps (absolute).  <= 0: dense */

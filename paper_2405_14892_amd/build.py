@@ -20,7 +20,7 @@ LIB = os.path.join(HERE, "libmvn.so")
 ARCH = os.environ.get("MVN_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["api.cpp", "kernels_chol.hip", "kernels_sov.hip", "kernels_sov_wide.hip", "kernels_sov_quad.hip",
-           "kernels_grad.hip",
+           "kernels_sov_narrow.hip", "kernels_grad.hip",
            "kernels_tlr.hip", "kernels_tlr_sweep.hip", "kernels_mc.hip", "kernels_post.hip"]
 
 # Per-file extra flags.  The sweep inlines the FP64 conditioning step into
@@ -29,6 +29,7 @@ SOURCES = ["api.cpp", "kernels_chol.hip", "kernels_sov.hip", "kernels_sov_wide.h
 EXTRA_FLAGS = {"kernels_sov.hip": ["-mllvm", "-disable-machine-licm"],
                "kernels_sov_wide.hip": ["-mllvm", "-disable-machine-licm"],
                "kernels_sov_quad.hip": ["-mllvm", "-disable-machine-licm"],
+               "kernels_sov_narrow.hip": ["-mllvm", "-disable-machine-licm"],
                "kernels_grad.hip": ["-mllvm", "-disable-machine-licm"],
                "kernels_tlr_sweep.hip": ["-mllvm", "-disable-machine-licm"],
                "kernels_mc.hip": ["-mllvm", "-disable-machine-licm"]}

@@ -35,14 +35,31 @@ int hip_fail(hipError_t e, const char* where) {
 
 constexpr size_t kAlign = 256;
 constexpr int kCUs = 256;      // compute units of an MI355X: the persistent grids are sized for it
+// Automatic narrow sweep: at most this many samples (16-column chunks), and
+// samples x dimensions at most kNarrowMaxWork.  Measured (FP64): 4096
+// sites, 10^4 samples: 10.3 against 11.9 ms, 2560 samples: 5.9 against
+// 11.8 ms; 8192 sites, 10^4 samples: 39 against 32 ms (each narrow
+// workgroup streams the whole factor, four times as many as 64-column ones).
+constexpr long kNarrowMaxNS = 20480;
+constexpr double kNarrowMaxWork = 4.5e7;
 
-// Rows per sweep block: 0 selects the default (128).
-int sweep_rows(const mvn_options* o) { return (!o || o->sweep_rows == 0) ? 128 : o->sweep_rows; }
+// Rows per sweep block: 0 selects the default (128); 32 (the narrow FP64
+// sweep of dense factors) runs its own 32-row blocks, and the other sweeps
+// take 128 then.
+int sweep_rows(const mvn_options* o) {
+  return (!o || o->sweep_rows == 0 || o->sweep_rows == 32) ? 128 : o->sweep_rows;
+}
+// The raw option (0 = automatic choice of the dense sweep).
+int rows_opt(const mvn_options* o) { return o ? o->sweep_rows : 0; }
 // The TLR sweep's blocks: its GEMMs are short (packed ranks plus the dense
 // part of one tile), so conditioning dominates and 64-row blocks (four
 // workgroups per CU) are the default.
 int tlr_sweep_rows(const mvn_options* o) { return (!o || o->sweep_rows == 0) ? 64 : o->sweep_rows; }
 bool sweep_rows_ok(const mvn_options* o) { return !o || o->sweep_rows == 0 || o->sweep_rows == 64 || o->sweep_rows == 128; }
+// Dense probability and nested-set sweeps also take 32 (FP64 only).
+bool dense_rows_ok(const mvn_options* o) {
+  return sweep_rows_ok(o) || (o->sweep_rows == 32 && o->precision == MVN_FP64);
+}
 int max_grid(int rows, int prec) { return kCUs * mvn::sweep_wg_per_cu(rows, prec); }
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -131,7 +148,11 @@ struct ProbLayout {
 };
 
 // Which dense sweep kernel runs a call.
-enum SweepKind { kSweep64 = 0, kSweepWide = 1, kSweepQuad = 2 };
+enum SweepKind { kSweep64 = 0, kSweepWide = 1, kSweepQuad = 2, kSweepNarrow = 3 };
+
+// Columns per workgroup of the narrow sweep: 16 while the chunks fit its
+// workgroup slots, else 32.
+int narrow_cols(long NS) { return (NS + 15) / 16 <= (long)kCUs * mvn::narrow_sweep_wg_per_cu(16) ? 16 : 32; }
 
 // Workspace of one probability call.  ld is the factor's leading dimension
 // (rows of the Y scratch); zslice > 0 adds the TLR Z scratch (FP64).
@@ -143,7 +164,13 @@ ProbLayout prob_layout_ld(int ld, int N, int S, int prec, long zslice, int rows,
   ProbLayout L{};
   L.ld = ld;
   const long NS = (long)N * S;
-  if (kind == kSweepWide) {
+  if (kind == kSweepNarrow) {
+    const int cols = narrow_cols(NS);
+    const long chunks = (NS + cols - 1) / cols;
+    const int gmax = mvn::narrow_sweep_wg_per_cu(cols) * kCUs;
+    L.grid = (int)(chunks < gmax ? chunks : gmax);
+    L.yslice = (long)L.ld * cols;
+  } else if (kind == kSweepWide) {
     const long slices = (NS + 31) / 32;
     const int gmax = mvn::wide_sweep_wg_per_cu() * kCUs;
     L.grid = (int)(slices < gmax ? slices : gmax);
@@ -191,15 +218,29 @@ bool use_wide(int prec, int rows, bool prefix, long NS) {
 // 16384-site problem: BF16 282 against 456 ms, split BF16 976 against 1065,
 // FP32 579 against 604; the FP64 and few-sample sweeps are faster with 64
 // columns per workgroup).
-int sweep_kind(int prec, int rows, bool prefix, long NS) {
+// The narrow sweep (FP64; sweep_rows 32, or 0 with few samples and sites):
+// with few samples the 64-column sweep leaves CUs idle and each workgroup's
+// time is its own chain of n steps plus its GEMM.
+// rows_raw: the sweep_rows option as given (0 = automatic).
+int sweep_kind(int prec, int rows_raw, bool prefix, long NS, int n) {
+  if (prec == MVN_FP64 &&
+      (rows_raw == 32 || (rows_raw == 0 && NS <= kNarrowMaxNS && (double)NS * n <= kNarrowMaxWork)))
+    return kSweepNarrow;
+  const int rows = rows_raw == 0 || rows_raw == 32 ? 128 : rows_raw;
   if (use_wide(prec, rows, prefix, NS)) return kSweepWide;
   const long chunks = (NS + mvn::quad_sweep_cols() - 1) / mvn::quad_sweep_cols();
   if (prec != MVN_FP64 && rows == 128 && chunks >= (long)kCUs * mvn::quad_wg_per_cu(prec, rows)) return kSweepQuad;
   return kSweep64;
 }
 
-ProbLayout prob_layout(int n, int N, int S, int prec, int rows, bool prefix = false) {
-  return prob_layout_ld(padded(n), N, S, prec, 0, rows, sweep_kind(prec, rows, prefix, (long)N * S));
+ProbLayout prob_layout(int n, int N, int S, int prec, int rows_raw, bool prefix = false) {
+  const int rows = rows_raw == 0 || rows_raw == 32 ? 128 : rows_raw;
+  return prob_layout_ld(padded(n), N, S, prec, 0, rows, sweep_kind(prec, rows_raw, prefix, (long)N * S, n));
+}
+
+// Sample columns per chunk of a dense sweep's nested-set partials.
+int prefix_cols(int prec, int rows_raw, long NS, int n) {
+  return sweep_kind(prec, rows_raw, true, NS, n) == kSweepNarrow ? narrow_cols(NS) : mvn::sweep_tile_cols();
 }
 
 // Front of the workspace of a nested-set call: the running-product partials
@@ -208,11 +249,13 @@ ProbLayout prob_layout(int n, int N, int S, int prec, int rows, bool prefix = fa
 struct PrefixRegion {
   size_t part, lps, total;
   long nchunks;
+  int cols;
 };
 
-PrefixRegion prefix_region(int n, int N, int S) {
+PrefixRegion prefix_region(int n, int N, int S, int cols) {
   PrefixRegion P{};
-  P.nchunks = ((long)N * S + mvn::sweep_tile_cols() - 1) / mvn::sweep_tile_cols();
+  P.cols = cols;
+  P.nchunks = ((long)N * S + cols - 1) / cols;
   size_t off = 0;
   P.part = off; off = align_up(off + sizeof(double) * 4 * (size_t)n * (size_t)P.nchunks);
   P.lps = off; off = align_up(off + sizeof(double) * (size_t)n * (size_t)S);
@@ -505,9 +548,10 @@ int dense_sweep(const mvn_factor* f, const double* d_a, const double* d_b, const
   sa.grid = Lay.grid;
   sa.rows = rows;
   sa.prefix = prefix;
-  const int kind = sweep_kind(prec, rows, prefix != nullptr, (long)N * S);
+  const int kind = sweep_kind(prec, rows_opt(opts), prefix != nullptr, (long)N * S, n);
   sa.wide = kind == kSweepWide ? 1 : 0;
   sa.quad = kind == kSweepQuad ? 1 : 0;
+  sa.narrow = kind == kSweepNarrow ? narrow_cols((long)N * S) : 0;
   e = mvn::launch_sweep(sa, stream);
   if (e != hipSuccess) return hip_fail(e, "sweep");
   if (prefix) return 0;
@@ -678,8 +722,9 @@ int mvn_prob_workspace_bytes(int n, int N, int S, const mvn_options* opts, size_
     *bytes = L.fixed + L.dyn_bytes(kmax, kmax, L.grid, G.m);
     return 0;
   }
-  if (!sweep_rows_ok(opts)) return fail(-4, "sweep_rows must be 0, 64 or 128 (got %d)", opts->sweep_rows);
-  *bytes = prob_layout(n, N, S, prec, sweep_rows(opts)).total;
+  if (!dense_rows_ok(opts))
+    return fail(-4, "sweep_rows must be 0, 64, 128 or 32 (FP64) (got %d)", opts->sweep_rows);
+  *bytes = prob_layout(n, N, S, prec, rows_opt(opts)).total;
   return 0;
 }
 
@@ -711,7 +756,10 @@ int mvn_prob_prefix_workspace_bytes(const mvn_factor* f, int N, int S, const mvn
   size_t rest = 0;
   const int rc = mvn_prob_workspace_bytes_factor(f, N, S, opts, &rest, stream);
   if (rc) return rc;
-  *bytes = prefix_region(f->n, N, S).total + rest;
+  const bool tlr = (f->flags & MVN_FACTOR_TLR) != 0;
+  const int cols = tlr ? mvn::sweep_tile_cols()
+                       : prefix_cols(opts ? opts->precision : MVN_FP64, rows_opt(opts), (long)N * S, f->n);
+  *bytes = prefix_region(f->n, N, S, cols).total + rest;
   return 0;
 }
 
@@ -735,8 +783,10 @@ int mvn_prob_prefix(const mvn_factor* f, const double* d_a, const double* d_b, c
   if (tlr && prec != MVN_FP64) return fail(-8, "the TLR sweep is FP64");
   if (!tlr && prec != MVN_FP64 && (prec != f->precision || !f->L_low))
     return fail(-8, "the factor holds no operand copy for precision %d (built with %d)", prec, f->precision);
-  if (!sweep_rows_ok(opts)) return fail(-8, "sweep_rows must be 0, 64 or 128 (got %d)", opts->sweep_rows);
-  const PrefixRegion R = prefix_region(f->n, N, S);
+  if (tlr ? !sweep_rows_ok(opts) : !dense_rows_ok(opts))
+    return fail(-8, "sweep_rows must be 0, 64, 128 or 32 (FP64, dense) (got %d)", opts->sweep_rows);
+  const PrefixRegion R =
+      prefix_region(f->n, N, S, tlr ? mvn::sweep_tile_cols() : prefix_cols(prec, rows_opt(opts), (long)N * S, f->n));
   if (!ws) return fail(-9, "workspace is NULL");
   if (ws_bytes < R.total) return fail(-10, "workspace too small: %zu < %zu", ws_bytes, R.total);
   if (!d_prefix) return fail(-11, "output is NULL");
@@ -749,14 +799,14 @@ int mvn_prob_prefix(const mvn_factor* f, const double* d_a, const double* d_b, c
   if (tlr) {
     rc = tlr_sweep_call(f, d_a, d_b, d_mu, N, S, seed, opts, rest, rest_bytes, nullptr, part, nullptr, stream, &bad);
   } else {
-    const ProbLayout Lay = prob_layout(f->n, N, S, prec, sweep_rows(opts), true);
+    const ProbLayout Lay = prob_layout(f->n, N, S, prec, rows_opt(opts), true);
     if (rest_bytes < Lay.total) return fail(-10, "workspace too small: %zu < %zu", ws_bytes, R.total + Lay.total);
     bad = (const int*)((char*)rest + Lay.bad);
     rc = dense_sweep(f, d_a, d_b, d_mu, N, S, seed, opts, rest, Lay, nullptr, part, nullptr, stream);
   }
   if (rc) return rc;
-  const hipError_t e = mvn::launch_prefix_reduce(part, R.nchunks, f->n, N, S, (double*)(w + R.lps), f->info, bad,
-                                                 d_prefix, stream);
+  const hipError_t e = mvn::launch_prefix_reduce(part, R.nchunks, R.cols, f->n, N, S, (double*)(w + R.lps), f->info,
+                                                 bad, d_prefix, stream);
   if (e != hipSuccess) return hip_fail(e, "prefix reduce");
   return 0;
 }
@@ -1075,8 +1125,9 @@ int mvn_prob(const mvn_factor* f, const double* d_a, const double* d_b, const do
   }
   if (prec != MVN_FP64 && (prec != f->precision || !f->L_low))
     return fail(-8, "the factor holds no operand copy for precision %d (built with %d)", prec, f->precision);
-  if (!sweep_rows_ok(opts)) return fail(-8, "sweep_rows must be 0, 64 or 128 (got %d)", opts->sweep_rows);
-  const ProbLayout Lay = prob_layout(f->n, N, S, prec, sweep_rows(opts));
+  if (!dense_rows_ok(opts))
+    return fail(-8, "sweep_rows must be 0, 64, 128 or 32 (FP64) (got %d)", opts->sweep_rows);
+  const ProbLayout Lay = prob_layout(f->n, N, S, prec, rows_opt(opts));
   if (!ws) return fail(-9, "workspace is NULL");
   if (ws_bytes < Lay.total) return fail(-10, "workspace too small: %zu < %zu", ws_bytes, Lay.total);
   if (!d_out) return fail(-11, "output is NULL");
@@ -1353,10 +1404,11 @@ int mvn_prob_static(const mvn_factor* f, const double* d_a, const double* d_b, c
   if (!prec_ok(prec)) return fail(-8, "unknown precision %d", prec);
   if (prec != MVN_FP64 && (prec != f->precision || !f->L_low))
     return fail(-8, "the factor holds no operand copy for precision %d (built with %d)", prec, f->precision);
-  if (!sweep_rows_ok(opts)) return fail(-8, "sweep_rows must be 0, 64 or 128 (got %d)", opts->sweep_rows);
+  if (!dense_rows_ok(opts))
+    return fail(-8, "sweep_rows must be 0, 64, 128 or 32 (FP64) (got %d)", opts->sweep_rows);
   if (!d_out) return fail(-9, "output is NULL");
   const int rows = sweep_rows(opts);
-  const int kind = sweep_kind(prec, rows, false, (long)N * S);
+  const int kind = sweep_kind(prec, rows_opt(opts), false, (long)N * S, f->n);
   // as many persistent workgroups as the scratch holds
   const ProbLayout one = prob_layout_ld(padded(f->n), N, S, prec, 0, rows, kind, 1);
   const size_t per = align_up((size_t)mvn::sweep_elem_bytes(prec) * (size_t)one.yslice);

@@ -241,6 +241,7 @@ static hipError_t launch_sweep_t(const SweepArgs& a, hipStream_t st) {
 }
 
 hipError_t launch_sweep(const SweepArgs& a, hipStream_t st) {
+  if (a.narrow) return launch_narrow_sweep(a, st);
   if (a.wide) return launch_wide_sweep(a, st);
   if (a.quad) return launch_quad_sweep(a, st);
   return a.prefix ? launch_sweep_t<true>(a, st) : launch_sweep_t<false>(a, st);
@@ -343,17 +344,17 @@ hipError_t launch_reduce(const double* ell, int N, int S, double* part, const in
 // Per (row, shift): the running products of the shift's N samples after the
 // row, summed exactly over the chunk partials of prefix_row in chunk order;
 // lps = log(sum 2^E / N), the shift's estimate of P(first row + 1 sites).
-__global__ __launch_bounds__(256) void prefix_shift_kernel(const double* __restrict__ part, long nchunks, int n,
-                                                           int N, int S, double* __restrict__ lps) {
+__global__ __launch_bounds__(256) void prefix_shift_kernel(const double* __restrict__ part, long nchunks, int cols,
+                                                           int n, int N, int S, double* __restrict__ lps) {
   const long id = (long)blockIdx.x * 256 + threadIdx.x;
   if (id >= (long)n * S) return;
   const long row = id / S;
   const int s = (int)(id % S);
-  const long c_lo = (long)s * N / kCols, c_hi = ((long)(s + 1) * N - 1) / kCols;
+  const long c_lo = (long)s * N / cols, c_hi = ((long)(s + 1) * N - 1) / cols;
   int E = kNoExp;
   double sum = 0.0;
   for (long c = c_lo; c <= c_hi; ++c) {
-    const int slot = (c * kCols / N == s) ? 0 : 1;
+    const int slot = (c * cols / N == s) ? 0 : 1;
     const double* d = part + (row * nchunks + c) * 4 + 2 * slot;
     const double v = d[1];
     if (!(v > 0.0)) continue;
@@ -402,11 +403,11 @@ __global__ __launch_bounds__(256) void prefix_final_kernel(const double* __restr
   }
 }
 
-hipError_t launch_prefix_reduce(const double* part, long nchunks, int n, int N, int S, double* lps,
+hipError_t launch_prefix_reduce(const double* part, long nchunks, int cols, int n, int N, int S, double* lps,
                                 const int* info_factor, const int* bad_limits, double* out, hipStream_t st) {
   const long tot = (long)n * S;
-  hipLaunchKernelGGL(prefix_shift_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, part, nchunks, n,
-                     N, S, lps);
+  hipLaunchKernelGGL(prefix_shift_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, part, nchunks,
+                     cols, n, N, S, lps);
   hipLaunchKernelGGL(prefix_final_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
                      (const double*)lps, n, S, info_factor, bad_limits, out);
   return hipGetLastError();

@@ -139,6 +139,7 @@ struct SweepArgs {
   double* prefix;          // nullptr, or n x nchunks x 4 partials of the running products per row
   int wide;                // FP64, 128 rows, no prefix: the 128-column sweep (yslice = ld x 128)
   int quad;                // the 256-column sweep with four conditioning waves (yslice = quad_yslice)
+  int narrow;              // 16 or 32: the FP64 sweep with that many columns per workgroup (yslice = ld x narrow)
 };
 
 // Setup of one probability call: centred limits and the invalid-limit flag.
@@ -152,7 +153,8 @@ int wide_sweep_cols();
 int wide_sweep_wg_per_cu();
 // log P-hat of every nested set (first k sites) and its relative standard
 // error over shifts from the partials of a prefix sweep: out[2k], out[2k+1].
-hipError_t launch_prefix_reduce(const double* part, long nchunks, int n, int N, int S, double* lps,
+// cols: sample columns per chunk of the partials (64, or the narrow sweep's 16 / 32).
+hipError_t launch_prefix_reduce(const double* part, long nchunks, int cols, int n, int N, int S, double* lps,
                                 const int* info_factor, const int* bad_limits, double* out, hipStream_t st);
 long sweep_yslice(int prec, int ld);
 int sweep_elem_bytes(int prec);
@@ -247,6 +249,11 @@ hipError_t launch_batch_sweep(const BatchSweepArgs& a, hipStream_t st);
 hipError_t launch_quad_sweep(const SweepArgs& a, hipStream_t st);
 hipError_t launch_quad_batch_sweep(const BatchSweepArgs& a, hipStream_t st);
 int quad_sweep_cols();
+// The FP64 sweep for few samples (kernels_sov_narrow.hip): 16 or 32 columns
+// per three-wave workgroup, the next block's GEMM overlapped with the
+// recurrence.
+hipError_t launch_narrow_sweep(const SweepArgs& a, hipStream_t st);
+int narrow_sweep_wg_per_cu(int cols);
 int quad_wg_per_cu(int prec, int rows);
 long quad_yslice(int prec, int ld);
 hipError_t launch_batch_reduce(const double* ell, int count, int N, int S, double* part, const int* info,
