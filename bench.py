@@ -187,6 +187,21 @@ class Problem:
         off = self.fac.ranks - self.fbuf.data_ptr()
         return self.fbuf[off: off + 4 * cnt].view(self.torch.int32).cpu().numpy().astype(np.int64)
 
+    def tile(self, i, j):
+        """Tile (i, j), j <= i, of a TLR factor's tile store: for j < i the
+        tile the panel was compressed from."""
+        m = self.fac.tile
+        off = self.fac.L - self.fbuf.data_ptr() + 8 * (i * (i + 1) // 2 + j) * m * m
+        return self.fbuf[off: off + 8 * m * m].view(self.torch.float64).view(m, m).cpu().numpy()
+
+
+def _frob_eps_rank(A, eps):
+    """Smallest k with ||A - A_k||_F <= eps for the truncated SVD A_k."""
+    import numpy as np
+    s = np.linalg.svd(A, compute_uv=False)
+    tail = np.sqrt(np.cumsum((s ** 2)[::-1]))[::-1]
+    return int(np.sum(tail > eps))
+
 
 def _flops(n, NS):
     return n ** 3 / 3.0, float(n) * (n - 1) * NS
@@ -359,6 +374,15 @@ def variant_tlr(dev, dense=None) -> dict:
         p = Problem(w, mvn.options(tile=w.tile, tlr_eps=eps, max_rank=256), dev)
         r = p.run(3, 1)
         ranks, ld = np.abs(p.ranks()), p.fac.ld
+        # ranks against the tiles' Frobenius eps-ranks (host SVD) on sampled panels:
+        # every 8th adjacent tile and 8 others
+        nt_ = ld // w.tile
+        rng = np.random.default_rng(5)
+        sample = [(i, i - 1) for i in range(1, nt_, 8)]
+        for _ in range(8):
+            i = int(rng.integers(2, nt_))
+            sample.append((i, int(rng.integers(0, i - 1))))
+        svd_r = [(int(ranks[i * (i - 1) // 2 + k]), _frob_eps_rank(p.tile(i, k), eps)) for i, k in sample]
         full_ws = p.wsb
         csw = _tlr_compact_sweep(p, w, dev)
         dsw = _tlr_dense_sweep(p, w, dev)
@@ -390,7 +414,13 @@ def variant_tlr(dev, dense=None) -> dict:
                 "note": "TLR factorisation, factor written out dense, dense FP64 sweep (one timed call)"},
             "ranks": {"mean": float(ranks.mean()), "max": int(ranks.max()),
                       "adjacent_mean": float(np.mean([ranks[i * (i - 1) // 2 + i - 1] for i in range(1, nt)])),
-                      "histogram_by_16": np.bincount(np.minimum(ranks // 16, 16)).tolist()}}
+                      "histogram_by_16": np.bincount(np.minimum(ranks // 16, 16)).tolist(),
+                      "sampled_vs_svd_eps_rank": {
+                          "panels": [list(x) for x in sample], "ranks": [a for a, _ in svd_r],
+                          "svd_eps_ranks": [b for _, b in svd_r],
+                          "sum_ratio": sum(a for a, _ in svd_r) / max(1, sum(b for _, b in svd_r)),
+                          "note": "Frobenius eps-rank: smallest k with ||A - A_k||_F <= eps (host SVD of "
+                                  "the tile the panel was compressed from)"}}}
     out["config"] = (f"n={w.n} (256^2 Morton grid), Matern nu={w.nu}, beta={w.beta}, nugget={w.nugget}, "
                      f"N={w.N} x S={w.S}; dense tile 1024, TLR tile {w.tile}, max_rank 256; TLR eps > 0 is "
                      "checked by per-tile residual and rank properties, not entry-wise against the oracle")

@@ -294,7 +294,8 @@ struct TlrGeom {
   int m, nt, rs, ld;
   long ntiles, npanels;
   size_t tiles, info, U, Vt, ranks, total;
-  size_t ws_local, ws_wt, ws_t, ws_total;  // factorisation workspace
+  size_t ws_local, ws_wt, ws_t, ws_rc, ws_total;  // factorisation workspace
+  int rc_grid;
 };
 
 TlrGeom tlr_geom(int n, int m, int max_rank) {
@@ -317,6 +318,9 @@ TlrGeom tlr_geom(int n, int m, int max_rank) {
   G.ws_local = w; w = align_up(w + sizeof(int));
   G.ws_wt = w; w = align_up(w + sizeof(double) * (size_t)batch * G.rs * G.rs);
   G.ws_t = w; w = align_up(w + sizeof(double) * (size_t)batch * m * G.rs);
+  // recompression: one workgroup per panel, at most kTlrRcGrid
+  G.rc_grid = (int)std::min<long>(mvn::kTlrRcGrid, G.npanels);
+  G.ws_rc = w; w = align_up(w + sizeof(double) * (size_t)G.rc_grid * (size_t)mvn::tlr_rc_scratch_doubles(m, G.rs));
   G.ws_total = w;
   return G;
 }
@@ -926,6 +930,8 @@ int cholesky_impl(int n, const double* d_sigma, int ld_sigma, const int64_t* d_p
     a.local_info = (int*)(w + G.ws_local);
     a.WT = (double*)(w + G.ws_wt);
     a.T = (double*)(w + G.ws_t);
+    a.rc_scratch = G.rc_grid > 0 ? (double*)(w + G.ws_rc) : nullptr;
+    a.rc_grid = G.rc_grid;
     a.m = G.m;
     a.nt = G.nt;
     a.rs = G.rs;

@@ -438,6 +438,445 @@ __global__ __launch_bounds__(256) void tlr_trsm_rows_kernel(const double* __rest
   }
 }
 
+// ------------------------------------------------------------ recompression
+// After the factorisation every panel L_ik = U V'^T (rank r >= 2, not
+// capped) is recompressed to the smallest rank whose error in the tile
+// it approximates stays within eps (Section III-E: the truncated SVD of the
+// tile, here taken within the column and row spaces the cross approximation
+// found).  With V = L_kk V' (A_ik ~ U V^T):
+//   1. G_u = U^T U = D_u Lu Lu^T D_u and G_v = V^T V = D_v Lv Lv^T D_v
+//      (D: square roots of the diagonals, Lu, Lv: Cholesky factors of the
+//      equilibrated Grams), so Q_u = U D_u^-1 Lu^-T and
+//      Q_v = V D_v^-1 Lv^-T are orthonormal bases of those spaces;
+//   2. B = Q_u^T A Q_v = Lu^-1 (D_u^-1 U^T A V D_v^-1) Lv^-T: the tile's
+//      projection onto them, whose residual ||A - Q_u B Q_v^T|| is orthogonal
+//      to any change inside them;
+//   3. B B^T = W diag(sigma^2) W^T by cyclic Jacobi (the disjoint rotations of
+//      a round-robin schedule applied together; the working matrix in LDS up
+//      to rank 128, else in the scratch; W in the scratch);
+//   4. k = the smallest rank whose discarded sum of sigma^2 is <= f eps^2
+//      (f = 0.95, then 0.7, 0.4), and with W_k the top k vectors
+//        U2 = U X_u, X_u = D_u^-1 Lu^-T W_k;  V2'^T = X_v^T V'^T,
+//        X_v = D_v^-1 Lv^-T B^T W_k
+//      (U2 V2^T = Q_u W_k W_k^T B Q_v^T, the best rank-k approximation of
+//      the tile within those spaces);
+//   5. the new factors replace the old ones only if the exact residual
+//      ||A - U2 V2^T||_F (V2^T = X_v^T V^T) is <= eps.
+// Small products on MFMA in 128 x 128 blocks with masked, double-buffered
+// LDS stages; triangular solves one vector per lane against the factor in
+// the working matrix.  One workgroup per CU takes the panels in order of
+// distance from the diagonal, each with its own scratch.
+// Stage loads of the small products, masked at the operand edges: lane t
+// holds 8 values of one stage (k row t / 16, columns 8 (t % 16) .. + 7 for a
+// k-major operand; row t / 2, k 8 (t % 2) .. + 7 for a row-major one).
+__device__ __forceinline__ void rc_load_kmaj(const double* __restrict__ A, long lda, int na, int K, int k0,
+                                             double (&r)[8]) {
+  const int t = threadIdx.x, k = k0 + (t >> 4), cb = (t & 15) * 8;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) r[q] = (k < K && cb + q < na) ? A[(long)k * lda + cb + q] : 0.0;
+}
+__device__ __forceinline__ void rc_load_rmaj(const double* __restrict__ A, long lda, int na, int K, int k0,
+                                             double (&r)[8]) {
+  const int t = threadIdx.x, row = t >> 1, kb = k0 + (t & 1) * 8;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) r[q] = (row < na && kb + q < K) ? A[(long)row * lda + kb + q] : 0.0;
+}
+
+// One 128 x 128 block: acc = A^T B (TN: both operands k-major) or A B^T
+// (both row-major), K in stages of 16 through double-buffered LDS.
+template <bool TN>
+__device__ __forceinline__ void rc_block(const double* __restrict__ A, long lda, int na, const double* __restrict__ B,
+                                         long ldb, int nb, int K, Acc& acc, double* lds) {
+  const int nst = (K + kStageK - 1) / kStageK;
+  if (nst == 0) return;
+  double ra[8], rb[8];
+  const auto load = [&](int k0) {
+    if (TN) {
+      rc_load_kmaj(A, lda, na, K, k0, ra);
+      rc_load_kmaj(B, ldb, nb, K, k0, rb);
+    } else {
+      rc_load_rmaj(A, lda, na, K, k0, ra);
+      rc_load_rmaj(B, ldb, nb, K, k0, rb);
+    }
+  };
+  const auto store = [&](double* st) {
+    if (TN) {
+      store_cols(st, ra);
+      store_cols(st + kStageDoubles, rb);
+    } else {
+      store_rows(st, ra);
+      store_rows(st + kStageDoubles, rb);
+    }
+  };
+  load(0);
+  __syncthreads();  // the LDS's previous use is over
+  store(lds);
+  __syncthreads();
+  for (int s = 0; s < nst; ++s) {
+    double* cur = lds + (s & 1) * 2 * kStageDoubles;
+    double* nxt = lds + ((s + 1) & 1) * 2 * kStageDoubles;
+    if (s + 1 < nst) load((s + 1) * kStageK);
+    mma_stage(cur, cur + kStageDoubles, acc);
+    if (s + 1 < nst) store(nxt);
+    __syncthreads();
+  }
+}
+
+// C = A^T B (TN; A[k lda + i], B[k ldb + j]) or A B^T (NT; A[i lda + k],
+// B[j ldb + k]) for i < M, j < N (operands zero past na / nb, k past K), in
+// 128 x 128 blocks; out of line so that the recompression's many products
+// share one body and its registers.
+template <bool TN>
+__device__ __noinline__ void rc_gemm(const double* __restrict__ A, long lda, int na, const double* __restrict__ B,
+                                     long ldb, int nb, int K, double* __restrict__ C, long ldc, int M, int N,
+                                     double* lds) {
+  for (int tm = 0; tm * kTile < M; ++tm)
+    for (int tn = 0; tn * kTile < N; ++tn) {
+      const double* Ab = TN ? A + tm * kTile : A + (long)tm * kTile * lda;
+      const double* Bb = TN ? B + tn * kTile : B + (long)tn * kTile * ldb;
+      Acc acc;
+      acc_zero(acc);
+      rc_block<TN>(Ab, lda, na - tm * kTile, Bb, ldb, nb - tn * kTile, K, acc, lds);
+      const int mm = min(kTile, M - tm * kTile), nn = min(kTile, N - tn * kTile);
+      double* Cb = C + (long)tm * kTile * ldc + tn * kTile;
+#pragma unroll
+      for (int ib = 0; ib < 4; ++ib)
+#pragma unroll
+        for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int i = acc_row(ib, q), j = acc_col(jb);
+            if (i < mm && j < nn) Cb[(long)i * ldc + j] = acc.v[ib][jb][q];
+          }
+    }
+}
+
+__device__ __noinline__ double rc_residual(const double* __restrict__ A, int m, const double* __restrict__ Up, int ld,
+                                           const double* __restrict__ Vp, int kr, double* lds, double* sv) {
+  return residual_norm2(A, m, Up, ld, Vp, kr, lds, sv);
+}
+
+// Pair p of round rho of the round-robin schedule on n (even) indices.
+__device__ __forceinline__ void rc_pair(int n, int rho, int p, int& a, int& b) {
+  if (p == 0) {
+    a = n - 1;
+    b = rho;
+  } else {
+    a = (rho + p) % (n - 1);
+    b = (rho - p + n - 1) % (n - 1);
+  }
+}
+
+constexpr int kRcLdsR = 128;       // ranks up to this keep the eigenproblem in LDS
+constexpr int kRcLd = kRcLdsR + 1; // its LDS row stride
+constexpr int kRcSweeps = 15;
+
+// Shared state of one workgroup's recompression.
+struct RcShared {
+  double* S;         // the kr x kr working matrix (LDS, or the scratch slot for larger ranks)
+  int sld;           // its row stride
+  double* lds;       // GEMM stages (aliases the LDS matrix)
+  double *cs, *sn, *lam, *du, *dv, *tail, *sv;
+  int *pa, *pb, *ord, *flag;
+};
+
+// Lower Cholesky factor of the Gram matrix G (kr x kr, row stride R,
+// indices >= r the identity) after equilibration by d = sqrt of its
+// diagonal, written back to G (upper part zero); false if not positive
+// definite.
+__device__ __forceinline__ bool rc_gram_chol(const RcShared& sh, double* __restrict__ G, int R, int kr, int r,
+                                             double* d) {
+  const int t = threadIdx.x;
+  double* S = sh.S;
+  const int ld = sh.sld;
+  for (int e = t; e < kr; e += 256) d[e] = e < r ? sqrt(G[(long)e * R + e]) : 1.0;
+  if (t == 0) *sh.flag = 0;
+  __syncthreads();
+  for (int e = t; e < kr * kr; e += 256) {
+    const int p = e / kr, q = e % kr;
+    S[p * ld + q] = (p < r && q < r) ? G[(long)p * R + q] / (d[p] * d[q]) : (p == q ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  for (int j = 0; j < kr; ++j) {
+    if (t == 0) {
+      const double piv = S[j * ld + j];
+      if (!(piv > 0.0) || !isfinite(piv)) *sh.flag = 1;
+      S[j * ld + j] = piv > 0.0 ? sqrt(piv) : 1.0;
+    }
+    __syncthreads();
+    const double dj = S[j * ld + j];
+    for (int e = j + 1 + t; e < kr; e += 256) S[e * ld + j] /= dj;
+    __syncthreads();
+    const int nr = kr - j - 1;
+    for (int e = t; e < nr * nr; e += 256) {
+      const int ii = j + 1 + e / nr, ll = j + 1 + e % nr;
+      if (ll <= ii) S[ii * ld + ll] -= S[ii * ld + j] * S[ll * ld + j];
+    }
+    __syncthreads();
+  }
+  const bool ok = *sh.flag == 0;
+  for (int e = t; e < kr * kr; e += 256) {
+    const int p = e / kr, q = e % kr;
+    G[(long)p * R + q] = q <= p ? S[p * ld + q] : 0.0;
+  }
+  __syncthreads();
+  return ok;
+}
+
+// Lower factor (kr x kr, row stride R) into the working matrix.
+__device__ __forceinline__ void rc_load_factor(const RcShared& sh, const double* __restrict__ Lg, int R, int kr) {
+  for (int e = threadIdx.x; e < kr * kr; e += 256) sh.S[(e / kr) * sh.sld + e % kr] = Lg[(long)(e / kr) * R + e % kr];
+  __syncthreads();
+}
+
+// With the lower factor F in the working matrix, vector x (stride sx) in
+// place: forward F x = b, or (TRANS) backward F^T x = b.
+template <bool TRANS>
+__device__ __forceinline__ void rc_solve(const RcShared& sh, int kr, double* __restrict__ x, long sx) {
+  const double* S = sh.S;
+  const int ld = sh.sld;
+  if (!TRANS) {
+    for (int p = 0; p < kr; ++p) {
+      double v = x[p * sx];
+      for (int l = 0; l < p; ++l) v -= S[p * ld + l] * x[l * sx];
+      x[p * sx] = v / S[p * ld + p];
+    }
+  } else {
+    for (int p = kr - 1; p >= 0; --p) {
+      double v = x[p * sx];
+      for (int l = p + 1; l < kr; ++l) v -= S[l * ld + p] * x[l * sx];
+      x[p * sx] = v / S[p * ld + p];
+    }
+  }
+}
+
+// The recompression of one panel (see above).  Scratch slots: Yt, V2t, V2p
+// R x m, U2 m x R, the R x R slots Lu, Lv, W, Bm, Tm, Xu, Xv.
+__device__ __forceinline__ void rc_panel(const RcShared& sh, const double* __restrict__ A,
+                                         const double* __restrict__ Lkk, double* __restrict__ Up,
+                                         double* __restrict__ Vp, int* __restrict__ rank_out, int m, int rs, int r,
+                                         double eps, double* ws) {
+  const int t = threadIdx.x, R = rs, kr = (r + 15) & ~15;
+  double* Yt = ws;
+  double* U2 = Yt + (long)R * m;
+  double* V2t = U2 + (long)R * m;
+  double* V2p = V2t + (long)R * m;
+  double* Lu = V2p + (long)R * m;
+  double* Lv = Lu + (long)R * R;
+  double* W = Lv + (long)R * R;
+  double* Bm = W + (long)R * R;
+  double* Tm = Bm + (long)R * R;
+  double* Xu = Tm + (long)R * R;
+  double* Xv = Xu + (long)R * R;
+  double* S = sh.S;
+  const int ld = sh.sld;
+  // V^T = V'^T L_kk^T (column block tn of L_kk^T needs L_kk's first 128 (tn + 1) columns)
+  for (int tn = 0; tn < m / kTile; ++tn)
+    rc_gemm<false>(Vp, m, kr, Lkk + (long)tn * kTile * m, m, kTile, (tn + 1) * kTile, Yt + tn * kTile, m, kr, kTile,
+                   sh.lds);
+  __syncthreads();
+  rc_gemm<true>(Up, rs, kr, Up, rs, kr, m, Lu, R, kr, kr, sh.lds);
+  rc_gemm<false>(Yt, m, kr, Yt, m, kr, m, Lv, R, kr, kr, sh.lds);
+  __syncthreads();
+  if (!rc_gram_chol(sh, Lu, R, kr, r, sh.du)) return;
+  if (!rc_gram_chol(sh, Lv, R, kr, r, sh.dv)) return;
+  // U^T A V (A V staged in U2's buffer), scaled by D_u^-1 . D_v^-1
+  rc_gemm<false>(A, m, m, Yt, m, kr, m, U2, R, m, kr, sh.lds);
+  __syncthreads();
+  rc_gemm<true>(Up, rs, kr, U2, R, kr, m, Tm, R, kr, kr, sh.lds);
+  __syncthreads();
+  for (int e = t; e < kr * kr; e += 256) {
+    const int p = e / kr, q = e % kr;
+    Tm[(long)p * R + q] /= sh.du[p] * sh.dv[q];
+  }
+  __syncthreads();
+  // B = Lu^-1 T Lv^-T: columns by forward solves with Lu, then rows with Lv
+  rc_load_factor(sh, Lu, R, kr);
+  for (int c = t; c < kr; c += 256) rc_solve<false>(sh, kr, Tm + c, R);
+  __syncthreads();
+  rc_load_factor(sh, Lv, R, kr);
+  for (int c = t; c < kr; c += 256) rc_solve<false>(sh, kr, Tm + (long)c * R, 1);
+  __syncthreads();
+  for (int e = t; e < kr * kr; e += 256) Bm[(long)(e / kr) * R + e % kr] = Tm[(long)(e / kr) * R + e % kr];
+  __syncthreads();
+  // B B^T into the working matrix (via W's slot), W = I, cyclic Jacobi
+  rc_gemm<false>(Bm, R, kr, Bm, R, kr, kr, W, R, kr, kr, sh.lds);
+  __syncthreads();
+  for (int e = t; e < kr * kr; e += 256) {
+    const int p = e / kr, q = e % kr;
+    S[p * ld + q] = 0.5 * (W[(long)p * R + q] + W[(long)q * R + p]);  // symmetric against rounding
+  }
+  __syncthreads();
+  for (int e = t; e < kr * kr; e += 256) W[(long)(e / kr) * R + e % kr] = (e / kr == e % kr) ? 1.0 : 0.0;
+  __syncthreads();
+  const int half = kr / 2;
+  for (int sw = 0; sw < kRcSweeps; ++sw) {
+    if (t == 0) *sh.flag = 0;
+    __syncthreads();
+    for (int rho = 0; rho < kr - 1; ++rho) {
+      for (int p = t; p < half; p += 256) {
+        int a, b;
+        rc_pair(kr, rho, p, a, b);
+        const double app = S[a * ld + a], aqq = S[b * ld + b], apq = S[a * ld + b];
+        double c = 1.0, s = 0.0;
+        if (apq != 0.0 && fabs(apq) > 1e-15 * sqrt(fabs(app * aqq))) {
+          const double th = (aqq - app) / (2.0 * apq);
+          const double tt = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
+          c = 1.0 / sqrt(1.0 + tt * tt);
+          s = tt * c;
+          *sh.flag = 1;
+        }
+        sh.cs[p] = c;
+        sh.sn[p] = s;
+        sh.pa[p] = a;
+        sh.pb[p] = b;
+      }
+      __syncthreads();
+      for (int e = t; e < half * kr; e += 256) {  // rows a, b of S
+        const int p = e / kr, j = e % kr;
+        const double s = sh.sn[p];
+        if (s == 0.0) continue;
+        const double c = sh.cs[p];
+        const int a = sh.pa[p], b = sh.pb[p];
+        const double x = S[a * ld + j], y = S[b * ld + j];
+        S[a * ld + j] = c * x - s * y;
+        S[b * ld + j] = s * x + c * y;
+      }
+      __syncthreads();
+      for (int e = t; e < half * kr; e += 256) {  // columns a, b of S and W
+        const int p = e / kr, j = e % kr;
+        const double s = sh.sn[p];
+        if (s == 0.0) continue;
+        const double c = sh.cs[p];
+        const int a = sh.pa[p], b = sh.pb[p];
+        const double x = S[j * ld + a], y = S[j * ld + b];
+        S[j * ld + a] = c * x - s * y;
+        S[j * ld + b] = s * x + c * y;
+        const double fx = W[(long)j * R + a], fy = W[(long)j * R + b];
+        W[(long)j * R + a] = c * fx - s * fy;
+        W[(long)j * R + b] = s * fx + c * fy;
+      }
+      __syncthreads();
+    }
+    const bool more = *sh.flag != 0;
+    __syncthreads();
+    if (!more) break;
+  }
+  // sigma^2 in decreasing order and the discarded sums
+  for (int e = t; e < kr; e += 256) sh.lam[e] = fmax(S[e * ld + e], 0.0);
+  __syncthreads();
+  for (int e = t; e < kr; e += 256) {
+    int rk = 0;
+    const double v = sh.lam[e];
+    for (int q = 0; q < kr; ++q) rk += (sh.lam[q] > v || (sh.lam[q] == v && q < e)) ? 1 : 0;
+    sh.ord[rk] = e;
+  }
+  __syncthreads();
+  if (t == 0) {
+    double acc = 0.0;
+    sh.tail[kr] = 0.0;
+    for (int q = kr - 1; q >= 0; --q) {
+      acc += sh.lam[sh.ord[q]];
+      sh.tail[q] = acc;
+    }
+  }
+  __syncthreads();
+  for (int at = 0; at < 3; ++at) {
+    const double f = at == 0 ? 0.95 : (at == 1 ? 0.7 : 0.4);
+    int kk = 0;
+    while (kk < r && sh.tail[kk] > f * eps * eps) ++kk;
+    if (kk >= r) return;  // uniform: no smaller rank
+    const int kr2 = (kk + 15) & ~15;
+    // W_k ([l][j], columns past kk zero); X_v = D_v^-1 Lv^-T B^T W_k
+    for (int e = t; e < kr * kr; e += 256) {
+      const int l = e / kr, j = e % kr;
+      Tm[(long)l * R + j] = j < kk ? W[(long)l * R + sh.ord[j]] : 0.0;
+    }
+    __syncthreads();
+    rc_gemm<true>(Bm, R, kr, Tm, R, kr, kr, Xv, R, kr, kr, sh.lds);
+    __syncthreads();
+    rc_load_factor(sh, Lv, R, kr);
+    for (int c = t; c < kk; c += 256) {
+      rc_solve<true>(sh, kr, Xv + c, R);
+      for (int p = 0; p < kr; ++p) Xv[(long)p * R + c] /= sh.dv[p];
+    }
+    __syncthreads();
+    // X_u^T row j = (D_u^-1 Lu^-T W_k(:, j))^T
+    rc_load_factor(sh, Lu, R, kr);
+    for (int c = t; c < kr; c += 256) {
+      double* z = Xu + (long)c * R;
+      for (int p = 0; p < kr; ++p) z[p] = c < kk ? Tm[(long)p * R + c] : 0.0;
+      if (c < kk) {
+        rc_solve<true>(sh, kr, z, 1);
+        for (int p = 0; p < kr; ++p) z[p] /= sh.du[p];
+      }
+    }
+    __syncthreads();
+    // U2 = U X_u (m x kr2); V2^T = X_v^T V^T and V2'^T = X_v^T V'^T (kr2 x m)
+    if (kr2 > 0) {
+      rc_gemm<false>(Up, rs, m, Xu, R, kr2, kr, U2, R, m, kr2, sh.lds);
+      rc_gemm<true>(Xv, R, kr2, Yt, m, m, kr, V2t, m, kr2, m, sh.lds);
+      rc_gemm<true>(Xv, R, kr2, Vp, m, m, kr, V2p, m, kr2, m, sh.lds);
+    }
+    __syncthreads();
+    const double res = rc_residual(A, m, U2, R, V2t, kr2, sh.lds, sh.sv);
+    if (!(res <= eps * eps)) continue;  // uniform: try a larger rank
+    for (long e = t; e < (long)m * r; e += 256) {
+      const long row = e / r;
+      const int c = (int)(e % r);
+      Up[row * rs + c] = c < kk ? U2[row * R + c] : 0.0;
+    }
+    for (long e = t; e < (long)r * m; e += 256) {
+      const int q = (int)(e / m);
+      Vp[e] = q < kk ? V2p[e] : 0.0;
+    }
+    if (t == 0) *rank_out = kk;
+    return;
+  }
+}
+
+__global__ __launch_bounds__(256, 1) void tlr_recompress_kernel(double* __restrict__ tiles, int m, int nt, int rs,
+                                                                double eps, double* __restrict__ U,
+                                                                double* __restrict__ Vt, int* __restrict__ ranks,
+                                                                double* __restrict__ scratch,
+                                                                const int* __restrict__ info) {
+  if (*info != 0) return;
+  __shared__ double S[kRcLdsR * kRcLd];  // working matrix for ranks <= 128, and the GEMM stages
+  __shared__ double cs[kTlrMaxRank / 2], sn[kTlrMaxRank / 2], lam[kTlrMaxRank], du[kTlrMaxRank],
+      dv[kTlrMaxRank], tail[kTlrMaxRank + 1], sv[256];
+  __shared__ int pa[kTlrMaxRank / 2], pb[kTlrMaxRank / 2], ord[kTlrMaxRank];
+  __shared__ int s_flag;
+  static_assert(4 * kStageDoubles <= kRcLdsR * kRcLd, "the GEMM stages alias S");
+  const long npan = (long)nt * (nt - 1) / 2;
+  double* ws = scratch + (long)blockIdx.x * tlr_rc_scratch_doubles(m, rs);
+  double* Sg = ws + tlr_rc_scratch_doubles(m, rs) - (long)rs * (rs + 1);  // working matrix for larger ranks
+  // panels in order of distance from the diagonal (the largest ranks first)
+  for (long w = blockIdx.x; w < npan; w += gridDim.x) {
+    __syncthreads();  // the previous panel is done with the LDS
+    long d = 1, rem = w;
+    while (rem >= nt - d) {
+      rem -= nt - d;
+      ++d;
+    }
+    const long k = rem, i = k + d;
+    const long pid = tri_st(i, k);
+    const int r = ranks[pid];
+    if (r < 2 || r > rs) continue;  // uniform
+    const bool big = ((r + 15) & ~15) > kRcLdsR;
+    const RcShared sh{big ? Sg : S, big ? rs + 1 : kRcLd, S, cs, sn, lam, du, dv, tail, sv, pa, pb, ord, &s_flag};
+    rc_panel(sh, tiles + tri_lo(i, k) * (long)m * m, tiles + tri_lo(k, k) * (long)m * m, U + pid * (long)m * rs,
+             Vt + pid * (long)rs * m, ranks + pid, m, rs, r, eps, ws);
+  }
+}
+
+hipError_t launch_tlr_recompress(double* tiles, int m, int nt, int rs, double eps, double* U, double* Vt, int* ranks,
+                                 double* scratch, int grid, const int* info, hipStream_t st) {
+  if (nt < 2 || grid < 1) return hipSuccess;
+  hipLaunchKernelGGL(tlr_recompress_kernel, dim3(grid), dim3(256), 0, st, tiles, m, nt, rs, eps, U, Vt, ranks, scratch,
+                     info);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------ updates
 // Left-looking: before column j is factored, every tile (i, j), i >= j,
 // takes all of its updates at once,
@@ -709,6 +1148,8 @@ hipError_t launch_tlr_cholesky(const TlrCholArgs& a, hipStream_t st) {
     e = hipGetLastError();
     if (e != hipSuccess) return fail(e);
   }
+  if (a.rc_scratch) return launch_tlr_recompress(a.tiles, m, nt, rs, a.eps, a.U, a.Vt, a.ranks, a.rc_scratch,
+                                                 a.rc_grid, a.info, st);
   return hipGetLastError();
 }
 

@@ -141,6 +141,45 @@ def test_tlr_tile_accuracy_ranks_and_probability():
     print(f"ranks mean={ranks.mean():.1f} max={ranks.max()} dlogP={r['logP'].item() - ref['logP']:.3e}")
 
 
+def _frob_eps_rank(A, eps):
+    """Smallest k with ||A - A_k||_F <= eps (A_k the truncated SVD): the
+    optimal rank for the Frobenius criterion (Eckart-Young)."""
+    s = np.linalg.svd(A, compute_uv=False)
+    tail = np.sqrt(np.cumsum((s ** 2)[::-1]))[::-1]  # tail[k] = ||s[k:]||
+    return int(np.sum(tail > eps))
+
+
+@pytest.mark.parametrize("n,tile,eps", [(2048, 256, 1e-6), (1536, 128, 1e-5)])
+def test_tlr_recompressed_ranks_near_svd_eps_rank(n, tile, eps):
+    """After the recompression every panel keeps ||A_ik - U V'^T L_kk^T||_F
+    <= eps, no rank is below the tile's Frobenius eps-rank (no rank-k matrix
+    does better than the truncated SVD), and the ranks sum to within 10% of
+    the eps-ranks' sum."""
+    print(f"tlr recompression n={n} tile={tile} eps={eps}", flush=True)
+    locs, kern, a, b = _tlr_inputs(64, n, seed=91)
+    f = _factor(n, locs, kern, tile, eps, 128)
+    assert f.info() == 0
+    tiles = f.tiles().cpu().numpy()
+    U, Vt, ranks = f.U().cpu().numpy(), f.Vt().cpu().numpy(), f.ranks().cpu().numpy()
+    tot_r = tot_opt = 0
+    for i in range(f.nt):
+        for k in range(i):
+            p = i * (i - 1) // 2 + k
+            A = tiles[i * (i + 1) // 2 + k]
+            Dk = np.tril(tiles[k * (k + 1) // 2 + k])
+            r = int(ranks[p])
+            assert r >= 0
+            assert np.all(U[p][:, r:] == 0) and np.all(Vt[p][r:] == 0)
+            res = np.linalg.norm(A - (U[p] @ Vt[p]) @ Dk.T)
+            assert res <= eps * (1 + 1e-6) + 1e-12, (i, k, res)
+            kopt = _frob_eps_rank(A, eps)
+            assert r >= kopt, (i, k, r, kopt)
+            tot_r += r
+            tot_opt += kopt
+    print(f"sum of ranks {tot_r}, of Frobenius eps-ranks {tot_opt}: ratio {tot_r / max(tot_opt, 1):.3f}", flush=True)
+    assert tot_r <= 1.10 * tot_opt
+
+
 def test_tlr_rank_cap_is_flagged():
     """A cap below the eps-rank is reported by a negative rank; with a large
     nugget the truncated matrix stays positive definite."""
