@@ -320,7 +320,9 @@ TlrGeom tlr_geom(int n, int m, int max_rank) {
   G.ws_t = w; w = align_up(w + sizeof(double) * (size_t)batch * m * G.rs);
   // recompression: one workgroup per panel, at most kTlrRcGrid
   G.rc_grid = (int)std::min<long>(mvn::kTlrRcGrid, G.npanels);
-  G.ws_rc = w; w = align_up(w + sizeof(double) * (size_t)G.rc_grid * (size_t)mvn::tlr_rc_scratch_doubles(m, G.rs));
+  // (+ the panel counter after the slots)
+  G.ws_rc = w;
+  w = align_up(w + sizeof(double) * (size_t)G.rc_grid * (size_t)mvn::tlr_rc_scratch_doubles(m, G.rs) + 64);
   G.ws_total = w;
   return G;
 }

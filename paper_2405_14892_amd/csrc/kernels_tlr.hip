@@ -439,8 +439,8 @@ __global__ __launch_bounds__(256) void tlr_trsm_rows_kernel(const double* __rest
 }
 
 // ------------------------------------------------------------ recompression
-// After the factorisation every panel L_ik = U V'^T (rank r >= 2, not
-// capped) is recompressed to the smallest rank whose error in the tile
+// After the factorisation every panel L_ik = U V'^T (rank 2 <= r <= 192,
+// not capped) is recompressed to the smallest rank whose error in the tile
 // it approximates stays within eps (Section III-E: the truncated SVD of the
 // tile, here taken within the column and row spaces the cross approximation
 // found).  With V = L_kk V' (A_ik ~ U V^T):
@@ -452,8 +452,8 @@ __global__ __launch_bounds__(256) void tlr_trsm_rows_kernel(const double* __rest
 //      projection onto them, whose residual ||A - Q_u B Q_v^T|| is orthogonal
 //      to any change inside them;
 //   3. B B^T = W diag(sigma^2) W^T by cyclic Jacobi (the disjoint rotations of
-//      a round-robin schedule applied together; the working matrix in LDS up
-//      to rank 128, else in the scratch; W in the scratch);
+//      a round-robin schedule applied together; the matrix packed in LDS, so
+//      ranks up to 192; W in the scratch);
 //   4. k = the smallest rank whose discarded sum of sigma^2 is <= f eps^2
 //      (f = 0.95, then 0.7, 0.4), and with W_k the top k vectors
 //        U2 = U X_u, X_u = D_u^-1 Lu^-T W_k;  V2'^T = X_v^T V'^T,
@@ -463,23 +463,37 @@ __global__ __launch_bounds__(256) void tlr_trsm_rows_kernel(const double* __rest
 //   5. the new factors replace the old ones only if the exact residual
 //      ||A - U2 V2^T||_F (V2^T = X_v^T V^T) is <= eps.
 // Small products on MFMA in 128 x 128 blocks with masked, double-buffered
-// LDS stages; triangular solves one vector per lane against the factor in
-// the working matrix.  One workgroup per CU takes the panels in order of
+// LDS stages; triangular solves one vector per lane against the factor
+// packed in LDS.  One workgroup per CU takes the panels in order of
 // distance from the diagonal, each with its own scratch.
 // Stage loads of the small products, masked at the operand edges: lane t
 // holds 8 values of one stage (k row t / 16, columns 8 (t % 16) .. + 7 for a
 // k-major operand; row t / 2, k 8 (t % 2) .. + 7 for a row-major one).
+__device__ __forceinline__ void rc_load8(const double* __restrict__ p, bool full, int nv, double (&r)[8]) {
+  if (full && (((uintptr_t)p & 15) == 0)) {
+    const double2* p2 = reinterpret_cast<const double2*>(p);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const double2 v = p2[q];
+      r[2 * q] = v.x;
+      r[2 * q + 1] = v.y;
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) r[q] = q < nv ? p[q] : 0.0;
+  }
+}
 __device__ __forceinline__ void rc_load_kmaj(const double* __restrict__ A, long lda, int na, int K, int k0,
                                              double (&r)[8]) {
   const int t = threadIdx.x, k = k0 + (t >> 4), cb = (t & 15) * 8;
-#pragma unroll
-  for (int q = 0; q < 8; ++q) r[q] = (k < K && cb + q < na) ? A[(long)k * lda + cb + q] : 0.0;
+  const int nv = k < K ? min(8, na - cb) : 0;
+  rc_load8(A + (long)k * lda + cb, nv >= 8, nv, r);
 }
 __device__ __forceinline__ void rc_load_rmaj(const double* __restrict__ A, long lda, int na, int K, int k0,
                                              double (&r)[8]) {
   const int t = threadIdx.x, row = t >> 1, kb = k0 + (t & 1) * 8;
-#pragma unroll
-  for (int q = 0; q < 8; ++q) r[q] = (row < na && kb + q < K) ? A[(long)row * lda + kb + q] : 0.0;
+  const int nv = row < na ? min(8, K - kb) : 0;
+  rc_load8(A + (long)row * lda + kb, nv >= 8, nv, r);
 }
 
 // One 128 x 128 block: acc = A^T B (TN: both operands k-major) or A B^T
@@ -551,6 +565,133 @@ __device__ __noinline__ void rc_gemm(const double* __restrict__ A, long lda, int
     }
 }
 
+// Thin products for ranks up to 32, operands loaded straight into registers
+// (each entry of the m x m tile is used once: no LDS stage, no barrier).
+// Wave w takes the 16-row tiles w, w + 4, ...; for MFMA j of a 16-deep step
+// k0, lane (r = lane & 15, q = lane >> 4) supplies its A row's and its B row's
+// values at k = k0 + 4q + j (the same bijection of k for both operands).
+struct RcThin {
+  double a[4];
+  double b[2][4];
+};
+
+__device__ __forceinline__ void rc_thin_load(const double* __restrict__ pa, const double* __restrict__ pb0,
+                                             const double* __restrict__ pb1, bool v0, bool v1, int k0, RcThin& g) {
+  const double2* a2 = reinterpret_cast<const double2*>(pa + k0);
+  const double2 a0 = a2[0], a1 = a2[1];
+  g.a[0] = a0.x; g.a[1] = a0.y; g.a[2] = a1.x; g.a[3] = a1.y;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    g.b[0][j] = v0 ? pb0[k0 + j] : 0.0;
+    g.b[1][j] = v1 ? pb1[k0 + j] : 0.0;
+  }
+}
+
+__device__ __forceinline__ void rc_thin_mma(const RcThin& g, f64x4& c0, f64x4& c1) {
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(g.a[j], g.b[0][j], c0, 0, 0, 0);
+    c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(g.a[j], g.b[1][j], c1, 0, 0, 0);
+  }
+}
+
+// C = A B^T: rows i < M (a multiple of 16) of A (lda), rows j < N <= 32 of
+// B (ldb), k < K (a multiple of 16), or k < 16 (tile + 1) with LOWER (A lower
+// triangular).  TRANSC stores C^T (C[j ldc + i]).
+template <bool LOWER, bool TRANSC>
+__device__ __noinline__ void rc_thin_nt(const double* __restrict__ A, long lda, int M, const double* __restrict__ B,
+                                        long ldb, int N, int K, double* __restrict__ C, long ldc) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, r = lane & 15, q = lane >> 4;
+  const bool v0 = r < N, v1 = 16 + r < N;
+  const double* pb0 = B + (long)(v0 ? r : 0) * ldb + 4 * q;
+  const double* pb1 = B + (long)(v1 ? 16 + r : 0) * ldb + 4 * q;
+  for (int rt = w; rt * 16 < M; rt += 4) {
+    const int kmax = LOWER ? min(K, 16 * (rt + 1)) : K;
+    const double* pa = A + (long)(16 * rt + r) * lda + 4 * q;
+    f64x4 c0 = {0.0, 0.0, 0.0, 0.0}, c1 = {0.0, 0.0, 0.0, 0.0};
+    RcThin g0, g1, g2;
+    rc_thin_load(pa, pb0, pb1, v0, v1, 0, g0);
+    if (16 < kmax) rc_thin_load(pa, pb0, pb1, v0, v1, 16, g1);
+    for (int k0 = 0; k0 < kmax; k0 += 48) {
+      if (k0 + 32 < kmax) rc_thin_load(pa, pb0, pb1, v0, v1, k0 + 32, g2);
+      rc_thin_mma(g0, c0, c1);
+      if (k0 + 16 >= kmax) break;
+      if (k0 + 48 < kmax) rc_thin_load(pa, pb0, pb1, v0, v1, k0 + 48, g0);
+      rc_thin_mma(g1, c0, c1);
+      if (k0 + 32 >= kmax) break;
+      if (k0 + 64 < kmax) rc_thin_load(pa, pb0, pb1, v0, v1, k0 + 64, g1);
+      rc_thin_mma(g2, c0, c1);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const long i = 16 * rt + q + 4 * v;
+      if (v0) {
+        if (TRANSC) C[(long)r * ldc + i] = c0[v]; else C[i * ldc + r] = c0[v];
+      }
+      if (v1) {
+        if (TRANSC) C[(long)(16 + r) * ldc + i] = c1[v]; else C[i * ldc + 16 + r] = c1[v];
+      }
+    }
+  }
+}
+
+// ||A - U2 V2^T||_F^2 for the m x m tile A, U2 and V2 (m x K row-major, ld,
+// K <= 32 and a multiple of 16, columns past the rank zero): per 16-row tile
+// and pair of 16-column tiles, the product on MFMA folded against A, with the
+// next pair's operands loaded ahead.
+__device__ __noinline__ double rc_thin_residual(const double* __restrict__ A, int m, const double* __restrict__ U2,
+                                                const double* __restrict__ V2, int ld, int K, double* sv) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, r = lane & 15, q = lane >> 4;
+  double res2 = 0.0;
+  for (int rt = w; rt * 16 < m; rt += 4) {
+    const double* pa = U2 + (long)(16 * rt + r) * ld + 4 * q;
+    double ua[2][4];
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) ua[s][j] = 16 * s < K ? pa[16 * s + j] : 0.0;
+    const double* arow = A + (long)(16 * rt + q) * m + r;
+    // stage: B operands of two column tiles and the A entries they meet
+    double vb[2][2][4], av[2][4];
+    const auto load = [&](int ct) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const double* pv = V2 + (long)(16 * (ct + h) + r) * ld + 4 * q;
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) vb[h][s][j] = 16 * s < K ? pv[16 * s + j] : 0.0;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) av[h][v] = arow[(long)4 * v * m + 16 * (ct + h)];
+      }
+    };
+    load(0);
+    for (int ct = 0; ct < m / 16; ct += 2) {
+      f64x4 c0 = {0.0, 0.0, 0.0, 0.0}, c1 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(ua[s][j], vb[0][s][j], c0, 0, 0, 0);
+          c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(ua[s][j], vb[1][s][j], c1, 0, 0, 0);
+        }
+      double a0[4], a1[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        a0[v] = av[0][v];
+        a1[v] = av[1][v];
+      }
+      if (ct + 2 < m / 16) load(ct + 2);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const double d0 = a0[v] - c0[v], d1 = a1[v] - c1[v];
+        res2 += d0 * d0 + d1 * d1;
+      }
+    }
+  }
+  return block_sum(res2, sv);
+}
+
 __device__ __noinline__ double rc_residual(const double* __restrict__ A, int m, const double* __restrict__ Up, int ld,
                                            const double* __restrict__ Vp, int kr, double* lds, double* sv) {
   return residual_norm2(A, m, Up, ld, Vp, kr, lds, sv);
@@ -567,15 +708,18 @@ __device__ __forceinline__ void rc_pair(int n, int rho, int p, int& a, int& b) {
   }
 }
 
-constexpr int kRcLdsR = 128;       // ranks up to this keep the eigenproblem in LDS
-constexpr int kRcLd = kRcLdsR + 1; // its LDS row stride
+constexpr int kRcMaxRank = 192;  // largest rank recompressed: its packed working matrix fills the LDS
+constexpr int kRcPacked = kRcMaxRank * (kRcMaxRank + 1) / 2;
 constexpr int kRcSweeps = 15;
+
+// Packed symmetric / lower-triangular storage: (i, j), j <= i, at i(i+1)/2 + j.
+__device__ __forceinline__ int rc_pk(int i, int j) { return i >= j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i; }
+
+typedef __attribute__((address_space(3))) double rc_lds;
 
 // Shared state of one workgroup's recompression.
 struct RcShared {
-  double* S;         // the kr x kr working matrix (LDS, or the scratch slot for larger ranks)
-  int sld;           // its row stride
-  double* lds;       // GEMM stages (aliases the LDS matrix)
+  double* S;         // packed kr x kr working matrix (LDS), also the GEMM stages
   double *cs, *sn, *lam, *du, *dv, *tail, *sv;
   int *pa, *pb, *ord, *flag;
 };
@@ -587,66 +731,193 @@ struct RcShared {
 __device__ __forceinline__ bool rc_gram_chol(const RcShared& sh, double* __restrict__ G, int R, int kr, int r,
                                              double* d) {
   const int t = threadIdx.x;
-  double* S = sh.S;
-  const int ld = sh.sld;
+  rc_lds* S = (rc_lds*)sh.S;
   for (int e = t; e < kr; e += 256) d[e] = e < r ? sqrt(G[(long)e * R + e]) : 1.0;
   if (t == 0) *sh.flag = 0;
   __syncthreads();
   for (int e = t; e < kr * kr; e += 256) {
     const int p = e / kr, q = e % kr;
-    S[p * ld + q] = (p < r && q < r) ? G[(long)p * R + q] / (d[p] * d[q]) : (p == q ? 1.0 : 0.0);
+    if (q <= p) S[rc_pk(p, q)] = (p < r && q < r) ? G[(long)p * R + q] / (d[p] * d[q]) : (p == q ? 1.0 : 0.0);
   }
   __syncthreads();
   for (int j = 0; j < kr; ++j) {
     if (t == 0) {
-      const double piv = S[j * ld + j];
+      const double piv = S[rc_pk(j, j)];
       if (!(piv > 0.0) || !isfinite(piv)) *sh.flag = 1;
-      S[j * ld + j] = piv > 0.0 ? sqrt(piv) : 1.0;
+      S[rc_pk(j, j)] = piv > 0.0 ? sqrt(piv) : 1.0;
     }
     __syncthreads();
-    const double dj = S[j * ld + j];
-    for (int e = j + 1 + t; e < kr; e += 256) S[e * ld + j] /= dj;
+    const double dj = S[rc_pk(j, j)];
+    for (int e = j + 1 + t; e < kr; e += 256) S[rc_pk(e, j)] /= dj;
     __syncthreads();
     const int nr = kr - j - 1;
     for (int e = t; e < nr * nr; e += 256) {
       const int ii = j + 1 + e / nr, ll = j + 1 + e % nr;
-      if (ll <= ii) S[ii * ld + ll] -= S[ii * ld + j] * S[ll * ld + j];
+      if (ll <= ii) S[rc_pk(ii, ll)] -= S[rc_pk(ii, j)] * S[rc_pk(ll, j)];
     }
     __syncthreads();
   }
   const bool ok = *sh.flag == 0;
   for (int e = t; e < kr * kr; e += 256) {
     const int p = e / kr, q = e % kr;
-    G[(long)p * R + q] = q <= p ? S[p * ld + q] : 0.0;
+    G[(long)p * R + q] = q <= p ? S[rc_pk(p, q)] : 0.0;
   }
   __syncthreads();
   return ok;
 }
 
-// Lower factor (kr x kr, row stride R) into the working matrix.
+// Lower factor (kr x kr, row stride R) into the packed working matrix.
 __device__ __forceinline__ void rc_load_factor(const RcShared& sh, const double* __restrict__ Lg, int R, int kr) {
-  for (int e = threadIdx.x; e < kr * kr; e += 256) sh.S[(e / kr) * sh.sld + e % kr] = Lg[(long)(e / kr) * R + e % kr];
+  for (int e = threadIdx.x; e < kr * kr; e += 256) {
+    const int p = e / kr, q = e % kr;
+    if (q <= p) ((rc_lds*)sh.S)[rc_pk(p, q)] = Lg[(long)p * R + q];
+  }
   __syncthreads();
 }
 
-// With the lower factor F in the working matrix, vector x (stride sx) in
-// place: forward F x = b, or (TRANS) backward F^T x = b.
+// With the lower factor F packed in the working matrix, vector x (stride sx)
+// in place: forward F x = b, or (TRANS) backward F^T x = b.
 template <bool TRANS>
 __device__ __forceinline__ void rc_solve(const RcShared& sh, int kr, double* __restrict__ x, long sx) {
-  const double* S = sh.S;
-  const int ld = sh.sld;
+  const rc_lds* S = (const rc_lds*)sh.S;
   if (!TRANS) {
     for (int p = 0; p < kr; ++p) {
-      double v = x[p * sx];
-      for (int l = 0; l < p; ++l) v -= S[p * ld + l] * x[l * sx];
-      x[p * sx] = v / S[p * ld + p];
+      const rc_lds* Sp = S + p * (p + 1) / 2;
+      double v0 = x[p * sx], v1 = 0.0;
+      int l = 0;
+      for (; l + 1 < p; l += 2) {
+        v0 -= Sp[l] * x[l * sx];
+        v1 -= Sp[l + 1] * x[(l + 1) * sx];
+      }
+      if (l < p) v0 -= Sp[l] * x[l * sx];
+      x[p * sx] = (v0 + v1) / Sp[p];
     }
   } else {
     for (int p = kr - 1; p >= 0; --p) {
-      double v = x[p * sx];
-      for (int l = p + 1; l < kr; ++l) v -= S[l * ld + p] * x[l * sx];
-      x[p * sx] = v / S[p * ld + p];
+      double v0 = x[p * sx], v1 = 0.0;
+      int l = p + 1;
+      for (; l + 1 < kr; l += 2) {
+        v0 -= S[l * (l + 1) / 2 + p] * x[l * sx];
+        v1 -= S[(l + 1) * (l + 2) / 2 + p] * x[(l + 1) * sx];
+      }
+      if (l < kr) v0 -= S[l * (l + 1) / 2 + p] * x[l * sx];
+      x[p * sx] = (v0 + v1) / S[p * (p + 1) / 2 + p];
     }
+  }
+}
+
+// Eigen-decomposition of the symmetric kr x kr matrix packed in the working
+// matrix by cyclic Jacobi: the disjoint rotations of a round of a round-robin
+// schedule are applied together, as 2 x 2 block transforms between pairs
+// (J_P^T [S_PQ] J_Q, each block read and written once) in one phase; the
+// accumulated rotations are kept transposed (Wt = W^T, kr x kr, row stride
+// R, scratch), so that a rotation of columns a, b of W updates rows a, b of
+// Wt with consecutive lanes on consecutive entries.  A rotation is skipped
+// when |S_ab| <= 1e-14 sqrt(S_aa S_bb); a sweep without rotations ends.  On
+// return the diagonal holds the eigenvalues and Wt the eigenvectors as rows.
+__device__ __forceinline__ void rc_jacobi(const RcShared& sh, int kr, double* __restrict__ Wt, int R) {
+  const int t = threadIdx.x, np = kr / 2;
+  rc_lds* S = (rc_lds*)sh.S;
+  const int nh = kr <= 128 ? 256 / kr : 1;  // lanes per column of Wt (kr >= 16)
+  const int jc = t % kr, hh = t / kr;
+  for (int e = t; e < kr * kr; e += 256) {
+    const int p = e / kr, q = e - (e / kr) * kr;
+    Wt[(long)p * R + q] = p == q ? 1.0 : 0.0;
+  }
+  // the block items (P, Q), P <= Q, of this lane: P rows of the triangle in
+  // order, precomputed once (np (np + 1) / 2 <= 4656 items, <= 19 per lane)
+  constexpr int kMaxItems = (kRcMaxRank / 2) * (kRcMaxRank / 2 + 1) / 2 / 256 + 1;
+  short iP[kMaxItems], iQ[kMaxItems];
+  int nitems = 0;
+  {
+    int P = 0, Q = 0, e = 0;
+    for (int it = 0; it < kMaxItems; ++it) {
+      const int target = t + 256 * it;
+      // advance (P, Q) to the target-th pair of the triangle (row P, Q >= P)
+      while (e < target && P < np) {
+        ++e;
+        if (++Q == np) {
+          ++P;
+          Q = P;
+        }
+      }
+      if (P < np && e == target) {
+        iP[it] = (short)P;
+        iQ[it] = (short)Q;
+        nitems = it + 1;
+      } else {
+        iP[it] = iQ[it] = -1;
+      }
+    }
+  }
+  for (int sw = 0; sw < kRcSweeps; ++sw) {
+    if (t == 0) *sh.flag = 0;
+    __syncthreads();
+    for (int rho = 0; rho < kr - 1; ++rho) {
+      if (t < np) {
+        int a, b;
+        rc_pair(kr, rho, t, a, b);
+        const double app = S[rc_pk(a, a)], aqq = S[rc_pk(b, b)], apq = S[rc_pk(a, b)];
+        double c = 1.0, s = 0.0;
+        if (apq != 0.0 && fabs(apq) > 1e-14 * sqrt(fabs(app * aqq))) {
+          const double th = (aqq - app) / (2.0 * apq);
+          const double tt = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
+          c = 1.0 / sqrt(1.0 + tt * tt);
+          s = tt * c;
+          *sh.flag = 1;
+        }
+        sh.cs[t] = c;
+        sh.sn[t] = s;
+        sh.pa[t] = a;
+        sh.pb[t] = b;
+      }
+      __syncthreads();
+      // blocks (P, Q), P <= Q: rows by P's rotation, columns by Q's
+      for (int it = 0; it < nitems; ++it) {
+        const int P = iP[it], Q = iQ[it];
+        if (P < 0) continue;
+        const double sP = sh.sn[P], sQ = sh.sn[Q];
+        if (sP == 0.0 && sQ == 0.0) continue;
+        const double cP = sh.cs[P], cQ = sh.cs[Q];
+        const int a = sh.pa[P], b = sh.pb[P], c = sh.pa[Q], d = sh.pb[Q];
+        const int iac = rc_pk(a, c), iad = rc_pk(a, d), ibc = rc_pk(b, c), ibd = rc_pk(b, d);
+        const double xac = S[iac], xad = S[iad], xbc = S[ibc], xbd = S[ibd];
+        const double rac = cP * xac - sP * xbc, rad = cP * xad - sP * xbd;
+        const double rbc = sP * xac + cP * xbc, rbd = sP * xad + cP * xbd;
+        S[iac] = cQ * rac - sQ * rad;
+        S[ibd] = sQ * rbc + cQ * rbd;
+        S[iad] = sQ * rac + cQ * rad;                 // for P == Q the pair's own (a, b) entry
+        if (P != Q) S[ibc] = cQ * rbc - sQ * rbd;
+      }
+      // rows a, b of Wt: lane t takes column jc of every nh-th pair from hh,
+      // the loads of 16 pairs issued before their stores
+      if (hh < nh) {
+        for (int P0 = hh; P0 < np; P0 += 16 * nh) {
+          double xa[16], xb[16];
+#pragma unroll
+          for (int u = 0; u < 16; ++u) {
+            const int P = P0 + u * nh;
+            if (P < np && sh.sn[P] != 0.0) {
+              xa[u] = Wt[(long)sh.pa[P] * R + jc];
+              xb[u] = Wt[(long)sh.pb[P] * R + jc];
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < 16; ++u) {
+            const int P = P0 + u * nh;
+            if (P < np && sh.sn[P] != 0.0) {
+              const double cP = sh.cs[P], sP = sh.sn[P];
+              Wt[(long)sh.pa[P] * R + jc] = cP * xa[u] - sP * xb[u];
+              Wt[(long)sh.pb[P] * R + jc] = sP * xa[u] + cP * xb[u];
+            }
+          }
+        }
+      }
+      __syncthreads();
+    }
+    const bool more = *sh.flag != 0;
+    __syncthreads();
+    if (!more) break;
   }
 }
 
@@ -663,27 +934,34 @@ __device__ __forceinline__ void rc_panel(const RcShared& sh, const double* __res
   double* V2p = V2t + (long)R * m;
   double* Lu = V2p + (long)R * m;
   double* Lv = Lu + (long)R * R;
-  double* W = Lv + (long)R * R;
+  double* W = Lv + (long)R * R;          // B B^T, then the eigenvectors as rows
   double* Bm = W + (long)R * R;
   double* Tm = Bm + (long)R * R;
   double* Xu = Tm + (long)R * R;
   double* Xv = Xu + (long)R * R;
   double* S = sh.S;
-  const int ld = sh.sld;
+  const bool thin = kr <= 32;
   // V^T = V'^T L_kk^T (column block tn of L_kk^T needs L_kk's first 128 (tn + 1) columns)
-  for (int tn = 0; tn < m / kTile; ++tn)
-    rc_gemm<false>(Vp, m, kr, Lkk + (long)tn * kTile * m, m, kTile, (tn + 1) * kTile, Yt + tn * kTile, m, kr, kTile,
-                   sh.lds);
+  if (thin) {
+    rc_thin_nt<true, true>(Lkk, m, m, Vp, m, kr, m, Yt, m);
+  } else {
+    for (int tn = 0; tn < m / kTile; ++tn)
+      rc_gemm<false>(Vp, m, kr, Lkk + (long)tn * kTile * m, m, kTile, (tn + 1) * kTile, Yt + tn * kTile, m, kr,
+                     kTile, S);
+  }
   __syncthreads();
-  rc_gemm<true>(Up, rs, kr, Up, rs, kr, m, Lu, R, kr, kr, sh.lds);
-  rc_gemm<false>(Yt, m, kr, Yt, m, kr, m, Lv, R, kr, kr, sh.lds);
+  rc_gemm<true>(Up, rs, kr, Up, rs, kr, m, Lu, R, kr, kr, S);
+  rc_gemm<false>(Yt, m, kr, Yt, m, kr, m, Lv, R, kr, kr, S);
   __syncthreads();
   if (!rc_gram_chol(sh, Lu, R, kr, r, sh.du)) return;
   if (!rc_gram_chol(sh, Lv, R, kr, r, sh.dv)) return;
   // U^T A V (A V staged in U2's buffer), scaled by D_u^-1 . D_v^-1
-  rc_gemm<false>(A, m, m, Yt, m, kr, m, U2, R, m, kr, sh.lds);
+  if (thin)
+    rc_thin_nt<false, false>(A, m, m, Yt, m, kr, m, U2, R);
+  else
+    rc_gemm<false>(A, m, m, Yt, m, kr, m, U2, R, m, kr, S);
   __syncthreads();
-  rc_gemm<true>(Up, rs, kr, U2, R, kr, m, Tm, R, kr, kr, sh.lds);
+  rc_gemm<true>(Up, rs, kr, U2, R, kr, m, Tm, R, kr, kr, S);
   __syncthreads();
   for (int e = t; e < kr * kr; e += 256) {
     const int p = e / kr, q = e % kr;
@@ -699,71 +977,17 @@ __device__ __forceinline__ void rc_panel(const RcShared& sh, const double* __res
   __syncthreads();
   for (int e = t; e < kr * kr; e += 256) Bm[(long)(e / kr) * R + e % kr] = Tm[(long)(e / kr) * R + e % kr];
   __syncthreads();
-  // B B^T into the working matrix (via W's slot), W = I, cyclic Jacobi
-  rc_gemm<false>(Bm, R, kr, Bm, R, kr, kr, W, R, kr, kr, sh.lds);
+  // B B^T (via W's slot) packed into the working matrix, then its eigenvectors
+  rc_gemm<false>(Bm, R, kr, Bm, R, kr, kr, W, R, kr, kr, S);
   __syncthreads();
   for (int e = t; e < kr * kr; e += 256) {
     const int p = e / kr, q = e % kr;
-    S[p * ld + q] = 0.5 * (W[(long)p * R + q] + W[(long)q * R + p]);  // symmetric against rounding
+    if (q <= p) S[rc_pk(p, q)] = 0.5 * (W[(long)p * R + q] + W[(long)q * R + p]);  // symmetric against rounding
   }
   __syncthreads();
-  for (int e = t; e < kr * kr; e += 256) W[(long)(e / kr) * R + e % kr] = (e / kr == e % kr) ? 1.0 : 0.0;
-  __syncthreads();
-  const int half = kr / 2;
-  for (int sw = 0; sw < kRcSweeps; ++sw) {
-    if (t == 0) *sh.flag = 0;
-    __syncthreads();
-    for (int rho = 0; rho < kr - 1; ++rho) {
-      for (int p = t; p < half; p += 256) {
-        int a, b;
-        rc_pair(kr, rho, p, a, b);
-        const double app = S[a * ld + a], aqq = S[b * ld + b], apq = S[a * ld + b];
-        double c = 1.0, s = 0.0;
-        if (apq != 0.0 && fabs(apq) > 1e-15 * sqrt(fabs(app * aqq))) {
-          const double th = (aqq - app) / (2.0 * apq);
-          const double tt = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
-          c = 1.0 / sqrt(1.0 + tt * tt);
-          s = tt * c;
-          *sh.flag = 1;
-        }
-        sh.cs[p] = c;
-        sh.sn[p] = s;
-        sh.pa[p] = a;
-        sh.pb[p] = b;
-      }
-      __syncthreads();
-      for (int e = t; e < half * kr; e += 256) {  // rows a, b of S
-        const int p = e / kr, j = e % kr;
-        const double s = sh.sn[p];
-        if (s == 0.0) continue;
-        const double c = sh.cs[p];
-        const int a = sh.pa[p], b = sh.pb[p];
-        const double x = S[a * ld + j], y = S[b * ld + j];
-        S[a * ld + j] = c * x - s * y;
-        S[b * ld + j] = s * x + c * y;
-      }
-      __syncthreads();
-      for (int e = t; e < half * kr; e += 256) {  // columns a, b of S and W
-        const int p = e / kr, j = e % kr;
-        const double s = sh.sn[p];
-        if (s == 0.0) continue;
-        const double c = sh.cs[p];
-        const int a = sh.pa[p], b = sh.pb[p];
-        const double x = S[j * ld + a], y = S[j * ld + b];
-        S[j * ld + a] = c * x - s * y;
-        S[j * ld + b] = s * x + c * y;
-        const double fx = W[(long)j * R + a], fy = W[(long)j * R + b];
-        W[(long)j * R + a] = c * fx - s * fy;
-        W[(long)j * R + b] = s * fx + c * fy;
-      }
-      __syncthreads();
-    }
-    const bool more = *sh.flag != 0;
-    __syncthreads();
-    if (!more) break;
-  }
+  rc_jacobi(sh, kr, W, R);
   // sigma^2 in decreasing order and the discarded sums
-  for (int e = t; e < kr; e += 256) sh.lam[e] = fmax(S[e * ld + e], 0.0);
+  for (int e = t; e < kr; e += 256) sh.lam[e] = fmax(S[rc_pk(e, e)], 0.0);
   __syncthreads();
   for (int e = t; e < kr; e += 256) {
     int rk = 0;
@@ -790,10 +1014,10 @@ __device__ __forceinline__ void rc_panel(const RcShared& sh, const double* __res
     // W_k ([l][j], columns past kk zero); X_v = D_v^-1 Lv^-T B^T W_k
     for (int e = t; e < kr * kr; e += 256) {
       const int l = e / kr, j = e % kr;
-      Tm[(long)l * R + j] = j < kk ? W[(long)l * R + sh.ord[j]] : 0.0;
+      Tm[(long)l * R + j] = j < kk ? W[(long)sh.ord[j] * R + l] : 0.0;
     }
     __syncthreads();
-    rc_gemm<true>(Bm, R, kr, Tm, R, kr, kr, Xv, R, kr, kr, sh.lds);
+    rc_gemm<true>(Bm, R, kr, Tm, R, kr, kr, Xv, R, kr, kr, S);
     __syncthreads();
     rc_load_factor(sh, Lv, R, kr);
     for (int c = t; c < kk; c += 256) {
@@ -812,14 +1036,20 @@ __device__ __forceinline__ void rc_panel(const RcShared& sh, const double* __res
       }
     }
     __syncthreads();
-    // U2 = U X_u (m x kr2); V2^T = X_v^T V^T and V2'^T = X_v^T V'^T (kr2 x m)
+    // U2 = U X_u (m x kr2); V2 = V X_v (m x kr2, thin) or V2^T (kr2 x m) for
+    // the check; V2'^T = X_v^T V'^T (kr2 x m)
     if (kr2 > 0) {
-      rc_gemm<false>(Up, rs, m, Xu, R, kr2, kr, U2, R, m, kr2, sh.lds);
-      rc_gemm<true>(Xv, R, kr2, Yt, m, m, kr, V2t, m, kr2, m, sh.lds);
-      rc_gemm<true>(Xv, R, kr2, Vp, m, m, kr, V2p, m, kr2, m, sh.lds);
+      rc_gemm<false>(Up, rs, m, Xu, R, kr2, kr, U2, R, m, kr2, S);
+      if (thin)
+        rc_gemm<true>(Yt, m, m, Xv, R, kr2, kr, V2t, R, m, kr2, S);
+      else
+        rc_gemm<true>(Xv, R, kr2, Yt, m, m, kr, V2t, m, kr2, m, S);
+      rc_gemm<true>(Xv, R, kr2, Vp, m, m, kr, V2p, m, kr2, m, S);
     }
     __syncthreads();
-    const double res = rc_residual(A, m, U2, R, V2t, kr2, sh.lds, sh.sv);
+    const double res = kr2 == 0 ? rc_thin_residual(A, m, U2, V2t, R, 0, sh.sv)
+                       : thin   ? rc_thin_residual(A, m, U2, V2t, R, kr2, sh.sv)
+                                : rc_residual(A, m, U2, R, V2t, kr2, S, sh.sv);
     if (!(res <= eps * eps)) continue;  // uniform: try a larger rank
     for (long e = t; e < (long)m * r; e += 256) {
       const long row = e / r;
@@ -835,24 +1065,36 @@ __device__ __forceinline__ void rc_panel(const RcShared& sh, const double* __res
   }
 }
 
+__global__ void tlr_rc_queue_init_kernel(unsigned long long* __restrict__ q) {
+  if (threadIdx.x == 0) *q = 0ull;
+}
+
 __global__ __launch_bounds__(256, 1) void tlr_recompress_kernel(double* __restrict__ tiles, int m, int nt, int rs,
                                                                 double eps, double* __restrict__ U,
                                                                 double* __restrict__ Vt, int* __restrict__ ranks,
                                                                 double* __restrict__ scratch,
+                                                                unsigned long long* __restrict__ queue,
                                                                 const int* __restrict__ info) {
   if (*info != 0) return;
-  __shared__ double S[kRcLdsR * kRcLd];  // working matrix for ranks <= 128, and the GEMM stages
-  __shared__ double cs[kTlrMaxRank / 2], sn[kTlrMaxRank / 2], lam[kTlrMaxRank], du[kTlrMaxRank],
-      dv[kTlrMaxRank], tail[kTlrMaxRank + 1], sv[256];
-  __shared__ int pa[kTlrMaxRank / 2], pb[kTlrMaxRank / 2], ord[kTlrMaxRank];
+  __shared__ double S[kRcPacked];  // packed working matrix, and the GEMM stages
+  __shared__ double cs[kRcMaxRank / 2], sn[kRcMaxRank / 2], lam[kRcMaxRank], du[kRcMaxRank], dv[kRcMaxRank],
+      tail[kRcMaxRank + 1], sv[8];
+  __shared__ int pa[kRcMaxRank / 2], pb[kRcMaxRank / 2], ord[kRcMaxRank];
   __shared__ int s_flag;
-  static_assert(4 * kStageDoubles <= kRcLdsR * kRcLd, "the GEMM stages alias S");
+  __shared__ long s_w;
+  static_assert(4 * kStageDoubles <= kRcPacked, "the GEMM stages alias S");
   const long npan = (long)nt * (nt - 1) / 2;
   double* ws = scratch + (long)blockIdx.x * tlr_rc_scratch_doubles(m, rs);
-  double* Sg = ws + tlr_rc_scratch_doubles(m, rs) - (long)rs * (rs + 1);  // working matrix for larger ranks
-  // panels in order of distance from the diagonal (the largest ranks first)
-  for (long w = blockIdx.x; w < npan; w += gridDim.x) {
-    __syncthreads();  // the previous panel is done with the LDS
+  const RcShared sh{S, cs, sn, lam, du, dv, tail, sv, pa, pb, ord, &s_flag};
+  // panels in order of distance from the diagonal (the largest ranks first),
+  // taken from a device counter, so that workgroups with cheap panels take
+  // more; every workgroup leaves once the counter passes the panel count
+  for (;;) {
+    __syncthreads();  // the previous panel is done with the LDS and s_w
+    if (threadIdx.x == 0) s_w = (long)atomicAdd(queue, 1ull);
+    __syncthreads();
+    const long w = s_w;
+    if (w >= npan) break;
     long d = 1, rem = w;
     while (rem >= nt - d) {
       rem -= nt - d;
@@ -861,9 +1103,7 @@ __global__ __launch_bounds__(256, 1) void tlr_recompress_kernel(double* __restri
     const long k = rem, i = k + d;
     const long pid = tri_st(i, k);
     const int r = ranks[pid];
-    if (r < 2 || r > rs) continue;  // uniform
-    const bool big = ((r + 15) & ~15) > kRcLdsR;
-    const RcShared sh{big ? Sg : S, big ? rs + 1 : kRcLd, S, cs, sn, lam, du, dv, tail, sv, pa, pb, ord, &s_flag};
+    if (r < 2 || r > kRcMaxRank || r > rs) continue;  // uniform
     rc_panel(sh, tiles + tri_lo(i, k) * (long)m * m, tiles + tri_lo(k, k) * (long)m * m, U + pid * (long)m * rs,
              Vt + pid * (long)rs * m, ranks + pid, m, rs, r, eps, ws);
   }
@@ -872,8 +1112,10 @@ __global__ __launch_bounds__(256, 1) void tlr_recompress_kernel(double* __restri
 hipError_t launch_tlr_recompress(double* tiles, int m, int nt, int rs, double eps, double* U, double* Vt, int* ranks,
                                  double* scratch, int grid, const int* info, hipStream_t st) {
   if (nt < 2 || grid < 1) return hipSuccess;
+  unsigned long long* queue = (unsigned long long*)(scratch + (long)grid * tlr_rc_scratch_doubles(m, rs));
+  hipLaunchKernelGGL(tlr_rc_queue_init_kernel, dim3(1), dim3(64), 0, st, queue);
   hipLaunchKernelGGL(tlr_recompress_kernel, dim3(grid), dim3(256), 0, st, tiles, m, nt, rs, eps, U, Vt, ranks, scratch,
-                     info);
+                     queue, info);
   return hipGetLastError();
 }
 

@@ -265,11 +265,8 @@ constexpr int kTlrMaxRank = 256;    // largest rank cap (one lane per rank row i
 constexpr long kTlrPairBatch = 256; // tile pairs per update launch (sizes the WT / T workspace)
 constexpr int kTlrRcGrid = 256;     // most recompression workgroups (one per CU, each with its scratch)
 // Scratch doubles per recompression workgroup for tile edge m and rank
-// stride rs: three rs x m and one m x rs blocks, seven rs x rs ones and the
-// working matrix of ranks above 128.
-__host__ __device__ inline long tlr_rc_scratch_doubles(int m, int rs) {
-  return 4L * rs * m + 7L * rs * rs + (long)rs * (rs + 1);
-}
+// stride rs: three rs x m and one m x rs blocks and seven rs x rs ones.
+__host__ __device__ inline long tlr_rc_scratch_doubles(int m, int rs) { return 4L * rs * m + 7L * rs * rs; }
 
 // Lower tiles of Sigma (tile-major, m x m each, identity past n) from the
 // caller's Sigma or from locations with the Matern kernel; clears *info.
@@ -286,14 +283,15 @@ struct TlrCholArgs {
   int* local_info;   // per-tile info scratch (1 int)
   double* WT;        // kTlrPairBatch x rs x rs
   double* T;         // kTlrPairBatch x m x rs
-  double* rc_scratch;  // rc_grid x tlr_rc_scratch_doubles(m), or nullptr: no recompression
+  double* rc_scratch;  // rc_grid x tlr_rc_scratch_doubles(m, rs) + a 64-byte counter, or nullptr: no recompression
   int rc_grid;
   int m, nt, rs, rcap;
   double eps;
 };
 hipError_t launch_tlr_cholesky(const TlrCholArgs& a, hipStream_t st);
 // Recompression of every panel of a finished TLR factor to the smallest rank
-// within eps (kernels_tlr.hip); grid workgroups with their scratch slots.
+// within eps (kernels_tlr.hip); grid workgroups with their scratch slots, the
+// panel counter after them.
 hipError_t launch_tlr_recompress(double* tiles, int m, int nt, int rs, double eps, double* U, double* Vt, int* ranks,
                                  double* scratch, int grid, const int* info, hipStream_t st);
 // The TLR factor as a dense row-major lower factor D (ldd x ldd, ldd <= nt m):
