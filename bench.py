@@ -491,7 +491,7 @@ def variant_batch(dev) -> dict:
         res_c["P_fp64_quantiles_0_50_100"] = [float(q) for q in np.quantile(Ps[(conv, "fp64")], [0, 0.5, 1])]
         out[conv] = res_c
     out["config"] = (f"{len(sizes)} problems, n_p in [{int(sizes.min())}, {int(sizes.max())}], "
-                     f"sum n_p = {int(sizes.sum())}, N={bw.N} x S={bw.S}, 128-wide Cholesky steps with every "
+                     f"sum n_p = {int(sizes.sum())}, N={bw.N} x S={bw.S}, 256-wide Cholesky steps with every "
                      "trailing update in the stated type; sweep block rows chosen by the autotuner on b = u - mu")
     return out
 

@@ -1020,7 +1020,10 @@ hipError_t launch_batch_build(const BatchDesc* desc, int count, long total_tiles
   return hipGetLastError();
 }
 
-constexpr int kBatchTile = 128;
+// Columns per step of the batched factorisation: each step's trailing update
+// reads and rewrites the trailing matrix once, so 256-wide steps halve that
+// traffic against 128-wide ones (the sub-panels stay 32 wide).
+constexpr int kBatchTile = 256;
 
 __global__ __launch_bounds__(64) void batch_diag_kernel(const BatchDesc* __restrict__ desc,
                                                         const int* __restrict__ order, double* factor, int j0,
@@ -1063,7 +1066,7 @@ __global__ __launch_bounds__(256) void batch_trsm_kernel(const BatchDesc* __rest
   group_item(g, blockIdx.x, rank, item);
   const int p = order[rank];
   const BatchDesc d = desc[p];
-  chol_panel_body<true>(factor + d.factor_off, d.ld, k0, j0, kSub, k0 + kBatchTile, info + p, item);
+  chol_panel_body<true>(factor + d.factor_off, d.ld, k0, j0, kSub, min(k0 + kBatchTile, d.ld), info + p, item);
 }
 
 __global__ __launch_bounds__(256) void batch_syrk_kernel(const BatchDesc* __restrict__ desc,
