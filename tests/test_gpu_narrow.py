@@ -134,3 +134,40 @@ def test_narrow_rejections():
                           device=DEV)
     with pytest.raises(mvn.MvnError):
         mvn.mvn_prob(ft, a, b, mu, N=64, S=1, seed=1, opts=mvn.options(tile=128, sweep_rows=32))
+
+
+def test_narrow_graph_capture_replays_match_eager():
+    """The narrow sweep and its nested-set form enqueue no allocation, copy
+    of device data to the host or fill: captured in a graph, every replay (with
+    eager work in between) equals the eager result bit for bit."""
+    n, N, S = 300, 700, 3
+    w, locs, kern, a, b, mu = _sub(n)
+    f = mvn.mvn_cholesky(n, locs=locs, kern=kern, opts=mvn.options(tile=64), device=DEV)
+    opts = mvn.options(tile=64, sweep_rows=32)
+    ta, tb, tm = (torch.as_tensor(x, device=DEV) for x in (a, b, mu))
+    wsb = mvn.mvn_prob_workspace_bytes(n, N, S, opts)
+    ws = torch.empty(wsb, dtype=torch.uint8, device=DEV)
+    r = mvn.mvn_prob(f, ta, tb, tm, N=N, S=S, seed=5, opts=opts, workspace=ws)
+    p = mvn.mvn_prob_prefix(f, ta, tb, tm, N=N, S=S, seed=5, opts=opts)
+    torch.cuda.synchronize()
+    eager, eager_p = r["out"].clone(), p["out"].clone()
+    assert torch.isfinite(eager[0])
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            rg = mvn.mvn_prob(f, ta, tb, tm, N=N, S=S, seed=5, opts=opts, workspace=ws)
+            pg = mvn.mvn_prob_prefix(f, ta, tb, tm, N=N, S=S, seed=5, opts=opts)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        rg["out"].fill_(0.0)
+        pg["out"].fill_(0.0)
+        junk = torch.randn(1 << 20, device=DEV).sum()  # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(rg["out"], eager), rep
+        assert torch.equal(pg["out"], eager_p), rep
+        del junk
