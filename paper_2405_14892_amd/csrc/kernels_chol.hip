@@ -1101,6 +1101,140 @@ __global__ __launch_bounds__(256) void batch_syrk_lp_kernel(const BatchDesc* __r
                        r0 + (long)bx * kCols, d.ld, PrecMap{});
 }
 
+// The BF16 trailing updates of the batch read their operands from a BF16
+// copy of the step's panel instead of converting FP64 rows per tile: rows
+// [k0 + 256, ld) x columns [k0, k0 + 256) of every problem are rounded once
+// per step into the low-precision factor planes (the layout of the FP64
+// factor, `plane` elements apart; the final conversion after the last step
+// rewrites them with the same rounding), as hi and, for SPLIT 2, lo =
+// bf16(x - hi).  Item i of a problem covers its 128-row block i.
+template <int SPLIT>
+__global__ __launch_bounds__(256) void batch_panel_bf16_kernel(const BatchDesc* __restrict__ desc,
+                                                               const int* __restrict__ order,
+                                                               const double* __restrict__ factor,
+                                                               __bf16* __restrict__ low, long plane, int k0,
+                                                               const int* __restrict__ info, BatchGroups g) {
+  int rank, item;
+  group_item(g, blockIdx.x, rank, item);
+  const int p = order[rank];
+  if (info[p] != 0) return;
+  const BatchDesc d = desc[p];
+  const long row0 = (long)k0 + kBatchTile + (long)item * kTile;
+  const double* src = factor + d.factor_off + row0 * d.ld + k0;
+  __bf16* dst = low + d.factor_off + row0 * d.ld + k0;
+  // 128 rows x 256 columns in runs of 8: 16 runs per thread
+#pragma unroll 4
+  for (int e = threadIdx.x; e < kTile * (kBatchTile / 8); e += 256) {
+    const long off = (long)(e / (kBatchTile / 8)) * d.ld + (e % (kBatchTile / 8)) * 8;
+    const double2* s = reinterpret_cast<const double2*>(src + off);
+    bf16x8 hi, lo;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const double2 v = s[q];
+      hi[2 * q] = to_bf16(v.x);
+      hi[2 * q + 1] = to_bf16(v.y);
+      if (SPLIT == 2) {
+        lo[2 * q] = to_bf16(v.x - (double)(float)hi[2 * q]);
+        lo[2 * q + 1] = to_bf16(v.y - (double)(float)hi[2 * q + 1]);
+      }
+    }
+    *reinterpret_cast<bf16x8*>(dst + off) = hi;
+    if (SPLIT == 2) *reinterpret_cast<bf16x8*>(dst + plane + off) = lo;
+  }
+}
+
+// One lower 128 x 64 tile of a problem's trailing update in BF16 (three
+// products of hi and lo planes for SPLIT 2) with FP32 accumulation, the
+// operands loaded from the BF16 panel straight into the MFMA registers: no
+// LDS and no barrier, so occupancy is set by registers alone.  Wave w owns
+// rows 32 w .. 32 w + 31 of the tile; lane (r = lane & 15, q = lane >> 4)
+// holds k = 8 q .. 8 q + 7 of each 32-deep block of its A rows and B columns,
+// the operand layout of the LDS-staged policy, and the K blocks run in the
+// same order, so the tile equals that policy's bit for bit.
+template <int SPLIT>
+struct BatchBf16Frag {
+  bf16x8 a[SPLIT][2];
+  bf16x8 b[SPLIT][4];
+};
+
+template <int SPLIT>
+__device__ __forceinline__ void batch_bf16_load(const __bf16* __restrict__ pa, const __bf16* __restrict__ pb,
+                                                long ld, long plane, int k, BatchBf16Frag<SPLIT>& f) {
+#pragma unroll
+  for (int sp = 0; sp < SPLIT; ++sp) {
+#pragma unroll
+    for (int ib = 0; ib < 2; ++ib)
+      f.a[sp][ib] = *reinterpret_cast<const bf16x8*>(pa + sp * plane + (long)ib * 16 * ld + k);
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb)
+      f.b[sp][jb] = *reinterpret_cast<const bf16x8*>(pb + sp * plane + (long)jb * 16 * ld + k);
+  }
+}
+
+template <int SPLIT>
+__device__ __forceinline__ void batch_bf16_mma(const BatchBf16Frag<SPLIT>& f, f32x4 (&acc)[2][4]) {
+#pragma unroll
+  for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb) {
+      acc[ib][jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.a[0][ib], f.b[0][jb], acc[ib][jb], 0, 0, 0);
+      if (SPLIT == 2) {
+        acc[ib][jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.a[0][ib], f.b[SPLIT - 1][jb], acc[ib][jb], 0, 0, 0);
+        acc[ib][jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.a[SPLIT - 1][ib], f.b[0][jb], acc[ib][jb], 0, 0, 0);
+      }
+    }
+}
+
+template <int SPLIT>
+__global__ __launch_bounds__(256) void batch_syrk_bf16_kernel(const BatchDesc* __restrict__ desc,
+                                                              const int* __restrict__ order, double* factor,
+                                                              const __bf16* __restrict__ low, long plane, int k0,
+                                                              const int* __restrict__ info, BatchGroups g) {
+  int rank, item;
+  group_item(g, blockIdx.x, rank, item);
+  const int p = order[rank];
+  if (info[p] != 0) return;
+  const BatchDesc d = desc[p];
+  int by = (int)((sqrt(4.0 * item + 1.0) - 1.0) * 0.5);
+  while ((by + 1) * (by + 2) <= item) ++by;
+  while (by * (by + 1) > item) --by;
+  const int bx = item - by * (by + 1);
+  const long ld = d.ld;
+  const long r0 = (long)k0 + kBatchTile;
+  // ld is a multiple of 128 and r0 of 128, so the tile's rows and columns
+  // (colB + 63 <= rowA + 127 < ld) and K = [k0, k0 + 256) all exist
+  const long rowA = r0 + (long)by * kTile, colB = r0 + (long)bx * kCols;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r = lane & 15, q = lane >> 4;
+  const __bf16* Lp = low + d.factor_off;
+  const __bf16* pa = Lp + (rowA + 32 * w + r) * ld + k0 + 8 * q;
+  const __bf16* pb = Lp + (colB + r) * ld + k0 + 8 * q;
+  f32x4 acc[2][4];
+#pragma unroll
+  for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb) acc[ib][jb] = f32x4{0.f, 0.f, 0.f, 0.f};
+  constexpr int kSteps = kBatchTile / 32;
+  BatchBf16Frag<SPLIT> f[2];
+  batch_bf16_load<SPLIT>(pa, pb, ld, plane, 0, f[0]);
+  batch_bf16_load<SPLIT>(pa, pb, ld, plane, 32, f[1]);
+#pragma unroll
+  for (int s = 0; s < kSteps; ++s) {
+    batch_bf16_mma<SPLIT>(f[s & 1], acc);
+    if (s + 2 < kSteps) batch_bf16_load<SPLIT>(pa, pb, ld, plane, 32 * (s + 2), f[s & 1]);
+  }
+  double* A = factor + d.factor_off;
+#pragma unroll
+  for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const long gi = rowA + 32 * w + 16 * ib + 4 * q + v, gj = colB + 16 * jb + r;
+        if (gj <= gi) A[gi * ld + gj] -= (double)acc[ib][jb][v];
+      }
+}
+
 // Launches `launch(groups, total)` for the groups of ranks [0, cnt) with
 // items(ld) > 0 work items each, at most kMaxGroups groups per launch.
 template <class Items, class Launch>
@@ -1162,7 +1296,7 @@ hipError_t launch_batch_cholesky(int prec, const BatchDesc* desc, const int* ord
               hipLaunchKernelGGL(batch_syrk_kernel, dim3(total), dim3(256), 0, st, desc, order, factor, k0,
                                  (const int*)info, g);
             });
-      } else {
+      } else if (prec == 1) {
         e = for_groups(
             ld_rank, cnt2,
             [&](int ld) {
@@ -1170,13 +1304,37 @@ hipError_t launch_batch_cholesky(int prec, const BatchDesc* desc, const int* ord
               return nt * (nt + 1);
             },
             [&](const BatchGroups& g, int total) {
-              const dim3 grid(total);
-              switch (prec) {
-                case 1: hipLaunchKernelGGL(batch_syrk_lp_kernel<GemmF32>, grid, dim3(256), 0, st, desc, order, factor, k0, (const int*)info, g); break;
-                case 2: hipLaunchKernelGGL(batch_syrk_lp_kernel<GemmBF16>, grid, dim3(256), 0, st, desc, order, factor, k0, (const int*)info, g); break;
-                case 3: hipLaunchKernelGGL(batch_syrk_lp_kernel<GemmBF16x3>, grid, dim3(256), 0, st, desc, order, factor, k0, (const int*)info, g); break;
-              }
+              hipLaunchKernelGGL(batch_syrk_lp_kernel<GemmF32>, dim3(total), dim3(256), 0, st, desc, order, factor,
+                                 k0, (const int*)info, g);
             });
+      } else {
+        // BF16 / split BF16: the step's panel rounded once, then the tiles
+        __bf16* lb = (__bf16*)low;
+        e = for_groups(
+            ld_rank, cnt2, [&](int ld) { return (ld - (k0 + kBatchTile)) / kTile; },
+            [&](const BatchGroups& g, int total) {
+              if (prec == 2)
+                hipLaunchKernelGGL(batch_panel_bf16_kernel<1>, dim3(total), dim3(256), 0, st, desc, order,
+                                   (const double*)factor, lb, factor_elems, k0, (const int*)info, g);
+              else
+                hipLaunchKernelGGL(batch_panel_bf16_kernel<2>, dim3(total), dim3(256), 0, st, desc, order,
+                                   (const double*)factor, lb, factor_elems, k0, (const int*)info, g);
+            });
+        if (e == hipSuccess)
+          e = for_groups(
+              ld_rank, cnt2,
+              [&](int ld) {
+                const int nt = (ld - (k0 + kBatchTile)) / kTile;
+                return nt * (nt + 1);
+              },
+              [&](const BatchGroups& g, int total) {
+                if (prec == 2)
+                  hipLaunchKernelGGL(batch_syrk_bf16_kernel<1>, dim3(total), dim3(256), 0, st, desc, order, factor,
+                                     (const __bf16*)lb, factor_elems, k0, (const int*)info, g);
+                else
+                  hipLaunchKernelGGL(batch_syrk_bf16_kernel<2>, dim3(total), dim3(256), 0, st, desc, order, factor,
+                                     (const __bf16*)lb, factor_elems, k0, (const int*)info, g);
+              });
       }
       if (e != hipSuccess) return e;
     }
