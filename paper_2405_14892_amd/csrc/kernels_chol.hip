@@ -183,15 +183,19 @@ __global__ __launch_bounds__(64) void chol_diag_kernel(double* __restrict__ A, i
 // FULL: jw == 32 (every sub-panel except the last of a tile whose width is
 // not a multiple of 32, which has no later diagonal block); the constant
 // bound keeps the substitution in registers.
-constexpr int kPanelK = 32;  // k per LDS stage of the panel update
+// PK: k per LDS stage of the panel update: 32 for the single factor (91 KB of
+// LDS), 16 for the batch (50 KB: three workgroups per CU, where thousands of
+// row blocks of small problems wait for residency).  The k order of the
+// products is the same either way.
+constexpr int kPanelK = 32;
 
-template <bool FULL>
+template <bool FULL, int PK = kPanelK>
 __device__ __forceinline__ void chol_panel_body(double* __restrict__ A, int ld, int k0, int j0, int jw_arg,
                                                 int kend, int* __restrict__ info, int rblock) {
   if (*info != 0) return;
   const int jw = FULL ? kSub : jw_arg;
   constexpr int kALd = kTile + 1, kBLd = kSub + 1;
-  constexpr int kAS = kPanelK * kALd, kBS = kPanelK * kBLd;
+  constexpr int kAS = PK * kALd, kBS = PK * kBLd;
   static_assert(kTile * (kSub + 1) <= 2 * (kAS + kBS), "X must fit in the stage buffers");
   __shared__ double stage[2 * (kAS + kBS)];
   __shared__ double D[kSub][kSub + 1];
@@ -205,40 +209,41 @@ __device__ __forceinline__ void chol_panel_body(double* __restrict__ A, int ld, 
 #pragma unroll
     for (int jb = 0; jb < 2; ++jb) acc[ib][jb] = f64x4{0.0, 0.0, 0.0, 0.0};
   if (K > 0) {
-    // lane t: A row r0 + t/2, 16 consecutive k (rows at or past ld read as
-    // zero); B row t/8 of the diagonal block, 4 consecutive k (masked at jw)
-    double ra[16], rb[4];
+    // lane t: A row r0 + t/2, PK/2 consecutive k (rows at or past ld read as
+    // zero); B row t/8 of the diagonal block, PK/8 consecutive k (masked at jw)
+    constexpr int kQA = PK / 2, kQB = PK / 8;
+    double ra[kQA], rb[kQB];
     const long arow = r0 + (t >> 1);
     const int brow = t >> 3;
     auto load = [&](int kk) {
-      const long kb = (long)k0 + kk + (t & 1) * 16;
+      const long kb = (long)k0 + kk + (t & 1) * kQA;
 #pragma unroll
-      for (int q = 0; q < 16; ++q) ra[q] = arow < ld ? A[arow * ld + kb + q] : 0.0;
-      const long kc = (long)k0 + kk + (t & 7) * 4;
+      for (int q = 0; q < kQA; ++q) ra[q] = arow < ld ? A[arow * ld + kb + q] : 0.0;
+      const long kc = (long)k0 + kk + (t & 7) * kQB;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) rb[q] = brow < jw ? A[(long)(j0 + brow) * ld + kc + q] : 0.0;
+      for (int q = 0; q < kQB; ++q) rb[q] = brow < jw ? A[(long)(j0 + brow) * ld + kc + q] : 0.0;
     };
     auto store = [&](double* s) {
-      const int row = t >> 1, kb = (t & 1) * 16;
+      const int row = t >> 1, kb = (t & 1) * kQA;
 #pragma unroll
-      for (int q = 0; q < 16; ++q) s[(kb + q) * kALd + row] = ra[q];
+      for (int q = 0; q < kQA; ++q) s[(kb + q) * kALd + row] = ra[q];
       double* sb = s + kAS;
-      const int kc = (t & 7) * 4;
+      const int kc = (t & 7) * kQB;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) sb[(kc + q) * kBLd + brow] = rb[q];
+      for (int q = 0; q < kQB; ++q) sb[(kc + q) * kBLd + brow] = rb[q];
     };
-    const int nst = K / kPanelK;
+    const int nst = K / PK;
     load(0);
     store(stage);
     __syncthreads();
     for (int s = 0; s < nst; ++s) {
       double* cur = stage + (s & 1) * (kAS + kBS);
       double* nxt = stage + ((s + 1) & 1) * (kAS + kBS);
-      if (s + 1 < nst) load((s + 1) * kPanelK);
+      if (s + 1 < nst) load((s + 1) * PK);
       const double* As = cur;
       const double* Bs = cur + kAS;
 #pragma unroll
-      for (int kk = 0; kk < kPanelK / 4; ++kk) {
+      for (int kk = 0; kk < PK / 4; ++kk) {
         const int k = kk * 4 + (lane >> 4);
         double a[2], b[2];
 #pragma unroll
@@ -1066,7 +1071,7 @@ __global__ __launch_bounds__(256) void batch_trsm_kernel(const BatchDesc* __rest
   group_item(g, blockIdx.x, rank, item);
   const int p = order[rank];
   const BatchDesc d = desc[p];
-  chol_panel_body<true>(factor + d.factor_off, d.ld, k0, j0, kSub, min(k0 + kBatchTile, d.ld), info + p, item);
+  chol_panel_body<true, 16>(factor + d.factor_off, d.ld, k0, j0, kSub, min(k0 + kBatchTile, d.ld), info + p, item);
 }
 
 __global__ __launch_bounds__(256) void batch_syrk_kernel(const BatchDesc* __restrict__ desc,
