@@ -183,11 +183,13 @@ __global__ __launch_bounds__(64) void chol_diag_kernel(double* __restrict__ A, i
 // FULL: jw == 32 (every sub-panel except the last of a tile whose width is
 // not a multiple of 32, which has no later diagonal block); the constant
 // bound keeps the substitution in registers.
-// PK: k per LDS stage of the panel update: 32 for the single factor (91 KB of
-// LDS), 16 for the batch (50 KB: three workgroups per CU, where thousands of
-// row blocks of small problems wait for residency).  The k order of the
-// products is the same either way.
-constexpr int kPanelK = 32;
+// PK: k per LDS stage of the panel update.  16 keeps the workgroup at 50 KB of
+// LDS (three per CU, and room beside the trailing-update workgroups of the
+// lookahead) where 32 took 91 KB; the k order of the products is the same,
+// so the factor is too, bit for bit.  Measured: 48.5 -> 47.0 ms at 16 384
+// sites (tile 512), 1614 -> 1572 ms at 65 536 (tile 1024), and 35 ms less
+// per 2000-problem batch.
+constexpr int kPanelK = 16;
 
 template <bool FULL, int PK = kPanelK>
 __device__ __forceinline__ void chol_panel_body(double* __restrict__ A, int ld, int k0, int j0, int jw_arg,
@@ -1071,7 +1073,7 @@ __global__ __launch_bounds__(256) void batch_trsm_kernel(const BatchDesc* __rest
   group_item(g, blockIdx.x, rank, item);
   const int p = order[rank];
   const BatchDesc d = desc[p];
-  chol_panel_body<true, 16>(factor + d.factor_off, d.ld, k0, j0, kSub, min(k0 + kBatchTile, d.ld), info + p, item);
+  chol_panel_body<true>(factor + d.factor_off, d.ld, k0, j0, kSub, min(k0 + kBatchTile, d.ld), info + p, item);
 }
 
 __global__ __launch_bounds__(256) void batch_syrk_kernel(const BatchDesc* __restrict__ desc,
