@@ -1091,21 +1091,11 @@ __global__ __launch_bounds__(256) void batch_syrk_kernel(const BatchDesc* __rest
 
 // Lower 128 x 64 tiles of the trailing matrix: row tile by holds 2 by + 2
 // of them, so item t has by = floor((sqrt(4 t + 1) - 1) / 2).
-template <class G>
-__global__ __launch_bounds__(256) void batch_syrk_lp_kernel(const BatchDesc* __restrict__ desc,
-                                                            const int* __restrict__ order, double* factor,
-                                                            int k0, const int* info, BatchGroups g) {
-  int rank, item;
-  group_item(g, blockIdx.x, rank, item);
-  const int p = order[rank];
-  const BatchDesc d = desc[p];
-  int by = (int)((sqrt(4.0 * item + 1.0) - 1.0) * 0.5);
+__device__ __forceinline__ void batch_lp_tile(int item, int& by, int& bx) {
+  by = (int)((sqrt(4.0 * item + 1.0) - 1.0) * 0.5);
   while ((by + 1) * (by + 2) <= item) ++by;
   while (by * (by + 1) > item) --by;
-  const int bx = item - by * (by + 1);
-  const long r0 = (long)k0 + kBatchTile;
-  chol_syrk_lp_body<G>(factor + d.factor_off, d.ld, k0, kBatchTile, info + p, r0 + (long)by * kTile,
-                       r0 + (long)bx * kCols, d.ld, PrecMap{});
+  bx = item - by * (by + 1);
 }
 
 // The BF16 trailing updates of the batch read their operands from a BF16
@@ -1202,10 +1192,8 @@ __global__ __launch_bounds__(256) void batch_syrk_bf16_kernel(const BatchDesc* _
   const int p = order[rank];
   if (info[p] != 0) return;
   const BatchDesc d = desc[p];
-  int by = (int)((sqrt(4.0 * item + 1.0) - 1.0) * 0.5);
-  while ((by + 1) * (by + 2) <= item) ++by;
-  while (by * (by + 1) > item) --by;
-  const int bx = item - by * (by + 1);
+  int by, bx;
+  batch_lp_tile(item, by, bx);
   const long ld = d.ld;
   const long r0 = (long)k0 + kBatchTile;
   // ld is a multiple of 128 and r0 of 128, so the tile's rows and columns
@@ -1229,6 +1217,114 @@ __global__ __launch_bounds__(256) void batch_syrk_bf16_kernel(const BatchDesc* _
   for (int s = 0; s < kSteps; ++s) {
     batch_bf16_mma<SPLIT>(f[s & 1], acc);
     if (s + 2 < kSteps) batch_bf16_load<SPLIT>(pa, pb, ld, plane, 32 * (s + 2), f[s & 1]);
+  }
+  double* A = factor + d.factor_off;
+#pragma unroll
+  for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const long gi = rowA + 32 * w + 16 * ib + 4 * q + v, gj = colB + 16 * jb + r;
+        if (gj <= gi) A[gi * ld + gj] -= (double)acc[ib][jb][v];
+      }
+}
+
+// The FP32 form: the panel rounded to FP32 with each 32-column block stored
+// permuted, k = 4 j + q at 8 q + j, so that lane q of a 16 x 16 x 4 MFMA
+// finds its eight k of the block (j = 0..7) in 32 contiguous bytes.
+__global__ __launch_bounds__(256) void batch_panel_f32_kernel(const BatchDesc* __restrict__ desc,
+                                                              const int* __restrict__ order,
+                                                              const double* __restrict__ factor,
+                                                              float* __restrict__ low, int k0,
+                                                              const int* __restrict__ info, BatchGroups g) {
+  int rank, item;
+  group_item(g, blockIdx.x, rank, item);
+  const int p = order[rank];
+  if (info[p] != 0) return;
+  const BatchDesc d = desc[p];
+  const long row0 = (long)k0 + kBatchTile + (long)item * kTile;
+  const double* src = factor + d.factor_off + row0 * d.ld + k0;
+  float* dst = low + d.factor_off + row0 * d.ld + k0;
+  // (row, 32-column block b, q), q fastest: the four lanes of a (row, b)
+  // read its 32 contiguous doubles between them
+  for (int e = threadIdx.x; e < kTile * (kBatchTile / 32) * 4; e += 256) {
+    const int q = e & 3, b = (e >> 2) & (kBatchTile / 32 - 1), row = e >> 5;
+    const double* sp = src + (long)row * d.ld + 32 * b + q;
+    const float4 v0{(float)sp[0], (float)sp[4], (float)sp[8], (float)sp[12]};
+    const float4 v1{(float)sp[16], (float)sp[20], (float)sp[24], (float)sp[28]};
+    float4* o = reinterpret_cast<float4*>(dst + (long)row * d.ld + 32 * b + 8 * q);
+    o[0] = v0;
+    o[1] = v1;
+  }
+}
+
+// One lower 128 x 64 tile in FP32 from the permuted FP32 panel, operands
+// straight into registers as in the BF16 form; the k order of the products
+// is that of the LDS-staged FP32 policy (k = 4 j + q in MFMA j), so the tile
+// equals its result bit for bit.
+struct BatchF32Frag {
+  float4 a[2][2];
+  float4 b[4][2];
+};
+
+__device__ __forceinline__ void batch_f32_load(const float* __restrict__ pa, const float* __restrict__ pb, long ld,
+                                               int k, BatchF32Frag& f) {
+#pragma unroll
+  for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) f.a[ib][h] = *reinterpret_cast<const float4*>(pa + (long)ib * 16 * ld + k + 4 * h);
+#pragma unroll
+  for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) f.b[jb][h] = *reinterpret_cast<const float4*>(pb + (long)jb * 16 * ld + k + 4 * h);
+}
+
+__device__ __forceinline__ float f4_at(const float4& v, int i) { return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w; }
+
+__device__ __forceinline__ void batch_f32_mma(const BatchF32Frag& f, f32x4 (&acc)[2][4]) {
+#pragma unroll
+  for (int j = 0; j < 8; ++j)
+#pragma unroll
+    for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+      for (int jb = 0; jb < 4; ++jb)
+        acc[ib][jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(f4_at(f.a[ib][j >> 2], j & 3), f4_at(f.b[jb][j >> 2], j & 3),
+                                                           acc[ib][jb], 0, 0, 0);
+}
+
+__global__ __launch_bounds__(256) void batch_syrk_f32_kernel(const BatchDesc* __restrict__ desc,
+                                                             const int* __restrict__ order, double* factor,
+                                                             const float* __restrict__ low, int k0,
+                                                             const int* __restrict__ info, BatchGroups g) {
+  int rank, item;
+  group_item(g, blockIdx.x, rank, item);
+  const int p = order[rank];
+  if (info[p] != 0) return;
+  const BatchDesc d = desc[p];
+  int by, bx;
+  batch_lp_tile(item, by, bx);
+  const long ld = d.ld;
+  const long r0 = (long)k0 + kBatchTile;
+  const long rowA = r0 + (long)by * kTile, colB = r0 + (long)bx * kCols;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r = lane & 15, q = lane >> 4;
+  const float* Lp = low + d.factor_off;
+  const float* pa = Lp + (rowA + 32 * w + r) * ld + k0 + 8 * q;
+  const float* pb = Lp + (colB + r) * ld + k0 + 8 * q;
+  f32x4 acc[2][4];
+#pragma unroll
+  for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb) acc[ib][jb] = f32x4{0.f, 0.f, 0.f, 0.f};
+  constexpr int kSteps = kBatchTile / 32;
+  BatchF32Frag f[2];
+  batch_f32_load(pa, pb, ld, 0, f[0]);
+  batch_f32_load(pa, pb, ld, 32, f[1]);
+#pragma unroll
+  for (int s = 0; s < kSteps; ++s) {
+    batch_f32_mma(f[s & 1], acc);
+    if (s + 2 < kSteps) batch_f32_load(pa, pb, ld, 32 * (s + 2), f[s & 1]);
   }
   double* A = factor + d.factor_off;
 #pragma unroll
@@ -1304,16 +1400,25 @@ hipError_t launch_batch_cholesky(int prec, const BatchDesc* desc, const int* ord
                                  (const int*)info, g);
             });
       } else if (prec == 1) {
+        // FP32: the step's panel rounded once (permuted), then the tiles
+        float* lf = (float*)low;
         e = for_groups(
-            ld_rank, cnt2,
-            [&](int ld) {
-              const int nt = (ld - (k0 + kBatchTile)) / kTile;
-              return nt * (nt + 1);
-            },
+            ld_rank, cnt2, [&](int ld) { return (ld - (k0 + kBatchTile)) / kTile; },
             [&](const BatchGroups& g, int total) {
-              hipLaunchKernelGGL(batch_syrk_lp_kernel<GemmF32>, dim3(total), dim3(256), 0, st, desc, order, factor,
-                                 k0, (const int*)info, g);
+              hipLaunchKernelGGL(batch_panel_f32_kernel, dim3(total), dim3(256), 0, st, desc, order,
+                                 (const double*)factor, lf, k0, (const int*)info, g);
             });
+        if (e == hipSuccess)
+          e = for_groups(
+              ld_rank, cnt2,
+              [&](int ld) {
+                const int nt = (ld - (k0 + kBatchTile)) / kTile;
+                return nt * (nt + 1);
+              },
+              [&](const BatchGroups& g, int total) {
+                hipLaunchKernelGGL(batch_syrk_f32_kernel, dim3(total), dim3(256), 0, st, desc, order, factor,
+                                   (const float*)lf, k0, (const int*)info, g);
+              });
       } else {
         // BF16 / split BF16: the step's panel rounded once, then the tiles
         __bf16* lb = (__bf16*)low;
