@@ -1249,7 +1249,7 @@ __global__ __launch_bounds__(256) void batch_panel_f32_kernel(const BatchDesc* _
   // (row, 32-column block b, q), q fastest: the four lanes of a (row, b)
   // read its 32 contiguous doubles between them
   for (int e = threadIdx.x; e < kTile * (kBatchTile / 32) * 4; e += 256) {
-    const int q = e & 3, b = (e >> 2) & (kBatchTile / 32 - 1), row = e >> 5;
+    const int q = e & 3, b = (e >> 2) & (kBatchTile / 32 - 1), row = e / (kBatchTile / 8);
     const double* sp = src + (long)row * d.ld + 32 * b + q;
     const float4 v0{(float)sp[0], (float)sp[4], (float)sp[8], (float)sp[12]};
     const float4 v1{(float)sp[16], (float)sp[20], (float)sp[24], (float)sp[28]};
