@@ -54,7 +54,17 @@ int rows_opt(const mvn_options* o) { return o ? o->sweep_rows : 0; }
 // The TLR sweep's blocks: its GEMMs are short (packed ranks plus the dense
 // part of one tile), so conditioning dominates and 64-row blocks (four
 // workgroups per CU) are the default.
-int tlr_sweep_rows(const mvn_options* o) { return (!o || o->sweep_rows == 0) ? 64 : o->sweep_rows; }
+// TLR sweeps: 64- or 128-row blocks of 64 columns per workgroup, or 256 (the
+// four-wave sweep: 256 columns per workgroup, 64-row blocks), the automatic
+// choice once the 256-column chunks fill every CU.
+constexpr long kTlrQuadMinNS = 256L * 256;
+int tlr_sweep_rows(const mvn_options* o, long NS) {
+  if (!o || o->sweep_rows == 0) return NS >= kTlrQuadMinNS ? 256 : 64;
+  return o->sweep_rows;
+}
+bool tlr_rows_ok(const mvn_options* o) {
+  return !o || o->sweep_rows == 0 || o->sweep_rows == 64 || o->sweep_rows == 128 || o->sweep_rows == 256;
+}
 bool sweep_rows_ok(const mvn_options* o) { return !o || o->sweep_rows == 0 || o->sweep_rows == 64 || o->sweep_rows == 128; }
 // Dense probability and nested-set sweeps also take 32 (FP64 only).
 bool dense_rows_ok(const mvn_options* o) {
@@ -352,12 +362,13 @@ struct TlrProbLayout {
   ProbLayout base;
   size_t kk, zcol, kpad0, kval, vrow0, ucol0, zdst, hdr, fixed;
   long yslice;
+  int cols;       // sample columns per workgroup: 64, or 256 (four-wave sweep)
   int grid;       // launch grid (the device runs as many as the region holds)
   bool ext_pack;  // compact factor: the packed operands are the factor's, not in the region
   size_t dyn_bytes(long ksum, long kpad, long g, int m) const {
     const size_t kp = kpad > 0 ? (size_t)kpad : 1;
     const size_t ysc = ext_pack ? 0 : align_up(8 * (size_t)(ksum + 128) * m) + align_up(8 * (size_t)m * kp);
-    return ysc + (size_t)g * (align_up(8 * (size_t)yslice) + align_up(8 * kp * mvn::sweep_tile_cols()));
+    return ysc + (size_t)g * (align_up(8 * (size_t)yslice) + align_up(8 * kp * (size_t)cols));
   }
 };
 
@@ -366,7 +377,8 @@ bool is_compact(const mvn_factor* f) { return (f->flags & MVN_FACTOR_TLR_COMPACT
 TlrProbLayout tlr_prob_layout(int ld, int nt, int rs, int N, int S, int rows, bool ext_pack = false) {
   TlrProbLayout L{};
   L.ext_pack = ext_pack;
-  L.base = prob_layout_ld(ld, N, S, MVN_FP64, 0, rows);
+  const bool quad = rows == 256;
+  L.base = quad ? prob_layout_ld(ld, N, S, MVN_FP64, 0, 64, kSweepQuad) : prob_layout_ld(ld, N, S, MVN_FP64, 0, rows);
   const size_t np = (size_t)nt * (nt - 1) / 2;
   const size_t np1 = np > 0 ? np : 1;
   size_t off = L.base.yscr;
@@ -379,7 +391,8 @@ TlrProbLayout tlr_prob_layout(int ld, int nt, int rs, int N, int S, int rows, bo
   L.zdst = off; off = align_up(off + sizeof(long) * np1 * rs);
   L.hdr = off; off = align_up(off + sizeof(mvn::TlrSweepHdr));
   L.fixed = off;
-  L.yslice = (long)ld * mvn::sweep_tile_cols();
+  L.cols = quad ? mvn::quad_sweep_cols() : mvn::sweep_tile_cols();
+  L.yslice = (long)ld * L.cols;
   L.grid = L.base.grid;
   return L;
 }
@@ -577,7 +590,7 @@ int dense_sweep(const mvn_factor* f, const double* d_a, const double* d_b, const
 int tlr_sweep_call(const mvn_factor* f, const double* d_a, const double* d_b, const double* d_mu, int N, int S,
                    uint64_t seed, const mvn_options* opts, void* ws, size_t ws_bytes, double* d_ell,
                    double* prefix, double* d_out, hipStream_t stream, const int** bad_out) {
-  const int rows = tlr_sweep_rows(opts);
+  const int rows = tlr_sweep_rows(opts, (long)N * S);
   const int n = f->n, m = f->tile, nt = f->ld / f->tile, rs = f->rank_stride;
   const int np = nt * (nt - 1) / 2;
   const bool compact = is_compact(f);
@@ -607,6 +620,7 @@ int tlr_sweep_call(const mvn_factor* f, const double* d_a, const double* d_b, co
   tb.m = m;
   tb.ext_pack = compact ? 1 : 0;
   tb.yslice = Lay.yslice;
+  tb.cols = Lay.cols;
   tb.grid_max = Lay.grid;
   tb.dyn_bytes = ws_bytes - Lay.fixed;
   tb.kk = (int*)(w + Lay.kk);
@@ -721,10 +735,10 @@ int mvn_prob_workspace_bytes(int n, int N, int S, const mvn_options* opts, size_
   if (is_tlr(opts)) {
     // every tile at the rank stride: enough for any factor with these options
     if (tlr_opts_check(opts)) return -4;
-    if (!sweep_rows_ok(opts)) return fail(-4, "sweep_rows must be 0, 64 or 128 (got %d)", opts->sweep_rows);
+    if (!tlr_rows_ok(opts)) return fail(-4, "sweep_rows must be 0, 64, 128 or 256 (got %d)", opts->sweep_rows);
     const TlrGeom G = tlr_geom(n, opts->tile, opts->max_rank);
     const long kmax = G.npanels * G.rs;
-    const TlrProbLayout L = tlr_prob_layout(G.ld, G.nt, G.rs, N, S, tlr_sweep_rows(opts));
+    const TlrProbLayout L = tlr_prob_layout(G.ld, G.nt, G.rs, N, S, tlr_sweep_rows(opts, (long)N * S));
     *bytes = L.fixed + L.dyn_bytes(kmax, kmax, L.grid, G.m);
     return 0;
   }
@@ -742,13 +756,14 @@ int mvn_prob_workspace_bytes_factor(const mvn_factor* f, int N, int S, const mvn
   if (S < 1) return fail(-3, "S must be >= 1 (got %d)", S);
   if (!bytes) return fail(-5, "bytes is NULL");
   if (!f->ranks || f->tile < 128 || f->ld % f->tile != 0) return fail(-1, "invalid factor handle");
-  if (!sweep_rows_ok(opts)) return fail(-4, "sweep_rows must be 0, 64 or 128 (got %d)", opts->sweep_rows);
+  if (!tlr_rows_ok(opts)) return fail(-4, "sweep_rows must be 0, 64, 128 or 256 (got %d)", opts->sweep_rows);
   std::vector<int> ranks;
   const hipError_t e = tlr_read_ranks(f, ranks, stream);
   if (e != hipSuccess) return hip_fail(e, "rank read-back");
   const int nt = f->ld / f->tile;
   const mvn::TlrTables T = mvn::build_tlr_tables(nt, f->rank_stride, ranks.data());
-  const TlrProbLayout L = tlr_prob_layout(f->ld, nt, f->rank_stride, N, S, tlr_sweep_rows(opts), is_compact(f));
+  const TlrProbLayout L =
+      tlr_prob_layout(f->ld, nt, f->rank_stride, N, S, tlr_sweep_rows(opts, (long)N * S), is_compact(f));
   *bytes = L.fixed + L.dyn_bytes(T.ksum, T.kpad0[nt], L.grid, f->tile);
   return 0;
 }
@@ -789,8 +804,8 @@ int mvn_prob_prefix(const mvn_factor* f, const double* d_a, const double* d_b, c
   if (tlr && prec != MVN_FP64) return fail(-8, "the TLR sweep is FP64");
   if (!tlr && prec != MVN_FP64 && (prec != f->precision || !f->L_low))
     return fail(-8, "the factor holds no operand copy for precision %d (built with %d)", prec, f->precision);
-  if (tlr ? !sweep_rows_ok(opts) : !dense_rows_ok(opts))
-    return fail(-8, "sweep_rows must be 0, 64, 128 or 32 (FP64, dense) (got %d)", opts->sweep_rows);
+  if (tlr ? !tlr_rows_ok(opts) : !dense_rows_ok(opts))
+    return fail(-8, "sweep_rows must be 0, 64, 128, 32 (FP64, dense) or 256 (TLR) (got %d)", opts->sweep_rows);
   const PrefixRegion R =
       prefix_region(f->n, N, S, tlr ? mvn::sweep_tile_cols() : prefix_cols(prec, rows_opt(opts), (long)N * S, f->n));
   if (!ws) return fail(-9, "workspace is NULL");
@@ -1126,7 +1141,7 @@ int mvn_prob(const mvn_factor* f, const double* d_a, const double* d_b, const do
   if (!prec_ok(prec)) return fail(-8, "unknown precision %d", prec);
   if (tlr) {
     if (prec != MVN_FP64) return fail(-8, "the TLR sweep is FP64");
-    if (!sweep_rows_ok(opts)) return fail(-8, "sweep_rows must be 0, 64 or 128 (got %d)", opts->sweep_rows);
+    if (!tlr_rows_ok(opts)) return fail(-8, "sweep_rows must be 0, 64, 128 or 256 (got %d)", opts->sweep_rows);
     if (!ws) return fail(-9, "workspace is NULL");
     if (!d_out) return fail(-11, "output is NULL");
     return tlr_sweep_call(f, d_a, d_b, d_mu, N, S, seed, opts, ws, ws_bytes, d_ell, nullptr, d_out, stream, nullptr);

@@ -589,6 +589,95 @@ __global__ __launch_bounds__(256, QuadLds<P>::kWG) void quad_batch_kernel(BatchS
   }
 }
 
+// A TLR factor (Section III-E's tiles, the layout of kernels_tlr.hip) with
+// 256 columns per workgroup, every wave conditioning its own 64: per
+// tile-row i and 64-row block b of it
+//   S_b = [U_i0 .. U_i,i-1][b, :] [Z_i0; ..] + L_ii[b, <b] Y_i[<b]
+// in one K loop (the packed low-rank columns, then the dense diagonal tile),
+// the block conditioned with L_ii as in the dense four-wave sweep, and after
+// the tile-row the stacked product of tile column i,
+//   [Z_(i+1)i; Z_(i+2)i; ..] = [V'_(i+1)i^T; V'_(i+2)i^T; ..] Y_i,
+// in 64-row MFMA tiles whose rows go to their places in the packed Z of the
+// tile-rows below.  Against 64 columns per workgroup this reads every U and
+// V' column once per 256 samples instead of once per 64, and four waves
+// condition at a time instead of one.  Y slice: (nt m) x 256; Z slice:
+// Kpad_total x 256, padding rows cleared once.
+template <bool PREFIX>
+__global__ __launch_bounds__(256, QuadLds<QuadF64>::kWG) void quad_tlr_kernel(TlrSweepArgs p) {
+  using P = QuadF64;
+  MVN_QUAD_LDS(P);
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int m = p.m;
+  const TlrSweepHdr h = *p.hdr;
+  if ((long)blockIdx.x >= h.grid) return;  // the workspace holds h.grid workgroups
+  const double* Vpack = p.vpack_ext ? p.vpack_ext : (const double*)(p.dyn + h.vpack);
+  const double* Upack = p.upack_ext ? p.upack_ext : (const double*)(p.dyn + h.upack);
+  double* Y = (double*)(p.dyn + h.yscr) + (long)blockIdx.x * p.yslice;
+  double* Z = (double*)(p.dyn + h.zscr) + (long)blockIdx.x * h.zslice;
+  for (int i = 1; i < p.nt; ++i)
+    for (long e = (p.kpad0[i] + p.kval[i]) * kQC + t; e < p.kpad0[i + 1] * kQC; e += 256) Z[e] = 0.0;
+  __syncthreads();
+  const long nchunks = ((long)p.N * p.S + kQC - 1) / kQC;
+  for (long chunk = blockIdx.x; chunk < nchunks; chunk += h.grid) {
+    const QuadLane ln = quad_lane(chunk, p.N, p.S, p.prefix);
+    LogProd prod{1.0, 0};
+    for (int ti = 0; ti < p.nt; ++ti) {
+      const long g0 = (long)ti * m;
+      const long kp0 = p.kpad0[ti], Kp = p.kpad0[ti + 1] - kp0;
+      const int nst_lr = (int)(Kp / P::kK);  // Kp is a multiple of 16
+      const double* Ui = Upack + kp0 * m;     // m x Kp
+      const double* Zi = Z + kp0 * kQC;       // Kp x 256
+      const double* D = p.tiles + (p.diag_compact ? (long)ti : (long)ti * (ti + 1) / 2 + ti) * (long)m * m;
+      const double* Yi = Y + g0 * kQC;
+      for (int b0 = 0; b0 < m && g0 + b0 < p.n; b0 += P::kRows) {
+        const int rows = (int)min((long)P::kRows, p.n - (g0 + b0));
+        P::AccV acc[P::kRows / 16][4];
+        quad_zero<P>(acc);
+        quad_gemm<P>(sh, acc, nst_lr + b0 / P::kK, [&](int s, P::Regs& rg) {
+          if (s < nst_lr) P::load(Ui, Kp, 0, b0, (long)s * P::kK, Zi, 0, rg);
+          else P::load(D, m, 0, b0, (long)(s - nst_lr) * P::kK, Yi, 0, rg);
+        });
+        quad_condition<P, PREFIX>(sh, acc, D + (long)b0 * m + b0, m, rows, g0 + b0, p.at, p.bt, p.lattice, p.seed,
+                                  p.n, p.periodize, Y, 0, ln, prod);
+      }
+      // ---- the stacked product of tile column ti (every tile-row but the
+      // last is full, so Y_i has all m rows); V' rows past the column's M
+      // belong to the next column or to the zero rows after the last, and
+      // their products are not stored
+      if (ti + 1 < p.nt) {
+        const long z0 = p.zcol[ti], M = p.zcol[ti + 1] - z0;
+        const double* Vj = Vpack + z0 * m;
+        const long* zd = p.zdst + z0;
+        for (long r0 = 0; r0 < M; r0 += P::kRows) {
+          P::AccV acc[P::kRows / 16][4];
+          quad_zero<P>(acc);
+          quad_gemm<P>(sh, acc, m / P::kK, [&](int s, P::Regs& rg) {
+            P::load(Vj, m, 0, r0, (long)s * P::kK, Yi, 0, rg);
+          });
+#pragma unroll
+          for (int ib = 0; ib < P::kRows / 16; ++ib)
+#pragma unroll
+            for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+              for (int r = 0; r < 4; ++r) {
+                const long rho = r0 + 16 * ib + P::row_of(lane, r);
+                if (rho < M) Z[zd[rho] * kQC + 64 * w + 16 * jb + (lane & 15)] = acc[ib][jb][r];
+              }
+        }
+        __syncthreads();  // Z rows written before the next tile-rows read them
+      }
+    }
+    if (ln.valid) p.ell[ln.col] = logprod_log(prod);
+  }
+}
+
+hipError_t launch_quad_tlr_sweep(const TlrSweepArgs& a, hipStream_t st) {
+  const dim3 g(a.grid), b(256);
+  if (a.prefix) hipLaunchKernelGGL(quad_tlr_kernel<true>, g, b, 0, st, a);
+  else hipLaunchKernelGGL(quad_tlr_kernel<false>, g, b, 0, st, a);
+  return hipGetLastError();
+}
+
 int quad_sweep_cols() { return kQC; }
 
 // FP64 always runs 64-row blocks; the reduced precisions take rows = 64 or 128.

@@ -64,7 +64,7 @@ __global__ __launch_bounds__(1024) void tlr_tables_kernel(TlrTableArgs a) {
     h.vpack = 0;
     h.upack = a.ext_pack ? 0 : align256(8 * (h.ksum + 128) * m);
     h.yscr = a.ext_pack ? 0 : align256(h.upack + 8 * m * (h.kpad > 0 ? h.kpad : 1));
-    h.zslice = (h.kpad > 0 ? h.kpad : 1) * kCols;
+    h.zslice = (h.kpad > 0 ? h.kpad : 1) * (a.cols > 0 ? a.cols : kCols);
     const long per = align256(8 * a.yslice) + align256(8 * h.zslice);
     const long room = (long)a.dyn_bytes - h.yscr;
     long g = room > 0 ? room / per : 0;
@@ -388,6 +388,7 @@ __global__ __launch_bounds__(256, RB == 128 ? 2 : 4) void tlr_sweep_kernel(TlrSw
 }
 
 hipError_t launch_tlr_sweep(const TlrSweepArgs& a, hipStream_t st) {
+  if (a.rows == 256) return launch_quad_tlr_sweep(a, st);
   const dim3 g(a.grid), b(256);
   if (a.prefix) {
     if (a.rows == 64) hipLaunchKernelGGL((tlr_sweep_kernel<64, true>), g, b, 0, st, a);

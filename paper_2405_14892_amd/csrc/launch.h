@@ -326,6 +326,7 @@ struct TlrTableArgs {
   long yslice;
   long grid_max;
   size_t dyn_bytes;
+  int cols;             // sample columns per sweep workgroup (Z slice kpad x cols): 64, or 256 (four-wave sweep)
   int* kk;              // per pair: rank used (|rank| clipped to rs)
   long* zcol;           // nt + 1
   long* kpad0;          // nt + 1
@@ -368,15 +369,18 @@ struct TlrSweepArgs {
   const uint64_t* lattice;
   uint64_t seed;
   int N, S, periodize;
-  long yslice;      // (nt m) x 64
+  long yslice;      // (nt m) x 64, or (nt m) x 256 for the four-wave sweep
   double* ell;
   int grid;         // launch grid (workgroups past hdr->grid leave at once)
-  int rows;         // rows per sweep block: 128 (two workgroups per CU) or 64 (four)
+  int rows;         // rows per sweep block: 128 (two workgroups per CU) or 64 (four); 256 selects the
+                    // four-wave sweep (256 columns per workgroup, 64-row blocks; yslice (nt m) x 256)
   double* prefix;   // nullptr, or n x nchunks x 4 partials of the running products per row
   const double* vpack_ext;  // compact factor: its packed V' rows and U columns (else nullptr:
   const double* upack_ext;  //   the copies in dyn at the header's offsets)
   int diag_compact;         // diagonal tile i at i m^2 (compact) instead of (i(i+1)/2 + i) m^2
 };
 hipError_t launch_tlr_sweep(const TlrSweepArgs& a, hipStream_t st);
+// The four-wave form (kernels_sov_quad.hip), launched by launch_tlr_sweep for rows == 256.
+hipError_t launch_quad_tlr_sweep(const TlrSweepArgs& a, hipStream_t st);
 
 }  // namespace mvn

@@ -110,7 +110,7 @@ def _dense_from_tlr(f):
     return L[:n, :n]
 
 
-@pytest.mark.parametrize("rows", [64, 128])
+@pytest.mark.parametrize("rows", [64, 128, 256])
 def test_prefix_on_tlr_factor_matches_oracle(rows):
     """Nested sets through the tile low-rank sweep (ranks of some tens, a
     partial last tile): every prefix against the oracle's running products

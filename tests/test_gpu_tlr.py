@@ -59,7 +59,8 @@ def _prob(f, a, b, N, S, seed, tile, eps, max_rank, rows=0):
     return r
 
 
-@pytest.mark.parametrize("n,tile,rows", [(1000, 128, 128), (700, 256, 128), (700, 256, 64)])
+@pytest.mark.parametrize("n,tile,rows", [(1000, 128, 128), (700, 256, 128), (700, 256, 64), (1000, 128, 256),
+                                        (700, 256, 256)])
 def test_tlr_exact_limit_matches_dense_oracle(n, tile, rows):
     """eps = 1e-13 with the cap at the tile edge: the factor and every
     sample's log-product agree with the dense oracle (n ragged against the
@@ -83,7 +84,7 @@ def test_tlr_exact_limit_matches_dense_oracle(n, tile, rows):
     assert abs(r["logP"].item() - ref["logP"]) < 1e-9 * max(1.0, abs(ref["logP"]))
 
 
-@pytest.mark.parametrize("rows", [128, 64])
+@pytest.mark.parametrize("rows", [128, 64, 256])
 def test_tlr_sweep_matches_oracle_on_the_compressed_factor(rows):
     """At a working accuracy (ranks from near zero on far tiles to some tens
     on adjacent ones, a partial last tile of 20 rows), the TLR sweep equals,
@@ -331,7 +332,7 @@ def test_tlr_dense_form_and_dense_sweep(n, tile):
     assert abs(rd["logP"].item() - rt["logP"].item()) < 1e-9 * max(1.0, abs(rt["logP"].item()))
 
 
-@pytest.mark.parametrize("n,tile,rows", [(1300, 128, 64), (700, 256, 128)])
+@pytest.mark.parametrize("n,tile,rows", [(1300, 128, 64), (700, 256, 128), (1300, 128, 256)])
 def test_tlr_compact_factor(n, tile, rows):
     """The compact TLR factor (diagonal tiles and U, V'^T at the actual
     ranks): its buffer is what the ranks need, a sweep through it is bit for
@@ -368,3 +369,30 @@ def test_tlr_compact_factor(n, tile, rows):
     assert np.array_equal(pc["logP"].cpu().numpy(), lp_f)
     with pytest.raises(mvn.MvnError):
         mvn.mvn_tlr_dense(c)
+
+
+def test_tlr_four_wave_sweep_is_the_automatic_choice_with_many_samples():
+    """N*S = 140 000 >= 65 536: the automatic choice is the four-wave sweep
+    (sweep_rows = 256, bit for bit), 547 chunks of 256 columns for at most
+    512 workgroups (some sweep two, reusing their Y and Z slices); sampled
+    columns of every chunk match the oracle's sweep through the assembled
+    factor, and every column the 64-column sweep's to 1e-9."""
+    n, tile, eps, rcap = 300, 128, 1e-6, 128
+    N, S, seed = 14000, 10, 333
+    print(f"tlr four-wave auto n={n} N={N} S={S}", flush=True)
+    locs, kern, a, b = _tlr_inputs(20, n, seed=87, beta=0.05)
+    f = _factor(n, locs, kern, tile, eps, rcap)
+    assert f.info() == 0
+    r0 = _prob(f, a, b, N, S, seed, tile, eps, rcap, 0)
+    r256 = _prob(f, a, b, N, S, seed, tile, eps, rcap, 256)
+    r64 = _prob(f, a, b, N, S, seed, tile, eps, rcap, 64)
+    assert torch.equal(r0["ell"], r256["ell"])
+    ell = r0["ell"].cpu().numpy()
+    NS = N * S
+    cols = np.unique(np.concatenate([np.arange(0, NS, 97), np.arange(NS - 300, NS)]))
+    L = _dense_from_tlr(f)
+    at, bt = oracle.centre(a, b)
+    ell_ref = oracle.sweep(L, at, bt, N, S, seed, cols=cols)
+    assert np.max(np.abs(ell[cols] - ell_ref)) < 1e-8
+    assert np.max(np.abs(ell - r64["ell"].cpu().numpy())) < 1e-9
+    assert abs(r0["logP"].item() - r64["logP"].item()) < 1e-10 * max(1.0, abs(r64["logP"].item()))
