@@ -251,15 +251,18 @@ def test_tlr_factor_rejected_where_unsupported():
         f.L()
 
 
-def test_tlr_sweep_graph_capture_replays_match_eager():
+@pytest.mark.parametrize("rows", [0, 256])
+def test_tlr_sweep_graph_capture_replays_match_eager(rows):
     """A TLR probability call reads nothing back (its index tables and the
     layout of its workspace are built on the device from the ranks), so it can
     be captured in a graph: every replay, with eager work in between, equals
     the eager result bit for bit; a workspace too small for one sweep
-    workgroup once the ranks are known gives NaN outputs, not a fault."""
+    workgroup once the ranks are known gives NaN outputs, not a fault.  Both
+    the 64-column form (the automatic choice here) and the four-wave form."""
+    print(f"tlr graph capture rows={rows}", flush=True)
     locs, kern, a, b = _tlr_inputs(32, 900)
     f = _factor(900, locs, kern, 256, 1e-5, 64)
-    opts = mvn.options(tile=256, tlr_eps=1e-5, max_rank=64)
+    opts = mvn.options(tile=256, tlr_eps=1e-5, max_rank=64, sweep_rows=rows)
     N, S = 500, 3
     wsb = mvn.mvn_prob_workspace_bytes_factor(f, N, S, opts)
     ws = torch.empty(wsb, dtype=torch.uint8, device=DEV)
