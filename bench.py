@@ -757,8 +757,7 @@ def main() -> int:
     sweep_tf = roof_flops / (r["sov_ms"] * 1e-3) / 1e12
     peak = PEAK_TFLOPS["fp64" if tlr else args.precision]
     wide = not tlr and args.precision == "fp64" and N * S >= 32768
-    kernel = (("quad_tlr_kernel (TLR SOV update, 256 columns, four conditioning waves)" if N * S >= 65536 else
-               "tlr_sweep_kernel (TLR SOV update + conditioning)") if tlr else
+    kernel = ("tlr_sweep_kernel (TLR SOV update + conditioning, 64-row blocks)" if tlr else
               "wide_sweep_kernel (256-row x 128-column FP64 SOV GEMM + conditioning)" if wide else
               "sweep_kernel (SOV GEMM + conditioning)")
     line = {

@@ -82,10 +82,10 @@ typedef struct mvn_options {
                      /* 128 (two workgroups per CU) or 64 (four, three for   */
                      /* split BF16: more sample columns conditioned at once, */
                      /* Y read twice as often); 0 = 128 for dense factors    */
-                     /* and batches.  TLR factors also take 256: 256 sample  */
-                     /* columns per workgroup, each wave conditioning its    */
-                     /* own 64 (64-row blocks); 0 selects it for N*S >=      */
-                     /* 65536, else 64.  The adjoint sweep                   */
+                     /* and batches, 64 for TLR factors, which also take     */
+                     /* 256: 256 sample columns per workgroup, each wave     */
+                     /* conditioning its own 64 (64-row blocks; on request   */
+                     /* only).  The adjoint sweep                            */
                      /* uses 128.  32 (dense FP64 mvn_prob, mvn_prob_prefix, */
                      /* mvn_prob_static): the narrow sweep, 16 sample        */
                      /* columns per workgroup (32 above 20480 samples), the  */

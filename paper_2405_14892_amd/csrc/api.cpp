@@ -54,12 +54,12 @@ int rows_opt(const mvn_options* o) { return o ? o->sweep_rows : 0; }
 // The TLR sweep's blocks: its GEMMs are short (packed ranks plus the dense
 // part of one tile), so conditioning dominates and 64-row blocks (four
 // workgroups per CU) are the default.
-// TLR sweeps: 64- or 128-row blocks of 64 columns per workgroup, or 256 (the
-// four-wave sweep: 256 columns per workgroup, 64-row blocks), the automatic
-// choice once the 256-column chunks fill every CU.
-constexpr long kTlrQuadMinNS = 256L * 256;
-int tlr_sweep_rows(const mvn_options* o, long NS) {
-  if (!o || o->sweep_rows == 0) return NS >= kTlrQuadMinNS ? 256 : 64;
+// TLR sweeps: 64- or 128-row blocks of 64 columns per workgroup (0 = 64), or
+// 256: the four-wave sweep, 256 columns per workgroup and 64-row blocks, on
+// request only (at 65 536 sites it beat the 64-row blocks by 2% at N*S = 10^5
+// and lost at 32 768, 65 536, 131 072 and 200 000 samples).
+int tlr_sweep_rows(const mvn_options* o, long) {
+  if (!o || o->sweep_rows == 0) return 64;
   return o->sweep_rows;
 }
 bool tlr_rows_ok(const mvn_options* o) {

@@ -218,20 +218,19 @@ def test_tlr_size_queries_and_option_checks():
 
 
 def test_tlr_sweep_form_choice_in_the_size_query():
-    """TLR factors take sweep_rows 0, 64, 128 or 256; 0 is the four-wave form
-    (256 columns per workgroup, Y and Z slices four times as wide) once N*S
-    reaches 65 536 and the 64-column form below; dense factors refuse 256."""
+    """TLR factors take sweep_rows 0 (= 64), 64, 128 or 256 (the four-wave
+    form: 256 columns per workgroup, Y and Z slices four times as wide, on
+    request only); dense factors refuse 256."""
     n = 1000
     base = dict(tile=256, tlr_eps=1e-6, max_rank=100)
     size = lambda N, S, rows: mvn.mvn_prob_workspace_bytes(n, N, S, mvn.options(sweep_rows=rows, **base))
     # (the slices differ in total width where the chunk counts do not fill
     # the workgroup caps the same way: 625 chunks of 64 against 157 of 256,
     # and 1024 capped chunks of 64 against 391 of 256)
-    assert size(1000, 2, 0) == size(1000, 2, 64)
-    assert size(65535, 1, 0) == size(65535, 1, 64)
-    assert size(20_000, 2, 0) == size(20_000, 2, 64) != size(20_000, 2, 256)
-    assert size(65536, 1, 0) == size(65536, 1, 256)
-    assert size(10_000, 10, 0) == size(10_000, 10, 256) != size(10_000, 10, 64)
+    for N, S in ((1000, 2), (20_000, 2), (65536, 1), (10_000, 10)):
+        assert size(N, S, 0) == size(N, S, 64)
+    assert size(20_000, 2, 256) != size(20_000, 2, 64)
+    assert size(10_000, 10, 256) != size(10_000, 10, 64)
     for bad in (32, 96, 512):
         with pytest.raises(mvn.MvnError):
             size(1000, 2, bad)
