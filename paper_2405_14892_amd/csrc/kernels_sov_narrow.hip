@@ -15,24 +15,27 @@
 //     P = 64 / C lanes per sample column splitting the dot product (summed
 //     by DPP within the quad or pair), and stores y to LDS and to the
 //     workgroup's Y scratch;
-//   * meanwhile waves 1 and 2 (16 rows of the next block each) accumulate
-//     S_{r+1} = L[block r+1, 0:i0] Y[0:i0] on MFMA with operands loaded
-//     straight into registers (no LDS stage, so no barrier inside the K
-//     loop), stage the next block's triangle, limits and QMC points into the
-//     other half of double-buffered LDS, and load L[block r+1, block r];
-//   * after the block, the two waves add L[block r+1, block r] y_r (y_r from
-//     LDS) and write S_{r+1} to LDS: two barriers per 32 rows.
+//   * meanwhile waves 1 and 2 accumulate S_{r+1} = L[block r+1, 0:i0] Y[0:i0]
+//     on MFMA, each over all 32 rows and the 16-deep K stages of one parity
+//     (so the workgroup reads its Y slice once per block, not once per
+//     wave), with operands loaded straight into registers (no LDS stage, so
+//     no barrier inside the K loop); they stage the next block's triangle,
+//     limits and QMC points into the other half of double-buffered LDS and
+//     load L[block r+1, block r];
+//   * after the block, each adds its half of L[block r+1, block r] y_r (y_r
+//     from LDS) and writes its partial S_{r+1} to LDS (the conditioning
+//     wave adds the two): two barriers per 32 rows.
 // The recurrence thus never waits on the GEMM except for that last product
 // (eight MFMAs per wave), and with several workgroups per CU the MFMA work
 // of some overlaps the conditioning of others.
 //
-// Measured on one box (FP64, 4096 sites): 10.3 ms for 10^4 samples against
-// 11.9 ms for the 64-column sweep, 5.9 against 11.8 ms for 2560.  The chain
-// alone (the GEMM loop removed in a timing copy) takes 5.9-6.4 ms, 1.45 us
-// per row; the rest is the GEMM, whose waves wait on their loads (one
-// register stage in flight).  Each workgroup streams the whole factor and
-// re-reads its Y slice once per 32 rows, so with more sites the 64-column
-// sweep is faster (8192 sites, 10^4 samples: 39 against 32 ms).
+// Measured on one box (FP64, 4096 sites): 9.2-10.3 ms for 10^4 samples
+// against 11.9 ms for the 64-column sweep, 5.3 against 11.8 ms for 2560.
+// The chain alone (the GEMM loop removed in a timing copy) takes 5.9-6.4 ms,
+// 1.45 us per row; the rest is the GEMM, whose waves wait on their loads.
+// Each workgroup streams the whole factor and re-reads its Y slice once per
+// 32 rows; splitting K instead of rows between the two GEMM waves took
+// 8192 sites, 10^4 samples from 39 to 31 ms (the 64-column sweep: 32 ms).
 //
 // The Y scratch is laid out for the B operand: element (k, c) of a
 // workgroup's slice at ((k / 4) C + c) 4 + k % 4, so a lane's four k values
@@ -54,37 +57,40 @@ constexpr int kNFLd = kNR + 1;  // LDS row stride of the closing product's L til
 
 typedef __attribute__((ext_vector_type(2))) double n_f64x2;
 
-// K columns per register stage: 32 for 16 sample columns (A 8 + B 8 doubles
-// per lane), 16 for 32 columns (A 4 + B 8).
+// K columns per register stage: 16 (A 8 doubles for the two 16-row tiles,
+// B 4 or 8 per lane).
 template <int C>
 struct NarrowShape {
   static constexpr int kCT = C / 16;         // 16-column MFMA tiles
-  static constexpr int kKS = C == 16 ? 32 : 16;
+  static constexpr int kKS = 16;
   static constexpr int kSub = kKS / 16;      // 16-deep groups per stage
   static constexpr int kP = 64 / C;          // conditioning lanes per sample column
 };
 
-// One register stage of the GEMM: a[s][j] = L[row, k0 + 16 s + 4 q + j],
+// One register stage of the GEMM: a[rt][s][j] = L[16 rt + r, k0 + 16 s + 4 q + j],
 // b[t][s][j] = Y(k0 + 16 s + 4 q + j, 16 t + r) for lane (r = lane & 15,
 // q = lane >> 4).
 template <int C>
 struct NarrowRegs {
-  double a[NarrowShape<C>::kSub][4];
+  double a[2][NarrowShape<C>::kSub][4];
   double b[NarrowShape<C>::kCT][NarrowShape<C>::kSub][4];
 };
 
 template <int C>
-__device__ __forceinline__ void narrow_load(const double* __restrict__ Arow, const double* __restrict__ Bq, int k0,
-                                            NarrowRegs<C>& g) {
+__device__ __forceinline__ void narrow_load(const double* __restrict__ Arow, long ld, const double* __restrict__ Bq,
+                                            int k0, NarrowRegs<C>& g) {
   using Sh = NarrowShape<C>;
 #pragma unroll
   for (int s = 0; s < Sh::kSub; ++s) {
-    const n_f64x2* pa = (const n_f64x2*)(Arow + k0 + 16 * s);
-    const n_f64x2 a0 = pa[0], a1 = pa[1];
-    g.a[s][0] = a0.x;
-    g.a[s][1] = a0.y;
-    g.a[s][2] = a1.x;
-    g.a[s][3] = a1.y;
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt) {
+      const n_f64x2* pa = (const n_f64x2*)(Arow + (long)rt * 16 * ld + k0 + 16 * s);
+      const n_f64x2 a0 = pa[0], a1 = pa[1];
+      g.a[rt][s][0] = a0.x;
+      g.a[rt][s][1] = a0.y;
+      g.a[rt][s][2] = a1.x;
+      g.a[rt][s][3] = a1.y;
+    }
 #pragma unroll
     for (int t = 0; t < Sh::kCT; ++t) {
       const n_f64x2* pb = (const n_f64x2*)(Bq + (long)(k0 + 16 * s) * C + 64 * t);
@@ -97,12 +103,13 @@ __device__ __forceinline__ void narrow_load(const double* __restrict__ Arow, con
   }
 }
 
-// Accumulators: one 16 x 16 tile per column tile; with one column tile, two
-// chains (alternate groups) so that consecutive MFMAs are independent.
+// Accumulators: one 16 x 16 tile per row tile and column tile; with one
+// column tile, two chains (alternate groups) so that consecutive MFMAs on a
+// tile are independent.
 template <int C>
 struct NarrowAcc {
   static constexpr int kChains = NarrowShape<C>::kCT == 1 ? 2 : 1;
-  f64x4 v[kChains][NarrowShape<C>::kCT];
+  f64x4 v[kChains][2][NarrowShape<C>::kCT];
 };
 
 template <int C>
@@ -113,10 +120,12 @@ __device__ __forceinline__ void narrow_mma(const NarrowRegs<C>& g, NarrowAcc<C>&
 #pragma unroll
     for (int j = 0; j < 4; ++j)
 #pragma unroll
-      for (int t = 0; t < Sh::kCT; ++t) {
-        f64x4& d = acc.v[(s * 4 + j) % NarrowAcc<C>::kChains][t];
-        d = __builtin_amdgcn_mfma_f64_16x16x4f64(g.a[s][j], g.b[t][s][j], d, 0, 0, 0);
-      }
+      for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int t = 0; t < Sh::kCT; ++t) {
+          f64x4& d = acc.v[(s * 4 + j) % NarrowAcc<C>::kChains][rt][t];
+          d = __builtin_amdgcn_mfma_f64_16x16x4f64(g.a[rt][s][j], g.b[t][s][j], d, 0, 0, 0);
+        }
 }
 
 // LDS of one workgroup: S of the block (written by the GEMM waves), y of the
@@ -124,7 +133,8 @@ __device__ __forceinline__ void narrow_mma(const NarrowRegs<C>& g, NarrowAcc<C>&
 // double-buffered per-block inputs of the recurrence.
 template <int C>
 struct NarrowLds {
-  double S[kNR * C];
+  double S[kNR * C];       // S of the block: the even K stages and the closing product's first half
+  double S1[kNR * C];      // the odd K stages and its second half (added by the conditioning wave)
   double Yb[kNR * C];
   double F[kNR * kNFLd];  // L[block r+1, block r]
   double W[2][kNR * C];   // QMC points
@@ -202,8 +212,10 @@ __global__ __launch_bounds__(kNThreads, narrow_wg(C)) void narrow_sweep_kernel(S
   const auto ninv = [tab](double x) { return ninv_lower_tab(x, tab); };
   // wave 0: sample column lane / P, part lane % P of its dot products
   const int ccol = lane / Sh::kP, part = lane % Sh::kP;
-  // GEMM waves: u in 0..127 for staging, rows 16 g + (lane & 15) of the next block
-  const int u = t - 64, g = wv - 1;
+  // GEMM waves: u in 0..127 for staging; wave 1 + kp takes every row of the
+  // next block and the K stages of parity kp, so each wave reads its half of
+  // the Y slice once per block
+  const int u = t - 64, kp = wv - 1;
   for (long chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x) {
     const long col = chunk * C + ccol;
     const bool valid = wv == 0 && col < NS;
@@ -219,34 +231,42 @@ __global__ __launch_bounds__(kNThreads, narrow_wg(C)) void narrow_sweep_kernel(S
 #pragma unroll
     for (int c = 0; c < NarrowAcc<C>::kChains; ++c)
 #pragma unroll
-      for (int ct = 0; ct < Sh::kCT; ++ct) acc.v[c][ct] = f64x4{0.0, 0.0, 0.0, 0.0};
+      for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < Sh::kCT; ++ct) acc.v[c][rt][ct] = f64x4{0.0, 0.0, 0.0, 0.0};
       if (wv > 0) narrow_stage<C>(sh, 0, u, p.L, ld, n, 0, p.at, p.bt, p.lattice, p.seed, ssidx, sjpt, p.periodize);
     for (int r = 0; r < nb; ++r) {
       const int i0 = r * kNR, buf = r & 1;
-      // ---- phase A: S_r = (L[block r, 0:i0 - 32] Y) + L[block r, block r-1] y_{r-1}
+      // ---- phase A: S_r = (L[block r, 0:i0 - 32] Y) + L[block r, block r-1] y_{r-1},
+      // as two partial sums: each K parity adds its 16 of the closing
+      // product's 32 columns and writes its own array
       if (wv > 0) {
         if (r > 0) {
 #pragma unroll
-          for (int s = 0; s < 2; ++s)
+          for (int j = 0; j < 4; ++j) {
+            const int k = 16 * kp + 4 * (lane >> 4) + j;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-              const int k = 16 * s + 4 * (lane >> 4) + j;
-              const double a = sh.F[(16 * g + (lane & 15)) * kNFLd + k];
+            for (int rt = 0; rt < 2; ++rt) {
+              const double a = sh.F[(16 * rt + (lane & 15)) * kNFLd + k];
 #pragma unroll
               for (int ct = 0; ct < Sh::kCT; ++ct) {
-                f64x4& d = acc.v[(s * 4 + j) % NarrowAcc<C>::kChains][ct];
+                f64x4& d = acc.v[j % NarrowAcc<C>::kChains][rt][ct];
                 d = __builtin_amdgcn_mfma_f64_16x16x4f64(a, sh.Yb[k * C + 16 * ct + (lane & 15)], d, 0, 0, 0);
               }
             }
-        }
-#pragma unroll
-        for (int ct = 0; ct < Sh::kCT; ++ct)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            double x = acc.v[0][ct][v];
-            if constexpr (NarrowAcc<C>::kChains == 2) x += acc.v[1][ct][v];
-            sh.S[(16 * g + (lane >> 4) + 4 * v) * C + 16 * ct + (lane & 15)] = x;
           }
+        }
+        double* Sd = kp ? sh.S1 : sh.S;
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+          for (int ct = 0; ct < Sh::kCT; ++ct)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              double x = acc.v[0][rt][ct][v];
+              if constexpr (NarrowAcc<C>::kChains == 2) x += acc.v[1][rt][ct][v];
+              Sd[(16 * rt + (lane >> 4) + 4 * v) * C + 16 * ct + (lane & 15)] = x;
+            }
       }
       __syncthreads();  // S_r and the block's inputs are in LDS; Yb is free
       // ---- phase B
@@ -259,8 +279,11 @@ __global__ __launch_bounds__(kNThreads, narrow_wg(C)) void narrow_sweep_kernel(S
         for (int i = 0; i < rows; ++i) {
           const int pt = narrow_opaque(part);
           // D is zero from column i on and Yb holds finite values (or the
-          // zeros it starts with), so every term of the part can be summed
-          double s0 = 0.0, s1 = 0.0;
+          // zeros it starts with), so every term of the part can be summed;
+          // the part-0 lane starts from the two halves of S (read off the
+          // recurrence's dependency chain, summed once by the DPP reduction)
+          double s0 = part == 0 ? sh.S[i * C + ccol] : 0.0;
+          double s1 = part == 0 ? sh.S1[i * C + ccol] : 0.0;
           const lds_f64* Di = D + i * kNR;
 #pragma unroll
           for (int kk = 0; kk < kNR / Sh::kP; kk += 2) {
@@ -271,7 +294,6 @@ __global__ __launch_bounds__(kNThreads, narrow_wg(C)) void narrow_sweep_kernel(S
           double s = s0 + s1;
           s += dpp_f64<0xB1>(s);                 // partner lane xor 1
           if constexpr (Sh::kP == 4) s += dpp_f64<0x4E>(s);  // xor 2
-          s += sh.S[i * C + ccol];
           const double rl = sh.rl[buf][i];
           const double alpha = (sh.at[buf][i] - s) * rl;
           const double beta = (sh.bt[buf][i] - s) * rl;
@@ -286,24 +308,32 @@ __global__ __launch_bounds__(kNThreads, narrow_wg(C)) void narrow_sweep_kernel(S
       } else if (r + 1 < nb) {
         const int i1 = i0 + kNR;
         narrow_stage<C>(sh, buf ^ 1, u, p.L, ld, n, i1, p.at, p.bt, p.lattice, p.seed, ssidx, sjpt, p.periodize);
-        const double* Arow = p.L + (long)(i1 + 16 * g + (lane & 15)) * ld + 4 * (lane >> 4);
+        const double* Arow = p.L + (long)(i1 + (lane & 15)) * ld + 4 * (lane >> 4);
         const double* Bq = Y + ((long)(lane >> 4) * C + (lane & 15)) * 4;
 #pragma unroll
         for (int c = 0; c < NarrowAcc<C>::kChains; ++c)
 #pragma unroll
-          for (int ct = 0; ct < Sh::kCT; ++ct) acc.v[c][ct] = f64x4{0.0, 0.0, 0.0, 0.0};
-        // S_{r+1} over the finished blocks 0..r-1 (K = i0, a multiple of kKS)
-        if (i0 > 0) {
+          for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+            for (int ct = 0; ct < Sh::kCT; ++ct) acc.v[c][rt][ct] = f64x4{0.0, 0.0, 0.0, 0.0};
+        // S_{r+1} over the finished blocks 0..r-1 (K = i0, a multiple of
+        // 2 kKS): this wave's stages k0 = kp kKS + 2 kKS m < i0, two register
+        // sets in flight
+        int k0 = kp * Sh::kKS;
+        if (k0 < i0) {
           NarrowRegs<C> g0, g1;
-          narrow_load<C>(Arow, Bq, 0, g0);
-          int k0 = 0;
-          for (; k0 + 2 * Sh::kKS <= i0; k0 += 2 * Sh::kKS) {
-            narrow_load<C>(Arow, Bq, k0 + Sh::kKS, g1);
+          narrow_load<C>(Arow, ld, Bq, k0, g0);
+          for (;;) {
+            const int k1 = k0 + 2 * Sh::kKS;
+            if (k1 < i0) narrow_load<C>(Arow, ld, Bq, k1, g1);
             narrow_mma<C>(g0, acc);
-            if (k0 + 2 * Sh::kKS < i0) narrow_load<C>(Arow, Bq, k0 + 2 * Sh::kKS, g0);
+            if (k1 >= i0) break;
+            const int k2 = k1 + 2 * Sh::kKS;
+            if (k2 < i0) narrow_load<C>(Arow, ld, Bq, k2, g0);
             narrow_mma<C>(g1, acc);
+            if (k2 >= i0) break;
+            k0 = k2;
           }
-          if (k0 < i0) narrow_mma<C>(g0, acc);
         }
         // the L tile of the closing product with y_r
         const int uf = narrow_opaque(u);
