@@ -91,7 +91,8 @@ typedef struct mvn_options {
                      /* columns per workgroup (32 above 20480 samples), the  */
                      /* next block's GEMM overlapped with the recurrence;    */
                      /* 0 selects it for dense FP64 calls with N*S <= 20480  */
-                     /* and N*S*n <= 4.5e7                                   */
+                     /* and N*S*n <= 9e7 (4.5e7 above 12288 samples, where  */
+                     /* the chunks are 32 columns wide)                      */
   double tlr_eps;    /* > 0: tile low-rank factor (Section III-E): every      */
                      /* off-diagonal tile is compressed to U V^T with         */
                      /* ||A_ij - U V^T||_F <= tlr_eps (absolute).  <= 0: dense */

@@ -35,13 +35,16 @@ int hip_fail(hipError_t e, const char* where) {
 
 constexpr size_t kAlign = 256;
 constexpr int kCUs = 256;      // compute units of an MI355X: the persistent grids are sized for it
-// Automatic narrow sweep: at most this many samples (16-column chunks), and
-// samples x dimensions at most kNarrowMaxWork.  Measured (FP64): 4096
-// sites, 10^4 samples: 10.3 against 11.9 ms, 2560 samples: 5.9 against
-// 11.8 ms; 8192 sites, 10^4 samples: 39 against 32 ms (each narrow
-// workgroup streams the whole factor, four times as many as 64-column ones).
+// Automatic narrow sweep: at most kNarrowMaxNS samples, and samples x
+// dimensions at most kNarrowMaxWork16 with 16-column chunks (up to 12 288
+// samples), kNarrowMaxWork32 with 32-column ones.  Measured (FP64, one box,
+// 64-column sweep against the narrow one, 10^4 samples): 4096 sites 11.9 /
+// 9.2 ms, 6144 sites 20.0 / 18.5 ms, 8192 sites 31.9 / 31.0 ms, 12 288 sites
+// 63.6 / 69.9 ms; 4096 sites with 2 x 10^4 samples (32 columns) 15.2 / 17.7
+// ms.  Each narrow workgroup streams the whole factor, so the factor's size
+// bounds it.
 constexpr long kNarrowMaxNS = 20480;
-constexpr double kNarrowMaxWork = 4.5e7;
+constexpr double kNarrowMaxWork16 = 9e7, kNarrowMaxWork32 = 4.5e7;
 
 // Rows per sweep block: 0 selects the default (128); 32 (the narrow FP64
 // sweep of dense factors) runs its own 32-row blocks, and the other sweeps
@@ -234,7 +237,8 @@ bool use_wide(int prec, int rows, bool prefix, long NS) {
 // rows_raw: the sweep_rows option as given (0 = automatic).
 int sweep_kind(int prec, int rows_raw, bool prefix, long NS, int n) {
   if (prec == MVN_FP64 &&
-      (rows_raw == 32 || (rows_raw == 0 && NS <= kNarrowMaxNS && (double)NS * n <= kNarrowMaxWork)))
+      (rows_raw == 32 || (rows_raw == 0 && NS <= kNarrowMaxNS &&
+                          (double)NS * n <= (narrow_cols(NS) == 16 ? kNarrowMaxWork16 : kNarrowMaxWork32))))
     return kSweepNarrow;
   const int rows = rows_raw == 0 || rows_raw == 32 ? 128 : rows_raw;
   if (use_wide(prec, rows, prefix, NS)) return kSweepWide;

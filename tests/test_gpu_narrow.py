@@ -1,5 +1,5 @@
 """The narrow FP64 sweep (sweep_rows = 32; the automatic choice for N*S <=
-20480 with N*S*n <= 4.5e7): 16 or 32 sample columns per workgroup, 32-row blocks, the next block's
+20480 with N*S*n <= 9e7, 4.5e7 above 12288 samples): 16 or 32 sample columns per workgroup, 32-row blocks, the next block's
 limit-update GEMM overlapped with the recurrence.  Per-sample log-products
 against the oracle's sweep on identical QMC points (1e-9 absolute, as for the
 other sweeps), nested-set probabilities against the oracle's running
@@ -171,3 +171,24 @@ def test_narrow_graph_capture_replays_match_eager():
         assert torch.equal(rg["out"], eager), rep
         assert torch.equal(pg["out"], eager_p), rep
         del junk
+
+
+@pytest.mark.parametrize("n,N,S,narrow", [(6144, 1000, 10, True), (9216, 1000, 10, False),
+                                          (2048, 2000, 10, True), (4096, 2000, 10, False)])
+def test_narrow_automatic_choice_bounds(n, N, S, narrow):
+    """The automatic choice takes the narrow sweep up to N*S*n = 9e7 with
+    16-column chunks (N*S <= 12 288) and 4.5e7 with 32-column ones: each case
+    equals, bit for bit, the sweep it should pick (sweep_rows = 32 for the
+    narrow one, 128 for the 64-column one), and the two agree to 1e-9."""
+    print(f"narrow auto n={n} N={N} S={S} narrow={narrow}", flush=True)
+    k = int(np.ceil(np.sqrt(n)))
+    locs = workloads.grid_locations(k)[:n]
+    kern = (1.0, 0.1, 0.5, 1e-8)
+    rng = np.random.default_rng(5)
+    a, b = np.full(n, -np.inf), rng.normal(0.5, 1.0, n)
+    f = mvn.mvn_cholesky(n, locs=locs, kern=kern, opts=mvn.options(tile=256), device=DEV)
+    r = {rows: mvn.mvn_prob(f, a, b, None, N=N, S=S, seed=9, opts=mvn.options(tile=256, sweep_rows=rows),
+                            return_ell=True)["ell"] for rows in (0, 32, 128)}
+    torch.cuda.synchronize()
+    assert torch.equal(r[0], r[32] if narrow else r[128])
+    assert torch.max(torch.abs(r[32] - r[128])).item() < 1e-9
